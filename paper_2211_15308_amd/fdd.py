@@ -1,0 +1,266 @@
+"""Thin ctypes binding of libfdd.so (the C ABI in include/fdd.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP kernels.
+PyTorch supplies device memory (the workspace and the vectors) and the HIP stream.
+The binding raises if the shared library is missing; there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdd.so")
+
+FDD_OK = 0
+FDD_NOT_CONVERGED = 1
+FDD_E_ARG = -1
+FDD_E_NOMEM = -2
+FDD_E_HIP = -3
+FDD_E_RA = -4
+FDD_E_BREAKDOWN = -5
+FDD_E_NONFINITE = -6
+FDD_E_WORKSPACE = -7
+FDD_E_STATE = -8
+FDD_FP64 = 0
+FDD_MIXED = 1
+FDD_RA_PRECOND = 0
+FDD_RA_OPERATOR = 1
+
+STATUS_NAMES = {
+    FDD_OK: "FDD_OK", FDD_NOT_CONVERGED: "FDD_NOT_CONVERGED", FDD_E_ARG: "FDD_E_ARG",
+    FDD_E_NOMEM: "FDD_E_NOMEM", FDD_E_HIP: "FDD_E_HIP", FDD_E_RA: "FDD_E_RA",
+    FDD_E_BREAKDOWN: "FDD_E_BREAKDOWN", FDD_E_NONFINITE: "FDD_E_NONFINITE",
+    FDD_E_WORKSPACE: "FDD_E_WORKSPACE", FDD_E_STATE: "FDD_E_STATE",
+}
+
+# every symbol declared in include/fdd.h
+EXPORTED = [
+    "fdd_opts_default", "fdd_setup_mesh", "fdd_problem_info", "fdd_workspace_bytes",
+    "fdd_bind_workspace", "fdd_build_rational_pc", "fdd_ratpc_from_table", "fdd_ratpc_query",
+    "fdd_interior_solve", "fdd_schur_apply", "fdd_precond_apply", "fdd_apply_operator",
+    "fdd_solve", "fdd_destroy_problem", "fdd_destroy_ratpc", "fdd_last_error", "fdd_version",
+]
+
+
+class FddDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("K", ctypes.c_double),
+                ("mu", ctypes.c_double)]
+
+
+class FddOpts(ctypes.Structure):
+    _fields_ = [("outer_rtol", ctypes.c_double), ("outer_maxit", ctypes.c_int),
+                ("inner_rtol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
+                ("precision", ctypes.c_int), ("mg_nu", ctypes.c_int),
+                ("inner_chunk", ctypes.c_int), ("check_true_residual", ctypes.c_int),
+                ("warmstart", ctypes.c_void_p), ("use_graph", ctypes.c_int)]
+
+
+class FddStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("outer_its", ctypes.c_int),
+                ("inner_solves", ctypes.c_int), ("inner_its_total", ctypes.c_int),
+                ("inner_its_max", ctypes.c_int), ("refine_steps", ctypes.c_int),
+                ("rel_precond_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class FddError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Loads libfdd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(f"{LIB_PATH} is missing: build it with paper_2211_15308_amd.build_lib")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, V, I, D = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    lib.fdd_opts_default.argtypes = [ctypes.POINTER(FddOpts)]
+    lib.fdd_opts_default.restype = None
+    lib.fdd_setup_mesh.argtypes = [ctypes.POINTER(FddDesc), I, ctypes.POINTER(P)]
+    lib.fdd_problem_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.fdd_workspace_bytes.argtypes = [P, ctypes.POINTER(FddOpts), ctypes.POINTER(ctypes.c_size_t)]
+    lib.fdd_bind_workspace.argtypes = [P, V, ctypes.c_size_t, V]
+    lib.fdd_build_rational_pc.argtypes = [P, I, D, I, ctypes.POINTER(P)]
+    lib.fdd_ratpc_from_table.argtypes = [P, I, I, D, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(P)]
+    lib.fdd_ratpc_query.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(D), ctypes.POINTER(D),
+                                    ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.fdd_interior_solve.argtypes = [P, V, V, ctypes.POINTER(FddOpts), V, ctypes.POINTER(I)]
+    lib.fdd_schur_apply.argtypes = [P, P, V, V, ctypes.POINTER(FddOpts), V]
+    lib.fdd_precond_apply.argtypes = [P, P, V, V, V]
+    lib.fdd_apply_operator.argtypes = [P, P, V, V, V]
+    lib.fdd_solve.argtypes = [P, P, P, V, V, ctypes.POINTER(FddOpts), V, ctypes.POINTER(FddStats)]
+    lib.fdd_destroy_problem.argtypes = [P]
+    lib.fdd_destroy_problem.restype = None
+    lib.fdd_destroy_ratpc.argtypes = [P]
+    lib.fdd_destroy_ratpc.restype = None
+    lib.fdd_last_error.restype = ctypes.c_char_p
+    lib.fdd_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc, allow=(FDD_OK,)):
+    if rc not in allow:
+        raise FddError(rc, load().fdd_last_error().decode())
+    return rc
+
+
+def opts_default(**kw):
+    o = FddOpts()
+    load().fdd_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    """Device pointer of a contiguous torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class RationalTable:
+    """One rational-approximation table (eq. (RA)); owns the library handle."""
+
+    def __init__(self, handle, which):
+        self.h = handle
+        self.which = which
+
+    def query(self):
+        lib = load()
+        m = ctypes.c_int()
+        lib.fdd_ratpc_query(self.h, ctypes.byref(m), None, None, None, None)
+        c = (ctypes.c_double * max(m.value, 1))()
+        p = (ctypes.c_double * max(m.value, 1))()
+        c0 = ctypes.c_double()
+        err = ctypes.c_double()
+        _check(lib.fdd_ratpc_query(self.h, ctypes.byref(m), ctypes.byref(c0), c, p, ctypes.byref(err)))
+        return dict(m=m.value, c0=c0.value, c=list(c)[:m.value], p=list(p)[:m.value], max_rel_err=err.value)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fdd_destroy_ratpc(self.h)
+            self.h = None
+
+
+class Problem:
+    """A set-up problem (fdd_setup_mesh); host only until bind_workspace is called."""
+
+    def __init__(self, n, K, mu, dim=2, device=0):
+        lib = load()
+        d = FddDesc(dim, n, K, mu)
+        h = ctypes.c_void_p()
+        _check(lib.fdd_setup_mesh(ctypes.byref(d), device, ctypes.byref(h)))
+        self.h = h
+        self.n, self.K, self.mu, self.dim = n, K, mu, dim
+        self.device = device
+        self.workspace = None
+        N, NI, NG = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        _check(lib.fdd_problem_info(h, ctypes.byref(N), ctypes.byref(NI), ctypes.byref(NG),
+                                    ctypes.byref(lo), ctypes.byref(hi)))
+        self.N, self.NI, self.NG = N.value, NI.value, NG.value
+        self.lam_lo, self.lam_hi = lo.value, hi.value
+
+    def workspace_bytes(self, opts=None):
+        b = ctypes.c_size_t()
+        _check(load().fdd_workspace_bytes(self.h, ctypes.byref(opts or opts_default()), ctypes.byref(b)))
+        return b.value
+
+    def bind_workspace(self, workspace=None, stream=None):
+        """Binds a uint8 CUDA tensor (allocated here if not given) as the solver workspace."""
+        import torch
+        nbytes = self.workspace_bytes()
+        if workspace is None:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=f"cuda:{self.device}")
+        ptr = workspace.data_ptr()
+        off = (-ptr) % 256
+        _check(load().fdd_bind_workspace(self.h, ctypes.c_void_p(ptr + off), workspace.numel() - off,
+                                         _stream(stream)))
+        self.workspace = workspace
+        return self
+
+    def build_rational_pc(self, which=FDD_RA_PRECOND, tol=1e-12, max_poles=64):
+        h = ctypes.c_void_p()
+        _check(load().fdd_build_rational_pc(self.h, which, tol, max_poles, ctypes.byref(h)))
+        return RationalTable(h, which)
+
+    def ratpc_from_table(self, which, c0, c, p):
+        m = len(c)
+        ca = (ctypes.c_double * max(m, 1))(*c)
+        pa = (ctypes.c_double * max(m, 1))(*p)
+        h = ctypes.c_void_p()
+        _check(load().fdd_ratpc_from_table(self.h, which, m, c0, ca, pa, ctypes.byref(h)))
+        return RationalTable(h, which)
+
+    def interior_solve(self, f, u, opts=None, stream=None):
+        its = ctypes.c_int()
+        rc = load().fdd_interior_solve(self.h, _ptr(f), _ptr(u), ctypes.byref(opts or opts_default()),
+                                       _stream(stream), ctypes.byref(its))
+        _check(rc)
+        return its.value
+
+    def schur_apply(self, H, x_G, y_G, opts=None, stream=None):
+        _check(load().fdd_schur_apply(self.h, H.h, _ptr(x_G), _ptr(y_G),
+                                      ctypes.byref(opts or opts_default()), _stream(stream)))
+
+    def precond_apply(self, P, r_G, z_G, stream=None):
+        _check(load().fdd_precond_apply(self.h, P.h, _ptr(r_G), _ptr(z_G), _stream(stream)))
+
+    def apply_operator(self, H, x, y, stream=None):
+        _check(load().fdd_apply_operator(self.h, H.h, _ptr(x), _ptr(y), _stream(stream)))
+
+    def solve(self, P, H, b, x, opts=None, stream=None, allow_not_converged=False):
+        st = FddStats()
+        rc = load().fdd_solve(self.h, P.h, H.h, _ptr(b), _ptr(x), ctypes.byref(opts or opts_default()),
+                              _stream(stream), ctypes.byref(st))
+        _check(rc, (FDD_OK, FDD_NOT_CONVERGED) if allow_not_converged else (FDD_OK,))
+        return st.as_dict()
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fdd_destroy_problem(self.h)
+            self.h = None
+
+
+# names of the C ABI calls
+def setup_mesh(n, K, mu, dim=2, device=0):
+    return Problem(n, K, mu, dim, device)
+
+
+def build_rational_pc(prob, which=FDD_RA_PRECOND, tol=1e-12, max_poles=64):
+    return prob.build_rational_pc(which, tol, max_poles)
+
+
+def schur_apply(prob, H, x_G, y_G, opts=None, stream=None):
+    return prob.schur_apply(H, x_G, y_G, opts, stream)
+
+
+def precond_apply(prob, P, r_G, z_G, stream=None):
+    return prob.precond_apply(P, r_G, z_G, stream)
+
+
+def solve(prob, P, H, b, x, opts=None, stream=None):
+    return prob.solve(P, H, b, x, opts, stream)

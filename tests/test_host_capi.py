@@ -1,0 +1,117 @@
+"""Host-side checks of the C ABI (CPU only: no call here touches a GPU).
+
+The library must load, export every symbol its header declares, validate its arguments, and
+build rational tables whose error on the exact discrete spectrum (computed by the oracle)
+meets the requested tolerance.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import ra, spectral
+
+F = pytest.importorskip("paper_2211_15308_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return F.load()
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "fdd.h")).read()
+    return sorted(set(re.findall(r"\b(fdd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(lib):
+    syms = header_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(F.fdd.EXPORTED)
+
+
+def test_setup_validates_arguments():
+    for bad in ((3, 1.0, 1.0), (7, 1.0, 1.0), (64, 0.0, 1.0), (64, 1.0, -1.0), (64, float("nan"), 1.0)):
+        with pytest.raises(F.FddError) as e:
+            F.setup_mesh(*bad)
+        assert e.value.status == F.FDD_E_ARG
+    with pytest.raises(F.FddError) as e:
+        F.setup_mesh(64, 1.0, 1.0, dim=4)
+    assert e.value.status == F.FDD_E_ARG
+    # n whose coarsest multigrid grid would exceed 16 x 16 points (2 * 37 = 74 -> 73 -> 36)
+    with pytest.raises(F.FddError) as e:
+        F.setup_mesh(2 * 37 * 2, 1.0, 1.0)
+    assert e.value.status == F.FDD_E_ARG
+
+
+@pytest.mark.parametrize("n", [4, 8, 64, 96, 1024])
+def test_problem_info_matches_closed_form(n):
+    P = F.setup_mesh(n, 1.0, 1.0)
+    assert (P.N, P.NI, P.NG) == (n * (n - 1), (n - 1) ** 2, n - 1)
+    lam = spectral.interface_eigs_1d(n)
+    assert P.lam_lo == pytest.approx(lam[0], rel=1e-14)
+    assert P.lam_hi == pytest.approx(lam[-1], rel=1e-14)
+    assert P.workspace_bytes() > 0
+
+
+@pytest.mark.parametrize("n,K,mu", [(64, 1.0, 1.0), (256, 1e-2, 1e-3), (1024, 1.0, 1e-6),
+                                    (2048, 1e-4, 1e3), (96, 1e-4, 1.0)])
+def test_rational_tables_meet_tolerance_on_exact_spectrum(n, K, mu):
+    P = F.setup_mesh(n, K, mu)
+    lam = spectral.interface_eigs_1d(n)
+    TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12).query()
+    TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12).query()
+    fP = spectral.f_precond(K, 1.0 / mu)
+    eP = ra.max_rel_error(fP, TP["c0"], TP["c"], TP["p"], lam)
+    eH = ra.max_rel_error(spectral.g_operator, TH["c0"], TH["c"], TH["p"], lam)
+    assert eP <= 1e-11 and eH <= 1e-11
+    assert eP == pytest.approx(TP["max_rel_err"], rel=0.5, abs=1e-13)
+    assert min(TP["p"]) >= 0 and min(TH["p"]) >= 0
+    # lambda^{-1/2} is Stieltjes: its residues are positive; pole counts grow only with
+    # log(lam_hi / lam_lo), not with the interface dimension (Sec. 2, after eq. (RA))
+    assert min(TH["c"]) > 0
+    assert 12 <= TH["m"] <= 36 and TP["m"] <= 37
+    # positivity of the approximate inverse on the spectrum
+    assert np.all(ra.eval_scalar(TP["c0"], TP["c"], TP["p"], lam) > 0)
+
+
+def test_pole_count_grows_only_logarithmically():
+    ms = []
+    for n in (64, 256, 1024, 2048):
+        ms.append(F.setup_mesh(n, 1.0, 1.0).build_rational_pc(F.FDD_RA_OPERATOR, 1e-12).query()["m"])
+    assert ms == sorted(ms) or max(ms) - min(ms) <= 14
+    assert ms[-1] - ms[0] <= 14  # 32x more interface dofs, a handful more poles
+
+
+def test_table_injection_rejects_negative_shifts():
+    P = F.setup_mesh(64, 1.0, 1.0)
+    with pytest.raises(F.FddError) as e:
+        P.ratpc_from_table(F.FDD_RA_PRECOND, 0.0, [1.0, 2.0], [3.0, -5.0])
+    assert e.value.status == F.FDD_E_RA
+    T = P.ratpc_from_table(F.FDD_RA_PRECOND, 0.1, [1.0], [3.0])
+    assert T.query()["m"] == 1
+
+
+def test_calls_without_workspace_fail_cleanly(lib):
+    P = F.setup_mesh(64, 1.0, 1.0)
+    T = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-8)
+    rc = lib.fdd_precond_apply(P.h, T.h, ctypes.c_void_p(256), ctypes.c_void_p(512), None)
+    assert rc == F.FDD_E_WORKSPACE
+    # too small or misaligned workspace is rejected before any device call
+    assert lib.fdd_bind_workspace(P.h, ctypes.c_void_p(257), 1 << 30, None) == F.FDD_E_WORKSPACE
+    assert lib.fdd_bind_workspace(P.h, ctypes.c_void_p(256), 16, None) == F.FDD_E_WORKSPACE
+
+
+def test_table_of_another_problem_is_rejected(lib):
+    P = F.setup_mesh(64, 1.0, 1.0)
+    Q = F.setup_mesh(128, 1.0, 1.0)
+    T = Q.build_rational_pc(F.FDD_RA_OPERATOR, 1e-8)
+    P.workspace = None
+    rc = lib.fdd_schur_apply(P.h, T.h, ctypes.c_void_p(256), ctypes.c_void_p(512), None, None)
+    assert rc in (F.FDD_E_WORKSPACE, F.FDD_E_STATE)
