@@ -28,10 +28,12 @@ def parse():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--nu", type=int, default=1, help="red-black sweep pairs per level")
     ap.add_argument("--inner-rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cases", default="all", help="'all' or 'K,mu'")
+    ap.add_argument("--eager", action="store_true", help="launch kernels eagerly (no hipGraph replay)")
     return ap.parse_args()
 
 
@@ -84,7 +86,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     prec = F.FDD_MIXED if args.precision == "mixed" else F.FDD_FP64
-    opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, precision=prec)
+    opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, precision=prec,
+                          mg_nu=args.nu, use_graph=0 if args.eager else 1)
     case_list = cases(args)
     probs = []
     for ci, (K, mu) in enumerate(case_list):

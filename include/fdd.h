@@ -81,7 +81,8 @@ typedef struct {
   int inner_chunk;     /* FP32 PCG iterations per refinement step (mixed precision)            */
   int check_true_residual; /* nonzero: fdd_solve computes ||b - A x|| / ||b|| at the end       */
   void* warmstart;     /* reserved for the learned initial guess; must be NULL                 */
-  int use_graph;       /* reserved; must be 0                                                  */
+  int use_graph;       /* 1 (default): fdd_solve replays each outer iteration from a captured
+                          hipGraph on a library-owned stream ordered after `stream`; 0: eager */
 } fdd_opts;
 
 /* Per-solve statistics. */

@@ -8,7 +8,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -46,9 +48,16 @@ struct PcgSet {
   T* x = nullptr;
   T* r[2] = {nullptr, nullptr};
   T* p[2] = {nullptr, nullptr};
+  T* s[2] = {nullptr, nullptr};  // s = A p
   T* z = nullptr;
-  T* q = nullptr;
+  T* w = nullptr;                // w = A z
   MGBuffers<T> mg{};
+};
+
+// An instantiated graph of one outer iteration and the host-side buffer state after it.
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  int cur_r = 0, cur_p = 0, S = 0, k = 0;
 };
 
 }  // namespace
@@ -67,7 +76,8 @@ struct fdd_problem_s {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   DevState* st = nullptr;
-  double* partials = nullptr;
+  double* partials = nullptr;   // true-residual reduction
+  Reductions red{};
   float* cinv32 = nullptr;
   double* cinv64 = nullptr;
   PcgSet<float> s32;
@@ -82,8 +92,14 @@ struct fdd_problem_s {
   double* scratchP = nullptr;
   double* scratchH = nullptr;
   DevState* host_st = nullptr;  // pinned copy
-  // adaptive inner schedule
-  int sched_steps = 3, sched_its = 6, sched_its64 = 12;
+  // inner schedule (refinement steps x PCG iterations, or FP64 PCG iterations); only grows
+  int sched_steps = 1, sched_its = 2, sched_its64 = 4;
+  int sched_step_its[8] = {2, 2, 2, 2, 2, 2, 2, 2};  // per refinement step (mixed)
+  bool calibrated = false;  // the first interior solve runs every PCG to its own criterion
+  // captured outer iterations, keyed by (parity, schedule, precision, smoother)
+  std::map<std::tuple<int, int, int, int, int>, GraphEntry> graphs;
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
 struct fdd_ratpc_s {
@@ -109,7 +125,17 @@ size_t plan_workspace(fdd_problem_s* P, char* base) {
   const size_t v0 = (size_t)L0.nf * L0.pitch;
   P->st = (DevState*)take(sizeof(DevState));
   const int t0 = (L0.nf + kTile - 1) / kTile;
-  P->partials = (double*)take(sizeof(double) * (size_t)std::max(t0 * t0, 4096) * 2);
+  const size_t nb0 = (size_t)t0 * t0;
+  P->partials = (double*)take(sizeof(double) * 4096 * 2);
+  P->red.nb0 = (int)nb0;
+  P->red.pq = (double*)take(sizeof(double) * nb0);
+  P->red.rr = (double*)take(sizeof(double) * nb0);
+  P->red.rz[0] = (double*)take(sizeof(double) * nb0);
+  P->red.rz[1] = (double*)take(sizeof(double) * nb0);
+  P->red.zw[0] = (double*)take(sizeof(double) * nb0);
+  P->red.zw[1] = (double*)take(sizeof(double) * nb0);
+  P->red.ir = (double*)take(sizeof(double) * nb0);
+  P->red.ff = (double*)take(sizeof(double) * nb0);
   const int nfc = P->lev[P->nlev - 1].nf;
   P->cinv32 = (float*)take(sizeof(float) * (size_t)nfc * nfc * nfc * nfc);
   P->cinv64 = (double*)take(sizeof(double) * (size_t)nfc * nfc * nfc * nfc);
@@ -118,8 +144,9 @@ size_t plan_workspace(fdd_problem_s* P, char* base) {
     S.x = (T*)take(esz * v0);
     for (int k = 0; k < 2; ++k) S.r[k] = (T*)take(esz * v0);
     for (int k = 0; k < 2; ++k) S.p[k] = (T*)take(esz * v0);
+    for (int k = 0; k < 2; ++k) S.s[k] = (T*)take(esz * v0);
     S.z = (T*)take(esz * v0);
-    S.q = (T*)take(esz * v0);
+    S.w = (T*)take(esz * v0);
     S.mg.u[0] = (T*)take(esz * v0);
     S.mg.e[0] = S.z;
     S.mg.f[0] = nullptr;
@@ -196,7 +223,7 @@ LaunchCtx make_ctx(const fdd_problem_s* P, hipStream_t s, int nu, bool fp64) {
   c.coarse_inv = P->cinv32;
   c.coarse_inv64 = P->cinv64;
   c.st = P->st;
-  c.partials = P->partials;
+  c.red = P->red;
   return c;
 }
 
@@ -229,33 +256,74 @@ ShiftTable make_table(const fdd_ratpc_s* t) {
   return T;
 }
 
-struct InnerState {
-  int cur_r = 0, cur_p = 0;  // ping-pong parities of the level-0 PCG
-};
-
 bool opts_ok(const fdd_opts* o) {
   return o && o->outer_rtol > 0 && o->inner_rtol > 0 && o->outer_maxit > 0 &&
          o->inner_maxit > 0 && (o->precision == FDD_MIXED || o->precision == FDD_FP64) &&
          (o->mg_nu == 1 || o->mg_nu == 2) && o->inner_chunk > 0 && o->warmstart == nullptr &&
-         o->use_graph == 0;
+         (o->use_graph == 0 || o->use_graph == 1);
 }
 
 constexpr double kTau32 = 1e-5;  // FP32 PCG relative reduction per refinement step
 
-// Enqueue `steps` refinement steps (mixed) or `its` PCG iterations (FP64) of an interior solve.
-void enqueue_inner_mixed(fdd_problem_s* P, const LaunchCtx& c, const RhsDesc& f, InnerState& s,
-                         int steps, int its) {
-  auto& S = P->s32;
-  for (int st = 0; st < steps; ++st) {
-    launch_pcg_init<float>(c, S.mg, S.r[s.cur_r], S.z);
-    for (int k = 0; k < its; ++k) {
-      launch_pcg_iteration<float>(c, S.mg, S.x, S.r[s.cur_r], S.r[s.cur_r ^ 1], S.z,
-                                  S.p[s.cur_p], S.p[s.cur_p ^ 1], S.q);
-      s.cur_r ^= 1;
-      s.cur_p ^= 1;
+// Host-side record of an interior solve in flight: which buffers hold what.  Buffer parities
+// follow the enqueued schedule (kernels of a converged solve copy instead of skipping), so the
+// host always knows where the result is.
+struct InnerTrack {
+  bool fp64 = false;
+  RhsDesc f{};
+  int cur_r = 0, cur_p = 0;
+  int S = 0;  // refinement steps enqueued after the first residual (mixed precision)
+  int k = 0;  // PCG iterations enqueued in the running PCG (FP64)
+};
+
+const double* inner_u(const fdd_problem_s* P, const InnerTrack& t) {
+  return t.fp64 ? P->s64.x : P->u64[t.S & 1];
+}
+
+// First residual (u = 0) of an interior solve, and in FP64 the start of its PCG.
+void enqueue_inner_start(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, const fdd_opts& o) {
+  const double tol2 = o.inner_rtol * o.inner_rtol;
+  t.cur_r = t.cur_p = 0;
+  t.S = t.k = 0;
+  if (!t.fp64) {
+    launch_ir_residual(c, t.f, nullptr, nullptr, nullptr, P->u64[0], P->s32.r[t.cur_r], nullptr, 1,
+                       tol2, kTau32 * kTau32, 0);
+  } else {
+    launch_ir_residual(c, t.f, nullptr, nullptr, nullptr, P->u64[0], nullptr, P->s64.r[t.cur_r], 1,
+                       tol2, tol2, 1);
+    launch_pcg_init<double>(c, P->s64.mg, P->s64.r[t.cur_r], P->s64.z, P->s64.w);
+  }
+}
+
+// `steps` refinement steps of `its` FP32 PCG iterations (mixed; its < 0: the per-step
+// schedule), or `its` more FP64 iterations.
+void enqueue_inner_more(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, int steps, int its) {
+  if (!t.fp64) {
+    auto& S = P->s32;
+    for (int st = 0; st < steps; ++st) {
+      launch_pcg_init<float>(c, S.mg, S.r[t.cur_r], S.z, S.w);
+      const int n_its = its >= 0 ? its : (t.S < 8 ? P->sched_step_its[t.S] : P->sched_its);
+      for (int k = 0; k < n_its; ++k) {
+        launch_pcg_iteration<float>(c, S.mg, k, S.x, S.r[t.cur_r], S.r[t.cur_r ^ 1], S.z, S.w,
+                                    S.p[t.cur_p], S.p[t.cur_p ^ 1], S.s[t.cur_p],
+                                    S.s[t.cur_p ^ 1]);
+        t.cur_r ^= 1;
+        t.cur_p ^= 1;
+      }
+      launch_ir_residual(c, t.f, P->u64[t.S & 1], S.x, nullptr, P->u64[(t.S + 1) & 1],
+                         S.r[t.cur_r], nullptr, 0, 0, 0, 0);
+      t.S += 1;
     }
-    launch_ir_residual(c, f, P->u64[0], P->u64[1], S.x, nullptr, P->u64[0], P->u64[1],
-                       S.r[s.cur_r], nullptr, 0, 0, 0, 0);
+  } else {
+    auto& S = P->s64;
+    for (int k = 0; k < its; ++k) {
+      launch_pcg_iteration<double>(c, S.mg, t.k, S.x, S.r[t.cur_r], S.r[t.cur_r ^ 1], S.z, S.w,
+                                   S.p[t.cur_p], S.p[t.cur_p ^ 1], S.s[t.cur_p],
+                                   S.s[t.cur_p ^ 1]);
+      t.k += 1;
+      t.cur_r ^= 1;
+      t.cur_p ^= 1;
+    }
   }
 }
 
@@ -265,92 +333,70 @@ int read_state(fdd_problem_s* P, hipStream_t s) {
   return FDD_OK;
 }
 
-// A complete interior solve A_II u = f: enqueue the predicted schedule, synchronize, top up
-// until converged.  On return the solution is in the buffers given by inner_result().
-int interior_solve(fdd_problem_s* P, hipStream_t s, const RhsDesc& f, const fdd_opts& o,
-                   int* its_out, int* steps_out) {
-  const bool fp64 = (o.precision == FDD_FP64);
-  LaunchCtx c = make_ctx(P, s, o.mg_nu, fp64);
-  InnerState is;
-  const double tol2 = o.inner_rtol * o.inner_rtol;
-  if (!fp64) {
-    launch_ir_residual(c, f, P->u64[0], P->u64[1], nullptr, nullptr, P->u64[0], P->u64[1],
-                       P->s32.r[is.cur_r], nullptr, 1, tol2, kTau32 * kTau32, 0);
-    int steps = P->sched_steps, its = std::max(P->sched_its, 1);
-    int total_its_sched = 0;
-    for (int round = 0;; ++round) {
-      enqueue_inner_mixed(P, c, f, is, steps, its);
-      total_its_sched += steps * its;
-      int rc = read_state(P, s);
-      if (rc) return rc;
-      const DevState& h = *P->host_st;
-      if (h.breakdown) return fail(h.breakdown & 4 ? FDD_E_NONFINITE : FDD_E_BREAKDOWN,
-                                   "interior solve: breakdown flags %d", h.breakdown);
-      if (h.solve_done) {
-        if (its_out) *its_out = h.inner_its;
-        if (steps_out) *steps_out = h.refine_steps;
-        // adapt the schedule to what this solve needed
-        if (round == 0 && h.refine_steps > 0) {
-          P->sched_steps = h.refine_steps;
-          P->sched_its = std::max(1, (h.inner_its + h.refine_steps - 1) / h.refine_steps);
-        }
-        return FDD_OK;
+struct InnerResult {
+  int its = 0, steps = 0;
+};
+
+// After a synchronization: finish the interior solve tracked by t, topping up eagerly until it
+// has converged.  `enqueued_its` counts what the schedule allowed so far.
+int inner_finish(fdd_problem_s* P, hipStream_t s, InnerTrack& t, const fdd_opts& o,
+                 InnerResult* res) {
+  LaunchCtx c = make_ctx(P, s, o.mg_nu, t.fp64);
+  for (int round = 0;; ++round) {
+    const DevState& h = *P->host_st;
+    if (h.breakdown)
+      return fail(h.breakdown & 4 ? FDD_E_NONFINITE : FDD_E_BREAKDOWN,
+                  "interior solve: breakdown flags %d", h.breakdown);
+    if (h.solve_done) {
+      res->its = h.inner_its;
+      res->steps = h.refine_steps;
+      // the schedule only grows, so replays converge without top-ups once it has settled
+      if (!t.fp64) {
+        // one iteration of slack so that runs end on their own criterion, not on the schedule
+        P->sched_steps = std::max(P->sched_steps, std::max(h.refine_steps, 1));
+        P->sched_its = std::max(P->sched_its, h.run_its_max + 1);
+        for (int q = 0; q < std::min(h.refine_steps, 8); ++q)
+          P->sched_step_its[q] = std::max(P->sched_step_its[q], h.run_len[q] + 1);
+      } else {
+        P->sched_its64 = std::max(P->sched_its64, std::max(h.inner_its, 1));
       }
-      if (h.inner_its >= o.inner_maxit || total_its_sched > 4 * o.inner_maxit) {
-        if (its_out) *its_out = h.inner_its;
-        return fail(FDD_NOT_CONVERGED, "interior solve: %d iterations, residual %.3e of %.3e",
-                    h.inner_its, std::sqrt(h.res2), std::sqrt(h.ff));
-      }
-      // not yet: one more step at a time, with a longer PCG run
-      P->sched_steps = std::max(P->sched_steps, h.refine_steps + 1);
-      steps = 1;
-      its = std::max(its, 2 * P->sched_its);
+      return FDD_OK;
     }
-  } else {
-    auto& S = P->s64;
-    launch_ir_residual(c, f, P->u64[0], P->u64[1], nullptr, nullptr, P->u64[0], P->u64[1],
-                       nullptr, S.r[is.cur_r], 1, tol2, tol2, 1);
-    launch_pcg_init<double>(c, S.mg, S.r[is.cur_r], S.z);
-    int its = std::max(P->sched_its64, 1);
-    for (int round = 0;; ++round) {
-      for (int k = 0; k < its; ++k) {
-        launch_pcg_iteration<double>(c, S.mg, S.x, S.r[is.cur_r], S.r[is.cur_r ^ 1], S.z,
-                                     S.p[is.cur_p], S.p[is.cur_p ^ 1], S.q);
-        is.cur_r ^= 1;
-        is.cur_p ^= 1;
-      }
-      int rc = read_state(P, s);
-      if (rc) return rc;
-      const DevState& h = *P->host_st;
-      if (h.breakdown) return fail(h.breakdown & 4 ? FDD_E_NONFINITE : FDD_E_BREAKDOWN,
-                                   "interior solve: breakdown flags %d", h.breakdown);
-      if (h.solve_done) {
-        if (its_out) *its_out = h.inner_its;
-        if (steps_out) *steps_out = 0;
-        if (round == 0) P->sched_its64 = std::max(1, h.inner_its);
-        return FDD_OK;
-      }
-      if (h.inner_its >= o.inner_maxit) {
-        if (its_out) *its_out = h.inner_its;
-        return fail(FDD_NOT_CONVERGED, "interior solve (fp64): %d iterations", h.inner_its);
-      }
-      its = std::max(2, P->sched_its64 / 2);
-      P->sched_its64 += its;
+    if (h.inner_its >= o.inner_maxit || round > o.inner_maxit) {
+      res->its = h.inner_its;
+      return fail(FDD_NOT_CONVERGED, "interior solve: %d iterations, residual %.3e of %.3e",
+                  h.inner_its, std::sqrt(h.res2), std::sqrt(h.ff));
     }
+    if (!t.fp64) enqueue_inner_more(P, c, t, 1, std::max(P->sched_its, 30));
+    else enqueue_inner_more(P, c, t, 0, std::max(P->sched_its64 / 2, 2));
+    int rc = read_state(P, s);
+    if (rc) return rc;
   }
 }
 
-// where the last interior solution lives
-void inner_result(const fdd_problem_s* P, const fdd_opts& o, const double** u0, const double** u1,
-                  const int** sel) {
-  if (o.precision == FDD_FP64) {
-    *u0 = *u1 = P->s64.x;
-    *sel = nullptr;
+// A complete interior solve A_II u = f, eager launches.
+int interior_solve(fdd_problem_s* P, hipStream_t s, const RhsDesc& f, const fdd_opts& o,
+                   InnerTrack& t, InnerResult* res) {
+  const bool fp64 = (o.precision == FDD_FP64);
+  LaunchCtx c = make_ctx(P, s, o.mg_nu, fp64);
+  t = InnerTrack{};
+  t.fp64 = fp64;
+  t.f = f;
+  enqueue_inner_start(P, c, t, o);
+  if (!P->calibrated) {
+    // the first solve of a problem measures the schedule: long PCG runs, one step at a time
+    if (!fp64) enqueue_inner_more(P, c, t, 1, 30);
+    else enqueue_inner_more(P, c, t, 0, 60);
+  } else if (!fp64) {
+    enqueue_inner_more(P, c, t, P->sched_steps, -1);
   } else {
-    *u0 = P->u64[0];
-    *u1 = P->u64[1];
-    *sel = &P->st->refine_steps;
+    enqueue_inner_more(P, c, t, 0, P->sched_its64);
   }
+  int rc = read_state(P, s);
+  if (rc) return rc;
+  rc = inner_finish(P, s, t, o, res);
+  if (rc == FDD_OK) P->calibrated = true;
+  return rc;
 }
 
 int check_problem(fdd_problem_s* P) {
@@ -383,7 +429,7 @@ void fdd_opts_default(fdd_opts* o) {
   o->inner_chunk = 6;
   o->check_true_residual = 0;
   o->warmstart = nullptr;
-  o->use_graph = 0;
+  o->use_graph = 1;
 }
 
 const char* fdd_last_error(void) { return g_err.c_str(); }
@@ -568,13 +614,12 @@ int fdd_interior_solve(fdd_problem P, const double* f, double* u, const fdd_opts
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
-  RhsDesc rd{f, 1.0, nullptr, 0.0};
-  rc = interior_solve(P, s, rd, o, its, nullptr);
+  InnerTrack t;
+  InnerResult res;
+  rc = interior_solve(P, s, RhsDesc{f, 1.0, nullptr, 0.0}, o, t, &res);
+  if (its) *its = res.its;
   if (rc < 0) return rc;
-  const double *u0, *u1;
-  const int* sel;
-  inner_result(P, o, &u0, &u1, &sel);
-  launch_scatter(s, (int)P->NG, P->lev[0].pitch, u0, u1, sel, nullptr, u);
+  launch_scatter(s, (int)P->NG, P->lev[0].pitch, inner_u(P, t), nullptr, nullptr, nullptr, u);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   return rc;
@@ -605,17 +650,16 @@ int fdd_schur_apply(fdd_problem P, fdd_ratpc H, const double* x, double* y, cons
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
-  RhsDesc rd{nullptr, 0.0, x, 1.0};
-  rc = interior_solve(P, s, rd, o, nullptr, nullptr);
+  InnerTrack t;
+  InnerResult res;
+  rc = interior_solve(P, s, RhsDesc{nullptr, 0.0, x, 1.0}, o, t, &res);
   if (rc) return rc;
   ShiftTable tab = make_table(H);
   launch_iface_batch(s, (int)P->NG, P->h, tab, kIfaceOperator, x, P->Hp, P->scratchH, P->st,
                      nullptr, nullptr, 0, 0);
-  const double *u0, *u1;
-  const int* sel;
-  inner_result(P, o, &u0, &u1, &sel);
-  launch_schur_gather(s, (int)P->NG, P->lev[0].nf, P->lev[0].pitch, P->K, P->gamma, x, u0, u1,
-                      sel, P->Hp, y, nullptr, nullptr, nullptr, nullptr, P->st, 0, 0);
+  launch_schur_gather(s, (int)P->NG, P->lev[0].nf, P->lev[0].pitch, P->K, P->gamma, x,
+                      inner_u(P, t), nullptr, nullptr, P->Hp, y, nullptr, nullptr, nullptr,
+                      nullptr, P->st, 0, 0);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   return FDD_OK;
@@ -637,6 +681,74 @@ int fdd_apply_operator(fdd_problem P, fdd_ratpc H, const double* x, double* y, v
   return FDD_OK;
 }
 
+namespace {
+
+// One outer PCG step after the interior solve for the lifted p (version v -> v+1):
+// the Schur product y = S p, alpha, x and r updates, then z = P r, rho, beta and p.
+void enqueue_outer_tail(fdd_problem_s* P, hipStream_t s, const ShiftTable& tabP, const double* u,
+                        int v) {
+  const int a = v & 1, b = (v + 1) & 1;
+  launch_schur_gather(s, (int)P->NG, P->lev[0].nf, P->lev[0].pitch, P->K, P->gamma, P->pG[a], u,
+                      nullptr, nullptr, P->Hp, P->yG, P->xG[a], P->xG[b], P->rG[a], P->rG[b],
+                      P->st, 1, v);
+  launch_iface_batch(s, (int)P->NG, P->h, tabP, kIfacePrecondOuter, P->rG[b], P->zG, P->scratchP,
+                     P->st, P->pG[a], P->pG[b], v, 0);
+}
+
+// Everything of outer iteration v up to the synchronization: interior solve for the lifted p
+// (on the current schedule), H p, and the outer tail.
+void enqueue_outer_iteration(fdd_problem_s* P, hipStream_t s, const ShiftTable& tabP,
+                             const ShiftTable& tabH, const fdd_opts& o, int v, InnerTrack& t) {
+  const int a = v & 1;
+  LaunchCtx c = make_ctx(P, s, o.mg_nu, t.fp64);
+  t.f = RhsDesc{nullptr, 0.0, P->pG[a], 1.0};
+  enqueue_inner_start(P, c, t, o);
+  if (!t.fp64) enqueue_inner_more(P, c, t, P->sched_steps, -1);
+  else enqueue_inner_more(P, c, t, 0, P->sched_its64);
+  launch_iface_batch(s, (int)P->NG, P->h, tabH, kIfaceOperator, P->pG[a], P->Hp, P->scratchH,
+                     P->st, nullptr, nullptr, 0, 0);
+  enqueue_outer_tail(P, s, tabP, inner_u(P, t), v);
+}
+
+// Replays (capturing first if needed) the graph of outer iteration v for the current schedule.
+int launch_outer_graph(fdd_problem_s* P, hipStream_t s, const ShiftTable& tabP,
+                       const ShiftTable& tabH, const fdd_opts& o, int v, InnerTrack& t) {
+  int sched_code = P->sched_its64;
+  if (!t.fp64) {
+    sched_code = P->sched_steps;
+    for (int q = 0; q < 8; ++q) sched_code = sched_code * 37 + P->sched_step_its[q];
+  }
+  const auto key = std::make_tuple(v & 1, t.fp64 ? 0 : P->sched_steps, sched_code, (int)t.fp64,
+                                   o.mg_nu);
+  auto it = P->graphs.find(key);
+  if (it == P->graphs.end()) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    enqueue_outer_iteration(P, s, tabP, tabH, o, v, t);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess) return fail(FDD_E_HIP, "graph capture: %s", hipGetErrorString(e));
+    GraphEntry ge;
+    e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(FDD_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    ge.cur_r = t.cur_r;
+    ge.cur_p = t.cur_p;
+    ge.S = t.S;
+    ge.k = t.k;
+    it = P->graphs.emplace(key, ge).first;
+  }
+  // the tables are baked into the graph: they depend only on the problem
+  t.cur_r = it->second.cur_r;
+  t.cur_p = it->second.cur_p;
+  t.S = it->second.S;
+  t.k = it->second.k;
+  t.f = RhsDesc{nullptr, 0.0, P->pG[v & 1], 1.0};
+  HIPCHK(hipGraphLaunch(it->second.exec, s));
+  return FDD_OK;
+}
+
+}  // namespace
+
 int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double* x,
               const fdd_opts* opts, void* stream, fdd_stats* stats) {
   const auto t_start = std::chrono::steady_clock::now();
@@ -652,22 +764,34 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   else fdd_opts_default(&o);
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
   HIPCHK(hipSetDevice(P->device));
-  hipStream_t s = (hipStream_t)stream;
+  hipStream_t us = (hipStream_t)stream;
+  hipStream_t s = us;
+  if (o.use_graph) {
+    // graphs are captured and replayed on the library's own stream (default priority), ordered
+    // after the caller's stream at entry and before it at exit
+    if (!P->gstream) {
+      HIPCHK(hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&P->ev_out, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(P->ev_in, us));
+    HIPCHK(hipStreamWaitEvent(P->gstream, P->ev_in, 0));
+    s = P->gstream;
+  }
+  const bool fp64 = (o.precision == FDD_FP64);
   const int ng = (int)P->NG, nf = P->lev[0].nf, pitch = P->lev[0].pitch;
   const ShiftTable tabP = make_table(PT), tabH = make_table(HT);
-  const double *u0, *u1;
-  const int* sel;
-  inner_result(P, o, &u0, &u1, &sel);
-  auto inner = [&](const RhsDesc& f) -> int {
-    int its = 0, steps = 0;
-    int r = interior_solve(P, s, f, o, &its, &steps);
+  auto account = [&](const InnerResult& r) {
     st.inner_solves += 1;
-    st.inner_its_total += its;
-    st.inner_its_max = std::max(st.inner_its_max, its);
-    st.refine_steps += steps;
-    return r;
+    st.inner_its_total += r.its;
+    st.inner_its_max = std::max(st.inner_its_max, r.its);
+    st.refine_steps += r.steps;
   };
   auto finish = [&](int code) -> int {
+    if (o.use_graph) {
+      (void)hipEventRecord(P->ev_out, s);
+      (void)hipStreamWaitEvent(us, P->ev_out, 0);
+    }
     st.status = code;
     st.t_solve_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
@@ -675,9 +799,12 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
     return code;
   };
   // 1. g = b_G - A_GI A_II^{-1} b_I
-  rc = inner(RhsDesc{b, 1.0, nullptr, 0.0});
+  InnerTrack t;
+  InnerResult res;
+  rc = interior_solve(P, s, RhsDesc{b, 1.0, nullptr, 0.0}, o, t, &res);
+  account(res);
   if (rc) return finish(rc);
-  launch_rhs_reduce(s, ng, pitch, b + P->NI, u0, u1, sel, P->rG[0], P->xG[0]);
+  launch_rhs_reduce(s, ng, pitch, b + P->NI, inner_u(P, t), nullptr, nullptr, P->rG[0], P->xG[0]);
   // 2. outer PCG from x_G = 0: z = P r, rho0 = r.z, p = z
   launch_iface_batch(s, ng, P->h, tabP, kIfacePrecondOuter, P->rG[0], P->zG, P->scratchP, P->st,
                      nullptr, P->pG[0], 0, 1);
@@ -689,18 +816,29 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   double rho = rho0;
   bool converged = !(rho0 > 0.0);
   while (!converged && st.outer_its < o.outer_maxit) {
-    const int a = v & 1, bnx = (v + 1) & 1;
-    // interior solve for the lifted p, then H p, then the Schur product and the x/r updates
-    rc = inner(RhsDesc{nullptr, 0.0, P->pG[a], 1.0});
-    if (rc) return finish(rc);
-    launch_iface_batch(s, ng, P->h, tabH, kIfaceOperator, P->pG[a], P->Hp, P->scratchH, P->st,
-                       nullptr, nullptr, 0, 0);
-    launch_schur_gather(s, ng, nf, pitch, P->K, P->gamma, P->pG[a], u0, u1, sel, P->Hp, P->yG,
-                        P->xG[a], P->xG[bnx], P->rG[a], P->rG[bnx], P->st, 1, v);
-    launch_iface_batch(s, ng, P->h, tabP, kIfacePrecondOuter, P->rG[bnx], P->zG, P->scratchP,
-                       P->st, P->pG[a], P->pG[bnx], v, 0);
+    t = InnerTrack{};
+    t.fp64 = fp64;
+    if (o.use_graph) {
+      if ((rc = launch_outer_graph(P, s, tabP, tabH, o, v, t))) return finish(rc);
+    } else {
+      enqueue_outer_iteration(P, s, tabP, tabH, o, v, t);
+    }
     HIPCHK(hipGetLastError());
     if ((rc = read_state(P, s))) return finish(rc);
+    if (!P->host_st->solve_done && !P->host_st->breakdown) {
+      // the schedule was short for this right-hand side: finish the interior solve eagerly and
+      // redo the outer tail (it reads only version-v vectors, so it can be repeated)
+      rc = inner_finish(P, s, t, o, &res);
+      account(res);
+      if (rc) return finish(rc);
+      enqueue_outer_tail(P, s, tabP, inner_u(P, t), v);
+      HIPCHK(hipGetLastError());
+      if ((rc = read_state(P, s))) return finish(rc);
+    } else {
+      rc = inner_finish(P, s, t, o, &res);
+      account(res);
+      if (rc) return finish(rc);
+    }
     const DevState& h = *P->host_st;
     if (h.breakdown)
       return finish(fail(h.breakdown & 4 ? FDD_E_NONFINITE : FDD_E_BREAKDOWN,
@@ -713,9 +851,10 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   }
   st.rel_precond_res = rho0 > 0 ? std::sqrt(std::max(rho, 0.0) / rho0) : 0.0;
   // 3. back-substitution x_I = A_II^{-1} (b_I / K - A_IG x_G)
-  rc = inner(RhsDesc{b, 1.0 / P->K, P->xG[v & 1], 1.0});
+  rc = interior_solve(P, s, RhsDesc{b, 1.0 / P->K, P->xG[v & 1], 1.0}, o, t, &res);
+  account(res);
   if (rc) return finish(rc);
-  launch_scatter(s, nf, pitch, u0, u1, sel, P->xG[v & 1], x);
+  launch_scatter(s, nf, pitch, inner_u(P, t), nullptr, nullptr, P->xG[v & 1], x);
   if (o.check_true_residual) {
     launch_iface_batch(s, ng, P->h, tabH, kIfaceOperator, x + P->NI, P->Hp, P->scratchH, P->st,
                        nullptr, nullptr, 0, 0);
@@ -731,6 +870,11 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
 
 void fdd_destroy_problem(fdd_problem P) {
   if (!P) return;
+  for (auto& kv : P->graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  if (P->gstream) (void)hipStreamDestroy(P->gstream);
+  if (P->ev_in) (void)hipEventDestroy(P->ev_in);
+  if (P->ev_out) (void)hipEventDestroy(P->ev_out);
   if (P->host_st) (void)hipHostFree(P->host_st);
   delete P;
 }

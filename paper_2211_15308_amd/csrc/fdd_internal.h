@@ -45,17 +45,18 @@ struct DevState {
   double o_rho0;
   double o_pq, o_alpha, o_beta;
   double t_res[2];   // true residual: ||b - A x||^2, ||b||^2
-  double pad0;
+  double cg_alpha[2];  // step length of the inner PCG, by iteration parity
   // counters / flags
   int inner_done;    // the running multigrid-PCG has converged (or broke down)
   int solve_done;    // the interior solve has met its tolerance
   int inner_its;     // multigrid-PCG iterations of the current interior solve
-  int pcg_k;         // iteration index inside the current PCG run
+  int pcg_k;         // iterations executed in the current PCG run
   int refine_steps;  // refinement steps of the current interior solve (also buffer parity)
   int breakdown;     // bit 0: inner breakdown, bit 1: outer breakdown, bit 2: non-finite
   int pcg_is_final;  // FP64 mode: the PCG residual is the interior solve's residual
-  int pad1;
-  unsigned counters[16];   // last-block reduction tickets, one per kernel kind
+  int run_its_max;   // largest iteration count of a PCG run in this interior solve
+  int run_len[8];    // PCG iterations of each refinement step's run (first 8 steps)
+  unsigned counters[16];   // ticket of the true-residual reduction
 };
 
 // Right-hand side of an interior solve, formed on the fly:
@@ -74,6 +75,17 @@ struct MGBuffers {
   T* e[kMaxLevels];   // result of the V-cycle per level (level 0: z)
 };
 
+// Per-block partial sums of the level-0 reductions (each has one slot per level-0 tile).
+struct Reductions {
+  double* pq;      // unused slot (kept for layout)
+  double* rr;      // ||r||^2 after the update
+  double* rz[2];   // r . z, by iteration parity
+  double* zw[2];   // z . A z, by iteration parity
+  double* ir;      // ||f - A u||^2 of the refinement residual
+  double* ff;      // ||f||^2
+  int nb0;         // number of level-0 tiles
+};
+
 struct LaunchCtx {
   hipStream_t stream;
   int nlev;
@@ -83,21 +95,24 @@ struct LaunchCtx {
   const float* coarse_inv; // dense inverse on the coarsest level (nfc^2 x nfc^2), FP32
   const double* coarse_inv64;
   DevState* st;
-  double* partials;        // per-block partial sums
+  Reductions red;
 };
 
 // ---- multigrid-PCG (kernels_mg.hip) --------------------------------------------------------
 template <typename T>
-void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z_out);
+void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z_out, T* w_out);
+// Iteration k of the inner PCG in its single-reduction (Chronopoulos-Gear) form: z = V r and
+// w = A z come from the previous V-cycle; p = z + beta p', s = w + beta s' (s = A p), x += alpha p,
+// r -= alpha s, then the V-cycle of the new r yields the next z, w and the dots r.z, z.w.
 template <typename T>
-void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, T* x, T* r_old, T* r_new,
-                          T* z, T* p_old, T* p_new, T* q);
+void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
+                          T* r_new, T* z, T* w, T* p_old, T* p_new, T* s_old, T* s_new);
 
-// FP64 refinement residual.  Buffers u0/u1 alternate with the refinement-step parity:
-// u_next = u_cur + e (the first call sets u0 = 0), r = f - A u_next.
-void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* u0, const double* u1,
-                        const float* e32, const double* e64, double* w0, double* w1, float* r32,
-                        double* r64, int first, double tol2, double tau2, int pcg_is_final);
+// FP64 refinement residual plus its one-block finalize: uout = uin + e (uout = 0 on the first
+// call; a plain copy once the solve has converged), r = f - A uout.
+void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin, const float* e32,
+                        const double* e64, double* uout, float* r32, double* r64, int first,
+                        double tol2, double tau2, int pcg_is_final);
 
 // ---- interface kernels (kernels_iface.hip) -------------------------------------------------
 struct ShiftTable {

@@ -6,8 +6,8 @@
 // poles plus M_G^{-1} r; each is a symmetric diagonally dominant tridiagonal system.  One
 // workgroup per system solves it by parallel cyclic reduction in LDS (rows normalized so the
 // diagonal is 1; ceil(log2(n-1)) elimination steps, each a neighbour exchange at distance 2^s).
-// The weighted sum over systems is formed by the last workgroup to finish, in a fixed order, and
-// fused with the epilogue (outer-PCG update, or the mass products of the operator H).
+// A single-workgroup kernel then forms the weighted sum over systems in a fixed order, fused with
+// the epilogue (outer-PCG update, or the mass products of the operator H).
 #include "fdd_internal.h"
 
 namespace fdd {
@@ -38,17 +38,13 @@ __device__ __forceinline__ double mass_apply(const double* v, int n, double h, i
   return (h / 6.0) * (4.0 * v[i] + l + r);
 }
 
-// One batch of shifted systems.  Block k solves (alpha_k A_G + beta_k M_G) y_k = rhs and stores
-// coef_k y_k in scratch[k]; the last block sums them (k ascending) and applies the epilogue.
-//   mode kIfacePrecond:      out = sum
-//   mode kIfaceOperator:     rhs = M p (p = in), out = d0 M p + M sum   (= H_RA p)
-//   mode kIfacePrecondOuter: out = z = sum; rho_new = r.z; p_next = z + beta p_prev
-__global__ __launch_bounds__(kIfaceThreads) void k_iface_batch(
-    int n, double h, ShiftTable tab, int mode, const double* __restrict__ in,
-    double* __restrict__ out, double* __restrict__ scratch, DevState* st,
-    const double* __restrict__ p_prev, double* __restrict__ p_next, int ver, int first) {
+// One batch of shifted systems: block k solves (alpha_k A_G + beta_k M_G) y_k = rhs and stores
+// coef_k y_k in scratch[k].  mode kIfaceOperator takes rhs = M p (p = in), otherwise rhs = in.
+__global__ __launch_bounds__(kIfaceThreads) void k_iface_solve(int n, double h, ShiftTable tab,
+                                                               int mode,
+                                                               const double* __restrict__ in,
+                                                               double* __restrict__ scratch) {
   __shared__ double sa[kIfaceMaxN], sc[kIfaceMaxN], sd[kIfaceMaxN];
-  __shared__ int s_last;
   const int k = blockIdx.x;
   const double al = tab.alpha[k], be = tab.beta[k];
   const double off = -al / h + be * h / 6.0;
@@ -92,23 +88,20 @@ __global__ __launch_bounds__(kIfaceThreads) void k_iface_batch(
   }
   const double ck = tab.coef[k];
   for (int i = threadIdx.x; i < n; i += blockDim.x) scratch[(size_t)k * n + i] = ck * sd[i];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned t = __hip_atomic_fetch_add(&st->counters[8], 1u, __ATOMIC_ACQ_REL,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (t == gridDim.x - 1);
-    if (s_last) {
-      __threadfence();
-      __hip_atomic_store(&st->counters[8], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-  __syncthreads();
-  if (!s_last) return;
-  // fixed-order sum over the systems
+}
+
+// One block: sum of the m weighted solutions (k ascending) and the epilogue.
+//   mode kIfacePrecond:      out = sum
+//   mode kIfaceOperator:     out = d0 M p + M sum   (= H_RA p, p = in)
+//   mode kIfacePrecondOuter: out = z = sum; rho_new = r.z (r = in); p_next = z + beta p_prev
+__global__ __launch_bounds__(kIfaceThreads) void k_iface_combine(
+    int n, double h, int m, double d0, int mode, const double* __restrict__ in,
+    double* __restrict__ out, const double* __restrict__ scratch, DevState* st,
+    const double* __restrict__ p_prev, double* __restrict__ p_next, int ver, int first) {
+  __shared__ double sd[kIfaceMaxN];
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double v = 0.0;
-    for (int kk = 0; kk < (int)gridDim.x; ++kk) v += scratch[(size_t)kk * n + i];
+    for (int kk = 0; kk < m; ++kk) v += scratch[(size_t)kk * n + i];
     sd[i] = v;
   }
   __syncthreads();
@@ -116,9 +109,8 @@ __global__ __launch_bounds__(kIfaceThreads) void k_iface_batch(
     for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = sd[i];
   } else if (mode == kIfaceOperator) {
     for (int i = threadIdx.x; i < n; i += blockDim.x)
-      out[i] = tab.d0 * mass_apply(in, n, h, i) + mass_apply(sd, n, h, i);
+      out[i] = d0 * mass_apply(in, n, h, i) + mass_apply(sd, n, h, i);
   } else {
-    // outer PCG: z = sum, rho_new = r . z, p_next = z + beta p_prev
     double rz = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       out[i] = sd[i];
@@ -293,8 +285,10 @@ __global__ __launch_bounds__(256) void k_full_operator(int n, double K, double g
 void launch_iface_batch(hipStream_t s, int ng, double h, const ShiftTable& tab, int mode,
                         const double* in, double* out, double* scratch, DevState* st,
                         const double* p_prev, double* p_next, int ver, int first) {
-  hipLaunchKernelGGL(k_iface_batch, dim3(tab.m), dim3(kIfaceThreads), 0, s, ng, h, tab, mode, in,
-                     out, scratch, st, p_prev, p_next, ver, first);
+  hipLaunchKernelGGL(k_iface_solve, dim3(tab.m), dim3(kIfaceThreads), 0, s, ng, h, tab, mode, in,
+                     scratch);
+  hipLaunchKernelGGL(k_iface_combine, dim3(1), dim3(kIfaceThreads), 0, s, ng, h, tab.m, tab.d0,
+                     mode, in, out, scratch, st, p_prev, p_next, ver, first);
 }
 
 void launch_schur_gather(hipStream_t s, int ng, int nf, int pitch, double K, double gamma,

@@ -12,10 +12,15 @@
 //     (pre-smooth from zero, residual, restriction) and one going up (prolongation + correction,
 //     post-smooth).  Halo cells are recomputed redundantly so that a tile never waits on a
 //     neighbour.  Levels with at most 63 x 63 points run in one workgroup entirely in LDS.
-//   - The PCG vector updates are fused into the level-0 kernels; dot products are reduced
-//     deterministically (per-block partials, the last block to arrive sums them in order).
-//   - Scalars and convergence flags stay on the device; every kernel returns at once when its
-//     solve has converged, so the host can enqueue a schedule without reading anything back.
+//   - The PCG runs in its single-reduction form (Chronopoulos and Gear 1989): the vector updates
+//     are fused into the level-0 down kernel, w = A z into the level-0 up kernel, and r . z and
+//     z . A z are reduced together, so an iteration is one V-cycle and nothing else.
+//   - Dot products are reduced without atomics or fences: every block stores its partial sum,
+//     and each block of the kernel that needs the scalar sums all partials in the same fixed
+//     order (kernel boundaries make the partials visible), so every block sees bit-identical
+//     scalars and the result is deterministic.
+//   - Scalars and flags stay on the device; every kernel returns at once when its solve has
+//     converged, so the host can enqueue (or replay as a graph) a fixed schedule.
 #include "fdd_internal.h"
 
 namespace fdd {
@@ -26,52 +31,58 @@ namespace fdd {
 
 __device__ __forceinline__ bool is_red(int i, int j) { return ((i + j) & 1) == 0; }
 
-// Sum over the block (kBlock threads); result valid in thread 0.
-__device__ __forceinline__ double block_sum(double v) {
-  __shared__ double sh[kCoarseThreads / 64];
+__device__ __forceinline__ int flat_tid() { return threadIdx.y * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ int nthreads() { return blockDim.x * blockDim.y; }
+
+// Sum over the block, broadcast to every thread (fixed order: deterministic).
+__device__ __forceinline__ double block_sum_all(double v) {
+  __shared__ double sh[kCoarseThreads / 64 + 1];
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int t = flat_tid();
+  const int lane = t & 63, wid = t >> 6;
   __syncthreads();
   if (lane == 0) sh[wid] = v;
   __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0) {
-    const int nw = (int)(blockDim.x >> 6);
+  if (t == 0) {
+    double s = 0.0;
+    const int nw = (nthreads() + 63) >> 6;
     for (int w = 0; w < nw; ++w) s += sh[w];
-  }
-  return s;
-}
-
-// Stores this block's partial and reports whether the block is the last one to arrive.  In
-// the last block, partials of all blocks are visible after the call.
-__device__ __forceinline__ bool arrive(double partial, double* partials, unsigned* counter,
-                                       unsigned nblocks, unsigned bid) {
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
-    partials[bid] = partial;
-    __threadfence();
-    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    int last = (t == nblocks - 1);
-    if (last) {
-      __threadfence();
-      __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    s_last = last;
+    sh[kCoarseThreads / 64] = s;
   }
   __syncthreads();
-  return s_last != 0;
+  return sh[kCoarseThreads / 64];
 }
 
-// Fixed-order sum of the partials (call from every thread of the last block).
-__device__ __forceinline__ double gather_partials(const double* partials, unsigned nblocks) {
+// Fixed-order sum of nb partials, identical in every block of equal size.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int nb) {
   double v = 0.0;
-  for (unsigned k = threadIdx.x; k < nblocks; k += blockDim.x)
-    v += __builtin_nontemporal_load(partials + k);
-  return block_sum(v);
+  for (int k = flat_tid(); k < nb; k += nthreads()) v += p[k];
+  return block_sum_all(v);
 }
+
+__device__ __forceinline__ bool block0() { return blockIdx.x == 0 && blockIdx.y == 0; }
+__device__ __forceinline__ bool thread0() { return threadIdx.x == 0 && threadIdx.y == 0; }
 
 __device__ __forceinline__ bool stopped(const DevState* st) {
   return (st->inner_done | st->solve_done) != 0;
+}
+
+// Convergence test of the running PCG from the partials of ||r||^2 (stored by the level-0
+// down kernel).  Called by every block of the first kernel after it; returns true if the run
+// is over (converged or broken down).
+__device__ __forceinline__ bool pcg_converged(DevState* st, const Reductions& red) {
+  const double rr = sum_partials(red.rr, red.nb0);
+  const bool bad = !isfinite(rr);
+  const bool conv = bad || rr <= st->tau2 * st->rr0;
+  if (block0() && thread0()) {
+    st->rr = rr;
+    if (bad) st->breakdown |= 4;
+    if (conv) {
+      st->inner_done = 1;
+      if (st->pcg_is_final) st->solve_done = 1;
+    }
+  }
+  return conv;
 }
 
 template <typename T>
@@ -89,367 +100,461 @@ __device__ __forceinline__ T prolong(const T* ec, int pc, int nc, int i, int j) 
   return T(0.5) * (gload(ec, pc, nc, I, J) + gload(ec, pc, nc, I + 1, J + 1));
 }
 
-// --------------------------------------------------------------------------------------------
-// fused level kernels
-// --------------------------------------------------------------------------------------------
-
-// Going down one level: u = S^nu(0; f) (red first), r = f - A u, f_c = P^T r.
-// CG = true (level 0 inside PCG): f is r_new = r_old - alpha q, computed on the window; the
-// tile also updates x += alpha p on its own points, stores r_new, and reduces ||r_new||^2.
-template <typename T, int NU, bool CG>
-__global__ __launch_bounds__(kBlock) void k_mg_down(
-    const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
-    int pc, const T* __restrict__ q, T* __restrict__ x, const T* __restrict__ p,
-    T* __restrict__ rout, DevState* st, double* partials) {
-  constexpr int H = 2 * NU + 1;
-  constexpr int W = kTile + 2 * H;
-  __shared__ T sf[W][W + 1];
-  __shared__ T su[W][W + 1];
-  if (stopped(st)) return;
-  const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
-  const int ib = i0 + 1 - H, jb = j0 + 1 - H;  // global index of window cell (0, 0)
-  const int tid = threadIdx.x;
-  T alpha = T(0);
-  bool first = false;
-  if (CG) {
-    const double pq = st->pq, rho = st->rho;
-    first = (st->pcg_k == 0);
-    alpha = (pq > 0.0 && isfinite(pq)) ? (T)(rho / pq) : T(0);
-  }
-  double rr = 0.0;
-  for (int idx = tid; idx < W * W; idx += kBlock) {
-    const int li = idx % W, lj = idx / W;
-    const int i = ib + li, j = jb + lj;
-    T f = T(0);
-    if (i >= 1 && i <= nf && j >= 1 && j <= nf) {
-      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-      if (CG) {
-        f = fin[o] - alpha * q[o];
-        if (li >= H && li < H + kTile && lj >= H && lj < H + kTile) {
-          rout[o] = f;
-          x[o] = first ? alpha * p[o] : x[o] + alpha * p[o];
-          rr += (double)f * (double)f;
-        }
-      } else {
-        f = fin[o];
-      }
-    }
-    sf[lj][li] = f;
-    // first red half-sweep from a zero iterate: u = f / 4 on red points, 0 on black points
-    su[lj][li] = is_red(i, j) ? T(0.25) * f : T(0);
-  }
-  __syncthreads();
-  // remaining half-sweeps: black, red, black, ...
-  for (int s = 1; s < 2 * NU; ++s) {
-    const bool red = !(s & 1);
-    for (int idx = tid; idx < W * W; idx += kBlock) {
-      const int li = idx % W, lj = idx / W;
-      const int i = ib + li, j = jb + lj;
-      if (li < 1 || li > W - 2 || lj < 1 || lj > W - 2) continue;
-      if (is_red(i, j) != red || i < 1 || i > nf || j < 1 || j > nf) continue;
+// one red or black half-sweep over the window cells 1..W-2 that lie inside the domain
+template <typename T, int W>
+__device__ __forceinline__ void tile_halfsweep(T (*su)[W + 1], const T (*sf)[W + 1], int ib, int jb,
+                                               int nf, bool red) {
+  for (int lj = 1 + threadIdx.y; lj < W - 1; lj += blockDim.y) {
+    const int j = jb + lj;
+    if (j < 1 || j > nf) continue;
+    for (int li = 1 + threadIdx.x; li < W - 1; li += blockDim.x) {
+      const int i = ib + li;
+      if (i < 1 || i > nf || is_red(i, j) != red) continue;
       su[lj][li] = T(0.25) * (sf[lj][li] + su[lj][li - 1] + su[lj][li + 1] + su[lj - 1][li] +
                               su[lj + 1][li]);
     }
-    __syncthreads();
   }
+  __syncthreads();
+}
+
+// --------------------------------------------------------------------------------------------
+// fused level kernels
+// --------------------------------------------------------------------------------------------
+// Thread layout of the tiled kernels: 32 x 8 threads; a window of W x W cells is covered by
+// RY x RX register slots per thread, cell (ty + 8 a, tx + 32 b).  All global loads of a window
+// are issued into registers before the first use, so a block waits for one memory latency.
+
+template <int W>
+struct Slots {
+  static constexpr int RY = (W + 7) / 8;
+  static constexpr int RX = (W + 31) / 32;
+};
+
+// Going down one level: u = S^nu(0; f) (red first), r = f - A u, f_c = P^T r.
+// CG = true (level 0, inner PCG iteration k, single-reduction form):
+//   gamma_k = r_k . z_k and delta_k = z_k . w_k come from the partials of the previous V-cycle;
+//   beta_k = gamma_k / gamma_{k-1}, alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1})
+//   (beta_0 = 0, alpha_0 = gamma_0 / delta_0).  On the window s_k = w_k + beta_k s_{k-1} and
+//   f = r_{k+1} = r_k - alpha_k s_k; on own points p_k = z_k + beta_k p_{k-1}, x += alpha_k p_k,
+//   and r_{k+1}, s_k, p_k are stored; ||r_{k+1}||^2 goes to red.rr.
+// check != 0 (first kernel after the level-0 down kernel): returns if the PCG has converged.
+template <typename T, int NU, bool CG>
+__global__ __launch_bounds__(kBlock) void k_mg_down(
+    const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
+    int pc, const T* __restrict__ w, const T* __restrict__ sold, T* __restrict__ snew,
+    const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ x,
+    T* __restrict__ rout, DevState* st, Reductions red, int k, int check) {
+  constexpr int H = 2 * NU + 1;
+  constexpr int W = kTile + 2 * H;
+  constexpr int RY = Slots<W>::RY, RX = Slots<W>::RX;
+  __shared__ T sf[W][W + 1];
+  __shared__ T su[W][W + 1];
+  if (stopped(st)) return;
+  if (check && pcg_converged(st, red)) return;
+  const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
+  const int ib = i0 + 1 - H, jb = j0 + 1 - H;  // global index of window cell (0, 0)
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  T fr[RY][RX], wr[RY][RX], sr[RY][RX], zr[RY][RX], pr[RY][RX], xr[RY][RX];
+#pragma unroll
+  for (int a = 0; a < RY; ++a) {
+#pragma unroll
+    for (int b = 0; b < RX; ++b) {
+      const int lj = ty + 8 * a, li = tx + 32 * b;
+      const int i = ib + li, j = jb + lj;
+      const bool in = lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+      fr[a][b] = in ? fin[o] : T(0);
+      if (CG) {
+        const bool own = in && li >= H && li < H + kTile && lj >= H && lj < H + kTile;
+        wr[a][b] = in ? w[o] : T(0);
+        sr[a][b] = (in && k > 0) ? sold[o] : T(0);
+        zr[a][b] = own ? z[o] : T(0);
+        pr[a][b] = (own && k > 0) ? pold[o] : T(0);
+        xr[a][b] = (own && k > 0) ? x[o] : T(0);
+      }
+    }
+  }
+  T alpha = T(0), beta = T(0);
+  if (CG) {
+    const double gam = sum_partials(red.rz[k & 1], red.nb0);
+    const double del = sum_partials(red.zw[k & 1], red.nb0);
+    double b = 0.0, den = del;
+    if (k > 0) {
+      const double gam_prev = sum_partials(red.rz[(k - 1) & 1], red.nb0);
+      b = gam / gam_prev;
+      den = del - b * gam / st->cg_alpha[(k - 1) & 1];
+    }
+    if (!(gam > 0.0) || !(den > 0.0) || !isfinite(den) || !isfinite(gam)) {
+      // gamma = 0: the residual is exactly zero and the run is over; otherwise a breakdown
+      if (block0() && thread0()) {
+        if (gam != 0.0) st->breakdown |= (isfinite(den) && isfinite(gam)) ? 1 : 4;
+        st->inner_done = 1;
+      }
+      return;
+    }
+    const double al = gam / den;
+    if (block0() && thread0()) st->cg_alpha[k & 1] = al;
+    alpha = (T)al;
+    beta = (T)b;
+  }
+  double rr = 0.0;
+#pragma unroll
+  for (int a = 0; a < RY; ++a) {
+#pragma unroll
+    for (int b = 0; b < RX; ++b) {
+      const int lj = ty + 8 * a, li = tx + 32 * b;
+      if (lj >= W || li >= W) continue;
+      const int i = ib + li, j = jb + lj;
+      T f = fr[a][b];
+      if (CG) {
+        const T sv = wr[a][b] + beta * sr[a][b];
+        f = f - alpha * sv;
+        const bool own = li >= H && li < H + kTile && lj >= H && lj < H + kTile && i >= 1 &&
+                         i <= nf && j >= 1 && j <= nf;
+        if (own) {
+          const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+          const T pv = zr[a][b] + beta * pr[a][b];
+          rout[o] = f;
+          snew[o] = sv;
+          pnew[o] = pv;
+          x[o] = xr[a][b] + alpha * pv;
+          rr += (double)f * (double)f;
+        }
+      }
+      sf[lj][li] = f;
+      // first red half-sweep from a zero iterate: u = f / 4 on red points, 0 on black points
+      su[lj][li] = is_red(i, j) ? T(0.25) * f : T(0);
+    }
+  }
+  __syncthreads();
+  for (int s = 1; s < 2 * NU; ++s) tile_halfsweep<T, W>(su, sf, ib, jb, nf, !(s & 1));
   // residual, in place of f (each point reads its own f and the neighbours' u)
-  for (int idx = tid; idx < W * W; idx += kBlock) {
-    const int li = idx % W, lj = idx / W;
-    if (li < 1 || li > W - 2 || lj < 1 || lj > W - 2) continue;
-    sf[lj][li] = sf[lj][li] - (T(4) * su[lj][li] - su[lj][li - 1] - su[lj][li + 1] -
-                               su[lj - 1][li] - su[lj + 1][li]);
-  }
+  for (int lj = 1 + ty; lj < W - 1; lj += 8)
+    for (int li = 1 + tx; li < W - 1; li += 32)
+      sf[lj][li] = sf[lj][li] - (T(4) * su[lj][li] - su[lj][li - 1] - su[lj][li + 1] -
+                                 su[lj - 1][li] - su[lj + 1][li]);
   __syncthreads();
   // restriction to the coarse points whose fine index 2I lies in this tile
   const int nc = (nf - 1) >> 1;
   constexpr int TC = kTile / 2;
-  for (int idx = tid; idx < TC * TC; idx += kBlock) {
-    const int a = idx % TC, b = idx / TC;
-    const int I = (i0 >> 1) + 1 + a, J = (j0 >> 1) + 1 + b;
-    if (I > nc || J > nc) continue;
+  for (int bb = ty; bb < TC; bb += 8) {
+    const int J = (j0 >> 1) + 1 + bb;
+    const int I = (i0 >> 1) + 1 + tx;
+    if (J > nc || tx >= TC || I > nc) continue;
     const int li = 2 * I - ib, lj = 2 * J - jb;
     const T v = sf[lj][li] + T(0.5) * (sf[lj][li - 1] + sf[lj][li + 1] + sf[lj - 1][li] +
                                        sf[lj + 1][li] + sf[lj - 1][li - 1] + sf[lj + 1][li + 1]);
     fc[(size_t)(J - 1) * pc + (I - 1)] = v;
   }
   // store the pre-smoothed iterate on own points
-  for (int idx = tid; idx < kTile * kTile; idx += kBlock) {
-    const int a = idx % kTile, b = idx / kTile;
-    const int i = i0 + 1 + a, j = j0 + 1 + b;
-    if (i > nf || j > nf) continue;
-    uout[(size_t)(j - 1) * pitch + (i - 1)] = su[b + H][a + H];
+  for (int bb = ty; bb < kTile; bb += 8) {
+    const int j = j0 + 1 + bb, i = i0 + 1 + tx;
+    if (j > nf || i > nf) continue;
+    uout[(size_t)(j - 1) * pitch + (i - 1)] = su[bb + H][tx + H];
   }
   if (CG) {
-    const double tot = block_sum(rr);
-    const unsigned nb = gridDim.x * gridDim.y, bid = blockIdx.y * gridDim.x + blockIdx.x;
-    if (arrive(tot, partials, &st->counters[1], nb, bid)) {
-      const double rr_all = gather_partials(partials, nb);
-      if (threadIdx.x == 0) {
-        st->rr = rr_all;
-        st->inner_its += 1;
-        st->pcg_k += 1;
-        const double pq = st->pq;
-        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rr_all)) {
-          st->breakdown |= isfinite(rr_all) ? 1 : 4;
-          st->inner_done = 1;
-        } else if (rr_all <= st->tau2 * st->rr0) {
-          st->inner_done = 1;
-          if (st->pcg_is_final) st->solve_done = 1;  // FP64 mode: the PCG residual is the solve's residual
-        }
-      }
-    }
+    const double tot = block_sum_all(rr);
+    if (thread0()) red.rr[blockIdx.y * gridDim.x + blockIdx.x] = tot;
   }
 }
 
 // Going up one level: u = u_pre + P e_c, then nu (black, red) pairs; result to eout.
-// CG = true (level 0): also reduces r . z over own points (f is r, the result is z).
+// CG = true (level 0): the result z is kept valid one cell beyond the tile, so that w = A z is
+// formed on own points too; z and w are stored and the block's parts of r . z and z . w go to
+// red.rz[kn & 1] and red.zw[kn & 1] (f is r).
 template <typename T, int NU, bool CG>
 __global__ __launch_bounds__(kBlock) void k_mg_up(
     const T* __restrict__ fin, const T* __restrict__ upre, const T* __restrict__ ec,
-    T* __restrict__ eout, int nf, int pitch, int pc, DevState* st, double* partials) {
-  constexpr int H = 2 * NU;
+    T* __restrict__ eout, T* __restrict__ wout, int nf, int pitch, int pc, DevState* st,
+    Reductions red, int kn, int count_iteration) {
+  constexpr int H = 2 * NU + (CG ? 1 : 0);
   constexpr int W = kTile + 2 * H;
+  constexpr int RY = Slots<W>::RY, RX = Slots<W>::RX;
+  constexpr int CW = W / 2 + 2;  // coarse patch edge
+  constexpr int CRY = Slots<CW>::RY, CRX = Slots<CW>::RX;
   __shared__ T sf[W][W + 1];
   __shared__ T su[W][W + 1];
+  __shared__ T sc[CW][CW + 1];
   if (stopped(st)) return;
   const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
   const int ib = i0 + 1 - H, jb = j0 + 1 - H;
+  const int Ib = ib >> 1, Jb = jb >> 1;  // floor (arithmetic shift)
   const int nc = (nf - 1) >> 1;
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < W * W; idx += kBlock) {
-    const int li = idx % W, lj = idx / W;
-    const int i = ib + li, j = jb + lj;
-    T f = T(0), u = T(0);
-    if (i >= 1 && i <= nf && j >= 1 && j <= nf) {
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  T fr[RY][RX], ur[RY][RX], cr[CRY][CRX];
+#pragma unroll
+  for (int a = 0; a < RY; ++a) {
+#pragma unroll
+    for (int b = 0; b < RX; ++b) {
+      const int lj = ty + 8 * a, li = tx + 32 * b;
+      const int i = ib + li, j = jb + lj;
+      const bool in = lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
       const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-      f = fin[o];
-      u = upre[o] + prolong(ec, pc, nc, i, j);
+      fr[a][b] = in ? fin[o] : T(0);
+      ur[a][b] = in ? upre[o] : T(0);
     }
-    sf[lj][li] = f;
-    su[lj][li] = u;
+  }
+#pragma unroll
+  for (int a = 0; a < CRY; ++a) {
+#pragma unroll
+    for (int b = 0; b < CRX; ++b) {
+      const int lj = ty + 8 * a, li = tx + 32 * b;
+      const int I = Ib + li, J = Jb + lj;
+      const bool in = lj < CW && li < CW && I >= 1 && I <= nc && J >= 1 && J <= nc;
+      cr[a][b] = in ? ec[(size_t)(J - 1) * pc + (I - 1)] : T(0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < CRY; ++a)
+#pragma unroll
+    for (int b = 0; b < CRX; ++b) {
+      const int lj = ty + 8 * a, li = tx + 32 * b;
+      if (lj < CW && li < CW) sc[lj][li] = cr[a][b];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < RY; ++a) {
+#pragma unroll
+    for (int b = 0; b < RX; ++b) {
+      const int lj = ty + 8 * a, li = tx + 32 * b;
+      if (lj >= W || li >= W) continue;
+      const int i = ib + li, j = jb + lj;
+      T u = T(0);
+      if (i >= 1 && i <= nf && j >= 1 && j <= nf) {
+        // P1 interpolation of the coarse correction (nested diagonal-split meshes)
+        const int ci = (i >> 1) - Ib, cj = (j >> 1) - Jb;
+        T e;
+        if (!(i & 1) && !(j & 1)) e = sc[cj][ci];
+        else if ((i & 1) && !(j & 1)) e = T(0.5) * (sc[cj][ci] + sc[cj][ci + 1]);
+        else if (!(i & 1) && (j & 1)) e = T(0.5) * (sc[cj][ci] + sc[cj + 1][ci]);
+        else e = T(0.5) * (sc[cj][ci] + sc[cj + 1][ci + 1]);
+        u = ur[a][b] + e;
+      }
+      sf[lj][li] = fr[a][b];
+      su[lj][li] = u;
+    }
   }
   __syncthreads();
-  for (int s = 0; s < 2 * NU; ++s) {
-    const bool red = (s & 1);  // black first
-    for (int idx = tid; idx < W * W; idx += kBlock) {
-      const int li = idx % W, lj = idx / W;
-      const int i = ib + li, j = jb + lj;
-      if (li < 1 || li > W - 2 || lj < 1 || lj > W - 2) continue;
-      if (is_red(i, j) != red || i < 1 || i > nf || j < 1 || j > nf) continue;
-      su[lj][li] = T(0.25) * (sf[lj][li] + su[lj][li - 1] + su[lj][li + 1] + su[lj - 1][li] +
-                              su[lj + 1][li]);
+  for (int s = 0; s < 2 * NU; ++s) tile_halfsweep<T, W>(su, sf, ib, jb, nf, (s & 1));
+  double rz = 0.0, zw = 0.0;
+  for (int bb = ty; bb < kTile; bb += 8) {
+    const int j = j0 + 1 + bb, i = i0 + 1 + tx;
+    if (j > nf || i > nf) continue;
+    const int lj = bb + H, li = tx + H;
+    const T zv = su[lj][li];
+    const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+    eout[o] = zv;
+    if (CG) {
+      const T wv = T(4) * zv - su[lj][li - 1] - su[lj][li + 1] - su[lj - 1][li] - su[lj + 1][li];
+      wout[o] = wv;
+      rz += (double)sf[lj][li] * (double)zv;
+      zw += (double)zv * (double)wv;
     }
-    __syncthreads();
-  }
-  double rz = 0.0;
-  for (int idx = tid; idx < kTile * kTile; idx += kBlock) {
-    const int a = idx % kTile, b = idx / kTile;
-    const int i = i0 + 1 + a, j = j0 + 1 + b;
-    if (i > nf || j > nf) continue;
-    const T z = su[b + H][a + H];
-    eout[(size_t)(j - 1) * pitch + (i - 1)] = z;
-    if (CG) rz += (double)sf[b + H][a + H] * (double)z;
   }
   if (CG) {
-    const double tot = block_sum(rz);
-    const unsigned nb = gridDim.x * gridDim.y, bid = blockIdx.y * gridDim.x + blockIdx.x;
-    if (arrive(tot, partials, &st->counters[2], nb, bid)) {
-      const double rz_all = gather_partials(partials, nb);
-      if (threadIdx.x == 0) {
-        st->rho_old = st->rho;
-        st->rho = rz_all;
-        if (!(rz_all > 0.0) || !isfinite(rz_all)) {
-          // r = 0 exactly gives rho = 0: nothing left to do; otherwise an indefinite V-cycle
-          if (rz_all != 0.0) st->breakdown |= isfinite(rz_all) ? 1 : 4;
-          st->inner_done = 1;
-        }
+    const double trz = block_sum_all(rz);
+    const double tzw = block_sum_all(zw);
+    if (thread0()) {
+      const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+      red.rz[kn & 1][bid] = trz;
+      red.zw[kn & 1][bid] = tzw;
+      if (count_iteration && block0()) {
+        st->inner_its += 1;
+        st->pcg_k += 1;
+        st->run_its_max = max(st->run_its_max, st->pcg_k);
       }
     }
-  }
-}
-
-// p_new = z + beta p_old (beta = rho / rho_old, 0 on the first iteration), q = A p_new, p.q.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pcg_spmv(const T* __restrict__ z,
-                                                     const T* __restrict__ pold,
-                                                     T* __restrict__ pnew, T* __restrict__ q,
-                                                     int nf, int pitch, DevState* st,
-                                                     double* partials) {
-  constexpr int W = kTile + 2;
-  __shared__ T sp[W][W + 1];
-  if (stopped(st)) return;
-  const bool first = (st->pcg_k == 0);
-  const T beta = first ? T(0) : (T)(st->rho / st->rho_old);
-  const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
-  const int ib = i0, jb = j0;
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < W * W; idx += kBlock) {
-    const int li = idx % W, lj = idx / W;
-    const int i = ib + li, j = jb + lj;
-    T v = T(0);
-    if (i >= 1 && i <= nf && j >= 1 && j <= nf) {
-      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-      v = first ? z[o] : z[o] + beta * pold[o];
-    }
-    sp[lj][li] = v;
-  }
-  __syncthreads();
-  double pq = 0.0;
-  for (int idx = tid; idx < kTile * kTile; idx += kBlock) {
-    const int a = idx % kTile, b = idx / kTile;
-    const int i = i0 + 1 + a, j = j0 + 1 + b;
-    if (i > nf || j > nf) continue;
-    const int li = a + 1, lj = b + 1;
-    const T pv = sp[lj][li];
-    const T qv = T(4) * pv - sp[lj][li - 1] - sp[lj][li + 1] - sp[lj - 1][li] - sp[lj + 1][li];
-    const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-    pnew[o] = pv;
-    q[o] = qv;
-    pq += (double)pv * (double)qv;
-  }
-  const double tot = block_sum(pq);
-  const unsigned nb = gridDim.x * gridDim.y, bid = blockIdx.y * gridDim.x + blockIdx.x;
-  if (arrive(tot, partials, &st->counters[3], nb, bid)) {
-    const double pq_all = gather_partials(partials, nb);
-    if (threadIdx.x == 0) st->pq = pq_all;
   }
 }
 
 // --------------------------------------------------------------------------------------------
 // coarse levels in one workgroup
 // --------------------------------------------------------------------------------------------
+// Each level lives in LDS with a one-cell zero border ((nf + 2)^2 cells, row pitch nf + 2), so
+// stencils need no bounds tests.  The 1024 threads form a 32 x 32 grid; thread (tx, ty) owns the
+// points (tx + 1 + 32 a, ty + 1 + 32 b) of a level, at most 2 x 2 of them (nf <= 63).
+
+constexpr int kCinvLds = 64;  // coarsest inverses up to 64 x 64 are staged in LDS
 
 template <typename T>
-struct CoarseLds;  // sizes of the in-LDS hierarchy
+struct CoarseLds;  // padded sizes of the in-LDS hierarchy
 template <>
 struct CoarseLds<float> {
   static constexpr int kMaxNf = 63;
-  static constexpr int kElems = 63 * 63 + 31 * 31 + 15 * 15 + 7 * 7 + 3 * 3 + 1 + 64;
+  static constexpr int kElems = 65 * 65 + 33 * 33 + 17 * 17 + 9 * 9 + 5 * 5 + 3 * 3 + 128;
 };
 template <>
 struct CoarseLds<double> {
   static constexpr int kMaxNf = 31;
-  static constexpr int kElems = 31 * 31 + 15 * 15 + 7 * 7 + 3 * 3 + 1 + 64;
+  static constexpr int kElems = 33 * 33 + 17 * 17 + 9 * 9 + 5 * 5 + 3 * 3 + 128;
 };
 
+// one red or black half-sweep of a padded level
 template <typename T>
-__device__ __forceinline__ T lds_at(const T* a, int nf, int i, int j) {
-  return (i >= 1 && i <= nf && j >= 1 && j <= nf) ? a[(j - 1) * nf + (i - 1)] : T(0);
-}
-
-template <typename T>
-__device__ void lds_halfsweep(T* u, const T* f, int nf, bool red) {
-  const int npts = nf * nf;
-  for (int k = threadIdx.x; k < npts; k += blockDim.x) {
-    const int i = k % nf + 1, j = k / nf + 1;
-    if (is_red(i, j) != red) continue;
-    u[k] = T(0.25) * (f[k] + lds_at(u, nf, i - 1, j) + lds_at(u, nf, i + 1, j) +
-                      lds_at(u, nf, i, j - 1) + lds_at(u, nf, i, j + 1));
-  }
+__device__ __forceinline__ void lds_halfsweep(T* u, const T* f, int nf, bool red) {
+  const int pw = nf + 2;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
+      if (i > nf || j > nf || is_red(i, j) != red) continue;
+      const int o = j * pw + i;
+      u[o] = T(0.25) * (f[o] + u[o - 1] + u[o + 1] + u[o - pw] + u[o + pw]);
+    }
   __syncthreads();
 }
 
 // Levels first..nlev-1 entirely in LDS: V-cycle from the right-hand side fin (level `first`,
 // global memory) to the result eout (global).  The coarsest level is solved exactly with the
-// dense inverse cinv (nfc^2 x nfc^2, row-major).
+// dense inverse cinv (nfc^2 x nfc^2, row-major), staged in LDS when small.
 template <typename T, int NU>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(
     const T* __restrict__ fin, int pin, T* __restrict__ eout, LaunchLevels lv,
-    const T* __restrict__ cinv, DevState* st) {
+    const T* __restrict__ cinv, DevState* st, Reductions red, int check) {
   __shared__ T buf[2 * CoarseLds<T>::kElems];
+  __shared__ T scinv[kCinvLds * kCinvLds];
   if (stopped(st)) return;
+  if (check && pcg_converged(st, red)) return;
   const int first = lv.first, last = lv.nlev - 1;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   T* uL[kMaxLevels];
   T* fL[kMaxLevels];
-  {
-    int off = 0;
-    for (int l = first; l <= last; ++l) {
-      const int np = lv.nf[l] * lv.nf[l];
-      uL[l] = buf + off;
-      off += np;
-      fL[l] = buf + off;
-      off += np;
-    }
+  int tot = 0;
+  for (int l = first; l <= last; ++l) {
+    const int pw = lv.nf[l] + 2;
+    uL[l] = buf + tot;
+    fL[l] = buf + tot + pw * pw;
+    tot += 2 * pw * pw;
   }
-  // load the right-hand side of the first in-LDS level
-  {
-    const int nf = lv.nf[first];
-    for (int k = threadIdx.x; k < nf * nf; k += blockDim.x) {
-      const int i = k % nf, j = k / nf;
-      fL[first][k] = fin[(size_t)j * pin + i];
+  // issue the loads of the first level's right-hand side and of a small inverse first
+  const int nf0 = lv.nf[first];
+  T v[2][2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
+      v[b][a] = (i <= nf0 && j <= nf0) ? fin[(size_t)(j - 1) * pin + (i - 1)] : T(0);
     }
+  const int npc = lv.nf[last] * lv.nf[last];
+  if (npc <= kCinvLds) {
+    constexpr int RC = kCinvLds * kCinvLds / kCoarseThreads;
+    T cv[RC];
+#pragma unroll
+    for (int t = 0; t < RC; ++t) {
+      const int k = threadIdx.x + t * kCoarseThreads;
+      cv[t] = k < npc * npc ? cinv[k] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < RC; ++t) scinv[threadIdx.x + t * kCoarseThreads] = cv[t];
+  }
+  for (int k = threadIdx.x; k < tot; k += blockDim.x) buf[k] = T(0);
+  __syncthreads();
+  {
+    const int pw = nf0 + 2;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
+        if (i <= nf0 && j <= nf0) fL[first][j * pw + i] = v[b][a];
+      }
   }
   __syncthreads();
-  // down
+  // down: pre-smooth from zero (red first), restrict the residual
   for (int l = first; l < last; ++l) {
     const int nf = lv.nf[l], nc = lv.nf[l + 1];
+    const int pw = nf + 2, pcw = nc + 2;
     T* u = uL[l];
-    T* f = fL[l];
-    for (int k = threadIdx.x; k < nf * nf; k += blockDim.x) {
-      const int i = k % nf + 1, j = k / nf + 1;
-      u[k] = is_red(i, j) ? T(0.25) * f[k] : T(0);
-    }
+    const T* f = fL[l];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
+        if (i <= nf && j <= nf && is_red(i, j)) u[j * pw + i] = T(0.25) * f[j * pw + i];
+      }
     __syncthreads();
     for (int s = 1; s < 2 * NU; ++s) lds_halfsweep(u, f, nf, !(s & 1));
-    // residual into the coarse right-hand side buffer's neighbour: compute on the fly
-    T* fcb = fL[l + 1];
-    for (int k = threadIdx.x; k < nc * nc; k += blockDim.x) {
-      const int I = k % nc + 1, J = k / nc + 1;
-      T acc = T(0);
-      const int di[7] = {0, -1, 1, 0, 0, -1, 1};
-      const int dj[7] = {0, 0, 0, -1, 1, -1, 1};
+    // coarse points: one per thread (nc <= 31)
+    {
+      const int I = tx + 1, J = ty + 1;
+      if (I <= nc && J <= nc) {
+        const int di[7] = {0, -1, 1, 0, 0, -1, 1};
+        const int dj[7] = {0, 0, 0, -1, 1, -1, 1};
+        T acc = T(0);
 #pragma unroll
-      for (int t = 0; t < 7; ++t) {
-        const int i = 2 * I + di[t], j = 2 * J + dj[t];
-        const T r = lds_at(f, nf, i, j) -
-                    (T(4) * lds_at(u, nf, i, j) - lds_at(u, nf, i - 1, j) -
-                     lds_at(u, nf, i + 1, j) - lds_at(u, nf, i, j - 1) - lds_at(u, nf, i, j + 1));
-        acc += (t == 0 ? T(1) : T(0.5)) * r;
+        for (int t = 0; t < 7; ++t) {
+          const int o = (2 * J + dj[t]) * pw + (2 * I + di[t]);
+          const T r = f[o] - (T(4) * u[o] - u[o - 1] - u[o + 1] - u[o - pw] - u[o + pw]);
+          acc += (t == 0 ? T(1) : T(0.5)) * r;
+        }
+        fL[l + 1][J * pcw + I] = acc;
       }
-      fcb[k] = acc;
     }
     __syncthreads();
   }
-  // coarsest: exact solve with the dense inverse
+  // coarsest: exact solve with the dense inverse; the right-hand side is first packed densely
+  // (into the zero border-free tail of the buffer) so the product runs without index arithmetic
   {
-    const int nf = lv.nf[last];
+    const int nf = lv.nf[last], pw = nf + 2;
     const int np = nf * nf;
+    T* u = uL[last];
+    const T* f = fL[last];
+    T* fpk = buf + tot;  // room after the last level: np <= 256 cells
+    for (int k = threadIdx.x; k < np; k += blockDim.x) fpk[k] = f[(k / nf + 1) * pw + (k % nf + 1)];
+    __syncthreads();
     for (int k = threadIdx.x; k < np; k += blockDim.x) {
       T acc = T(0);
-      for (int m = 0; m < np; ++m) acc += cinv[(size_t)k * np + m] * fL[last][m];
-      uL[last][k] = acc;
+      if (np <= kCinvLds) {
+#pragma unroll 7
+        for (int m = 0; m < np; ++m) acc += scinv[k * np + m] * fpk[m];
+      } else {
+#pragma unroll 8
+        for (int m = 0; m < np; ++m) acc += cinv[(size_t)k * np + m] * fpk[m];
+      }
+      u[(k / nf + 1) * pw + (k % nf + 1)] = acc;
     }
     __syncthreads();
   }
-  // up
+  // up: prolongate and correct, post-smooth (black first)
   for (int l = last - 1; l >= first; --l) {
-    const int nf = lv.nf[l], nc = lv.nf[l + 1];
+    const int nf = lv.nf[l], pw = nf + 2, pcw = lv.nf[l + 1] + 2;
     T* u = uL[l];
     const T* ec = uL[l + 1];
-    for (int k = threadIdx.x; k < nf * nf; k += blockDim.x) {
-      const int i = k % nf + 1, j = k / nf + 1;
-      const int I = i >> 1, J = j >> 1;
-      T e;
-      if (!(i & 1) && !(j & 1)) e = lds_at(ec, nc, I, J);
-      else if ((i & 1) && !(j & 1)) e = T(0.5) * (lds_at(ec, nc, I, J) + lds_at(ec, nc, I + 1, J));
-      else if (!(i & 1) && (j & 1)) e = T(0.5) * (lds_at(ec, nc, I, J) + lds_at(ec, nc, I, J + 1));
-      else e = T(0.5) * (lds_at(ec, nc, I, J) + lds_at(ec, nc, I + 1, J + 1));
-      u[k] += e;
-    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
+        if (i > nf || j > nf) continue;
+        const int o = (j >> 1) * pcw + (i >> 1);
+        T e;
+        if (!(i & 1) && !(j & 1)) e = ec[o];
+        else if ((i & 1) && !(j & 1)) e = T(0.5) * (ec[o] + ec[o + 1]);
+        else if (!(i & 1) && (j & 1)) e = T(0.5) * (ec[o] + ec[o + pcw]);
+        else e = T(0.5) * (ec[o] + ec[o + pcw + 1]);
+        u[j * pw + i] += e;
+      }
     __syncthreads();
     for (int s = 0; s < 2 * NU; ++s) lds_halfsweep(u, fL[l], nf, (s & 1));
   }
   {
-    const int nf = lv.nf[first];
-    for (int k = threadIdx.x; k < nf * nf; k += blockDim.x) {
-      const int i = k % nf, j = k / nf;
-      eout[(size_t)j * pin + i] = uL[first][k];
-    }
+    const int pw = nf0 + 2;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
+        if (i <= nf0 && j <= nf0) eout[(size_t)(j - 1) * pin + (i - 1)] = uL[first][j * pw + i];
+      }
   }
 }
 
 // --------------------------------------------------------------------------------------------
-// FP64 residual of the interior solve (iterative refinement) and right-hand side set-up
+// FP64 residual of the interior solve (iterative refinement)
 // --------------------------------------------------------------------------------------------
 
 __device__ __forceinline__ double rhs_at(const RhsDesc& f, int nf, int i, int j) {
@@ -459,80 +564,110 @@ __device__ __forceinline__ double rhs_at(const RhsDesc& f, int nf, int i, int j)
   return v;
 }
 
-// u_out = u_in + e (u_in = 0 on the first call), r = f - A u_out (written as FP32 or FP64),
-// ||r||^2 reduced in FP64; the last block updates the refinement state.
+// first: u_out = 0, r = f.  Otherwise u_out = u_in + e and r = f - A u_out, or, once the solve
+// has converged, the copy u_out = u_in (so buffer parity follows the schedule).  r is written as
+// FP32 or FP64; the block's ||r||^2 goes to red.ir (and red.ff on the first call).
 template <typename E>
-__global__ __launch_bounds__(kBlock) void k_ir_residual(RhsDesc f, const double* __restrict__ u0,
-                                                        const double* __restrict__ u1,
-                                                        const E* __restrict__ e,
-                                                        double* __restrict__ w0,
-                                                        double* __restrict__ w1,
-                                                        float* __restrict__ r32,
-                                                        double* __restrict__ r64, int nf,
-                                                        int pitch, int first, double tol2,
-                                                        double tau2, int pcg_is_final,
-                                                        DevState* st, double* partials) {
+__global__ __launch_bounds__(kBlock) void k_ir_residual(
+    RhsDesc f, const double* __restrict__ uin, const E* __restrict__ e, double* __restrict__ uout,
+    float* __restrict__ r32, double* __restrict__ r64, int nf, int pitch, int first, double tol2,
+    double tau2, int pcg_is_final, DevState* st, Reductions red) {
   constexpr int W = kTile + 2;
   __shared__ double su[W][W + 1];
-  if (!first && st->solve_done) return;
-  const int cur = st->refine_steps & 1;  // parity selects the current buffer
-  const double* uin = first ? nullptr : (cur ? u1 : u0);
-  double* uout = first ? w0 : (cur ? w0 : w1);
   const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < W * W; idx += kBlock) {
-    const int li = idx % W, lj = idx / W;
-    const int i = i0 + li, j = j0 + lj;
-    double v = 0.0;
-    if (i >= 1 && i <= nf && j >= 1 && j <= nf && !first) {
-      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-      v = uin[o] + (e ? (double)e[o] : 0.0);
+  if (!first && st->solve_done) {
+    for (int b = threadIdx.y; b < kTile; b += blockDim.y) {
+      const int j = j0 + 1 + b;
+      if (j > nf) continue;
+      for (int a = threadIdx.x; a < kTile; a += blockDim.x) {
+        const int i = i0 + 1 + a;
+        if (i > nf) continue;
+        const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+        uout[o] = uin[o];
+      }
     }
-    su[lj][li] = v;
+    return;
   }
+  constexpr int RY = Slots<W>::RY, RX = Slots<W>::RX;
+  double ur[RY][RX];
+#pragma unroll
+  for (int a = 0; a < RY; ++a) {
+#pragma unroll
+    for (int b = 0; b < RX; ++b) {
+      const int lj = threadIdx.y + 8 * a, li = threadIdx.x + 32 * b;
+      const int i = i0 + li, j = j0 + lj;
+      const bool in = !first && lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+      ur[a][b] = in ? uin[o] + (double)e[o] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < RY; ++a)
+#pragma unroll
+    for (int b = 0; b < RX; ++b) {
+      const int lj = threadIdx.y + 8 * a, li = threadIdx.x + 32 * b;
+      if (lj < W && li < W) su[lj][li] = ur[a][b];
+    }
   __syncthreads();
   double rr = 0.0;
-  for (int idx = tid; idx < kTile * kTile; idx += kBlock) {
-    const int a = idx % kTile, b = idx / kTile;
-    const int i = i0 + 1 + a, j = j0 + 1 + b;
-    if (i > nf || j > nf) continue;
-    const int li = a + 1, lj = b + 1;
-    const double u = su[lj][li];
-    const double r = rhs_at(f, nf, i, j) -
-                     (4.0 * u - su[lj][li - 1] - su[lj][li + 1] - su[lj - 1][li] - su[lj + 1][li]);
-    const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-    uout[o] = u;
-    if (r32) r32[o] = (float)r;
-    if (r64) r64[o] = r;
-    rr += r * r;
+  for (int b = threadIdx.y; b < kTile; b += blockDim.y) {
+    const int j = j0 + 1 + b;
+    if (j > nf) continue;
+    for (int a = threadIdx.x; a < kTile; a += blockDim.x) {
+      const int i = i0 + 1 + a;
+      if (i > nf) continue;
+      const int li = a + 1, lj = b + 1;
+      const double u = su[lj][li];
+      const double r = rhs_at(f, nf, i, j) - (4.0 * u - su[lj][li - 1] - su[lj][li + 1] -
+                                              su[lj - 1][li] - su[lj + 1][li]);
+      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+      uout[o] = u;
+      if (r32) r32[o] = (float)r;
+      if (r64) r64[o] = r;
+      rr += r * r;
+    }
   }
-  const double tot = block_sum(rr);
-  const unsigned nb = gridDim.x * gridDim.y, bid = blockIdx.y * gridDim.x + blockIdx.x;
-  if (arrive(tot, partials, &st->counters[4], nb, bid)) {
-    const double res = gather_partials(partials, nb);
-    if (threadIdx.x == 0) {
+  const double tot = block_sum_all(rr);
+  if (thread0()) {
+    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+    red.ir[bid] = tot;
+    if (first) red.ff[bid] = tot;
+    if (bid == 0) {
       if (first) {
         st->tol2 = tol2;
         st->tau2 = tau2;
         st->pcg_is_final = pcg_is_final;
         st->breakdown = 0;
-        st->ff = res;
-        st->refine_steps = 0;
         st->inner_its = 0;
-        st->solve_done = (res == 0.0) ? 1 : 0;
+        st->refine_steps = 0;
+        st->run_its_max = 0;
+        for (int q = 0; q < 8; ++q) st->run_len[q] = 0;
+        st->solve_done = 0;
       } else {
+        if (st->refine_steps < 8) st->run_len[st->refine_steps] = st->pcg_k;
         st->refine_steps += 1;
       }
-      st->res2 = res;
-      st->rr0 = res;
-      st->pcg_k = 0;
-      st->inner_done = 0;
-      if (!isfinite(res)) {
-        st->breakdown |= 4;
-        st->solve_done = 1;
-      } else if (res <= st->tol2 * st->ff) {
-        st->solve_done = 1;
-      }
+    }
+  }
+}
+
+// One block: reads the refinement residual back from the partials and sets the solve's state
+// for the next PCG run (or ends the solve).
+__global__ __launch_bounds__(kBlock) void k_ir_finalize(DevState* st, Reductions red) {
+  if (st->solve_done) return;
+  const double res = sum_partials(red.ir, red.nb0);
+  const double ff = sum_partials(red.ff, red.nb0);
+  if (thread0()) {
+    st->ff = ff;
+    st->res2 = res;
+    st->rr0 = res;
+    st->inner_done = 0;
+    st->pcg_k = 0;
+    if (!isfinite(res)) {
+      st->breakdown |= 4;
+      st->solve_done = 1;
+    } else if (res <= st->tol2 * ff) {
+      st->solve_done = 1;
     }
   }
 }
@@ -545,17 +680,19 @@ static inline dim3 tiles(int nf) {
   const int t = (nf + kTile - 1) / kTile;
   return dim3(t, t);
 }
+static inline dim3 tblock() { return dim3(32, kBlock / 32); }
 
 template <typename T, int NU>
-static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg) {
-  // levels 1 .. first_coarse-1 go down, the coarse kernel, then back up to level 1
+static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check) {
+  // levels 1 .. first_coarse-1 go down, the coarse kernel, then back up to level 1; the first
+  // of these kernels also runs the PCG convergence test when `check` is set
   const int fc = c.first_coarse;
   for (int l = 1; l < fc; ++l) {
     const Level& L = c.lev[l];
-    hipLaunchKernelGGL((k_mg_down<T, NU, false>), tiles(L.nf), dim3(kBlock), 0, c.stream,
-                       mg.f[l], mg.u[l], mg.f[l + 1], L.nf, L.pitch, c.lev[l + 1].pitch,
-                       (const T*)nullptr, (T*)nullptr, (const T*)nullptr, (T*)nullptr, c.st,
-                       c.partials);
+    hipLaunchKernelGGL((k_mg_down<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, mg.f[l],
+                       mg.u[l], mg.f[l + 1], L.nf, L.pitch, c.lev[l + 1].pitch, (const T*)nullptr,
+                       (const T*)nullptr, (T*)nullptr, (const T*)nullptr, (const T*)nullptr,
+                       (T*)nullptr, (T*)nullptr, (T*)nullptr, c.st, c.red, 0, l == 1 ? check : 0);
   }
   LaunchLevels lv;
   lv.first = fc;
@@ -565,80 +702,77 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg) {
   if constexpr (sizeof(T) == 4) cinv = (const T*)c.coarse_inv;
   else cinv = (const T*)c.coarse_inv64;
   hipLaunchKernelGGL((k_coarse_vcycle<T, NU>), dim3(1), dim3(kCoarseThreads), 0, c.stream,
-                     mg.f[fc], c.lev[fc].pitch, mg.e[fc], lv, cinv, c.st);
+                     mg.f[fc], c.lev[fc].pitch, mg.e[fc], lv, cinv, c.st, c.red,
+                     fc == 1 ? check : 0);
   for (int l = fc - 1; l >= 1; --l) {
     const Level& L = c.lev[l];
-    hipLaunchKernelGGL((k_mg_up<T, NU, false>), tiles(L.nf), dim3(kBlock), 0, c.stream, mg.f[l],
-                       mg.u[l], mg.e[l + 1], mg.e[l], L.nf, L.pitch, c.lev[l + 1].pitch, c.st,
-                       c.partials);
+    hipLaunchKernelGGL((k_mg_up<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, mg.f[l],
+                       mg.u[l], mg.e[l + 1], mg.e[l], (T*)nullptr, L.nf, L.pitch,
+                       c.lev[l + 1].pitch, c.st, c.red, 0, 0);
   }
 }
 
+template <typename T, int NU>
+static void pcg_init_nu(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z, T* w) {
+  const Level& L = c.lev[0];
+  hipLaunchKernelGGL((k_mg_down<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, r, mg.u[0],
+                     mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)nullptr, (const T*)nullptr,
+                     (T*)nullptr, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (T*)nullptr,
+                     (T*)nullptr, c.st, c.red, 0, 0);
+  vcycle_tail_nu<T, NU>(c, mg, 0);
+  hipLaunchKernelGGL((k_mg_up<T, NU, true>), tiles(L.nf), tblock(), 0, c.stream, r, mg.u[0],
+                     mg.e[1], z, w, L.nf, L.pitch, c.lev[1].pitch, c.st, c.red, 0, 0);
+}
+
 template <typename T>
-void launch_vcycle_tail(const LaunchCtx& c, const MGBuffers<T>& mg) {
-  if (c.nu == 2) vcycle_tail_nu<T, 2>(c, mg);
-  else vcycle_tail_nu<T, 1>(c, mg);
+void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z, T* w) {
+  if (c.nu == 2) pcg_init_nu<T, 2>(c, mg, r, z, w);
+  else pcg_init_nu<T, 1>(c, mg, r, z, w);
 }
 
 template <typename T, int NU>
-static void pcg_init_nu(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z) {
+static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
+                        T* r_new, T* z, T* w, T* p_old, T* p_new, T* s_old, T* s_new) {
   const Level& L = c.lev[0];
-  hipLaunchKernelGGL((k_mg_down<T, NU, false>), tiles(L.nf), dim3(kBlock), 0, c.stream, r,
-                     mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)nullptr,
-                     (T*)nullptr, (const T*)nullptr, (T*)nullptr, c.st, c.partials);
-  launch_vcycle_tail<T>(c, mg);
-  hipLaunchKernelGGL((k_mg_up<T, NU, true>), tiles(L.nf), dim3(kBlock), 0, c.stream, r, mg.u[0],
-                     mg.e[1], z, L.nf, L.pitch, c.lev[1].pitch, c.st, c.partials);
+  hipLaunchKernelGGL((k_mg_down<T, NU, true>), tiles(L.nf), tblock(), 0, c.stream, r_old, mg.u[0],
+                     mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)w, (const T*)s_old, s_new,
+                     (const T*)z, (const T*)p_old, p_new, x, r_new, c.st, c.red, k, 0);
+  vcycle_tail_nu<T, NU>(c, mg, 1);
+  hipLaunchKernelGGL((k_mg_up<T, NU, true>), tiles(L.nf), tblock(), 0, c.stream, r_new, mg.u[0],
+                     mg.e[1], z, w, L.nf, L.pitch, c.lev[1].pitch, c.st, c.red, k + 1, 1);
 }
 
 template <typename T>
-void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z) {
-  if (c.nu == 2) pcg_init_nu<T, 2>(c, mg, r, z);
-  else pcg_init_nu<T, 1>(c, mg, r, z);
+void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
+                          T* r_new, T* z, T* w, T* p_old, T* p_new, T* s_old, T* s_new) {
+  if (c.nu == 2) pcg_iter_nu<T, 2>(c, mg, k, x, r_old, r_new, z, w, p_old, p_new, s_old, s_new);
+  else pcg_iter_nu<T, 1>(c, mg, k, x, r_old, r_new, z, w, p_old, p_new, s_old, s_new);
 }
 
-template <typename T, int NU>
-static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, T* x, T* r_old, T* r_new,
-                        T* z, T* p_old, T* p_new, T* q) {
-  const Level& L = c.lev[0];
-  hipLaunchKernelGGL((k_pcg_spmv<T>), tiles(L.nf), dim3(kBlock), 0, c.stream, z, p_old, p_new, q,
-                     L.nf, L.pitch, c.st, c.partials);
-  hipLaunchKernelGGL((k_mg_down<T, NU, true>), tiles(L.nf), dim3(kBlock), 0, c.stream, r_old,
-                     mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)q, x,
-                     (const T*)p_new, r_new, c.st, c.partials);
-  launch_vcycle_tail<T>(c, mg);
-  hipLaunchKernelGGL((k_mg_up<T, NU, true>), tiles(L.nf), dim3(kBlock), 0, c.stream, r_new,
-                     mg.u[0], mg.e[1], z, L.nf, L.pitch, c.lev[1].pitch, c.st, c.partials);
-}
-
-template <typename T>
-void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, T* x, T* r_old, T* r_new,
-                          T* z, T* p_old, T* p_new, T* q) {
-  if (c.nu == 2) pcg_iter_nu<T, 2>(c, mg, x, r_old, r_new, z, p_old, p_new, q);
-  else pcg_iter_nu<T, 1>(c, mg, x, r_old, r_new, z, p_old, p_new, q);
-}
-
-void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* u0, const double* u1,
-                        const float* e32, const double* e64, double* w0, double* w1, float* r32,
-                        double* r64, int first, double tol2, double tau2, int pcg_is_final) {
+void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin, const float* e32,
+                        const double* e64, double* uout, float* r32, double* r64, int first,
+                        double tol2, double tau2, int pcg_is_final) {
   const Level& L = c.lev[0];
   if (e64 || !e32)
-    hipLaunchKernelGGL((k_ir_residual<double>), tiles(L.nf), dim3(kBlock), 0, c.stream, f, u0,
-                       u1, e64, w0, w1, r32, r64, L.nf, L.pitch, first, tol2, tau2, pcg_is_final,
-                       c.st, c.partials);
+    hipLaunchKernelGGL((k_ir_residual<double>), tiles(L.nf), tblock(), 0, c.stream, f, uin, e64,
+                       uout, r32, r64, L.nf, L.pitch, first, tol2, tau2, pcg_is_final, c.st,
+                       c.red);
   else
-    hipLaunchKernelGGL((k_ir_residual<float>), tiles(L.nf), dim3(kBlock), 0, c.stream, f, u0, u1,
-                       e32, w0, w1, r32, r64, L.nf, L.pitch, first, tol2, tau2, pcg_is_final,
-                       c.st, c.partials);
+    hipLaunchKernelGGL((k_ir_residual<float>), tiles(L.nf), tblock(), 0, c.stream, f, uin, e32,
+                       uout, r32, r64, L.nf, L.pitch, first, tol2, tau2, pcg_is_final, c.st,
+                       c.red);
+  hipLaunchKernelGGL(k_ir_finalize, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red);
 }
 
 template void launch_pcg_init<float>(const LaunchCtx&, const MGBuffers<float>&, const float*,
-                                     float*);
+                                     float*, float*);
 template void launch_pcg_init<double>(const LaunchCtx&, const MGBuffers<double>&, const double*,
-                                      double*);
-template void launch_pcg_iteration<float>(const LaunchCtx&, const MGBuffers<float>&, float*,
-                                          float*, float*, float*, float*, float*, float*);
-template void launch_pcg_iteration<double>(const LaunchCtx&, const MGBuffers<double>&, double*,
-                                           double*, double*, double*, double*, double*, double*);
+                                      double*, double*);
+template void launch_pcg_iteration<float>(const LaunchCtx&, const MGBuffers<float>&, int, float*,
+                                          float*, float*, float*, float*, float*, float*, float*,
+                                          float*);
+template void launch_pcg_iteration<double>(const LaunchCtx&, const MGBuffers<double>&, int,
+                                           double*, double*, double*, double*, double*, double*,
+                                           double*, double*, double*);
 
 }  // namespace fdd

@@ -72,9 +72,12 @@ def test_interior_solve_second_call_is_deterministic():
     f = dev(np.random.default_rng(1).standard_normal(63 * 63))
     u1 = torch.zeros(63 * 63, dtype=torch.float64, device="cuda")
     u2 = torch.zeros_like(u1)
+    u0 = torch.zeros_like(u1)
+    P.interior_solve(f, u0)  # calibrates the schedule
     P.interior_solve(f, u1)
     P.interior_solve(f, u2)
     assert torch.equal(u1, u2)
+    assert rel(host(u0), host(u1)) <= 1e-10
 
 
 @pytest.mark.parametrize("n,K,mu", [(16, 1.0, 1.0), (64, 1e-2, 1e-3), (256, 1e-4, 1e3), (2048, 1.0, 1e-6)])
@@ -228,3 +231,27 @@ def test_error_paths():
     # the library still works afterwards
     st = P.solve(TP, TH, dev(b), x, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12))
     assert rel(host(x), system.solve_dst_2d(n, 1.0, 1.0, b)) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", [F.FDD_MIXED, F.FDD_FP64])
+def test_graph_replay_matches_eager_launches(precision):
+    # each outer iteration is replayed from a captured graph; replays (with eager work and
+    # synchronizations in between) must give bit-identical results to eager launches
+    n = 256
+    print(f"[graph] precision={precision}", flush=True)
+    P = make(n, 1e-2, 1e-3)
+    TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+    TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+    b = dev(workloads.rhs(2, n, 77))
+    xs = []
+    x = torch.zeros_like(b)
+    P.solve(TP, TH, b, x, F.opts_default(precision=precision, use_graph=0))  # settles the schedule
+    for use_graph in (0, 1, 1, 0, 1):
+        x = torch.zeros_like(b)
+        st = P.solve(TP, TH, b, x, F.opts_default(precision=precision, use_graph=use_graph))
+        xs.append(host(x))
+        assert st["outer_its"] <= 20
+    for xx in xs[1:]:
+        assert np.array_equal(xx, xs[0])
+    x_ref = system.solve_dst_2d(n, 1e-2, 1e-3, b.cpu().numpy())
+    assert rel(xs[0], x_ref) <= 1e-6
