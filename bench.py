@@ -31,9 +31,11 @@ def parse():
     ap.add_argument("--nu", type=int, default=1, help="red-black sweep pairs per level")
     ap.add_argument("--inner-rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--cases", default="all", help="'all' or 'K,mu'")
     ap.add_argument("--eager", action="store_true", help="launch kernels eagerly (no hipGraph replay)")
+    ap.add_argument("--pmc-mode", action="store_true",
+                    help="a few solves and a 256 MiB device copy, for rocprofv3 counter runs")
     return ap.parse_args()
 
 
@@ -45,30 +47,48 @@ def cases(args):
 
 
 def cpu_baseline(args, case_list):
-    """The oracle's separable exact solver, timed on this host on a bounded sample of cases."""
-    import numpy as np
+    """The oracle's exact separable solver, timed on this host on a bounded sample of the cases.
 
+    scipy.fft runs single-threaded by default and the banded solves are sequential, so the
+    oracle uses one core.
+    """
     import workloads
     from oracle import system
     n = args.n
     t0 = time.perf_counter()
     done = 0
-    names = []
-    while time.perf_counter() - t0 < args.cpu_seconds and done < 4 * len(case_list):
+    while time.perf_counter() - t0 < args.cpu_seconds:
         K, mu = case_list[done % len(case_list)]
         b = workloads.rhs(2, n, 1000 + done % len(case_list))
         system.solve_dst_2d(n, K, mu, b)
-        names.append((K, mu))
         done += 1
     dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} solves of the 2D n={n} problem by the oracle's separable sine-transform "
+                      f"solver (FP64, numpy/scipy, one thread), cycling the same (K, mu) cases, {dt:.1f} s"}
+
+
+# Algorithmic bytes of the finest-level down kernel per interior dof (FP32): it reads r, w
+# (window) and z (own), plus s', p', x on iterations k >= 1, and writes r_new, s, p, x, the
+# pre-smoothed u and a quarter-size coarse right-hand side.
+DOWN0_BYTES_K0 = 4 * 3 + 4 * 5 + 1
+DOWN0_BYTES_K = DOWN0_BYTES_K0 + 4 * 3
+HBM_PEAK_GBS = 8000.0
+
+
+def traffic_from_profile(root):
+    """HBM bytes per launch from the committed PMC summary, if it matches the current kernel."""
+    import hashlib
+    path = os.path.join(root, "profiles", "down0_traffic.json")
+    src = os.path.join(root, "paper_2211_15308_amd", "csrc", "kernels_mg.hip")
     try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count()
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or cores
-    return {"value": done / dt, "unit": "solves/s", "cores": min(cores, threads), "kind": "oracle",
-            "sample": f"{done} solves of the 2D n={n} problem (separable sine-transform oracle, FP64, "
-                      f"numpy/scipy) cycling the same (K, mu) cases, {dt:.1f} s"}
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_mg_sha256") != sha:
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def main():
@@ -89,6 +109,14 @@ def main():
     opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, precision=prec,
                           mg_nu=args.nu, use_graph=0 if args.eager else 1)
     case_list = cases(args)
+    if args.pmc_mode:
+        # calibration copy of known size, then a short run of the benchmark workload
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        case_list = case_list[:2]
+        args.steps, args.warmup = 2, 1
     probs = []
     for ci, (K, mu) in enumerate(case_list):
         P = F.setup_mesh(args.n, K, mu)
@@ -113,7 +141,43 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = args.steps / elapsed
-    # parity spot-check of the last solve of every case against the separable oracle
+    if args.pmc_mode:
+        print(json.dumps({"pmc_mode": True, "steps": args.steps}))
+        return
+    # roofline of the dominant kernel (the finest-level down kernel with the PCG update):
+    # the same steps again, with a HIP event pair attached to every launch of it
+    import paper_2211_15308_amd.fdd as FF
+    for P, *_ in probs:
+        P.set_kernel_timer(FF.FDD_KT_DOWN0)
+    its = runs = 0
+    for s in range(args.steps):
+        P, TP, TH, b, x, K, mu = probs[s % len(probs)]
+        st = P.solve(TP, TH, b, x, opts)
+        its += st["inner_its_total"]
+        runs += st["refine_steps"] if prec == F.FDD_MIXED else st["inner_solves"]
+    launches = tot_ms = long_n = long_ms = 0
+    for P, *_ in probs:
+        nl, ms, nlong, lms, _ = P.kernel_timer()
+        launches += nl
+        tot_ms += ms
+        long_n += nlong
+        long_ms += lms
+        P.set_kernel_timer(FF.FDD_KT_NONE)
+    ni = (args.n - 1) ** 2
+    elem = 4 if prec == F.FDD_MIXED else 8
+    # working launches: those that did the update (the others returned at once after their PCG
+    # run had converged); their algorithmic bytes over their own time is the achieved rate
+    alg_bytes = ni * elem / 4 * (DOWN0_BYTES_K * (its - runs) + DOWN0_BYTES_K0 * runs)
+    achieved = alg_bytes / (long_ms * 1e-3) / 1e9 if long_ms > 0 else 0.0
+    traffic = traffic_from_profile(ROOT) if prec == F.FDD_MIXED and args.n == 1024 else None
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "k_mg_down<float,1,true> (finest level, PCG update fused)",
+                "launches": launches, "avg_launch_us": 1e3 * tot_ms / max(launches, 1),
+                "working_launches": its, "timed_long_launches": long_n,
+                "avg_working_launch_us": 1e3 * long_ms / max(long_n, 1),
+                "alg_bytes_per_working_launch": alg_bytes / max(its, 1)}
+    # parity spot-check of one solve of the first cases against the separable oracle
     from oracle import system
     errs = []
     for ci, (P, TP, TH, b, x, K, mu) in enumerate(probs):
@@ -142,7 +206,7 @@ def main():
         "outer_its": [s["outer"] for s in stats[: len(case_list)]],
         "inner_its": [s["inner"] for s in stats[: len(case_list)]],
         "rel_err_vs_oracle": errs,
-        "roofline": None,
+        "roofline": roofline,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args, case_list),
     }
     print(json.dumps(out))

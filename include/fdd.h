@@ -168,6 +168,25 @@ int fdd_apply_operator(fdd_problem prob, fdd_ratpc H, const double* x, double* y
 int fdd_solve(fdd_problem prob, fdd_ratpc P, fdd_ratpc H, const double* b, double* x,
               const fdd_opts* opts, void* stream, fdd_stats* stats);
 
+/* ---- measurement ---------------------------------------------------------------------------
+ * Times every launch of one kernel kind with a pair of HIP events attached to that kernel's own
+ * dispatch on the stream it is launched on (hipExtLaunchKernelGGL: stamped at kernel begin and
+ * end); events are harvested at the solver's synchronization points.  While a timer is set,
+ * fdd_solve launches eagerly.  Setting a timer resets the totals.
+ * kind: FDD_KT_NONE (off), FDD_KT_DOWN0 (finest-level down kernel carrying the PCG update),
+ * FDD_KT_UP0 (finest-level up kernel producing z, A z and the dots), FDD_KT_COARSE (the
+ * single-workgroup coarse-level V-cycle).  Host call; creates events on first use.          */
+enum { FDD_KT_NONE = 0, FDD_KT_DOWN0 = 1, FDD_KT_UP0 = 2, FDD_KT_COARSE = 3 };
+/* split_us: launches lasting at least this long are also counted separately ("long" launches:
+ * those that did their work, as opposed to launches that returned at once because their solve
+ * had already converged).                                                                     */
+int fdd_set_kernel_timer(fdd_problem prob, int kind, double split_us);
+/* launches / total_ms: all timed launches and their summed durations; long_launches / long_ms:
+ * the same for launches of at least split_us; untimed: launches missed because more than 4096
+ * were pending between two synchronizations.  Any pointer may be NULL.                        */
+int fdd_get_kernel_timer(fdd_problem prob, int64_t* launches, double* total_ms,
+                         int64_t* long_launches, double* long_ms, int64_t* untimed);
+
 void fdd_destroy_problem(fdd_problem prob);
 void fdd_destroy_ratpc(fdd_ratpc t);
 const char* fdd_last_error(void);

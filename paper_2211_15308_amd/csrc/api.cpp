@@ -100,6 +100,11 @@ struct fdd_problem_s {
   std::map<std::tuple<int, int, int, int, int>, GraphEntry> graphs;
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // kernel timer (HIP events around every launch of one kernel kind)
+  EventHook hook;
+  long long timed_launches = 0, timed_long = 0;
+  double timed_ms = 0.0, timed_long_ms = 0.0;
+  double timer_split_ms = 0.008;
 };
 
 struct fdd_ratpc_s {
@@ -215,6 +220,7 @@ std::vector<double> dense_inverse_5pt(int nf) {
 
 LaunchCtx make_ctx(const fdd_problem_s* P, hipStream_t s, int nu, bool fp64) {
   LaunchCtx c{};
+  c.hook = P->hook.kind != kTimeNone ? const_cast<EventHook*>(&P->hook) : nullptr;
   c.stream = s;
   c.nlev = P->nlev;
   c.first_coarse = fp64 ? P->first_coarse64 : P->first_coarse32;
@@ -330,6 +336,18 @@ void enqueue_inner_more(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, int
 int read_state(fdd_problem_s* P, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(P->host_st, P->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  // harvest the kernel timer: every recorded pair has completed
+  for (int i = 0; i < P->hook.used; ++i) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, P->hook.ev[2 * i], P->hook.ev[2 * i + 1]));
+    P->timed_ms += ms;
+    P->timed_launches += 1;
+    if (ms >= P->timer_split_ms) {
+      P->timed_long_ms += ms;
+      P->timed_long += 1;
+    }
+  }
+  P->hook.used = 0;
   return FDD_OK;
 }
 
@@ -766,6 +784,7 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   HIPCHK(hipSetDevice(P->device));
   hipStream_t us = (hipStream_t)stream;
   hipStream_t s = us;
+  if (P->hook.kind != kTimeNone) o.use_graph = 0;  // timed launches carry their own events
   if (o.use_graph) {
     // graphs are captured and replayed on the library's own stream (default priority), ordered
     // after the caller's stream at entry and before it at exit
@@ -868,8 +887,44 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   return finish(converged ? FDD_OK : FDD_NOT_CONVERGED);
 }
 
+int fdd_set_kernel_timer(fdd_problem P, int kind, double split_us) {
+  if (!P) return fail(FDD_E_ARG, "null problem");
+  if (!(split_us >= 0)) return fail(FDD_E_ARG, "split_us must be >= 0");
+  P->timer_split_ms = split_us * 1e-3;
+  if (kind < FDD_KT_NONE || kind > FDD_KT_COARSE) return fail(FDD_E_ARG, "bad timer kind");
+  HIPCHK(hipSetDevice(P->device));
+  if (kind != FDD_KT_NONE && !P->hook.ev) {
+    const int cap = 4096;
+    P->hook.ev = new (std::nothrow) hipEvent_t[2 * cap];
+    if (!P->hook.ev) return fail(FDD_E_NOMEM, "out of host memory");
+    for (int i = 0; i < 2 * cap; ++i) HIPCHK(hipEventCreate(&P->hook.ev[i]));
+    P->hook.cap = cap;
+  }
+  P->hook.kind = kind;
+  P->hook.used = 0;
+  P->hook.skipped = 0;
+  P->timed_launches = P->timed_long = 0;
+  P->timed_ms = P->timed_long_ms = 0.0;
+  return FDD_OK;
+}
+
+int fdd_get_kernel_timer(fdd_problem P, int64_t* launches, double* total_ms, int64_t* long_launches,
+                         double* long_ms, int64_t* untimed) {
+  if (!P) return fail(FDD_E_ARG, "null problem");
+  if (launches) *launches = P->timed_launches;
+  if (total_ms) *total_ms = P->timed_ms;
+  if (long_launches) *long_launches = P->timed_long;
+  if (long_ms) *long_ms = P->timed_long_ms;
+  if (untimed) *untimed = P->hook.skipped;
+  return FDD_OK;
+}
+
 void fdd_destroy_problem(fdd_problem P) {
   if (!P) return;
+  if (P->hook.ev) {
+    for (int i = 0; i < 2 * P->hook.cap; ++i) (void)hipEventDestroy(P->hook.ev[i]);
+    delete[] P->hook.ev;
+  }
   for (auto& kv : P->graphs)
     if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
   if (P->gstream) (void)hipStreamDestroy(P->gstream);

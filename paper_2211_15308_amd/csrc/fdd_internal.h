@@ -1,5 +1,6 @@
 // Internal declarations shared by the host orchestration and the HIP kernels.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -86,7 +87,34 @@ struct Reductions {
   int nb0;         // number of level-0 tiles
 };
 
+// Optional HIP-event timing of one kernel kind (pairs of events around each launch of it).
+enum TimedKernel { kTimeNone = 0, kTimeDown0 = 1, kTimeUp0 = 2, kTimeCoarse = 3 };
+struct EventHook {
+  int kind = kTimeNone;
+  hipEvent_t* ev = nullptr;  // 2 * cap events
+  int cap = 0;
+  int used = 0;              // pairs recorded since the last harvest
+  long long skipped = 0;     // launches not timed because the pool was full
+};
+// Launch `kernel`, attaching the next event pair of the hook to its dispatch packet when the hook
+// times this kernel kind (hipExtLaunchKernelGGL stamps the events at kernel begin and end).
+template <typename F, typename... Args>
+inline void launch_timed(EventHook* h, int kind, F kernel, dim3 grid, dim3 block, hipStream_t s,
+                         Args... args) {
+  if (h && h->kind == kind) {
+    if (h->used < h->cap) {
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, s, h->ev[2 * h->used], h->ev[2 * h->used + 1],
+                            0, args...);
+      ++h->used;
+      return;
+    }
+    ++h->skipped;
+  }
+  hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
 struct LaunchCtx {
+  EventHook* hook = nullptr;
   hipStream_t stream;
   int nlev;
   int first_coarse;        // first level handled by the single-workgroup kernel

@@ -61,6 +61,20 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
 }
 
 __device__ __forceinline__ bool block0() { return blockIdx.x == 0 && blockIdx.y == 0; }
+
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8 XCDs by linear id, so
+// the linear id b runs on XCD b % 8.  Tile t = (b % 8) q + b / 8 (q = nb / 8; the remainder keeps
+// t = b) gives each XCD a contiguous strip of tile rows, so halos shared by neighbouring tiles are
+// fetched into one L2 instead of several.  Returns the tile id; (tx, ty) are its coordinates.
+__device__ __forceinline__ int xcd_tile(int* tx, int* ty) {
+  const int nbx = gridDim.x, nb = gridDim.x * gridDim.y;
+  const int b = blockIdx.y * nbx + blockIdx.x;
+  const int q = nb >> 3;
+  const int t = (b < 8 * q) ? (b & 7) * q + (b >> 3) : b;
+  *tx = t % nbx;
+  *ty = t / nbx;
+  return t;
+}
 __device__ __forceinline__ bool thread0() { return threadIdx.x == 0 && threadIdx.y == 0; }
 
 __device__ __forceinline__ bool stopped(const DevState* st) {
@@ -151,7 +165,9 @@ __global__ __launch_bounds__(kBlock) void k_mg_down(
   __shared__ T su[W][W + 1];
   if (stopped(st)) return;
   if (check && pcg_converged(st, red)) return;
-  const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
+  int tile_x, tile_y;
+  const int tile = xcd_tile(&tile_x, &tile_y);
+  const int i0 = tile_x * kTile, j0 = tile_y * kTile;
   const int ib = i0 + 1 - H, jb = j0 + 1 - H;  // global index of window cell (0, 0)
   const int tx = threadIdx.x, ty = threadIdx.y;
   T fr[RY][RX], wr[RY][RX], sr[RY][RX], zr[RY][RX], pr[RY][RX], xr[RY][RX];
@@ -254,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_down(
   }
   if (CG) {
     const double tot = block_sum_all(rr);
-    if (thread0()) red.rr[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    if (thread0()) red.rr[tile] = tot;
   }
 }
 
@@ -276,7 +292,9 @@ __global__ __launch_bounds__(kBlock) void k_mg_up(
   __shared__ T su[W][W + 1];
   __shared__ T sc[CW][CW + 1];
   if (stopped(st)) return;
-  const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
+  int tile_x, tile_y;
+  const int tile = xcd_tile(&tile_x, &tile_y);
+  const int i0 = tile_x * kTile, j0 = tile_y * kTile;
   const int ib = i0 + 1 - H, jb = j0 + 1 - H;
   const int Ib = ib >> 1, Jb = jb >> 1;  // floor (arithmetic shift)
   const int nc = (nf - 1) >> 1;
@@ -355,9 +373,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_up(
     const double trz = block_sum_all(rz);
     const double tzw = block_sum_all(zw);
     if (thread0()) {
-      const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-      red.rz[kn & 1][bid] = trz;
-      red.zw[kn & 1][bid] = tzw;
+      red.rz[kn & 1][tile] = trz;
+      red.zw[kn & 1][tile] = tzw;
       if (count_iteration && block0()) {
         st->inner_its += 1;
         st->pcg_k += 1;
@@ -574,7 +591,9 @@ __global__ __launch_bounds__(kBlock) void k_ir_residual(
     double tau2, int pcg_is_final, DevState* st, Reductions red) {
   constexpr int W = kTile + 2;
   __shared__ double su[W][W + 1];
-  const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
+  int tile_x, tile_y;
+  const int tile = xcd_tile(&tile_x, &tile_y);
+  const int i0 = tile_x * kTile, j0 = tile_y * kTile;
   if (!first && st->solve_done) {
     for (int b = threadIdx.y; b < kTile; b += blockDim.y) {
       const int j = j0 + 1 + b;
@@ -629,10 +648,9 @@ __global__ __launch_bounds__(kBlock) void k_ir_residual(
   }
   const double tot = block_sum_all(rr);
   if (thread0()) {
-    const int bid = blockIdx.y * gridDim.x + blockIdx.x;
-    red.ir[bid] = tot;
-    if (first) red.ff[bid] = tot;
-    if (bid == 0) {
+    red.ir[tile] = tot;
+    if (first) red.ff[tile] = tot;
+    if (block0()) {
       if (first) {
         st->tol2 = tol2;
         st->tau2 = tau2;
@@ -701,9 +719,9 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
   const T* cinv = nullptr;
   if constexpr (sizeof(T) == 4) cinv = (const T*)c.coarse_inv;
   else cinv = (const T*)c.coarse_inv64;
-  hipLaunchKernelGGL((k_coarse_vcycle<T, NU>), dim3(1), dim3(kCoarseThreads), 0, c.stream,
-                     mg.f[fc], c.lev[fc].pitch, mg.e[fc], lv, cinv, c.st, c.red,
-                     fc == 1 ? check : 0);
+  launch_timed(c.hook, kTimeCoarse, k_coarse_vcycle<T, NU>, dim3(1), dim3(kCoarseThreads),
+               c.stream, (const T*)mg.f[fc], c.lev[fc].pitch, mg.e[fc], lv, cinv, c.st, c.red,
+               fc == 1 ? check : 0);
   for (int l = fc - 1; l >= 1; --l) {
     const Level& L = c.lev[l];
     hipLaunchKernelGGL((k_mg_up<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, mg.f[l],
@@ -734,12 +752,14 @@ template <typename T, int NU>
 static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
                         T* r_new, T* z, T* w, T* p_old, T* p_new, T* s_old, T* s_new) {
   const Level& L = c.lev[0];
-  hipLaunchKernelGGL((k_mg_down<T, NU, true>), tiles(L.nf), tblock(), 0, c.stream, r_old, mg.u[0],
-                     mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)w, (const T*)s_old, s_new,
-                     (const T*)z, (const T*)p_old, p_new, x, r_new, c.st, c.red, k, 0);
+  launch_timed(c.hook, kTimeDown0, k_mg_down<T, NU, true>, tiles(L.nf), tblock(), c.stream,
+               (const T*)r_old, mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)w,
+               (const T*)s_old, s_new, (const T*)z, (const T*)p_old, p_new, x, r_new, c.st, c.red,
+               k, 0);
   vcycle_tail_nu<T, NU>(c, mg, 1);
-  hipLaunchKernelGGL((k_mg_up<T, NU, true>), tiles(L.nf), tblock(), 0, c.stream, r_new, mg.u[0],
-                     mg.e[1], z, w, L.nf, L.pitch, c.lev[1].pitch, c.st, c.red, k + 1, 1);
+  launch_timed(c.hook, kTimeUp0, k_mg_up<T, NU, true>, tiles(L.nf), tblock(), c.stream,
+               (const T*)r_new, (const T*)mg.u[0], (const T*)mg.e[1], z, w, L.nf, L.pitch,
+               c.lev[1].pitch, c.st, c.red, k + 1, 1);
 }
 
 template <typename T>

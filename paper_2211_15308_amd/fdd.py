@@ -37,8 +37,10 @@ EXPORTED = [
     "fdd_opts_default", "fdd_setup_mesh", "fdd_problem_info", "fdd_workspace_bytes",
     "fdd_bind_workspace", "fdd_build_rational_pc", "fdd_ratpc_from_table", "fdd_ratpc_query",
     "fdd_interior_solve", "fdd_schur_apply", "fdd_precond_apply", "fdd_apply_operator",
-    "fdd_solve", "fdd_destroy_problem", "fdd_destroy_ratpc", "fdd_last_error", "fdd_version",
+    "fdd_solve", "fdd_set_kernel_timer", "fdd_get_kernel_timer", "fdd_destroy_problem",
+    "fdd_destroy_ratpc", "fdd_last_error", "fdd_version",
 ]
+FDD_KT_NONE, FDD_KT_DOWN0, FDD_KT_UP0, FDD_KT_COARSE = 0, 1, 2, 3
 
 
 class FddDesc(ctypes.Structure):
@@ -99,6 +101,10 @@ def load():
     lib.fdd_precond_apply.argtypes = [P, P, V, V, V]
     lib.fdd_apply_operator.argtypes = [P, P, V, V, V]
     lib.fdd_solve.argtypes = [P, P, P, V, V, ctypes.POINTER(FddOpts), V, ctypes.POINTER(FddStats)]
+    lib.fdd_set_kernel_timer.argtypes = [P, I, D]
+    lib.fdd_get_kernel_timer.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D),
+                                         ctypes.POINTER(ctypes.c_int64)]
     lib.fdd_destroy_problem.argtypes = [P]
     lib.fdd_destroy_problem.restype = None
     lib.fdd_destroy_ratpc.argtypes = [P]
@@ -238,6 +244,17 @@ class Problem:
                               _stream(stream), ctypes.byref(st))
         _check(rc, (FDD_OK, FDD_NOT_CONVERGED) if allow_not_converged else (FDD_OK,))
         return st.as_dict()
+
+    def set_kernel_timer(self, kind, split_us=8.0):
+        _check(load().fdd_set_kernel_timer(self.h, kind, split_us))
+
+    def kernel_timer(self):
+        """(launches, total_ms, long_launches, long_ms, untimed) of the kernel timer."""
+        n, ms, nl, lms, un = (ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(),
+                              ctypes.c_int64())
+        _check(load().fdd_get_kernel_timer(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(nl),
+                                           ctypes.byref(lms), ctypes.byref(un)))
+        return n.value, ms.value, nl.value, lms.value, un.value
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -1,0 +1,122 @@
+"""Summaries of rocprofv3 result databases (kernel durations and PMC counters).
+
+Used to turn the SQLite output of ``rocprofv3 --kernel-trace --stats`` and
+``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs into the short text summaries kept
+under profiles/.  Command line:
+
+  python -m paper_2211_15308_amd.profile_tools stats  <results.db> [name filter]
+  python -m paper_2211_15308_amd.profile_tools pmc    <results.db> <counter> <name filter>
+  python -m paper_2211_15308_amd.profile_tools csvstats <kernel_stats.csv>
+  python -m paper_2211_15308_amd.profile_tools csvpmc <counter_collection.csv>
+  python -m paper_2211_15308_amd.profile_tools csvtrace <kernel_trace.csv> <name> <split_us>
+"""
+import csv
+import collections
+import sqlite3
+import sys
+
+
+def _rows(db, table):
+    con = sqlite3.connect(db)
+    cur = con.cursor()
+    cols = [r[1] for r in cur.execute(f"pragma table_info({table})")]
+    return cols, cur.execute(f"select * from {table}").fetchall()
+
+
+def kernel_stats(db, name_filter=None):
+    """{kernel name: (calls, total_us, avg_us)} from the kernel trace."""
+    cols, rows = _rows(db, "kernels")
+    ci = {c: i for i, c in enumerate(cols)}
+    agg = collections.defaultdict(lambda: [0, 0.0])
+    for r in rows:
+        nm = r[ci["name"]]
+        if name_filter and name_filter not in nm:
+            continue
+        d = (r[ci["end"]] - r[ci["start"]]) / 1e3
+        agg[nm][0] += 1
+        agg[nm][1] += d
+    return {k: (v[0], v[1], v[1] / v[0]) for k, v in agg.items()}
+
+
+def pmc_per_dispatch(db, counter, name_filter):
+    """Per-dispatch values of one counter for kernels whose name contains name_filter."""
+    con = sqlite3.connect(db)
+    cur = con.cursor()
+    cols = [r[1] for r in cur.execute("pragma table_info(counters_collection)")]
+    rows = cur.execute("select * from counters_collection").fetchall()
+    ci = {c: i for i, c in enumerate(cols)}
+    name_col = "kernel_name" if "kernel_name" in ci else "name"
+    val_col = "value" if "value" in ci else "counter_value"
+    cname_col = "counter_name" if "counter_name" in ci else "counter"
+    out = collections.defaultdict(float)
+    for r in rows:
+        if name_filter not in str(r[ci[name_col]]) or r[ci[cname_col]] != counter:
+            continue
+        key = r[ci["dispatch_id"]] if "dispatch_id" in ci else r[ci["id"]]
+        out[key] += float(r[ci[val_col]])
+    return list(out.values())
+
+
+def csv_kernel_stats(path):
+    """Rows of a rocprofv3 *_kernel_stats.csv, sorted by total time."""
+    rows = list(csv.DictReader(open(path)))
+    out = []
+    for r in rows:
+        out.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
+                    float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    return sorted(out, key=lambda t: -t[2])
+
+
+def csv_pmc(path):
+    """{kernel name: (dispatches, counter name, per-dispatch values)} of a counter CSV."""
+    agg = collections.defaultdict(list)
+    cname = {}
+    disp = collections.defaultdict(float)
+    for r in csv.DictReader(open(path)):
+        key = (r["Kernel_Name"], r["Dispatch_Id"])
+        disp[key] += float(r["Counter_Value"])
+        cname[r["Kernel_Name"]] = r["Counter_Name"]
+    for (k, _), v in disp.items():
+        agg[k].append(v)
+    return {k: (len(v), cname[k], v) for k, v in agg.items()}
+
+
+def csv_trace_split(path, name, split_us):
+    """Durations (us) of the dispatches of one kernel from a kernel_trace.csv, split at split_us."""
+    durs = []
+    for r in csv.DictReader(open(path)):
+        if r["Kernel_Name"].split("(")[0].strip() == name:
+            durs.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    long = [d for d in durs if d >= split_us]
+    return durs, long
+
+
+def main(argv):
+    if argv[0] == "stats":
+        st = kernel_stats(argv[1], argv[2] if len(argv) > 2 else None)
+        tot = sum(v[1] for v in st.values())
+        print(f"{'total_us':>12} {'pct':>6} {'calls':>7} {'avg_us':>9}  kernel")
+        for k, (c, t, a) in sorted(st.items(), key=lambda kv: -kv[1][1]):
+            print(f"{t:12.1f} {100 * t / tot:6.1f} {c:7d} {a:9.2f}  {k.split('(')[0]}")
+    elif argv[0] == "csvstats":
+        print(f"{'total_us':>12} {'pct':>6} {'calls':>7} {'avg_us':>9}  kernel")
+        for name, calls, tot, avg, pct in csv_kernel_stats(argv[1]):
+            print(f"{tot:12.1f} {pct:6.2f} {calls:7d} {avg:9.2f}  {name.split('(')[0]}")
+    elif argv[0] == "csvpmc":
+        for k, (n, cn, vals) in sorted(csv_pmc(argv[1]).items(), key=lambda kv: -sum(kv[1][2])):
+            big = [v for v in vals if v > 0.1 * max(vals)]
+            print(f"{cn} dispatches {n:6d} working {len(big):6d} avg_working_KiB "
+                  f"{sum(big) / max(len(big), 1):14.1f} max_KiB {max(vals):14.1f}  {k.split('(')[0]}")
+    elif argv[0] == "csvtrace":
+        durs, long = csv_trace_split(argv[1], argv[2], float(argv[3]))
+        print(f"{argv[2]}: dispatches {len(durs)} avg_us {sum(durs) / max(len(durs), 1):.2f}; "
+              f">= {argv[3]} us: {len(long)} avg_us {sum(long) / max(len(long), 1):.2f}")
+    elif argv[0] == "pmc":
+        vals = pmc_per_dispatch(argv[1], argv[2], argv[3])
+        nz = [v for v in vals if v > 0]
+        print(f"{argv[2]} {argv[3]}: dispatches {len(vals)} nonzero {len(nz)} "
+              f"avg_nonzero {sum(nz) / max(len(nz), 1):.1f} max {max(vals) if vals else 0:.1f}")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
