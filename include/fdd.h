@@ -61,8 +61,11 @@ enum { FDD_RA_PRECOND = 0, FDD_RA_OPERATOR = 1 };     /* which function a table 
 
 typedef struct fdd_problem_s* fdd_problem;   /* opaque: host state + views into the workspace */
 typedef struct fdd_ratpc_s* fdd_ratpc;       /* opaque: one rational table (host copy)          */
+typedef struct fdd_batch_s* fdd_batch;       /* opaque: a batch of problems solved together     */
 
-/* Problem description.  dim = 2 (3 reserved); n = cells per side (n >= 2); K > 0; mu > 0. */
+/* Problem description.  dim = 2 (3 reserved); n = cells per side, even, 4 <= n <= 2048 and
+ * such that halving the (n - 1)-point grid while its point count is odd ends at <= 16 points
+ * (every n = 2^k and n = 2^k (2j + 1) with small j); K > 0; mu > 0.                           */
 typedef struct {
   int dim;
   int n;
@@ -104,8 +107,9 @@ void fdd_opts_default(fdd_opts* opts);
  * fdd_setup_mesh: validates the description and builds the host-side plan: level hierarchy of
  * the interior multigrid, the coarsest-grid inverse, the spectral interval of (A_G, M_G).
  * Host only; hip_device is recorded and made current by later device calls.
- * Errors: FDD_E_ARG for dim != 2, n < 2, n whose multigrid coarsest grid exceeds 32 x 32
- * interior points, K <= 0, mu <= 0, or non-finite values.                                    */
+ * Errors: FDD_E_ARG for dim != 2, n odd, n < 4 or n > 2048 (one interface vector must fit in
+ * a workgroup's LDS), n whose multigrid coarsest grid exceeds 16 x 16 interior points, K <= 0,
+ * mu <= 0, or non-finite values.                                                             */
 int fdd_setup_mesh(const fdd_desc* desc, int hip_device, fdd_problem* out);
 
 /* Sizes: N free dofs, N_I interior, N_G interface; [lam_lo, lam_hi] encloses the discrete
@@ -167,6 +171,37 @@ int fdd_apply_operator(fdd_problem prob, fdd_ratpc H, const double* x, double* y
  * reached (x holds the last iterate), FDD_E_BREAKDOWN / FDD_E_NONFINITE on breakdown.       */
 int fdd_solve(fdd_problem prob, fdd_ratpc P, fdd_ratpc H, const double* b, double* x,
               const fdd_opts* opts, void* stream, fdd_stats* stats);
+
+/* ---- batched solves -------------------------------------------------------------------------
+ * Many independent problems of possibly different n, K, mu (and tables) solved together: the
+ * same method as fdd_solve, applied to every instance, with each kernel launch covering all
+ * instances (one grid over the concatenated multigrid tiles of every instance, one grid over all
+ * shifted interface systems of eq. (RA) of every instance).  Each instance runs its own outer
+ * PCG with its own stop rule; an instance that has converged is skipped by the kernels of later
+ * iterations.  All instances share one launch schedule, and each outer iteration of the batch
+ * is replayed from a captured hipGraph (opts->use_graph).  Only FDD_MIXED precision.
+ *
+ * fdd_batch_create: count >= 1 distinct problems, each with its own workspace bound, and their
+ * tables (P[i] of kind FDD_RA_PRECOND and H[i] of kind FDD_RA_OPERATOR built for probs[i]).
+ * The batch keeps pointers to the problems and tables: they must outlive it and keep their
+ * workspaces.  Host only.  Errors: FDD_E_ARG (empty, duplicate problem, mixed devices),
+ * FDD_E_WORKSPACE (a problem without workspace), FDD_E_STATE (a table of the wrong problem). */
+int fdd_batch_create(int count, const fdd_problem* probs, const fdd_ratpc* P, const fdd_ratpc* H,
+                     fdd_batch* out);
+/* Device bytes of the batch's own workspace (descriptors, work lists, tables).  Host only. */
+int fdd_batch_workspace_bytes(fdd_batch batch, size_t* bytes);
+/* Binds caller-owned device memory (256-byte aligned) to the batch and initializes it on
+ * `stream`; synchronizes the stream.  Errors: FDD_E_WORKSPACE.                              */
+int fdd_batch_bind_workspace(fdd_batch batch, void* dev_ptr, size_t bytes, void* stream);
+/* x[i] = A_i^{-1} b[i] for every instance.  b, x: host arrays of `count` device pointers (each
+ * of length N of its problem).  stats: NULL or an array of `count` entries (per-instance
+ * status, iteration counts and residuals; t_solve_ms is the batch's wall time).  Returns
+ * FDD_NOT_CONVERGED if any instance hit outer_maxit (that instance's x holds its last
+ * iterate), or an error code on breakdown or invalid input (the message names the instance).
+ * Returns after the whole batch has finished.                                                */
+int fdd_solve_batched(fdd_batch batch, const double* const* b, double* const* x,
+                      const fdd_opts* opts, void* stream, fdd_stats* stats);
+void fdd_batch_destroy(fdd_batch batch);
 
 /* ---- measurement ---------------------------------------------------------------------------
  * Times every launch of one kernel kind with a pair of HIP events attached to that kernel's own

@@ -14,15 +14,16 @@
 #include <string>
 #include <vector>
 
-#include "fdd_internal.h"
+#include "api_internal.h"
 
 using namespace fdd;
 
+namespace fdd {
+
 namespace {
-
 thread_local std::string g_err;
+}
 
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -33,89 +34,9 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIPCHK(call)                                                                    \
-  do {                                                                                  \
-    hipError_t e_ = (call);                                                             \
-    if (e_ != hipSuccess) return fail(FDD_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
+}  // namespace fdd
 
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-inline int round_up(int x, int a) { return (x + a - 1) / a * a; }
-
-// Per-precision multigrid-PCG buffers of level 0 plus the hierarchy.
-template <typename T>
-struct PcgSet {
-  T* x = nullptr;
-  T* r[2] = {nullptr, nullptr};
-  T* p[2] = {nullptr, nullptr};
-  T* s[2] = {nullptr, nullptr};  // s = A p
-  T* z = nullptr;
-  T* w = nullptr;                // w = A z
-  MGBuffers<T> mg{};
-};
-
-// An instantiated graph of one outer iteration and the host-side buffer state after it.
-struct GraphEntry {
-  hipGraphExec_t exec = nullptr;
-  int cur_r = 0, cur_p = 0, S = 0, k = 0;
-};
-
-}  // namespace
-
-struct fdd_problem_s {
-  int dim = 2, n = 0, device = 0;
-  double K = 1, mu = 1, gamma = 1, h = 1;
-  int64_t N = 0, NI = 0, NG = 0;
-  double lam_lo = 0, lam_hi = 0;
-  int nlev = 0;
-  int first_coarse32 = 1, first_coarse64 = 1;
-  Level lev[kMaxLevels];
-  std::vector<double> cinv;  // dense inverse on the coarsest level
-  std::vector<double> eig;   // exact interface eigenvalues (2D), check points of the RA builder
-  // workspace views
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  DevState* st = nullptr;
-  double* partials = nullptr;   // true-residual reduction
-  Reductions red{};
-  float* cinv32 = nullptr;
-  double* cinv64 = nullptr;
-  PcgSet<float> s32;
-  PcgSet<double> s64;
-  double* u64[2] = {nullptr, nullptr};  // refinement accumulators
-  double* xG[2] = {nullptr, nullptr};
-  double* rG[2] = {nullptr, nullptr};
-  double* pG[2] = {nullptr, nullptr};
-  double* zG = nullptr;
-  double* yG = nullptr;
-  double* Hp = nullptr;
-  double* scratchP = nullptr;
-  double* scratchH = nullptr;
-  DevState* host_st = nullptr;  // pinned copy
-  // inner schedule (refinement steps x PCG iterations, or FP64 PCG iterations); only grows
-  int sched_steps = 1, sched_its = 2, sched_its64 = 4;
-  int sched_step_its[8] = {2, 2, 2, 2, 2, 2, 2, 2};  // per refinement step (mixed)
-  bool calibrated = false;  // the first interior solve runs every PCG to its own criterion
-  // captured outer iterations, keyed by (parity, schedule, precision, smoother)
-  std::map<std::tuple<int, int, int, int, int>, GraphEntry> graphs;
-  hipStream_t gstream = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  // kernel timer (HIP events around every launch of one kernel kind)
-  EventHook hook;
-  long long timed_launches = 0, timed_long = 0;
-  double timed_ms = 0.0, timed_long_ms = 0.0;
-  double timer_split_ms = 0.008;
-};
-
-struct fdd_ratpc_s {
-  int which = 0;
-  const fdd_problem_s* prob = nullptr;
-  int n = 0;
-  double K = 0, mu = 0;
-  RaResult r{};
-};
-
-namespace {
+namespace fdd {
 
 // Assign (or just size) every workspace view.  When base is null only the size is computed.
 size_t plan_workspace(fdd_problem_s* P, char* base) {
@@ -431,7 +352,7 @@ int check_table(const fdd_problem_s* P, const fdd_ratpc_s* t, int which) {
   return FDD_OK;
 }
 
-}  // namespace
+}  // namespace fdd
 
 extern "C" {
 

@@ -1,0 +1,506 @@
+// Batched solves: many independent 2D problems (different n, K, mu, rational tables) advance
+// through the Schur-complement PCG together.  Every launch covers the whole batch (one grid over
+// the concatenated tiles of all instances, one grid over all shifted interface systems), all
+// instances share one enqueue schedule, and an outer iteration is one hipGraph replay for the
+// batch.  Per-instance state lives on the device: an instance whose outer PCG has converged is
+// skipped by every kernel of the outer loop, so the launch sequence stays fixed.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "api_internal.h"
+
+using namespace fdd;
+
+namespace {
+
+constexpr double kTau32b = 1e-5;  // FP32 PCG relative reduction per refinement step
+
+struct BGraph {
+  hipGraphExec_t exec = nullptr;
+  int cur_r = 0, cur_p = 0, S = 0;
+};
+
+struct BTrack {
+  int cur_r = 0, cur_p = 0, S = 0;
+};
+
+}  // namespace
+
+struct fdd_batch_s {
+  int count = 0, device = 0;
+  std::vector<fdd_problem_s*> probs;
+  std::vector<const fdd_ratpc_s*> tabP, tabH;
+  // launch geometry
+  int max_tiled = 1;
+  int tiles_total[kMaxLevels] = {};
+  int sysP_total = 0, sysH_total = 0;
+  std::vector<int> tiles_prefix[kMaxLevels];
+  std::vector<int> sysP_prefix, sysH_prefix;
+  // workspace views
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  BInst* d_inst = nullptr;
+  int* d_tiles[kMaxLevels] = {};
+  int* d_sysP = nullptr;
+  int* d_sysH = nullptr;
+  ShiftTable* d_tab = nullptr;  // P tables, then H tables
+  DevState* d_states = nullptr;
+  // pinned host mirrors
+  BInst* h_inst = nullptr;      // staging of the descriptors
+  DevState* h_states = nullptr;
+  std::vector<BInst> uploaded;  // descriptors as last uploaded
+  // shared enqueue schedule (refinement steps, PCG iterations per step); only grows
+  int sched_steps = 1, sched_its = 2;
+  int step_its[8] = {2, 2, 2, 2, 2, 2, 2, 2};
+  bool calibrated = false;
+  std::map<std::vector<int>, BGraph> graphs;
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace {
+
+size_t plan_batch(fdd_batch_s* B, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = align_up(off, 256);
+    char* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  const size_t c = (size_t)B->count;
+  B->d_inst = (BInst*)take(sizeof(BInst) * c);
+  for (int l = 0; l < kMaxLevels; ++l) B->d_tiles[l] = (int*)take(sizeof(int) * (c + 1));
+  B->d_sysP = (int*)take(sizeof(int) * (c + 1));
+  B->d_sysH = (int*)take(sizeof(int) * (c + 1));
+  B->d_tab = (ShiftTable*)take(sizeof(ShiftTable) * 2 * c);
+  B->d_states = (DevState*)take(sizeof(DevState) * c);
+  return align_up(off, 256);
+}
+
+// Descriptor of instance i from its problem's bound workspace and the caller's vectors.
+BInst make_inst(const fdd_batch_s* B, int i, const double* b, double* x) {
+  const fdd_problem_s* P = B->probs[i];
+  BInst I;
+  std::memset(&I, 0, sizeof(I));
+  I.nlev = P->nlev;
+  I.fc = P->first_coarse32;
+  for (int l = 0; l < P->nlev; ++l) {
+    I.nf[l] = P->lev[l].nf;
+    I.pitch[l] = P->lev[l].pitch;
+    I.tiles_x[l] = l < I.fc ? (P->lev[l].nf + kTile - 1) / kTile : 0;
+    I.f[l] = P->s32.mg.f[l];
+    I.u[l] = P->s32.mg.u[l];
+    I.e[l] = P->s32.mg.e[l];
+  }
+  I.x = P->s32.x;
+  for (int k = 0; k < 2; ++k) {
+    I.r[k] = P->s32.r[k];
+    I.p[k] = P->s32.p[k];
+    I.s[k] = P->s32.s[k];
+    I.u64[k] = P->u64[k];
+    I.xG[k] = P->xG[k];
+    I.rG[k] = P->rG[k];
+    I.pG[k] = P->pG[k];
+  }
+  I.z = P->s32.z;
+  I.w = P->s32.w;
+  I.cinv = P->cinv32;
+  I.st = P->st;
+  I.red = P->red;
+  I.ng = (int)P->NG;
+  I.mP = make_table(B->tabP[i]).m;
+  I.mH = make_table(B->tabH[i]).m;
+  I.h = P->h;
+  I.K = P->K;
+  I.gamma = P->gamma;
+  I.b = b;
+  I.xout = x;
+  I.zG = P->zG;
+  I.yG = P->yG;
+  I.Hp = P->Hp;
+  I.scrP = P->scratchP;
+  I.scrH = P->scratchH;
+  I.tabP = B->d_tab + i;
+  I.tabH = B->d_tab + B->count + i;
+  return I;
+}
+
+BatchCtx make_bctx(const fdd_batch_s* B, hipStream_t s, int nu, int skip_done) {
+  BatchCtx c{};
+  c.stream = s;
+  c.inst = B->d_inst;
+  for (int l = 0; l < kMaxLevels; ++l) c.lists.tiles[l] = B->d_tiles[l];
+  c.lists.sysP = B->d_sysP;
+  c.lists.sysH = B->d_sysH;
+  c.lists.ninst = B->count;
+  c.nu = nu;
+  c.max_tiled = B->max_tiled;
+  for (int l = 0; l < kMaxLevels; ++l) c.tiles_total[l] = B->tiles_total[l];
+  c.sysP_total = B->sysP_total;
+  c.sysH_total = B->sysH_total;
+  c.skip_done = skip_done;
+  return c;
+}
+
+int read_states(fdd_batch_s* B, hipStream_t s) {
+  BatchCtx c = make_bctx(B, s, 1, 0);
+  launch_b_gather_states(c, B->d_states);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(B->h_states, B->d_states, sizeof(DevState) * B->count,
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return FDD_OK;
+}
+
+void enqueue_start(const BatchCtx& c, BTrack& t, int rhs, int ver, const fdd_opts& o) {
+  t = BTrack{};
+  launch_b_inner_start(c, rhs, ver, o.inner_rtol * o.inner_rtol, kTau32b * kTau32b);
+}
+
+// `steps` refinement steps; its < 0 takes the per-step schedule.
+void enqueue_steps(const fdd_batch_s* B, const BatchCtx& c, BTrack& t, int rhs, int ver,
+                   int steps, int its) {
+  for (int q = 0; q < steps; ++q) {
+    const int n_its = its >= 0 ? its : (t.S < 8 ? B->step_its[t.S] : B->sched_its);
+    launch_b_inner_step(c, rhs, ver, n_its, t.S, t.cur_r, t.cur_p);
+    t.S += 1;
+  }
+}
+
+// After a synchronization: completes the interior solve of every instance marked in `live`
+// (eager top-up steps for the whole batch), then records iteration counts and grows the
+// shared schedule.
+int finish_inner(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, int rhs, int ver,
+                 const std::vector<char>& live, const fdd_opts& o, std::vector<fdd_stats>& st) {
+  for (int round = 0;; ++round) {
+    bool all = true;
+    for (int i = 0; i < B->count; ++i) {
+      if (!live[i]) continue;
+      const DevState& h = B->h_states[i];
+      if (h.breakdown)
+        return fail(h.breakdown & 4 ? FDD_E_NONFINITE : FDD_E_BREAKDOWN,
+                    "batch instance %d: interior solve breakdown (flags %d)", i, h.breakdown);
+      if (!h.solve_done) {
+        all = false;
+        if (h.inner_its >= o.inner_maxit || round > o.inner_maxit)
+          return fail(FDD_NOT_CONVERGED, "batch instance %d: interior solve did not converge in %d "
+                      "iterations", i, h.inner_its);
+      }
+    }
+    if (all) break;
+    enqueue_steps(B, c, t, rhs, ver, 1, std::max(B->sched_its, 30));
+    HIPCHK(hipGetLastError());
+    int rc = read_states(B, s);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < B->count; ++i) {
+    if (!live[i]) continue;
+    const DevState& h = B->h_states[i];
+    st[i].inner_solves += 1;
+    st[i].inner_its_total += h.inner_its;
+    st[i].inner_its_max = std::max(st[i].inner_its_max, h.inner_its);
+    st[i].refine_steps += h.refine_steps;
+    B->sched_steps = std::max(B->sched_steps, std::max(h.refine_steps, 1));
+    B->sched_its = std::max(B->sched_its, h.run_its_max + 1);
+    for (int q = 0; q < std::min(h.refine_steps, 8); ++q)
+      B->step_its[q] = std::max(B->step_its[q], h.run_len[q] + 1);
+  }
+  return FDD_OK;
+}
+
+// One batched interior solve from the enqueue of its first residual to completion (eager).
+int batch_inner(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, int rhs, int ver,
+                const std::vector<char>& live, const fdd_opts& o, std::vector<fdd_stats>& st) {
+  enqueue_start(c, t, rhs, ver, o);
+  if (!B->calibrated) enqueue_steps(B, c, t, rhs, ver, 1, 30);  // measures the schedule
+  else enqueue_steps(B, c, t, rhs, ver, B->sched_steps, -1);
+  HIPCHK(hipGetLastError());
+  int rc = read_states(B, s);
+  if (rc) return rc;
+  rc = finish_inner(B, s, c, t, rhs, ver, live, o, st);
+  if (rc == FDD_OK) B->calibrated = true;
+  return rc;
+}
+
+// Everything of outer iteration v up to the synchronization, for the instances still running.
+void enqueue_outer(const fdd_batch_s* B, const BatchCtx& c, BTrack& t, int v, const fdd_opts& o) {
+  enqueue_start(c, t, kRhsLiftP, v, o);
+  enqueue_steps(B, c, t, kRhsLiftP, v, B->sched_steps, -1);
+  launch_b_operator(c, v);
+  launch_b_outer_tail(c, t.S, v, o.outer_rtol);
+}
+
+int replay_outer(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, int v,
+                 const fdd_opts& o) {
+  std::vector<int> key = {v & 1, o.mg_nu, B->sched_steps, B->sched_its};
+  key.insert(key.end(), B->step_its, B->step_its + 8);
+  auto it = B->graphs.find(key);
+  if (it == B->graphs.end()) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    enqueue_outer(B, c, t, v, o);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess) return fail(FDD_E_HIP, "graph capture: %s", hipGetErrorString(e));
+    BGraph ge;
+    e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(FDD_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    ge.cur_r = t.cur_r;
+    ge.cur_p = t.cur_p;
+    ge.S = t.S;
+    it = B->graphs.emplace(key, ge).first;
+  }
+  t.cur_r = it->second.cur_r;
+  t.cur_p = it->second.cur_p;
+  t.S = it->second.S;
+  HIPCHK(hipGraphLaunch(it->second.exec, s));
+  return FDD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdd_batch_create(int count, const fdd_problem* probs, const fdd_ratpc* P, const fdd_ratpc* H,
+                     fdd_batch* out) {
+  if (!out) return fail(FDD_E_ARG, "null argument");
+  *out = nullptr;
+  if (count < 1 || !probs || !P || !H) return fail(FDD_E_ARG, "empty batch or null array");
+  for (int i = 0; i < count; ++i) {
+    int rc = check_problem(probs[i]);
+    if (rc) return fail(rc, "batch instance %d: %s", i, fdd_last_error());
+    if ((rc = check_table(probs[i], P[i], FDD_RA_PRECOND)) ||
+        (rc = check_table(probs[i], H[i], FDD_RA_OPERATOR)))
+      return fail(rc, "batch instance %d: %s", i, fdd_last_error());
+    if (probs[i]->device != probs[0]->device)
+      return fail(FDD_E_ARG, "batch instances on different devices");
+  }
+  std::vector<fdd_problem_s*> sorted(probs, probs + count);
+  std::sort(sorted.begin(), sorted.end());
+  if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+    return fail(FDD_E_ARG, "a problem appears twice in the batch (instances need their own workspace)");
+  fdd_batch_s* B = new (std::nothrow) fdd_batch_s();
+  if (!B) return fail(FDD_E_NOMEM, "out of host memory");
+  B->count = count;
+  B->device = probs[0]->device;
+  B->probs.assign(probs, probs + count);
+  B->tabP.assign(P, P + count);
+  B->tabH.assign(H, H + count);
+  B->max_tiled = 1;
+  for (int i = 0; i < count; ++i) B->max_tiled = std::max(B->max_tiled, probs[i]->first_coarse32);
+  for (int l = 0; l < kMaxLevels; ++l) {
+    auto& pre = B->tiles_prefix[l];
+    pre.assign(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+      const fdd_problem_s* Q = probs[i];
+      int t = 0;
+      if (l < Q->first_coarse32) {
+        const int tx = (Q->lev[l].nf + kTile - 1) / kTile;
+        t = tx * tx;
+      }
+      pre[i + 1] = pre[i] + t;
+    }
+    B->tiles_total[l] = pre[count];
+  }
+  B->sysP_prefix.assign(count + 1, 0);
+  B->sysH_prefix.assign(count + 1, 0);
+  for (int i = 0; i < count; ++i) {
+    B->sysP_prefix[i + 1] = B->sysP_prefix[i] + make_table(P[i]).m;
+    B->sysH_prefix[i + 1] = B->sysH_prefix[i] + make_table(H[i]).m;
+  }
+  B->sysP_total = B->sysP_prefix[count];
+  B->sysH_total = B->sysH_prefix[count];
+  *out = B;
+  return FDD_OK;
+}
+
+int fdd_batch_workspace_bytes(fdd_batch B, size_t* bytes) {
+  if (!B || !bytes) return fail(FDD_E_ARG, "null argument");
+  fdd_batch_s tmp;
+  tmp.count = B->count;
+  *bytes = plan_batch(&tmp, nullptr);
+  return FDD_OK;
+}
+
+int fdd_batch_bind_workspace(fdd_batch B, void* dev, size_t bytes, void* stream) {
+  if (!B || !dev) return fail(FDD_E_ARG, "null argument");
+  if (((uintptr_t)dev) & 255) return fail(FDD_E_WORKSPACE, "workspace must be 256-byte aligned");
+  fdd_batch_s tmp;
+  tmp.count = B->count;
+  const size_t need = plan_batch(&tmp, nullptr);
+  if (bytes < need) return fail(FDD_E_WORKSPACE, "workspace %zu bytes < %zu needed", bytes, need);
+  HIPCHK(hipSetDevice(B->device));
+  hipStream_t s = (hipStream_t)stream;
+  B->ws = (char*)dev;
+  B->ws_bytes = bytes;
+  plan_batch(B, B->ws);
+  if (!B->h_inst)
+    HIPCHK(hipHostMalloc((void**)&B->h_inst, sizeof(BInst) * B->count, hipHostMallocDefault));
+  if (!B->h_states)
+    HIPCHK(hipHostMalloc((void**)&B->h_states, sizeof(DevState) * B->count, hipHostMallocDefault));
+  B->uploaded.clear();
+  std::vector<ShiftTable> tabs(2 * (size_t)B->count);
+  for (int i = 0; i < B->count; ++i) {
+    tabs[i] = make_table(B->tabP[i]);
+    tabs[B->count + i] = make_table(B->tabH[i]);
+  }
+  HIPCHK(hipMemsetAsync(B->ws, 0, need, s));
+  for (int l = 0; l < kMaxLevels; ++l)
+    HIPCHK(hipMemcpyAsync(B->d_tiles[l], B->tiles_prefix[l].data(), sizeof(int) * (B->count + 1),
+                          hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(B->d_sysP, B->sysP_prefix.data(), sizeof(int) * (B->count + 1),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(B->d_sysH, B->sysH_prefix.data(), sizeof(int) * (B->count + 1),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(B->d_tab, tabs.data(), sizeof(ShiftTable) * tabs.size(),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return FDD_OK;
+}
+
+int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, const fdd_opts* opts,
+                      void* stream, fdd_stats* stats) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!B || !b || !x) return fail(FDD_E_ARG, "null argument");
+  if (!B->ws) return fail(FDD_E_WORKSPACE, "no batch workspace bound");
+  for (int i = 0; i < B->count; ++i) {
+    if (!b[i] || !x[i]) return fail(FDD_E_ARG, "batch instance %d: null vector", i);
+    if (!B->probs[i]->ws) return fail(FDD_E_WORKSPACE, "batch instance %d: no workspace bound", i);
+  }
+  fdd_opts o;
+  if (opts) o = *opts;
+  else fdd_opts_default(&o);
+  if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
+  if (o.precision != FDD_MIXED)
+    return fail(FDD_E_ARG, "batched solves run FP32 multigrid-PCG inside FP64 refinement only");
+  HIPCHK(hipSetDevice(B->device));
+  hipStream_t us = (hipStream_t)stream;
+  hipStream_t s = us;
+  if (o.use_graph) {
+    if (!B->gstream) {
+      HIPCHK(hipStreamCreateWithFlags(&B->gstream, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(B->ev_in, us));
+    HIPCHK(hipStreamWaitEvent(B->gstream, B->ev_in, 0));
+    s = B->gstream;
+  }
+  const int n = B->count;
+  std::vector<fdd_stats> st(n);
+  for (auto& q : st) {
+    std::memset(&q, 0, sizeof(q));
+    q.true_rel_res = -1.0;
+  }
+  auto finish = [&](int code) -> int {
+    if (o.use_graph) {
+      (void)hipEventRecord(B->ev_out, s);
+      (void)hipStreamWaitEvent(us, B->ev_out, 0);
+    }
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    for (int i = 0; i < n; ++i) {
+      if (code < 0) st[i].status = code;
+      st[i].t_solve_ms = ms;
+    }
+    if (stats) std::memcpy(stats, st.data(), sizeof(fdd_stats) * n);
+    return code;
+  };
+  // descriptors (uploaded when a vector or a problem's workspace changed)
+  std::vector<BInst> cur(n);
+  for (int i = 0; i < n; ++i) cur[i] = make_inst(B, i, b[i], x[i]);
+  if (B->uploaded.size() != (size_t)n ||
+      std::memcmp(B->uploaded.data(), cur.data(), sizeof(BInst) * n) != 0) {
+    std::memcpy(B->h_inst, cur.data(), sizeof(BInst) * n);
+    HIPCHK(hipMemcpyAsync(B->d_inst, B->h_inst, sizeof(BInst) * n, hipMemcpyHostToDevice, s));
+    B->uploaded = cur;
+  }
+  const std::vector<char> all(n, 1);
+  BatchCtx c0 = make_bctx(B, s, o.mg_nu, 0), c1 = make_bctx(B, s, o.mg_nu, 1);
+  BTrack t;
+  // 1. g = b_G - A_GI A_II^{-1} b_I for every instance
+  int rc = batch_inner(B, s, c0, t, kRhsB, 0, all, o, st);
+  if (rc) return finish(rc);
+  launch_b_rhs_reduce(c0, t.S);
+  // 2. outer PCG from x_G = 0 (device-side convergence test per instance)
+  launch_b_precond_init(c0, o.outer_rtol);
+  HIPCHK(hipGetLastError());
+  if ((rc = read_states(B, s))) return finish(rc);
+  std::vector<char> live(n);
+  int nlive = 0;
+  for (int i = 0; i < n; ++i) {
+    if (B->h_states[i].breakdown)
+      return finish(fail(FDD_E_BREAKDOWN, "batch instance %d: preconditioner not positive", i));
+    live[i] = !B->h_states[i].outer_done;
+    nlive += live[i];
+  }
+  int v = 0;
+  while (nlive > 0 && v < o.outer_maxit) {
+    if (o.use_graph) {
+      if ((rc = replay_outer(B, s, c1, t, v, o))) return finish(rc);
+    } else {
+      enqueue_outer(B, c1, t, v, o);
+    }
+    HIPCHK(hipGetLastError());
+    if ((rc = read_states(B, s))) return finish(rc);
+    bool short_solve = false;
+    for (int i = 0; i < n; ++i)
+      if (live[i] && !B->h_states[i].solve_done && !B->h_states[i].breakdown) short_solve = true;
+    if ((rc = finish_inner(B, s, c1, t, kRhsLiftP, v, live, o, st))) return finish(rc);
+    if (short_solve) {
+      // the schedule was short for some instance: its tail was skipped; now that every interior
+      // solve is complete, repeat the tail (it depends on version-v data only)
+      launch_b_outer_tail(c1, t.S, v, o.outer_rtol);
+      HIPCHK(hipGetLastError());
+      if ((rc = read_states(B, s))) return finish(rc);
+    }
+    ++v;
+    for (int i = 0; i < n; ++i) {
+      if (!live[i]) continue;
+      const DevState& h = B->h_states[i];
+      if (h.breakdown)
+        return finish(fail(h.breakdown & 4 ? FDD_E_NONFINITE : FDD_E_BREAKDOWN,
+                           "batch instance %d: outer PCG breakdown (flags %d, p.Sp = %g)", i,
+                           h.breakdown, h.o_pq));
+      st[i].outer_its = v;
+      if (h.outer_done) {
+        live[i] = 0;
+        --nlive;
+      }
+    }
+  }
+  // 3. back-substitution x_I = A_II^{-1} (b_I / K - A_IG x_G) for every instance
+  if ((rc = batch_inner(B, s, c0, t, kRhsBack, v, all, o, st))) return finish(rc);
+  launch_b_scatter(c0, t.S, v);
+  HIPCHK(hipGetLastError());
+  if ((rc = read_states(B, s))) return finish(rc);
+  int code = FDD_OK;
+  for (int i = 0; i < n; ++i) {
+    const DevState& h = B->h_states[i];
+    const int fv = h.outer_done ? h.o_ver : v;
+    const double rho = h.o_rho[fv & 1];
+    st[i].rel_precond_res = h.o_rho0 > 0 ? std::sqrt(std::max(rho, 0.0) / h.o_rho0) : 0.0;
+    st[i].status = h.outer_done ? FDD_OK : FDD_NOT_CONVERGED;
+    if (!h.outer_done) code = FDD_NOT_CONVERGED;
+  }
+  return finish(code);
+}
+
+void fdd_batch_destroy(fdd_batch B) {
+  if (!B) return;
+  for (auto& kv : B->graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  if (B->gstream) (void)hipStreamDestroy(B->gstream);
+  if (B->ev_in) (void)hipEventDestroy(B->ev_in);
+  if (B->ev_out) (void)hipEventDestroy(B->ev_out);
+  if (B->h_inst) (void)hipHostFree(B->h_inst);
+  if (B->h_states) (void)hipHostFree(B->h_states);
+  delete B;
+}
+
+}  // extern "C"

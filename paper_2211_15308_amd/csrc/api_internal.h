@@ -1,0 +1,117 @@
+// Host-side state of the C ABI, shared by the single-problem (api.cpp) and batched
+// (api_batch.cpp) orchestration.
+#pragma once
+#include "fdd.h"
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "fdd_internal.h"
+
+namespace fdd {
+
+// Records the message of a failed call (returned by fdd_last_error) and returns code.
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define HIPCHK(call)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) return fail(FDD_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int round_up(int x, int a) { return (x + a - 1) / a * a; }
+
+// Per-precision multigrid-PCG buffers of level 0 plus the hierarchy.
+template <typename T>
+struct PcgSet {
+  T* x = nullptr;
+  T* r[2] = {nullptr, nullptr};
+  T* p[2] = {nullptr, nullptr};
+  T* s[2] = {nullptr, nullptr};  // s = A p
+  T* z = nullptr;
+  T* w = nullptr;                // w = A z
+  MGBuffers<T> mg{};
+};
+
+// An instantiated graph of one outer iteration and the host-side buffer state after it.
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  int cur_r = 0, cur_p = 0, S = 0, k = 0;
+};
+
+}  // namespace fdd
+
+using fdd::DevState;
+using fdd::EventHook;
+using fdd::GraphEntry;
+using fdd::Level;
+using fdd::PcgSet;
+using fdd::RaResult;
+using fdd::Reductions;
+using fdd::kMaxLevels;
+
+struct fdd_problem_s {
+  int dim = 2, n = 0, device = 0;
+  double K = 1, mu = 1, gamma = 1, h = 1;
+  int64_t N = 0, NI = 0, NG = 0;
+  double lam_lo = 0, lam_hi = 0;
+  int nlev = 0;
+  int first_coarse32 = 1, first_coarse64 = 1;
+  Level lev[kMaxLevels];
+  std::vector<double> cinv;  // dense inverse on the coarsest level
+  std::vector<double> eig;   // exact interface eigenvalues (2D), check points of the RA builder
+  // workspace views
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  DevState* st = nullptr;
+  double* partials = nullptr;   // true-residual reduction
+  Reductions red{};
+  float* cinv32 = nullptr;
+  double* cinv64 = nullptr;
+  PcgSet<float> s32;
+  PcgSet<double> s64;
+  double* u64[2] = {nullptr, nullptr};  // refinement accumulators
+  double* xG[2] = {nullptr, nullptr};
+  double* rG[2] = {nullptr, nullptr};
+  double* pG[2] = {nullptr, nullptr};
+  double* zG = nullptr;
+  double* yG = nullptr;
+  double* Hp = nullptr;
+  double* scratchP = nullptr;
+  double* scratchH = nullptr;
+  DevState* host_st = nullptr;  // pinned copy
+  // inner schedule (refinement steps x PCG iterations, or FP64 PCG iterations); only grows
+  int sched_steps = 1, sched_its = 2, sched_its64 = 4;
+  int sched_step_its[8] = {2, 2, 2, 2, 2, 2, 2, 2};  // per refinement step (mixed)
+  bool calibrated = false;  // the first interior solve runs every PCG to its own criterion
+  // captured outer iterations, keyed by (parity, schedule, precision, smoother)
+  std::map<std::tuple<int, int, int, int, int>, GraphEntry> graphs;
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // kernel timer (HIP events around every launch of one kernel kind)
+  EventHook hook;
+  long long timed_launches = 0, timed_long = 0;
+  double timed_ms = 0.0, timed_long_ms = 0.0;
+  double timer_split_ms = 0.008;
+};
+
+struct fdd_ratpc_s {
+  int which = 0;
+  const fdd_problem_s* prob = nullptr;
+  int n = 0;
+  double K = 0, mu = 0;
+  RaResult r{};
+};
+
+
+namespace fdd {
+
+ShiftTable make_table(const fdd_ratpc_s* t);
+bool opts_ok(const fdd_opts* o);
+int check_problem(fdd_problem_s* P);
+int check_table(const fdd_problem_s* P, const fdd_ratpc_s* t, int which);
+
+}  // namespace fdd

@@ -57,6 +57,10 @@ struct DevState {
   int pcg_is_final;  // FP64 mode: the PCG residual is the interior solve's residual
   int run_its_max;   // largest iteration count of a PCG run in this interior solve
   int run_len[8];    // PCG iterations of each refinement step's run (first 8 steps)
+  int outer_done;    // batched solve: this instance's outer PCG has converged
+  int o_ver;         // batched solve: version (parity) holding the final interface iterate
+  int o_its;         // batched solve: outer iterations of this instance
+  int pad2;
   unsigned counters[16];   // ticket of the true-residual reduction
 };
 
@@ -169,6 +173,63 @@ void launch_copy_rows(hipStream_t s, const double* src, int sp, double* dst, int
 void launch_full_operator(hipStream_t s, int n, double K, double gamma, const double* x,
                           const double* Hx, double* y, const double* b, double* partials,
                           unsigned* counter, double* res);
+
+// ---- batched solve (kernels_batch.hip) ------------------------------------------------------
+// One independent 2D instance of a batch, as seen by the batched kernels (device memory).  All
+// pointers refer to the instance's own bound workspace; the FP32 multigrid-PCG set is used.
+struct BInst {
+  int nlev, fc;                       // levels; first level solved inside one workgroup
+  int nf[kMaxLevels], pitch[kMaxLevels];
+  int tiles_x[kMaxLevels];            // tiles per row of each tiled level (0 if not tiled)
+  float* f[kMaxLevels];
+  float* u[kMaxLevels];
+  float* e[kMaxLevels];
+  float *x, *r[2], *p[2], *s[2], *z, *w;
+  double* u64[2];
+  const float* cinv;
+  DevState* st;
+  Reductions red;
+  // interface / outer PCG
+  int ng, mP, mH;                     // interface size; systems in the P and H batches
+  double h, K, gamma;
+  const double* b;                    // caller right-hand side (free-dof order)
+  double* xout;                       // caller solution
+  double *xG[2], *rG[2], *pG[2], *zG, *yG, *Hp, *scrP, *scrH;
+  const ShiftTable* tabP;
+  const ShiftTable* tabH;
+};
+
+// Work lists of a batch (device memory): prefix sums over instances.
+struct BLists {
+  const int* tiles[kMaxLevels];       // tiles of each instance at level l (ninst + 1 entries)
+  const int* sysP;                    // RA systems of the preconditioner batch
+  const int* sysH;                    // RA systems of the operator batch
+  int ninst;
+};
+
+// right-hand side kinds of a batched interior solve
+enum BRhs { kRhsB = 0, kRhsLiftP = 1, kRhsBack = 2 };
+
+struct BatchCtx {
+  hipStream_t stream;
+  const BInst* inst;
+  BLists lists;
+  int nu;
+  int max_tiled;                      // largest number of tiled levels over the instances
+  int tiles_total[kMaxLevels];        // grid sizes of the tiled levels
+  int sysP_total, sysH_total;
+  int skip_done;                      // kernels skip instances whose outer PCG has converged
+};
+
+void launch_b_inner_start(const BatchCtx& c, int rhs, int ver, double tol2, double tau2);
+void launch_b_inner_step(const BatchCtx& c, int rhs, int ver, int its, int S, int& cur_r,
+                         int& cur_p);
+void launch_b_rhs_reduce(const BatchCtx& c, int S);
+void launch_b_precond_init(const BatchCtx& c, double rtol);
+void launch_b_outer_tail(const BatchCtx& c, int S, int v, double rtol);
+void launch_b_operator(const BatchCtx& c, int v);
+void launch_b_scatter(const BatchCtx& c, int S, int ver);
+void launch_b_gather_states(const BatchCtx& c, DevState* out);
 
 // ---- host rational approximation (ra_build.cpp) --------------------------------------------
 struct RaResult {

@@ -1,0 +1,310 @@
+// Batched form of the 2D solver: many independent instances (different n, K, mu) advance
+// together, and every launch covers all of them.  A level kernel's grid is the concatenated list
+// of the tiles of every instance that has that level (a block finds its instance by binary search
+// in a prefix table); the coarse-level kernel runs one workgroup per instance; all shifted
+// interface systems of all instances (eq. (RA), one per pole) form one launch.  The arithmetic is
+// the single-instance device code (mg_device.h, iface_device.h), so a batch of one reproduces
+// the single-instance solve.  Instances whose outer PCG has converged return at once.
+#include "iface_device.h"
+#include "mg_device.h"
+
+namespace fdd {
+
+// Largest i with start[i] <= b, for a non-decreasing prefix table start[0..ninst].
+__device__ __forceinline__ int find_inst(const int* __restrict__ start, int ninst, int b) {
+  int lo = 0, hi = ninst;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool inst_idle(const DevState* st, int skip_done) {
+  return skip_done && st->outer_done;
+}
+
+// The outer tail of an instance runs only once its interior solve of this iteration has met its
+// tolerance; otherwise the host completes the solve and repeats the tail.
+__device__ __forceinline__ bool tail_idle(const DevState* st, int skip_done) {
+  return (skip_done && st->outer_done) || !st->solve_done;
+}
+
+template <int NU, bool CG>
+__global__ __launch_bounds__(kBlock) void kb_mg_down(const BInst* __restrict__ I, BLists L,
+                                                     int level, int k, int cur_r, int cur_p,
+                                                     int check, int skip_done) {
+  const int b = blockIdx.x;
+  const int* start = L.tiles[level];
+  const int i = find_inst(start, L.ninst, b);
+  const BInst& P = I[i];
+  DevState* st = P.st;
+  if (inst_idle(st, skip_done) || stopped(st)) return;
+  const int t = b - start[i];
+  const int tx = P.tiles_x[level];
+  const int tile_x = t % tx, tile_y = t / tx;
+  const bool lead = (t == 0);
+  if (check && level == 1 && pcg_converged(st, P.red, lead)) return;
+  if (CG) {
+    d_mg_down<float, NU, true>(P.r[cur_r], P.u[0], P.f[1], P.nf[0], P.pitch[0], P.pitch[1], P.w,
+                               P.s[cur_p], P.s[cur_p ^ 1], P.z, P.p[cur_p], P.p[cur_p ^ 1], P.x,
+                               P.r[cur_r ^ 1], st, P.red, k, tile_x, tile_y, t, lead);
+  } else {
+    const float* fin = level == 0 ? P.r[cur_r] : P.f[level];
+    d_mg_down<float, NU, false>(fin, P.u[level], P.f[level + 1], P.nf[level], P.pitch[level],
+                                P.pitch[level + 1], nullptr, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, nullptr, nullptr, st, P.red, 0, tile_x, tile_y, t, lead);
+  }
+}
+
+template <int NU, bool CG>
+__global__ __launch_bounds__(kBlock) void kb_mg_up(const BInst* __restrict__ I, BLists L,
+                                                   int level, int kn, int count, int cur_r,
+                                                   int skip_done) {
+  const int b = blockIdx.x;
+  const int* start = L.tiles[level];
+  const int i = find_inst(start, L.ninst, b);
+  const BInst& P = I[i];
+  DevState* st = P.st;
+  if (inst_idle(st, skip_done) || stopped(st)) return;
+  const int t = b - start[i];
+  const int tx = P.tiles_x[level];
+  const int tile_x = t % tx, tile_y = t / tx;
+  const bool lead = (t == 0);
+  if (CG) {
+    d_mg_up<float, NU, true>(P.r[cur_r], P.u[0], P.e[1], P.z, P.w, P.nf[0], P.pitch[0],
+                             P.pitch[1], st, P.red, kn, count, tile_x, tile_y, t, lead);
+  } else {
+    d_mg_up<float, NU, false>(P.f[level], P.u[level], P.e[level + 1], P.e[level], nullptr,
+                              P.nf[level], P.pitch[level], P.pitch[level + 1], st, P.red, 0, 0,
+                              tile_x, tile_y, t, lead);
+  }
+}
+
+template <int NU>
+__global__ __launch_bounds__(kCoarseThreads) void kb_coarse(const BInst* __restrict__ I, int check,
+                                                            int skip_done) {
+  const BInst& P = I[blockIdx.x];
+  DevState* st = P.st;
+  if (inst_idle(st, skip_done) || stopped(st)) return;
+  if (check && P.fc == 1 && pcg_converged(st, P.red, true)) return;
+  LaunchLevels lv;
+  lv.first = P.fc;
+  lv.nlev = P.nlev;
+  for (int l = 0; l < kMaxLevels; ++l) lv.nf[l] = P.nf[l];
+  d_coarse_vcycle<float, NU>(P.f[P.fc], P.pitch[P.fc], P.e[P.fc], lv, P.cinv);
+}
+
+// Version of the final interface iterate: the converged one, else the last (ver).
+__device__ __forceinline__ int final_ver(const DevState* st, int ver) {
+  return st->outer_done ? st->o_ver : ver;
+}
+
+// Right-hand side of a batched interior solve: b, the lifted p (version ver), or the
+// back-substitution b/K + lift(x_G) with x_G the instance's final iterate.
+__device__ __forceinline__ RhsDesc b_rhs(const BInst& P, int kind, int ver) {
+  if (kind == kRhsB) return RhsDesc{P.b, 1.0, nullptr, 0.0};
+  if (kind == kRhsLiftP) return RhsDesc{nullptr, 0.0, P.pG[ver & 1], 1.0};
+  return RhsDesc{P.b, 1.0 / P.K, P.xG[final_ver(P.st, ver) & 1], 1.0};
+}
+
+__global__ __launch_bounds__(kBlock) void kb_ir_residual(const BInst* __restrict__ I, BLists L,
+                                                         int first, int rhs, int ver, int S,
+                                                         int cur_r, double tol2, double tau2,
+                                                         int skip_done) {
+  const int b = blockIdx.x;
+  const int* start = L.tiles[0];
+  const int i = find_inst(start, L.ninst, b);
+  const BInst& P = I[i];
+  DevState* st = P.st;
+  if (inst_idle(st, skip_done)) return;
+  const int t = b - start[i];
+  const int tx = P.tiles_x[0];
+  const RhsDesc f = b_rhs(P, rhs, ver);
+  d_ir_residual<float>(f, first ? nullptr : P.u64[S & 1], P.x,
+                       first ? P.u64[0] : P.u64[(S + 1) & 1], P.r[cur_r], nullptr, P.nf[0],
+                       P.pitch[0], first, tol2, tau2, 0, st, P.red, t % tx, t / tx, t, t == 0);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_ir_finalize(const BInst* __restrict__ I,
+                                                         int skip_done) {
+  const BInst& P = I[blockIdx.x];
+  if (inst_idle(P.st, skip_done)) return;
+  d_ir_finalize(P.st, P.red);
+}
+
+// which = 0: preconditioner batch on r (sel 0: r_G[0], sel 1: r_G[(ver + 1) & 1], part of the
+// outer tail); which = 1: operator batch on p_G[ver & 1].
+__global__ __launch_bounds__(kIfaceThreads) void kb_iface_solve(const BInst* __restrict__ I,
+                                                                BLists L, int which, int sel,
+                                                                int ver, int skip_done) {
+  const int b = blockIdx.x;
+  const int* start = which ? L.sysH : L.sysP;
+  const int i = find_inst(start, L.ninst, b);
+  const BInst& P = I[i];
+  if (which == 0 && sel ? tail_idle(P.st, skip_done) : inst_idle(P.st, skip_done)) return;
+  const int k = b - start[i];
+  const ShiftTable* tab = which ? P.tabH : P.tabP;
+  const double* in = which ? P.pG[ver & 1] : (sel ? P.rG[(ver + 1) & 1] : P.rG[0]);
+  double* out = (which ? P.scrH : P.scrP) + (size_t)k * P.ng;
+  d_iface_solve(P.ng, P.h, tab->alpha[k], tab->beta[k], tab->coef[k],
+                which ? kIfaceOperator : kIfacePrecond, in, out);
+}
+
+__global__ __launch_bounds__(kIfaceThreads) void kb_iface_combine(const BInst* __restrict__ I,
+                                                                  int which, int ver, int first,
+                                                                  double rtol2, int skip_done) {
+  const BInst& P = I[blockIdx.x];
+  if (which == 0 && !first ? tail_idle(P.st, skip_done) : inst_idle(P.st, skip_done)) return;
+  if (which) {
+    d_iface_combine(P.ng, P.h, P.mH, P.tabH->d0, kIfaceOperator, P.pG[ver & 1], P.Hp, P.scrH,
+                    P.st, nullptr, nullptr, ver, 0, -1.0);
+  } else {
+    const double* r = first ? P.rG[0] : P.rG[(ver + 1) & 1];
+    double* pn = first ? P.pG[0] : P.pG[(ver + 1) & 1];
+    d_iface_combine(P.ng, P.h, P.mP, 0.0, kIfacePrecondOuter, r, P.zG, P.scrP, P.st,
+                    P.pG[ver & 1], pn, ver, first, rtol2);
+  }
+}
+
+__global__ __launch_bounds__(kIfaceThreads) void kb_schur_gather(const BInst* __restrict__ I,
+                                                                 int S, int ver, int skip_done) {
+  const BInst& P = I[blockIdx.x];
+  if (tail_idle(P.st, skip_done)) return;
+  const int a = ver & 1, bb = (ver + 1) & 1;
+  d_schur_gather(P.ng, P.nf[0], P.pitch[0], P.K, P.gamma, P.pG[a], P.u64[S & 1], P.Hp, P.yG,
+                 P.xG[a], P.xG[bb], P.rG[a], P.rG[bb], P.st, 1, ver);
+}
+
+// g = b_G + u|row nf, x_G = 0, and the outer state of every instance reset.
+__global__ __launch_bounds__(256) void kb_rhs_reduce(const BInst* __restrict__ I, int S) {
+  const BInst& P = I[blockIdx.x];
+  const size_t row = (size_t)(P.nf[0] - 1) * P.pitch[0];
+  const double* u = P.u64[S & 1];
+  const double* bG = P.b + (size_t)P.nf[0] * P.nf[0];
+  for (int i = threadIdx.x; i < P.ng; i += blockDim.x) {
+    P.rG[0][i] = bG[i] + u[row + i];
+    P.xG[0][i] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    P.st->outer_done = 0;
+    P.st->o_ver = 0;
+    P.st->o_its = 0;
+  }
+}
+
+// Interior solution (padded) and the final interface iterate into the caller's vector.
+__global__ __launch_bounds__(256) void kb_scatter(const BInst* __restrict__ I, int S, int ver) {
+  const BInst& P = I[blockIdx.x];
+  const int nf = P.nf[0];
+  const int64_t NI = (int64_t)nf * nf;
+  const double* u = P.u64[S & 1];
+  const double* xG = P.xG[final_ver(P.st, ver) & 1];
+  for (int64_t k = threadIdx.x + (int64_t)blockIdx.y * blockDim.x; k < NI + nf;
+       k += (int64_t)blockDim.x * gridDim.y) {
+    if (k < NI) P.xout[k] = u[(size_t)(k / nf) * P.pitch[0] + (k % nf)];
+    else P.xout[k] = xG[k - NI];
+  }
+}
+
+// Copies every instance's DevState into one array (one read-back per synchronization).
+__global__ void kb_gather_states(const BInst* __restrict__ I, int ninst, DevState* out) {
+  const int i = blockIdx.x;
+  if (i >= ninst) return;
+  const unsigned* src = reinterpret_cast<const unsigned*>(I[i].st);
+  unsigned* dst = reinterpret_cast<unsigned*>(out + i);
+  for (int w = threadIdx.x; w < (int)(sizeof(DevState) / 4); w += blockDim.x) dst[w] = src[w];
+}
+
+// ---- launchers ------------------------------------------------------------------------------
+
+static inline dim3 tb() { return dim3(32, kBlock / 32); }
+
+template <int NU>
+static void b_tail(const BatchCtx& c, int check) {
+  for (int l = 1; l < c.max_tiled; ++l)
+    if (c.tiles_total[l] > 0)
+      hipLaunchKernelGGL((kb_mg_down<NU, false>), dim3(c.tiles_total[l]), tb(), 0, c.stream,
+                         c.inst, c.lists, l, 0, 0, 0, check, c.skip_done);
+  hipLaunchKernelGGL((kb_coarse<NU>), dim3(c.lists.ninst), dim3(kCoarseThreads), 0, c.stream,
+                     c.inst, check, c.skip_done);
+  for (int l = c.max_tiled - 1; l >= 1; --l)
+    if (c.tiles_total[l] > 0)
+      hipLaunchKernelGGL((kb_mg_up<NU, false>), dim3(c.tiles_total[l]), tb(), 0, c.stream, c.inst,
+                         c.lists, l, 0, 0, 0, c.skip_done);
+}
+
+template <int NU>
+static void b_step(const BatchCtx& c, int rhs, int ver, int its, int S, int& cur_r, int& cur_p) {
+  // PCG start: z = V r, w = A z, r.z and z.w
+  hipLaunchKernelGGL((kb_mg_down<NU, false>), dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst,
+                     c.lists, 0, 0, cur_r, cur_p, 0, c.skip_done);
+  b_tail<NU>(c, 0);
+  hipLaunchKernelGGL((kb_mg_up<NU, true>), dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst,
+                     c.lists, 0, 0, 0, cur_r, c.skip_done);
+  for (int k = 0; k < its; ++k) {
+    hipLaunchKernelGGL((kb_mg_down<NU, true>), dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst,
+                       c.lists, 0, k, cur_r, cur_p, 0, c.skip_done);
+    b_tail<NU>(c, 1);
+    hipLaunchKernelGGL((kb_mg_up<NU, true>), dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst,
+                       c.lists, 0, k + 1, 1, cur_r ^ 1, c.skip_done);
+    cur_r ^= 1;
+    cur_p ^= 1;
+  }
+  hipLaunchKernelGGL(kb_ir_residual, dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst, c.lists,
+                     0, rhs, ver, S, cur_r, 0.0, 0.0, c.skip_done);
+  hipLaunchKernelGGL(kb_ir_finalize, dim3(c.lists.ninst), dim3(kBlock), 0, c.stream, c.inst,
+                     c.skip_done);
+}
+
+void launch_b_inner_start(const BatchCtx& c, int rhs, int ver, double tol2, double tau2) {
+  hipLaunchKernelGGL(kb_ir_residual, dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst, c.lists,
+                     1, rhs, ver, 0, 0, tol2, tau2, c.skip_done);
+  hipLaunchKernelGGL(kb_ir_finalize, dim3(c.lists.ninst), dim3(kBlock), 0, c.stream, c.inst,
+                     c.skip_done);
+}
+
+void launch_b_inner_step(const BatchCtx& c, int rhs, int ver, int its, int S, int& cur_r,
+                         int& cur_p) {
+  if (c.nu == 2) b_step<2>(c, rhs, ver, its, S, cur_r, cur_p);
+  else b_step<1>(c, rhs, ver, its, S, cur_r, cur_p);
+}
+
+void launch_b_rhs_reduce(const BatchCtx& c, int S) {
+  hipLaunchKernelGGL(kb_rhs_reduce, dim3(c.lists.ninst), dim3(256), 0, c.stream, c.inst, S);
+}
+
+void launch_b_precond_init(const BatchCtx& c, double rtol) {
+  hipLaunchKernelGGL(kb_iface_solve, dim3(c.sysP_total), dim3(kIfaceThreads), 0, c.stream, c.inst,
+                     c.lists, 0, 0, 0, 0);
+  hipLaunchKernelGGL(kb_iface_combine, dim3(c.lists.ninst), dim3(kIfaceThreads), 0, c.stream,
+                     c.inst, 0, 0, 1, rtol * rtol, 0);
+}
+
+void launch_b_operator(const BatchCtx& c, int v) {
+  hipLaunchKernelGGL(kb_iface_solve, dim3(c.sysH_total), dim3(kIfaceThreads), 0, c.stream, c.inst,
+                     c.lists, 1, 0, v, c.skip_done);
+  hipLaunchKernelGGL(kb_iface_combine, dim3(c.lists.ninst), dim3(kIfaceThreads), 0, c.stream,
+                     c.inst, 1, v, 0, -1.0, c.skip_done);
+}
+
+void launch_b_outer_tail(const BatchCtx& c, int S, int v, double rtol) {
+  hipLaunchKernelGGL(kb_schur_gather, dim3(c.lists.ninst), dim3(kIfaceThreads), 0, c.stream,
+                     c.inst, S, v, c.skip_done);
+  hipLaunchKernelGGL(kb_iface_solve, dim3(c.sysP_total), dim3(kIfaceThreads), 0, c.stream, c.inst,
+                     c.lists, 0, 1, v, c.skip_done);
+  hipLaunchKernelGGL(kb_iface_combine, dim3(c.lists.ninst), dim3(kIfaceThreads), 0, c.stream,
+                     c.inst, 0, v, 0, rtol * rtol, c.skip_done);
+}
+
+void launch_b_scatter(const BatchCtx& c, int S, int ver) {
+  hipLaunchKernelGGL(kb_scatter, dim3(c.lists.ninst, 64), dim3(256), 0, c.stream, c.inst, S, ver);
+}
+
+void launch_b_gather_states(const BatchCtx& c, DevState* out) {
+  hipLaunchKernelGGL(kb_gather_states, dim3(c.lists.ninst), dim3(64), 0, c.stream, c.inst,
+                     c.lists.ninst, out);
+}
+
+}  // namespace fdd

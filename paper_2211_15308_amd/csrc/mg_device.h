@@ -1,0 +1,667 @@
+// Device-side building blocks of the interior multigrid-PCG solve (2D P1 grid, 5-point
+// stencil 4, -1, -1, -1, -1), shared by the single-instance kernels (kernels_mg.hip) and the
+// batched kernels (kernels_batch.hip).  See kernels_mg.hip for the method.
+#pragma once
+#include "fdd_internal.h"
+
+namespace fdd {
+
+// --------------------------------------------------------------------------------------------
+// helpers
+// --------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ bool is_red(int i, int j) { return ((i + j) & 1) == 0; }
+
+__device__ __forceinline__ int flat_tid() { return threadIdx.y * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ int nthreads() { return blockDim.x * blockDim.y; }
+
+// Sum over the block, broadcast to every thread (fixed order: deterministic).
+__device__ __forceinline__ double block_sum_all(double v) {
+  __shared__ double sh[kCoarseThreads / 64 + 1];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int t = flat_tid();
+  const int lane = t & 63, wid = t >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  if (t == 0) {
+    double s = 0.0;
+    const int nw = (nthreads() + 63) >> 6;
+    for (int w = 0; w < nw; ++w) s += sh[w];
+    sh[kCoarseThreads / 64] = s;
+  }
+  __syncthreads();
+  return sh[kCoarseThreads / 64];
+}
+
+// Fixed-order sum of nb partials, identical in every block of equal size.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, int nb) {
+  double v = 0.0;
+  for (int k = flat_tid(); k < nb; k += nthreads()) v += p[k];
+  return block_sum_all(v);
+}
+
+__device__ __forceinline__ bool block0() { return blockIdx.x == 0 && blockIdx.y == 0; }
+
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8 XCDs by linear id, so
+// the linear id b runs on XCD b % 8.  Tile t = (b % 8) q + b / 8 (q = nb / 8; the remainder keeps
+// t = b) gives each XCD a contiguous strip of tile rows, so halos shared by neighbouring tiles are
+// fetched into one L2 instead of several.  Returns the tile id; (tx, ty) are its coordinates.
+__device__ __forceinline__ int xcd_tile(int* tx, int* ty) {
+  const int nbx = gridDim.x, nb = gridDim.x * gridDim.y;
+  const int b = blockIdx.y * nbx + blockIdx.x;
+  const int q = nb >> 3;
+  const int t = (b < 8 * q) ? (b & 7) * q + (b >> 3) : b;
+  *tx = t % nbx;
+  *ty = t / nbx;
+  return t;
+}
+__device__ __forceinline__ bool thread0() { return threadIdx.x == 0 && threadIdx.y == 0; }
+
+__device__ __forceinline__ bool stopped(const DevState* st) {
+  return (st->inner_done | st->solve_done) != 0;
+}
+
+// Convergence test of the running PCG from the partials of ||r||^2 (stored by the level-0
+// down kernel).  Called by every block of the first kernel after it; returns true if the run
+// is over (converged or broken down).
+__device__ __forceinline__ bool pcg_converged(DevState* st, const Reductions& red, bool lead) {
+  const double rr = sum_partials(red.rr, red.nb0);
+  const bool bad = !isfinite(rr);
+  const bool conv = bad || rr <= st->tau2 * st->rr0;
+  if (lead && thread0()) {
+    st->rr = rr;
+    if (bad) st->breakdown |= 4;
+    if (conv) {
+      st->inner_done = 1;
+      if (st->pcg_is_final) st->solve_done = 1;
+    }
+  }
+  return conv;
+}
+
+template <typename T>
+__device__ __forceinline__ T gload(const T* a, int pitch, int nf, int i, int j) {
+  return (i >= 1 && i <= nf && j >= 1 && j <= nf) ? a[(size_t)(j - 1) * pitch + (i - 1)] : T(0);
+}
+
+// P1 interpolation from the coarse grid (nc points per side) to fine point (i, j).
+template <typename T>
+__device__ __forceinline__ T prolong(const T* ec, int pc, int nc, int i, int j) {
+  const int I = i >> 1, J = j >> 1;
+  if (!(i & 1) && !(j & 1)) return gload(ec, pc, nc, I, J);
+  if ((i & 1) && !(j & 1)) return T(0.5) * (gload(ec, pc, nc, I, J) + gload(ec, pc, nc, I + 1, J));
+  if (!(i & 1) && (j & 1)) return T(0.5) * (gload(ec, pc, nc, I, J) + gload(ec, pc, nc, I, J + 1));
+  return T(0.5) * (gload(ec, pc, nc, I, J) + gload(ec, pc, nc, I + 1, J + 1));
+}
+
+// one red or black half-sweep over the window cells 1..W-2 that lie inside the domain
+template <typename T, int W>
+__device__ __forceinline__ void tile_halfsweep(T (*su)[W + 1], const T (*sf)[W + 1], int ib, int jb,
+                                               int nf, bool red) {
+  for (int lj = 1 + threadIdx.y; lj < W - 1; lj += blockDim.y) {
+    const int j = jb + lj;
+    if (j < 1 || j > nf) continue;
+    for (int li = 1 + threadIdx.x; li < W - 1; li += blockDim.x) {
+      const int i = ib + li;
+      if (i < 1 || i > nf || is_red(i, j) != red) continue;
+      su[lj][li] = T(0.25) * (sf[lj][li] + su[lj][li - 1] + su[lj][li + 1] + su[lj - 1][li] +
+                              su[lj + 1][li]);
+    }
+  }
+  __syncthreads();
+}
+
+// --------------------------------------------------------------------------------------------
+// fused level kernels
+// --------------------------------------------------------------------------------------------
+// Thread layout of the tiled kernels: 32 x 8 threads; a window of W x W cells is covered by
+// RY x RX register slots per thread, cell (ty + 8 a, tx + 32 b).  All global loads of a window
+// are issued into registers before the first use, so a block waits for one memory latency.
+
+template <int W>
+struct Slots {
+  static constexpr int RY = (W + 7) / 8;
+  static constexpr int RX = (W + 31) / 32;
+};
+
+// Going down one level: u = S^nu(0; f) (red first), r = f - A u, f_c = P^T r.
+// CG = true (level 0, inner PCG iteration k, single-reduction form):
+//   gamma_k = r_k . z_k and delta_k = z_k . w_k come from the partials of the previous V-cycle;
+//   beta_k = gamma_k / gamma_{k-1}, alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1})
+//   (beta_0 = 0, alpha_0 = gamma_0 / delta_0).  On the window s_k = w_k + beta_k s_{k-1} and
+//   f = r_{k+1} = r_k - alpha_k s_k; on own points p_k = z_k + beta_k p_{k-1}, x += alpha_k p_k,
+//   and r_{k+1}, s_k, p_k are stored; ||r_{k+1}||^2 goes to red.rr.
+// check != 0 (first kernel after the level-0 down kernel): returns if the PCG has converged.
+template <typename T, int NU, bool CG>
+__device__ __forceinline__ void d_mg_down(
+    const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
+    int pc, const T* __restrict__ w, const T* __restrict__ sold, T* __restrict__ snew,
+    const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ x,
+    T* __restrict__ rout, DevState* st, const Reductions& red, int k, int tile_x, int tile_y,
+    int tile, bool lead) {
+  constexpr int H = 2 * NU + 1;
+  constexpr int W = kTile + 2 * H;
+  constexpr int RY = Slots<W>::RY, RX = Slots<W>::RX;
+  __shared__ T sf[W][W + 1];
+  __shared__ T su[W][W + 1];
+  const int i0 = tile_x * kTile, j0 = tile_y * kTile;
+  const int ib = i0 + 1 - H, jb = j0 + 1 - H;  // global index of window cell (0, 0)
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  T fr[RY][RX], wr[RY][RX], sr[RY][RX], zr[RY][RX], pr[RY][RX], xr[RY][RX];
+#pragma unroll
+  for (int a = 0; a < RY; ++a) {
+#pragma unroll
+    for (int b = 0; b < RX; ++b) {
+      const int lj = ty + 8 * a, li = tx + 32 * b;
+      const int i = ib + li, j = jb + lj;
+      const bool in = lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+      fr[a][b] = in ? fin[o] : T(0);
+      if (CG) {
+        const bool own = in && li >= H && li < H + kTile && lj >= H && lj < H + kTile;
+        wr[a][b] = in ? w[o] : T(0);
+        sr[a][b] = (in && k > 0) ? sold[o] : T(0);
+        zr[a][b] = own ? z[o] : T(0);
+        pr[a][b] = (own && k > 0) ? pold[o] : T(0);
+        xr[a][b] = (own && k > 0) ? x[o] : T(0);
+      }
+    }
+  }
+  T alpha = T(0), beta = T(0);
+  if (CG) {
+    const double gam = sum_partials(red.rz[k & 1], red.nb0);
+    const double del = sum_partials(red.zw[k & 1], red.nb0);
+    double b = 0.0, den = del;
+    if (k > 0) {
+      const double gam_prev = sum_partials(red.rz[(k - 1) & 1], red.nb0);
+      b = gam / gam_prev;
+      den = del - b * gam / st->cg_alpha[(k - 1) & 1];
+    }
+    if (!(gam > 0.0) || !(den > 0.0) || !isfinite(den) || !isfinite(gam)) {
+      // gamma = 0: the residual is exactly zero and the run is over; otherwise a breakdown
+      if (lead && thread0()) {
+        if (gam != 0.0) st->breakdown |= (isfinite(den) && isfinite(gam)) ? 1 : 4;
+        st->inner_done = 1;
+      }
+      return;
+    }
+    const double al = gam / den;
+    if (lead && thread0()) st->cg_alpha[k & 1] = al;
+    alpha = (T)al;
+    beta = (T)b;
+  }
+  double rr = 0.0;
+#pragma unroll
+  for (int a = 0; a < RY; ++a) {
+#pragma unroll
+    for (int b = 0; b < RX; ++b) {
+      const int lj = ty + 8 * a, li = tx + 32 * b;
+      if (lj >= W || li >= W) continue;
+      const int i = ib + li, j = jb + lj;
+      T f = fr[a][b];
+      if (CG) {
+        const T sv = wr[a][b] + beta * sr[a][b];
+        f = f - alpha * sv;
+        const bool own = li >= H && li < H + kTile && lj >= H && lj < H + kTile && i >= 1 &&
+                         i <= nf && j >= 1 && j <= nf;
+        if (own) {
+          const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+          const T pv = zr[a][b] + beta * pr[a][b];
+          rout[o] = f;
+          snew[o] = sv;
+          pnew[o] = pv;
+          x[o] = xr[a][b] + alpha * pv;
+          rr += (double)f * (double)f;
+        }
+      }
+      sf[lj][li] = f;
+      // first red half-sweep from a zero iterate: u = f / 4 on red points, 0 on black points
+      su[lj][li] = is_red(i, j) ? T(0.25) * f : T(0);
+    }
+  }
+  __syncthreads();
+  for (int s = 1; s < 2 * NU; ++s) tile_halfsweep<T, W>(su, sf, ib, jb, nf, !(s & 1));
+  // residual, in place of f (each point reads its own f and the neighbours' u)
+  for (int lj = 1 + ty; lj < W - 1; lj += 8)
+    for (int li = 1 + tx; li < W - 1; li += 32)
+      sf[lj][li] = sf[lj][li] - (T(4) * su[lj][li] - su[lj][li - 1] - su[lj][li + 1] -
+                                 su[lj - 1][li] - su[lj + 1][li]);
+  __syncthreads();
+  // restriction to the coarse points whose fine index 2I lies in this tile
+  const int nc = (nf - 1) >> 1;
+  constexpr int TC = kTile / 2;
+  for (int bb = ty; bb < TC; bb += 8) {
+    const int J = (j0 >> 1) + 1 + bb;
+    const int I = (i0 >> 1) + 1 + tx;
+    if (J > nc || tx >= TC || I > nc) continue;
+    const int li = 2 * I - ib, lj = 2 * J - jb;
+    const T v = sf[lj][li] + T(0.5) * (sf[lj][li - 1] + sf[lj][li + 1] + sf[lj - 1][li] +
+                                       sf[lj + 1][li] + sf[lj - 1][li - 1] + sf[lj + 1][li + 1]);
+    fc[(size_t)(J - 1) * pc + (I - 1)] = v;
+  }
+  // store the pre-smoothed iterate on own points
+  for (int bb = ty; bb < kTile; bb += 8) {
+    const int j = j0 + 1 + bb, i = i0 + 1 + tx;
+    if (j > nf || i > nf) continue;
+    uout[(size_t)(j - 1) * pitch + (i - 1)] = su[bb + H][tx + H];
+  }
+  if (CG) {
+    const double tot = block_sum_all(rr);
+    if (thread0()) red.rr[tile] = tot;
+  }
+}
+
+// Going up one level: u = u_pre + P e_c, then nu (black, red) pairs; result to eout.
+// CG = true (level 0): the result z is kept valid one cell beyond the tile, so that w = A z is
+// formed on own points too; z and w are stored and the block's parts of r . z and z . w go to
+// red.rz[kn & 1] and red.zw[kn & 1] (f is r).
+template <typename T, int NU, bool CG>
+__device__ __forceinline__ void d_mg_up(
+    const T* __restrict__ fin, const T* __restrict__ upre, const T* __restrict__ ec,
+    T* __restrict__ eout, T* __restrict__ wout, int nf, int pitch, int pc, DevState* st,
+    const Reductions& red, int kn, int count_iteration, int tile_x, int tile_y, int tile,
+    bool lead) {
+  constexpr int H = 2 * NU + (CG ? 1 : 0);
+  constexpr int W = kTile + 2 * H;
+  constexpr int RY = Slots<W>::RY, RX = Slots<W>::RX;
+  constexpr int CW = W / 2 + 2;  // coarse patch edge
+  constexpr int CRY = Slots<CW>::RY, CRX = Slots<CW>::RX;
+  __shared__ T sf[W][W + 1];
+  __shared__ T su[W][W + 1];
+  __shared__ T sc[CW][CW + 1];
+  const int i0 = tile_x * kTile, j0 = tile_y * kTile;
+  const int ib = i0 + 1 - H, jb = j0 + 1 - H;
+  const int Ib = ib >> 1, Jb = jb >> 1;  // floor (arithmetic shift)
+  const int nc = (nf - 1) >> 1;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  T fr[RY][RX], ur[RY][RX], cr[CRY][CRX];
+#pragma unroll
+  for (int a = 0; a < RY; ++a) {
+#pragma unroll
+    for (int b = 0; b < RX; ++b) {
+      const int lj = ty + 8 * a, li = tx + 32 * b;
+      const int i = ib + li, j = jb + lj;
+      const bool in = lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+      fr[a][b] = in ? fin[o] : T(0);
+      ur[a][b] = in ? upre[o] : T(0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < CRY; ++a) {
+#pragma unroll
+    for (int b = 0; b < CRX; ++b) {
+      const int lj = ty + 8 * a, li = tx + 32 * b;
+      const int I = Ib + li, J = Jb + lj;
+      const bool in = lj < CW && li < CW && I >= 1 && I <= nc && J >= 1 && J <= nc;
+      cr[a][b] = in ? ec[(size_t)(J - 1) * pc + (I - 1)] : T(0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < CRY; ++a)
+#pragma unroll
+    for (int b = 0; b < CRX; ++b) {
+      const int lj = ty + 8 * a, li = tx + 32 * b;
+      if (lj < CW && li < CW) sc[lj][li] = cr[a][b];
+    }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < RY; ++a) {
+#pragma unroll
+    for (int b = 0; b < RX; ++b) {
+      const int lj = ty + 8 * a, li = tx + 32 * b;
+      if (lj >= W || li >= W) continue;
+      const int i = ib + li, j = jb + lj;
+      T u = T(0);
+      if (i >= 1 && i <= nf && j >= 1 && j <= nf) {
+        // P1 interpolation of the coarse correction (nested diagonal-split meshes)
+        const int ci = (i >> 1) - Ib, cj = (j >> 1) - Jb;
+        T e;
+        if (!(i & 1) && !(j & 1)) e = sc[cj][ci];
+        else if ((i & 1) && !(j & 1)) e = T(0.5) * (sc[cj][ci] + sc[cj][ci + 1]);
+        else if (!(i & 1) && (j & 1)) e = T(0.5) * (sc[cj][ci] + sc[cj + 1][ci]);
+        else e = T(0.5) * (sc[cj][ci] + sc[cj + 1][ci + 1]);
+        u = ur[a][b] + e;
+      }
+      sf[lj][li] = fr[a][b];
+      su[lj][li] = u;
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < 2 * NU; ++s) tile_halfsweep<T, W>(su, sf, ib, jb, nf, (s & 1));
+  double rz = 0.0, zw = 0.0;
+  for (int bb = ty; bb < kTile; bb += 8) {
+    const int j = j0 + 1 + bb, i = i0 + 1 + tx;
+    if (j > nf || i > nf) continue;
+    const int lj = bb + H, li = tx + H;
+    const T zv = su[lj][li];
+    const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+    eout[o] = zv;
+    if (CG) {
+      const T wv = T(4) * zv - su[lj][li - 1] - su[lj][li + 1] - su[lj - 1][li] - su[lj + 1][li];
+      wout[o] = wv;
+      rz += (double)sf[lj][li] * (double)zv;
+      zw += (double)zv * (double)wv;
+    }
+  }
+  if (CG) {
+    const double trz = block_sum_all(rz);
+    const double tzw = block_sum_all(zw);
+    if (thread0()) {
+      red.rz[kn & 1][tile] = trz;
+      red.zw[kn & 1][tile] = tzw;
+      if (count_iteration && lead) {
+        st->inner_its += 1;
+        st->pcg_k += 1;
+        st->run_its_max = max(st->run_its_max, st->pcg_k);
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------------------------
+// coarse levels in one workgroup
+// --------------------------------------------------------------------------------------------
+// Each level lives in LDS with a one-cell zero border ((nf + 2)^2 cells, row pitch nf + 2), so
+// stencils need no bounds tests.  The 1024 threads form a 32 x 32 grid; thread (tx, ty) owns the
+// points (tx + 1 + 32 a, ty + 1 + 32 b) of a level, at most 2 x 2 of them (nf <= 63).
+
+constexpr int kCinvLds = 64;  // coarsest inverses up to 64 x 64 are staged in LDS
+
+template <typename T>
+struct CoarseLds;  // padded sizes of the in-LDS hierarchy
+template <>
+struct CoarseLds<float> {
+  static constexpr int kMaxNf = 63;
+  static constexpr int kElems = 65 * 65 + 33 * 33 + 17 * 17 + 9 * 9 + 5 * 5 + 3 * 3 + 128;
+};
+template <>
+struct CoarseLds<double> {
+  static constexpr int kMaxNf = 31;
+  static constexpr int kElems = 33 * 33 + 17 * 17 + 9 * 9 + 5 * 5 + 3 * 3 + 128;
+};
+
+// one red or black half-sweep of a padded level
+template <typename T>
+__device__ __forceinline__ void lds_halfsweep(T* u, const T* f, int nf, bool red) {
+  const int pw = nf + 2;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
+      if (i > nf || j > nf || is_red(i, j) != red) continue;
+      const int o = j * pw + i;
+      u[o] = T(0.25) * (f[o] + u[o - 1] + u[o + 1] + u[o - pw] + u[o + pw]);
+    }
+  __syncthreads();
+}
+
+// Levels first..nlev-1 entirely in LDS: V-cycle from the right-hand side fin (level `first`,
+// global memory) to the result eout (global).  The coarsest level is solved exactly with the
+// dense inverse cinv (nfc^2 x nfc^2, row-major), staged in LDS when small.
+template <typename T, int NU>
+__device__ __forceinline__ void d_coarse_vcycle(const T* __restrict__ fin, int pin,
+                                                T* __restrict__ eout, const LaunchLevels& lv,
+                                                const T* __restrict__ cinv) {
+  __shared__ T buf[2 * CoarseLds<T>::kElems];
+  __shared__ T scinv[kCinvLds * kCinvLds];
+  const int first = lv.first, last = lv.nlev - 1;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  T* uL[kMaxLevels];
+  T* fL[kMaxLevels];
+  int tot = 0;
+  for (int l = first; l <= last; ++l) {
+    const int pw = lv.nf[l] + 2;
+    uL[l] = buf + tot;
+    fL[l] = buf + tot + pw * pw;
+    tot += 2 * pw * pw;
+  }
+  // issue the loads of the first level's right-hand side and of a small inverse first
+  const int nf0 = lv.nf[first];
+  T v[2][2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
+      v[b][a] = (i <= nf0 && j <= nf0) ? fin[(size_t)(j - 1) * pin + (i - 1)] : T(0);
+    }
+  const int npc = lv.nf[last] * lv.nf[last];
+  if (npc <= kCinvLds) {
+    constexpr int RC = kCinvLds * kCinvLds / kCoarseThreads;
+    T cv[RC];
+#pragma unroll
+    for (int t = 0; t < RC; ++t) {
+      const int k = threadIdx.x + t * kCoarseThreads;
+      cv[t] = k < npc * npc ? cinv[k] : T(0);
+    }
+#pragma unroll
+    for (int t = 0; t < RC; ++t) scinv[threadIdx.x + t * kCoarseThreads] = cv[t];
+  }
+  for (int k = threadIdx.x; k < tot; k += blockDim.x) buf[k] = T(0);
+  __syncthreads();
+  {
+    const int pw = nf0 + 2;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
+        if (i <= nf0 && j <= nf0) fL[first][j * pw + i] = v[b][a];
+      }
+  }
+  __syncthreads();
+  // down: pre-smooth from zero (red first), restrict the residual
+  for (int l = first; l < last; ++l) {
+    const int nf = lv.nf[l], nc = lv.nf[l + 1];
+    const int pw = nf + 2, pcw = nc + 2;
+    T* u = uL[l];
+    const T* f = fL[l];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
+        if (i <= nf && j <= nf && is_red(i, j)) u[j * pw + i] = T(0.25) * f[j * pw + i];
+      }
+    __syncthreads();
+    for (int s = 1; s < 2 * NU; ++s) lds_halfsweep(u, f, nf, !(s & 1));
+    // coarse points: one per thread (nc <= 31)
+    {
+      const int I = tx + 1, J = ty + 1;
+      if (I <= nc && J <= nc) {
+        const int di[7] = {0, -1, 1, 0, 0, -1, 1};
+        const int dj[7] = {0, 0, 0, -1, 1, -1, 1};
+        T acc = T(0);
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+          const int o = (2 * J + dj[t]) * pw + (2 * I + di[t]);
+          const T r = f[o] - (T(4) * u[o] - u[o - 1] - u[o + 1] - u[o - pw] - u[o + pw]);
+          acc += (t == 0 ? T(1) : T(0.5)) * r;
+        }
+        fL[l + 1][J * pcw + I] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  // coarsest: exact solve with the dense inverse; the right-hand side is first packed densely
+  // (into the zero border-free tail of the buffer) so the product runs without index arithmetic
+  {
+    const int nf = lv.nf[last], pw = nf + 2;
+    const int np = nf * nf;
+    T* u = uL[last];
+    const T* f = fL[last];
+    T* fpk = buf + tot;  // room after the last level: np <= 256 cells
+    for (int k = threadIdx.x; k < np; k += blockDim.x) fpk[k] = f[(k / nf + 1) * pw + (k % nf + 1)];
+    __syncthreads();
+    for (int k = threadIdx.x; k < np; k += blockDim.x) {
+      T acc = T(0);
+      if (np <= kCinvLds) {
+#pragma unroll 7
+        for (int m = 0; m < np; ++m) acc += scinv[k * np + m] * fpk[m];
+      } else {
+#pragma unroll 8
+        for (int m = 0; m < np; ++m) acc += cinv[(size_t)k * np + m] * fpk[m];
+      }
+      u[(k / nf + 1) * pw + (k % nf + 1)] = acc;
+    }
+    __syncthreads();
+  }
+  // up: prolongate and correct, post-smooth (black first)
+  for (int l = last - 1; l >= first; --l) {
+    const int nf = lv.nf[l], pw = nf + 2, pcw = lv.nf[l + 1] + 2;
+    T* u = uL[l];
+    const T* ec = uL[l + 1];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
+        if (i > nf || j > nf) continue;
+        const int o = (j >> 1) * pcw + (i >> 1);
+        T e;
+        if (!(i & 1) && !(j & 1)) e = ec[o];
+        else if ((i & 1) && !(j & 1)) e = T(0.5) * (ec[o] + ec[o + 1]);
+        else if (!(i & 1) && (j & 1)) e = T(0.5) * (ec[o] + ec[o + pcw]);
+        else e = T(0.5) * (ec[o] + ec[o + pcw + 1]);
+        u[j * pw + i] += e;
+      }
+    __syncthreads();
+    for (int s = 0; s < 2 * NU; ++s) lds_halfsweep(u, fL[l], nf, (s & 1));
+  }
+  {
+    const int pw = nf0 + 2;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
+        if (i <= nf0 && j <= nf0) eout[(size_t)(j - 1) * pin + (i - 1)] = uL[first][j * pw + i];
+      }
+  }
+}
+
+// --------------------------------------------------------------------------------------------
+// FP64 residual of the interior solve (iterative refinement)
+// --------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ double rhs_at(const RhsDesc& f, int nf, int i, int j) {
+  double v = 0.0;
+  if (f.b) v = f.sb * f.b[(size_t)(j - 1) * nf + (i - 1)];
+  if (f.g && j == nf) v += f.sg * f.g[i - 1];
+  return v;
+}
+
+// first: u_out = 0, r = f.  Otherwise u_out = u_in + e and r = f - A u_out, or, once the solve
+// has converged, the copy u_out = u_in (so buffer parity follows the schedule).  r is written as
+// FP32 or FP64; the block's ||r||^2 goes to red.ir (and red.ff on the first call).
+template <typename E>
+__device__ __forceinline__ void d_ir_residual(
+    const RhsDesc& f, const double* __restrict__ uin, const E* __restrict__ e,
+    double* __restrict__ uout, float* __restrict__ r32, double* __restrict__ r64, int nf,
+    int pitch, int first, double tol2, double tau2, int pcg_is_final, DevState* st,
+    const Reductions& red, int tile_x, int tile_y, int tile, bool lead) {
+  constexpr int W = kTile + 2;
+  __shared__ double su[W][W + 1];
+  const int i0 = tile_x * kTile, j0 = tile_y * kTile;
+  if (!first && st->solve_done) {
+    for (int b = threadIdx.y; b < kTile; b += blockDim.y) {
+      const int j = j0 + 1 + b;
+      if (j > nf) continue;
+      for (int a = threadIdx.x; a < kTile; a += blockDim.x) {
+        const int i = i0 + 1 + a;
+        if (i > nf) continue;
+        const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+        uout[o] = uin[o];
+      }
+    }
+    return;
+  }
+  constexpr int RY = Slots<W>::RY, RX = Slots<W>::RX;
+  double ur[RY][RX];
+#pragma unroll
+  for (int a = 0; a < RY; ++a) {
+#pragma unroll
+    for (int b = 0; b < RX; ++b) {
+      const int lj = threadIdx.y + 8 * a, li = threadIdx.x + 32 * b;
+      const int i = i0 + li, j = j0 + lj;
+      const bool in = !first && lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+      ur[a][b] = in ? uin[o] + (double)e[o] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < RY; ++a)
+#pragma unroll
+    for (int b = 0; b < RX; ++b) {
+      const int lj = threadIdx.y + 8 * a, li = threadIdx.x + 32 * b;
+      if (lj < W && li < W) su[lj][li] = ur[a][b];
+    }
+  __syncthreads();
+  double rr = 0.0;
+  for (int b = threadIdx.y; b < kTile; b += blockDim.y) {
+    const int j = j0 + 1 + b;
+    if (j > nf) continue;
+    for (int a = threadIdx.x; a < kTile; a += blockDim.x) {
+      const int i = i0 + 1 + a;
+      if (i > nf) continue;
+      const int li = a + 1, lj = b + 1;
+      const double u = su[lj][li];
+      const double r = rhs_at(f, nf, i, j) - (4.0 * u - su[lj][li - 1] - su[lj][li + 1] -
+                                              su[lj - 1][li] - su[lj + 1][li]);
+      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+      uout[o] = u;
+      if (r32) r32[o] = (float)r;
+      if (r64) r64[o] = r;
+      rr += r * r;
+    }
+  }
+  const double tot = block_sum_all(rr);
+  if (thread0()) {
+    red.ir[tile] = tot;
+    if (first) red.ff[tile] = tot;
+    if (lead) {
+      if (first) {
+        st->tol2 = tol2;
+        st->tau2 = tau2;
+        st->pcg_is_final = pcg_is_final;
+        st->breakdown = 0;
+        st->inner_its = 0;
+        st->refine_steps = 0;
+        st->run_its_max = 0;
+        for (int q = 0; q < 8; ++q) st->run_len[q] = 0;
+        st->solve_done = 0;
+      } else {
+        if (st->refine_steps < 8) st->run_len[st->refine_steps] = st->pcg_k;
+        st->refine_steps += 1;
+      }
+    }
+  }
+}
+
+// One block: reads the refinement residual back from the partials and sets the solve's state
+// for the next PCG run (or ends the solve).
+__device__ __forceinline__ void d_ir_finalize(DevState* st, const Reductions& red) {
+  if (st->solve_done) return;
+  const double res = sum_partials(red.ir, red.nb0);
+  const double ff = sum_partials(red.ff, red.nb0);
+  if (thread0()) {
+    st->ff = ff;
+    st->res2 = res;
+    st->rr0 = res;
+    st->inner_done = 0;
+    st->pcg_k = 0;
+    if (!isfinite(res)) {
+      st->breakdown |= 4;
+      st->solve_done = 1;
+    } else if (res <= st->tol2 * ff) {
+      st->solve_done = 1;
+    }
+  }
+}
+
+
+}  // namespace fdd

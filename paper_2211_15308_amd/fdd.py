@@ -38,7 +38,9 @@ EXPORTED = [
     "fdd_bind_workspace", "fdd_build_rational_pc", "fdd_ratpc_from_table", "fdd_ratpc_query",
     "fdd_interior_solve", "fdd_schur_apply", "fdd_precond_apply", "fdd_apply_operator",
     "fdd_solve", "fdd_set_kernel_timer", "fdd_get_kernel_timer", "fdd_destroy_problem",
-    "fdd_destroy_ratpc", "fdd_last_error", "fdd_version",
+    "fdd_destroy_ratpc", "fdd_last_error", "fdd_version", "fdd_batch_create",
+    "fdd_batch_workspace_bytes", "fdd_batch_bind_workspace", "fdd_solve_batched",
+    "fdd_batch_destroy",
 ]
 FDD_KT_NONE, FDD_KT_DOWN0, FDD_KT_UP0, FDD_KT_COARSE = 0, 1, 2, 3
 
@@ -109,6 +111,14 @@ def load():
     lib.fdd_destroy_problem.restype = None
     lib.fdd_destroy_ratpc.argtypes = [P]
     lib.fdd_destroy_ratpc.restype = None
+    lib.fdd_batch_create.argtypes = [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                     ctypes.POINTER(P)]
+    lib.fdd_batch_workspace_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.fdd_batch_bind_workspace.argtypes = [P, V, ctypes.c_size_t, V]
+    lib.fdd_solve_batched.argtypes = [P, ctypes.POINTER(V), ctypes.POINTER(V), ctypes.POINTER(FddOpts), V,
+                                      ctypes.POINTER(FddStats)]
+    lib.fdd_batch_destroy.argtypes = [P]
+    lib.fdd_batch_destroy.restype = None
     lib.fdd_last_error.restype = ctypes.c_char_p
     lib.fdd_version.restype = ctypes.c_char_p
     _lib = lib
@@ -262,6 +272,56 @@ class Problem:
             self.h = None
 
 
+class Batch:
+    """A batch of set-up problems solved together (fdd_batch_create / fdd_solve_batched).
+
+    problems: Problem objects with workspaces bound; P, H: their RationalTable pairs.  The batch
+    keeps references to all of them.
+    """
+
+    def __init__(self, problems, P, H, stream=None):
+        lib = load()
+        n = len(problems)
+        if not (n == len(P) == len(H)) or n == 0:
+            raise ValueError("problems, P and H must be non-empty and of equal length")
+        self.problems, self.P, self.H = list(problems), list(P), list(H)
+        arr = lambda hs: (ctypes.c_void_p * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in hs])
+        h = ctypes.c_void_p()
+        _check(lib.fdd_batch_create(n, arr([p.h for p in problems]), arr([t.h for t in P]),
+                                    arr([t.h for t in H]), ctypes.byref(h)))
+        self.h = h
+        self.count = n
+        import torch
+        nb = ctypes.c_size_t()
+        _check(lib.fdd_batch_workspace_bytes(h, ctypes.byref(nb)))
+        ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=f"cuda:{problems[0].device}")
+        ptr = ws.data_ptr()
+        off = (-ptr) % 256
+        _check(lib.fdd_batch_bind_workspace(h, ctypes.c_void_p(ptr + off), ws.numel() - off, _stream(stream)))
+        self.workspace = ws
+
+    def solve(self, bs, xs, opts=None, stream=None, allow_not_converged=False):
+        """Solves every instance; returns the list of per-instance stats dicts."""
+        n = self.count
+        if len(bs) != n or len(xs) != n:
+            raise ValueError("one b and one x per instance")
+        for p, b, x in zip(self.problems, bs, xs):
+            if b.numel() != p.N or x.numel() != p.N:
+                raise ValueError("vector length does not match its problem")
+        ba = (ctypes.c_void_p * n)(*[_ptr(b).value for b in bs])
+        xa = (ctypes.c_void_p * n)(*[_ptr(x).value for x in xs])
+        st = (FddStats * n)()
+        rc = load().fdd_solve_batched(self.h, ba, xa, ctypes.byref(opts or opts_default()),
+                                      _stream(stream), st)
+        _check(rc, (FDD_OK, FDD_NOT_CONVERGED) if allow_not_converged else (FDD_OK,))
+        return [s.as_dict() for s in st]
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fdd_batch_destroy(self.h)
+            self.h = None
+
+
 # names of the C ABI calls
 def setup_mesh(n, K, mu, dim=2, device=0):
     return Problem(n, K, mu, dim, device)
@@ -281,3 +341,7 @@ def precond_apply(prob, P, r_G, z_G, stream=None):
 
 def solve(prob, P, H, b, x, opts=None, stream=None):
     return prob.solve(P, H, b, x, opts, stream)
+
+
+def solve_batched(batch, bs, xs, opts=None, stream=None):
+    return batch.solve(bs, xs, opts, stream)

@@ -1,0 +1,146 @@
+"""GPU parity of the batched solve (fdd_solve_batched) against the oracle and against fdd_solve.
+
+Instances follow the batched workload: n drawn from a grid of even sizes, log-uniform K and mu,
+b ~ N(0, 1) per instance (workloads.batch_instances).  Expected values come from the oracle's
+separable solver; the per-instance fdd_solve results are compared as a second check (same
+kernel arithmetic, so the two agree to rounding unless a PCG run was cut differently by the
+shared launch schedule).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import system
+
+torch = pytest.importorskip("torch")
+F = pytest.importorskip("paper_2211_15308_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def make_batch(cases, tol_p=1e-12, max_p=64, tol_h=1e-12):
+    probs, TP, TH, bs = [], [], [], []
+    for c in cases:
+        P = F.setup_mesh(c["n"], c["K"], c["mu"])
+        P.bind_workspace()
+        probs.append(P)
+        TP.append(P.build_rational_pc(F.FDD_RA_PRECOND, tol_p, max_p))
+        TH.append(P.build_rational_pc(F.FDD_RA_OPERATOR, tol_h))
+        bs.append(dev(workloads.rhs(2, c["n"], c["seed"])))
+    return F.Batch(probs, TP, TH), probs, TP, TH, bs
+
+
+SMALL_SIZES = [16, 24, 32, 48, 64, 80, 96, 112, 128]
+
+
+def test_ragged_batch_matches_oracle_and_single_solves():
+    cases = workloads.batch_instances(count=12, seed=7, sizes=SMALL_SIZES)
+    print("[batch small] n =", [c["n"] for c in cases], flush=True)
+    B, probs, TP, TH, bs = make_batch(cases)
+    opts = F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12)
+    xs = [torch.zeros_like(b) for b in bs]
+    stats = B.solve(bs, xs, opts)
+    identical = 0
+    for i, c in enumerate(cases):
+        xb = host(xs[i])
+        x_ref = system.solve_dst_2d(c["n"], c["K"], c["mu"], host(bs[i]))
+        err = rel(xb, x_ref)
+        xsgl = torch.zeros_like(bs[i])
+        st1 = probs[i].solve(TP[i], TH[i], bs[i], xsgl, opts)
+        xs1 = host(xsgl)
+        identical += int(np.array_equal(xb, xs1))
+        print(f"  {i}: n={c['n']} K={c['K']:.2e} mu={c['mu']:.2e} outer {stats[i]['outer_its']} "
+              f"(single {st1['outer_its']}) err {err:.2e} vs single {rel(xb, xs1):.2e}", flush=True)
+        assert stats[i]["status"] == F.FDD_OK
+        assert err <= 1e-8
+        assert rel(xb, xs1) <= 1e-9
+        assert abs(stats[i]["outer_its"] - st1["outer_its"]) <= 1
+        assert stats[i]["rel_precond_res"] <= 1e-10
+    print(f"  bit-identical to the single-instance solve: {identical} of {len(cases)}", flush=True)
+
+
+def test_batch_of_the_batched_workload_at_bench_settings():
+    # the batched workload's distributions (n in {64, 96, ..., 512}), preconditioner tables to
+    # 1e-8 with at most 20 poles, outer rtol 1e-8, inner rtol 1e-10
+    cases = workloads.batch_instances(count=24, seed=4)
+    print("[batch C4 sample] n =", [c["n"] for c in cases], flush=True)
+    B, probs, TP, TH, bs = make_batch(cases, tol_p=1e-8, max_p=20)
+    ms = [t.query()["m"] for t in TP]
+    assert all(1 <= m <= 20 for m in ms)
+    xs = [torch.zeros_like(b) for b in bs]
+    stats = B.solve(bs, xs)
+    stats = B.solve(bs, xs)  # second call: settled schedule, graph replays
+    worst = 0.0
+    for i, c in enumerate(cases):
+        x_ref = system.solve_dst_2d(c["n"], c["K"], c["mu"], host(bs[i]))
+        err = rel(host(xs[i]), x_ref)
+        worst = max(worst, err)
+        assert stats[i]["status"] == F.FDD_OK
+        assert stats[i]["outer_its"] <= 25
+        assert err <= 1e-6, (i, c, err)
+    print(f"  worst rel err {worst:.2e}; outer its {[s['outer_its'] for s in stats]}; "
+          f"{stats[0]['t_solve_ms']:.1f} ms", flush=True)
+
+
+def test_batched_graph_replay_matches_eager_launches():
+    cases = workloads.batch_instances(count=6, seed=11, sizes=[64, 96, 128, 160, 192, 256])
+    print("[batch graph]", flush=True)
+    B, probs, TP, TH, bs = make_batch(cases)
+    xs0 = [torch.zeros_like(b) for b in bs]
+    B.solve(bs, xs0, F.opts_default(use_graph=0))  # settles the schedule
+    runs = []
+    for use_graph in (0, 1, 1, 0, 1):
+        xs = [torch.zeros_like(b) for b in bs]
+        B.solve(bs, xs, F.opts_default(use_graph=use_graph))
+        runs.append([host(x) for x in xs])
+    for r in runs[1:]:
+        for a, b in zip(r, runs[0]):
+            assert np.array_equal(a, b)
+    for i, c in enumerate(cases):
+        x_ref = system.solve_dst_2d(c["n"], c["K"], c["mu"], host(bs[i]))
+        assert rel(runs[0][i], x_ref) <= 1e-6
+
+
+def test_batch_error_paths():
+    cases = workloads.batch_instances(count=3, seed=12, sizes=[16, 32, 48])
+    B, probs, TP, TH, bs = make_batch(cases)
+    xs = [torch.zeros_like(b) for b in bs]
+    # duplicate problem, table of another problem, empty batch
+    with pytest.raises(F.FddError) as e:
+        F.Batch([probs[0], probs[0]], [TP[0], TP[0]], [TH[0], TH[0]])
+    assert e.value.status == F.FDD_E_ARG
+    with pytest.raises(F.FddError) as e:
+        F.Batch([probs[0], probs[1]], [TP[1], TP[0]], [TH[0], TH[1]])
+    assert e.value.status == F.FDD_E_STATE
+    # FP64 interior solves are not offered in batched form
+    with pytest.raises(F.FddError) as e:
+        B.solve(bs, xs, F.opts_default(precision=F.FDD_FP64))
+    assert e.value.status == F.FDD_E_ARG
+    # iteration limit: every instance reports it, outputs hold the last iterate
+    st = B.solve(bs, xs, F.opts_default(outer_maxit=1, outer_rtol=1e-14), allow_not_converged=True)
+    assert all(s["status"] == F.FDD_NOT_CONVERGED and s["outer_its"] == 1 for s in st)
+    # a non-finite right-hand side in one instance
+    bad = bs[1].clone()
+    bad[3] = float("nan")
+    with pytest.raises(F.FddError) as e:
+        B.solve([bs[0], bad, bs[2]], xs)
+    assert e.value.status == F.FDD_E_NONFINITE
+    assert "instance 1" in str(e.value)
+    # the batch still works afterwards
+    st = B.solve(bs, xs, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12))
+    for i, c in enumerate(cases):
+        x_ref = system.solve_dst_2d(c["n"], c["K"], c["mu"], host(bs[i]))
+        assert rel(host(xs[i]), x_ref) <= 1e-8

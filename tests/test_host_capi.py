@@ -115,3 +115,17 @@ def test_table_of_another_problem_is_rejected(lib):
     P.workspace = None
     rc = lib.fdd_schur_apply(P.h, T.h, ctypes.c_void_p(256), ctypes.c_void_p(512), None, None)
     assert rc in (F.FDD_E_WORKSPACE, F.FDD_E_STATE)
+
+
+def test_batch_create_validates_without_device(lib):
+    P = F.setup_mesh(64, 1.0, 1.0)
+    T = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-8)
+    H = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-8)
+    h = ctypes.c_void_p()
+    arr = lambda *xs: (ctypes.c_void_p * len(xs))(*[x.value for x in xs])
+    # no workspace bound on the problem
+    rc = lib.fdd_batch_create(1, arr(P.h), arr(T.h), arr(H.h), ctypes.byref(h))
+    assert rc == F.FDD_E_WORKSPACE and not h.value
+    # empty batch
+    assert lib.fdd_batch_create(0, arr(P.h), arr(T.h), arr(H.h), ctypes.byref(h)) == F.FDD_E_ARG
+    assert lib.fdd_solve_batched(None, None, None, None, None, None) == F.FDD_E_ARG
