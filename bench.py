@@ -8,6 +8,12 @@ back-substitution.  Steps cycle through the (K, mu) grid K in {1, 1e-2, 1e-4} x
 mu in {1e-6, 1e-3, 1, 1e3}; b ~ N(0, 1) per case (seeded).  Set-up (mesh plan, rational
 tables, workspace) is outside the timed region; inputs are resident in HBM before timing.
 
+Beside the headline figure the same JSON line carries the batched form: "batched_1024", a batch
+of 32 instances at n = 1024 with K log-uniform in [1e-4, 1] and mu log-uniform in [1e-6, 1e2]
+(every instance one complete solve, all advancing together through shared launches), and "c4",
+256 instances with n uniform on {64, 96, ..., 512} and the same K, mu distributions
+(preconditioner tables to 1e-8 with at most 20 poles).  Both report instance solves/s.
+
 Prints one JSON line (rank 0, N = 1 only).
 """
 import argparse
@@ -36,6 +42,11 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="launch kernels eagerly (no hipGraph replay)")
     ap.add_argument("--pmc-mode", action="store_true",
                     help="a few solves and a 256 MiB device copy, for rocprofv3 counter runs")
+    ap.add_argument("--batched", choices=["all", "none", "1024", "c4"], default="all",
+                    help="which batched workloads to run beside the headline figure")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--only-batched", action="store_true",
+                    help="skip the headline single-problem run (for profiling the batched kernels)")
     return ap.parse_args()
 
 
@@ -91,6 +102,82 @@ def traffic_from_profile(root):
     return rec.get("traffic_bytes_per_launch")
 
 
+def setup_instances(F, cases, tol_p, max_p, tol_h, threads=8):
+    """Problems and rational tables of a batch (host work, run on a thread pool), workspaces bound."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(c):
+        P = F.setup_mesh(c["n"], c["K"], c["mu"])
+        TP = P.build_rational_pc(F.FDD_RA_PRECOND, tol_p, max_p)
+        TH = P.build_rational_pc(F.FDD_RA_OPERATOR, tol_h)
+        return P, TP, TH
+
+    with ThreadPoolExecutor(threads) as ex:
+        out = list(ex.map(one, cases))
+    for P, _, _ in out:
+        P.bind_workspace()
+    return out
+
+
+def run_batched(F, args, label, cases, tol_p, max_p):
+    """Instance solves/s of one batch; roofline of the batched finest-level down kernel."""
+    import numpy as np
+    import torch
+
+    import workloads
+    import paper_2211_15308_amd.fdd as FF
+    from oracle import system
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    inst = setup_instances(F, cases, tol_p, max_p, 1e-12)
+    setup_s = time.perf_counter() - t0
+    B = F.Batch([i[0] for i in inst], [i[1] for i in inst], [i[2] for i in inst])
+    bs = [torch.as_tensor(workloads.rhs(2, c["n"], c["seed"]), dtype=torch.float64, device=dev)
+          for c in cases]
+    xs = [torch.zeros_like(b) for b in bs]
+    opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, mg_nu=args.nu,
+                          use_graph=0 if args.eager else 1)
+    for _ in range(2):
+        B.solve(bs, xs, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        st = B.solve(bs, xs, opts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = len(cases) * args.batch_steps / el
+    # roofline pass: eager launches with an event pair on every batched down kernel
+    B.set_kernel_timer(FF.FDD_KT_DOWN0)
+    st_t = B.solve(bs, xs, opts)
+    nl, ms, nlong, lms, _ = B.kernel_timer()
+    B.set_kernel_timer(FF.FDD_KT_NONE)
+    alg = 0.0
+    for c, s_ in zip(cases, st_t):
+        ni = (c["n"] - 1) ** 2
+        its, runs = s_["inner_its_total"], s_["refine_steps"]
+        alg += ni * (DOWN0_BYTES_K * (its - runs) + DOWN0_BYTES_K0 * runs)
+    achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    errs = []
+    for i in range(min(3, len(cases))):
+        c = cases[i]
+        xr = system.solve_dst_2d(c["n"], c["K"], c["mu"], bs[i].cpu().numpy())
+        errs.append(float(np.linalg.norm(xs[i].cpu().numpy() - xr) / np.linalg.norm(xr)))
+    outer = [s_["outer_its"] for s_ in st]
+    return {
+        "label": label, "value": value, "unit": "instance solves/s", "instances": len(cases),
+        "dofs": int(sum(c["n"] * (c["n"] - 1) for c in cases)), "ms_per_batch": 1e3 * el / args.batch_steps,
+        "batches_timed": args.batch_steps, "setup_s": setup_s,
+        "outer_its_min_mean_max": [min(outer), float(np.mean(outer)), max(outer)],
+        "poles_P_min_max": [min(i[1].query()["m"] for i in inst), max(i[1].query()["m"] for i in inst)],
+        "rel_err_vs_oracle_first3": errs,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "kb_mg_down<1,true> (finest level of every instance, PCG update fused)",
+                     "launches": nl, "avg_launch_us": 1e3 * ms / max(nl, 1),
+                     "alg_bytes_per_batch_solve": alg},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -109,6 +196,16 @@ def main():
     opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, precision=prec,
                           mg_nu=args.nu, use_graph=0 if args.eager else 1)
     case_list = cases(args)
+    if args.only_batched:
+        res = {}
+        if args.batched in ("all", "1024"):
+            res["batched_1024"] = run_batched(F, args, "32 instances, n=1024",
+                                              workloads.batch_instances(count=32, seed=4, sizes=[1024]), 1e-12, 64)
+        if args.batched in ("all", "c4"):
+            res["c4"] = run_batched(F, args, "256 instances, n in {64,...,512}",
+                                    workloads.batch_instances(count=256, seed=4), 1e-8, 20)
+        print(json.dumps(res))
+        return
     if args.pmc_mode:
         # calibration copy of known size, then a short run of the benchmark workload
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -186,6 +283,13 @@ def main():
         P.solve(TP, TH, b, x, opts)
         xr = system.solve_dst_2d(args.n, K, mu, b.cpu().numpy())
         errs.append(float(np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)))
+    batched = {}
+    if args.batched in ("all", "1024"):
+        batched["batched_1024"] = run_batched(F, args, "32 instances, n=1024",
+                                              workloads.batch_instances(count=32, seed=4, sizes=[1024]), 1e-12, 64)
+    if args.batched in ("all", "c4"):
+        batched["c4"] = run_batched(F, args, "256 instances, n in {64,...,512}",
+                                    workloads.batch_instances(count=256, seed=4), 1e-8, 20)
     out = {
         "metric": "Schur-PCG solves/s, 2D 1024^2 P1 @1e-8 (plain)",
         "value": value,
@@ -209,6 +313,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args, case_list),
     }
+    out.update(batched)
     print(json.dumps(out))
 
 

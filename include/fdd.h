@@ -221,6 +221,12 @@ int fdd_set_kernel_timer(fdd_problem prob, int kind, double split_us);
  * were pending between two synchronizations.  Any pointer may be NULL.                        */
 int fdd_get_kernel_timer(fdd_problem prob, int64_t* launches, double* total_ms,
                          int64_t* long_launches, double* long_ms, int64_t* untimed);
+/* The same timer for the batched kernels of a batch (FDD_KT_DOWN0 / FDD_KT_UP0: the finest-level
+ * kernels over the tiles of all instances; FDD_KT_COARSE: the coarse-level kernel, one workgroup
+ * per instance).  While set, fdd_solve_batched launches eagerly.                              */
+int fdd_batch_set_kernel_timer(fdd_batch batch, int kind, double split_us);
+int fdd_batch_get_kernel_timer(fdd_batch batch, int64_t* launches, double* total_ms,
+                               int64_t* long_launches, double* long_ms, int64_t* untimed);
 
 void fdd_destroy_problem(fdd_problem prob);
 void fdd_destroy_ratpc(fdd_ratpc t);

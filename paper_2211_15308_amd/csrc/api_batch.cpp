@@ -60,6 +60,11 @@ struct fdd_batch_s {
   std::map<std::vector<int>, BGraph> graphs;
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // kernel timer (HIP events attached to every launch of one kernel kind)
+  EventHook hook;
+  long long timed_launches = 0, timed_long = 0;
+  double timed_ms = 0.0, timed_long_ms = 0.0;
+  double timer_split_ms = 0.008;
 };
 
 namespace {
@@ -132,6 +137,7 @@ BInst make_inst(const fdd_batch_s* B, int i, const double* b, double* x) {
 
 BatchCtx make_bctx(const fdd_batch_s* B, hipStream_t s, int nu, int skip_done) {
   BatchCtx c{};
+  c.hook = B->hook.kind != kTimeNone ? const_cast<EventHook*>(&B->hook) : nullptr;
   c.stream = s;
   c.inst = B->d_inst;
   for (int l = 0; l < kMaxLevels; ++l) c.lists.tiles[l] = B->d_tiles[l];
@@ -154,6 +160,17 @@ int read_states(fdd_batch_s* B, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(B->h_states, B->d_states, sizeof(DevState) * B->count,
                         hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  for (int i = 0; i < B->hook.used; ++i) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, B->hook.ev[2 * i], B->hook.ev[2 * i + 1]));
+    B->timed_ms += ms;
+    B->timed_launches += 1;
+    if (ms >= B->timer_split_ms) {
+      B->timed_long_ms += ms;
+      B->timed_long += 1;
+    }
+  }
+  B->hook.used = 0;
   return FDD_OK;
 }
 
@@ -381,6 +398,7 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
   HIPCHK(hipSetDevice(B->device));
   hipStream_t us = (hipStream_t)stream;
   hipStream_t s = us;
+  if (B->hook.kind != kTimeNone) o.use_graph = 0;  // timed launches carry their own events
   if (o.use_graph) {
     if (!B->gstream) {
       HIPCHK(hipStreamCreateWithFlags(&B->gstream, hipStreamNonBlocking));
@@ -491,8 +509,44 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
   return finish(code);
 }
 
+int fdd_batch_set_kernel_timer(fdd_batch B, int kind, double split_us) {
+  if (!B) return fail(FDD_E_ARG, "null batch");
+  if (!(split_us >= 0)) return fail(FDD_E_ARG, "split_us must be >= 0");
+  if (kind < FDD_KT_NONE || kind > FDD_KT_COARSE) return fail(FDD_E_ARG, "bad timer kind");
+  HIPCHK(hipSetDevice(B->device));
+  if (kind != FDD_KT_NONE && !B->hook.ev) {
+    const int cap = 4096;
+    B->hook.ev = new (std::nothrow) hipEvent_t[2 * cap];
+    if (!B->hook.ev) return fail(FDD_E_NOMEM, "out of host memory");
+    for (int i = 0; i < 2 * cap; ++i) HIPCHK(hipEventCreate(&B->hook.ev[i]));
+    B->hook.cap = cap;
+  }
+  B->timer_split_ms = split_us * 1e-3;
+  B->hook.kind = kind;
+  B->hook.used = 0;
+  B->hook.skipped = 0;
+  B->timed_launches = B->timed_long = 0;
+  B->timed_ms = B->timed_long_ms = 0.0;
+  return FDD_OK;
+}
+
+int fdd_batch_get_kernel_timer(fdd_batch B, int64_t* launches, double* total_ms,
+                               int64_t* long_launches, double* long_ms, int64_t* untimed) {
+  if (!B) return fail(FDD_E_ARG, "null batch");
+  if (launches) *launches = B->timed_launches;
+  if (total_ms) *total_ms = B->timed_ms;
+  if (long_launches) *long_launches = B->timed_long;
+  if (long_ms) *long_ms = B->timed_long_ms;
+  if (untimed) *untimed = B->hook.skipped;
+  return FDD_OK;
+}
+
 void fdd_batch_destroy(fdd_batch B) {
   if (!B) return;
+  if (B->hook.ev) {
+    for (int i = 0; i < 2 * B->hook.cap; ++i) (void)hipEventDestroy(B->hook.ev[i]);
+    delete[] B->hook.ev;
+  }
   for (auto& kv : B->graphs)
     if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
   if (B->gstream) (void)hipStreamDestroy(B->gstream);

@@ -47,6 +47,7 @@ struct DevState {
   double o_pq, o_alpha, o_beta;
   double t_res[2];   // true residual: ||b - A x||^2, ||b||^2
   double cg_alpha[2];  // step length of the inner PCG, by iteration parity
+  double cg_gam[2];    // r . z of the inner PCG, by iteration parity
   // counters / flags
   int inner_done;    // the running multigrid-PCG has converged (or broke down)
   int solve_done;    // the interior solve has met its tolerance
@@ -211,6 +212,7 @@ struct BLists {
 enum BRhs { kRhsB = 0, kRhsLiftP = 1, kRhsBack = 2 };
 
 struct BatchCtx {
+  EventHook* hook;                    // optional kernel timer
   hipStream_t stream;
   const BInst* inst;
   BLists lists;

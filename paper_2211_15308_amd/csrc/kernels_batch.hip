@@ -21,6 +21,15 @@ __device__ __forceinline__ int find_inst(const int* __restrict__ start, int nins
   return lo;
 }
 
+// XCD-aware order of the concatenated tile list: workgroup b runs on XCD b % 8, so tile
+// (b % 8) q + b / 8 (q = grid / 8) gives each XCD one contiguous stretch of the list (whole
+// instances, or neighbouring tile rows of one instance), keeping shared halos in one L2.
+__device__ __forceinline__ int xcd_linear() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int q = nb >> 3;
+  return (b < 8 * q) ? (b & 7) * q + (b >> 3) : b;
+}
+
 __device__ __forceinline__ bool inst_idle(const DevState* st, int skip_done) {
   return skip_done && st->outer_done;
 }
@@ -35,7 +44,7 @@ template <int NU, bool CG>
 __global__ __launch_bounds__(kBlock) void kb_mg_down(const BInst* __restrict__ I, BLists L,
                                                      int level, int k, int cur_r, int cur_p,
                                                      int check, int skip_done) {
-  const int b = blockIdx.x;
+  const int b = xcd_linear();
   const int* start = L.tiles[level];
   const int i = find_inst(start, L.ninst, b);
   const BInst& P = I[i];
@@ -62,7 +71,7 @@ template <int NU, bool CG>
 __global__ __launch_bounds__(kBlock) void kb_mg_up(const BInst* __restrict__ I, BLists L,
                                                    int level, int kn, int count, int cur_r,
                                                    int skip_done) {
-  const int b = blockIdx.x;
+  const int b = xcd_linear();
   const int* start = L.tiles[level];
   const int i = find_inst(start, L.ninst, b);
   const BInst& P = I[i];
@@ -113,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void kb_ir_residual(const BInst* __restrict
                                                          int first, int rhs, int ver, int S,
                                                          int cur_r, double tol2, double tau2,
                                                          int skip_done) {
-  const int b = blockIdx.x;
+  const int b = xcd_linear();
   const int* start = L.tiles[0];
   const int i = find_inst(start, L.ninst, b);
   const BInst& P = I[i];
@@ -227,8 +236,8 @@ static void b_tail(const BatchCtx& c, int check) {
     if (c.tiles_total[l] > 0)
       hipLaunchKernelGGL((kb_mg_down<NU, false>), dim3(c.tiles_total[l]), tb(), 0, c.stream,
                          c.inst, c.lists, l, 0, 0, 0, check, c.skip_done);
-  hipLaunchKernelGGL((kb_coarse<NU>), dim3(c.lists.ninst), dim3(kCoarseThreads), 0, c.stream,
-                     c.inst, check, c.skip_done);
+  launch_timed(c.hook, kTimeCoarse, kb_coarse<NU>, dim3(c.lists.ninst), dim3(kCoarseThreads),
+               c.stream, c.inst, check, c.skip_done);
   for (int l = c.max_tiled - 1; l >= 1; --l)
     if (c.tiles_total[l] > 0)
       hipLaunchKernelGGL((kb_mg_up<NU, false>), dim3(c.tiles_total[l]), tb(), 0, c.stream, c.inst,
@@ -244,11 +253,11 @@ static void b_step(const BatchCtx& c, int rhs, int ver, int its, int S, int& cur
   hipLaunchKernelGGL((kb_mg_up<NU, true>), dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst,
                      c.lists, 0, 0, 0, cur_r, c.skip_done);
   for (int k = 0; k < its; ++k) {
-    hipLaunchKernelGGL((kb_mg_down<NU, true>), dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst,
-                       c.lists, 0, k, cur_r, cur_p, 0, c.skip_done);
+    launch_timed(c.hook, kTimeDown0, kb_mg_down<NU, true>, dim3(c.tiles_total[0]), tb(), c.stream,
+                 c.inst, c.lists, 0, k, cur_r, cur_p, 0, c.skip_done);
     b_tail<NU>(c, 1);
-    hipLaunchKernelGGL((kb_mg_up<NU, true>), dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst,
-                       c.lists, 0, k + 1, 1, cur_r ^ 1, c.skip_done);
+    launch_timed(c.hook, kTimeUp0, kb_mg_up<NU, true>, dim3(c.tiles_total[0]), tb(), c.stream,
+                 c.inst, c.lists, 0, k + 1, 1, cur_r ^ 1, c.skip_done);
     cur_r ^= 1;
     cur_p ^= 1;
   }

@@ -95,44 +95,86 @@ __device__ __forceinline__ T prolong(const T* ec, int pc, int nc, int i, int j) 
   return T(0.5) * (gload(ec, pc, nc, I, J) + gload(ec, pc, nc, I + 1, J + 1));
 }
 
-// one red or black half-sweep over the window cells 1..W-2 that lie inside the domain
+// One red or black half-sweep over the window cells 1..W-2 that lie inside the domain.  The
+// cells of one colour are enumerated directly (W - 2 rows of (W - 2) / 2 cells each), so every
+// thread of the block updates a cell of the sweep's colour.
 template <typename T, int W>
 __device__ __forceinline__ void tile_halfsweep(T (*su)[W + 1], const T (*sf)[W + 1], int ib, int jb,
                                                int nf, bool red) {
-  for (int lj = 1 + threadIdx.y; lj < W - 1; lj += blockDim.y) {
+  constexpr int R = W - 2;  // even
+  constexpr int C = R / 2;
+  const int want = red ? 0 : 1;
+  for (int c = flat_tid(); c < R * C; c += kBlock) {
+    const int lj = 1 + c / C, m = c % C;
     const int j = jb + lj;
-    if (j < 1 || j > nf) continue;
-    for (int li = 1 + threadIdx.x; li < W - 1; li += blockDim.x) {
-      const int i = ib + li;
-      if (i < 1 || i > nf || is_red(i, j) != red) continue;
-      su[lj][li] = T(0.25) * (sf[lj][li] + su[lj][li - 1] + su[lj][li + 1] + su[lj - 1][li] +
-                              su[lj + 1][li]);
-    }
+    const int li = 1 + (((ib + 1 + j) & 1) != want) + 2 * m;
+    const int i = ib + li;
+    if (j < 1 || j > nf || i < 1 || i > nf) continue;
+    su[lj][li] = T(0.25) * (sf[lj][li] + su[lj][li - 1] + su[lj][li + 1] + su[lj - 1][li] +
+                            su[lj + 1][li]);
   }
   __syncthreads();
+}
+
+// Sums of two values over the block, broadcast to every thread (fixed order: deterministic).
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+  __shared__ double sh[2][kBlock / 64 + 1];
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+  }
+  const int t = flat_tid();
+  const int lane = t & 63, wid = t >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh[0][wid] = a;
+    sh[1][wid] = b;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      sa += sh[0][w];
+      sb += sh[1][w];
+    }
+    sh[0][kBlock / 64] = sa;
+    sh[1][kBlock / 64] = sb;
+  }
+  __syncthreads();
+  a = sh[0][kBlock / 64];
+  b = sh[1][kBlock / 64];
 }
 
 // --------------------------------------------------------------------------------------------
 // fused level kernels
 // --------------------------------------------------------------------------------------------
-// Thread layout of the tiled kernels: 32 x 8 threads; a window of W x W cells is covered by
-// RY x RX register slots per thread, cell (ty + 8 a, tx + 32 b).  All global loads of a window
-// are issued into registers before the first use, so a block waits for one memory latency.
+// The tiled kernels run 256 threads on a kTile x kTile tile plus a halo.  Window cells are
+// enumerated row-major over the flat thread index (cell t + 256 q), own cells likewise over the
+// tile (8 rows of 32 per pass), so loads are row-contiguous and no lane idles on a short row.
+// All global loads of a window are issued into registers before the first use, so a block waits
+// for one memory latency.
 
+// Register slots of a W x W window in the 32 x 8 layout (cell (ty + 8 a, tx + 32 b)).
 template <int W>
 struct Slots {
   static constexpr int RY = (W + 7) / 8;
   static constexpr int RX = (W + 31) / 32;
 };
 
+template <int W>
+struct Flat {
+  static constexpr int N = (W * W + kBlock - 1) / kBlock;  // window slots per thread
+};
+constexpr int kOwnSlots = kTile * kTile / kBlock;
+
 // Going down one level: u = S^nu(0; f) (red first), r = f - A u, f_c = P^T r.
 // CG = true (level 0, inner PCG iteration k, single-reduction form):
-//   gamma_k = r_k . z_k and delta_k = z_k . w_k come from the partials of the previous V-cycle;
-//   beta_k = gamma_k / gamma_{k-1}, alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1})
-//   (beta_0 = 0, alpha_0 = gamma_0 / delta_0).  On the window s_k = w_k + beta_k s_{k-1} and
-//   f = r_{k+1} = r_k - alpha_k s_k; on own points p_k = z_k + beta_k p_{k-1}, x += alpha_k p_k,
-//   and r_{k+1}, s_k, p_k are stored; ||r_{k+1}||^2 goes to red.rr.
-// check != 0 (first kernel after the level-0 down kernel): returns if the PCG has converged.
+//   gamma_k = r_k . z_k and delta_k = z_k . w_k come from the partials of the previous V-cycle
+//   (summed here in one pass); beta_k = gamma_k / gamma_{k-1}, alpha_k = gamma_k / (delta_k -
+//   beta_k gamma_k / alpha_{k-1}) (beta_0 = 0, alpha_0 = gamma_0 / delta_0), with gamma_{k-1}
+//   and alpha_{k-1} recorded by the previous iteration.  On the window s_k = w_k + beta_k s_{k-1}
+//   and f = r_{k+1} = r_k - alpha_k s_k; on own points p_k = z_k + beta_k p_{k-1},
+//   x += alpha_k p_k, and r_{k+1}, s_k, p_k are stored; ||r_{k+1}||^2 goes to red.rr.
 template <typename T, int NU, bool CG>
 __device__ __forceinline__ void d_mg_down(
     const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
@@ -142,40 +184,51 @@ __device__ __forceinline__ void d_mg_down(
     int tile, bool lead) {
   constexpr int H = 2 * NU + 1;
   constexpr int W = kTile + 2 * H;
-  constexpr int RY = Slots<W>::RY, RX = Slots<W>::RX;
+  constexpr int NW = Flat<W>::N;
+  constexpr int NO = CG ? kOwnSlots : 1;
   __shared__ T sf[W][W + 1];
   __shared__ T su[W][W + 1];
   const int i0 = tile_x * kTile, j0 = tile_y * kTile;
   const int ib = i0 + 1 - H, jb = j0 + 1 - H;  // global index of window cell (0, 0)
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  T fr[RY][RX], wr[RY][RX], sr[RY][RX], zr[RY][RX], pr[RY][RX], xr[RY][RX];
+  const int t = flat_tid();
+  T fr[NW], wr[NW], sr[NW];
+  T zr[NO], pr[NO], xr[NO];
 #pragma unroll
-  for (int a = 0; a < RY; ++a) {
+  for (int q = 0; q < NW; ++q) {
+    const int c = t + kBlock * q;
+    const int lj = c / W, li = c % W;
+    const int i = ib + li, j = jb + lj;
+    const bool in = c < W * W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+    const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+    fr[q] = in ? fin[o] : T(0);
+    if (CG) {
+      wr[q] = in ? w[o] : T(0);
+      sr[q] = (in && k > 0) ? sold[o] : T(0);
+    }
+  }
+  if (CG) {
 #pragma unroll
-    for (int b = 0; b < RX; ++b) {
-      const int lj = ty + 8 * a, li = tx + 32 * b;
-      const int i = ib + li, j = jb + lj;
-      const bool in = lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+    for (int q = 0; q < NO; ++q) {
+      const int c = t + kBlock * q;
+      const int i = i0 + 1 + (c % kTile), j = j0 + 1 + c / kTile;
+      const bool in = i <= nf && j <= nf;
       const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-      fr[a][b] = in ? fin[o] : T(0);
-      if (CG) {
-        const bool own = in && li >= H && li < H + kTile && lj >= H && lj < H + kTile;
-        wr[a][b] = in ? w[o] : T(0);
-        sr[a][b] = (in && k > 0) ? sold[o] : T(0);
-        zr[a][b] = own ? z[o] : T(0);
-        pr[a][b] = (own && k > 0) ? pold[o] : T(0);
-        xr[a][b] = (own && k > 0) ? x[o] : T(0);
-      }
+      zr[q] = in ? z[o] : T(0);
+      pr[q] = (in && k > 0) ? pold[o] : T(0);
+      xr[q] = (in && k > 0) ? x[o] : T(0);
     }
   }
   T alpha = T(0), beta = T(0);
   if (CG) {
-    const double gam = sum_partials(red.rz[k & 1], red.nb0);
-    const double del = sum_partials(red.zw[k & 1], red.nb0);
+    double gam = 0.0, del = 0.0;
+    for (int q = t; q < red.nb0; q += kBlock) {
+      gam += red.rz[k & 1][q];
+      del += red.zw[k & 1][q];
+    }
+    block_sum2(gam, del);
     double b = 0.0, den = del;
     if (k > 0) {
-      const double gam_prev = sum_partials(red.rz[(k - 1) & 1], red.nb0);
-      b = gam / gam_prev;
+      b = gam / st->cg_gam[(k - 1) & 1];
       den = del - b * gam / st->cg_alpha[(k - 1) & 1];
     }
     if (!(gam > 0.0) || !(den > 0.0) || !isfinite(den) || !isfinite(gam)) {
@@ -187,64 +240,81 @@ __device__ __forceinline__ void d_mg_down(
       return;
     }
     const double al = gam / den;
-    if (lead && thread0()) st->cg_alpha[k & 1] = al;
+    if (lead && thread0()) {
+      st->cg_alpha[k & 1] = al;
+      st->cg_gam[k & 1] = gam;
+    }
     alpha = (T)al;
     beta = (T)b;
   }
   double rr = 0.0;
 #pragma unroll
-  for (int a = 0; a < RY; ++a) {
-#pragma unroll
-    for (int b = 0; b < RX; ++b) {
-      const int lj = ty + 8 * a, li = tx + 32 * b;
-      if (lj >= W || li >= W) continue;
-      const int i = ib + li, j = jb + lj;
-      T f = fr[a][b];
-      if (CG) {
-        const T sv = wr[a][b] + beta * sr[a][b];
-        f = f - alpha * sv;
-        const bool own = li >= H && li < H + kTile && lj >= H && lj < H + kTile && i >= 1 &&
-                         i <= nf && j >= 1 && j <= nf;
-        if (own) {
-          const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-          const T pv = zr[a][b] + beta * pr[a][b];
-          rout[o] = f;
-          snew[o] = sv;
-          pnew[o] = pv;
-          x[o] = xr[a][b] + alpha * pv;
-          rr += (double)f * (double)f;
-        }
+  for (int q = 0; q < NW; ++q) {
+    const int c = t + kBlock * q;
+    if (c >= W * W) continue;
+    const int lj = c / W, li = c % W;
+    const int i = ib + li, j = jb + lj;
+    T f = fr[q];
+    if (CG) {
+      const T sv = wr[q] + beta * sr[q];
+      f = f - alpha * sv;
+      const bool own = li >= H && li < H + kTile && lj >= H && lj < H + kTile && i <= nf &&
+                       j <= nf;
+      if (own) {
+        const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+        rout[o] = f;
+        snew[o] = sv;
+        rr += (double)f * (double)f;
       }
-      sf[lj][li] = f;
-      // first red half-sweep from a zero iterate: u = f / 4 on red points, 0 on black points
-      su[lj][li] = is_red(i, j) ? T(0.25) * f : T(0);
+    }
+    sf[lj][li] = f;
+    // first red half-sweep from a zero iterate: u = f / 4 on red points, 0 on black points
+    su[lj][li] = is_red(i, j) ? T(0.25) * f : T(0);
+  }
+  if (CG) {
+#pragma unroll
+    for (int q = 0; q < NO; ++q) {
+      const int c = t + kBlock * q;
+      const int i = i0 + 1 + (c % kTile), j = j0 + 1 + c / kTile;
+      if (i > nf || j > nf) continue;
+      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+      const T pv = zr[q] + beta * pr[q];
+      pnew[o] = pv;
+      x[o] = xr[q] + alpha * pv;
     }
   }
   __syncthreads();
   for (int s = 1; s < 2 * NU; ++s) tile_halfsweep<T, W>(su, sf, ib, jb, nf, !(s & 1));
-  // residual, in place of f (each point reads its own f and the neighbours' u)
-  for (int lj = 1 + ty; lj < W - 1; lj += 8)
-    for (int li = 1 + tx; li < W - 1; li += 32)
-      sf[lj][li] = sf[lj][li] - (T(4) * su[lj][li] - su[lj][li - 1] - su[lj][li + 1] -
-                                 su[lj - 1][li] - su[lj + 1][li]);
+  // residual, in place of f, on the cells the restriction reads (window rows and columns
+  // H .. H + kTile); each reads its own f and the neighbours' u
+  constexpr int RW = kTile + 1;
+  for (int c = t; c < RW * RW; c += kBlock) {
+    const int lj = H + c / RW, li = H + c % RW;
+    sf[lj][li] = sf[lj][li] - (T(4) * su[lj][li] - su[lj][li - 1] - su[lj][li + 1] -
+                               su[lj - 1][li] - su[lj + 1][li]);
+  }
   __syncthreads();
-  // restriction to the coarse points whose fine index 2I lies in this tile
-  const int nc = (nf - 1) >> 1;
-  constexpr int TC = kTile / 2;
-  for (int bb = ty; bb < TC; bb += 8) {
-    const int J = (j0 >> 1) + 1 + bb;
-    const int I = (i0 >> 1) + 1 + tx;
-    if (J > nc || tx >= TC || I > nc) continue;
-    const int li = 2 * I - ib, lj = 2 * J - jb;
-    const T v = sf[lj][li] + T(0.5) * (sf[lj][li - 1] + sf[lj][li + 1] + sf[lj - 1][li] +
-                                       sf[lj + 1][li] + sf[lj - 1][li - 1] + sf[lj + 1][li + 1]);
-    fc[(size_t)(J - 1) * pc + (I - 1)] = v;
+  // restriction to the coarse points whose fine index 2I lies in this tile (one per thread)
+  {
+    const int nc = (nf - 1) >> 1;
+    constexpr int TC = kTile / 2;
+    static_assert(TC * TC == kBlock, "one coarse point per thread");
+    const int J = (j0 >> 1) + 1 + t / TC, I = (i0 >> 1) + 1 + t % TC;
+    if (J <= nc && I <= nc) {
+      const int li = 2 * I - ib, lj = 2 * J - jb;
+      const T v = sf[lj][li] + T(0.5) * (sf[lj][li - 1] + sf[lj][li + 1] + sf[lj - 1][li] +
+                                         sf[lj + 1][li] + sf[lj - 1][li - 1] + sf[lj + 1][li + 1]);
+      fc[(size_t)(J - 1) * pc + (I - 1)] = v;
+    }
   }
   // store the pre-smoothed iterate on own points
-  for (int bb = ty; bb < kTile; bb += 8) {
-    const int j = j0 + 1 + bb, i = i0 + 1 + tx;
+#pragma unroll
+  for (int q = 0; q < kOwnSlots; ++q) {
+    const int c = t + kBlock * q;
+    const int bi = c % kTile, bj = c / kTile;
+    const int i = i0 + 1 + bi, j = j0 + 1 + bj;
     if (j > nf || i > nf) continue;
-    uout[(size_t)(j - 1) * pitch + (i - 1)] = su[bb + H][tx + H];
+    uout[(size_t)(j - 1) * pitch + (i - 1)] = su[bj + H][bi + H];
   }
   if (CG) {
     const double tot = block_sum_all(rr);
@@ -264,9 +334,9 @@ __device__ __forceinline__ void d_mg_up(
     bool lead) {
   constexpr int H = 2 * NU + (CG ? 1 : 0);
   constexpr int W = kTile + 2 * H;
-  constexpr int RY = Slots<W>::RY, RX = Slots<W>::RX;
+  constexpr int NW = Flat<W>::N;
   constexpr int CW = W / 2 + 2;  // coarse patch edge
-  constexpr int CRY = Slots<CW>::RY, CRX = Slots<CW>::RX;
+  constexpr int NC = Flat<CW>::N;
   __shared__ T sf[W][W + 1];
   __shared__ T su[W][W + 1];
   __shared__ T sc[CW][CW + 1];
@@ -274,67 +344,62 @@ __device__ __forceinline__ void d_mg_up(
   const int ib = i0 + 1 - H, jb = j0 + 1 - H;
   const int Ib = ib >> 1, Jb = jb >> 1;  // floor (arithmetic shift)
   const int nc = (nf - 1) >> 1;
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  T fr[RY][RX], ur[RY][RX], cr[CRY][CRX];
+  const int t = flat_tid();
+  T fr[NW], ur[NW], cr[NC];
 #pragma unroll
-  for (int a = 0; a < RY; ++a) {
-#pragma unroll
-    for (int b = 0; b < RX; ++b) {
-      const int lj = ty + 8 * a, li = tx + 32 * b;
-      const int i = ib + li, j = jb + lj;
-      const bool in = lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
-      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-      fr[a][b] = in ? fin[o] : T(0);
-      ur[a][b] = in ? upre[o] : T(0);
-    }
+  for (int q = 0; q < NW; ++q) {
+    const int c = t + kBlock * q;
+    const int lj = c / W, li = c % W;
+    const int i = ib + li, j = jb + lj;
+    const bool in = c < W * W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+    const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+    fr[q] = in ? fin[o] : T(0);
+    ur[q] = in ? upre[o] : T(0);
   }
 #pragma unroll
-  for (int a = 0; a < CRY; ++a) {
-#pragma unroll
-    for (int b = 0; b < CRX; ++b) {
-      const int lj = ty + 8 * a, li = tx + 32 * b;
-      const int I = Ib + li, J = Jb + lj;
-      const bool in = lj < CW && li < CW && I >= 1 && I <= nc && J >= 1 && J <= nc;
-      cr[a][b] = in ? ec[(size_t)(J - 1) * pc + (I - 1)] : T(0);
-    }
+  for (int q = 0; q < NC; ++q) {
+    const int c = t + kBlock * q;
+    const int lj = c / CW, li = c % CW;
+    const int I = Ib + li, J = Jb + lj;
+    const bool in = c < CW * CW && I >= 1 && I <= nc && J >= 1 && J <= nc;
+    cr[q] = in ? ec[(size_t)(J - 1) * pc + (I - 1)] : T(0);
   }
 #pragma unroll
-  for (int a = 0; a < CRY; ++a)
-#pragma unroll
-    for (int b = 0; b < CRX; ++b) {
-      const int lj = ty + 8 * a, li = tx + 32 * b;
-      if (lj < CW && li < CW) sc[lj][li] = cr[a][b];
-    }
+  for (int q = 0; q < NC; ++q) {
+    const int c = t + kBlock * q;
+    if (c < CW * CW) sc[c / CW][c % CW] = cr[q];
+  }
   __syncthreads();
 #pragma unroll
-  for (int a = 0; a < RY; ++a) {
-#pragma unroll
-    for (int b = 0; b < RX; ++b) {
-      const int lj = ty + 8 * a, li = tx + 32 * b;
-      if (lj >= W || li >= W) continue;
-      const int i = ib + li, j = jb + lj;
-      T u = T(0);
-      if (i >= 1 && i <= nf && j >= 1 && j <= nf) {
-        // P1 interpolation of the coarse correction (nested diagonal-split meshes)
-        const int ci = (i >> 1) - Ib, cj = (j >> 1) - Jb;
-        T e;
-        if (!(i & 1) && !(j & 1)) e = sc[cj][ci];
-        else if ((i & 1) && !(j & 1)) e = T(0.5) * (sc[cj][ci] + sc[cj][ci + 1]);
-        else if (!(i & 1) && (j & 1)) e = T(0.5) * (sc[cj][ci] + sc[cj + 1][ci]);
-        else e = T(0.5) * (sc[cj][ci] + sc[cj + 1][ci + 1]);
-        u = ur[a][b] + e;
-      }
-      sf[lj][li] = fr[a][b];
-      su[lj][li] = u;
+  for (int q = 0; q < NW; ++q) {
+    const int c = t + kBlock * q;
+    if (c >= W * W) continue;
+    const int lj = c / W, li = c % W;
+    const int i = ib + li, j = jb + lj;
+    T u = T(0);
+    if (i >= 1 && i <= nf && j >= 1 && j <= nf) {
+      // P1 interpolation of the coarse correction (nested diagonal-split meshes)
+      const int ci = (i >> 1) - Ib, cj = (j >> 1) - Jb;
+      T e;
+      if (!(i & 1) && !(j & 1)) e = sc[cj][ci];
+      else if ((i & 1) && !(j & 1)) e = T(0.5) * (sc[cj][ci] + sc[cj][ci + 1]);
+      else if (!(i & 1) && (j & 1)) e = T(0.5) * (sc[cj][ci] + sc[cj + 1][ci]);
+      else e = T(0.5) * (sc[cj][ci] + sc[cj + 1][ci + 1]);
+      u = ur[q] + e;
     }
+    sf[lj][li] = fr[q];
+    su[lj][li] = u;
   }
   __syncthreads();
   for (int s = 0; s < 2 * NU; ++s) tile_halfsweep<T, W>(su, sf, ib, jb, nf, (s & 1));
   double rz = 0.0, zw = 0.0;
-  for (int bb = ty; bb < kTile; bb += 8) {
-    const int j = j0 + 1 + bb, i = i0 + 1 + tx;
+#pragma unroll
+  for (int q = 0; q < kOwnSlots; ++q) {
+    const int c = t + kBlock * q;
+    const int bi = c % kTile, bj = c / kTile;
+    const int i = i0 + 1 + bi, j = j0 + 1 + bj;
     if (j > nf || i > nf) continue;
-    const int lj = bb + H, li = tx + H;
+    const int lj = bj + H, li = bi + H;
     const T zv = su[lj][li];
     const size_t o = (size_t)(j - 1) * pitch + (i - 1);
     eout[o] = zv;
@@ -346,11 +411,10 @@ __device__ __forceinline__ void d_mg_up(
     }
   }
   if (CG) {
-    const double trz = block_sum_all(rz);
-    const double tzw = block_sum_all(zw);
+    block_sum2(rz, zw);
     if (thread0()) {
-      red.rz[kn & 1][tile] = trz;
-      red.zw[kn & 1][tile] = tzw;
+      red.rz[kn & 1][tile] = rz;
+      red.zw[kn & 1][tile] = zw;
       if (count_iteration && lead) {
         st->inner_its += 1;
         st->pcg_k += 1;

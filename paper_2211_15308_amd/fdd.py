@@ -40,7 +40,7 @@ EXPORTED = [
     "fdd_solve", "fdd_set_kernel_timer", "fdd_get_kernel_timer", "fdd_destroy_problem",
     "fdd_destroy_ratpc", "fdd_last_error", "fdd_version", "fdd_batch_create",
     "fdd_batch_workspace_bytes", "fdd_batch_bind_workspace", "fdd_solve_batched",
-    "fdd_batch_destroy",
+    "fdd_batch_destroy", "fdd_batch_set_kernel_timer", "fdd_batch_get_kernel_timer",
 ]
 FDD_KT_NONE, FDD_KT_DOWN0, FDD_KT_UP0, FDD_KT_COARSE = 0, 1, 2, 3
 
@@ -117,6 +117,10 @@ def load():
     lib.fdd_batch_bind_workspace.argtypes = [P, V, ctypes.c_size_t, V]
     lib.fdd_solve_batched.argtypes = [P, ctypes.POINTER(V), ctypes.POINTER(V), ctypes.POINTER(FddOpts), V,
                                       ctypes.POINTER(FddStats)]
+    lib.fdd_batch_set_kernel_timer.argtypes = [P, I, D]
+    lib.fdd_batch_get_kernel_timer.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D),
+                                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D),
+                                               ctypes.POINTER(ctypes.c_int64)]
     lib.fdd_batch_destroy.argtypes = [P]
     lib.fdd_batch_destroy.restype = None
     lib.fdd_last_error.restype = ctypes.c_char_p
@@ -315,6 +319,17 @@ class Batch:
                                       _stream(stream), st)
         _check(rc, (FDD_OK, FDD_NOT_CONVERGED) if allow_not_converged else (FDD_OK,))
         return [s.as_dict() for s in st]
+
+    def set_kernel_timer(self, kind, split_us=8.0):
+        _check(load().fdd_batch_set_kernel_timer(self.h, kind, split_us))
+
+    def kernel_timer(self):
+        """(launches, total_ms, long_launches, long_ms, untimed) of the kernel timer."""
+        n, ms, nl, lms, un = (ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(),
+                              ctypes.c_int64())
+        _check(load().fdd_batch_get_kernel_timer(self.h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(nl),
+                                                 ctypes.byref(lms), ctypes.byref(un)))
+        return n.value, ms.value, nl.value, lms.value, un.value
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
