@@ -91,15 +91,23 @@ def traffic_from_profile(root):
     """HBM bytes per launch from the committed PMC summary, if it matches the current kernel."""
     import hashlib
     path = os.path.join(root, "profiles", "down0_traffic.json")
-    src = os.path.join(root, "paper_2211_15308_amd", "csrc", "kernels_mg.hip")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_source_sha(root)
     except (OSError, ValueError):
         return None
-    if rec.get("kernels_mg_sha256") != sha:
+    if rec.get("kernel_sources_sha256") != sha:
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def kernel_source_sha(root):
+    """sha256 over the sources the multigrid kernels are compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels_mg.hip", "mg_device.h", "fdd_internal.h"):
+        h.update(open(os.path.join(root, "paper_2211_15308_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
 
 
 def setup_instances(F, cases, tol_p, max_p, tol_h, threads=8):

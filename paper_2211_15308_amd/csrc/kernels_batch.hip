@@ -11,14 +11,20 @@
 namespace fdd {
 
 // Largest i with start[i] <= b, for a non-decreasing prefix table start[0..ninst].
+// b is the same for the whole workgroup, and so is the result: the loaded values are made
+// wave-uniform so that the instance's descriptor is read with scalar loads.
 __device__ __forceinline__ int find_inst(const int* __restrict__ start, int ninst, int b) {
   int lo = 0, hi = ninst;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (start[mid] <= b) lo = mid;
+    if (__builtin_amdgcn_readfirstlane(start[mid]) <= b) lo = mid;
     else hi = mid;
   }
-  return lo;
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+__device__ __forceinline__ int first_tile(const int* __restrict__ start, int i) {
+  return __builtin_amdgcn_readfirstlane(start[i]);
 }
 
 // XCD-aware order of the concatenated tile list: workgroup b runs on XCD b % 8, so tile
@@ -27,7 +33,7 @@ __device__ __forceinline__ int find_inst(const int* __restrict__ start, int nins
 __device__ __forceinline__ int xcd_linear() {
   const int b = blockIdx.x, nb = gridDim.x;
   const int q = nb >> 3;
-  return (b < 8 * q) ? (b & 7) * q + (b >> 3) : b;
+  return __builtin_amdgcn_readfirstlane((b < 8 * q) ? (b & 7) * q + (b >> 3) : b);
 }
 
 __device__ __forceinline__ bool inst_idle(const DevState* st, int skip_done) {
@@ -50,20 +56,23 @@ __global__ __launch_bounds__(kBlock) void kb_mg_down(const BInst* __restrict__ I
   const BInst& P = I[i];
   DevState* st = P.st;
   if (inst_idle(st, skip_done) || stopped(st)) return;
-  const int t = b - start[i];
+  const int t = b - first_tile(start, i);
   const int tx = P.tiles_x[level];
   const int tile_x = t % tx, tile_y = t / tx;
   const bool lead = (t == 0);
-  if (check && level == 1 && pcg_converged(st, P.red, lead)) return;
+  const Reductions red = P.red;
+  if (check && level == 1 && pcg_converged(st, red, lead)) return;
   if (CG) {
-    d_mg_down<float, NU, true>(P.r[cur_r], P.u[0], P.f[1], P.nf[0], P.pitch[0], P.pitch[1], P.w,
-                               P.s[cur_p], P.s[cur_p ^ 1], P.z, P.p[cur_p], P.p[cur_p ^ 1], P.x,
-                               P.r[cur_r ^ 1], st, P.red, k, tile_x, tile_y, t, lead);
+    d_mg_down<float, NU, true>(P.r[cur_r], P.u[0], P.f[1], P.nf[0], P.pitch[0],
+                               P.pitch[1], P.w, P.s[cur_p], P.s[cur_p ^ 1],
+                               P.z, P.p[cur_p], P.p[cur_p ^ 1], P.x,
+                               P.r[cur_r ^ 1], st, red, k, tile_x, tile_y, t, lead);
   } else {
     const float* fin = level == 0 ? P.r[cur_r] : P.f[level];
-    d_mg_down<float, NU, false>(fin, P.u[level], P.f[level + 1], P.nf[level], P.pitch[level],
-                                P.pitch[level + 1], nullptr, nullptr, nullptr, nullptr, nullptr,
-                                nullptr, nullptr, nullptr, st, P.red, 0, tile_x, tile_y, t, lead);
+    d_mg_down<float, NU, false>(fin, P.u[level], P.f[level + 1], P.nf[level],
+                                P.pitch[level], P.pitch[level + 1], nullptr, nullptr, nullptr,
+                                nullptr, nullptr, nullptr, nullptr, nullptr, st, red, 0, tile_x,
+                                tile_y, t, lead);
   }
 }
 
@@ -77,17 +86,19 @@ __global__ __launch_bounds__(kBlock) void kb_mg_up(const BInst* __restrict__ I, 
   const BInst& P = I[i];
   DevState* st = P.st;
   if (inst_idle(st, skip_done) || stopped(st)) return;
-  const int t = b - start[i];
+  const int t = b - first_tile(start, i);
   const int tx = P.tiles_x[level];
   const int tile_x = t % tx, tile_y = t / tx;
   const bool lead = (t == 0);
+  const Reductions red = P.red;
   if (CG) {
-    d_mg_up<float, NU, true>(P.r[cur_r], P.u[0], P.e[1], P.z, P.w, P.nf[0], P.pitch[0],
-                             P.pitch[1], st, P.red, kn, count, tile_x, tile_y, t, lead);
+    d_mg_up<float, NU, true>(P.r[cur_r], P.u[0], P.e[1], P.z, P.w,
+                             P.nf[0], P.pitch[0], P.pitch[1], st, red, kn, count, tile_x, tile_y,
+                             t, lead);
   } else {
-    d_mg_up<float, NU, false>(P.f[level], P.u[level], P.e[level + 1], P.e[level], nullptr,
-                              P.nf[level], P.pitch[level], P.pitch[level + 1], st, P.red, 0, 0,
-                              tile_x, tile_y, t, lead);
+    d_mg_up<float, NU, false>(P.f[level], P.u[level], P.e[level + 1],
+                              P.e[level], nullptr, P.nf[level], P.pitch[level],
+                              P.pitch[level + 1], st, red, 0, 0, tile_x, tile_y, t, lead);
   }
 }
 
@@ -128,12 +139,13 @@ __global__ __launch_bounds__(kBlock) void kb_ir_residual(const BInst* __restrict
   const BInst& P = I[i];
   DevState* st = P.st;
   if (inst_idle(st, skip_done)) return;
-  const int t = b - start[i];
+  const int t = b - first_tile(start, i);
   const int tx = P.tiles_x[0];
-  const RhsDesc f = b_rhs(P, rhs, ver);
+  RhsDesc f = b_rhs(P, rhs, ver);
   d_ir_residual<float>(f, first ? nullptr : P.u64[S & 1], P.x,
-                       first ? P.u64[0] : P.u64[(S + 1) & 1], P.r[cur_r], nullptr, P.nf[0],
-                       P.pitch[0], first, tol2, tau2, 0, st, P.red, t % tx, t / tx, t, t == 0);
+                       first ? P.u64[0] : P.u64[(S + 1) & 1], P.r[cur_r], nullptr,
+                       P.nf[0], P.pitch[0], first, tol2, tau2, 0, st, P.red, t % tx, t / tx,
+                       t, t == 0);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_ir_finalize(const BInst* __restrict__ I,
@@ -153,7 +165,7 @@ __global__ __launch_bounds__(kIfaceThreads) void kb_iface_solve(const BInst* __r
   const int i = find_inst(start, L.ninst, b);
   const BInst& P = I[i];
   if (which == 0 && sel ? tail_idle(P.st, skip_done) : inst_idle(P.st, skip_done)) return;
-  const int k = b - start[i];
+  const int k = b - first_tile(start, i);
   const ShiftTable* tab = which ? P.tabH : P.tabP;
   const double* in = which ? P.pG[ver & 1] : (sel ? P.rG[(ver + 1) & 1] : P.rG[0]);
   double* out = (which ? P.scrH : P.scrP) + (size_t)k * P.ng;

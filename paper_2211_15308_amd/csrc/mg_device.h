@@ -12,6 +12,22 @@ namespace fdd {
 
 __device__ __forceinline__ bool is_red(int i, int j) { return ((i + j) & 1) == 0; }
 
+// Element o of a vector in global memory, addressed by a 32-bit byte offset (every vector here
+// is below 2^31 bytes).  The pointer is cast to the global address space, so the access is a
+// global (not flat) one with a wave-uniform base and one lane register, also where the pointer
+// was read from memory (the batched kernels' instance descriptors) rather than passed as a
+// kernel argument.
+template <typename T>
+using GlobalT = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p, unsigned o) {
+  return *(const GlobalT<T>*)((const GlobalT<char>*)p + o * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* p, unsigned o, T v) {
+  *(GlobalT<T>*)((GlobalT<char>*)p + o * (unsigned)sizeof(T)) = v;
+}
+
 __device__ __forceinline__ int flat_tid() { return threadIdx.y * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ int nthreads() { return blockDim.x * blockDim.y; }
 
@@ -37,7 +53,7 @@ __device__ __forceinline__ double block_sum_all(double v) {
 // Fixed-order sum of nb partials, identical in every block of equal size.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int nb) {
   double v = 0.0;
-  for (int k = flat_tid(); k < nb; k += nthreads()) v += p[k];
+  for (int k = flat_tid(); k < nb; k += nthreads()) v += ldg(p, (unsigned)k);
   return block_sum_all(v);
 }
 
@@ -199,11 +215,11 @@ __device__ __forceinline__ void d_mg_down(
     const int lj = c / W, li = c % W;
     const int i = ib + li, j = jb + lj;
     const bool in = c < W * W && i >= 1 && i <= nf && j >= 1 && j <= nf;
-    const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-    fr[q] = in ? fin[o] : T(0);
+    const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+    fr[q] = in ? ldg(fin, o) : T(0);
     if (CG) {
-      wr[q] = in ? w[o] : T(0);
-      sr[q] = (in && k > 0) ? sold[o] : T(0);
+      wr[q] = in ? ldg(w, o) : T(0);
+      sr[q] = (in && k > 0) ? ldg(sold, o) : T(0);
     }
   }
   if (CG) {
@@ -212,18 +228,21 @@ __device__ __forceinline__ void d_mg_down(
       const int c = t + kBlock * q;
       const int i = i0 + 1 + (c % kTile), j = j0 + 1 + c / kTile;
       const bool in = i <= nf && j <= nf;
-      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-      zr[q] = in ? z[o] : T(0);
-      pr[q] = (in && k > 0) ? pold[o] : T(0);
-      xr[q] = (in && k > 0) ? x[o] : T(0);
+      const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+      zr[q] = in ? ldg(z, o) : T(0);
+      pr[q] = (in && k > 0) ? ldg(pold, o) : T(0);
+      xr[q] = (in && k > 0) ? ldg((const T*)x, o) : T(0);
     }
   }
   T alpha = T(0), beta = T(0);
   if (CG) {
     double gam = 0.0, del = 0.0;
+    // (parity selects, not indexing: a runtime index into the struct would put it in scratch)
+    const double* rzp = (k & 1) ? red.rz[1] : red.rz[0];
+    const double* zwp = (k & 1) ? red.zw[1] : red.zw[0];
     for (int q = t; q < red.nb0; q += kBlock) {
-      gam += red.rz[k & 1][q];
-      del += red.zw[k & 1][q];
+      gam += ldg(rzp, (unsigned)q);
+      del += ldg(zwp, (unsigned)q);
     }
     block_sum2(gam, del);
     double b = 0.0, den = del;
@@ -261,9 +280,9 @@ __device__ __forceinline__ void d_mg_down(
       const bool own = li >= H && li < H + kTile && lj >= H && lj < H + kTile && i <= nf &&
                        j <= nf;
       if (own) {
-        const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-        rout[o] = f;
-        snew[o] = sv;
+        const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+        stg(rout, o, f);
+        stg(snew, o, sv);
         rr += (double)f * (double)f;
       }
     }
@@ -277,10 +296,10 @@ __device__ __forceinline__ void d_mg_down(
       const int c = t + kBlock * q;
       const int i = i0 + 1 + (c % kTile), j = j0 + 1 + c / kTile;
       if (i > nf || j > nf) continue;
-      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
+      const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
       const T pv = zr[q] + beta * pr[q];
-      pnew[o] = pv;
-      x[o] = xr[q] + alpha * pv;
+      stg(pnew, o, pv);
+      stg(x, o, xr[q] + alpha * pv);
     }
   }
   __syncthreads();
@@ -304,7 +323,7 @@ __device__ __forceinline__ void d_mg_down(
       const int li = 2 * I - ib, lj = 2 * J - jb;
       const T v = sf[lj][li] + T(0.5) * (sf[lj][li - 1] + sf[lj][li + 1] + sf[lj - 1][li] +
                                          sf[lj + 1][li] + sf[lj - 1][li - 1] + sf[lj + 1][li + 1]);
-      fc[(size_t)(J - 1) * pc + (I - 1)] = v;
+      stg(fc, (unsigned)((J - 1) * pc + (I - 1)), v);
     }
   }
   // store the pre-smoothed iterate on own points
@@ -314,7 +333,7 @@ __device__ __forceinline__ void d_mg_down(
     const int bi = c % kTile, bj = c / kTile;
     const int i = i0 + 1 + bi, j = j0 + 1 + bj;
     if (j > nf || i > nf) continue;
-    uout[(size_t)(j - 1) * pitch + (i - 1)] = su[bj + H][bi + H];
+    stg(uout, (unsigned)((j - 1) * pitch + (i - 1)), su[bj + H][bi + H]);
   }
   if (CG) {
     const double tot = block_sum_all(rr);
@@ -352,9 +371,9 @@ __device__ __forceinline__ void d_mg_up(
     const int lj = c / W, li = c % W;
     const int i = ib + li, j = jb + lj;
     const bool in = c < W * W && i >= 1 && i <= nf && j >= 1 && j <= nf;
-    const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-    fr[q] = in ? fin[o] : T(0);
-    ur[q] = in ? upre[o] : T(0);
+    const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+    fr[q] = in ? ldg(fin, o) : T(0);
+    ur[q] = in ? ldg(upre, o) : T(0);
   }
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
@@ -362,7 +381,7 @@ __device__ __forceinline__ void d_mg_up(
     const int lj = c / CW, li = c % CW;
     const int I = Ib + li, J = Jb + lj;
     const bool in = c < CW * CW && I >= 1 && I <= nc && J >= 1 && J <= nc;
-    cr[q] = in ? ec[(size_t)(J - 1) * pc + (I - 1)] : T(0);
+    cr[q] = in ? ldg(ec, (unsigned)((J - 1) * pc + (I - 1))) : T(0);
   }
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
@@ -401,11 +420,11 @@ __device__ __forceinline__ void d_mg_up(
     if (j > nf || i > nf) continue;
     const int lj = bj + H, li = bi + H;
     const T zv = su[lj][li];
-    const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-    eout[o] = zv;
+    const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+    stg(eout, o, zv);
     if (CG) {
       const T wv = T(4) * zv - su[lj][li - 1] - su[lj][li + 1] - su[lj - 1][li] - su[lj + 1][li];
-      wout[o] = wv;
+      stg(wout, o, wv);
       rz += (double)sf[lj][li] * (double)zv;
       zw += (double)zv * (double)wv;
     }
@@ -413,8 +432,8 @@ __device__ __forceinline__ void d_mg_up(
   if (CG) {
     block_sum2(rz, zw);
     if (thread0()) {
-      red.rz[kn & 1][tile] = rz;
-      red.zw[kn & 1][tile] = zw;
+      stg((kn & 1) ? red.rz[1] : red.rz[0], (unsigned)tile, rz);
+      stg((kn & 1) ? red.zw[1] : red.zw[0], (unsigned)tile, zw);
       if (count_iteration && lead) {
         st->inner_its += 1;
         st->pcg_k += 1;
@@ -474,33 +493,41 @@ __device__ __forceinline__ void d_coarse_vcycle(const T* __restrict__ fin, int p
   __shared__ T scinv[kCinvLds * kCinvLds];
   const int first = lv.first, last = lv.nlev - 1;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  T* uL[kMaxLevels];
-  T* fL[kMaxLevels];
-  int tot = 0;
-  for (int l = first; l <= last; ++l) {
-    const int pw = lv.nf[l] + 2;
-    uL[l] = buf + tot;
-    fL[l] = buf + tot + pw * pw;
-    tot += 2 * pw * pw;
+  // Level sizes and offsets into buf go to LDS (read with constant indices here), so that later
+  // accesses by level number neither index a private array nor lose the LDS address space.
+  __shared__ int s_nf[kMaxLevels];
+  __shared__ int s_off[kMaxLevels];
+  int tot = 0, nf0 = 0, nfl = 0;
+#pragma unroll
+  for (int l = 0; l < kMaxLevels; ++l) {
+    const int nfv = lv.nf[l];
+    if (threadIdx.x == 0) {
+      s_nf[l] = nfv;
+      s_off[l] = tot;
+    }
+    if (l == first) nf0 = nfv;
+    if (l == last) nfl = nfv;
+    if (l >= first && l <= last) tot += 2 * (nfv + 2) * (nfv + 2);
   }
+  auto UL = [&](int l) { return buf + s_off[l]; };
+  auto FL = [&](int l) { return buf + s_off[l] + (s_nf[l] + 2) * (s_nf[l] + 2); };
   // issue the loads of the first level's right-hand side and of a small inverse first
-  const int nf0 = lv.nf[first];
   T v[2][2];
 #pragma unroll
   for (int b = 0; b < 2; ++b)
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
-      v[b][a] = (i <= nf0 && j <= nf0) ? fin[(size_t)(j - 1) * pin + (i - 1)] : T(0);
+      v[b][a] = (i <= nf0 && j <= nf0) ? ldg(fin, (unsigned)((j - 1) * pin + (i - 1))) : T(0);
     }
-  const int npc = lv.nf[last] * lv.nf[last];
+  const int npc = nfl * nfl;
   if (npc <= kCinvLds) {
     constexpr int RC = kCinvLds * kCinvLds / kCoarseThreads;
     T cv[RC];
 #pragma unroll
     for (int t = 0; t < RC; ++t) {
       const int k = threadIdx.x + t * kCoarseThreads;
-      cv[t] = k < npc * npc ? cinv[k] : T(0);
+      cv[t] = k < npc * npc ? ldg(cinv, (unsigned)k) : T(0);
     }
 #pragma unroll
     for (int t = 0; t < RC; ++t) scinv[threadIdx.x + t * kCoarseThreads] = cv[t];
@@ -514,16 +541,16 @@ __device__ __forceinline__ void d_coarse_vcycle(const T* __restrict__ fin, int p
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
-        if (i <= nf0 && j <= nf0) fL[first][j * pw + i] = v[b][a];
+        if (i <= nf0 && j <= nf0) FL(first)[j * pw + i] = v[b][a];
       }
   }
   __syncthreads();
   // down: pre-smooth from zero (red first), restrict the residual
   for (int l = first; l < last; ++l) {
-    const int nf = lv.nf[l], nc = lv.nf[l + 1];
+    const int nf = s_nf[l], nc = s_nf[l + 1];
     const int pw = nf + 2, pcw = nc + 2;
-    T* u = uL[l];
-    const T* f = fL[l];
+    T* u = UL(l);
+    const T* f = FL(l);
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -546,7 +573,7 @@ __device__ __forceinline__ void d_coarse_vcycle(const T* __restrict__ fin, int p
           const T r = f[o] - (T(4) * u[o] - u[o - 1] - u[o + 1] - u[o - pw] - u[o + pw]);
           acc += (t == 0 ? T(1) : T(0.5)) * r;
         }
-        fL[l + 1][J * pcw + I] = acc;
+        FL(l + 1)[J * pcw + I] = acc;
       }
     }
     __syncthreads();
@@ -554,10 +581,10 @@ __device__ __forceinline__ void d_coarse_vcycle(const T* __restrict__ fin, int p
   // coarsest: exact solve with the dense inverse; the right-hand side is first packed densely
   // (into the zero border-free tail of the buffer) so the product runs without index arithmetic
   {
-    const int nf = lv.nf[last], pw = nf + 2;
+    const int nf = nfl, pw = nf + 2;
     const int np = nf * nf;
-    T* u = uL[last];
-    const T* f = fL[last];
+    T* u = UL(last);
+    const T* f = FL(last);
     T* fpk = buf + tot;  // room after the last level: np <= 256 cells
     for (int k = threadIdx.x; k < np; k += blockDim.x) fpk[k] = f[(k / nf + 1) * pw + (k % nf + 1)];
     __syncthreads();
@@ -568,7 +595,7 @@ __device__ __forceinline__ void d_coarse_vcycle(const T* __restrict__ fin, int p
         for (int m = 0; m < np; ++m) acc += scinv[k * np + m] * fpk[m];
       } else {
 #pragma unroll 8
-        for (int m = 0; m < np; ++m) acc += cinv[(size_t)k * np + m] * fpk[m];
+        for (int m = 0; m < np; ++m) acc += ldg(cinv, (unsigned)(k * np + m)) * fpk[m];
       }
       u[(k / nf + 1) * pw + (k % nf + 1)] = acc;
     }
@@ -576,9 +603,9 @@ __device__ __forceinline__ void d_coarse_vcycle(const T* __restrict__ fin, int p
   }
   // up: prolongate and correct, post-smooth (black first)
   for (int l = last - 1; l >= first; --l) {
-    const int nf = lv.nf[l], pw = nf + 2, pcw = lv.nf[l + 1] + 2;
-    T* u = uL[l];
-    const T* ec = uL[l + 1];
+    const int nf = s_nf[l], pw = nf + 2, pcw = s_nf[l + 1] + 2;
+    T* u = UL(l);
+    const T* ec = UL(l + 1);
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -594,7 +621,7 @@ __device__ __forceinline__ void d_coarse_vcycle(const T* __restrict__ fin, int p
         u[j * pw + i] += e;
       }
     __syncthreads();
-    for (int s = 0; s < 2 * NU; ++s) lds_halfsweep(u, fL[l], nf, (s & 1));
+    for (int s = 0; s < 2 * NU; ++s) lds_halfsweep(u, FL(l), nf, (s & 1));
   }
   {
     const int pw = nf0 + 2;
@@ -603,7 +630,7 @@ __device__ __forceinline__ void d_coarse_vcycle(const T* __restrict__ fin, int p
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
-        if (i <= nf0 && j <= nf0) eout[(size_t)(j - 1) * pin + (i - 1)] = uL[first][j * pw + i];
+        if (i <= nf0 && j <= nf0) stg(eout, (unsigned)((j - 1) * pin + (i - 1)), UL(first)[j * pw + i]);
       }
   }
 }
@@ -614,8 +641,8 @@ __device__ __forceinline__ void d_coarse_vcycle(const T* __restrict__ fin, int p
 
 __device__ __forceinline__ double rhs_at(const RhsDesc& f, int nf, int i, int j) {
   double v = 0.0;
-  if (f.b) v = f.sb * f.b[(size_t)(j - 1) * nf + (i - 1)];
-  if (f.g && j == nf) v += f.sg * f.g[i - 1];
+  if (f.b) v = f.sb * ldg(f.b, (unsigned)((j - 1) * nf + (i - 1)));
+  if (f.g && j == nf) v += f.sg * ldg(f.g, (unsigned)(i - 1));
   return v;
 }
 
@@ -638,8 +665,8 @@ __device__ __forceinline__ void d_ir_residual(
       for (int a = threadIdx.x; a < kTile; a += blockDim.x) {
         const int i = i0 + 1 + a;
         if (i > nf) continue;
-        const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-        uout[o] = uin[o];
+        const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+        stg(uout, o, ldg(uin, o));
       }
     }
     return;
@@ -653,8 +680,8 @@ __device__ __forceinline__ void d_ir_residual(
       const int lj = threadIdx.y + 8 * a, li = threadIdx.x + 32 * b;
       const int i = i0 + li, j = j0 + lj;
       const bool in = !first && lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
-      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-      ur[a][b] = in ? uin[o] + (double)e[o] : 0.0;
+      const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+      ur[a][b] = in ? ldg(uin, o) + (double)ldg(e, o) : 0.0;
     }
   }
 #pragma unroll
@@ -676,10 +703,10 @@ __device__ __forceinline__ void d_ir_residual(
       const double u = su[lj][li];
       const double r = rhs_at(f, nf, i, j) - (4.0 * u - su[lj][li - 1] - su[lj][li + 1] -
                                               su[lj - 1][li] - su[lj + 1][li]);
-      const size_t o = (size_t)(j - 1) * pitch + (i - 1);
-      uout[o] = u;
-      if (r32) r32[o] = (float)r;
-      if (r64) r64[o] = r;
+      const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+      stg(uout, o, u);
+      if (r32) stg(r32, o, (float)r);
+      if (r64) stg(r64, o, r);
       rr += r * r;
     }
   }

@@ -9,6 +9,11 @@ under profiles/.  Command line:
   python -m paper_2211_15308_amd.profile_tools csvstats <kernel_stats.csv>
   python -m paper_2211_15308_amd.profile_tools csvpmc <counter_collection.csv>
   python -m paper_2211_15308_amd.profile_tools csvtrace <kernel_trace.csv> <name> <split_us>
+  python -m paper_2211_15308_amd.profile_tools traffic <fetch.csv> <write.csv> <kernel> <out.json>
+
+`traffic` turns a FETCH_SIZE run and a WRITE_SIZE run of ``bench.py --pmc-mode`` (which also
+copies 256 MiB device-to-device once, as the calibration of known size) into HBM bytes per
+working launch of one kernel; bench.py reads the record while its sources are unchanged.
 """
 import csv
 import collections
@@ -91,6 +96,37 @@ def csv_trace_split(path, name, split_us):
     return durs, long
 
 
+def traffic_record(fetch_csv, write_csv, kernel, copy_bytes=256 << 20):
+    """HBM bytes per working dispatch of `kernel`, each counter scaled by the copy's reading."""
+    fet, wri = csv_pmc(fetch_csv), csv_pmc(write_csv)
+
+    def pick(table, name):
+        for k, (n, cn, vals) in table.items():
+            if k.split("(")[0].strip() == name:
+                return vals
+        raise KeyError(name)
+
+    def copy_reading(table):
+        best = 0.0
+        for k, (n, cn, vals) in table.items():
+            if "copyBuffer" in k or "elementwise" in k:
+                best = max(best, max(vals))
+        return best
+
+    def working(vals):
+        big = [v for v in vals if v > 0.1 * max(vals)]
+        return sum(big) / len(big)
+
+    cf, cw = copy_reading(fet), copy_reading(wri)
+    ff = copy_bytes / 1024.0 / cf
+    wf = copy_bytes / 1024.0 / cw
+    f_kib, w_kib = working(pick(fet, kernel)), working(pick(wri, kernel))
+    return {"kernel": kernel, "fetch_kib_per_working_dispatch": f_kib,
+            "write_kib_per_working_dispatch": w_kib, "copy_bytes": float(copy_bytes),
+            "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_factor": ff, "write_factor": wf,
+            "traffic_bytes_per_launch": 1024.0 * (f_kib * ff + w_kib * wf)}
+
+
 def main(argv):
     if argv[0] == "stats":
         st = kernel_stats(argv[1], argv[2] if len(argv) > 2 else None)
@@ -111,6 +147,22 @@ def main(argv):
         durs, long = csv_trace_split(argv[1], argv[2], float(argv[3]))
         print(f"{argv[2]}: dispatches {len(durs)} avg_us {sum(durs) / max(len(durs), 1):.2f}; "
               f">= {argv[3]} us: {len(long)} avg_us {sum(long) / max(len(long), 1):.2f}")
+    elif argv[0] == "traffic":
+        import json
+        import os
+        sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        import bench
+        rec = traffic_record(argv[1], argv[2], argv[3])
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        rec["kernel_sources_sha256"] = bench.kernel_source_sha(root)
+        rec["workload"] = "2D n=1024 finest level (1023^2 interior points), FP32"
+        rec["commands"] = [
+            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d /tmp/pmc_fetch -o pmc -- python3 bench.py --pmc-mode",
+            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d /tmp/pmc_write -o pmc -- python3 bench.py --pmc-mode",
+            "python3 -m paper_2211_15308_amd.profile_tools traffic /tmp/pmc_fetch/pmc_counter_collection.csv "
+            "/tmp/pmc_write/pmc_counter_collection.csv 'void fdd::k_mg_down<float, 1, true>' profiles/down0_traffic.json"]
+        json.dump(rec, open(argv[4], "w"), indent=1)
+        print(json.dumps(rec))
     elif argv[0] == "pmc":
         vals = pmc_per_dispatch(argv[1], argv[2], argv[3])
         nz = [v for v in vals if v > 0]
