@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--batched", choices=["all", "none", "1024", "c4"], default="all",
                     help="which batched workloads to run beside the headline figure")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched runs use --nu and the default per-step reduction instead of the autotuner")
     ap.add_argument("--only-batched", action="store_true",
                     help="skip the headline single-problem run (for profiling the batched kernels)")
     return ap.parse_args()
@@ -145,6 +147,10 @@ def run_batched(F, args, label, cases, tol_p, max_p):
     xs = [torch.zeros_like(b) for b in bs]
     opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, mg_nu=args.nu,
                           use_graph=0 if args.eager else 1)
+    tune = None
+    if not args.no_autotune:
+        from paper_2211_15308_amd import autotune
+        opts, tune = autotune.tune_batch(B, bs, xs, opts, reps=1)
     for _ in range(2):
         B.solve(bs, xs, opts)
     torch.cuda.synchronize()
@@ -175,6 +181,8 @@ def run_batched(F, args, label, cases, tol_p, max_p):
         "label": label, "value": value, "unit": "instance solves/s", "instances": len(cases),
         "dofs": int(sum(c["n"] * (c["n"] - 1) for c in cases)), "ms_per_batch": 1e3 * el / args.batch_steps,
         "batches_timed": args.batch_steps, "setup_s": setup_s,
+        "schedule": {"mg_nu": opts.mg_nu, "step_rtol": opts.step_rtol,
+                     "autotune_ms_per_batch": tune["ms_per_batch"] if tune else None},
         "outer_its_min_mean_max": [min(outer), float(np.mean(outer)), max(outer)],
         "poles_P_min_max": [min(i[1].query()["m"] for i in inst), max(i[1].query()["m"] for i in inst)],
         "rel_err_vs_oracle_first3": errs,

@@ -81,7 +81,8 @@ typedef struct {
   int inner_maxit;     /* limit on multigrid-PCG iterations per interior solve                 */
   int precision;       /* FDD_MIXED (FP32 multigrid-PCG inside FP64 refinement) or FDD_FP64     */
   int mg_nu;           /* red-black Gauss-Seidel sweep pairs before and after coarse correction */
-  int inner_chunk;     /* FP32 PCG iterations per refinement step (mixed precision)            */
+  double step_rtol;    /* mixed precision: each FP32 multigrid-PCG run (one refinement step)
+                          reduces its residual by this factor (default 1e-5; 1e-7 .. 1e-2)    */
   int check_true_residual; /* nonzero: fdd_solve computes ||b - A x|| / ||b|| at the end       */
   void* warmstart;     /* reserved for the learned initial guess; must be NULL                 */
   int use_graph;       /* 1 (default): fdd_solve replays each outer iteration from a captured

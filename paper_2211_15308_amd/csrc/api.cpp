@@ -186,11 +186,17 @@ ShiftTable make_table(const fdd_ratpc_s* t) {
 bool opts_ok(const fdd_opts* o) {
   return o && o->outer_rtol > 0 && o->inner_rtol > 0 && o->outer_maxit > 0 &&
          o->inner_maxit > 0 && (o->precision == FDD_MIXED || o->precision == FDD_FP64) &&
-         (o->mg_nu == 1 || o->mg_nu == 2) && o->inner_chunk > 0 && o->warmstart == nullptr &&
+         (o->mg_nu == 1 || o->mg_nu == 2) && o->step_rtol >= 1e-7 && o->step_rtol <= 1e-2 &&
+         o->warmstart == nullptr &&
          (o->use_graph == 0 || o->use_graph == 1);
 }
 
-constexpr double kTau32 = 1e-5;  // FP32 PCG relative reduction per refinement step
+double step_tau(const fdd_opts& o) { return o.step_rtol; }
+
+// Selects the problem's schedule for these options.
+void use_schedule(fdd_problem_s* P, const fdd_opts& o) {
+  P->sc = &P->scheds[std::make_pair(o.mg_nu, o.precision == FDD_FP64 ? 0.0 : o.step_rtol)];
+}
 
 // Host-side record of an interior solve in flight: which buffers hold what.  Buffer parities
 // follow the enqueued schedule (kernels of a converged solve copy instead of skipping), so the
@@ -214,7 +220,7 @@ void enqueue_inner_start(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, co
   t.S = t.k = 0;
   if (!t.fp64) {
     launch_ir_residual(c, t.f, nullptr, nullptr, nullptr, P->u64[0], P->s32.r[t.cur_r], nullptr, 1,
-                       tol2, kTau32 * kTau32, 0);
+                       tol2, step_tau(o) * step_tau(o), 0);
   } else {
     launch_ir_residual(c, t.f, nullptr, nullptr, nullptr, P->u64[0], nullptr, P->s64.r[t.cur_r], 1,
                        tol2, tol2, 1);
@@ -229,7 +235,7 @@ void enqueue_inner_more(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, int
     auto& S = P->s32;
     for (int st = 0; st < steps; ++st) {
       launch_pcg_init<float>(c, S.mg, S.r[t.cur_r], S.z, S.w);
-      const int n_its = its >= 0 ? its : (t.S < 8 ? P->sched_step_its[t.S] : P->sched_its);
+      const int n_its = its >= 0 ? its : (t.S < 8 ? P->sc->step_its[t.S] : P->sc->its);
       for (int k = 0; k < n_its; ++k) {
         launch_pcg_iteration<float>(c, S.mg, k, S.x, S.r[t.cur_r], S.r[t.cur_r ^ 1], S.z, S.w,
                                     S.p[t.cur_p], S.p[t.cur_p ^ 1], S.s[t.cur_p],
@@ -292,12 +298,12 @@ int inner_finish(fdd_problem_s* P, hipStream_t s, InnerTrack& t, const fdd_opts&
       // the schedule only grows, so replays converge without top-ups once it has settled
       if (!t.fp64) {
         // one iteration of slack so that runs end on their own criterion, not on the schedule
-        P->sched_steps = std::max(P->sched_steps, std::max(h.refine_steps, 1));
-        P->sched_its = std::max(P->sched_its, h.run_its_max + 1);
+        P->sc->steps = std::max(P->sc->steps, std::max(h.refine_steps, 1));
+        P->sc->its = std::max(P->sc->its, h.run_its_max + 1);
         for (int q = 0; q < std::min(h.refine_steps, 8); ++q)
-          P->sched_step_its[q] = std::max(P->sched_step_its[q], h.run_len[q] + 1);
+          P->sc->step_its[q] = std::max(P->sc->step_its[q], h.run_len[q] + 1);
       } else {
-        P->sched_its64 = std::max(P->sched_its64, std::max(h.inner_its, 1));
+        P->sc->its64 = std::max(P->sc->its64, std::max(h.inner_its, 1));
       }
       return FDD_OK;
     }
@@ -306,8 +312,8 @@ int inner_finish(fdd_problem_s* P, hipStream_t s, InnerTrack& t, const fdd_opts&
       return fail(FDD_NOT_CONVERGED, "interior solve: %d iterations, residual %.3e of %.3e",
                   h.inner_its, std::sqrt(h.res2), std::sqrt(h.ff));
     }
-    if (!t.fp64) enqueue_inner_more(P, c, t, 1, std::max(P->sched_its, 30));
-    else enqueue_inner_more(P, c, t, 0, std::max(P->sched_its64 / 2, 2));
+    if (!t.fp64) enqueue_inner_more(P, c, t, 1, std::max(P->sc->its, 30));
+    else enqueue_inner_more(P, c, t, 0, std::max(P->sc->its64 / 2, 2));
     int rc = read_state(P, s);
     if (rc) return rc;
   }
@@ -322,19 +328,19 @@ int interior_solve(fdd_problem_s* P, hipStream_t s, const RhsDesc& f, const fdd_
   t.fp64 = fp64;
   t.f = f;
   enqueue_inner_start(P, c, t, o);
-  if (!P->calibrated) {
+  if (!P->sc->calibrated) {
     // the first solve of a problem measures the schedule: long PCG runs, one step at a time
     if (!fp64) enqueue_inner_more(P, c, t, 1, 30);
     else enqueue_inner_more(P, c, t, 0, 60);
   } else if (!fp64) {
-    enqueue_inner_more(P, c, t, P->sched_steps, -1);
+    enqueue_inner_more(P, c, t, P->sc->steps, -1);
   } else {
-    enqueue_inner_more(P, c, t, 0, P->sched_its64);
+    enqueue_inner_more(P, c, t, 0, P->sc->its64);
   }
   int rc = read_state(P, s);
   if (rc) return rc;
   rc = inner_finish(P, s, t, o, res);
-  if (rc == FDD_OK) P->calibrated = true;
+  if (rc == FDD_OK) P->sc->calibrated = true;
   return rc;
 }
 
@@ -365,7 +371,7 @@ void fdd_opts_default(fdd_opts* o) {
   o->inner_maxit = 400;
   o->precision = FDD_MIXED;
   o->mg_nu = 1;
-  o->inner_chunk = 6;
+  o->step_rtol = 1e-5;
   o->check_true_residual = 0;
   o->warmstart = nullptr;
   o->use_graph = 1;
@@ -551,6 +557,7 @@ int fdd_interior_solve(fdd_problem P, const double* f, double* u, const fdd_opts
   if (opts) o = *opts;
   else fdd_opts_default(&o);
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
+  use_schedule(P, o);
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
   InnerTrack t;
@@ -587,6 +594,7 @@ int fdd_schur_apply(fdd_problem P, fdd_ratpc H, const double* x, double* y, cons
   if (opts) o = *opts;
   else fdd_opts_default(&o);
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
+  use_schedule(P, o);
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
   InnerTrack t;
@@ -642,8 +650,8 @@ void enqueue_outer_iteration(fdd_problem_s* P, hipStream_t s, const ShiftTable& 
   LaunchCtx c = make_ctx(P, s, o.mg_nu, t.fp64);
   t.f = RhsDesc{nullptr, 0.0, P->pG[a], 1.0};
   enqueue_inner_start(P, c, t, o);
-  if (!t.fp64) enqueue_inner_more(P, c, t, P->sched_steps, -1);
-  else enqueue_inner_more(P, c, t, 0, P->sched_its64);
+  if (!t.fp64) enqueue_inner_more(P, c, t, P->sc->steps, -1);
+  else enqueue_inner_more(P, c, t, 0, P->sc->its64);
   launch_iface_batch(s, (int)P->NG, P->h, tabH, kIfaceOperator, P->pG[a], P->Hp, P->scratchH,
                      P->st, nullptr, nullptr, 0, 0);
   enqueue_outer_tail(P, s, tabP, inner_u(P, t), v);
@@ -652,13 +660,10 @@ void enqueue_outer_iteration(fdd_problem_s* P, hipStream_t s, const ShiftTable& 
 // Replays (capturing first if needed) the graph of outer iteration v for the current schedule.
 int launch_outer_graph(fdd_problem_s* P, hipStream_t s, const ShiftTable& tabP,
                        const ShiftTable& tabH, const fdd_opts& o, int v, InnerTrack& t) {
-  int sched_code = P->sched_its64;
-  if (!t.fp64) {
-    sched_code = P->sched_steps;
-    for (int q = 0; q < 8; ++q) sched_code = sched_code * 37 + P->sched_step_its[q];
-  }
-  const auto key = std::make_tuple(v & 1, t.fp64 ? 0 : P->sched_steps, sched_code, (int)t.fp64,
-                                   o.mg_nu);
+  // everything the captured launch sequence depends on
+  std::vector<int> key = {v & 1, (int)t.fp64, o.mg_nu, P->sc->steps, P->sc->its, P->sc->its64,
+                          (int)std::lround(std::log10(o.step_rtol) * 16.0)};
+  key.insert(key.end(), P->sc->step_its, P->sc->step_its + 8);
   auto it = P->graphs.find(key);
   if (it == P->graphs.end()) {
     hipGraph_t g = nullptr;
@@ -702,6 +707,7 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   if (opts) o = *opts;
   else fdd_opts_default(&o);
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
+  use_schedule(P, o);
   HIPCHK(hipSetDevice(P->device));
   hipStream_t us = (hipStream_t)stream;
   hipStream_t s = us;

@@ -17,8 +17,6 @@ using namespace fdd;
 
 namespace {
 
-constexpr double kTau32b = 1e-5;  // FP32 PCG relative reduction per refinement step
-
 struct BGraph {
   hipGraphExec_t exec = nullptr;
   int cur_r = 0, cur_p = 0, S = 0;
@@ -53,10 +51,9 @@ struct fdd_batch_s {
   BInst* h_inst = nullptr;      // staging of the descriptors
   DevState* h_states = nullptr;
   std::vector<BInst> uploaded;  // descriptors as last uploaded
-  // shared enqueue schedule (refinement steps, PCG iterations per step); only grows
-  int sched_steps = 1, sched_its = 2;
-  int step_its[8] = {2, 2, 2, 2, 2, 2, 2, 2};
-  bool calibrated = false;
+  // shared enqueue schedule per (smoother sweeps, per-step reduction); only grows
+  std::map<std::pair<int, double>, Schedule> scheds;
+  Schedule* sc = nullptr;
   std::map<std::vector<int>, BGraph> graphs;
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -176,14 +173,14 @@ int read_states(fdd_batch_s* B, hipStream_t s) {
 
 void enqueue_start(const BatchCtx& c, BTrack& t, int rhs, int ver, const fdd_opts& o) {
   t = BTrack{};
-  launch_b_inner_start(c, rhs, ver, o.inner_rtol * o.inner_rtol, kTau32b * kTau32b);
+  launch_b_inner_start(c, rhs, ver, o.inner_rtol * o.inner_rtol, step_tau(o) * step_tau(o));
 }
 
 // `steps` refinement steps; its < 0 takes the per-step schedule.
 void enqueue_steps(const fdd_batch_s* B, const BatchCtx& c, BTrack& t, int rhs, int ver,
                    int steps, int its) {
   for (int q = 0; q < steps; ++q) {
-    const int n_its = its >= 0 ? its : (t.S < 8 ? B->step_its[t.S] : B->sched_its);
+    const int n_its = its >= 0 ? its : (t.S < 8 ? B->sc->step_its[t.S] : B->sc->its);
     launch_b_inner_step(c, rhs, ver, n_its, t.S, t.cur_r, t.cur_p);
     t.S += 1;
   }
@@ -210,7 +207,7 @@ int finish_inner(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, in
       }
     }
     if (all) break;
-    enqueue_steps(B, c, t, rhs, ver, 1, std::max(B->sched_its, 30));
+    enqueue_steps(B, c, t, rhs, ver, 1, std::max(B->sc->its, 30));
     HIPCHK(hipGetLastError());
     int rc = read_states(B, s);
     if (rc) return rc;
@@ -222,10 +219,10 @@ int finish_inner(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, in
     st[i].inner_its_total += h.inner_its;
     st[i].inner_its_max = std::max(st[i].inner_its_max, h.inner_its);
     st[i].refine_steps += h.refine_steps;
-    B->sched_steps = std::max(B->sched_steps, std::max(h.refine_steps, 1));
-    B->sched_its = std::max(B->sched_its, h.run_its_max + 1);
+    B->sc->steps = std::max(B->sc->steps, std::max(h.refine_steps, 1));
+    B->sc->its = std::max(B->sc->its, h.run_its_max + 1);
     for (int q = 0; q < std::min(h.refine_steps, 8); ++q)
-      B->step_its[q] = std::max(B->step_its[q], h.run_len[q] + 1);
+      B->sc->step_its[q] = std::max(B->sc->step_its[q], h.run_len[q] + 1);
   }
   return FDD_OK;
 }
@@ -234,28 +231,29 @@ int finish_inner(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, in
 int batch_inner(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, int rhs, int ver,
                 const std::vector<char>& live, const fdd_opts& o, std::vector<fdd_stats>& st) {
   enqueue_start(c, t, rhs, ver, o);
-  if (!B->calibrated) enqueue_steps(B, c, t, rhs, ver, 1, 30);  // measures the schedule
-  else enqueue_steps(B, c, t, rhs, ver, B->sched_steps, -1);
+  if (!B->sc->calibrated) enqueue_steps(B, c, t, rhs, ver, 1, 30);  // measures the schedule
+  else enqueue_steps(B, c, t, rhs, ver, B->sc->steps, -1);
   HIPCHK(hipGetLastError());
   int rc = read_states(B, s);
   if (rc) return rc;
   rc = finish_inner(B, s, c, t, rhs, ver, live, o, st);
-  if (rc == FDD_OK) B->calibrated = true;
+  if (rc == FDD_OK) B->sc->calibrated = true;
   return rc;
 }
 
 // Everything of outer iteration v up to the synchronization, for the instances still running.
 void enqueue_outer(const fdd_batch_s* B, const BatchCtx& c, BTrack& t, int v, const fdd_opts& o) {
   enqueue_start(c, t, kRhsLiftP, v, o);
-  enqueue_steps(B, c, t, kRhsLiftP, v, B->sched_steps, -1);
+  enqueue_steps(B, c, t, kRhsLiftP, v, B->sc->steps, -1);
   launch_b_operator(c, v);
   launch_b_outer_tail(c, t.S, v, o.outer_rtol);
 }
 
 int replay_outer(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, int v,
                  const fdd_opts& o) {
-  std::vector<int> key = {v & 1, o.mg_nu, B->sched_steps, B->sched_its};
-  key.insert(key.end(), B->step_its, B->step_its + 8);
+  std::vector<int> key = {v & 1, o.mg_nu, B->sc->steps, B->sc->its,
+                          (int)std::lround(std::log10(o.step_rtol) * 16.0)};
+  key.insert(key.end(), B->sc->step_its, B->sc->step_its + 8);
   auto it = B->graphs.find(key);
   if (it == B->graphs.end()) {
     hipGraph_t g = nullptr;
@@ -395,6 +393,7 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
   if (o.precision != FDD_MIXED)
     return fail(FDD_E_ARG, "batched solves run FP32 multigrid-PCG inside FP64 refinement only");
+  B->sc = &B->scheds[std::make_pair(o.mg_nu, o.step_rtol)];
   HIPCHK(hipSetDevice(B->device));
   hipStream_t us = (hipStream_t)stream;
   hipStream_t s = us;

@@ -24,6 +24,15 @@ int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline int round_up(int x, int a) { return (x + a - 1) / a * a; }
 
+// Launch schedule of the interior solves: refinement steps x FP32 PCG iterations per step
+// (mixed), or FP64 PCG iterations.  It only grows; the first solve runs every PCG to its own
+// criterion and measures it.
+struct Schedule {
+  int steps = 1, its = 2, its64 = 4;
+  int step_its[8] = {2, 2, 2, 2, 2, 2, 2, 2};
+  bool calibrated = false;
+};
+
 // Per-precision multigrid-PCG buffers of level 0 plus the hierarchy.
 template <typename T>
 struct PcgSet {
@@ -84,11 +93,11 @@ struct fdd_problem_s {
   double* scratchH = nullptr;
   DevState* host_st = nullptr;  // pinned copy
   // inner schedule (refinement steps x PCG iterations, or FP64 PCG iterations); only grows
-  int sched_steps = 1, sched_its = 2, sched_its64 = 4;
-  int sched_step_its[8] = {2, 2, 2, 2, 2, 2, 2, 2};  // per refinement step (mixed)
-  bool calibrated = false;  // the first interior solve runs every PCG to its own criterion
+  // one schedule per (smoother sweeps, per-step reduction); `sc` is the current one
+  std::map<std::pair<int, double>, fdd::Schedule> scheds;
+  fdd::Schedule* sc = nullptr;
   // captured outer iterations, keyed by (parity, schedule, precision, smoother)
-  std::map<std::tuple<int, int, int, int, int>, GraphEntry> graphs;
+  std::map<std::vector<int>, GraphEntry> graphs;
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // kernel timer (HIP events around every launch of one kernel kind)
@@ -111,6 +120,7 @@ namespace fdd {
 
 ShiftTable make_table(const fdd_ratpc_s* t);
 bool opts_ok(const fdd_opts* o);
+double step_tau(const fdd_opts& o);
 int check_problem(fdd_problem_s* P);
 int check_table(const fdd_problem_s* P, const fdd_ratpc_s* t, int which);
 

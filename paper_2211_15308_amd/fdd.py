@@ -54,7 +54,7 @@ class FddOpts(ctypes.Structure):
     _fields_ = [("outer_rtol", ctypes.c_double), ("outer_maxit", ctypes.c_int),
                 ("inner_rtol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("precision", ctypes.c_int), ("mg_nu", ctypes.c_int),
-                ("inner_chunk", ctypes.c_int), ("check_true_residual", ctypes.c_int),
+                ("step_rtol", ctypes.c_double), ("check_true_residual", ctypes.c_int),
                 ("warmstart", ctypes.c_void_p), ("use_graph", ctypes.c_int)]
 
 

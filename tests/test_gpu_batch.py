@@ -144,3 +144,26 @@ def test_batch_error_paths():
     for i, c in enumerate(cases):
         x_ref = system.solve_dst_2d(c["n"], c["K"], c["mu"], host(bs[i]))
         assert rel(host(xs[i]), x_ref) <= 1e-8
+
+
+def test_autotuner_times_candidates_then_reuses_its_cache(tmp_path):
+    from paper_2211_15308_amd import autotune
+    cases = workloads.batch_instances(count=4, seed=13, sizes=[64, 128, 192])
+    B, probs, TP, TH, bs = make_batch(cases, tol_p=1e-8, max_p=20)
+    xs = [torch.zeros_like(b) for b in bs]
+    cache = str(tmp_path / "tune.json")
+    cands = [(1, 1e-5), (2, 1e-5), (1, 1e-4)]
+    opts, rec = autotune.tune_batch(B, bs, xs, reps=1, cache_path=cache, candidates=cands)
+    print(f"[autotune] {rec['ms_per_batch']} -> nu={rec['mg_nu']} tau={rec['step_rtol']}", flush=True)
+    assert not rec["cached"] and len(rec["ms_per_batch"]) == len(cands)
+    assert (opts.mg_nu, opts.step_rtol) in cands
+    opts2, rec2 = autotune.tune_batch(B, bs, xs, reps=1, cache_path=cache, candidates=cands)
+    assert rec2["cached"] and (opts2.mg_nu, opts2.step_rtol) == (opts.mg_nu, opts.step_rtol)
+    # every candidate solves to the method's tolerance
+    for nu, tau in cands:
+        xs = [torch.zeros_like(b) for b in bs]
+        st = B.solve(bs, xs, F.opts_default(mg_nu=nu, step_rtol=tau))
+        for i, c in enumerate(cases):
+            x_ref = system.solve_dst_2d(c["n"], c["K"], c["mu"], host(bs[i]))
+            assert rel(host(xs[i]), x_ref) <= 1e-6
+            assert st[i]["status"] == F.FDD_OK
