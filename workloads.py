@@ -71,3 +71,16 @@ def sine_series_traces(count, n, kmax=64, seed=5):
     x = np.arange(1, n) / n
     basis = np.sin(np.pi * k[:, None] * x[None, :])      # (kmax, n-1)
     return a, a @ basis
+
+
+def cnn_init(widths=(5, 32, 32, 32, 32, 32, 1), seed=6):
+    """Seeded He-normal weights (std sqrt(2 / fan_in), fan_in = 9 C_in) and zero biases.
+
+    Returns [(W (3, 3, C_in, C_out), b (C_out,))] in float64.
+    """
+    rng = np.random.default_rng(seed)
+    params = []
+    for cin, cout in zip(widths[:-1], widths[1:]):
+        W = rng.standard_normal((3, 3, cin, cout)) * np.sqrt(2.0 / (9 * cin))
+        params.append((W, np.zeros(cout)))
+    return params
