@@ -62,6 +62,7 @@ enum { FDD_RA_PRECOND = 0, FDD_RA_OPERATOR = 1 };     /* which function a table 
 typedef struct fdd_problem_s* fdd_problem;   /* opaque: host state + views into the workspace */
 typedef struct fdd_ratpc_s* fdd_ratpc;       /* opaque: one rational table (host copy)          */
 typedef struct fdd_batch_s* fdd_batch;       /* opaque: a batch of problems solved together     */
+typedef struct fdd_cnn_s* fdd_cnn;           /* opaque: the warm-start network                  */
 
 /* Problem description.  dim = 2 (3 reserved); n = cells per side, even, 4 <= n <= 2048 and
  * such that halving the (n - 1)-point grid while its point count is odd ends at <= 16 points
@@ -84,7 +85,11 @@ typedef struct {
   double step_rtol;    /* mixed precision: each FP32 multigrid-PCG run (one refinement step)
                           reduces its residual by this factor (default 1e-5; 1e-7 .. 1e-2)    */
   int check_true_residual; /* nonzero: fdd_solve computes ||b - A x|| / ||b|| at the end       */
-  void* warmstart;     /* reserved for the learned initial guess; must be NULL                 */
+  void* warmstart;     /* NULL, or a network handle of type fdd_cnn with its parameters set,
+                          its workspace bound and n_max >= n:
+                          fdd_solve (mixed precision) starts the interior solve of every outer
+                          iteration from the network's guess for the lifted search direction,
+                          kept only if it lowers the residual below that of the zero guess    */
   int use_graph;       /* 1 (default): fdd_solve replays each outer iteration from a captured
                           hipGraph on a library-owned stream ordered after `stream`; 0: eager */
 } fdd_opts;
@@ -100,6 +105,8 @@ typedef struct {
   double rel_precond_res;  /* final (r^T z / r0^T z0)^{1/2}                                     */
   double true_rel_res;     /* ||b - A x||_2 / ||b||_2 if requested, else -1                     */
   double t_solve_ms;       /* host wall time of fdd_solve                                      */
+  int warm_starts;         /* interior solves started from the network's guess                 */
+  int warm_accepted;       /* ... of which the guess was kept                                  */
 } fdd_stats;
 
 void fdd_opts_default(fdd_opts* opts);
@@ -203,6 +210,44 @@ int fdd_batch_bind_workspace(fdd_batch batch, void* dev_ptr, size_t bytes, void*
 int fdd_solve_batched(fdd_batch batch, const double* const* b, double* const* x,
                       const fdd_opts* opts, void* stream, fdd_stats* stats);
 void fdd_batch_destroy(fdd_batch batch);
+
+/* ---- learned warm start ----------------------------------------------------------------------
+ * A convolutional network predicts the discrete harmonic extension E t (the interior solution of
+ * A_II u = lift(t), eq. (block_op)) of an interface trace t, as the initial guess of the interior
+ * solves inside the outer PCG.  Six 3x3 'same' convolutions, widths 5 -> 32 (x5) -> 1, exact
+ * GELU after the first five; BF16 weights and activations with FP32 accumulation on the matrix
+ * cores.  Input channels of an image (n - 1 rows j, n - 1 columns i): t_i / s, y = j / n,
+ * y t_i / s, log10 K, log10 mu, with s the root-mean-square of t.  Parameters: one FP32 device
+ * vector, per layer W[3][3][c_in][c_out] then b[c_out] (fdd_cnn_param_count entries); they are
+ * owned by the caller, as are gradients and Adam moments.  Images and outputs are row-major
+ * (row j - 1, column i - 1), i.e. the interior free-dof order.
+ *
+ * fdd_cnn_create: sizes for up to batch_max images of up to n_max (n - 1 pixels a side); train
+ * != 0 keeps the activations for fdd_cnn_backward.  Host only.  Errors: FDD_E_ARG.          */
+int fdd_cnn_create(int batch_max, int n_max, int train, int hip_device, fdd_cnn* out);
+int fdd_cnn_param_count(fdd_cnn cnn, int64_t* count);
+int fdd_cnn_workspace_bytes(fdd_cnn cnn, size_t* bytes);
+/* Binds caller-owned device memory (256-byte aligned).  Parameters must be set again after.  */
+int fdd_cnn_bind_workspace(fdd_cnn cnn, void* dev_ptr, size_t bytes, void* stream);
+/* Converts the FP32 parameters to the BF16 layouts the kernels read (asynchronous).          */
+int fdd_cnn_set_params(fdd_cnn cnn, const float* theta, void* stream);
+/* out (FP32, batch x (n-1)^2) = network(features of traces[b] (row stride ld >= n - 1),
+ * log10K[b], log10mu[b]); rescale != 0 multiplies image b by s_b (the guess for t itself),
+ * else the output is that for t / s_b.  All pointers device.  Asynchronous.                  */
+int fdd_cnn_forward(fdd_cnn cnn, const double* traces, int ld, int batch, int n,
+                    const double* log10K, const double* log10mu, float* out, int rescale,
+                    void* stream);
+/* Mean squared error of out against target (both batch x (n-1)^2, FP32, device) into *loss
+ * (device double; NULL: internal), and its gradient for fdd_cnn_backward.  Asynchronous.     */
+int fdd_cnn_loss(fdd_cnn cnn, const float* out, const float* target, int batch, int n,
+                 double* loss, void* stream);
+/* grad (FP32, parameter layout) = gradient of the last loss against the parameters, through the
+ * last forward pass (same batch and n).  Deterministic.  Asynchronous.                       */
+int fdd_cnn_backward(fdd_cnn cnn, int batch, int n, float* grad, void* stream);
+/* One Adam step (Kingma and Ba 2015) on theta with moments m, v (FP32, device); step >= 1. */
+int fdd_cnn_adam_step(fdd_cnn cnn, float* theta, const float* grad, float* m, float* v, float lr,
+                      float b1, float b2, float eps, int step, void* stream);
+void fdd_cnn_destroy(fdd_cnn cnn);
 
 /* ---- measurement ---------------------------------------------------------------------------
  * Times every launch of one kernel kind with a pair of HIP events attached to that kernel's own

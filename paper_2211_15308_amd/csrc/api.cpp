@@ -93,6 +93,7 @@ size_t plan_workspace(fdd_problem_s* P, char* base) {
   P->zG = (double*)take(g);
   P->yG = (double*)take(g);
   P->Hp = (double*)take(g);
+  P->lk_lmu = (double*)take(2 * sizeof(double));
   P->scratchP = (double*)take(g * (kMaxPoles + 1));
   P->scratchH = (double*)take(g * (kMaxPoles + 1));
   return align_up(off, 256);
@@ -187,7 +188,7 @@ bool opts_ok(const fdd_opts* o) {
   return o && o->outer_rtol > 0 && o->inner_rtol > 0 && o->outer_maxit > 0 &&
          o->inner_maxit > 0 && (o->precision == FDD_MIXED || o->precision == FDD_FP64) &&
          (o->mg_nu == 1 || o->mg_nu == 2) && o->step_rtol >= 1e-7 && o->step_rtol <= 1e-2 &&
-         o->warmstart == nullptr &&
+         (o->warmstart == nullptr || o->precision == FDD_MIXED) &&
          (o->use_graph == 0 || o->use_graph == 1);
 }
 
@@ -213,14 +214,17 @@ const double* inner_u(const fdd_problem_s* P, const InnerTrack& t) {
   return t.fp64 ? P->s64.x : P->u64[t.S & 1];
 }
 
-// First residual (u = 0) of an interior solve, and in FP64 the start of its PCG.
-void enqueue_inner_start(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, const fdd_opts& o) {
+// First residual (u = 0, or the learned guess `warm` times *wscale) of an interior solve, and in
+// FP64 the start of its PCG.
+void enqueue_inner_start(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, const fdd_opts& o,
+                         const float* warm = nullptr, const double* wscale = nullptr) {
   const double tol2 = o.inner_rtol * o.inner_rtol;
   t.cur_r = t.cur_p = 0;
   t.S = t.k = 0;
   if (!t.fp64) {
     launch_ir_residual(c, t.f, nullptr, nullptr, nullptr, P->u64[0], P->s32.r[t.cur_r], nullptr, 1,
-                       tol2, step_tau(o) * step_tau(o), 0);
+                       tol2, step_tau(o) * step_tau(o), 0, warm, wscale);
+    if (warm) launch_ir_reject(c, t.f, P->u64[0], P->s32.r[t.cur_r]);
   } else {
     launch_ir_residual(c, t.f, nullptr, nullptr, nullptr, P->u64[0], nullptr, P->s64.r[t.cur_r], 1,
                        tol2, tol2, 1);
@@ -478,6 +482,8 @@ int fdd_bind_workspace(fdd_problem P, void* dev, size_t bytes, void* stream) {
   for (size_t k = 0; k < np; ++k) c32[k] = (float)P->cinv[k];
   HIPCHK(hipMemcpyAsync(P->cinv64, P->cinv.data(), np * sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(P->cinv32, c32.data(), np * sizeof(float), hipMemcpyHostToDevice, s));
+  const double lkm[2] = {std::log10(P->K), std::log10(P->mu)};
+  HIPCHK(hipMemcpyAsync(P->lk_lmu, lkm, sizeof(lkm), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   return FDD_OK;
 }
@@ -649,7 +655,11 @@ void enqueue_outer_iteration(fdd_problem_s* P, hipStream_t s, const ShiftTable& 
   const int a = v & 1;
   LaunchCtx c = make_ctx(P, s, o.mg_nu, t.fp64);
   t.f = RhsDesc{nullptr, 0.0, P->pG[a], 1.0};
-  enqueue_inner_start(P, c, t, o);
+  const float* warm = nullptr;
+  const double* wscale = nullptr;
+  if (o.warmstart)  // checked by the caller; the network's guess for E p
+    (void)cnn_warm_guess((fdd_cnn_s*)o.warmstart, s, P->pG[a], P->n, P->lk_lmu, &warm, &wscale);
+  enqueue_inner_start(P, c, t, o, warm, wscale);
   if (!t.fp64) enqueue_inner_more(P, c, t, P->sc->steps, -1);
   else enqueue_inner_more(P, c, t, 0, P->sc->its64);
   launch_iface_batch(s, (int)P->NG, P->h, tabH, kIfaceOperator, P->pG[a], P->Hp, P->scratchH,
@@ -664,6 +674,9 @@ int launch_outer_graph(fdd_problem_s* P, hipStream_t s, const ShiftTable& tabP,
   std::vector<int> key = {v & 1, (int)t.fp64, o.mg_nu, P->sc->steps, P->sc->its, P->sc->its64,
                           (int)std::lround(std::log10(o.step_rtol) * 16.0)};
   key.insert(key.end(), P->sc->step_its, P->sc->step_its + 8);
+  const uint64_t ws = (uint64_t)(uintptr_t)o.warmstart;
+  key.push_back((int)(ws & 0xffffffffu));
+  key.push_back((int)(ws >> 32));
   auto it = P->graphs.find(key);
   if (it == P->graphs.end()) {
     hipGraph_t g = nullptr;
@@ -707,6 +720,7 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   if (opts) o = *opts;
   else fdd_opts_default(&o);
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
+  if (o.warmstart && (rc = cnn_check_for((const fdd_cnn_s*)o.warmstart, P->n))) return rc;
   use_schedule(P, o);
   HIPCHK(hipSetDevice(P->device));
   hipStream_t us = (hipStream_t)stream;
@@ -784,6 +798,10 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
       rc = inner_finish(P, s, t, o, &res);
       account(res);
       if (rc) return finish(rc);
+    }
+    if (o.warmstart) {
+      st.warm_starts += 1;
+      st.warm_accepted += P->host_st->warm_used;
     }
     const DevState& h = *P->host_st;
     if (h.breakdown)

@@ -393,6 +393,7 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
   if (o.precision != FDD_MIXED)
     return fail(FDD_E_ARG, "batched solves run FP32 multigrid-PCG inside FP64 refinement only");
+  if (o.warmstart) return fail(FDD_E_ARG, "the batched solve takes no warm start");
   B->sc = &B->scheds[std::make_pair(o.mg_nu, o.step_rtol)];
   HIPCHK(hipSetDevice(B->device));
   hipStream_t us = (hipStream_t)stream;

@@ -89,6 +89,7 @@ struct fdd_problem_s {
   double* zG = nullptr;
   double* yG = nullptr;
   double* Hp = nullptr;
+  double* lk_lmu = nullptr;     // {log10 K, log10 mu} for the warm-start network
   double* scratchP = nullptr;
   double* scratchH = nullptr;
   DevState* host_st = nullptr;  // pinned copy
@@ -121,6 +122,10 @@ namespace fdd {
 ShiftTable make_table(const fdd_ratpc_s* t);
 bool opts_ok(const fdd_opts* o);
 double step_tau(const fdd_opts& o);
+// warm-start network (api_cnn.cpp)
+int cnn_check_for(const fdd_cnn_s* C, int n);
+int cnn_warm_guess(fdd_cnn_s* C, hipStream_t s, const double* trace, int n, const double* lk_lmu,
+                   const float** guess, const double** scale);
 int check_problem(fdd_problem_s* P);
 int check_table(const fdd_problem_s* P, const fdd_ratpc_s* t, int which);
 

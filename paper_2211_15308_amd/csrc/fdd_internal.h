@@ -58,6 +58,10 @@ struct DevState {
   int pcg_is_final;  // FP64 mode: the PCG residual is the interior solve's residual
   int run_its_max;   // largest iteration count of a PCG run in this interior solve
   int run_len[8];    // PCG iterations of each refinement step's run (first 8 steps)
+  int warm_try;      // the running interior solve started from a learned guess
+  int warm_reject;   // ... which was rejected (||f - A u0|| >= ||f||): restarted from zero
+  int warm_used;     // ... which was accepted
+  int pad3;
   int outer_done;    // batched solve: this instance's outer PCG has converged
   int o_ver;         // batched solve: version (parity) holding the final interface iterate
   int o_its;         // batched solve: outer iterations of this instance
@@ -145,7 +149,11 @@ void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* 
 // call; a plain copy once the solve has converged), r = f - A uout.
 void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin, const float* e32,
                         const double* e64, double* uout, float* r32, double* r64, int first,
-                        double tol2, double tau2, int pcg_is_final);
+                        double tol2, double tau2, int pcg_is_final,
+                        const float* warm = nullptr, const double* wscale = nullptr);
+// After a first residual from a learned guess: if the guess was rejected, restarts the interior
+// solve from zero (u = 0, r = f); otherwise does nothing.
+void launch_ir_reject(const LaunchCtx& c, const RhsDesc& f, double* uout, float* r32);
 
 // ---- interface kernels (kernels_iface.hip) -------------------------------------------------
 struct ShiftTable {

@@ -68,11 +68,18 @@ template <typename E>
 __global__ __launch_bounds__(kBlock) void k_ir_residual(
     RhsDesc f, const double* __restrict__ uin, const E* __restrict__ e, double* __restrict__ uout,
     float* __restrict__ r32, double* __restrict__ r64, int nf, int pitch, int first, double tol2,
-    double tau2, int pcg_is_final, DevState* st, Reductions red) {
+    double tau2, int pcg_is_final, DevState* st, Reductions red, const float* __restrict__ warm,
+    const double* __restrict__ wscale) {
   int tile_x, tile_y;
   const int tile = xcd_tile(&tile_x, &tile_y);
   d_ir_residual<E>(f, uin, e, uout, r32, r64, nf, pitch, first, tol2, tau2, pcg_is_final, st, red,
-                   tile_x, tile_y, tile, block0());
+                   tile_x, tile_y, tile, block0(), warm, wscale);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ir_reject(RhsDesc f, double* __restrict__ uout,
+                                                      float* __restrict__ r32, int nf, int pitch,
+                                                      const DevState* st) {
+  d_ir_reject(f, uout, r32, nf, pitch, st, blockIdx.x, blockIdx.y);
 }
 
 __global__ __launch_bounds__(kBlock) void k_ir_finalize(DevState* st, Reductions red) {
@@ -160,17 +167,24 @@ void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* 
 
 void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin, const float* e32,
                         const double* e64, double* uout, float* r32, double* r64, int first,
-                        double tol2, double tau2, int pcg_is_final) {
+                        double tol2, double tau2, int pcg_is_final, const float* warm,
+                        const double* wscale) {
   const Level& L = c.lev[0];
   if (e64 || !e32)
     hipLaunchKernelGGL((k_ir_residual<double>), tiles(L.nf), tblock(), 0, c.stream, f, uin, e64,
                        uout, r32, r64, L.nf, L.pitch, first, tol2, tau2, pcg_is_final, c.st,
-                       c.red);
+                       c.red, warm, wscale);
   else
     hipLaunchKernelGGL((k_ir_residual<float>), tiles(L.nf), tblock(), 0, c.stream, f, uin, e32,
                        uout, r32, r64, L.nf, L.pitch, first, tol2, tau2, pcg_is_final, c.st,
-                       c.red);
+                       c.red, warm, wscale);
   hipLaunchKernelGGL(k_ir_finalize, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red);
+}
+
+void launch_ir_reject(const LaunchCtx& c, const RhsDesc& f, double* uout, float* r32) {
+  const Level& L = c.lev[0];
+  hipLaunchKernelGGL(k_ir_reject, tiles(L.nf), tblock(), 0, c.stream, f, uout, r32, L.nf,
+                     L.pitch, (const DevState*)c.st);
 }
 
 template void launch_pcg_init<float>(const LaunchCtx&, const MGBuffers<float>&, const float*,

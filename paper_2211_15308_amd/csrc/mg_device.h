@@ -654,7 +654,8 @@ __device__ __forceinline__ void d_ir_residual(
     const RhsDesc& f, const double* __restrict__ uin, const E* __restrict__ e,
     double* __restrict__ uout, float* __restrict__ r32, double* __restrict__ r64, int nf,
     int pitch, int first, double tol2, double tau2, int pcg_is_final, DevState* st,
-    const Reductions& red, int tile_x, int tile_y, int tile, bool lead) {
+    const Reductions& red, int tile_x, int tile_y, int tile, bool lead,
+    const float* __restrict__ warm = nullptr, const double* __restrict__ wscale = nullptr) {
   constexpr int W = kTile + 2;
   __shared__ double su[W][W + 1];
   const int i0 = tile_x * kTile, j0 = tile_y * kTile;
@@ -672,6 +673,8 @@ __device__ __forceinline__ void d_ir_residual(
     return;
   }
   constexpr int RY = Slots<W>::RY, RX = Slots<W>::RX;
+  // first call: u = 0, or u = s g for a learned guess g (compact FP32 image) with scale s
+  const double ws = (first && warm) ? *wscale : 0.0;
   double ur[RY][RX];
 #pragma unroll
   for (int a = 0; a < RY; ++a) {
@@ -679,9 +682,15 @@ __device__ __forceinline__ void d_ir_residual(
     for (int b = 0; b < RX; ++b) {
       const int lj = threadIdx.y + 8 * a, li = threadIdx.x + 32 * b;
       const int i = i0 + li, j = j0 + lj;
-      const bool in = !first && lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+      const bool cell = lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
       const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
-      ur[a][b] = in ? ldg(uin, o) + (double)ldg(e, o) : 0.0;
+      double uv = 0.0;
+      if (!first) {
+        if (cell) uv = ldg(uin, o) + (double)ldg(e, o);
+      } else if (warm) {
+        if (cell) uv = ws * (double)ldg(warm, (unsigned)((j - 1) * nf + (i - 1)));
+      }
+      ur[a][b] = uv;
     }
   }
 #pragma unroll
@@ -692,7 +701,7 @@ __device__ __forceinline__ void d_ir_residual(
       if (lj < W && li < W) su[lj][li] = ur[a][b];
     }
   __syncthreads();
-  double rr = 0.0;
+  double rr = 0.0, fsq = 0.0;
   for (int b = threadIdx.y; b < kTile; b += blockDim.y) {
     const int j = j0 + 1 + b;
     if (j > nf) continue;
@@ -701,21 +710,27 @@ __device__ __forceinline__ void d_ir_residual(
       if (i > nf) continue;
       const int li = a + 1, lj = b + 1;
       const double u = su[lj][li];
-      const double r = rhs_at(f, nf, i, j) - (4.0 * u - su[lj][li - 1] - su[lj][li + 1] -
-                                              su[lj - 1][li] - su[lj + 1][li]);
+      const double fv = rhs_at(f, nf, i, j);
+      const double r = fv - (4.0 * u - su[lj][li - 1] - su[lj][li + 1] - su[lj - 1][li] -
+                             su[lj + 1][li]);
       const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
       stg(uout, o, u);
       if (r32) stg(r32, o, (float)r);
       if (r64) stg(r64, o, r);
       rr += r * r;
+      fsq += fv * fv;
     }
   }
   const double tot = block_sum_all(rr);
+  const double ftot = first ? block_sum_all(fsq) : 0.0;
   if (thread0()) {
     red.ir[tile] = tot;
-    if (first) red.ff[tile] = tot;
+    if (first) red.ff[tile] = ftot;
     if (lead) {
       if (first) {
+        st->warm_try = warm ? 1 : 0;
+        st->warm_reject = 0;
+        st->warm_used = 0;
         st->tol2 = tol2;
         st->tau2 = tau2;
         st->pcg_is_final = pcg_is_final;
@@ -733,6 +748,25 @@ __device__ __forceinline__ void d_ir_residual(
   }
 }
 
+// After a rejected learned guess: u = 0 and r = f on own points (otherwise nothing).
+__device__ __forceinline__ void d_ir_reject(const RhsDesc& f, double* __restrict__ uout,
+                                            float* __restrict__ r32, int nf, int pitch,
+                                            const DevState* st, int tile_x, int tile_y) {
+  if (!st->warm_reject) return;
+  const int i0 = tile_x * kTile, j0 = tile_y * kTile;
+  for (int b = threadIdx.y; b < kTile; b += blockDim.y) {
+    const int j = j0 + 1 + b;
+    if (j > nf) continue;
+    for (int a = threadIdx.x; a < kTile; a += blockDim.x) {
+      const int i = i0 + 1 + a;
+      if (i > nf) continue;
+      const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+      stg(uout, o, 0.0);
+      stg(r32, o, (float)rhs_at(f, nf, i, j));
+    }
+  }
+}
+
 // One block: reads the refinement residual back from the partials and sets the solve's state
 // for the next PCG run (or ends the solve).
 __device__ __forceinline__ void d_ir_finalize(DevState* st, const Reductions& red) {
@@ -740,15 +774,26 @@ __device__ __forceinline__ void d_ir_finalize(DevState* st, const Reductions& re
   const double res = sum_partials(red.ir, red.nb0);
   const double ff = sum_partials(red.ff, red.nb0);
   if (thread0()) {
+    double r2 = res;
+    if (st->warm_try) {
+      // a learned initial guess is kept only if it reduces the residual below that of zero
+      if (res < ff) {
+        st->warm_used = 1;
+      } else {
+        st->warm_reject = 1;
+        r2 = ff;
+      }
+      st->warm_try = 0;
+    }
     st->ff = ff;
-    st->res2 = res;
-    st->rr0 = res;
+    st->res2 = r2;
+    st->rr0 = r2;
     st->inner_done = 0;
     st->pcg_k = 0;
-    if (!isfinite(res)) {
+    if (!isfinite(r2)) {
       st->breakdown |= 4;
       st->solve_done = 1;
-    } else if (res <= st->tol2 * ff) {
+    } else if (r2 <= st->tol2 * ff) {
       st->solve_done = 1;
     }
   }

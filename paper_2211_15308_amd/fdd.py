@@ -41,6 +41,9 @@ EXPORTED = [
     "fdd_destroy_ratpc", "fdd_last_error", "fdd_version", "fdd_batch_create",
     "fdd_batch_workspace_bytes", "fdd_batch_bind_workspace", "fdd_solve_batched",
     "fdd_batch_destroy", "fdd_batch_set_kernel_timer", "fdd_batch_get_kernel_timer",
+    "fdd_cnn_create", "fdd_cnn_param_count", "fdd_cnn_workspace_bytes", "fdd_cnn_bind_workspace",
+    "fdd_cnn_set_params", "fdd_cnn_forward", "fdd_cnn_loss", "fdd_cnn_backward",
+    "fdd_cnn_adam_step", "fdd_cnn_destroy",
 ]
 FDD_KT_NONE, FDD_KT_DOWN0, FDD_KT_UP0, FDD_KT_COARSE = 0, 1, 2, 3
 
@@ -63,7 +66,8 @@ class FddStats(ctypes.Structure):
                 ("inner_solves", ctypes.c_int), ("inner_its_total", ctypes.c_int),
                 ("inner_its_max", ctypes.c_int), ("refine_steps", ctypes.c_int),
                 ("rel_precond_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
-                ("t_solve_ms", ctypes.c_double)]
+                ("t_solve_ms", ctypes.c_double), ("warm_starts", ctypes.c_int),
+                ("warm_accepted", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -123,6 +127,18 @@ def load():
                                                ctypes.POINTER(ctypes.c_int64)]
     lib.fdd_batch_destroy.argtypes = [P]
     lib.fdd_batch_destroy.restype = None
+    F_ = ctypes.c_float
+    lib.fdd_cnn_create.argtypes = [I, I, I, I, ctypes.POINTER(P)]
+    lib.fdd_cnn_param_count.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.fdd_cnn_workspace_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.fdd_cnn_bind_workspace.argtypes = [P, V, ctypes.c_size_t, V]
+    lib.fdd_cnn_set_params.argtypes = [P, V, V]
+    lib.fdd_cnn_forward.argtypes = [P, V, I, I, I, V, V, V, I, V]
+    lib.fdd_cnn_loss.argtypes = [P, V, V, I, I, V, V]
+    lib.fdd_cnn_backward.argtypes = [P, I, I, V, V]
+    lib.fdd_cnn_adam_step.argtypes = [P, V, V, V, V, F_, F_, F_, F_, I, V]
+    lib.fdd_cnn_destroy.argtypes = [P]
+    lib.fdd_cnn_destroy.restype = None
     lib.fdd_last_error.restype = ctypes.c_char_p
     lib.fdd_version.restype = ctypes.c_char_p
     _lib = lib
@@ -335,6 +351,78 @@ class Batch:
         if getattr(self, "h", None) and _lib is not None:
             _lib.fdd_batch_destroy(self.h)
             self.h = None
+
+
+class Cnn:
+    """The warm-start network (fdd_cnn_*): a handle plus its bound workspace.
+
+    Parameters, gradients and Adam moments are caller-owned FP32 CUDA tensors of length
+    param_count in the layout of include/fdd.h (per layer W[3][3][c_in][c_out], then b).
+    """
+
+    def __init__(self, batch_max, n_max, train=False, device=0, stream=None):
+        import torch
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.fdd_cnn_create(batch_max, n_max, 1 if train else 0, device, ctypes.byref(h)))
+        self.h = h
+        self.batch_max, self.n_max, self.train = batch_max, n_max, train
+        c = ctypes.c_int64()
+        _check(lib.fdd_cnn_param_count(h, ctypes.byref(c)))
+        self.param_count = c.value
+        nb = ctypes.c_size_t()
+        _check(lib.fdd_cnn_workspace_bytes(h, ctypes.byref(nb)))
+        ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=f"cuda:{device}")
+        ptr = ws.data_ptr()
+        off = (-ptr) % 256
+        _check(lib.fdd_cnn_bind_workspace(h, ctypes.c_void_p(ptr + off), ws.numel() - off, _stream(stream)))
+        self.workspace = ws
+
+    def set_params(self, theta, stream=None):
+        if theta.numel() != self.param_count:
+            raise ValueError("parameter vector has the wrong length")
+        _check(load().fdd_cnn_set_params(self.h, _ptr(theta), _stream(stream)))
+
+    def forward(self, traces, log10K, log10mu, out, n, rescale=True, stream=None):
+        B = traces.shape[0]
+        _check(load().fdd_cnn_forward(self.h, _ptr(traces), traces.stride(0), B, n, _ptr(log10K),
+                                      _ptr(log10mu), _ptr(out), 1 if rescale else 0, _stream(stream)))
+
+    def loss(self, out, target, n, loss=None, stream=None):
+        B = out.shape[0]
+        _check(load().fdd_cnn_loss(self.h, _ptr(out), _ptr(target), B, n, _ptr(loss), _stream(stream)))
+
+    def backward(self, batch, n, grad, stream=None):
+        _check(load().fdd_cnn_backward(self.h, batch, n, _ptr(grad), _stream(stream)))
+
+    def adam_step(self, theta, grad, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        _check(load().fdd_cnn_adam_step(self.h, _ptr(theta), _ptr(grad), _ptr(m), _ptr(v), lr, b1, b2,
+                                        eps, step, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.fdd_cnn_destroy(self.h)
+            self.h = None
+
+
+def pack_params(params):
+    """Flattens [(W (3, 3, c_in, c_out), b)] into the library's parameter order (numpy)."""
+    import numpy as np
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params])
+
+
+def unpack_params(theta, widths=(5, 32, 32, 32, 32, 32, 1)):
+    """Inverse of pack_params."""
+    import numpy as np
+    theta = np.asarray(theta)
+    out, o = [], 0
+    for a, c in zip(widths[:-1], widths[1:]):
+        W = theta[o:o + 9 * a * c].reshape(3, 3, a, c)
+        o += 9 * a * c
+        b = theta[o:o + c]
+        o += c
+        out.append((W, b))
+    return out
 
 
 # names of the C ABI calls
