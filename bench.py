@@ -47,6 +47,11 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched runs use --nu and the default per-step reduction instead of the autotuner")
+    ap.add_argument("--weights", default=None,
+                    help="warm-start network parameters (.npz); default: the package's trained weights")
+    ap.add_argument("--learned", choices=["auto", "none", "only"], default="auto",
+                    help="run the learned-warm-start comparison (auto: if weights exist)")
+    ap.add_argument("--learned-steps", type=int, default=6)
     ap.add_argument("--only-batched", action="store_true",
                     help="skip the headline single-problem run (for profiling the batched kernels)")
     return ap.parse_args()
@@ -194,6 +199,53 @@ def run_batched(F, args, label, cases, tol_p, max_p):
     }
 
 
+def run_learned(F, args, sizes=(256, 512, 1024), mus=(1e-3, 1.0)):
+    """Plain zero-guess vs learned-warm-start solves at K = 1 (same rtol): solves/s, inner its."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2211_15308_amd import train_warmstart
+    from oracle import system
+    path = args.weights or train_warmstart.DEFAULT_OUT
+    if not os.path.exists(path):
+        return {"skipped": f"no trained weights at {os.path.relpath(path, ROOT)}"}
+    theta_np, meta = train_warmstart.load_weights(path)
+    theta = torch.as_tensor(theta_np, dtype=torch.float32, device="cuda")
+    res = {"weights": os.path.relpath(path, ROOT), "trained": {k: meta[k] for k in
+                                                                ("n", "pairs", "steps", "val_loss", "train_seconds")},
+           "cases": []}
+    for n in sizes:
+        net = F.Cnn(1, n)
+        net.set_params(theta)
+        for ci, mu in enumerate(mus):
+            P = F.setup_mesh(n, 1.0, mu)
+            P.bind_workspace()
+            TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+            TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+            b = torch.as_tensor(workloads.rhs(2, n, 5000 + 10 * ci + n), dtype=torch.float64, device="cuda")
+            row = {"n": n, "K": 1.0, "mu": mu}
+            for label, ws in (("plain", None), ("learned", net.h.value)):
+                opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, mg_nu=args.nu)
+                opts.warmstart = ws
+                x = torch.zeros_like(b)
+                for _ in range(2):
+                    st = P.solve(TP, TH, b, x, opts)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.learned_steps):
+                    st = P.solve(TP, TH, b, x, opts)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                xr = system.solve_dst_2d(n, 1.0, mu, b.cpu().numpy())
+                row[label] = {"solves_per_s": args.learned_steps / el, "outer_its": st["outer_its"],
+                              "inner_its": st["inner_its_total"], "warm_accepted": st["warm_accepted"],
+                              "warm_starts": st["warm_starts"],
+                              "rel_err_vs_oracle": float(np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr))}
+            res["cases"].append(row)
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -212,6 +264,9 @@ def main():
     opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, precision=prec,
                           mg_nu=args.nu, use_graph=0 if args.eager else 1)
     case_list = cases(args)
+    if args.learned == "only":
+        print(json.dumps({"learned": run_learned(F, args)}))
+        return
     if args.only_batched:
         res = {}
         if args.batched in ("all", "1024"):
@@ -330,6 +385,8 @@ def main():
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args, case_list),
     }
     out.update(batched)
+    if args.learned == "auto":
+        out["learned"] = run_learned(F, args)
     print(json.dumps(out))
 
 

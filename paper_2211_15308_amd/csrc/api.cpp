@@ -214,17 +214,17 @@ const double* inner_u(const fdd_problem_s* P, const InnerTrack& t) {
   return t.fp64 ? P->s64.x : P->u64[t.S & 1];
 }
 
-// First residual (u = 0, or the learned guess `warm` times *wscale) of an interior solve, and in
-// FP64 the start of its PCG.
+// First residual (u = 0, or the learned guess `warm` scaled by its Galerkin factor) of an
+// interior solve, and in FP64 the start of its PCG.
 void enqueue_inner_start(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, const fdd_opts& o,
-                         const float* warm = nullptr, const double* wscale = nullptr) {
+                         const float* warm = nullptr) {
   const double tol2 = o.inner_rtol * o.inner_rtol;
   t.cur_r = t.cur_p = 0;
   t.S = t.k = 0;
   if (!t.fp64) {
+    if (warm) launch_warm_alpha(c, t.f, warm);
     launch_ir_residual(c, t.f, nullptr, nullptr, nullptr, P->u64[0], P->s32.r[t.cur_r], nullptr, 1,
-                       tol2, step_tau(o) * step_tau(o), 0, warm, wscale);
-    if (warm) launch_ir_reject(c, t.f, P->u64[0], P->s32.r[t.cur_r]);
+                       tol2, step_tau(o) * step_tau(o), 0, warm, warm ? &P->st->warm_alpha : nullptr);
   } else {
     launch_ir_residual(c, t.f, nullptr, nullptr, nullptr, P->u64[0], nullptr, P->s64.r[t.cur_r], 1,
                        tol2, tol2, 1);
@@ -657,9 +657,9 @@ void enqueue_outer_iteration(fdd_problem_s* P, hipStream_t s, const ShiftTable& 
   t.f = RhsDesc{nullptr, 0.0, P->pG[a], 1.0};
   const float* warm = nullptr;
   const double* wscale = nullptr;
-  if (o.warmstart)  // checked by the caller; the network's guess for E p
+  if (o.warmstart)  // checked by the caller; the network's guess for E p (any scale)
     (void)cnn_warm_guess((fdd_cnn_s*)o.warmstart, s, P->pG[a], P->n, P->lk_lmu, &warm, &wscale);
-  enqueue_inner_start(P, c, t, o, warm, wscale);
+  enqueue_inner_start(P, c, t, o, warm);
   if (!t.fp64) enqueue_inner_more(P, c, t, P->sc->steps, -1);
   else enqueue_inner_more(P, c, t, 0, P->sc->its64);
   launch_iface_batch(s, (int)P->NG, P->h, tabH, kIfaceOperator, P->pG[a], P->Hp, P->scratchH,

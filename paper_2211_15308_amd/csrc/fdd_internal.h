@@ -48,6 +48,7 @@ struct DevState {
   double t_res[2];   // true residual: ||b - A x||^2, ||b||^2
   double cg_alpha[2];  // step length of the inner PCG, by iteration parity
   double cg_gam[2];    // r . z of the inner PCG, by iteration parity
+  double warm_alpha;   // Galerkin factor of the learned initial guess (0: not used)
   // counters / flags
   int inner_done;    // the running multigrid-PCG has converged (or broke down)
   int solve_done;    // the interior solve has met its tolerance
@@ -58,9 +59,7 @@ struct DevState {
   int pcg_is_final;  // FP64 mode: the PCG residual is the interior solve's residual
   int run_its_max;   // largest iteration count of a PCG run in this interior solve
   int run_len[8];    // PCG iterations of each refinement step's run (first 8 steps)
-  int warm_try;      // the running interior solve started from a learned guess
-  int warm_reject;   // ... which was rejected (||f - A u0|| >= ||f||): restarted from zero
-  int warm_used;     // ... which was accepted
+  int warm_used;     // the running interior solve started from a learned guess (alpha > 0)
   int pad3;
   int outer_done;    // batched solve: this instance's outer PCG has converged
   int o_ver;         // batched solve: version (parity) holding the final interface iterate
@@ -151,9 +150,9 @@ void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin,
                         const double* e64, double* uout, float* r32, double* r64, int first,
                         double tol2, double tau2, int pcg_is_final,
                         const float* warm = nullptr, const double* wscale = nullptr);
-// After a first residual from a learned guess: if the guess was rejected, restarts the interior
-// solve from zero (u = 0, r = f); otherwise does nothing.
-void launch_ir_reject(const LaunchCtx& c, const RhsDesc& f, double* uout, float* r32);
+// Galerkin factor of a learned guess g (FP32 image, pitch nf) for the right-hand side f, into
+// st->warm_alpha (0 when the guess does not lower the energy error).
+void launch_warm_alpha(const LaunchCtx& c, const RhsDesc& f, const float* g);
 
 // ---- interface kernels (kernels_iface.hip) -------------------------------------------------
 struct ShiftTable {

@@ -76,10 +76,13 @@ __global__ __launch_bounds__(kBlock) void k_ir_residual(
                    tile_x, tile_y, tile, block0(), warm, wscale);
 }
 
-__global__ __launch_bounds__(kBlock) void k_ir_reject(RhsDesc f, double* __restrict__ uout,
-                                                      float* __restrict__ r32, int nf, int pitch,
-                                                      const DevState* st) {
-  d_ir_reject(f, uout, r32, nf, pitch, st, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(kBlock) void k_warm_dots(RhsDesc f, const float* __restrict__ g,
+                                                      int nf, Reductions red) {
+  d_warm_dots(f, g, nf, red, blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_warm_alpha(DevState* st, Reductions red) {
+  d_warm_alpha(st, red);
 }
 
 __global__ __launch_bounds__(kBlock) void k_ir_finalize(DevState* st, Reductions red) {
@@ -181,10 +184,10 @@ void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin,
   hipLaunchKernelGGL(k_ir_finalize, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red);
 }
 
-void launch_ir_reject(const LaunchCtx& c, const RhsDesc& f, double* uout, float* r32) {
+void launch_warm_alpha(const LaunchCtx& c, const RhsDesc& f, const float* g) {
   const Level& L = c.lev[0];
-  hipLaunchKernelGGL(k_ir_reject, tiles(L.nf), tblock(), 0, c.stream, f, uout, r32, L.nf,
-                     L.pitch, (const DevState*)c.st);
+  hipLaunchKernelGGL(k_warm_dots, tiles(L.nf), tblock(), 0, c.stream, f, g, L.nf, c.red);
+  hipLaunchKernelGGL(k_warm_alpha, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red);
 }
 
 template void launch_pcg_init<float>(const LaunchCtx&, const MGBuffers<float>&, const float*,

@@ -728,9 +728,6 @@ __device__ __forceinline__ void d_ir_residual(
     if (first) red.ff[tile] = ftot;
     if (lead) {
       if (first) {
-        st->warm_try = warm ? 1 : 0;
-        st->warm_reject = 0;
-        st->warm_used = 0;
         st->tol2 = tol2;
         st->tau2 = tau2;
         st->pcg_is_final = pcg_is_final;
@@ -748,22 +745,50 @@ __device__ __forceinline__ void d_ir_residual(
   }
 }
 
-// After a rejected learned guess: u = 0 and r = f on own points (otherwise nothing).
-__device__ __forceinline__ void d_ir_reject(const RhsDesc& f, double* __restrict__ uout,
-                                            float* __restrict__ r32, int nf, int pitch,
-                                            const DevState* st, int tile_x, int tile_y) {
-  if (!st->warm_reject) return;
+// A learned initial guess g for A u = f enters scaled by the Galerkin factor
+// alpha = f.g / g.A g, the minimizer of the energy error ||u - alpha g||_A over alpha; the guess is
+// used when alpha > 0 (then alpha g has a smaller energy error than the zero guess) and dropped
+// (alpha = 0) otherwise.  d_warm_dots stores the tile partials of f.g and g.A g (g is the FP32
+// image with pitch nf; A the 5-point operator with zero Dirichlet values); d_warm_alpha sums
+// them and sets st->warm_alpha, which the first residual then applies.
+__device__ __forceinline__ void d_warm_dots(const RhsDesc& f, const float* __restrict__ g, int nf,
+                                            const Reductions& red, int tile_x, int tile_y,
+                                            int tile) {
   const int i0 = tile_x * kTile, j0 = tile_y * kTile;
+  auto gv = [&](int i, int j) -> double {
+    return (i >= 1 && i <= nf && j >= 1 && j <= nf)
+               ? (double)ldg(g, (unsigned)((j - 1) * nf + (i - 1)))
+               : 0.0;
+  };
+  double fg = 0.0, gag = 0.0;
   for (int b = threadIdx.y; b < kTile; b += blockDim.y) {
     const int j = j0 + 1 + b;
     if (j > nf) continue;
     for (int a = threadIdx.x; a < kTile; a += blockDim.x) {
       const int i = i0 + 1 + a;
       if (i > nf) continue;
-      const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
-      stg(uout, o, 0.0);
-      stg(r32, o, (float)rhs_at(f, nf, i, j));
+      const double c = gv(i, j);
+      const double ag = 4.0 * c - gv(i - 1, j) - gv(i + 1, j) - gv(i, j - 1) - gv(i, j + 1);
+      fg += rhs_at(f, nf, i, j) * c;
+      gag += c * ag;
     }
+  }
+  const double tfg = block_sum_all(fg);
+  const double tgag = block_sum_all(gag);
+  if (thread0()) {
+    red.ir[tile] = tfg;
+    red.ff[tile] = tgag;
+  }
+}
+
+__device__ __forceinline__ void d_warm_alpha(DevState* st, const Reductions& red) {
+  const double fg = sum_partials(red.ir, red.nb0);
+  const double gag = sum_partials(red.ff, red.nb0);
+  if (thread0()) {
+    const double al = fg / gag;
+    const bool ok = gag > 0.0 && isfinite(al) && al > 0.0;
+    st->warm_alpha = ok ? al : 0.0;
+    st->warm_used = ok ? 1 : 0;
   }
 }
 
@@ -774,17 +799,7 @@ __device__ __forceinline__ void d_ir_finalize(DevState* st, const Reductions& re
   const double res = sum_partials(red.ir, red.nb0);
   const double ff = sum_partials(red.ff, red.nb0);
   if (thread0()) {
-    double r2 = res;
-    if (st->warm_try) {
-      // a learned initial guess is kept only if it reduces the residual below that of zero
-      if (res < ff) {
-        st->warm_used = 1;
-      } else {
-        st->warm_reject = 1;
-        r2 = ff;
-      }
-      st->warm_try = 0;
-    }
+    const double r2 = res;
     st->ff = ff;
     st->res2 = r2;
     st->rr0 = r2;
