@@ -199,6 +199,49 @@ def run_batched(F, args, label, cases, tol_p, max_p):
     }
 
 
+CNN_FWD_FLOP_PER_PX = 2 * 9 * (5 * 32 + 4 * 32 * 32 + 32 * 1)  # the six convolutions
+# forward + data gradient (all layers but the first) + weight gradient
+CNN_TRAIN_FLOP_PER_PX = 3 * CNN_FWD_FLOP_PER_PX - 2 * 9 * 5 * 32
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def cnn_timing(F, theta, reps=10):
+    """Inference at n = 1024 and one training step at n = 256, batch 16: time and MFMA rate."""
+    import torch
+    out = {}
+    for label, n, B, train in (("inference_n1024_b1", 1024, 1, False), ("train_step_n256_b16", 256, 16, True)):
+        net = F.Cnn(B, n, train=train)
+        net.set_params(theta)
+        tr = torch.randn((B, n - 1), dtype=torch.float64, device="cuda")
+        lk = torch.zeros(B, dtype=torch.float64, device="cuda")
+        y = torch.empty((B, (n - 1) ** 2), dtype=torch.float32, device="cuda")
+        tgt = torch.zeros_like(y)
+        th = theta.clone()
+        g, m, v = torch.zeros_like(th), torch.zeros_like(th), torch.zeros_like(th)
+
+        def once(step):
+            if train:
+                net.set_params(th)
+            net.forward(tr, lk, lk, y, n, rescale=not train)
+            if train:
+                net.loss(y, tgt, n)
+                net.backward(B, n, g)
+                net.adam_step(th, g, m, v, 1e-4, step)
+
+        once(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(reps):
+            once(k + 2)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        flop = (CNN_TRAIN_FLOP_PER_PX if train else CNN_FWD_FLOP_PER_PX) * B * (n - 1) ** 2
+        tf = flop / (ms * 1e-3) / 1e12
+        out[label] = {"ms": ms, "alg_tflops": tf, "frac_of_bf16_peak": tf / MFMA_BF16_PEAK_TFLOPS}
+    return out
+
+
 def run_learned(F, args, sizes=(256, 512, 1024), mus=(1e-3, 1.0)):
     """Plain zero-guess vs learned-warm-start solves at K = 1 (same rtol): solves/s, inner its."""
     import numpy as np
@@ -212,9 +255,10 @@ def run_learned(F, args, sizes=(256, 512, 1024), mus=(1e-3, 1.0)):
         return {"skipped": f"no trained weights at {os.path.relpath(path, ROOT)}"}
     theta_np, meta = train_warmstart.load_weights(path)
     theta = torch.as_tensor(theta_np, dtype=torch.float32, device="cuda")
+    timing = cnn_timing(F, theta)
     res = {"weights": os.path.relpath(path, ROOT), "trained": {k: meta[k] for k in
                                                                 ("n", "pairs", "steps", "val_loss", "train_seconds")},
-           "cases": []}
+           "network": timing, "cases": []}
     for n in sizes:
         net = F.Cnn(1, n)
         net.set_params(theta)
