@@ -387,7 +387,20 @@ const char* fdd_version(void) { return "fdd 0.1 (gfx950)"; }
 int fdd_setup_mesh(const fdd_desc* d, int hip_device, fdd_problem* out) {
   if (!d || !out) return fail(FDD_E_ARG, "null argument");
   *out = nullptr;
-  if (d->dim != 2) return fail(FDD_E_ARG, "dim must be 2 (got %d)", d->dim);
+  if (d->dim != 2 && d->dim != 3) return fail(FDD_E_ARG, "dim must be 2 or 3 (got %d)", d->dim);
+  if (d->dim == 3) {
+    if (!(d->K > 0) || !std::isfinite(d->K) || !(d->mu > 0) || !std::isfinite(d->mu))
+      return fail(FDD_E_ARG, "K and mu must be positive and finite");
+    fdd_problem_s* P = new (std::nothrow) fdd_problem_s();
+    if (!P) return fail(FDD_E_NOMEM, "out of host memory");
+    const int rc = setup3(d, hip_device, P);
+    if (rc) {
+      delete P;
+      return rc;
+    }
+    *out = P;
+    return FDD_OK;
+  }
   // the interface kernels hold one Gamma vector per workgroup in LDS: n - 1 <= 2047
   if (d->n < 4 || (d->n & 1) || d->n > 2048)
     return fail(FDD_E_ARG, "n must be even, 4 <= n <= 2048 (got %d)", d->n);
@@ -459,6 +472,10 @@ int fdd_problem_info(fdd_problem P, int64_t* N, int64_t* NI, int64_t* NG, double
 int fdd_workspace_bytes(fdd_problem P, const fdd_opts* o, size_t* bytes) {
   (void)o;
   if (!P || !bytes) return fail(FDD_E_ARG, "null argument");
+  if (P->dim == 3) {
+    *bytes = workspace3(P);
+    return FDD_OK;
+  }
   fdd_problem_s tmp = *P;
   *bytes = plan_workspace(&tmp, nullptr);
   return FDD_OK;
@@ -467,6 +484,7 @@ int fdd_workspace_bytes(fdd_problem P, const fdd_opts* o, size_t* bytes) {
 int fdd_bind_workspace(fdd_problem P, void* dev, size_t bytes, void* stream) {
   if (!P || !dev) return fail(FDD_E_ARG, "null argument");
   if (((uintptr_t)dev) & 255) return fail(FDD_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (P->dim == 3) return bind3(P, dev, bytes, (hipStream_t)stream);
   fdd_problem_s tmp = *P;
   const size_t need = plan_workspace(&tmp, nullptr);
   if (bytes < need) return fail(FDD_E_WORKSPACE, "workspace %zu bytes < %zu needed", bytes, need);
@@ -566,6 +584,7 @@ int fdd_interior_solve(fdd_problem P, const double* f, double* u, const fdd_opts
   use_schedule(P, o);
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
+  if (P->dim == 3) return interior_solve3(P, f, u, o, s, its);
   InnerTrack t;
   InnerResult res;
   rc = interior_solve(P, s, RhsDesc{f, 1.0, nullptr, 0.0}, o, t, &res);
@@ -583,6 +602,7 @@ int fdd_precond_apply(fdd_problem P, fdd_ratpc T, const double* r, double* z, vo
   if ((rc = check_table(P, T, FDD_RA_PRECOND))) return rc;
   if (!r || !z) return fail(FDD_E_ARG, "null vector");
   HIPCHK(hipSetDevice(P->device));
+  if (P->dim == 3) return precond_apply3(P, T, r, z, (hipStream_t)stream);
   ShiftTable tab = make_table(T);
   launch_iface_batch((hipStream_t)stream, (int)P->NG, P->h, tab, kIfacePrecond, r, z, P->scratchP,
                      P->st, nullptr, nullptr, 0, 0);
@@ -603,6 +623,7 @@ int fdd_schur_apply(fdd_problem P, fdd_ratpc H, const double* x, double* y, cons
   use_schedule(P, o);
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
+  if (P->dim == 3) return schur_apply3(P, H, x, y, o, s);
   InnerTrack t;
   InnerResult res;
   rc = interior_solve(P, s, RhsDesc{nullptr, 0.0, x, 1.0}, o, t, &res);
@@ -625,6 +646,7 @@ int fdd_apply_operator(fdd_problem P, fdd_ratpc H, const double* x, double* y, v
   if (!x || !y) return fail(FDD_E_ARG, "null vector");
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
+  if (P->dim == 3) return apply_operator3(P, H, x, y, s);
   ShiftTable tab = make_table(H);
   launch_iface_batch(s, (int)P->NG, P->h, tab, kIfaceOperator, x + P->NI, P->Hp, P->scratchH,
                      P->st, nullptr, nullptr, 0, 0);
@@ -720,6 +742,11 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   if (opts) o = *opts;
   else fdd_opts_default(&o);
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
+  if (P->dim == 3) {
+    if (o.warmstart) return fail(FDD_E_ARG, "3D solves take no warm start");
+    HIPCHK(hipSetDevice(P->device));
+    return solve3(P, PT, HT, b, x, o, (hipStream_t)stream, stats);
+  }
   if (o.warmstart && (rc = cnn_check_for((const fdd_cnn_s*)o.warmstart, P->n))) return rc;
   use_schedule(P, o);
   HIPCHK(hipSetDevice(P->device));
@@ -866,6 +893,7 @@ int fdd_get_kernel_timer(fdd_problem P, int64_t* launches, double* total_ms, int
 
 void fdd_destroy_problem(fdd_problem P) {
   if (!P) return;
+  destroy3(P);
   if (P->hook.ev) {
     for (int i = 0; i < 2 * P->hook.cap; ++i) (void)hipEventDestroy(P->hook.ev[i]);
     delete[] P->hook.ev;

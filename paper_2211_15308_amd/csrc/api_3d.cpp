@@ -1,0 +1,551 @@
+// Host orchestration of the 3D solver (dim = 3 problems of the C ABI): the unit cube with Kuhn
+// tetrahedra, Gamma the face z = 1.  The method is the 2D one (paper, Sec. 2): outer PCG on the
+// interface Schur complement, interior solves by multigrid-preconditioned CG, the rational
+// preconditioner and operator of eq. (RA).  In 3D every interior block is h L7 (L7 the 7-point
+// stencil), the Gamma row of the stiffness is h (3, -1/2 x 4 in the face, -1 below), and the
+// shifted interface systems are 2D face problems solved by batched CG (kernels_3d.hip).  All
+// arithmetic is FP64; the host synchronizes every few iterations to test convergence.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "api_internal.h"
+#include "k3_internal.h"
+
+using namespace fdd;
+
+struct Problem3D {
+  int n = 0, nf = 0, nlev = 0, nc = 0;
+  int lnf[kMaxLevels] = {};
+  double* u[kMaxLevels] = {};  // level iterates (level 0: z)
+  double* f[kMaxLevels] = {};  // level right-hand sides (level 0: r)
+  double* t[kMaxLevels] = {};  // level residual scratch
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *part0 = nullptr, *part1 = nullptr;
+  State3* st = nullptr;
+  int* stop = nullptr;
+  double* cinv = nullptr;
+  std::vector<double> cinv_h;
+  double* S = nullptr;  // DST-I matrix of the face, nf x nf
+  std::vector<double> S_h;
+  Shift3* tabs = nullptr;  // [0] preconditioner batch, [1] operator batch
+  FaceCG* cg = nullptr;
+  int* done = nullptr;
+  double *fpart0 = nullptr, *fpart1 = nullptr;
+  double *fy = nullptr, *fr = nullptr, *fp = nullptr, *fq = nullptr, *fz = nullptr, *ft = nullptr;
+  double *xG = nullptr, *rG = nullptr, *pG = nullptr, *zG = nullptr, *yG = nullptr, *Hp = nullptr;
+  double *ftmp = nullptr, *gpart = nullptr;
+  // pinned host mirrors
+  State3* hst = nullptr;
+  int* hstop = nullptr;
+  int* hdone = nullptr;
+  double* hpart = nullptr;
+  Shift3* htab = nullptr;
+  double* htol = nullptr;
+};
+
+namespace {
+
+constexpr double kFaceTolP = 1e-10;  // shifted solves of the preconditioner (steer the iteration)
+constexpr double kFaceTolH = 1e-13;  // shifted solves of the operator H (enter the solution)
+constexpr int kChunk3 = 4;           // iterations enqueued between convergence checks
+
+size_t vol(int nf) { return (size_t)(nf + 2) * (nf + 2) * (nf + 2); }
+
+size_t plan3(fdd_problem_s* P, char* base) {
+  Problem3D* Q = P->p3;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = align_up(off, 256);
+    char* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  const size_t v0 = vol(Q->nf);
+  for (int l = 1; l < Q->nlev; ++l) {
+    Q->u[l] = (double*)take(8 * vol(Q->lnf[l]));
+    Q->f[l] = (double*)take(8 * vol(Q->lnf[l]));
+    Q->t[l] = (double*)take(8 * vol(Q->lnf[l]));
+  }
+  Q->t[0] = (double*)take(8 * v0);
+  Q->x = (double*)take(8 * v0);
+  Q->r = (double*)take(8 * v0);
+  Q->z = (double*)take(8 * v0);
+  Q->p = (double*)take(8 * v0);
+  Q->q = (double*)take(8 * v0);
+  Q->u[0] = Q->z;
+  Q->f[0] = Q->r;
+  Q->part0 = (double*)take(8 * kPart3);
+  Q->part1 = (double*)take(8 * kPart3);
+  Q->st = (State3*)take(sizeof(State3));
+  Q->stop = (int*)take(sizeof(int));
+  const size_t nc3 = (size_t)Q->nc * Q->nc * Q->nc;
+  Q->cinv = (double*)take(8 * nc3 * nc3);
+  Q->S = (double*)take(8 * (size_t)Q->nf * Q->nf);
+  Q->tabs = (Shift3*)take(2 * sizeof(Shift3));
+  Q->cg = (FaceCG*)take(sizeof(FaceCG));
+  Q->done = (int*)take(sizeof(int) * kMaxSys3);
+  Q->fpart0 = (double*)take(8 * (size_t)kMaxSys3 * kPartF);
+  Q->fpart1 = (double*)take(8 * (size_t)kMaxSys3 * kPartF);
+  const size_t ng = (size_t)Q->nf * Q->nf;
+  for (double** v : {&Q->fy, &Q->fr, &Q->fp, &Q->fq, &Q->fz, &Q->ft})
+    *v = (double*)take(8 * ng * kMaxSys3);
+  for (double** v : {&Q->xG, &Q->rG, &Q->pG, &Q->zG, &Q->yG, &Q->Hp, &Q->ftmp})
+    *v = (double*)take(8 * ng);
+  Q->gpart = (double*)take(8 * 2 * kPart3);
+  return align_up(off, 256);
+}
+
+// exact inverse of L7 on an nc^3 grid (Gauss-Jordan with pivoting)
+std::vector<double> dense_inverse_7pt(int nc) {
+  const int np = nc * nc * nc;
+  std::vector<double> A((size_t)np * np, 0.0), X((size_t)np * np, 0.0);
+  auto id = [&](int i, int j, int k) { return (k * nc + j) * nc + i; };
+  for (int k = 0; k < nc; ++k)
+    for (int j = 0; j < nc; ++j)
+      for (int i = 0; i < nc; ++i) {
+        const int r = id(i, j, k);
+        A[(size_t)r * np + r] = 6.0;
+        if (i > 0) A[(size_t)r * np + id(i - 1, j, k)] = -1.0;
+        if (i < nc - 1) A[(size_t)r * np + id(i + 1, j, k)] = -1.0;
+        if (j > 0) A[(size_t)r * np + id(i, j - 1, k)] = -1.0;
+        if (j < nc - 1) A[(size_t)r * np + id(i, j + 1, k)] = -1.0;
+        if (k > 0) A[(size_t)r * np + id(i, j, k - 1)] = -1.0;
+        if (k < nc - 1) A[(size_t)r * np + id(i, j, k + 1)] = -1.0;
+        X[(size_t)r * np + r] = 1.0;
+      }
+  for (int c = 0; c < np; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < np; ++r)
+      if (std::fabs(A[(size_t)r * np + c]) > std::fabs(A[(size_t)piv * np + c])) piv = r;
+    if (piv != c)
+      for (int k = 0; k < np; ++k) {
+        std::swap(A[(size_t)c * np + k], A[(size_t)piv * np + k]);
+        std::swap(X[(size_t)c * np + k], X[(size_t)piv * np + k]);
+      }
+    const double d = 1.0 / A[(size_t)c * np + c];
+    for (int k = 0; k < np; ++k) {
+      A[(size_t)c * np + k] *= d;
+      X[(size_t)c * np + k] *= d;
+    }
+    for (int r = 0; r < np; ++r) {
+      if (r == c) continue;
+      const double fac = A[(size_t)r * np + c];
+      if (fac == 0.0) continue;
+      for (int k = 0; k < np; ++k) {
+        A[(size_t)r * np + k] -= fac * A[(size_t)c * np + k];
+        X[(size_t)r * np + k] -= fac * X[(size_t)c * np + k];
+      }
+    }
+  }
+  return X;
+}
+
+// V-cycle z = V r on the interior (nu red-black pairs per level)
+void vcycle3(Problem3D* Q, hipStream_t s, int nu) {
+  const int L = Q->nlev;
+  const int* stop = Q->stop;
+  for (int l = 0; l < L - 1; ++l) {
+    const int nf = Q->lnf[l];
+    k3_launch_rb(s, Q->u[l], Q->f[l], nf, 1, 1, stop);
+    for (int sw = 1; sw < 2 * nu; ++sw) k3_launch_rb(s, Q->u[l], Q->f[l], nf, (sw & 1) ? 0 : 1, 0, stop);
+    k3_launch_resid(s, Q->u[l], Q->f[l], Q->t[l], nf, stop);
+    k3_launch_restrict(s, Q->t[l], Q->f[l + 1], nf, Q->lnf[l + 1], stop);
+  }
+  k3_launch_coarse(s, Q->f[L - 1], Q->u[L - 1], Q->lnf[L - 1], Q->cinv, stop);
+  for (int l = L - 2; l >= 0; --l) {
+    const int nf = Q->lnf[l];
+    k3_launch_prolong(s, Q->u[l + 1], Q->u[l], nf, Q->lnf[l + 1], stop);
+    for (int sw = 0; sw < 2 * nu; ++sw) k3_launch_rb(s, Q->u[l], Q->f[l], nf, (sw & 1) ? 1 : 0, 0, stop);
+  }
+}
+
+int sync_state(Problem3D* Q, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(Q->hst, Q->st, sizeof(State3), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(Q->hstop, Q->stop, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return FDD_OK;
+}
+
+// L7 x = f (f from rhs), to ||f - L7 x|| <= tol ||f||; x stays in Q->x (padded)
+int interior3(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int maxit, int nu,
+              int* its) {
+  Problem3D* Q = P->p3;
+  const int nf = Q->nf;
+  k3_launch_rhs(s, rhs, Q->r, nf);
+  HIPCHK(hipMemsetAsync(Q->x, 0, 8 * vol(nf), s));
+  *Q->htol = tol * tol;
+  HIPCHK(hipMemcpyAsync(&Q->st->tol2, Q->htol, sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(Q->stop, 0, sizeof(int), s));
+  vcycle3(Q, s, nu);
+  k3_launch_dot(s, Q->r, Q->r, nf, Q->part0, nullptr);
+  k3_launch_dot(s, Q->r, Q->z, nf, Q->part1, nullptr);
+  k3_launch_scalars(s, Q->st, Q->part0, Q->part1, 0, Q->stop);
+  k3_launch_pupdate(s, Q->p, Q->z, nf, Q->st, 1, Q->stop);
+  int done = 0;
+  for (int it = 0; it < maxit; it += kChunk3) {
+    for (int c = 0; c < kChunk3; ++c) {
+      k3_launch_apply(s, Q->p, Q->q, nf, Q->part0, Q->stop);
+      k3_launch_scalars(s, Q->st, Q->part0, nullptr, 1, Q->stop);
+      k3_launch_update(s, Q->x, Q->r, Q->p, Q->q, nf, Q->st, Q->part0, Q->stop);
+      k3_launch_scalars(s, Q->st, Q->part0, nullptr, 2, Q->stop);
+      vcycle3(Q, s, nu);
+      k3_launch_dot(s, Q->r, Q->z, nf, Q->part0, Q->stop);
+      k3_launch_scalars(s, Q->st, Q->part0, nullptr, 3, Q->stop);
+      k3_launch_pupdate(s, Q->p, Q->z, nf, Q->st, 0, Q->stop);
+    }
+    HIPCHK(hipGetLastError());
+    int rc = sync_state(Q, s);
+    if (rc) return rc;
+    if (*Q->hstop) {
+      done = 1;
+      break;
+    }
+  }
+  if (!done) {
+    int rc = sync_state(Q, s);
+    if (rc) return rc;
+    done = *Q->hstop;
+  }
+  if (its) *its = Q->hst->its;
+  if (Q->hst->breakdown)
+    return fail(Q->hst->breakdown & 4 ? FDD_E_NONFINITE : FDD_E_BREAKDOWN,
+                "3D interior solve: breakdown (flags %d)", Q->hst->breakdown);
+  if (!done)
+    return fail(FDD_NOT_CONVERGED, "3D interior solve: %d iterations, residual %.3e of %.3e",
+                Q->hst->its, std::sqrt(Q->hst->rr), std::sqrt(Q->hst->ff));
+  return FDD_OK;
+}
+
+Shift3 table3(const fdd_ratpc_s* t) {
+  Shift3 T{};
+  const RaResult& r = t->r;
+  if (t->which == FDD_RA_PRECOND) {
+    T.m = r.m + 1;
+    T.alpha[0] = 0.0;
+    T.beta[0] = 1.0;
+    T.coef[0] = r.c0;
+    for (int k = 0; k < r.m; ++k) {
+      T.alpha[k + 1] = 1.0;
+      T.beta[k + 1] = r.p[k];
+      T.coef[k + 1] = r.c[k];
+    }
+  } else {
+    T.m = std::max(r.m, 1);
+    T.alpha[0] = 1.0;
+    T.beta[0] = 1.0;
+    T.coef[0] = 0.0;
+    for (int k = 0; k < r.m; ++k) {
+      T.alpha[k] = 1.0;
+      T.beta[k] = r.p[k];
+      T.coef[k] = r.c[k];
+    }
+    T.d0 = r.c0;
+  }
+  return T;
+}
+
+// preconditioner of the face systems: z = S D^{-1} S r (batched)
+void face_prec(Problem3D* Q, hipStream_t s, const double* r, double* z, int m, const Shift3* tab,
+               double h) {
+  const int nf = Q->nf;
+  kf_launch_dst(s, Q->S, r, Q->ft, nf, m, 1, Q->done);
+  kf_launch_dst(s, Q->S, Q->ft, z, nf, m, 0, Q->done);
+  kf_launch_diag(s, z, nf, Q->n, h, m, tab, Q->done);
+  kf_launch_dst(s, Q->S, z, Q->ft, nf, m, 1, Q->done);
+  kf_launch_dst(s, Q->S, Q->ft, z, nf, m, 0, Q->done);
+}
+
+// out = preconditioner (which 0) or H_RA (which 1) applied to `in` (face vectors)
+int face_batch(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* T, const double* in,
+               double* out) {
+  Problem3D* Q = P->p3;
+  const int nf = Q->nf;
+  const double h = 1.0 / Q->n;
+  const int which = T->which == FDD_RA_OPERATOR ? 1 : 0;
+  *Q->htab = table3(T);
+  const int m = Q->htab->m;
+  if (m > kMaxSys3) return fail(FDD_E_RA, "%d shifted systems exceed the batch limit %d", m, kMaxSys3);
+  const double d0 = Q->htab->d0;
+  Shift3* tab = Q->tabs + which;
+  HIPCHK(hipMemcpyAsync(tab, Q->htab, sizeof(Shift3), hipMemcpyHostToDevice, s));
+  const double tol = which ? kFaceTolH : kFaceTolP;
+  HIPCHK(hipMemsetAsync(Q->done, 0, sizeof(int) * kMaxSys3, s));
+  HIPCHK(hipMemsetAsync(Q->cg, 0, sizeof(FaceCG), s));
+  kf_launch_bcast(s, in, Q->fr, nf, h, m, which);
+  kf_launch_bcast(s, nullptr, Q->fy, nf, h, m, 0);
+  face_prec(Q, s, Q->fr, Q->fz, m, tab, h);
+  kf_launch_dot(s, Q->fr, Q->fr, nf, m, Q->fpart0, nullptr);
+  kf_launch_dot(s, Q->fr, Q->fz, nf, m, Q->fpart1, nullptr);
+  kf_launch_scalars(s, Q->cg, Q->fpart0, Q->fpart1, m, 0, Q->done, tol * tol);
+  kf_launch_axpy(s, nullptr, nullptr, Q->fp, nullptr, Q->fz, nf, m, Q->cg->beta, 1, 1, Q->done);
+  bool all = false;
+  for (int it = 0; it < 400 && !all; it += kChunk3) {
+    for (int c = 0; c < kChunk3; ++c) {
+      kf_launch_apply(s, Q->fp, 0, Q->fq, nf, h, m, tab, Q->fpart0, Q->done);
+      kf_launch_scalars(s, Q->cg, Q->fpart0, nullptr, m, 1, Q->done, tol * tol);
+      kf_launch_axpy(s, Q->fy, Q->fr, Q->fp, Q->fq, nullptr, nf, m, Q->cg->alpha, 0, 0, Q->done);
+      kf_launch_dot(s, Q->fr, Q->fr, nf, m, Q->fpart0, Q->done);
+      kf_launch_scalars(s, Q->cg, Q->fpart0, nullptr, m, 2, Q->done, tol * tol);
+      face_prec(Q, s, Q->fr, Q->fz, m, tab, h);
+      kf_launch_dot(s, Q->fr, Q->fz, nf, m, Q->fpart0, Q->done);
+      kf_launch_scalars(s, Q->cg, Q->fpart0, nullptr, m, 3, Q->done, tol * tol);
+      kf_launch_axpy(s, nullptr, nullptr, Q->fp, nullptr, Q->fz, nf, m, Q->cg->beta, 1, 0, Q->done);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(Q->hdone, Q->done, sizeof(int) * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    all = true;
+    for (int k = 0; k < m; ++k) all = all && Q->hdone[k];
+  }
+  if (!all) return fail(FDD_NOT_CONVERGED, "3D face solves did not converge");
+  kf_launch_combine(s, Q->fy, m, nf, h, tab, which, in, Q->ftmp, out, d0);
+  HIPCHK(hipGetLastError());
+  return FDD_OK;
+}
+
+double face_dot(Problem3D* Q, hipStream_t s, const double* a, const double* b, int* rc) {
+  const int64_t N = (int64_t)Q->nf * Q->nf;
+  kf_launch_vdot(s, a, b, N, Q->gpart);
+  if (hipMemcpyAsync(Q->hpart, Q->gpart, 8 * kPart3, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    *rc = fail(FDD_E_HIP, "device read-back failed");
+    return 0.0;
+  }
+  double t = 0.0;
+  for (int k = 0; k < kPart3; ++k) t += Q->hpart[k];
+  return t;
+}
+
+// y = S p (Schur complement with H_RA); u = L7^{-1} lift(p) is left in Q->x
+int schur3(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* HT, const double* p, double* y,
+           const fdd_opts& o, int* its, double* pq) {
+  Problem3D* Q = P->p3;
+  int rc = interior3(P, s, Rhs3{nullptr, 0.0, p, 1.0}, o.inner_rtol, o.inner_maxit, o.mg_nu, its);
+  if (rc) return rc;
+  if ((rc = face_batch(P, s, HT, p, Q->Hp))) return rc;
+  kf_launch_schur(s, p, Q->x, Q->nf, 1.0 / Q->n, P->K, P->gamma, Q->Hp, y, Q->gpart);
+  HIPCHK(hipGetLastError());
+  if (pq) {
+    HIPCHK(hipMemcpyAsync(Q->hpart, Q->gpart, 8 * kPart3, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double t = 0.0;
+    for (int k = 0; k < kPart3; ++k) t += Q->hpart[k];
+    *pq = t;
+  }
+  return FDD_OK;
+}
+
+}  // namespace
+
+namespace fdd {
+
+int setup3(const fdd_desc* d, int hip_device, fdd_problem_s* P) {
+  const int n = d->n;
+  if (n < 4 || (n & 1) || n > 256)
+    return fail(FDD_E_ARG, "3D: n must be even, 4 <= n <= 256 (got %d)", n);
+  Problem3D* Q = new (std::nothrow) Problem3D();
+  if (!Q) return fail(FDD_E_NOMEM, "out of host memory");
+  Q->n = n;
+  Q->nf = n - 1;
+  int nf = n - 1, l = 0;
+  while (true) {
+    Q->lnf[l] = nf;
+    if (!(nf & 1) || nf <= 3) break;
+    nf = (nf - 1) / 2;
+    if (++l >= kMaxLevels) {
+      delete Q;
+      return fail(FDD_E_ARG, "too many multigrid levels");
+    }
+  }
+  Q->nlev = l + 1;
+  Q->nc = Q->lnf[l];
+  if (Q->nc > 4) {
+    delete Q;
+    return fail(FDD_E_ARG, "3D: n = %d leaves a %d^3 coarsest grid (max 4^3)", n, Q->nc);
+  }
+  Q->cinv_h = dense_inverse_7pt(Q->nc);
+  const int m = Q->nf;
+  Q->S_h.resize((size_t)m * m);
+  for (int a = 0; a < m; ++a)
+    for (int b = 0; b < m; ++b)
+      Q->S_h[(size_t)a * m + b] = std::sqrt(2.0 / n) * std::sin(M_PI * (a + 1) * (b + 1) / n);
+  P->p3 = Q;
+  P->dim = 3;
+  P->n = n;
+  P->device = hip_device;
+  P->K = d->K;
+  P->mu = d->mu;
+  P->gamma = 1.0 / d->mu;
+  P->h = 1.0 / n;
+  P->N = (int64_t)m * m * n;
+  P->NI = (int64_t)m * m * m;
+  P->NG = (int64_t)m * m;
+  // rigorous enclosure of the face spectrum: conforming P1 eigenvalues lie above the continuous
+  // ones (2 pi^2 on the unit square), and the element bound gives at most 36 / h^2
+  P->lam_lo = 2.0 * M_PI * M_PI;
+  P->lam_hi = 36.0 * n * (double)n;
+  return FDD_OK;
+}
+
+size_t workspace3(fdd_problem_s* P) {
+  Problem3D tmp = *P->p3;
+  fdd_problem_s pt = *P;
+  pt.p3 = &tmp;
+  return plan3(&pt, nullptr);
+}
+
+int bind3(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s) {
+  Problem3D* Q = P->p3;
+  const size_t need = workspace3(P);
+  if (bytes < need) return fail(FDD_E_WORKSPACE, "workspace %zu bytes < %zu needed", bytes, need);
+  HIPCHK(hipSetDevice(P->device));
+  P->ws = (char*)dev;
+  P->ws_bytes = bytes;
+  plan3(P, P->ws);
+  if (!Q->hst) {
+    HIPCHK(hipHostMalloc((void**)&Q->hst, sizeof(State3), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&Q->hstop, sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&Q->hdone, sizeof(int) * kMaxSys3, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&Q->hpart, 8 * 2 * kPart3, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&Q->htab, sizeof(Shift3), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&Q->htol, sizeof(double), hipHostMallocDefault));
+  }
+  HIPCHK(hipMemsetAsync(P->ws, 0, need, s));
+  HIPCHK(hipMemcpyAsync(Q->cinv, Q->cinv_h.data(), 8 * Q->cinv_h.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(Q->S, Q->S_h.data(), 8 * Q->S_h.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return FDD_OK;
+}
+
+void destroy3(fdd_problem_s* P) {
+  Problem3D* Q = P->p3;
+  if (!Q) return;
+  for (void* h : {(void*)Q->hst, (void*)Q->hstop, (void*)Q->hdone, (void*)Q->hpart,
+                  (void*)Q->htab, (void*)Q->htol})
+    if (h) (void)hipHostFree(h);
+  delete Q;
+  P->p3 = nullptr;
+}
+
+int interior_solve3(fdd_problem_s* P, const double* f, double* u, const fdd_opts& o, hipStream_t s,
+                    int* its) {
+  Problem3D* Q = P->p3;
+  // A_II u = f with A_II = h L7
+  int rc = interior3(P, s, Rhs3{f, 1.0 / P->h, nullptr, 0.0}, o.inner_rtol, o.inner_maxit, o.mg_nu,
+                     its);
+  if (rc < 0) return rc;
+  k3_launch_gather(s, Q->x, Q->nf, u, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return rc;
+}
+
+int precond_apply3(fdd_problem_s* P, const fdd_ratpc_s* T, const double* r, double* z,
+                   hipStream_t s) {
+  return face_batch(P, s, T, r, z);
+}
+
+int schur_apply3(fdd_problem_s* P, const fdd_ratpc_s* H, const double* x, double* y,
+                 const fdd_opts& o, hipStream_t s) {
+  int rc = schur3(P, s, H, x, y, o, nullptr, nullptr);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(s));
+  return FDD_OK;
+}
+
+int apply_operator3(fdd_problem_s* P, const fdd_ratpc_s* H, const double* x, double* y,
+                    hipStream_t s) {
+  Problem3D* Q = P->p3;
+  int rc = face_batch(P, s, H, x + P->NI, Q->Hp);
+  if (rc) return rc;
+  k3_launch_full_operator(s, P->n, P->K, P->gamma, x, Q->Hp, y, nullptr, nullptr);
+  HIPCHK(hipGetLastError());
+  return FDD_OK;
+}
+
+int solve3(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, const double* b,
+           double* x, const fdd_opts& o, hipStream_t s, fdd_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  Problem3D* Q = P->p3;
+  fdd_stats st{};
+  st.true_rel_res = -1.0;
+  const int nf = Q->nf;
+  const int64_t NG = P->NG;
+  const double h = P->h;
+  auto finish = [&](int code) {
+    st.status = code;
+    st.t_solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return code;
+  };
+  auto inner = [&](const Rhs3& rhs) {
+    int its = 0;
+    int rc = interior3(P, s, rhs, o.inner_rtol, o.inner_maxit, o.mg_nu, &its);
+    st.inner_solves += 1;
+    st.inner_its_total += its;
+    st.inner_its_max = std::max(st.inner_its_max, its);
+    return rc;
+  };
+  // 1. g = b_G - A_GI A_II^{-1} b_I = b_G + h w|plane nf,  w = L7^{-1} (b_I / h)
+  int rc = inner(Rhs3{b, 1.0 / h, nullptr, 0.0});
+  if (rc) return finish(rc);
+  kf_launch_rhs_reduce(s, b + P->NI, Q->x, nf, h, Q->rG, Q->xG);
+  // 2. outer PCG from x_G = 0
+  if ((rc = face_batch(P, s, PT, Q->rG, Q->zG))) return finish(rc);
+  const double rho0 = face_dot(Q, s, Q->rG, Q->zG, &rc);
+  if (rc) return finish(rc);
+  if (!(rho0 >= 0.0)) return finish(fail(FDD_E_BREAKDOWN, "preconditioner not positive"));
+  HIPCHK(hipMemcpyAsync(Q->pG, Q->zG, 8 * NG, hipMemcpyDeviceToDevice, s));
+  double rho = rho0;
+  bool conv = !(rho0 > 0.0);
+  while (!conv && st.outer_its < o.outer_maxit) {
+    double pq = 0.0;
+    int its = 0;
+    rc = schur3(P, s, HT, Q->pG, Q->yG, o, &its, &pq);
+    st.inner_solves += 1;
+    st.inner_its_total += its;
+    st.inner_its_max = std::max(st.inner_its_max, its);
+    if (rc) return finish(rc);
+    if (!(pq > 0.0) || !std::isfinite(pq))
+      return finish(fail(std::isfinite(pq) ? FDD_E_BREAKDOWN : FDD_E_NONFINITE,
+                         "3D outer PCG breakdown (p.Sp = %g)", pq));
+    const double alpha = rho / pq;
+    kf_launch_outer_axpy(s, Q->xG, Q->rG, Q->pG, Q->yG, nullptr, NG, alpha);
+    if ((rc = face_batch(P, s, PT, Q->rG, Q->zG))) return finish(rc);
+    const double rho_new = face_dot(Q, s, Q->rG, Q->zG, &rc);
+    if (rc) return finish(rc);
+    ++st.outer_its;
+    if (!(rho_new >= 0.0)) return finish(fail(FDD_E_BREAKDOWN, "3D outer r.z < 0"));
+    conv = std::sqrt(rho_new) <= o.outer_rtol * std::sqrt(rho0);
+    const double beta = rho_new / rho;
+    rho = rho_new;
+    if (!conv) kf_launch_outer_axpy(s, nullptr, nullptr, Q->pG, nullptr, Q->zG, NG, beta);
+  }
+  st.rel_precond_res = rho0 > 0 ? std::sqrt(std::max(rho, 0.0) / rho0) : 0.0;
+  // 3. x_I = A_II^{-1} (b_I / K - A_IG x_G) = L7^{-1} (b_I / (K h) + lift(x_G))
+  if ((rc = inner(Rhs3{b, 1.0 / (P->K * h), Q->xG, 1.0}))) return finish(rc);
+  k3_launch_gather(s, Q->x, nf, x, Q->xG);
+  if (o.check_true_residual) {
+    if ((rc = face_batch(P, s, HT, x + P->NI, Q->Hp))) return finish(rc);
+    k3_launch_full_operator(s, P->n, P->K, P->gamma, x, Q->Hp, nullptr, b, Q->gpart);
+    HIPCHK(hipMemcpyAsync(Q->hpart, Q->gpart, 8 * 2 * kPart3, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  if (o.check_true_residual) {
+    double e2 = 0.0, b2 = 0.0;
+    for (int k = 0; k < kPart3; ++k) {
+      e2 += Q->hpart[2 * k];
+      b2 += Q->hpart[2 * k + 1];
+    }
+    if (b2 > 0) st.true_rel_res = std::sqrt(e2 / b2);
+  }
+  return finish(conv ? FDD_OK : FDD_NOT_CONVERGED);
+}
+
+}  // namespace fdd

@@ -62,6 +62,8 @@ using fdd::RaResult;
 using fdd::Reductions;
 using fdd::kMaxLevels;
 
+struct Problem3D;  // the 3D solver's state (api_3d.cpp)
+
 struct fdd_problem_s {
   int dim = 2, n = 0, device = 0;
   double K = 1, mu = 1, gamma = 1, h = 1;
@@ -90,6 +92,7 @@ struct fdd_problem_s {
   double* yG = nullptr;
   double* Hp = nullptr;
   double* lk_lmu = nullptr;     // {log10 K, log10 mu} for the warm-start network
+  Problem3D* p3 = nullptr;      // dim = 3: everything of the 3D path
   double* scratchP = nullptr;
   double* scratchH = nullptr;
   DevState* host_st = nullptr;  // pinned copy
@@ -122,6 +125,21 @@ namespace fdd {
 ShiftTable make_table(const fdd_ratpc_s* t);
 bool opts_ok(const fdd_opts* o);
 double step_tau(const fdd_opts& o);
+// the 3D path (api_3d.cpp)
+int setup3(const fdd_desc* d, int hip_device, fdd_problem_s* P);
+size_t workspace3(fdd_problem_s* P);
+int bind3(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s);
+void destroy3(fdd_problem_s* P);
+int interior_solve3(fdd_problem_s* P, const double* f, double* u, const fdd_opts& o, hipStream_t s,
+                    int* its);
+int precond_apply3(fdd_problem_s* P, const fdd_ratpc_s* T, const double* r, double* z,
+                   hipStream_t s);
+int schur_apply3(fdd_problem_s* P, const fdd_ratpc_s* H, const double* x, double* y,
+                 const fdd_opts& o, hipStream_t s);
+int apply_operator3(fdd_problem_s* P, const fdd_ratpc_s* H, const double* x, double* y,
+                    hipStream_t s);
+int solve3(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, const double* b,
+           double* x, const fdd_opts& o, hipStream_t s, fdd_stats* stats);
 // warm-start network (api_cnn.cpp)
 int cnn_check_for(const fdd_cnn_s* C, int n);
 int cnn_warm_guess(fdd_cnn_s* C, hipStream_t s, const double* trace, int n, const double* lk_lmu,

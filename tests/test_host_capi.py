@@ -129,3 +129,19 @@ def test_batch_create_validates_without_device(lib):
     # empty batch
     assert lib.fdd_batch_create(0, arr(P.h), arr(T.h), arr(H.h), ctypes.byref(h)) == F.FDD_E_ARG
     assert lib.fdd_solve_batched(None, None, None, None, None, None) == F.FDD_E_ARG
+
+
+def test_setup_3d_sizes_bounds_and_validation():
+    import math
+    P = F.setup_mesh(16, 1.0, 1.0, dim=3)
+    assert (P.N, P.NI, P.NG) == (15 * 15 * 16, 15 ** 3, 15 * 15)
+    # rigorous enclosure of the face spectrum (oracle: the dense GEVP at this size)
+    from oracle import spectral
+    lo, hi = spectral.spectral_interval(3, 16)
+    assert P.lam_lo <= lo and hi <= P.lam_hi
+    assert P.lam_lo == pytest.approx(2 * math.pi ** 2)
+    for bad in (7, 18, 2):  # odd; coarsest grid 8^3; too small
+        with pytest.raises(F.FddError):
+            F.setup_mesh(bad, 1.0, 1.0, dim=3)
+    T = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-10)
+    assert T.query()["max_rel_err"] <= 1e-9
