@@ -34,7 +34,9 @@ def parse():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--nu", type=int, default=1, help="red-black sweep pairs per level")
+    ap.add_argument("--nu", type=int, default=2,
+                    help="red-black sweep pairs per level (2: the autotuner's choice on MI355X for "
+                         "this workload, see paper_2211_15308_amd.autotune.tune_solves)")
     ap.add_argument("--inner-rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -52,6 +54,9 @@ def parse():
     ap.add_argument("--learned", choices=["auto", "none", "only"], default="auto",
                     help="run the learned-warm-start comparison (auto: if weights exist)")
     ap.add_argument("--learned-steps", type=int, default=6)
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D cases")
+    ap.add_argument("--cnn-only", action="store_true", help="only time the warm-start network kernels")
+    ap.add_argument("--only-3d", action="store_true")
     ap.add_argument("--only-batched", action="store_true",
                     help="skip the headline single-problem run (for profiling the batched kernels)")
     return ap.parse_args()
@@ -94,16 +99,15 @@ DOWN0_BYTES_K = DOWN0_BYTES_K0 + 4 * 3
 HBM_PEAK_GBS = 8000.0
 
 
-def traffic_from_profile(root):
+def traffic_from_profile(root, nu):
     """HBM bytes per launch from the committed PMC summary, if it matches the current kernel."""
-    import hashlib
     path = os.path.join(root, "profiles", "down0_traffic.json")
     try:
         rec = json.load(open(path))
         sha = kernel_source_sha(root)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sources_sha256") != sha:
+    if rec.get("kernel_sources_sha256") != sha or rec.get("kernel") != f"void fdd::k_mg_down<float, {nu}, true>":
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -290,6 +294,37 @@ def run_learned(F, args, sizes=(256, 512, 1024), mus=(1e-3, 1.0)):
     return res
 
 
+def run_3d(F, args, sizes=(32, 64, 128), mus=(1e-4, 1.0, 1e2), reps=2):
+    """3D unit cube (Kuhn tetrahedra), Gamma = top face, K = 1: solves/s per (n, mu), FP64."""
+    import torch
+
+    import workloads
+    out = []
+    for n in sizes:
+        for ci, mu in enumerate(mus):
+            P = F.setup_mesh(n, 1.0, mu, dim=3)
+            P.bind_workspace()
+            TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+            TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+            b = torch.as_tensor(workloads.rhs(3, n, 3000 + len(out)), dtype=torch.float64, device="cuda")
+            x = torch.zeros_like(b)
+            opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol)
+            st = P.solve(TP, TH, b, x, opts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                st = P.solve(TP, TH, b, x, opts)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / reps
+            chk = P.solve(TP, TH, b, x, F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol,
+                                                        check_true_residual=1))
+            out.append({"n": n, "K": 1.0, "mu": mu, "dofs": P.N, "solves_per_s": 1.0 / el,
+                        "outer_its": st["outer_its"], "inner_its": st["inner_its_total"],
+                        "poles_P": TP.query()["m"], "poles_H": TH.query()["m"],
+                        "true_rel_res": chk["true_rel_res"]})
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -308,6 +343,14 @@ def main():
     opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, precision=prec,
                           mg_nu=args.nu, use_graph=0 if args.eager else 1)
     case_list = cases(args)
+    if args.cnn_only:
+        from paper_2211_15308_amd import train_warmstart
+        th, _ = train_warmstart.load_weights(args.weights or train_warmstart.DEFAULT_OUT)
+        print(json.dumps({"network": cnn_timing(F, torch.as_tensor(th, device="cuda"))}))
+        return
+    if args.only_3d:
+        print(json.dumps({"three_d": run_3d(F, args)}))
+        return
     if args.learned == "only":
         print(json.dumps({"learned": run_learned(F, args)}))
         return
@@ -381,10 +424,10 @@ def main():
     # run had converged); their algorithmic bytes over their own time is the achieved rate
     alg_bytes = ni * elem / 4 * (DOWN0_BYTES_K * (its - runs) + DOWN0_BYTES_K0 * runs)
     achieved = alg_bytes / (long_ms * 1e-3) / 1e9 if long_ms > 0 else 0.0
-    traffic = traffic_from_profile(ROOT) if prec == F.FDD_MIXED and args.n == 1024 else None
+    traffic = traffic_from_profile(ROOT, args.nu) if prec == F.FDD_MIXED and args.n == 1024 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_mg_down<float,1,true> (finest level, PCG update fused)",
+                "kernel": f"k_mg_down<float,{args.nu},true> (finest level, PCG update fused)",
                 "launches": launches, "avg_launch_us": 1e3 * tot_ms / max(launches, 1),
                 "working_launches": its, "timed_long_launches": long_n,
                 "avg_working_launch_us": 1e3 * long_ms / max(long_n, 1),
@@ -431,6 +474,8 @@ def main():
     out.update(batched)
     if args.learned == "auto":
         out["learned"] = run_learned(F, args)
+    if not args.no_3d:
+        out["three_d"] = run_3d(F, args)
     print(json.dumps(out))
 
 

@@ -1,7 +1,7 @@
-"""Autotuner of the batched solve.
+"""Autotuner of the launch schedule (batched and single-problem solves).
 
 Two launch-schedule parameters trade work against launches and are chosen by timing the
-caller's own batch on the device:
+caller's own workload on the device:
 
   * mg_nu      -- red-black sweep pairs per level in the multigrid V-cycle (1 or 2): more
                   smoothing per V-cycle, fewer PCG iterations;
@@ -9,9 +9,9 @@ caller's own batch on the device:
                   refinement (1e-4, 1e-5, 1e-6): fewer, longer runs or more, shorter ones.
 
 Every candidate is run once untimed (it measures its launch schedule and captures its graphs),
-then timed over `reps` solves; the fastest wins.  Choices are cached as JSON keyed by the
-workload signature (the sorted (n, log10 K, log10 mu) of the instances), the arithmetic
-(mixed) and the GPU architecture, so a repeated workload is not timed again.
+then timed; the fastest wins.  Choices are cached as JSON keyed by the workload signature (the
+sorted (n, log10 K, log10 mu) of the instances), the kind of solve, the arithmetic (mixed) and the
+GPU architecture, so a repeated workload is not timed again.
 """
 import hashlib
 import json
@@ -97,3 +97,36 @@ def _with(F, opts, nu, tau):
     o.mg_nu = nu
     o.step_rtol = tau
     return o
+
+
+def tune_solves(cases, base_opts=None, reps=1, cache_path=None, candidates=CANDIDATES, force=False):
+    """The same choice for single-problem solves: cases = [(problem, P table, H table, b, x)], timed
+    over one pass through all cases per candidate.  Returns (opts, record)."""
+    import torch
+
+    from . import fdd as F
+    opts = base_opts or F.opts_default()
+    key = "|".join(["solve", signature([c[0] for c in cases]), "mixed", arch(),
+                    f"rtol={opts.outer_rtol:g}", f"inner={opts.inner_rtol:g}"])
+    path = cache_path or default_cache_path()
+    table = _load(path)
+    if key in table and not force:
+        rec = dict(table[key], cached=True)
+        return _with(F, opts, rec["mg_nu"], rec["step_rtol"]), rec
+    timings = {}
+    for nu, tau in candidates:
+        o = _with(F, opts, nu, tau)
+        for P, TP, TH, b, x in cases:
+            P.solve(TP, TH, b, x, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for P, TP, TH, b, x in cases:
+                P.solve(TP, TH, b, x, o)
+        torch.cuda.synchronize()
+        timings[f"nu={nu},tau={tau:g}"] = 1e3 * (time.perf_counter() - t0) / (reps * len(cases))
+    best = min(candidates, key=lambda c: timings[f"nu={c[0]},tau={c[1]:g}"])
+    rec = {"key": key, "mg_nu": best[0], "step_rtol": best[1], "ms_per_solve": timings}
+    table[key] = rec
+    _store(path, table)
+    return _with(F, opts, best[0], best[1]), dict(rec, cached=False)

@@ -45,6 +45,12 @@ struct Problem3D {
   double* hpart = nullptr;
   Shift3* htab = nullptr;
   double* htol = nullptr;
+  // captured chunks of Krylov iterations (replayed on the library stream)
+  hipGraphExec_t g_inner = nullptr;
+  int g_inner_nu = 0;
+  hipGraphExec_t g_face[2] = {nullptr, nullptr};
+  int g_face_m[2] = {0, 0};
+  bool use_graph = true;
 };
 
 namespace {
@@ -170,6 +176,20 @@ int sync_state(Problem3D* Q, hipStream_t s) {
   return FDD_OK;
 }
 
+// Captures the launches of fn on s into an executable graph.
+template <typename Fn>
+int capture(hipStream_t s, Fn fn, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  fn();
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess) return fail(FDD_E_HIP, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(FDD_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+  return FDD_OK;
+}
+
 // L7 x = f (f from rhs), to ||f - L7 x|| <= tol ||f||; x stays in Q->x (padded)
 int interior3(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int maxit, int nu,
               int* its) {
@@ -186,7 +206,7 @@ int interior3(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int 
   k3_launch_scalars(s, Q->st, Q->part0, Q->part1, 0, Q->stop);
   k3_launch_pupdate(s, Q->p, Q->z, nf, Q->st, 1, Q->stop);
   int done = 0;
-  for (int it = 0; it < maxit; it += kChunk3) {
+  auto chunk = [&]() {
     for (int c = 0; c < kChunk3; ++c) {
       k3_launch_apply(s, Q->p, Q->q, nf, Q->part0, Q->stop);
       k3_launch_scalars(s, Q->st, Q->part0, nullptr, 1, Q->stop);
@@ -197,6 +217,17 @@ int interior3(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int 
       k3_launch_scalars(s, Q->st, Q->part0, nullptr, 3, Q->stop);
       k3_launch_pupdate(s, Q->p, Q->z, nf, Q->st, 0, Q->stop);
     }
+  };
+  if (Q->use_graph && (!Q->g_inner || Q->g_inner_nu != nu)) {
+    if (Q->g_inner) (void)hipGraphExecDestroy(Q->g_inner);
+    Q->g_inner = nullptr;
+    int rc = capture(s, chunk, &Q->g_inner);
+    if (rc) return rc;
+    Q->g_inner_nu = nu;
+  }
+  for (int it = 0; it < maxit; it += kChunk3) {
+    if (Q->use_graph) HIPCHK(hipGraphLaunch(Q->g_inner, s));
+    else chunk();
     HIPCHK(hipGetLastError());
     int rc = sync_state(Q, s);
     if (rc) return rc;
@@ -283,7 +314,7 @@ int face_batch(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* T, const doub
   kf_launch_scalars(s, Q->cg, Q->fpart0, Q->fpart1, m, 0, Q->done, tol * tol);
   kf_launch_axpy(s, nullptr, nullptr, Q->fp, nullptr, Q->fz, nf, m, Q->cg->beta, 1, 1, Q->done);
   bool all = false;
-  for (int it = 0; it < 400 && !all; it += kChunk3) {
+  auto chunk = [&]() {
     for (int c = 0; c < kChunk3; ++c) {
       kf_launch_apply(s, Q->fp, 0, Q->fq, nf, h, m, tab, Q->fpart0, Q->done);
       kf_launch_scalars(s, Q->cg, Q->fpart0, nullptr, m, 1, Q->done, tol * tol);
@@ -295,6 +326,17 @@ int face_batch(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* T, const doub
       kf_launch_scalars(s, Q->cg, Q->fpart0, nullptr, m, 3, Q->done, tol * tol);
       kf_launch_axpy(s, nullptr, nullptr, Q->fp, nullptr, Q->fz, nf, m, Q->cg->beta, 1, 0, Q->done);
     }
+  };
+  if (Q->use_graph && (!Q->g_face[which] || Q->g_face_m[which] != m)) {
+    if (Q->g_face[which]) (void)hipGraphExecDestroy(Q->g_face[which]);
+    Q->g_face[which] = nullptr;
+    int rc = capture(s, chunk, &Q->g_face[which]);
+    if (rc) return rc;
+    Q->g_face_m[which] = m;
+  }
+  for (int it = 0; it < 400 && !all; it += kChunk3) {
+    if (Q->use_graph) HIPCHK(hipGraphLaunch(Q->g_face[which], s));
+    else chunk();
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(Q->hdone, Q->done, sizeof(int) * m, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -338,6 +380,35 @@ int schur3(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* HT, const double*
   }
   return FDD_OK;
 }
+
+// The 3D work runs on the problem's own stream (graphs cannot be captured on the legacy default
+// stream), ordered after the caller's stream on entry and before it on exit.
+struct LibStream {
+  fdd_problem_s* P;
+  hipStream_t user, s;
+  int rc = FDD_OK;
+  LibStream(fdd_problem_s* P_, hipStream_t us) : P(P_), user(us), s(us) {
+    if (!P->gstream) {
+      if (hipStreamCreateWithFlags(&P->gstream, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&P->ev_out, hipEventDisableTiming) != hipSuccess) {
+        rc = fail(FDD_E_HIP, "stream creation failed");
+        return;
+      }
+    }
+    if (hipEventRecord(P->ev_in, us) != hipSuccess || hipStreamWaitEvent(P->gstream, P->ev_in, 0) != hipSuccess) {
+      rc = fail(FDD_E_HIP, "stream ordering failed");
+      return;
+    }
+    s = P->gstream;
+  }
+  ~LibStream() {
+    if (s != user) {
+      (void)hipEventRecord(P->ev_out, s);
+      (void)hipStreamWaitEvent(user, P->ev_out, 0);
+    }
+  }
+};
 
 }  // namespace
 
@@ -427,13 +498,20 @@ void destroy3(fdd_problem_s* P) {
   for (void* h : {(void*)Q->hst, (void*)Q->hstop, (void*)Q->hdone, (void*)Q->hpart,
                   (void*)Q->htab, (void*)Q->htol})
     if (h) (void)hipHostFree(h);
+  if (Q->g_inner) (void)hipGraphExecDestroy(Q->g_inner);
+  for (auto g : Q->g_face)
+    if (g) (void)hipGraphExecDestroy(g);
   delete Q;
   P->p3 = nullptr;
 }
 
-int interior_solve3(fdd_problem_s* P, const double* f, double* u, const fdd_opts& o, hipStream_t s,
+int interior_solve3(fdd_problem_s* P, const double* f, double* u, const fdd_opts& o, hipStream_t us,
                     int* its) {
   Problem3D* Q = P->p3;
+  LibStream ls(P, us);
+  if (ls.rc) return ls.rc;
+  const hipStream_t s = ls.s;
+  Q->use_graph = o.use_graph != 0;
   // A_II u = f with A_II = h L7
   int rc = interior3(P, s, Rhs3{f, 1.0 / P->h, nullptr, 0.0}, o.inner_rtol, o.inner_maxit, o.mg_nu,
                      its);
@@ -445,12 +523,18 @@ int interior_solve3(fdd_problem_s* P, const double* f, double* u, const fdd_opts
 }
 
 int precond_apply3(fdd_problem_s* P, const fdd_ratpc_s* T, const double* r, double* z,
-                   hipStream_t s) {
-  return face_batch(P, s, T, r, z);
+                   hipStream_t us) {
+  LibStream ls(P, us);
+  if (ls.rc) return ls.rc;
+  return face_batch(P, ls.s, T, r, z);
 }
 
 int schur_apply3(fdd_problem_s* P, const fdd_ratpc_s* H, const double* x, double* y,
-                 const fdd_opts& o, hipStream_t s) {
+                 const fdd_opts& o, hipStream_t us) {
+  LibStream ls(P, us);
+  if (ls.rc) return ls.rc;
+  const hipStream_t s = ls.s;
+  P->p3->use_graph = o.use_graph != 0;
   int rc = schur3(P, s, H, x, y, o, nullptr, nullptr);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(s));
@@ -458,8 +542,11 @@ int schur_apply3(fdd_problem_s* P, const fdd_ratpc_s* H, const double* x, double
 }
 
 int apply_operator3(fdd_problem_s* P, const fdd_ratpc_s* H, const double* x, double* y,
-                    hipStream_t s) {
+                    hipStream_t us) {
   Problem3D* Q = P->p3;
+  LibStream ls(P, us);
+  if (ls.rc) return ls.rc;
+  const hipStream_t s = ls.s;
   int rc = face_batch(P, s, H, x + P->NI, Q->Hp);
   if (rc) return rc;
   k3_launch_full_operator(s, P->n, P->K, P->gamma, x, Q->Hp, y, nullptr, nullptr);
@@ -468,9 +555,13 @@ int apply_operator3(fdd_problem_s* P, const fdd_ratpc_s* H, const double* x, dou
 }
 
 int solve3(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, const double* b,
-           double* x, const fdd_opts& o, hipStream_t s, fdd_stats* stats) {
+           double* x, const fdd_opts& o, hipStream_t us, fdd_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
   Problem3D* Q = P->p3;
+  LibStream ls(P, us);
+  if (ls.rc) return ls.rc;
+  const hipStream_t s = ls.s;
+  Q->use_graph = o.use_graph != 0;
   fdd_stats st{};
   st.true_rel_res = -1.0;
   const int nf = Q->nf;

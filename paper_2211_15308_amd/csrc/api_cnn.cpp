@@ -25,6 +25,7 @@ struct fdd_cnn_s {
   __bf16* dZ[2] = {};           // data-gradient ping-pong
   float* part = nullptr;        // weight-gradient block partials
   float* dbpart = nullptr;
+  float* stage = nullptr;       // two-pass gradient reduction
   double* lpart = nullptr;
   double* loss = nullptr;
   double* scale = nullptr;
@@ -60,6 +61,7 @@ size_t plan_cnn(fdd_cnn_s* C, char* base) {
     C->dZ[1] = (__bf16*)take(2 * BP * kCnnHidden);
     C->part = (float*)take(sizeof(float) * (size_t)C->dw_blocks_max * 9 * 1024);
     C->dbpart = (float*)take(sizeof(float) * (size_t)C->dw_blocks_max * 32);
+    C->stage = (float*)take(sizeof(float) * kCnnGradStage);
     C->lpart = (double*)take(sizeof(double) * kLossBlocks);
     C->loss = (double*)take(sizeof(double));
   } else {
@@ -250,7 +252,7 @@ int fdd_cnn_backward(fdd_cnn C, int batch, int n, float* grad, void* stream) {
     launch_conv_dw(s, dzc, l == 0 ? kCnnInCh : kCnnHidden, dz, a, batch, H, W, kCnnSegPerBlock,
                    C->part, C->dbpart);
     launch_cnn_grad_reduce(s, C->part, C->dbpart, nb, cin, cout, grad + C->offW[l],
-                           grad + C->offb[l]);
+                           grad + C->offb[l], C->stage);
     if (l > 0) {
       launch_conv(s, dzc, kConvGrad, dz, batch, H, W, C->wb[l], nullptr, nullptr, C->dZ[cur],
                   nullptr, C->Z[l - 1]);

@@ -250,25 +250,44 @@ __global__ __launch_bounds__(256) void k_conv_dw(const __bf16* __restrict__ dz,
   if (wave == 0 && lane < 32) dbpart[(size_t)blockIdx.x * 32 + lane] = dbacc;
 }
 
-// Sums the block partials of one layer in block order into the gradient of W (layout
-// [dy][dx][ci][co]) and b.
-__global__ __launch_bounds__(256) void k_cnn_grad_reduce(const float* __restrict__ part,
-                                                         const float* __restrict__ dbpart,
-                                                         int nblocks, int cin, int cout,
-                                                         float* __restrict__ gW,
-                                                         float* __restrict__ gb) {
+// Sums the block partials of one layer in a fixed order (deterministic), in two passes: pass 1
+// (grid: 37 column blocks x kRedSplit row groups) adds the partials of a contiguous range of
+// blocks, with consecutive threads on consecutive partial entries (coalesced); pass 2 adds the
+// kRedSplit group sums in order and writes the gradient of W (layout [dy][dx][ci][co]) and b.
+constexpr int kRedSplit = 16;
+constexpr int kRedLen = 9 * 1024 + 32;  // weight entries, then the bias entries
+
+__global__ __launch_bounds__(256) void k_cnn_grad_sum(const float* __restrict__ part,
+                                                      const float* __restrict__ dbpart,
+                                                      int nblocks, float* __restrict__ stage) {
   const int e = blockIdx.x * 256 + threadIdx.x;
-  const int nW = 9 * cin * cout;
-  if (e < nW) {
-    const int co = e % cout, ci = (e / cout) % cin, tap = e / (cout * cin);
-    float s = 0.0f;
-    for (int k = 0; k < nblocks; ++k) s += part[(size_t)k * 9 * 1024 + tap * 1024 + co * 32 + ci];
-    gW[e] = s;
-  } else if (e < nW + cout) {
-    const int co = e - nW;
-    float s = 0.0f;
-    for (int k = 0; k < nblocks; ++k) s += dbpart[(size_t)k * 32 + co];
-    gb[co] = s;
+  if (e >= kRedLen) return;
+  const int g = blockIdx.y;
+  const int k0 = (int)((int64_t)nblocks * g / kRedSplit);
+  const int k1 = (int)((int64_t)nblocks * (g + 1) / kRedSplit);
+  float s = 0.0f;
+  if (e < 9 * 1024) {
+    for (int k = k0; k < k1; ++k) s += part[(size_t)k * 9 * 1024 + e];
+  } else {
+    for (int k = k0; k < k1; ++k) s += dbpart[(size_t)k * 32 + (e - 9 * 1024)];
+  }
+  stage[(size_t)g * kRedLen + e] = s;
+}
+
+__global__ __launch_bounds__(256) void k_cnn_grad_scatter(const float* __restrict__ stage,
+                                                          int cin, int cout,
+                                                          float* __restrict__ gW,
+                                                          float* __restrict__ gb) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= kRedLen) return;
+  float s = 0.0f;
+  for (int g = 0; g < kRedSplit; ++g) s += stage[(size_t)g * kRedLen + e];
+  if (e < 9 * 1024) {
+    const int tap = e / 1024, co = (e / 32) % 32, ci = e % 32;
+    if (co < cout && ci < cin) gW[(tap * cin + ci) * cout + co] = s;
+  } else {
+    const int co = e - 9 * 1024;
+    if (co < cout) gb[co] = s;
   }
 }
 
@@ -399,10 +418,11 @@ void launch_conv_dw(hipStream_t s, int dzc, int cina, const __bf16* dz, const __
 }
 
 void launch_cnn_grad_reduce(hipStream_t s, const float* part, const float* dbpart, int nblocks,
-                            int cin, int cout, float* gW, float* gb) {
-  const int n = 9 * cin * cout + cout;
-  hipLaunchKernelGGL(k_cnn_grad_reduce, dim3((n + 255) / 256), dim3(256), 0, s, part, dbpart,
-                     nblocks, cin, cout, gW, gb);
+                            int cin, int cout, float* gW, float* gb, float* stage) {
+  const int gx = (kRedLen + 255) / 256;
+  hipLaunchKernelGGL(k_cnn_grad_sum, dim3(gx, kRedSplit), dim3(256), 0, s, part, dbpart, nblocks,
+                     stage);
+  hipLaunchKernelGGL(k_cnn_grad_scatter, dim3(gx), dim3(256), 0, s, stage, cin, cout, gW, gb);
 }
 
 void launch_cnn_mse(hipStream_t s, const float* out, const float* target, int64_t npix, __bf16* dz,

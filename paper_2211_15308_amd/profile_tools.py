@@ -160,7 +160,7 @@ def main(argv):
             "rocprofv3 --pmc FETCH_SIZE --output-format csv -d /tmp/pmc_fetch -o pmc -- python3 bench.py --pmc-mode",
             "rocprofv3 --pmc WRITE_SIZE --output-format csv -d /tmp/pmc_write -o pmc -- python3 bench.py --pmc-mode",
             "python3 -m paper_2211_15308_amd.profile_tools traffic /tmp/pmc_fetch/pmc_counter_collection.csv "
-            "/tmp/pmc_write/pmc_counter_collection.csv 'void fdd::k_mg_down<float, 1, true>' profiles/down0_traffic.json"]
+            f"/tmp/pmc_write/pmc_counter_collection.csv '{argv[3]}' profiles/down0_traffic.json"]
         json.dump(rec, open(argv[4], "w"), indent=1)
         print(json.dumps(rec))
     elif argv[0] == "pmc":
