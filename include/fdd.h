@@ -64,9 +64,10 @@ typedef struct fdd_ratpc_s* fdd_ratpc;       /* opaque: one rational table (host
 typedef struct fdd_batch_s* fdd_batch;       /* opaque: a batch of problems solved together     */
 typedef struct fdd_cnn_s* fdd_cnn;           /* opaque: the warm-start network                  */
 
-/* Problem description.  dim = 2 (3 reserved); n = cells per side, even, 4 <= n <= 2048 and
- * such that halving the (n - 1)-point grid while its point count is odd ends at <= 16 points
- * (every n = 2^k and n = 2^k (2j + 1) with small j); K > 0; mu > 0.                           */
+/* Problem description.  dim = 2 or 3 (Omega = (0,1)^dim, Gamma = the facet x_dim = 1);
+ * n = cells per side, even, 4 <= n <= 2048 (dim 3: the limits of fdd_setup_mesh) and such that
+ * halving the (n - 1)-point grid while its point count is odd ends at <= 16 points (every
+ * n = 2^k and n = 2^k (2j + 1) with small j); K > 0; mu > 0.                                  */
 typedef struct {
   int dim;
   int n;
@@ -88,10 +89,17 @@ typedef struct {
   void* warmstart;     /* NULL, or a network handle of type fdd_cnn with its parameters set,
                           its workspace bound and n_max >= n:
                           fdd_solve (mixed precision) starts the interior solve of every outer
-                          iteration from the network's guess for the lifted search direction,
-                          kept only if it lowers the residual below that of the zero guess    */
+                          iteration from the network's guess g for the lifted search direction,
+                          entered as a g with a = f.g / g.A g (the energy-optimal multiple) and
+                          dropped when a <= 0                                                  */
   int use_graph;       /* 1 (default): fdd_solve replays each outer iteration from a captured
                           hipGraph on a library-owned stream ordered after `stream`; 0: eager */
+  int back_solve;      /* 0 (default): the interior part of the solution is accumulated during
+                          the outer PCG, x_I = A_II^{-1} b_I / K + sum_k alpha_k E p_k (E p_k is
+                          the interior solve of outer iteration k; equal to the back-substitution
+                          of eq. (block_op) by linearity), so no interior solve follows the
+                          outer PCG; 1: x_I = A_II^{-1} (b_I / K - A_IG x_G) by one more
+                          interior solve after the outer PCG                                   */
 } fdd_opts;
 
 /* Per-solve statistics. */

@@ -86,6 +86,7 @@ size_t plan_workspace(fdd_problem_s* P, char* base) {
   pcg(P->s32, sizeof(float));
   pcg(P->s64, sizeof(double));
   for (int k = 0; k < 2; ++k) P->u64[k] = (double*)take(sizeof(double) * v0);
+  for (int k = 0; k < 2; ++k) P->xI[k] = (double*)take(sizeof(double) * v0);
   const size_t g = sizeof(double) * (size_t)std::max<int64_t>(P->NG, 1);
   for (int k = 0; k < 2; ++k) P->xG[k] = (double*)take(g);
   for (int k = 0; k < 2; ++k) P->rG[k] = (double*)take(g);
@@ -661,11 +662,15 @@ namespace {
 // One outer PCG step after the interior solve for the lifted p (version v -> v+1):
 // the Schur product y = S p, alpha, x and r updates, then z = P r, rho, beta and p.
 void enqueue_outer_tail(fdd_problem_s* P, hipStream_t s, const ShiftTable& tabP, const double* u,
-                        int v) {
+                        int v, bool accumulate) {
   const int a = v & 1, b = (v + 1) & 1;
   launch_schur_gather(s, (int)P->NG, P->lev[0].nf, P->lev[0].pitch, P->K, P->gamma, P->pG[a], u,
                       nullptr, nullptr, P->Hp, P->yG, P->xG[a], P->xG[b], P->rG[a], P->rG[b],
                       P->st, 1, v);
+  // x_I(v+1) = x_I(v) + alpha E p (u = E p; versioned, so a repeated tail gives the same result)
+  if (accumulate)
+    launch_interior_axpy(s, P->lev[0].nf, P->lev[0].pitch, P->xI[a], u, &P->st->o_alpha, 0.0,
+                         P->xI[b]);
   launch_iface_batch(s, (int)P->NG, P->h, tabP, kIfacePrecondOuter, P->rG[b], P->zG, P->scratchP,
                      P->st, P->pG[a], P->pG[b], v, 0);
 }
@@ -686,7 +691,7 @@ void enqueue_outer_iteration(fdd_problem_s* P, hipStream_t s, const ShiftTable& 
   else enqueue_inner_more(P, c, t, 0, P->sc->its64);
   launch_iface_batch(s, (int)P->NG, P->h, tabH, kIfaceOperator, P->pG[a], P->Hp, P->scratchH,
                      P->st, nullptr, nullptr, 0, 0);
-  enqueue_outer_tail(P, s, tabP, inner_u(P, t), v);
+  enqueue_outer_tail(P, s, tabP, inner_u(P, t), v, !o.back_solve);
 }
 
 // Replays (capturing first if needed) the graph of outer iteration v for the current schedule.
@@ -694,7 +699,7 @@ int launch_outer_graph(fdd_problem_s* P, hipStream_t s, const ShiftTable& tabP,
                        const ShiftTable& tabH, const fdd_opts& o, int v, InnerTrack& t) {
   // everything the captured launch sequence depends on
   std::vector<int> key = {v & 1, (int)t.fp64, o.mg_nu, P->sc->steps, P->sc->its, P->sc->its64,
-                          (int)std::lround(std::log10(o.step_rtol) * 16.0)};
+                          (int)std::lround(std::log10(o.step_rtol) * 16.0), o.back_solve ? 1 : 0};
   key.insert(key.end(), P->sc->step_its, P->sc->step_its + 8);
   const uint64_t ws = (uint64_t)(uintptr_t)o.warmstart;
   key.push_back((int)(ws & 0xffffffffu));
@@ -792,6 +797,8 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   account(res);
   if (rc) return finish(rc);
   launch_rhs_reduce(s, ng, pitch, b + P->NI, inner_u(P, t), nullptr, nullptr, P->rG[0], P->xG[0]);
+  if (!o.back_solve)  // x_I(0) = A_II^{-1} b_I / K
+    launch_interior_axpy(s, nf, pitch, nullptr, inner_u(P, t), nullptr, 1.0 / P->K, P->xI[0]);
   // 2. outer PCG from x_G = 0: z = P r, rho0 = r.z, p = z
   launch_iface_batch(s, ng, P->h, tabP, kIfacePrecondOuter, P->rG[0], P->zG, P->scratchP, P->st,
                      nullptr, P->pG[0], 0, 1);
@@ -818,7 +825,7 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
       rc = inner_finish(P, s, t, o, &res);
       account(res);
       if (rc) return finish(rc);
-      enqueue_outer_tail(P, s, tabP, inner_u(P, t), v);
+      enqueue_outer_tail(P, s, tabP, inner_u(P, t), v, !o.back_solve);
       HIPCHK(hipGetLastError());
       if ((rc = read_state(P, s))) return finish(rc);
     } else {
@@ -841,11 +848,16 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
     converged = std::sqrt(rho) <= o.outer_rtol * std::sqrt(rho0);
   }
   st.rel_precond_res = rho0 > 0 ? std::sqrt(std::max(rho, 0.0) / rho0) : 0.0;
-  // 3. back-substitution x_I = A_II^{-1} (b_I / K - A_IG x_G)
-  rc = interior_solve(P, s, RhsDesc{b, 1.0 / P->K, P->xG[v & 1], 1.0}, o, t, &res);
-  account(res);
-  if (rc) return finish(rc);
-  launch_scatter(s, nf, pitch, inner_u(P, t), nullptr, nullptr, P->xG[v & 1], x);
+  // 3. back-substitution x_I = A_II^{-1} (b_I / K - A_IG x_G): accumulated during the outer
+  //    PCG, or one more interior solve
+  if (o.back_solve) {
+    rc = interior_solve(P, s, RhsDesc{b, 1.0 / P->K, P->xG[v & 1], 1.0}, o, t, &res);
+    account(res);
+    if (rc) return finish(rc);
+    launch_scatter(s, nf, pitch, inner_u(P, t), nullptr, nullptr, P->xG[v & 1], x);
+  } else {
+    launch_scatter(s, nf, pitch, P->xI[v & 1], nullptr, nullptr, P->xG[v & 1], x);
+  }
   if (o.check_true_residual) {
     launch_iface_batch(s, ng, P->h, tabH, kIfaceOperator, x + P->NI, P->Hp, P->scratchH, P->st,
                        nullptr, nullptr, 0, 0);

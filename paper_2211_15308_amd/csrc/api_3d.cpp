@@ -24,6 +24,7 @@ struct Problem3D {
   double* f[kMaxLevels] = {};  // level right-hand sides (level 0: r)
   double* t[kMaxLevels] = {};  // level residual scratch
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double* xI = nullptr;  // interior part of the solution, accumulated during the outer PCG
   double *part0 = nullptr, *part1 = nullptr;
   State3* st = nullptr;
   int* stop = nullptr;
@@ -82,6 +83,7 @@ size_t plan3(fdd_problem_s* P, char* base) {
   Q->z = (double*)take(8 * v0);
   Q->p = (double*)take(8 * v0);
   Q->q = (double*)take(8 * v0);
+  Q->xI = (double*)take(8 * v0);
   Q->u[0] = Q->z;
   Q->f[0] = Q->r;
   Q->part0 = (double*)take(8 * kPart3);
@@ -586,6 +588,8 @@ int solve3(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, const
   int rc = inner(Rhs3{b, 1.0 / h, nullptr, 0.0});
   if (rc) return finish(rc);
   kf_launch_rhs_reduce(s, b + P->NI, Q->x, nf, h, Q->rG, Q->xG);
+  // x_I(0) = A_II^{-1} b_I / K (unless the back-substitution is solved at the end)
+  if (!o.back_solve) k3_launch_scale_add(s, Q->xI, Q->x, 1.0 / P->K, 0, (int64_t)vol(nf));
   // 2. outer PCG from x_G = 0
   if ((rc = face_batch(P, s, PT, Q->rG, Q->zG))) return finish(rc);
   const double rho0 = face_dot(Q, s, Q->rG, Q->zG, &rc);
@@ -607,6 +611,8 @@ int solve3(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, const
                          "3D outer PCG breakdown (p.Sp = %g)", pq));
     const double alpha = rho / pq;
     kf_launch_outer_axpy(s, Q->xG, Q->rG, Q->pG, Q->yG, nullptr, NG, alpha);
+    // x_I += alpha E p (Q->x holds E p = L7^{-1} lift(p) from the Schur product)
+    if (!o.back_solve) k3_launch_scale_add(s, Q->xI, Q->x, alpha, 1, (int64_t)vol(nf));
     if ((rc = face_batch(P, s, PT, Q->rG, Q->zG))) return finish(rc);
     const double rho_new = face_dot(Q, s, Q->rG, Q->zG, &rc);
     if (rc) return finish(rc);
@@ -618,9 +624,14 @@ int solve3(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, const
     if (!conv) kf_launch_outer_axpy(s, nullptr, nullptr, Q->pG, nullptr, Q->zG, NG, beta);
   }
   st.rel_precond_res = rho0 > 0 ? std::sqrt(std::max(rho, 0.0) / rho0) : 0.0;
-  // 3. x_I = A_II^{-1} (b_I / K - A_IG x_G) = L7^{-1} (b_I / (K h) + lift(x_G))
-  if ((rc = inner(Rhs3{b, 1.0 / (P->K * h), Q->xG, 1.0}))) return finish(rc);
-  k3_launch_gather(s, Q->x, nf, x, Q->xG);
+  // 3. x_I = A_II^{-1} (b_I / K - A_IG x_G) = L7^{-1} (b_I / (K h) + lift(x_G)): accumulated
+  //    during the outer PCG, or one more interior solve
+  if (o.back_solve) {
+    if ((rc = inner(Rhs3{b, 1.0 / (P->K * h), Q->xG, 1.0}))) return finish(rc);
+    k3_launch_gather(s, Q->x, nf, x, Q->xG);
+  } else {
+    k3_launch_gather(s, Q->xI, nf, x, Q->xG);
+  }
   if (o.check_true_residual) {
     if ((rc = face_batch(P, s, HT, x + P->NI, Q->Hp))) return finish(rc);
     k3_launch_full_operator(s, P->n, P->K, P->gamma, x, Q->Hp, nullptr, b, Q->gpart);

@@ -105,6 +105,7 @@ BInst make_inst(const fdd_batch_s* B, int i, const double* b, double* x) {
     I.p[k] = P->s32.p[k];
     I.s[k] = P->s32.s[k];
     I.u64[k] = P->u64[k];
+    I.xI[k] = P->xI[k];
     I.xG[k] = P->xG[k];
     I.rG[k] = P->rG[k];
     I.pG[k] = P->pG[k];
@@ -246,13 +247,13 @@ void enqueue_outer(const fdd_batch_s* B, const BatchCtx& c, BTrack& t, int v, co
   enqueue_start(c, t, kRhsLiftP, v, o);
   enqueue_steps(B, c, t, kRhsLiftP, v, B->sc->steps, -1);
   launch_b_operator(c, v);
-  launch_b_outer_tail(c, t.S, v, o.outer_rtol);
+  launch_b_outer_tail(c, t.S, v, o.outer_rtol, !o.back_solve);
 }
 
 int replay_outer(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, int v,
                  const fdd_opts& o) {
   std::vector<int> key = {v & 1, o.mg_nu, B->sc->steps, B->sc->its,
-                          (int)std::lround(std::log10(o.step_rtol) * 16.0)};
+                          (int)std::lround(std::log10(o.step_rtol) * 16.0), o.back_solve ? 1 : 0};
   key.insert(key.end(), B->sc->step_its, B->sc->step_its + 8);
   auto it = B->graphs.find(key);
   if (it == B->graphs.end()) {
@@ -446,6 +447,7 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
   int rc = batch_inner(B, s, c0, t, kRhsB, 0, all, o, st);
   if (rc) return finish(rc);
   launch_b_rhs_reduce(c0, t.S);
+  if (!o.back_solve) launch_b_xI_init(c0, t.S);
   // 2. outer PCG from x_G = 0 (device-side convergence test per instance)
   launch_b_precond_init(c0, o.outer_rtol);
   HIPCHK(hipGetLastError());
@@ -474,7 +476,7 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
     if (short_solve) {
       // the schedule was short for some instance: its tail was skipped; now that every interior
       // solve is complete, repeat the tail (it depends on version-v data only)
-      launch_b_outer_tail(c1, t.S, v, o.outer_rtol);
+      launch_b_outer_tail(c1, t.S, v, o.outer_rtol, !o.back_solve);
       HIPCHK(hipGetLastError());
       if ((rc = read_states(B, s))) return finish(rc);
     }
@@ -493,9 +495,10 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
       }
     }
   }
-  // 3. back-substitution x_I = A_II^{-1} (b_I / K - A_IG x_G) for every instance
-  if ((rc = batch_inner(B, s, c0, t, kRhsBack, v, all, o, st))) return finish(rc);
-  launch_b_scatter(c0, t.S, v);
+  // 3. back-substitution x_I = A_II^{-1} (b_I / K - A_IG x_G) for every instance: accumulated
+  //    during the outer PCG, or one more batched interior solve
+  if (o.back_solve && (rc = batch_inner(B, s, c0, t, kRhsBack, v, all, o, st))) return finish(rc);
+  launch_b_scatter(c0, t.S, v, !o.back_solve);
   HIPCHK(hipGetLastError());
   if ((rc = read_states(B, s))) return finish(rc);
   int code = FDD_OK;

@@ -85,6 +85,7 @@ struct fdd_problem_s {
   PcgSet<float> s32;
   PcgSet<double> s64;
   double* u64[2] = {nullptr, nullptr};  // refinement accumulators
+  double* xI[2] = {nullptr, nullptr};   // interior part of the solution, by outer version
   double* xG[2] = {nullptr, nullptr};
   double* rG[2] = {nullptr, nullptr};
   double* pG[2] = {nullptr, nullptr};

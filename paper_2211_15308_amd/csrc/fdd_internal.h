@@ -178,6 +178,10 @@ void launch_scatter(hipStream_t s, int nf, int pitch, const double* u0, const do
                     const int* sel, const double* xG, double* x);
 void launch_copy_rows(hipStream_t s, const double* src, int sp, double* dst, int dp, int width,
                       int rows);
+// out = a + c u on the nf x nf interior grid (row pitch `pitch`, FP64); a may be null (zero);
+// c = *coef when coef is non-null (a device scalar, read by the kernel), else c = scale.
+void launch_interior_axpy(hipStream_t s, int nf, int pitch, const double* a, const double* u,
+                          const double* coef, double scale, double* out);
 void launch_full_operator(hipStream_t s, int n, double K, double gamma, const double* x,
                           const double* Hx, double* y, const double* b, double* partials,
                           unsigned* counter, double* res);
@@ -194,6 +198,7 @@ struct BInst {
   float* e[kMaxLevels];
   float *x, *r[2], *p[2], *s[2], *z, *w;
   double* u64[2];
+  double* xI[2];                      // interior part of the solution, by outer version
   const float* cinv;
   DevState* st;
   Reductions red;
@@ -235,9 +240,13 @@ void launch_b_inner_step(const BatchCtx& c, int rhs, int ver, int its, int S, in
                          int& cur_p);
 void launch_b_rhs_reduce(const BatchCtx& c, int S);
 void launch_b_precond_init(const BatchCtx& c, double rtol);
-void launch_b_outer_tail(const BatchCtx& c, int S, int v, double rtol);
+// accumulate: x_I(v+1) = x_I(v) + alpha E p after the Schur product (no back-substitution solve)
+void launch_b_outer_tail(const BatchCtx& c, int S, int v, double rtol, bool accumulate);
+// x_I(0) = A_II^{-1} b_I / K from the interior solve of the right-hand side
+void launch_b_xI_init(const BatchCtx& c, int S);
 void launch_b_operator(const BatchCtx& c, int v);
-void launch_b_scatter(const BatchCtx& c, int S, int ver);
+// from_xI: the interior part comes from the accumulated x_I, else from the last interior solve
+void launch_b_scatter(const BatchCtx& c, int S, int ver, bool from_xI);
 void launch_b_gather_states(const BatchCtx& c, DevState* out);
 
 // ---- host rational approximation (ra_build.cpp) --------------------------------------------

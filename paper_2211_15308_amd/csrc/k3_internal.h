@@ -80,6 +80,9 @@ void k3_launch_full_operator(hipStream_t s, int n, double K, double gamma, const
                              const double* Hx, double* y, const double* b, double* part);
 void kf_launch_outer_axpy(hipStream_t s, double* x, double* r, double* p, const double* y,
                           const double* z, int64_t N, double a);
+// out = (accumulate ? out : 0) + c u over n elements
+void k3_launch_scale_add(hipStream_t s, double* out, const double* u, double c, int accumulate,
+                         int64_t n);
 void kf_launch_rhs_reduce(hipStream_t s, const double* bG, const double* w, int nf, double h,
                           double* g, double* xg);
 void kf_launch_vdot(hipStream_t s, const double* a, const double* b, int64_t N, double* part);

@@ -589,6 +589,13 @@ __global__ __launch_bounds__(kB3) void kf_outer_axpy(double* __restrict__ x, dou
   }
 }
 
+__global__ __launch_bounds__(kB3) void k3_scale_add(double* __restrict__ out,
+                                                   const double* __restrict__ u, double c,
+                                                   int accumulate, int64_t N) {
+  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3)
+    out[q] = (accumulate ? out[q] : 0.0) + c * u[q];
+}
+
 // g = b_G + h w|plane nf (right-hand side of the interface problem), x_G = 0
 __global__ __launch_bounds__(kB3) void kf_rhs_reduce(const double* __restrict__ bG,
                                                     const double* __restrict__ w, int nf,
@@ -744,6 +751,11 @@ void k3_launch_full_operator(hipStream_t s, int n, double K, double gamma, const
 void kf_launch_outer_axpy(hipStream_t s, double* x, double* r, double* p, const double* y,
                           const double* z, int64_t N, double a) {
   hipLaunchKernelGGL(kf_outer_axpy, dim3(grid_for(N, 1024)), dim3(kB3), 0, s, x, r, p, y, z, N, a);
+}
+void k3_launch_scale_add(hipStream_t s, double* out, const double* u, double c, int accumulate,
+                         int64_t n) {
+  hipLaunchKernelGGL(k3_scale_add, dim3(grid_for(n, 2048)), dim3(kB3), 0, s, out, u, c,
+                     accumulate, n);
 }
 void kf_launch_rhs_reduce(hipStream_t s, const double* bG, const double* w, int nf, double h,
                           double* g, double* xg) {

@@ -215,12 +215,41 @@ __global__ __launch_bounds__(256) void kb_rhs_reduce(const BInst* __restrict__ I
   }
 }
 
+// Interior accumulator over the level-0 tile list: init = 1: x_I(0) = u / K; init = 0:
+// x_I(ver+1) = x_I(ver) + alpha u (alpha from the Schur product of this iteration), with u the
+// interior solve's FP64 result.  Runs with the outer tail (after the Schur product, before the
+// convergence test may retire the instance).
+__global__ __launch_bounds__(kBlock) void kb_interior_axpy(const BInst* __restrict__ I, BLists L,
+                                                           int S, int ver, int init,
+                                                           int skip_done) {
+  const int b = xcd_linear();
+  const int* start = L.tiles[0];
+  const int i = find_inst(start, L.ninst, b);
+  const BInst& P = I[i];
+  if (!init && tail_idle(P.st, skip_done)) return;
+  const int t = b - first_tile(start, i);
+  const int tx = P.tiles_x[0];
+  const int i0 = (t % tx) * kTile, j0 = (t / tx) * kTile;
+  const int nf = P.nf[0], pitch = P.pitch[0];
+  const double* u = P.u64[S & 1];
+  const double c = init ? 1.0 / P.K : P.st->o_alpha;
+  const double* a = init ? nullptr : P.xI[ver & 1];
+  double* out = init ? P.xI[0] : P.xI[(ver + 1) & 1];
+  for (int q = flat_tid(); q < kTile * kTile; q += kBlock) {
+    const int ii = i0 + (q % kTile), jj = j0 + q / kTile;
+    if (ii >= nf || jj >= nf) continue;
+    const unsigned o = (unsigned)(jj * pitch + ii);
+    stg(out, o, (a ? ldg(a, o) : 0.0) + c * ldg(u, o));
+  }
+}
+
 // Interior solution (padded) and the final interface iterate into the caller's vector.
-__global__ __launch_bounds__(256) void kb_scatter(const BInst* __restrict__ I, int S, int ver) {
+__global__ __launch_bounds__(256) void kb_scatter(const BInst* __restrict__ I, int S, int ver,
+                                                  int from_xI) {
   const BInst& P = I[blockIdx.x];
   const int nf = P.nf[0];
   const int64_t NI = (int64_t)nf * nf;
-  const double* u = P.u64[S & 1];
+  const double* u = from_xI ? P.xI[final_ver(P.st, ver) & 1] : P.u64[S & 1];
   const double* xG = P.xG[final_ver(P.st, ver) & 1];
   for (int64_t k = threadIdx.x + (int64_t)blockIdx.y * blockDim.x; k < NI + nf;
        k += (int64_t)blockDim.x * gridDim.y) {
@@ -310,17 +339,26 @@ void launch_b_operator(const BatchCtx& c, int v) {
                      c.inst, 1, v, 0, -1.0, c.skip_done);
 }
 
-void launch_b_outer_tail(const BatchCtx& c, int S, int v, double rtol) {
+void launch_b_xI_init(const BatchCtx& c, int S) {
+  hipLaunchKernelGGL(kb_interior_axpy, dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst, c.lists,
+                     S, 0, 1, 0);
+}
+
+void launch_b_outer_tail(const BatchCtx& c, int S, int v, double rtol, bool accumulate) {
   hipLaunchKernelGGL(kb_schur_gather, dim3(c.lists.ninst), dim3(kIfaceThreads), 0, c.stream,
                      c.inst, S, v, c.skip_done);
+  if (accumulate)
+    hipLaunchKernelGGL(kb_interior_axpy, dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst,
+                       c.lists, S, v, 0, c.skip_done);
   hipLaunchKernelGGL(kb_iface_solve, dim3(c.sysP_total), dim3(kIfaceThreads), 0, c.stream, c.inst,
                      c.lists, 0, 1, v, c.skip_done);
   hipLaunchKernelGGL(kb_iface_combine, dim3(c.lists.ninst), dim3(kIfaceThreads), 0, c.stream,
                      c.inst, 0, v, 0, rtol * rtol, c.skip_done);
 }
 
-void launch_b_scatter(const BatchCtx& c, int S, int ver) {
-  hipLaunchKernelGGL(kb_scatter, dim3(c.lists.ninst, 64), dim3(256), 0, c.stream, c.inst, S, ver);
+void launch_b_scatter(const BatchCtx& c, int S, int ver, bool from_xI) {
+  hipLaunchKernelGGL(kb_scatter, dim3(c.lists.ninst, 64), dim3(256), 0, c.stream, c.inst, S, ver,
+                     from_xI ? 1 : 0);
 }
 
 void launch_b_gather_states(const BatchCtx& c, DevState* out) {

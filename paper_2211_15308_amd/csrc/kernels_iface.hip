@@ -79,6 +79,19 @@ __global__ void k_copy_rows(const double* __restrict__ src, int sp, double* __re
   }
 }
 
+// out = a + c u over the nf x nf interior grid (padded rows; the padding is not touched).
+__global__ __launch_bounds__(256) void k_interior_axpy(int nf, int pitch, const double* __restrict__ a,
+                                                       const double* __restrict__ u,
+                                                       const double* __restrict__ coef,
+                                                       double scale, double* __restrict__ out) {
+  const double c = coef ? *coef : scale;
+  const int tot = nf * pitch;  // below 2^23 (nf <= 2047)
+  for (int k = threadIdx.x + blockIdx.x * blockDim.x; k < tot; k += blockDim.x * gridDim.x) {
+    if (k % pitch >= nf) continue;
+    out[k] = (a ? a[k] : 0.0) + c * u[k];
+  }
+}
+
 // y = A x on all free dofs: K times the P1 stiffness (5-point inside, the natural-boundary row
 // (2, -1/2, -1/2, -1 below) on Gamma) plus gamma Hx on the Gamma row.  Optionally reduces
 // ||b - y||^2 and ||b||^2 into res[0], res[1] (via partials and the last block).
@@ -185,6 +198,14 @@ void launch_copy_rows(hipStream_t s, const double* src, int sp, double* dst, int
   const int64_t tot = (int64_t)width * rows;
   int blocks = (int)std::min<int64_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_copy_rows, dim3(blocks), dim3(256), 0, s, src, sp, dst, dp, width, rows);
+}
+
+void launch_interior_axpy(hipStream_t s, int nf, int pitch, const double* a, const double* u,
+                          const double* coef, double scale, double* out) {
+  const int64_t tot = (int64_t)nf * pitch;
+  int blocks = (int)std::min<int64_t>((tot + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_interior_axpy, dim3(blocks), dim3(256), 0, s, nf, pitch, a, u, coef, scale,
+                     out);
 }
 
 void launch_full_operator(hipStream_t s, int n, double K, double gamma, const double* x,

@@ -58,7 +58,8 @@ class FddOpts(ctypes.Structure):
                 ("inner_rtol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("precision", ctypes.c_int), ("mg_nu", ctypes.c_int),
                 ("step_rtol", ctypes.c_double), ("check_true_residual", ctypes.c_int),
-                ("warmstart", ctypes.c_void_p), ("use_graph", ctypes.c_int)]
+                ("warmstart", ctypes.c_void_p), ("use_graph", ctypes.c_int),
+                ("back_solve", ctypes.c_int)]
 
 
 class FddStats(ctypes.Structure):

@@ -81,16 +81,19 @@ def test_schur_apply_3d_matches_dense_schur(n, K, mu):
     assert rel(host(y), S @ x) <= 1e-9
 
 
-@pytest.mark.parametrize("n,K,mu", [(8, 1.0, 1.0), (8, 1e-2, 1e-4), (16, 1.0, 1e2), (16, 1e-4, 1.0)])
-def test_solve_3d_matches_dense_and_sparse_lu(n, K, mu):
-    print(f"[3d solve] n={n} K={K} mu={mu}", flush=True)
+@pytest.mark.parametrize("n,K,mu,back_solve", [(8, 1.0, 1.0, 0), (8, 1e-2, 1e-4, 0), (16, 1.0, 1e2, 0),
+                                               (16, 1e-4, 1.0, 0), (8, 1e-2, 1e-4, 1),
+                                               (16, 1e-4, 1.0, 1)])
+def test_solve_3d_matches_dense_and_sparse_lu(n, K, mu, back_solve):
+    print(f"[3d solve] n={n} K={K} mu={mu} back_solve={back_solve}", flush=True)
     P = make3(n, K, mu)
     TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
     TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
     b = workloads.rhs(3, n, 3000 + n)
     x = torch.zeros_like(dev(b))
     st = P.solve(TP, TH, dev(b), x, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12,
-                                                   check_true_residual=1))
+                                                   check_true_residual=1, back_solve=back_solve))
+    assert st["inner_solves"] == st["outer_its"] + 1 + back_solve
     R = system.Riesz(3, n, K, mu)
     x_ref = R.solve_splu(b)
     err = rel(host(x), x_ref)

@@ -72,6 +72,27 @@ def test_ragged_batch_matches_oracle_and_single_solves():
     print(f"  bit-identical to the single-instance solve: {identical} of {len(cases)}", flush=True)
 
 
+def test_batch_back_substitution_accumulated_or_solved():
+    # x_I accumulated from the outer iterations' interior solves (default) or by one more batched
+    # interior solve: both reach the oracle, and agree with each other
+    cases = workloads.batch_instances(count=8, seed=13, sizes=SMALL_SIZES)
+    print("[batch back-substitution] n =", [c["n"] for c in cases], flush=True)
+    B, probs, TP, TH, bs = make_batch(cases)
+    res = {}
+    for back_solve in (0, 1):
+        opts = F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12, back_solve=back_solve)
+        xs = [torch.zeros_like(b) for b in bs]
+        stats = B.solve(bs, xs, opts)
+        res[back_solve] = [host(x) for x in xs]
+        for i, c in enumerate(cases):
+            x_ref = system.solve_dst_2d(c["n"], c["K"], c["mu"], host(bs[i]))
+            assert stats[i]["status"] == F.FDD_OK
+            assert rel(res[back_solve][i], x_ref) <= 1e-8, (back_solve, i)
+    worst = max(rel(a, b) for a, b in zip(res[0], res[1]))
+    print(f"  accumulated vs solved: worst rel diff {worst:.2e}", flush=True)
+    assert worst <= 1e-9
+
+
 def test_batch_of_the_batched_workload_at_bench_settings():
     # the batched workload's distributions (n in {64, 96, ..., 512}), preconditioner tables to
     # 1e-8 with at most 20 poles, outer rtol 1e-8, inner rtol 1e-10

@@ -147,18 +147,22 @@ def test_apply_operator_matches_oracle(n, K, mu):
     assert rel(y_h, y_ref) <= 1e-11
 
 
+@pytest.mark.parametrize("back_solve", [0, 1])
 @pytest.mark.parametrize("precision", [F.FDD_FP64, F.FDD_MIXED])
-def test_solve_small_config_parity(precision):
-    # 64 x 64 unit square, K = mu = 1, b ~ N(0,1) seed 0, outer rtol 1e-10, inner 1e-12
+def test_solve_small_config_parity(precision, back_solve):
+    # 64 x 64 unit square, K = mu = 1, b ~ N(0,1) seed 0, outer rtol 1e-10, inner 1e-12;
+    # the interior part of x accumulated during the outer PCG (back_solve = 0) or solved after it
     n, K, mu = 64, 1.0, 1.0
-    print(f"[solve C1] precision={precision}", flush=True)
+    print(f"[solve C1] precision={precision} back_solve={back_solve}", flush=True)
     P = make(n, K, mu)
     TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
     TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
     b = workloads.rhs(2, n, 0)
     x = torch.zeros_like(dev(b))
     st = P.solve(TP, TH, dev(b), x, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12,
-                                                  precision=precision, check_true_residual=1))
+                                                  precision=precision, check_true_residual=1,
+                                                  back_solve=back_solve))
+    assert st["inner_solves"] == st["outer_its"] + 1 + back_solve
     R = system.Riesz(2, n, K, mu)
     x_ref = R.solve_dense(b)
     err = rel(host(x), x_ref)
@@ -170,15 +174,18 @@ def test_solve_small_config_parity(precision):
     assert st["true_rel_res"] <= 1e-9
 
 
-@pytest.mark.parametrize("n,K,mu", [(128, 1e-2, 1e-3), (256, 1e-4, 1e3), (96, 1.0, 1e-6), (512, 1.0, 1.0)])
-def test_solve_against_separable_oracle(n, K, mu):
-    print(f"[solve] n={n} K={K} mu={mu}", flush=True)
+@pytest.mark.parametrize("n,K,mu,back_solve", [(128, 1e-2, 1e-3, 0), (256, 1e-4, 1e3, 0),
+                                               (96, 1.0, 1e-6, 0), (512, 1.0, 1.0, 0),
+                                               (256, 1e-4, 1e3, 1), (96, 1.0, 1e-6, 1)])
+def test_solve_against_separable_oracle(n, K, mu, back_solve):
+    print(f"[solve] n={n} K={K} mu={mu} back_solve={back_solve}", flush=True)
     P = make(n, K, mu)
     TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
     TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
     b = workloads.rhs(2, n, 1000 + n)
     x = torch.zeros_like(dev(b))
-    st = P.solve(TP, TH, dev(b), x, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12))
+    st = P.solve(TP, TH, dev(b), x, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12,
+                                                  back_solve=back_solve))
     x_ref = system.solve_dst_2d(n, K, mu, b)
     err = rel(host(x), x_ref)
     print(f"  rel err {err:.3e}  outer {st['outer_its']} inner {st['inner_its_total']}", flush=True)
