@@ -63,7 +63,8 @@ size_t plan_workspace(fdd_problem_s* P, char* base) {
   P->red.ir = (double*)take(sizeof(double) * nb0);
   P->red.ff = (double*)take(sizeof(double) * nb0);
   const int nfc = P->lev[P->nlev - 1].nf;
-  P->cinv32 = (float*)take(sizeof(float) * (size_t)nfc * nfc * nfc * nfc);
+  P->dstS = (float*)take(sizeof(float) * kDstN * kDstN);
+  P->dstL = (float*)take(sizeof(float) * kDstN);
   P->cinv64 = (double*)take(sizeof(double) * (size_t)nfc * nfc * nfc * nfc);
   auto pcg = [&](auto& S, size_t esz) {
     using T = std::remove_pointer_t<decltype(S.x)>;
@@ -149,7 +150,8 @@ LaunchCtx make_ctx(const fdd_problem_s* P, hipStream_t s, int nu, bool fp64) {
   c.first_coarse = fp64 ? P->first_coarse64 : P->first_coarse32;
   for (int l = 0; l < P->nlev; ++l) c.lev[l] = P->lev[l];
   c.nu = nu;
-  c.coarse_inv = P->cinv32;
+  c.dst_S = P->dstS;
+  c.dst_lam = P->dstL;
   c.coarse_inv64 = P->cinv64;
   c.st = P->st;
   c.red = P->red;
@@ -497,10 +499,19 @@ int fdd_bind_workspace(fdd_problem P, void* dev, size_t bytes, void* stream) {
   if (!P->host_st) HIPCHK(hipHostMalloc((void**)&P->host_st, sizeof(DevState), hipHostMallocDefault));
   HIPCHK(hipMemsetAsync(P->ws, 0, need, s));
   const size_t np = P->cinv.size();
-  std::vector<float> c32(np);
-  for (size_t k = 0; k < np; ++k) c32[k] = (float)P->cinv[k];
   HIPCHK(hipMemcpyAsync(P->cinv64, P->cinv.data(), np * sizeof(double), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(P->cinv32, c32.data(), np * sizeof(float), hipMemcpyHostToDevice, s));
+  // FP32 coarse solve on the first level with <= 63 points per side: orthonormal sine transform
+  // S_ab = sqrt(2 / (m + 1)) sin(pi (a + 1)(b + 1) / (m + 1)) and symbols 2 - 2 cos(pi (k + 1) / (m + 1))
+  const int m = P->lev[P->first_coarse32].nf;
+  std::vector<float> S((size_t)kDstN * kDstN, 0.0f), L(kDstN, 0.0f);
+  for (int a = 0; a < m; ++a) {
+    for (int b = 0; b < m; ++b)
+      S[(size_t)a * kDstN + b] =
+          (float)(std::sqrt(2.0 / (m + 1)) * std::sin(M_PI * (a + 1) * (b + 1) / (m + 1)));
+    L[a] = (float)(2.0 - 2.0 * std::cos(M_PI * (a + 1) / (m + 1)));
+  }
+  HIPCHK(hipMemcpyAsync(P->dstS, S.data(), S.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(P->dstL, L.data(), L.size() * sizeof(float), hipMemcpyHostToDevice, s));
   const double lkm[2] = {std::log10(P->K), std::log10(P->mu)};
   HIPCHK(hipMemcpyAsync(P->lk_lmu, lkm, sizeof(lkm), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));

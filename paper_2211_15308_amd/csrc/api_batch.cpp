@@ -112,7 +112,8 @@ BInst make_inst(const fdd_batch_s* B, int i, const double* b, double* x) {
   }
   I.z = P->s32.z;
   I.w = P->s32.w;
-  I.cinv = P->cinv32;
+  I.dstS = P->dstS;
+  I.dstL = P->dstL;
   I.st = P->st;
   I.red = P->red;
   I.ng = (int)P->NG;

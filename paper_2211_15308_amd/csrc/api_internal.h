@@ -80,7 +80,8 @@ struct fdd_problem_s {
   DevState* st = nullptr;
   double* partials = nullptr;   // true-residual reduction
   Reductions red{};
-  float* cinv32 = nullptr;
+  float* dstS = nullptr;    // FP32 coarse solve: sine-transform matrix and symbols
+  float* dstL = nullptr;
   double* cinv64 = nullptr;
   PcgSet<float> s32;
   PcgSet<double> s64;

@@ -14,6 +14,7 @@ constexpr int kTile = 32;            // fine-grid tile edge of the fused multigr
 constexpr int kBlock = 256;          // threads per block of the tiled kernels
 constexpr int kCoarseThreads = 1024; // threads of the single-workgroup coarse V-cycle
 constexpr int kMaxCoarsestNf = 16;   // dense inverse on the coarsest grid up to 16 x 16 points
+constexpr int kDstN = 64;            // FP32 coarse solve by sine transforms: up to 63 x 63 points
 
 // One multigrid level of the interior Dirichlet grid.
 struct Level {
@@ -128,8 +129,9 @@ struct LaunchCtx {
   int first_coarse;        // first level handled by the single-workgroup kernel
   Level lev[kMaxLevels];
   int nu;                  // red-black sweep pairs
-  const float* coarse_inv; // dense inverse on the coarsest level (nfc^2 x nfc^2), FP32
-  const double* coarse_inv64;
+  const double* coarse_inv64;  // FP64: dense inverse on the coarsest level (nfc^2 x nfc^2)
+  const float* dst_S;      // FP32 coarse solve: sine-transform matrix (kDstN x kDstN, zero-padded)
+  const float* dst_lam;    // ... and the 1D symbols 2 - 2 cos(k pi / (m + 1)) (kDstN entries)
   DevState* st;
   Reductions red;
 };
@@ -199,7 +201,8 @@ struct BInst {
   float *x, *r[2], *p[2], *s[2], *z, *w;
   double* u64[2];
   double* xI[2];                      // interior part of the solution, by outer version
-  const float* cinv;
+  const float* dstS;                  // sine-transform matrix of the first coarse level
+  const float* dstL;                  // its 1D symbols
   DevState* st;
   Reductions red;
   // interface / outer PCG

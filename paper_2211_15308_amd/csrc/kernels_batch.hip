@@ -102,18 +102,13 @@ __global__ __launch_bounds__(kBlock) void kb_mg_up(const BInst* __restrict__ I, 
   }
 }
 
-template <int NU>
 __global__ __launch_bounds__(kCoarseThreads) void kb_coarse(const BInst* __restrict__ I, int check,
                                                             int skip_done) {
   const BInst& P = I[blockIdx.x];
   DevState* st = P.st;
   if (inst_idle(st, skip_done) || stopped(st)) return;
   if (check && P.fc == 1 && pcg_converged(st, P.red, true)) return;
-  LaunchLevels lv;
-  lv.first = P.fc;
-  lv.nlev = P.nlev;
-  for (int l = 0; l < kMaxLevels; ++l) lv.nf[l] = P.nf[l];
-  d_coarse_vcycle<float, NU>(P.f[P.fc], P.pitch[P.fc], P.e[P.fc], lv, P.cinv);
+  d_coarse_dst(P.f[P.fc], P.pitch[P.fc], P.e[P.fc], P.nf[P.fc], P.dstS, P.dstL);
 }
 
 // Version of the final interface iterate: the converged one, else the last (ver).
@@ -277,7 +272,7 @@ static void b_tail(const BatchCtx& c, int check) {
     if (c.tiles_total[l] > 0)
       hipLaunchKernelGGL((kb_mg_down<NU, false>), dim3(c.tiles_total[l]), tb(), 0, c.stream,
                          c.inst, c.lists, l, 0, 0, 0, check, c.skip_done);
-  launch_timed(c.hook, kTimeCoarse, kb_coarse<NU>, dim3(c.lists.ninst), dim3(kCoarseThreads),
+  launch_timed(c.hook, kTimeCoarse, kb_coarse, dim3(c.lists.ninst), dim3(kCoarseThreads),
                c.stream, c.inst, check, c.skip_done);
   for (int l = c.max_tiled - 1; l >= 1; --l)
     if (c.tiles_total[l] > 0)

@@ -11,7 +11,9 @@
 //   - The finest levels run as fused LDS-tiled kernels: one kernel per level going down
 //     (pre-smooth from zero, residual, restriction) and one going up (prolongation + correction,
 //     post-smooth).  Halo cells are recomputed redundantly so that a tile never waits on a
-//     neighbour.  Levels with at most 63 x 63 points run in one workgroup entirely in LDS.
+//     neighbour.  The first level with at most 63 x 63 points is solved in one workgroup: in
+//     FP32 exactly, by sine transforms on the matrix cores; in FP64 by a V-cycle in LDS down to
+//     a dense inverse on the coarsest grid.
 //   - The PCG runs in its single-reduction form (Chronopoulos and Gear 1989): the vector updates
 //     are fused into the level-0 down kernel, w = A z into the level-0 up kernel, and r . z and
 //     z . A z are reduced together, so an iteration is one V-cycle and nothing else.
@@ -64,6 +66,15 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(
   d_coarse_vcycle<T, NU>(fin, pin, eout, lv, cinv);
 }
 
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_dst(
+    const float* __restrict__ fin, int pin, float* __restrict__ eout, int m,
+    const float* __restrict__ S, const float* __restrict__ lam, DevState* st, Reductions red,
+    int check) {
+  if (stopped(st)) return;
+  if (check && pcg_converged(st, red, true)) return;
+  d_coarse_dst(fin, pin, eout, m, S, lam);
+}
+
 template <typename E>
 __global__ __launch_bounds__(kBlock) void k_ir_residual(
     RhsDesc f, const double* __restrict__ uin, const E* __restrict__ e, double* __restrict__ uout,
@@ -111,16 +122,19 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
                        (const T*)nullptr, (T*)nullptr, (const T*)nullptr, (const T*)nullptr,
                        (T*)nullptr, (T*)nullptr, (T*)nullptr, c.st, c.red, 0, l == 1 ? check : 0);
   }
-  LaunchLevels lv;
-  lv.first = fc;
-  lv.nlev = c.nlev;
-  for (int l = 0; l < c.nlev; ++l) lv.nf[l] = c.lev[l].nf;
-  const T* cinv = nullptr;
-  if constexpr (sizeof(T) == 4) cinv = (const T*)c.coarse_inv;
-  else cinv = (const T*)c.coarse_inv64;
-  launch_timed(c.hook, kTimeCoarse, k_coarse_vcycle<T, NU>, dim3(1), dim3(kCoarseThreads),
-               c.stream, (const T*)mg.f[fc], c.lev[fc].pitch, mg.e[fc], lv, cinv, c.st, c.red,
-               fc == 1 ? check : 0);
+  if constexpr (sizeof(T) == 4) {
+    launch_timed(c.hook, kTimeCoarse, k_coarse_dst, dim3(1), dim3(kCoarseThreads), c.stream,
+                 (const float*)mg.f[fc], c.lev[fc].pitch, (float*)mg.e[fc], c.lev[fc].nf, c.dst_S,
+                 c.dst_lam, c.st, c.red, fc == 1 ? check : 0);
+  } else {
+    LaunchLevels lv;
+    lv.first = fc;
+    lv.nlev = c.nlev;
+    for (int l = 0; l < c.nlev; ++l) lv.nf[l] = c.lev[l].nf;
+    launch_timed(c.hook, kTimeCoarse, k_coarse_vcycle<T, NU>, dim3(1), dim3(kCoarseThreads),
+                 c.stream, (const T*)mg.f[fc], c.lev[fc].pitch, mg.e[fc], lv,
+                 (const T*)c.coarse_inv64, c.st, c.red, fc == 1 ? check : 0);
+  }
   for (int l = fc - 1; l >= 1; --l) {
     const Level& L = c.lev[l];
     hipLaunchKernelGGL((k_mg_up<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, mg.f[l],

@@ -113,22 +113,37 @@ __device__ __forceinline__ T prolong(const T* ec, int pc, int nc, int i, int j) 
 
 // One red or black half-sweep over the window cells 1..W-2 that lie inside the domain.  The
 // cells of one colour are enumerated directly (W - 2 rows of (W - 2) / 2 cells each), so every
-// thread of the block updates a cell of the sweep's colour.
+// thread of the block updates a cell of the sweep's colour.  A thread's cells are independent
+// (cells of one colour only read the other colour), so all their LDS reads are issued before the
+// first write.
 template <typename T, int W>
 __device__ __forceinline__ void tile_halfsweep(T (*su)[W + 1], const T (*sf)[W + 1], int ib, int jb,
                                                int nf, bool red) {
   constexpr int R = W - 2;  // even
   constexpr int C = R / 2;
+  constexpr int N = R * C;
+  constexpr int TR = (N + kBlock - 1) / kBlock;
   const int want = red ? 0 : 1;
-  for (int c = flat_tid(); c < R * C; c += kBlock) {
+  T acc[TR];
+  int lis[TR], ljs[TR];
+  bool ok[TR];
+#pragma unroll
+  for (int q = 0; q < TR; ++q) {
+    const int c = flat_tid() + kBlock * q;
     const int lj = 1 + c / C, m = c % C;
     const int j = jb + lj;
     const int li = 1 + (((ib + 1 + j) & 1) != want) + 2 * m;
     const int i = ib + li;
-    if (j < 1 || j > nf || i < 1 || i > nf) continue;
-    su[lj][li] = T(0.25) * (sf[lj][li] + su[lj][li - 1] + su[lj][li + 1] + su[lj - 1][li] +
-                            su[lj + 1][li]);
+    ok[q] = c < N && j >= 1 && j <= nf && i >= 1 && i <= nf;
+    lis[q] = li;
+    ljs[q] = lj;
+    acc[q] = ok[q] ? (sf[lj][li] + su[lj][li - 1] + su[lj][li + 1] + su[lj - 1][li] +
+                      su[lj + 1][li])
+                   : T(0);
   }
+#pragma unroll
+  for (int q = 0; q < TR; ++q)
+    if (ok[q]) su[ljs[q]][lis[q]] = T(0.25) * acc[q];
   __syncthreads();
 }
 
@@ -455,30 +470,33 @@ constexpr int kCinvLds = 64;  // coarsest inverses up to 64 x 64 are staged in L
 template <typename T>
 struct CoarseLds;  // padded sizes of the in-LDS hierarchy
 template <>
-struct CoarseLds<float> {
-  static constexpr int kMaxNf = 63;
-  static constexpr int kElems = 65 * 65 + 33 * 33 + 17 * 17 + 9 * 9 + 5 * 5 + 3 * 3 + 128;
-};
-template <>
 struct CoarseLds<double> {
   static constexpr int kMaxNf = 31;
   static constexpr int kElems = 33 * 33 + 17 * 17 + 9 * 9 + 5 * 5 + 3 * 3 + 128;
 };
 
-// one red or black half-sweep of a padded level
+// one red or black half-sweep of a padded level (all reads of a thread before its writes)
 template <typename T>
 __device__ __forceinline__ void lds_halfsweep(T* u, const T* f, int nf, bool red) {
   const int pw = nf + 2;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  T acc[4];
+  int off[4];
+  bool ok[4];
 #pragma unroll
   for (int b = 0; b < 2; ++b)
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
+      const int q = 2 * b + a;
       const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
-      if (i > nf || j > nf || is_red(i, j) != red) continue;
       const int o = j * pw + i;
-      u[o] = T(0.25) * (f[o] + u[o - 1] + u[o + 1] + u[o - pw] + u[o + pw]);
+      ok[q] = i <= nf && j <= nf && is_red(i, j) == red;
+      off[q] = o;
+      acc[q] = ok[q] ? (f[o] + u[o - 1] + u[o + 1] + u[o - pw] + u[o + pw]) : T(0);
     }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (ok[q]) u[off[q]] = T(0.25) * acc[q];
   __syncthreads();
 }
 
@@ -632,6 +650,95 @@ __device__ __forceinline__ void d_coarse_vcycle(const T* __restrict__ fin, int p
         const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
         if (i <= nf0 && j <= nf0) stg(eout, (unsigned)((j - 1) * pin + (i - 1)), UL(first)[j * pw + i]);
       }
+  }
+}
+
+// --------------------------------------------------------------------------------------------
+// FP32 coarse-grid solve by sine transforms
+// --------------------------------------------------------------------------------------------
+// The 5-point operator on an m x m grid with zero Dirichlet values is diagonalised by the
+// orthonormal sine transform S (S_ab = sqrt(2 / (m + 1)) sin(pi (a + 1)(b + 1) / (m + 1))):
+// A = S diag(c_p + c_q) S with c_k = 2 - 2 cos(pi (k + 1) / (m + 1)).  The first level handled by
+// one workgroup is solved exactly as U = S ((S F S) ./ (c_p + c_q)) S: four 64 x 64 products in
+// LDS on the matrix cores (v_mfma_f32_16x16x4_f32), each of the 16 waves owning a 16 x 16 tile.
+// Rows and columns beyond m are zero in S, so the padding stays zero.
+constexpr int kDstP = kDstN + 1;  // LDS row pitch (odd: a fragment's 16 rows hit 16 banks)
+typedef float dst_f4 __attribute__((ext_vector_type(4)));
+
+// Tile (ti, tj) of A B (A, B: kDstN x kDstN in LDS).  Fragment layout of the 16x16x4 FP32
+// instruction: lane l supplies A(row l % 16, k l / 16) and B(k l / 16, col l % 16); result
+// register q holds C(row 4 (l / 16) + q, col l % 16).
+__device__ __forceinline__ dst_f4 dst_tile(const float* A, const float* B, int ti, int tj,
+                                           int lane) {
+  dst_f4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int r = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int k0 = 0; k0 < kDstN; k0 += 4) {
+    const float a = A[(16 * ti + r) * kDstP + k0 + kq];
+    const float b = B[(k0 + kq) * kDstP + 16 * tj + r];
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// e = A^{-1} f on the m x m level (m <= kDstN - 1); f and e in global memory with row pitch pin.
+// Needs kCoarseThreads = 1024 threads (16 waves).
+__device__ __forceinline__ void d_coarse_dst(const float* __restrict__ fin, int pin,
+                                             float* __restrict__ eout, int m,
+                                             const float* __restrict__ Sg,
+                                             const float* __restrict__ lamg) {
+  static_assert(kCoarseThreads == 1024 && kDstN == 64, "16 waves, 4 x 4 tiles of 16 x 16");
+  __shared__ float sS[kDstN * kDstP];
+  __shared__ float sX[kDstN * kDstP];
+  __shared__ float sY[kDstN * kDstP];
+  __shared__ float sl[kDstN];
+  const int t = threadIdx.x;
+  constexpr int Q = kDstN * kDstN / kCoarseThreads;
+  float sv[Q], fv[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = t + kCoarseThreads * q;
+    const int row = idx / kDstN, col = idx % kDstN;
+    sv[q] = ldg(Sg, (unsigned)idx);
+    fv[q] = (row < m && col < m) ? ldg(fin, (unsigned)(row * pin + col)) : 0.f;
+  }
+  const float lv = t < kDstN ? ldg(lamg, (unsigned)t) : 0.f;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = t + kCoarseThreads * q;
+    const int row = idx / kDstN, col = idx % kDstN;
+    sS[row * kDstP + col] = sv[q];
+    sX[row * kDstP + col] = fv[q];
+  }
+  if (t < kDstN) sl[t] = lv;
+  __syncthreads();
+  const int w = t >> 6, lane = t & 63;
+  const int ti = w >> 2, tj = w & 3;
+  const int col = 16 * tj + (lane & 15), row0 = 16 * ti + 4 * (lane >> 4);
+  // Y = S F
+  dst_f4 acc = dst_tile(sS, sX, ti, tj, lane);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sY[(row0 + q) * kDstP + col] = acc[q];
+  __syncthreads();
+  // X = (Y S) ./ (c_p + c_q)
+  acc = dst_tile(sY, sS, ti, tj, lane);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int p = row0 + q;
+    sX[p * kDstP + col] = (p < m && col < m) ? acc[q] / (sl[p] + sl[col]) : 0.f;
+  }
+  __syncthreads();
+  // Y = S X
+  acc = dst_tile(sS, sX, ti, tj, lane);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sY[(row0 + q) * kDstP + col] = acc[q];
+  __syncthreads();
+  // e = Y S
+  acc = dst_tile(sY, sS, ti, tj, lane);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int p = row0 + q;
+    if (p < m && col < m) stg(eout, (unsigned)(p * pin + col), acc[q]);
   }
 }
 
