@@ -96,55 +96,76 @@ __device__ __forceinline__ bool pcg_converged(DevState* st, const Reductions& re
   return conv;
 }
 
-template <typename T>
-__device__ __forceinline__ T gload(const T* a, int pitch, int nf, int i, int j) {
-  return (i >= 1 && i <= nf && j >= 1 && j <= nf) ? a[(size_t)(j - 1) * pitch + (i - 1)] : T(0);
-}
-
-// P1 interpolation from the coarse grid (nc points per side) to fine point (i, j).
-template <typename T>
-__device__ __forceinline__ T prolong(const T* ec, int pc, int nc, int i, int j) {
-  const int I = i >> 1, J = j >> 1;
-  if (!(i & 1) && !(j & 1)) return gload(ec, pc, nc, I, J);
-  if ((i & 1) && !(j & 1)) return T(0.5) * (gload(ec, pc, nc, I, J) + gload(ec, pc, nc, I + 1, J));
-  if (!(i & 1) && (j & 1)) return T(0.5) * (gload(ec, pc, nc, I, J) + gload(ec, pc, nc, I, J + 1));
-  return T(0.5) * (gload(ec, pc, nc, I, J) + gload(ec, pc, nc, I + 1, J + 1));
-}
-
-// One red or black half-sweep over the window cells 1..W-2 that lie inside the domain.  The
-// cells of one colour are enumerated directly (W - 2 rows of (W - 2) / 2 cells each), so every
-// thread of the block updates a cell of the sweep's colour.  A thread's cells are independent
-// (cells of one colour only read the other colour), so all their LDS reads are issued before the
-// first write.
-template <typename T, int W>
-__device__ __forceinline__ void tile_halfsweep(T (*su)[W + 1], const T (*sf)[W + 1], int ib, int jb,
-                                               int nf, bool red) {
-  constexpr int R = W - 2;  // even
-  constexpr int C = R / 2;
-  constexpr int N = R * C;
-  constexpr int TR = (N + kBlock - 1) / kBlock;
-  const int want = red ? 0 : 1;
-  T acc[TR];
-  int lis[TR], ljs[TR];
-  bool ok[TR];
+// NS red-black Gauss-Seidel half-sweeps (alternating colours, the first red if red_first) over
+// the window cells 1..W-2 that lie inside the domain.  Each thread owns a pair of adjacent
+// columns over a segment of SEG rows and keeps their f and u in registers.  In every row of the
+// segment exactly one cell of the pair has the sweep's colour; its update needs one LDS read (the
+// horizontal neighbour outside the pair), the rest comes from registers, except above and below
+// the segment.  Reads are unconditional (rows clamped into the window), so a half-sweep waits for
+// LDS once; the new values go to LDS for the neighbouring threads and a barrier ends it.  Cells of
+// one colour only read the other colour, so reads and writes of a half-sweep do not conflict.
+// The update is u = (f + u_w + u_e + u_s + u_n) / 4 in that order of summation.
+template <typename T, int W, int NS>
+__device__ __forceinline__ void tile_sweeps(T (*su)[W + 1], const T (*sf)[W + 1], int ib, int jb,
+                                            int nf, bool red_first) {
+  constexpr int R = W - 2;  // updated rows and columns: 1 .. R (R even)
+  constexpr int PAIRS = R / 2;
+  constexpr int SEG = (R + kBlock / PAIRS - 1) / (kBlock / PAIRS);
+  constexpr int NSEG = (R + SEG - 1) / SEG;
+  static_assert(R % 2 == 0 && PAIRS * NSEG <= kBlock, "column pairs x segments fit the block");
+  const int t = flat_tid();
+  const int pr = t % PAIRS, sg = t / PAIRS;
+  const bool act = sg < NSEG;
+  const int la = 1 + 2 * pr;  // left column of the pair; the right one is la + 1
+  const int lj0 = 1 + sg * SEG;
+  const int ia = ib + la;
+  auto rowc = [](int lj) { return lj < W - 1 ? lj : W - 1; };
+  T fa[SEG], fb[SEG], ua[SEG], ub[SEG];
+  bool ma[SEG], mb[SEG];
 #pragma unroll
-  for (int q = 0; q < TR; ++q) {
-    const int c = flat_tid() + kBlock * q;
-    const int lj = 1 + c / C, m = c % C;
-    const int j = jb + lj;
-    const int li = 1 + (((ib + 1 + j) & 1) != want) + 2 * m;
-    const int i = ib + li;
-    ok[q] = c < N && j >= 1 && j <= nf && i >= 1 && i <= nf;
-    lis[q] = li;
-    ljs[q] = lj;
-    acc[q] = ok[q] ? (sf[lj][li] + su[lj][li - 1] + su[lj][li + 1] + su[lj - 1][li] +
-                      su[lj + 1][li])
-                   : T(0);
+  for (int k = 0; k < SEG; ++k) {
+    const int lj = lj0 + k, j = jb + lj;
+    const bool rowok = act && lj <= R && j >= 1 && j <= nf;
+    ma[k] = rowok && ia >= 1 && ia <= nf;
+    mb[k] = rowok && ia + 1 >= 1 && ia + 1 <= nf;
+    const int lr = rowc(lj);
+    fa[k] = sf[lr][la];
+    fb[k] = sf[lr][la + 1];
+    ua[k] = su[lr][la];
+    ub[k] = su[lr][la + 1];
   }
+  const int par0 = (ia + jb + lj0) & 1;  // colour parity of cell (la, lj0); 0: red
+  bool red = red_first;
 #pragma unroll
-  for (int q = 0; q < TR; ++q)
-    if (ok[q]) su[ljs[q]][lis[q]] = T(0.25) * acc[q];
-  __syncthreads();
+  for (int h = 0; h < NS; ++h) {
+    const int want = red ? 0 : 1;
+    T nv[SEG];
+#pragma unroll
+    for (int k = 0; k < SEG; ++k) {
+      const bool left = ((par0 + k) & 1) == want;  // the updated cell of row k is column la
+      const int lj = lj0 + k;
+      const int col = left ? la : la + 1;
+      const T hn = su[rowc(lj)][left ? la - 1 : la + 2];
+      const T hin = left ? ub[k] : ua[k];
+      const T fv = left ? fa[k] : fb[k];
+      const T up = k > 0 ? (left ? ua[k - 1] : ub[k - 1]) : su[lj - 1][col];
+      const T dn = k + 1 < SEG ? (left ? ua[k + 1] : ub[k + 1]) : su[rowc(lj + 1)][col];
+      const T uw = left ? hn : hin;
+      const T ue = left ? hin : hn;
+      nv[k] = T(0.25) * (fv + uw + ue + up + dn);
+    }
+#pragma unroll
+    for (int k = 0; k < SEG; ++k) {
+      const bool left = ((par0 + k) & 1) == want;
+      if (left ? ma[k] : mb[k]) {
+        su[lj0 + k][left ? la : la + 1] = nv[k];
+        if (left) ua[k] = nv[k];
+        else ub[k] = nv[k];
+      }
+    }
+    __syncthreads();
+    red = !red;
+  }
 }
 
 // Sums of two values over the block, broadcast to every thread (fixed order: deterministic).
@@ -318,7 +339,7 @@ __device__ __forceinline__ void d_mg_down(
     }
   }
   __syncthreads();
-  for (int s = 1; s < 2 * NU; ++s) tile_halfsweep<T, W>(su, sf, ib, jb, nf, !(s & 1));
+  tile_sweeps<T, W, 2 * NU - 1>(su, sf, ib, jb, nf, false);  // black, red, black, ...
   // residual, in place of f, on the cells the restriction reads (window rows and columns
   // H .. H + kTile); each reads its own f and the neighbours' u
   constexpr int RW = kTile + 1;
@@ -412,20 +433,19 @@ __device__ __forceinline__ void d_mg_up(
     const int i = ib + li, j = jb + lj;
     T u = T(0);
     if (i >= 1 && i <= nf && j >= 1 && j <= nf) {
-      // P1 interpolation of the coarse correction (nested diagonal-split meshes)
+      // P1 interpolation of the coarse correction (nested diagonal-split meshes): the mean of
+      // the coarse values at (i >> 1, j >> 1) and at that point shifted by the parities of
+      // (i, j); at coincident points both are the same value, and 0.5 (a + a) = a exactly.
+      // Branch-free, so the reads of all window slots are issued together.
       const int ci = (i >> 1) - Ib, cj = (j >> 1) - Jb;
-      T e;
-      if (!(i & 1) && !(j & 1)) e = sc[cj][ci];
-      else if ((i & 1) && !(j & 1)) e = T(0.5) * (sc[cj][ci] + sc[cj][ci + 1]);
-      else if (!(i & 1) && (j & 1)) e = T(0.5) * (sc[cj][ci] + sc[cj + 1][ci]);
-      else e = T(0.5) * (sc[cj][ci] + sc[cj + 1][ci + 1]);
+      const T e = T(0.5) * (sc[cj][ci] + sc[cj + (j & 1)][ci + (i & 1)]);
       u = ur[q] + e;
     }
     sf[lj][li] = fr[q];
     su[lj][li] = u;
   }
   __syncthreads();
-  for (int s = 0; s < 2 * NU; ++s) tile_halfsweep<T, W>(su, sf, ib, jb, nf, (s & 1));
+  tile_sweeps<T, W, 2 * NU>(su, sf, ib, jb, nf, false);  // black, red, ...
   double rz = 0.0, zw = 0.0;
 #pragma unroll
   for (int q = 0; q < kOwnSlots; ++q) {
@@ -631,11 +651,7 @@ __device__ __forceinline__ void d_coarse_vcycle(const T* __restrict__ fin, int p
         const int i = tx + 1 + 32 * a, j = ty + 1 + 32 * b;
         if (i > nf || j > nf) continue;
         const int o = (j >> 1) * pcw + (i >> 1);
-        T e;
-        if (!(i & 1) && !(j & 1)) e = ec[o];
-        else if ((i & 1) && !(j & 1)) e = T(0.5) * (ec[o] + ec[o + 1]);
-        else if (!(i & 1) && (j & 1)) e = T(0.5) * (ec[o] + ec[o + pcw]);
-        else e = T(0.5) * (ec[o] + ec[o + pcw + 1]);
+        const T e = T(0.5) * (ec[o] + ec[o + (j & 1) * pcw + (i & 1)]);
         u[j * pw + i] += e;
       }
     __syncthreads();
