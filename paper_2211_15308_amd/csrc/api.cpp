@@ -7,6 +7,7 @@
 #include <type_traits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -197,9 +198,42 @@ bool opts_ok(const fdd_opts* o) {
 
 double step_tau(const fdd_opts& o) { return o.step_rtol; }
 
-// Selects the problem's schedule for these options.
-void use_schedule(fdd_problem_s* P, const fdd_opts& o) {
-  P->sc = &P->scheds[std::make_pair(o.mg_nu, o.precision == FDD_FP64 ? 0.0 : o.step_rtol)];
+// Kinds of interior right-hand sides with separate launch schedules: the iteration counts of
+// solves for a full right-hand side (b, the back-substitution) and for a lifted interface vector
+// (one row of data) differ, and a shared schedule would pad the cheaper kind to the other.
+enum SchedKind { kSchedGeneral = 0, kSchedLift = 1, kSchedLiftWarm = 2 };
+
+void schedule_record(Schedule* sc, int steps_needed, const int* run_len, int run_its_max) {
+  // the converging iteration of a run is the one after its last counted one
+  sc->its = std::max(sc->its, run_its_max + 1);
+  for (int q = 0; q < std::min(steps_needed, 8); ++q)
+    sc->step_its[q] = std::max(sc->step_its[q], run_len[q] + 1);
+  const int need = std::max(steps_needed, 1);
+  if (!sc->calibrated) {
+    sc->steps = need;
+    sc->over = sc->under = 0;
+    return;
+  }
+  if (need > sc->steps) {
+    sc->under = 0;
+    sc->over += 2;
+    if (sc->over >= 4) {  // two such solves in close succession
+      sc->steps += 1;
+      sc->over = 0;
+    }
+  } else {
+    sc->over = std::max(sc->over - 1, 0);
+    sc->under = need < sc->steps ? sc->under + 1 : 0;
+    if (sc->under >= 16) {
+      sc->steps -= 1;
+      sc->under = 0;
+    }
+  }
+}
+
+// Selects the problem's schedule for these options and right-hand-side kind.
+void use_schedule(fdd_problem_s* P, const fdd_opts& o, int kind) {
+  P->sc = &P->scheds[std::make_tuple(o.mg_nu, o.precision == FDD_FP64 ? 0.0 : o.step_rtol, kind)];
 }
 
 // Host-side record of an interior solve in flight: which buffers hold what.  Buffer parities
@@ -302,13 +336,16 @@ int inner_finish(fdd_problem_s* P, hipStream_t s, InnerTrack& t, const fdd_opts&
     if (h.solve_done) {
       res->its = h.inner_its;
       res->steps = h.refine_steps;
-      // the schedule only grows, so replays converge without top-ups once it has settled
       if (!t.fp64) {
-        // one iteration of slack so that runs end on their own criterion, not on the schedule
-        P->sc->steps = std::max(P->sc->steps, std::max(h.refine_steps, 1));
-        P->sc->its = std::max(P->sc->its, h.run_its_max + 1);
-        for (int q = 0; q < std::min(h.refine_steps, 8); ++q)
-          P->sc->step_its[q] = std::max(P->sc->step_its[q], h.run_len[q] + 1);
+        schedule_record(P->sc, h.refine_steps, h.run_len, h.run_its_max);
+        if (std::getenv("FDD_TRACE_SCHEDULE")) {
+          // diagnostic: the runs of this interior solve against the schedule it ran on
+          std::fprintf(stderr, "[fdd schedule] n=%d steps=%d runs=", P->n, h.refine_steps);
+          for (int q = 0; q < std::min(h.refine_steps, 8); ++q) std::fprintf(stderr, "%d ", h.run_len[q]);
+          std::fprintf(stderr, "schedule=%d:", P->sc->steps);
+          for (int q = 0; q < std::min(P->sc->steps, 8); ++q) std::fprintf(stderr, "%d ", P->sc->step_its[q]);
+          std::fprintf(stderr, "top-up rounds=%d\n", round);
+        }
       } else {
         P->sc->its64 = std::max(P->sc->its64, std::max(h.inner_its, 1));
       }
@@ -319,7 +356,8 @@ int inner_finish(fdd_problem_s* P, hipStream_t s, InnerTrack& t, const fdd_opts&
       return fail(FDD_NOT_CONVERGED, "interior solve: %d iterations, residual %.3e of %.3e",
                   h.inner_its, std::sqrt(h.res2), std::sqrt(h.ff));
     }
-    if (!t.fp64) enqueue_inner_more(P, c, t, 1, std::max(P->sc->its, 30));
+    // top-up: one more refinement step (long runs while the schedule is being measured)
+    if (!t.fp64) enqueue_inner_more(P, c, t, 1, P->sc->calibrated ? P->sc->its : 30);
     else enqueue_inner_more(P, c, t, 0, std::max(P->sc->its64 / 2, 2));
     int rc = read_state(P, s);
     if (rc) return rc;
@@ -593,7 +631,7 @@ int fdd_interior_solve(fdd_problem P, const double* f, double* u, const fdd_opts
   if (opts) o = *opts;
   else fdd_opts_default(&o);
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
-  use_schedule(P, o);
+  use_schedule(P, o, kSchedGeneral);
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
   if (P->dim == 3) return interior_solve3(P, f, u, o, s, its);
@@ -632,7 +670,7 @@ int fdd_schur_apply(fdd_problem P, fdd_ratpc H, const double* x, double* y, cons
   if (opts) o = *opts;
   else fdd_opts_default(&o);
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
-  use_schedule(P, o);
+  use_schedule(P, o, kSchedLift);
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
   if (P->dim == 3) return schur_apply3(P, H, x, y, o, s);
@@ -698,8 +736,15 @@ void enqueue_outer_iteration(fdd_problem_s* P, hipStream_t s, const ShiftTable& 
   if (o.warmstart)  // checked by the caller; the network's guess for E p (any scale)
     (void)cnn_warm_guess((fdd_cnn_s*)o.warmstart, s, P->pG[a], P->n, P->lk_lmu, &warm, &wscale);
   enqueue_inner_start(P, c, t, o, warm);
-  if (!t.fp64) enqueue_inner_more(P, c, t, P->sc->steps, -1);
-  else enqueue_inner_more(P, c, t, 0, P->sc->its64);
+  if (!P->sc->calibrated) {
+    // the first solve on this schedule measures it: long PCG runs, one step at a time
+    if (!t.fp64) enqueue_inner_more(P, c, t, 1, 30);
+    else enqueue_inner_more(P, c, t, 0, 60);
+  } else if (!t.fp64) {
+    enqueue_inner_more(P, c, t, P->sc->steps, -1);
+  } else {
+    enqueue_inner_more(P, c, t, 0, P->sc->its64);
+  }
   launch_iface_batch(s, (int)P->NG, P->h, tabH, kIfaceOperator, P->pG[a], P->Hp, P->scratchH,
                      P->st, nullptr, nullptr, 0, 0);
   enqueue_outer_tail(P, s, tabP, inner_u(P, t), v, !o.back_solve);
@@ -764,7 +809,7 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
     return solve3(P, PT, HT, b, x, o, (hipStream_t)stream, stats);
   }
   if (o.warmstart && (rc = cnn_check_for((const fdd_cnn_s*)o.warmstart, P->n))) return rc;
-  use_schedule(P, o);
+  use_schedule(P, o, kSchedGeneral);
   HIPCHK(hipSetDevice(P->device));
   hipStream_t us = (hipStream_t)stream;
   hipStream_t s = us;
@@ -815,6 +860,7 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
                      nullptr, P->pG[0], 0, 1);
   HIPCHK(hipGetLastError());
   if ((rc = read_state(P, s))) return finish(rc);
+  use_schedule(P, o, o.warmstart ? kSchedLiftWarm : kSchedLift);
   const double rho0 = P->host_st->o_rho0;
   if (P->host_st->breakdown) return finish(fail(FDD_E_BREAKDOWN, "preconditioner not positive"));
   int v = 0;
@@ -823,7 +869,7 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   while (!converged && st.outer_its < o.outer_maxit) {
     t = InnerTrack{};
     t.fp64 = fp64;
-    if (o.use_graph) {
+    if (o.use_graph && P->sc->calibrated) {
       if ((rc = launch_outer_graph(P, s, tabP, tabH, o, v, t))) return finish(rc);
     } else {
       enqueue_outer_iteration(P, s, tabP, tabH, o, v, t);
@@ -836,6 +882,7 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
       rc = inner_finish(P, s, t, o, &res);
       account(res);
       if (rc) return finish(rc);
+      P->sc->calibrated = true;
       enqueue_outer_tail(P, s, tabP, inner_u(P, t), v, !o.back_solve);
       HIPCHK(hipGetLastError());
       if ((rc = read_state(P, s))) return finish(rc);
@@ -843,6 +890,7 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
       rc = inner_finish(P, s, t, o, &res);
       account(res);
       if (rc) return finish(rc);
+      P->sc->calibrated = true;
     }
     if (o.warmstart) {
       st.warm_starts += 1;
@@ -862,6 +910,7 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   // 3. back-substitution x_I = A_II^{-1} (b_I / K - A_IG x_G): accumulated during the outer
   //    PCG, or one more interior solve
   if (o.back_solve) {
+    use_schedule(P, o, kSchedGeneral);
     rc = interior_solve(P, s, RhsDesc{b, 1.0 / P->K, P->xG[v & 1], 1.0}, o, t, &res);
     account(res);
     if (rc) return finish(rc);

@@ -52,7 +52,9 @@ struct fdd_batch_s {
   DevState* h_states = nullptr;
   std::vector<BInst> uploaded;  // descriptors as last uploaded
   // shared enqueue schedule per (smoother sweeps, per-step reduction); only grows
-  std::map<std::pair<int, double>, Schedule> scheds;
+  // launch schedules by (mg_nu, step_rtol, right-hand-side kind: 0 full, 1 lifted interface
+  // vector); the two kinds need different iteration counts
+  std::map<std::tuple<int, double, int>, Schedule> scheds;
   Schedule* sc = nullptr;
   std::map<std::vector<int>, BGraph> graphs;
   hipStream_t gstream = nullptr;
@@ -209,11 +211,15 @@ int finish_inner(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, in
       }
     }
     if (all) break;
-    enqueue_steps(B, c, t, rhs, ver, 1, std::max(B->sc->its, 30));
+    // top-up: one more refinement step (long runs while the schedule is being measured)
+    enqueue_steps(B, c, t, rhs, ver, 1, B->sc->calibrated ? B->sc->its : 30);
     HIPCHK(hipGetLastError());
     int rc = read_states(B, s);
     if (rc) return rc;
   }
+  // the batch needs what its slowest instance needs
+  int steps = 0, its_max = 0;
+  int run_len[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int i = 0; i < B->count; ++i) {
     if (!live[i]) continue;
     const DevState& h = B->h_states[i];
@@ -221,11 +227,11 @@ int finish_inner(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, in
     st[i].inner_its_total += h.inner_its;
     st[i].inner_its_max = std::max(st[i].inner_its_max, h.inner_its);
     st[i].refine_steps += h.refine_steps;
-    B->sc->steps = std::max(B->sc->steps, std::max(h.refine_steps, 1));
-    B->sc->its = std::max(B->sc->its, h.run_its_max + 1);
-    for (int q = 0; q < std::min(h.refine_steps, 8); ++q)
-      B->sc->step_its[q] = std::max(B->sc->step_its[q], h.run_len[q] + 1);
+    steps = std::max(steps, h.refine_steps);
+    its_max = std::max(its_max, h.run_its_max);
+    for (int q = 0; q < std::min(h.refine_steps, 8); ++q) run_len[q] = std::max(run_len[q], h.run_len[q]);
   }
+  schedule_record(B->sc, steps, run_len, its_max);
   return FDD_OK;
 }
 
@@ -246,7 +252,8 @@ int batch_inner(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, int
 // Everything of outer iteration v up to the synchronization, for the instances still running.
 void enqueue_outer(const fdd_batch_s* B, const BatchCtx& c, BTrack& t, int v, const fdd_opts& o) {
   enqueue_start(c, t, kRhsLiftP, v, o);
-  enqueue_steps(B, c, t, kRhsLiftP, v, B->sc->steps, -1);
+  if (!B->sc->calibrated) enqueue_steps(B, c, t, kRhsLiftP, v, 1, 30);  // measures the schedule
+  else enqueue_steps(B, c, t, kRhsLiftP, v, B->sc->steps, -1);
   launch_b_operator(c, v);
   launch_b_outer_tail(c, t.S, v, o.outer_rtol, !o.back_solve);
 }
@@ -397,7 +404,7 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
   if (o.precision != FDD_MIXED)
     return fail(FDD_E_ARG, "batched solves run FP32 multigrid-PCG inside FP64 refinement only");
   if (o.warmstart) return fail(FDD_E_ARG, "the batched solve takes no warm start");
-  B->sc = &B->scheds[std::make_pair(o.mg_nu, o.step_rtol)];
+  B->sc = &B->scheds[std::make_tuple(o.mg_nu, o.step_rtol, 0)];
   HIPCHK(hipSetDevice(B->device));
   hipStream_t us = (hipStream_t)stream;
   hipStream_t s = us;
@@ -453,6 +460,7 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
   launch_b_precond_init(c0, o.outer_rtol);
   HIPCHK(hipGetLastError());
   if ((rc = read_states(B, s))) return finish(rc);
+  B->sc = &B->scheds[std::make_tuple(o.mg_nu, o.step_rtol, 1)];
   std::vector<char> live(n);
   int nlive = 0;
   for (int i = 0; i < n; ++i) {
@@ -463,7 +471,7 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
   }
   int v = 0;
   while (nlive > 0 && v < o.outer_maxit) {
-    if (o.use_graph) {
+    if (o.use_graph && B->sc->calibrated) {
       if ((rc = replay_outer(B, s, c1, t, v, o))) return finish(rc);
     } else {
       enqueue_outer(B, c1, t, v, o);
@@ -474,6 +482,7 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
     for (int i = 0; i < n; ++i)
       if (live[i] && !B->h_states[i].solve_done && !B->h_states[i].breakdown) short_solve = true;
     if ((rc = finish_inner(B, s, c1, t, kRhsLiftP, v, live, o, st))) return finish(rc);
+    B->sc->calibrated = true;
     if (short_solve) {
       // the schedule was short for some instance: its tail was skipped; now that every interior
       // solve is complete, repeat the tail (it depends on version-v data only)
@@ -498,6 +507,7 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
   }
   // 3. back-substitution x_I = A_II^{-1} (b_I / K - A_IG x_G) for every instance: accumulated
   //    during the outer PCG, or one more batched interior solve
+  B->sc = &B->scheds[std::make_tuple(o.mg_nu, o.step_rtol, 0)];
   if (o.back_solve && (rc = batch_inner(B, s, c0, t, kRhsBack, v, all, o, st))) return finish(rc);
   launch_b_scatter(c0, t.S, v, !o.back_solve);
   HIPCHK(hipGetLastError());

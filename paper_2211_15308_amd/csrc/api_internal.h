@@ -31,7 +31,17 @@ struct Schedule {
   int steps = 1, its = 2, its64 = 4;
   int step_its[8] = {2, 2, 2, 2, 2, 2, 2, 2};
   bool calibrated = false;
+  int over = 0;   // recent solves that needed more refinement steps than scheduled (weighted)
+  int under = 0;  // consecutive solves that needed fewer
 };
+
+// Records what one interior solve (or the slowest instance of a batched one) needed in mixed
+// precision: its refinement steps and the PCG iterations of the runs of its first steps.
+// Per-step iteration counts only grow (plus the converging iteration).  The step count follows
+// the common case: a step more is added once solves keep needing it (a rare longer solve is
+// topped up instead of padding every replay), and one is dropped after a long streak of shorter
+// solves.
+void schedule_record(Schedule* sc, int steps_needed, const int* run_len, int run_its_max);
 
 // Per-precision multigrid-PCG buffers of level 0 plus the hierarchy.
 template <typename T>
@@ -100,7 +110,8 @@ struct fdd_problem_s {
   DevState* host_st = nullptr;  // pinned copy
   // inner schedule (refinement steps x PCG iterations, or FP64 PCG iterations); only grows
   // one schedule per (smoother sweeps, per-step reduction); `sc` is the current one
-  std::map<std::pair<int, double>, fdd::Schedule> scheds;
+  // launch schedules by (mg_nu, step_rtol (0 in FP64), right-hand-side kind)
+  std::map<std::tuple<int, double, int>, fdd::Schedule> scheds;
   fdd::Schedule* sc = nullptr;
   // captured outer iterations, keyed by (parity, schedule, precision, smoother)
   std::map<std::vector<int>, GraphEntry> graphs;
