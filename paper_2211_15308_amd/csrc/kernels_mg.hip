@@ -58,6 +58,29 @@ __global__ __launch_bounds__(kBlock) void k_mg_up(
 }
 
 template <typename T, int NU>
+__global__ __launch_bounds__(kPairThreads) void k_pair_down(
+    const T* __restrict__ fin0, T* __restrict__ uout0, T* __restrict__ fout1,
+    T* __restrict__ uout1, T* __restrict__ fout2, int nf0, int p0, int p1, int p2, DevState* st,
+    Reductions red, int check) {
+  if (stopped(st)) return;
+  if (check && pcg_converged(st, red, block0())) return;
+  int tile_x, tile_y;
+  (void)xcd_tile(&tile_x, &tile_y);
+  d_pair_down<T, NU>(fin0, uout0, fout1, uout1, fout2, nf0, p0, p1, p2, tile_x, tile_y);
+}
+
+template <typename T, int NU>
+__global__ __launch_bounds__(kPairThreads) void k_pair_up(
+    const T* __restrict__ f0, const T* __restrict__ u0pre, const T* __restrict__ f1,
+    const T* __restrict__ u1pre, const T* __restrict__ e2, T* __restrict__ eout0, int nf0, int p0,
+    int p1, int p2, DevState* st) {
+  if (stopped(st)) return;
+  int tile_x, tile_y;
+  (void)xcd_tile(&tile_x, &tile_y);
+  d_pair_up<T, NU>(f0, u0pre, f1, u1pre, e2, eout0, nf0, p0, p1, p2, tile_x, tile_y);
+}
+
+template <typename T, int NU>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(
     const T* __restrict__ fin, int pin, T* __restrict__ eout, LaunchLevels lv,
     const T* __restrict__ cinv, DevState* st, Reductions red, int check) {
@@ -112,15 +135,29 @@ static inline dim3 tblock() { return dim3(32, kBlock / 32); }
 
 template <typename T, int NU>
 static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check) {
-  // levels 1 .. first_coarse-1 go down, the coarse kernel, then back up to level 1; the first
-  // of these kernels also runs the PCG convergence test when `check` is set
+  // levels 1 .. first_coarse-1 go down, the coarse kernel, then back up to level 1; in FP32 the
+  // tiled levels run in pairs (1, 2), (3, 4), ... in one kernel each, an odd last one alone (the
+  // FP64 windows of a pair exceed the LDS); the first of these kernels also runs the PCG
+  // convergence test when `check` is set
   const int fc = c.first_coarse;
-  for (int l = 1; l < fc; ++l) {
+  const dim3 pblock(32, kPairThreads / 32);
+  constexpr bool kPairs = sizeof(T) == 4;
+  auto pair = [&](int l) { return kPairs && l + 1 < fc; };  // l odd: does level l start a pair?
+  for (int l = 1; l < fc; l += pair(l) ? 2 : 1) {
     const Level& L = c.lev[l];
-    hipLaunchKernelGGL((k_mg_down<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, mg.f[l],
-                       mg.u[l], mg.f[l + 1], L.nf, L.pitch, c.lev[l + 1].pitch, (const T*)nullptr,
-                       (const T*)nullptr, (T*)nullptr, (const T*)nullptr, (const T*)nullptr,
-                       (T*)nullptr, (T*)nullptr, (T*)nullptr, c.st, c.red, 0, l == 1 ? check : 0);
+    const int chk = l == 1 ? check : 0;
+    if (pair(l)) {
+      if constexpr (kPairs)
+        hipLaunchKernelGGL((k_pair_down<float, NU>), tiles(c.lev[l + 1].nf), pblock, 0, c.stream,
+                           (const float*)mg.f[l], mg.u[l], mg.f[l + 1], mg.u[l + 1], mg.f[l + 2],
+                           L.nf, L.pitch, c.lev[l + 1].pitch, c.lev[l + 2].pitch, c.st, c.red, chk);
+    } else {
+      hipLaunchKernelGGL((k_mg_down<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, mg.f[l],
+                         mg.u[l], mg.f[l + 1], L.nf, L.pitch, c.lev[l + 1].pitch,
+                         (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (const T*)nullptr,
+                         (const T*)nullptr, (T*)nullptr, (T*)nullptr, (T*)nullptr, c.st, c.red, 0,
+                         chk);
+    }
   }
   if constexpr (sizeof(T) == 4) {
     launch_timed(c.hook, kTimeCoarse, k_coarse_dst, dim3(1), dim3(kCoarseThreads), c.stream,
@@ -135,11 +172,32 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
                  c.stream, (const T*)mg.f[fc], c.lev[fc].pitch, mg.e[fc], lv,
                  (const T*)c.coarse_inv64, c.st, c.red, fc == 1 ? check : 0);
   }
-  for (int l = fc - 1; l >= 1; --l) {
+  // going up: an odd last tiled level alone, then the pairs from the bottom (FP64: every level
+  // alone)
+  const int ntiled = fc - 1;
+  int l = fc - 1;
+  for (; !kPairs && l >= 1; --l) {
     const Level& L = c.lev[l];
     hipLaunchKernelGGL((k_mg_up<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, mg.f[l],
                        mg.u[l], mg.e[l + 1], mg.e[l], (T*)nullptr, L.nf, L.pitch,
                        c.lev[l + 1].pitch, c.st, c.red, 0, 0);
+  }
+  if (kPairs && ntiled % 2 == 1) {
+    const Level& L = c.lev[l];
+    hipLaunchKernelGGL((k_mg_up<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, mg.f[l],
+                       mg.u[l], mg.e[l + 1], mg.e[l], (T*)nullptr, L.nf, L.pitch,
+                       c.lev[l + 1].pitch, c.st, c.red, 0, 0);
+    --l;
+  }
+  if constexpr (kPairs) {
+    for (; l >= 2; l -= 2) {
+      const int a = l - 1;  // the pair (a, a + 1)
+      hipLaunchKernelGGL((k_pair_up<float, NU>), tiles(c.lev[a + 1].nf), pblock, 0, c.stream,
+                         (const float*)mg.f[a], (const float*)mg.u[a], (const float*)mg.f[a + 1],
+                         (const float*)mg.u[a + 1], (const float*)mg.e[a + 2], mg.e[a],
+                         c.lev[a].nf, c.lev[a].pitch, c.lev[a + 1].pitch, c.lev[a + 2].pitch,
+                         c.st);
+    }
   }
 }
 

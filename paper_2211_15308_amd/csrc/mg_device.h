@@ -105,14 +105,14 @@ __device__ __forceinline__ bool pcg_converged(DevState* st, const Reductions& re
 // LDS once; the new values go to LDS for the neighbouring threads and a barrier ends it.  Cells of
 // one colour only read the other colour, so reads and writes of a half-sweep do not conflict.
 // The update is u = (f + u_w + u_e + u_s + u_n) / 4 in that order of summation.
-template <typename T, int W, int NS>
+template <typename T, int W, int NS, int NT = kBlock>
 __device__ __forceinline__ void tile_sweeps(T (*su)[W + 1], const T (*sf)[W + 1], int ib, int jb,
                                             int nf, bool red_first) {
   constexpr int R = W - 2;  // updated rows and columns: 1 .. R (R even)
   constexpr int PAIRS = R / 2;
-  constexpr int SEG = (R + kBlock / PAIRS - 1) / (kBlock / PAIRS);
+  constexpr int SEG = (R + NT / PAIRS - 1) / (NT / PAIRS);
   constexpr int NSEG = (R + SEG - 1) / SEG;
-  static_assert(R % 2 == 0 && PAIRS * NSEG <= kBlock, "column pairs x segments fit the block");
+  static_assert(R % 2 == 0 && PAIRS * NSEG <= NT, "column pairs x segments fit the block");
   const int t = flat_tid();
   const int pr = t % PAIRS, sg = t / PAIRS;
   const bool act = sg < NSEG;
@@ -475,6 +475,239 @@ __device__ __forceinline__ void d_mg_up(
         st->run_its_max = max(st->run_its_max, st->pcg_k);
       }
     }
+  }
+}
+
+// --------------------------------------------------------------------------------------------
+// two intermediate levels in one kernel
+// --------------------------------------------------------------------------------------------
+// A block of kPairThreads threads owns a kTile x kTile tile of level l+1 and the 2 kTile x 2 kTile
+// level-l cells above it.  Going down it smooths level l on a window wide enough that the
+// restricted residual gives f_{l+1} on the whole level-(l+1) window, then does level l+1 as the
+// tiled kernel does; going up it corrects and smooths level l+1 on a window whose valid part is
+// the coarse patch that level l interpolates from, then does level l.  The arithmetic of every
+// cell is that of the single-level kernels (the redundantly computed halos are discarded), so the
+// results are bit-identical to them; one launch and one inter-kernel gap fewer per level pair.
+constexpr int kPairThreads = 1024;
+
+template <int NU>
+struct PairDown {
+  static constexpr int H1 = 2 * NU + 1;               // level-(l+1) halo, as the tiled kernel
+  static constexpr int W1 = kTile + 2 * H1;           // level-(l+1) window
+  // level l: r_l on 2 W1 + 1 cells, u_l valid one further, 2 NU - 1 half-sweeps after the red
+  // start each lose one cell at the edge; one more column and row make the sweep extent even
+  static constexpr int S0 = 2 * NU - 1;
+  static constexpr int W0 = 2 * W1 + 3 + 2 * S0 + 1;
+  static constexpr int N0 = (W0 * W0 + kPairThreads - 1) / kPairThreads;
+};
+
+// Levels l (nf0 points per side, pitch p0) and l+1 going down: u_l = S^nu(0; f_l) stored on the
+// block's level-l cells, f_{l+1} = P^T (f_l - A u_l) and u_{l+1} = S^nu(0; f_{l+1}) stored on its
+// level-(l+1) tile, f_{l+2} = P^T (f_{l+1} - A u_{l+1}) on the coarse points of the tile.
+template <typename T, int NU>
+__device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __restrict__ uout0,
+                                            T* __restrict__ fout1, T* __restrict__ uout1,
+                                            T* __restrict__ fout2, int nf0, int p0, int p1,
+                                            int p2, int tile_x, int tile_y) {
+  using G = PairDown<NU>;
+  constexpr int H1 = G::H1, W1 = G::W1, W0 = G::W0, S0 = G::S0;
+  __shared__ T sf0[W0][W0 + 1];
+  __shared__ T su0[W0][W0 + 1];
+  __shared__ T sf1[W1][W1 + 1];
+  __shared__ T su1[W1][W1 + 1];
+  const int t = flat_tid();
+  const int nf1 = (nf0 - 1) >> 1;
+  const int I0 = tile_x * kTile, J0 = tile_y * kTile;
+  const int Ib = I0 + 1 - H1, Jb = J0 + 1 - H1;          // level-(l+1) window origin
+  const int ib0 = 2 * Ib - 2 - S0, jb0 = 2 * Jb - 2 - S0;  // level-l window origin
+  T fr[G::N0];
+#pragma unroll
+  for (int q = 0; q < G::N0; ++q) {
+    const int c = t + kPairThreads * q;
+    const int lj = c / W0, li = c % W0;
+    const int i = ib0 + li, j = jb0 + lj;
+    const bool in = c < W0 * W0 && i >= 1 && i <= nf0 && j >= 1 && j <= nf0;
+    fr[q] = in ? ldg(fin0, (unsigned)((j - 1) * p0 + (i - 1))) : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < G::N0; ++q) {
+    const int c = t + kPairThreads * q;
+    if (c >= W0 * W0) continue;
+    const int lj = c / W0, li = c % W0;
+    sf0[lj][li] = fr[q];
+    su0[lj][li] = is_red(ib0 + li, jb0 + lj) ? T(0.25) * fr[q] : T(0);
+  }
+  __syncthreads();
+  tile_sweeps<T, W0, S0, kPairThreads>(su0, sf0, ib0, jb0, nf0, false);  // black, red, black, ...
+  // level-l residual (in place of f) on the cells the restriction reads: window cells S0 + 1 ..
+  // S0 + 1 + 2 W1
+  constexpr int RW0 = 2 * W1 + 1;
+  for (int c = t; c < RW0 * RW0; c += kPairThreads) {
+    const int lj = S0 + 1 + c / RW0, li = S0 + 1 + c % RW0;
+    sf0[lj][li] = sf0[lj][li] - (T(4) * su0[lj][li] - su0[lj][li - 1] - su0[lj][li + 1] -
+                                 su0[lj - 1][li] - su0[lj + 1][li]);
+  }
+  // the block's level-l cells: 2 I0 + 1 .. 2 I0 + 2 kTile
+  for (int c = t; c < 4 * kTile * kTile; c += kPairThreads) {
+    const int bi = c % (2 * kTile), bj = c / (2 * kTile);
+    const int i = 2 * I0 + 1 + bi, j = 2 * J0 + 1 + bj;
+    if (i <= nf0 && j <= nf0)
+      stg(uout0, (unsigned)((j - 1) * p0 + (i - 1)), su0[j - jb0][i - ib0]);
+  }
+  __syncthreads();
+  // f_{l+1} on the level-(l+1) window (zero outside the level), stored on the tile; red start
+  for (int c = t; c < W1 * W1; c += kPairThreads) {
+    const int LJ = c / W1, LI = c % W1;
+    const int I = Ib + LI, J = Jb + LJ;
+    T v = T(0);
+    if (I >= 1 && I <= nf1 && J >= 1 && J <= nf1) {
+      const int li = 2 * I - ib0, lj = 2 * J - jb0;
+      v = sf0[lj][li] + T(0.5) * (sf0[lj][li - 1] + sf0[lj][li + 1] + sf0[lj - 1][li] +
+                                  sf0[lj + 1][li] + sf0[lj - 1][li - 1] + sf0[lj + 1][li + 1]);
+      if (LI >= H1 && LI < H1 + kTile && LJ >= H1 && LJ < H1 + kTile)
+        stg(fout1, (unsigned)((J - 1) * p1 + (I - 1)), v);
+    }
+    sf1[LJ][LI] = v;
+    su1[LJ][LI] = is_red(I, J) ? T(0.25) * v : T(0);
+  }
+  __syncthreads();
+  tile_sweeps<T, W1, 2 * NU - 1, kPairThreads>(su1, sf1, Ib, Jb, nf1, false);
+  constexpr int RW1 = kTile + 1;
+  for (int c = t; c < RW1 * RW1; c += kPairThreads) {
+    const int lj = H1 + c / RW1, li = H1 + c % RW1;
+    sf1[lj][li] = sf1[lj][li] - (T(4) * su1[lj][li] - su1[lj][li - 1] - su1[lj][li + 1] -
+                                 su1[lj - 1][li] - su1[lj + 1][li]);
+  }
+  __syncthreads();
+  {
+    const int nc = (nf1 - 1) >> 1;
+    constexpr int TC = kTile / 2;
+    if (t < TC * TC) {
+      const int J = (J0 >> 1) + 1 + t / TC, I = (I0 >> 1) + 1 + t % TC;
+      if (J <= nc && I <= nc) {
+        const int li = 2 * I - Ib, lj = 2 * J - Jb;
+        const T v = sf1[lj][li] + T(0.5) * (sf1[lj][li - 1] + sf1[lj][li + 1] + sf1[lj - 1][li] +
+                                            sf1[lj + 1][li] + sf1[lj - 1][li - 1] +
+                                            sf1[lj + 1][li + 1]);
+        stg(fout2, (unsigned)((J - 1) * p2 + (I - 1)), v);
+      }
+    }
+  }
+  for (int c = t; c < kTile * kTile; c += kPairThreads) {
+    const int bi = c % kTile, bj = c / kTile;
+    const int I = I0 + 1 + bi, J = J0 + 1 + bj;
+    if (I <= nf1 && J <= nf1) stg(uout1, (unsigned)((J - 1) * p1 + (I - 1)), su1[bj + H1][bi + H1]);
+  }
+}
+
+template <int NU>
+struct PairUp {
+  static constexpr int H = 2 * NU;                  // halo of an up window (no w = A z here)
+  static constexpr int W0 = 2 * kTile + 2 * H;      // level-l window
+  static constexpr int CW = W0 / 2 + 2;             // its coarse patch (valid part of level l+1)
+  static constexpr int W1 = CW + 2 * H;             // level-(l+1) window
+  static constexpr int CW2 = W1 / 2 + 2;            // coarse patch of level l+2
+  static constexpr int N0 = (W0 * W0 + kPairThreads - 1) / kPairThreads;
+  static constexpr int N1 = (W1 * W1 + kPairThreads - 1) / kPairThreads;
+  static constexpr int N2 = (CW2 * CW2 + kPairThreads - 1) / kPairThreads;
+};
+
+// Levels l+1 and l going up: u_{l+1} = u_{l+1,pre} + P e_{l+2}, 2 nu half-sweeps, on a window
+// whose valid part covers the coarse patch of level l; then u_l = u_{l,pre} + P e_{l+1} and 2 nu
+// half-sweeps; e_l stored on the block's level-l cells.
+template <typename T, int NU>
+__device__ __forceinline__ void d_pair_up(const T* __restrict__ f0, const T* __restrict__ u0pre,
+                                          const T* __restrict__ f1, const T* __restrict__ u1pre,
+                                          const T* __restrict__ e2, T* __restrict__ eout0, int nf0,
+                                          int p0, int p1, int p2, int tile_x, int tile_y) {
+  using G = PairUp<NU>;
+  constexpr int H = G::H, W0 = G::W0, W1 = G::W1, CW2 = G::CW2;
+  __shared__ T sf0[W0][W0 + 1];
+  __shared__ T su0[W0][W0 + 1];
+  __shared__ T sf1[W1][W1 + 1];
+  __shared__ T su1[W1][W1 + 1];
+  __shared__ T sc2[CW2][CW2 + 1];
+  const int t = flat_tid();
+  const int nf1 = (nf0 - 1) >> 1, nf2 = (nf1 - 1) >> 1;
+  const int I0 = tile_x * kTile, J0 = tile_y * kTile;
+  const int ib0 = 2 * I0 + 1 - H, jb0 = 2 * J0 + 1 - H;  // level-l window origin
+  const int Ic = ib0 >> 1, Jc = jb0 >> 1;                // its coarse patch origin (floor)
+  const int ib1 = Ic - H, jb1 = Jc - H;                  // level-(l+1) window origin
+  const int Ic2 = ib1 >> 1, Jc2 = jb1 >> 1;              // coarse patch of level l+2
+  T f1r[G::N1], u1r[G::N1], f0r[G::N0], u0r[G::N0], c2r[G::N2];
+#pragma unroll
+  for (int q = 0; q < G::N2; ++q) {
+    const int c = t + kPairThreads * q;
+    const int I = Ic2 + c % CW2, J = Jc2 + c / CW2;
+    const bool in = c < CW2 * CW2 && I >= 1 && I <= nf2 && J >= 1 && J <= nf2;
+    c2r[q] = in ? ldg(e2, (unsigned)((J - 1) * p2 + (I - 1))) : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < G::N1; ++q) {
+    const int c = t + kPairThreads * q;
+    const int i = ib1 + c % W1, j = jb1 + c / W1;
+    const bool in = c < W1 * W1 && i >= 1 && i <= nf1 && j >= 1 && j <= nf1;
+    const unsigned o = (unsigned)((j - 1) * p1 + (i - 1));
+    f1r[q] = in ? ldg(f1, o) : T(0);
+    u1r[q] = in ? ldg(u1pre, o) : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < G::N0; ++q) {
+    const int c = t + kPairThreads * q;
+    const int i = ib0 + c % W0, j = jb0 + c / W0;
+    const bool in = c < W0 * W0 && i >= 1 && i <= nf0 && j >= 1 && j <= nf0;
+    const unsigned o = (unsigned)((j - 1) * p0 + (i - 1));
+    f0r[q] = in ? ldg(f0, o) : T(0);
+    u0r[q] = in ? ldg(u0pre, o) : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < G::N2; ++q) {
+    const int c = t + kPairThreads * q;
+    if (c < CW2 * CW2) sc2[c / CW2][c % CW2] = c2r[q];
+  }
+  __syncthreads();
+  // level l+1: prolongation of e_{l+2} (the mean of the values at (i >> 1, j >> 1) and at that
+  // point shifted by the parities of (i, j)) plus the pre-smoothed iterate
+#pragma unroll
+  for (int q = 0; q < G::N1; ++q) {
+    const int c = t + kPairThreads * q;
+    if (c >= W1 * W1) continue;
+    const int lj = c / W1, li = c % W1;
+    const int i = ib1 + li, j = jb1 + lj;
+    T u = T(0);
+    if (i >= 1 && i <= nf1 && j >= 1 && j <= nf1) {
+      const int ci = (i >> 1) - Ic2, cj = (j >> 1) - Jc2;
+      const T e = T(0.5) * (sc2[cj][ci] + sc2[cj + (j & 1)][ci + (i & 1)]);
+      u = u1r[q] + e;
+    }
+    sf1[lj][li] = f1r[q];
+    su1[lj][li] = u;
+  }
+  __syncthreads();
+  tile_sweeps<T, W1, 2 * NU, kPairThreads>(su1, sf1, ib1, jb1, nf1, false);  // black, red, ...
+  // level l: the corrected level-(l+1) values on the patch are su1[H + c][H + d]
+#pragma unroll
+  for (int q = 0; q < G::N0; ++q) {
+    const int c = t + kPairThreads * q;
+    if (c >= W0 * W0) continue;
+    const int lj = c / W0, li = c % W0;
+    const int i = ib0 + li, j = jb0 + lj;
+    T u = T(0);
+    if (i >= 1 && i <= nf0 && j >= 1 && j <= nf0) {
+      const int ci = H + (i >> 1) - Ic, cj = H + (j >> 1) - Jc;
+      const T e = T(0.5) * (su1[cj][ci] + su1[cj + (j & 1)][ci + (i & 1)]);
+      u = u0r[q] + e;
+    }
+    sf0[lj][li] = f0r[q];
+    su0[lj][li] = u;
+  }
+  __syncthreads();
+  tile_sweeps<T, W0, 2 * NU, kPairThreads>(su0, sf0, ib0, jb0, nf0, false);
+  for (int c = t; c < 4 * kTile * kTile; c += kPairThreads) {
+    const int bi = c % (2 * kTile), bj = c / (2 * kTile);
+    const int i = 2 * I0 + 1 + bi, j = 2 * J0 + 1 + bj;
+    if (i <= nf0 && j <= nf0)
+      stg(eout0, (unsigned)((j - 1) * p0 + (i - 1)), su0[bj + H][bi + H]);
   }
 }
 
