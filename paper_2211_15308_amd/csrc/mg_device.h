@@ -245,6 +245,20 @@ __device__ __forceinline__ void d_mg_down(
   const int t = flat_tid();
   T fr[NW], wr[NW], sr[NW];
   T zr[NO], pr[NO], xr[NO];
+  // the partials of r.z and z.A z (CG) are loaded first: their sum is needed before any window
+  // value, and loads complete in issue order
+  constexpr int NP = CG ? 4 : 1;
+  double rzr[NP], zwr[NP];
+  // (parity selects, not indexing: a runtime index into the struct would put it in scratch)
+  const double* rzp = (k & 1) ? red.rz[1] : red.rz[0];
+  const double* zwp = (k & 1) ? red.zw[1] : red.zw[0];
+#pragma unroll
+  for (int a = 0; a < NP; ++a) {
+    const int q = t + kBlock * a;
+    const bool ok = CG && q < red.nb0;
+    rzr[a] = ok ? ldg(rzp, (unsigned)q) : 0.0;
+    zwr[a] = ok ? ldg(zwp, (unsigned)q) : 0.0;
+  }
 #pragma unroll
   for (int q = 0; q < NW; ++q) {
     const int c = t + kBlock * q;
@@ -273,10 +287,12 @@ __device__ __forceinline__ void d_mg_down(
   T alpha = T(0), beta = T(0);
   if (CG) {
     double gam = 0.0, del = 0.0;
-    // (parity selects, not indexing: a runtime index into the struct would put it in scratch)
-    const double* rzp = (k & 1) ? red.rz[1] : red.rz[0];
-    const double* zwp = (k & 1) ? red.zw[1] : red.zw[0];
-    for (int q = t; q < red.nb0; q += kBlock) {
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+      gam += rzr[a];
+      del += zwr[a];
+    }
+    for (int q = t + kBlock * NP; q < red.nb0; q += kBlock) {
       gam += ldg(rzp, (unsigned)q);
       del += ldg(zwp, (unsigned)q);
     }

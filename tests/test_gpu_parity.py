@@ -44,9 +44,11 @@ def announce():
 
 
 @pytest.mark.parametrize("precision", [F.FDD_FP64, F.FDD_MIXED])
-@pytest.mark.parametrize("n", [4, 8, 16, 64, 96, 120])
+@pytest.mark.parametrize("n", [4, 8, 16, 64, 96, 120, 256, 512])
 def test_interior_solve(n, precision):
-    # 96: 95 -> 47 -> 23 -> 11 -> 5 (dense coarsest 5 x 5); 120: 119 -> 59 -> 29 -> 14 (even)
+    # 96: 95 -> 47 -> 23 -> 11 -> 5 (dense coarsest 5 x 5); 120: 119 -> 59 -> 29 -> 14 (even);
+    # 256: one tiled intermediate level (255 -> 127) above the sine-transform solve of 63 x 63;
+    # 512: two intermediate levels (255, 127) run as one pair kernel each way (FP32)
     print(f"[interior] n={n} precision={precision}", flush=True)
     P = make(n)
     R = system.Riesz(2, n, 1.0, 1.0) if n <= 64 else None
@@ -240,12 +242,11 @@ def test_error_paths():
     assert rel(host(x), system.solve_dst_2d(n, 1.0, 1.0, b)) <= 1e-8
 
 
-@pytest.mark.parametrize("precision", [F.FDD_MIXED, F.FDD_FP64])
-def test_graph_replay_matches_eager_launches(precision):
+@pytest.mark.parametrize("precision,n", [(F.FDD_MIXED, 256), (F.FDD_FP64, 256), (F.FDD_MIXED, 512)])
+def test_graph_replay_matches_eager_launches(precision, n):
     # each outer iteration is replayed from a captured graph; replays (with eager work and
     # synchronizations in between) must give bit-identical results to eager launches
-    n = 256
-    print(f"[graph] precision={precision}", flush=True)
+    print(f"[graph] precision={precision} n={n}", flush=True)
     P = make(n, 1e-2, 1e-3)
     TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
     TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
