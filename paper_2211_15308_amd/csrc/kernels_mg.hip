@@ -132,6 +132,10 @@ static inline dim3 tiles(int nf) {
   return dim3(t, t);
 }
 static inline dim3 tblock() { return dim3(32, kBlock / 32); }
+static inline dim3 ptiles(int nf) {
+  const int t = (nf + kPairTile - 1) / kPairTile;
+  return dim3(t, t);
+}
 
 template <typename T, int NU>
 static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check) {
@@ -148,7 +152,7 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
     const int chk = l == 1 ? check : 0;
     if (pair(l)) {
       if constexpr (kPairs)
-        hipLaunchKernelGGL((k_pair_down<float, NU>), tiles(c.lev[l + 1].nf), pblock, 0, c.stream,
+        hipLaunchKernelGGL((k_pair_down<float, NU>), ptiles(c.lev[l + 1].nf), pblock, 0, c.stream,
                            (const float*)mg.f[l], mg.u[l], mg.f[l + 1], mg.u[l + 1], mg.f[l + 2],
                            L.nf, L.pitch, c.lev[l + 1].pitch, c.lev[l + 2].pitch, c.st, c.red, chk);
     } else {
@@ -192,7 +196,7 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
   if constexpr (kPairs) {
     for (; l >= 2; l -= 2) {
       const int a = l - 1;  // the pair (a, a + 1)
-      hipLaunchKernelGGL((k_pair_up<float, NU>), tiles(c.lev[a + 1].nf), pblock, 0, c.stream,
+      hipLaunchKernelGGL((k_pair_up<float, NU>), ptiles(c.lev[a + 1].nf), pblock, 0, c.stream,
                          (const float*)mg.f[a], (const float*)mg.u[a], (const float*)mg.f[a + 1],
                          (const float*)mg.u[a + 1], (const float*)mg.e[a + 2], mg.e[a],
                          c.lev[a].nf, c.lev[a].pitch, c.lev[a + 1].pitch, c.lev[a + 2].pitch,

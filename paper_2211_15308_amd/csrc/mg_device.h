@@ -497,7 +497,7 @@ __device__ __forceinline__ void d_mg_up(
 // --------------------------------------------------------------------------------------------
 // two intermediate levels in one kernel
 // --------------------------------------------------------------------------------------------
-// A block of kPairThreads threads owns a kTile x kTile tile of level l+1 and the 2 kTile x 2 kTile
+// A block of kPairThreads threads owns a kPairTile x kPairTile tile of level l+1 and the 2 kPairTile x 2 kPairTile
 // level-l cells above it.  Going down it smooths level l on a window wide enough that the
 // restricted residual gives f_{l+1} on the whole level-(l+1) window, then does level l+1 as the
 // tiled kernel does; going up it corrects and smooths level l+1 on a window whose valid part is
@@ -505,11 +505,12 @@ __device__ __forceinline__ void d_mg_up(
 // cell is that of the single-level kernels (the redundantly computed halos are discarded), so the
 // results are bit-identical to them; one launch and one inter-kernel gap fewer per level pair.
 constexpr int kPairThreads = 1024;
+constexpr int kPairTile = 16;  // level-(l+1) tile edge of a pair block
 
 template <int NU>
 struct PairDown {
   static constexpr int H1 = 2 * NU + 1;               // level-(l+1) halo, as the tiled kernel
-  static constexpr int W1 = kTile + 2 * H1;           // level-(l+1) window
+  static constexpr int W1 = kPairTile + 2 * H1;           // level-(l+1) window
   // level l: r_l on 2 W1 + 1 cells, u_l valid one further, 2 NU - 1 half-sweeps after the red
   // start each lose one cell at the edge; one more column and row make the sweep extent even
   static constexpr int S0 = 2 * NU - 1;
@@ -533,7 +534,7 @@ __device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __res
   __shared__ T su1[W1][W1 + 1];
   const int t = flat_tid();
   const int nf1 = (nf0 - 1) >> 1;
-  const int I0 = tile_x * kTile, J0 = tile_y * kTile;
+  const int I0 = tile_x * kPairTile, J0 = tile_y * kPairTile;
   const int Ib = I0 + 1 - H1, Jb = J0 + 1 - H1;          // level-(l+1) window origin
   const int ib0 = 2 * Ib - 2 - S0, jb0 = 2 * Jb - 2 - S0;  // level-l window origin
   T fr[G::N0];
@@ -563,9 +564,9 @@ __device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __res
     sf0[lj][li] = sf0[lj][li] - (T(4) * su0[lj][li] - su0[lj][li - 1] - su0[lj][li + 1] -
                                  su0[lj - 1][li] - su0[lj + 1][li]);
   }
-  // the block's level-l cells: 2 I0 + 1 .. 2 I0 + 2 kTile
-  for (int c = t; c < 4 * kTile * kTile; c += kPairThreads) {
-    const int bi = c % (2 * kTile), bj = c / (2 * kTile);
+  // the block's level-l cells: 2 I0 + 1 .. 2 I0 + 2 kPairTile
+  for (int c = t; c < 4 * kPairTile * kPairTile; c += kPairThreads) {
+    const int bi = c % (2 * kPairTile), bj = c / (2 * kPairTile);
     const int i = 2 * I0 + 1 + bi, j = 2 * J0 + 1 + bj;
     if (i <= nf0 && j <= nf0)
       stg(uout0, (unsigned)((j - 1) * p0 + (i - 1)), su0[j - jb0][i - ib0]);
@@ -580,7 +581,7 @@ __device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __res
       const int li = 2 * I - ib0, lj = 2 * J - jb0;
       v = sf0[lj][li] + T(0.5) * (sf0[lj][li - 1] + sf0[lj][li + 1] + sf0[lj - 1][li] +
                                   sf0[lj + 1][li] + sf0[lj - 1][li - 1] + sf0[lj + 1][li + 1]);
-      if (LI >= H1 && LI < H1 + kTile && LJ >= H1 && LJ < H1 + kTile)
+      if (LI >= H1 && LI < H1 + kPairTile && LJ >= H1 && LJ < H1 + kPairTile)
         stg(fout1, (unsigned)((J - 1) * p1 + (I - 1)), v);
     }
     sf1[LJ][LI] = v;
@@ -588,7 +589,7 @@ __device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __res
   }
   __syncthreads();
   tile_sweeps<T, W1, 2 * NU - 1, kPairThreads>(su1, sf1, Ib, Jb, nf1, false);
-  constexpr int RW1 = kTile + 1;
+  constexpr int RW1 = kPairTile + 1;
   for (int c = t; c < RW1 * RW1; c += kPairThreads) {
     const int lj = H1 + c / RW1, li = H1 + c % RW1;
     sf1[lj][li] = sf1[lj][li] - (T(4) * su1[lj][li] - su1[lj][li - 1] - su1[lj][li + 1] -
@@ -597,7 +598,7 @@ __device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __res
   __syncthreads();
   {
     const int nc = (nf1 - 1) >> 1;
-    constexpr int TC = kTile / 2;
+    constexpr int TC = kPairTile / 2;
     if (t < TC * TC) {
       const int J = (J0 >> 1) + 1 + t / TC, I = (I0 >> 1) + 1 + t % TC;
       if (J <= nc && I <= nc) {
@@ -609,8 +610,8 @@ __device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __res
       }
     }
   }
-  for (int c = t; c < kTile * kTile; c += kPairThreads) {
-    const int bi = c % kTile, bj = c / kTile;
+  for (int c = t; c < kPairTile * kPairTile; c += kPairThreads) {
+    const int bi = c % kPairTile, bj = c / kPairTile;
     const int I = I0 + 1 + bi, J = J0 + 1 + bj;
     if (I <= nf1 && J <= nf1) stg(uout1, (unsigned)((J - 1) * p1 + (I - 1)), su1[bj + H1][bi + H1]);
   }
@@ -619,7 +620,7 @@ __device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __res
 template <int NU>
 struct PairUp {
   static constexpr int H = 2 * NU;                  // halo of an up window (no w = A z here)
-  static constexpr int W0 = 2 * kTile + 2 * H;      // level-l window
+  static constexpr int W0 = 2 * kPairTile + 2 * H;      // level-l window
   static constexpr int CW = W0 / 2 + 2;             // its coarse patch (valid part of level l+1)
   static constexpr int W1 = CW + 2 * H;             // level-(l+1) window
   static constexpr int CW2 = W1 / 2 + 2;            // coarse patch of level l+2
@@ -645,7 +646,7 @@ __device__ __forceinline__ void d_pair_up(const T* __restrict__ f0, const T* __r
   __shared__ T sc2[CW2][CW2 + 1];
   const int t = flat_tid();
   const int nf1 = (nf0 - 1) >> 1, nf2 = (nf1 - 1) >> 1;
-  const int I0 = tile_x * kTile, J0 = tile_y * kTile;
+  const int I0 = tile_x * kPairTile, J0 = tile_y * kPairTile;
   const int ib0 = 2 * I0 + 1 - H, jb0 = 2 * J0 + 1 - H;  // level-l window origin
   const int Ic = ib0 >> 1, Jc = jb0 >> 1;                // its coarse patch origin (floor)
   const int ib1 = Ic - H, jb1 = Jc - H;                  // level-(l+1) window origin
@@ -719,8 +720,8 @@ __device__ __forceinline__ void d_pair_up(const T* __restrict__ f0, const T* __r
   }
   __syncthreads();
   tile_sweeps<T, W0, 2 * NU, kPairThreads>(su0, sf0, ib0, jb0, nf0, false);
-  for (int c = t; c < 4 * kTile * kTile; c += kPairThreads) {
-    const int bi = c % (2 * kTile), bj = c / (2 * kTile);
+  for (int c = t; c < 4 * kPairTile * kPairTile; c += kPairThreads) {
+    const int bi = c % (2 * kPairTile), bj = c / (2 * kPairTile);
     const int i = 2 * I0 + 1 + bi, j = 2 * J0 + 1 + bj;
     if (i <= nf0 && j <= nf0)
       stg(eout0, (unsigned)((j - 1) * p0 + (i - 1)), su0[bj + H][bi + H]);
