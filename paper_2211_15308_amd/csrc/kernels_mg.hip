@@ -31,7 +31,7 @@ namespace fdd {
 // single-instance kernels
 // --------------------------------------------------------------------------------------------
 
-template <typename T, int NU, bool CG>
+template <typename T, int NU, bool CG, int TT = kTile>
 __global__ __launch_bounds__(kBlock) void k_mg_down(
     const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
     int pc, const T* __restrict__ w, const T* __restrict__ sold, T* __restrict__ snew,
@@ -41,11 +41,11 @@ __global__ __launch_bounds__(kBlock) void k_mg_down(
   if (check && pcg_converged(st, red, block0())) return;
   int tile_x, tile_y;
   const int tile = xcd_tile(&tile_x, &tile_y);
-  d_mg_down<T, NU, CG>(fin, uout, fc, nf, pitch, pc, w, sold, snew, z, pold, pnew, x, rout, st,
-                       red, k, tile_x, tile_y, tile, block0());
+  d_mg_down<T, NU, CG, TT>(fin, uout, fc, nf, pitch, pc, w, sold, snew, z, pold, pnew, x, rout,
+                           st, red, k, tile_x, tile_y, tile, block0());
 }
 
-template <typename T, int NU, bool CG>
+template <typename T, int NU, bool CG, int TT = kTile>
 __global__ __launch_bounds__(kBlock) void k_mg_up(
     const T* __restrict__ fin, const T* __restrict__ upre, const T* __restrict__ ec,
     T* __restrict__ eout, T* __restrict__ wout, int nf, int pitch, int pc, DevState* st,
@@ -53,8 +53,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_up(
   if (stopped(st)) return;
   int tile_x, tile_y;
   const int tile = xcd_tile(&tile_x, &tile_y);
-  d_mg_up<T, NU, CG>(fin, upre, ec, eout, wout, nf, pitch, pc, st, red, kn, count_iteration,
-                     tile_x, tile_y, tile, block0());
+  d_mg_up<T, NU, CG, TT>(fin, upre, ec, eout, wout, nf, pitch, pc, st, red, kn,
+                         count_iteration, tile_x, tile_y, tile, block0());
 }
 
 template <typename T, int NU>
@@ -132,6 +132,13 @@ static inline dim3 tiles(int nf) {
   return dim3(t, t);
 }
 static inline dim3 tblock() { return dim3(32, kBlock / 32); }
+// intermediate levels that run alone use 16 x 16 tiles: they are latency-bound, and smaller
+// tiles spread them over four times the compute units with a third of the window per block
+constexpr int kMidTile = 16;
+static inline dim3 mtiles(int nf) {
+  const int t = (nf + kMidTile - 1) / kMidTile;
+  return dim3(t, t);
+}
 static inline dim3 ptiles(int nf) {
   const int t = (nf + kPairTile - 1) / kPairTile;
   return dim3(t, t);
@@ -156,8 +163,8 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
                            (const float*)mg.f[l], mg.u[l], mg.f[l + 1], mg.u[l + 1], mg.f[l + 2],
                            L.nf, L.pitch, c.lev[l + 1].pitch, c.lev[l + 2].pitch, c.st, c.red, chk);
     } else {
-      hipLaunchKernelGGL((k_mg_down<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, mg.f[l],
-                         mg.u[l], mg.f[l + 1], L.nf, L.pitch, c.lev[l + 1].pitch,
+      hipLaunchKernelGGL((k_mg_down<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0, c.stream,
+                         mg.f[l], mg.u[l], mg.f[l + 1], L.nf, L.pitch, c.lev[l + 1].pitch,
                          (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (const T*)nullptr,
                          (const T*)nullptr, (T*)nullptr, (T*)nullptr, (T*)nullptr, c.st, c.red, 0,
                          chk);
@@ -182,13 +189,13 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
   int l = fc - 1;
   for (; !kPairs && l >= 1; --l) {
     const Level& L = c.lev[l];
-    hipLaunchKernelGGL((k_mg_up<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, mg.f[l],
+    hipLaunchKernelGGL((k_mg_up<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0, c.stream, mg.f[l],
                        mg.u[l], mg.e[l + 1], mg.e[l], (T*)nullptr, L.nf, L.pitch,
                        c.lev[l + 1].pitch, c.st, c.red, 0, 0);
   }
   if (kPairs && ntiled % 2 == 1) {
     const Level& L = c.lev[l];
-    hipLaunchKernelGGL((k_mg_up<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, mg.f[l],
+    hipLaunchKernelGGL((k_mg_up<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0, c.stream, mg.f[l],
                        mg.u[l], mg.e[l + 1], mg.e[l], (T*)nullptr, L.nf, L.pitch,
                        c.lev[l + 1].pitch, c.st, c.red, 0, 0);
     --l;

@@ -200,9 +200,10 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
 // --------------------------------------------------------------------------------------------
 // fused level kernels
 // --------------------------------------------------------------------------------------------
-// The tiled kernels run 256 threads on a kTile x kTile tile plus a halo.  Window cells are
-// enumerated row-major over the flat thread index (cell t + 256 q), own cells likewise over the
-// tile (8 rows of 32 per pass), so loads are row-contiguous and no lane idles on a short row.
+// The tiled kernels run 256 threads on a TT x TT tile plus a halo (TT = kTile = 32 on the
+// finest level, 16 on an intermediate level that runs alone).  Window cells are enumerated
+// row-major over the flat thread index (cell t + 256 q), own cells likewise over the tile, so
+// loads are row-contiguous and no lane idles on a short row.
 // All global loads of a window are issued into registers before the first use, so a block waits
 // for one memory latency.
 
@@ -227,7 +228,7 @@ constexpr int kOwnSlots = kTile * kTile / kBlock;
 //   and alpha_{k-1} recorded by the previous iteration.  On the window s_k = w_k + beta_k s_{k-1}
 //   and f = r_{k+1} = r_k - alpha_k s_k; on own points p_k = z_k + beta_k p_{k-1},
 //   x += alpha_k p_k, and r_{k+1}, s_k, p_k are stored; ||r_{k+1}||^2 goes to red.rr.
-template <typename T, int NU, bool CG>
+template <typename T, int NU, bool CG, int TT = kTile>
 __device__ __forceinline__ void d_mg_down(
     const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
     int pc, const T* __restrict__ w, const T* __restrict__ sold, T* __restrict__ snew,
@@ -235,12 +236,12 @@ __device__ __forceinline__ void d_mg_down(
     T* __restrict__ rout, DevState* st, const Reductions& red, int k, int tile_x, int tile_y,
     int tile, bool lead) {
   constexpr int H = 2 * NU + 1;
-  constexpr int W = kTile + 2 * H;
+  constexpr int W = TT + 2 * H;
   constexpr int NW = Flat<W>::N;
-  constexpr int NO = CG ? kOwnSlots : 1;
+  constexpr int NO = CG ? (TT * TT / kBlock) : 1;
   __shared__ T sf[W][W + 1];
   __shared__ T su[W][W + 1];
-  const int i0 = tile_x * kTile, j0 = tile_y * kTile;
+  const int i0 = tile_x * TT, j0 = tile_y * TT;
   const int ib = i0 + 1 - H, jb = j0 + 1 - H;  // global index of window cell (0, 0)
   const int t = flat_tid();
   T fr[NW], wr[NW], sr[NW];
@@ -276,7 +277,7 @@ __device__ __forceinline__ void d_mg_down(
 #pragma unroll
     for (int q = 0; q < NO; ++q) {
       const int c = t + kBlock * q;
-      const int i = i0 + 1 + (c % kTile), j = j0 + 1 + c / kTile;
+      const int i = i0 + 1 + (c % TT), j = j0 + 1 + c / TT;
       const bool in = i <= nf && j <= nf;
       const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
       zr[q] = in ? ldg(z, o) : T(0);
@@ -329,7 +330,7 @@ __device__ __forceinline__ void d_mg_down(
     if (CG) {
       const T sv = wr[q] + beta * sr[q];
       f = f - alpha * sv;
-      const bool own = li >= H && li < H + kTile && lj >= H && lj < H + kTile && i <= nf &&
+      const bool own = li >= H && li < H + TT && lj >= H && lj < H + TT && i <= nf &&
                        j <= nf;
       if (own) {
         const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
@@ -346,7 +347,7 @@ __device__ __forceinline__ void d_mg_down(
 #pragma unroll
     for (int q = 0; q < NO; ++q) {
       const int c = t + kBlock * q;
-      const int i = i0 + 1 + (c % kTile), j = j0 + 1 + c / kTile;
+      const int i = i0 + 1 + (c % TT), j = j0 + 1 + c / TT;
       if (i > nf || j > nf) continue;
       const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
       const T pv = zr[q] + beta * pr[q];
@@ -357,8 +358,8 @@ __device__ __forceinline__ void d_mg_down(
   __syncthreads();
   tile_sweeps<T, W, 2 * NU - 1>(su, sf, ib, jb, nf, false);  // black, red, black, ...
   // residual, in place of f, on the cells the restriction reads (window rows and columns
-  // H .. H + kTile); each reads its own f and the neighbours' u
-  constexpr int RW = kTile + 1;
+  // H .. H + TT); each reads its own f and the neighbours' u
+  constexpr int RW = TT + 1;
   for (int c = t; c < RW * RW; c += kBlock) {
     const int lj = H + c / RW, li = H + c % RW;
     sf[lj][li] = sf[lj][li] - (T(4) * su[lj][li] - su[lj][li - 1] - su[lj][li + 1] -
@@ -368,10 +369,10 @@ __device__ __forceinline__ void d_mg_down(
   // restriction to the coarse points whose fine index 2I lies in this tile (one per thread)
   {
     const int nc = (nf - 1) >> 1;
-    constexpr int TC = kTile / 2;
-    static_assert(TC * TC == kBlock, "one coarse point per thread");
+    constexpr int TC = TT / 2;
+    static_assert(TC * TC <= kBlock, "at most one coarse point per thread");
     const int J = (j0 >> 1) + 1 + t / TC, I = (i0 >> 1) + 1 + t % TC;
-    if (J <= nc && I <= nc) {
+    if (t < TC * TC && J <= nc && I <= nc) {
       const int li = 2 * I - ib, lj = 2 * J - jb;
       const T v = sf[lj][li] + T(0.5) * (sf[lj][li - 1] + sf[lj][li + 1] + sf[lj - 1][li] +
                                          sf[lj + 1][li] + sf[lj - 1][li - 1] + sf[lj + 1][li + 1]);
@@ -380,9 +381,9 @@ __device__ __forceinline__ void d_mg_down(
   }
   // store the pre-smoothed iterate on own points
 #pragma unroll
-  for (int q = 0; q < kOwnSlots; ++q) {
+  for (int q = 0; q < (TT * TT / kBlock); ++q) {
     const int c = t + kBlock * q;
-    const int bi = c % kTile, bj = c / kTile;
+    const int bi = c % TT, bj = c / TT;
     const int i = i0 + 1 + bi, j = j0 + 1 + bj;
     if (j > nf || i > nf) continue;
     stg(uout, (unsigned)((j - 1) * pitch + (i - 1)), su[bj + H][bi + H]);
@@ -397,21 +398,21 @@ __device__ __forceinline__ void d_mg_down(
 // CG = true (level 0): the result z is kept valid one cell beyond the tile, so that w = A z is
 // formed on own points too; z and w are stored and the block's parts of r . z and z . w go to
 // red.rz[kn & 1] and red.zw[kn & 1] (f is r).
-template <typename T, int NU, bool CG>
+template <typename T, int NU, bool CG, int TT = kTile>
 __device__ __forceinline__ void d_mg_up(
     const T* __restrict__ fin, const T* __restrict__ upre, const T* __restrict__ ec,
     T* __restrict__ eout, T* __restrict__ wout, int nf, int pitch, int pc, DevState* st,
     const Reductions& red, int kn, int count_iteration, int tile_x, int tile_y, int tile,
     bool lead) {
   constexpr int H = 2 * NU + (CG ? 1 : 0);
-  constexpr int W = kTile + 2 * H;
+  constexpr int W = TT + 2 * H;
   constexpr int NW = Flat<W>::N;
   constexpr int CW = W / 2 + 2;  // coarse patch edge
   constexpr int NC = Flat<CW>::N;
   __shared__ T sf[W][W + 1];
   __shared__ T su[W][W + 1];
   __shared__ T sc[CW][CW + 1];
-  const int i0 = tile_x * kTile, j0 = tile_y * kTile;
+  const int i0 = tile_x * TT, j0 = tile_y * TT;
   const int ib = i0 + 1 - H, jb = j0 + 1 - H;
   const int Ib = ib >> 1, Jb = jb >> 1;  // floor (arithmetic shift)
   const int nc = (nf - 1) >> 1;
@@ -464,9 +465,9 @@ __device__ __forceinline__ void d_mg_up(
   tile_sweeps<T, W, 2 * NU>(su, sf, ib, jb, nf, false);  // black, red, ...
   double rz = 0.0, zw = 0.0;
 #pragma unroll
-  for (int q = 0; q < kOwnSlots; ++q) {
+  for (int q = 0; q < (TT * TT / kBlock); ++q) {
     const int c = t + kBlock * q;
-    const int bi = c % kTile, bj = c / kTile;
+    const int bi = c % TT, bj = c / TT;
     const int i = i0 + 1 + bi, j = j0 + 1 + bj;
     if (j > nf || i > nf) continue;
     const int lj = bj + H, li = bi + H;
