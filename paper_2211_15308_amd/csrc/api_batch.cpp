@@ -35,6 +35,7 @@ struct fdd_batch_s {
   // launch geometry
   int max_tiled = 1;
   int tiles_total[kMaxLevels] = {};
+  int tile_edge[kMaxLevels] = {};  // kTile, or kMidTile on intermediate levels with few tiles
   int sysP_total = 0, sysH_total = 0;
   std::vector<int> tiles_prefix[kMaxLevels];
   std::vector<int> sysP_prefix, sysH_prefix;
@@ -96,7 +97,8 @@ BInst make_inst(const fdd_batch_s* B, int i, const double* b, double* x) {
   for (int l = 0; l < P->nlev; ++l) {
     I.nf[l] = P->lev[l].nf;
     I.pitch[l] = P->lev[l].pitch;
-    I.tiles_x[l] = l < I.fc ? (P->lev[l].nf + kTile - 1) / kTile : 0;
+    const int tt = B->tile_edge[l];  // tile edge of the level (as the tile lists)
+    I.tiles_x[l] = l < I.fc ? (P->lev[l].nf + tt - 1) / tt : 0;
     I.f[l] = P->s32.mg.f[l];
     I.u[l] = P->s32.mg.u[l];
     I.e[l] = P->s32.mg.e[l];
@@ -147,7 +149,10 @@ BatchCtx make_bctx(const fdd_batch_s* B, hipStream_t s, int nu, int skip_done) {
   c.lists.ninst = B->count;
   c.nu = nu;
   c.max_tiled = B->max_tiled;
-  for (int l = 0; l < kMaxLevels; ++l) c.tiles_total[l] = B->tiles_total[l];
+  for (int l = 0; l < kMaxLevels; ++l) {
+    c.tiles_total[l] = B->tiles_total[l];
+    c.tile_edge[l] = B->tile_edge[l];
+  }
   c.sysP_total = B->sysP_total;
   c.sysH_total = B->sysH_total;
   c.skip_done = skip_done;
@@ -319,13 +324,23 @@ int fdd_batch_create(int count, const fdd_problem* probs, const fdd_ratpc* P, co
   B->max_tiled = 1;
   for (int i = 0; i < count; ++i) B->max_tiled = std::max(B->max_tiled, probs[i]->first_coarse32);
   for (int l = 0; l < kMaxLevels; ++l) {
+    // an intermediate level with fewer than four 32 x 32 tiles per compute unit over the batch is
+    // latency-bound: 16 x 16 tiles spread it further; otherwise the larger tiles re-read less halo
+    int t32 = 0;
+    for (int i = 0; i < count; ++i)
+      if (l < probs[i]->first_coarse32) {
+        const int tx = (probs[i]->lev[l].nf + kTile - 1) / kTile;
+        t32 += tx * tx;
+      }
+    B->tile_edge[l] = (l > 0 && t32 < 4 * 256) ? kMidTile : kTile;
     auto& pre = B->tiles_prefix[l];
     pre.assign(count + 1, 0);
     for (int i = 0; i < count; ++i) {
       const fdd_problem_s* Q = probs[i];
       int t = 0;
       if (l < Q->first_coarse32) {
-        const int tx = (Q->lev[l].nf + kTile - 1) / kTile;
+        const int tt = B->tile_edge[l];
+        const int tx = (Q->lev[l].nf + tt - 1) / tt;
         t = tx * tx;
       }
       pre[i + 1] = pre[i] + t;

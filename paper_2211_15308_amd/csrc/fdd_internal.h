@@ -11,6 +11,8 @@ namespace fdd {
 constexpr int kMaxLevels = 16;
 constexpr int kMaxPoles = 64;
 constexpr int kTile = 32;            // fine-grid tile edge of the fused multigrid kernels
+constexpr int kMidTile = 16;         // tile edge of an intermediate level (latency-bound: small
+                                     // tiles spread it over more compute units)
 constexpr int kBlock = 256;          // threads per block of the tiled kernels
 constexpr int kCoarseThreads = 1024; // threads of the single-workgroup coarse V-cycle
 constexpr int kMaxCoarsestNf = 16;   // dense inverse on the coarsest grid up to 16 x 16 points
@@ -234,6 +236,7 @@ struct BatchCtx {
   int nu;
   int max_tiled;                      // largest number of tiled levels over the instances
   int tiles_total[kMaxLevels];        // grid sizes of the tiled levels
+  int tile_edge[kMaxLevels];          // tile edge of each tiled level (kTile or kMidTile)
   int sysP_total, sysH_total;
   int skip_done;                      // kernels skip instances whose outer PCG has converged
 };

@@ -46,7 +46,7 @@ __device__ __forceinline__ bool tail_idle(const DevState* st, int skip_done) {
   return (skip_done && st->outer_done) || !st->solve_done;
 }
 
-template <int NU, bool CG>
+template <int NU, bool CG, int TT>
 __global__ __launch_bounds__(kBlock) void kb_mg_down(const BInst* __restrict__ I, BLists L,
                                                      int level, int k, int cur_r, int cur_p,
                                                      int check, int skip_done) {
@@ -62,21 +62,21 @@ __global__ __launch_bounds__(kBlock) void kb_mg_down(const BInst* __restrict__ I
   const bool lead = (t == 0);
   const Reductions red = P.red;
   if (check && level == 1 && pcg_converged(st, red, lead)) return;
-  if (CG) {
-    d_mg_down<float, NU, true>(P.r[cur_r], P.u[0], P.f[1], P.nf[0], P.pitch[0],
+  if constexpr (CG) {
+    d_mg_down<float, NU, true, TT>(P.r[cur_r], P.u[0], P.f[1], P.nf[0], P.pitch[0],
                                P.pitch[1], P.w, P.s[cur_p], P.s[cur_p ^ 1],
                                P.z, P.p[cur_p], P.p[cur_p ^ 1], P.x,
                                P.r[cur_r ^ 1], st, red, k, tile_x, tile_y, t, lead);
   } else {
     const float* fin = level == 0 ? P.r[cur_r] : P.f[level];
-    d_mg_down<float, NU, false>(fin, P.u[level], P.f[level + 1], P.nf[level],
+    d_mg_down<float, NU, false, TT>(fin, P.u[level], P.f[level + 1], P.nf[level],
                                 P.pitch[level], P.pitch[level + 1], nullptr, nullptr, nullptr,
                                 nullptr, nullptr, nullptr, nullptr, nullptr, st, red, 0, tile_x,
                                 tile_y, t, lead);
   }
 }
 
-template <int NU, bool CG>
+template <int NU, bool CG, int TT>
 __global__ __launch_bounds__(kBlock) void kb_mg_up(const BInst* __restrict__ I, BLists L,
                                                    int level, int kn, int count, int cur_r,
                                                    int skip_done) {
@@ -91,12 +91,12 @@ __global__ __launch_bounds__(kBlock) void kb_mg_up(const BInst* __restrict__ I, 
   const int tile_x = t % tx, tile_y = t / tx;
   const bool lead = (t == 0);
   const Reductions red = P.red;
-  if (CG) {
-    d_mg_up<float, NU, true>(P.r[cur_r], P.u[0], P.e[1], P.z, P.w,
+  if constexpr (CG) {
+    d_mg_up<float, NU, true, TT>(P.r[cur_r], P.u[0], P.e[1], P.z, P.w,
                              P.nf[0], P.pitch[0], P.pitch[1], st, red, kn, count, tile_x, tile_y,
                              t, lead);
   } else {
-    d_mg_up<float, NU, false>(P.f[level], P.u[level], P.e[level + 1],
+    d_mg_up<float, NU, false, TT>(P.f[level], P.u[level], P.e[level + 1],
                               P.e[level], nullptr, P.nf[level], P.pitch[level],
                               P.pitch[level + 1], st, red, 0, 0, tile_x, tile_y, t, lead);
   }
@@ -270,29 +270,39 @@ template <int NU>
 static void b_tail(const BatchCtx& c, int check) {
   for (int l = 1; l < c.max_tiled; ++l)
     if (c.tiles_total[l] > 0)
-      hipLaunchKernelGGL((kb_mg_down<NU, false>), dim3(c.tiles_total[l]), tb(), 0, c.stream,
-                         c.inst, c.lists, l, 0, 0, 0, check, c.skip_done);
+      if (c.tile_edge[l] == kMidTile)
+        hipLaunchKernelGGL((kb_mg_down<NU, false, kMidTile>), dim3(c.tiles_total[l]), tb(), 0,
+                           c.stream, c.inst, c.lists, l, 0, 0, 0, check, c.skip_done);
+      else
+        hipLaunchKernelGGL((kb_mg_down<NU, false, kTile>), dim3(c.tiles_total[l]), tb(), 0,
+                           c.stream, c.inst, c.lists, l, 0, 0, 0, check, c.skip_done);
   launch_timed(c.hook, kTimeCoarse, kb_coarse, dim3(c.lists.ninst), dim3(kCoarseThreads),
                c.stream, c.inst, check, c.skip_done);
   for (int l = c.max_tiled - 1; l >= 1; --l)
     if (c.tiles_total[l] > 0)
-      hipLaunchKernelGGL((kb_mg_up<NU, false>), dim3(c.tiles_total[l]), tb(), 0, c.stream, c.inst,
-                         c.lists, l, 0, 0, 0, c.skip_done);
+      if (c.tile_edge[l] == kMidTile)
+        hipLaunchKernelGGL((kb_mg_up<NU, false, kMidTile>), dim3(c.tiles_total[l]), tb(), 0,
+                           c.stream, c.inst, c.lists, l, 0, 0, 0, c.skip_done);
+      else
+        hipLaunchKernelGGL((kb_mg_up<NU, false, kTile>), dim3(c.tiles_total[l]), tb(), 0,
+                           c.stream, c.inst, c.lists, l, 0, 0, 0, c.skip_done);
 }
 
 template <int NU>
 static void b_step(const BatchCtx& c, int rhs, int ver, int its, int S, int& cur_r, int& cur_p) {
   // PCG start: z = V r, w = A z, r.z and z.w
-  hipLaunchKernelGGL((kb_mg_down<NU, false>), dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst,
-                     c.lists, 0, 0, cur_r, cur_p, 0, c.skip_done);
+  hipLaunchKernelGGL((kb_mg_down<NU, false, kTile>), dim3(c.tiles_total[0]), tb(), 0, c.stream,
+                     c.inst, c.lists, 0, 0, cur_r, cur_p, 0, c.skip_done);
   b_tail<NU>(c, 0);
-  hipLaunchKernelGGL((kb_mg_up<NU, true>), dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst,
-                     c.lists, 0, 0, 0, cur_r, c.skip_done);
+  hipLaunchKernelGGL((kb_mg_up<NU, true, kTile>), dim3(c.tiles_total[0]), tb(), 0, c.stream,
+                     c.inst, c.lists, 0, 0, 0, cur_r, c.skip_done);
   for (int k = 0; k < its; ++k) {
-    launch_timed(c.hook, kTimeDown0, kb_mg_down<NU, true>, dim3(c.tiles_total[0]), tb(), c.stream,
+    launch_timed(c.hook, kTimeDown0, kb_mg_down<NU, true, kTile>, dim3(c.tiles_total[0]), tb(),
+                 c.stream,
                  c.inst, c.lists, 0, k, cur_r, cur_p, 0, c.skip_done);
     b_tail<NU>(c, 1);
-    launch_timed(c.hook, kTimeUp0, kb_mg_up<NU, true>, dim3(c.tiles_total[0]), tb(), c.stream,
+    launch_timed(c.hook, kTimeUp0, kb_mg_up<NU, true, kTile>, dim3(c.tiles_total[0]), tb(),
+                 c.stream,
                  c.inst, c.lists, 0, k + 1, 1, cur_r ^ 1, c.skip_done);
     cur_r ^= 1;
     cur_p ^= 1;

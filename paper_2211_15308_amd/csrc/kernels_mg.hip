@@ -132,9 +132,6 @@ static inline dim3 tiles(int nf) {
   return dim3(t, t);
 }
 static inline dim3 tblock() { return dim3(32, kBlock / 32); }
-// intermediate levels that run alone use 16 x 16 tiles: they are latency-bound, and smaller
-// tiles spread them over four times the compute units with a third of the window per block
-constexpr int kMidTile = 16;
 static inline dim3 mtiles(int nf) {
   const int t = (nf + kMidTile - 1) / kMidTile;
   return dim3(t, t);
