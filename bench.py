@@ -107,7 +107,7 @@ def traffic_from_profile(root, nu):
         sha = kernel_source_sha(root)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sources_sha256") != sha or rec.get("kernel") != f"void fdd::k_mg_down<float, {nu}, true>":
+    if rec.get("kernel_sources_sha256") != sha or rec.get("kernel") != f"void fdd::k_mg_down<float, {nu}, true, 32>":
         return None
     return rec.get("traffic_bytes_per_launch")
 
@@ -197,7 +197,8 @@ def run_batched(F, args, label, cases, tol_p, max_p):
         "rel_err_vs_oracle_first3": errs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "kb_mg_down<1,true> (finest level of every instance, PCG update fused)",
+                     "kernel": f"kb_mg_down<{opts.mg_nu},true,32> (finest level of every instance, "
+                               "PCG update fused)",
                      "launches": nl, "avg_launch_us": 1e3 * ms / max(nl, 1),
                      "alg_bytes_per_batch_solve": alg},
     }
@@ -427,7 +428,7 @@ def main():
     traffic = traffic_from_profile(ROOT, args.nu) if prec == F.FDD_MIXED and args.n == 1024 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": f"k_mg_down<float,{args.nu},true> (finest level, PCG update fused)",
+                "kernel": f"k_mg_down<float,{args.nu},true,32> (finest level, PCG update fused)",
                 "launches": launches, "avg_launch_us": 1e3 * tot_ms / max(launches, 1),
                 "working_launches": its, "timed_long_launches": long_n,
                 "avg_working_launch_us": 1e3 * long_ms / max(long_n, 1),
