@@ -91,11 +91,11 @@ def cpu_baseline(args, case_list):
                       f"solver (FP64, numpy/scipy, one thread), cycling the same (K, mu) cases, {dt:.1f} s"}
 
 
-# Algorithmic bytes of the finest-level down kernel per interior dof (FP32): it reads r, w
-# (window) and z (own), plus s', p', x on iterations k >= 1, and writes r_new, s, p, x, the
-# pre-smoothed u and a quarter-size coarse right-hand side.
-DOWN0_BYTES_K0 = 4 * 3 + 4 * 5 + 1
-DOWN0_BYTES_K = DOWN0_BYTES_K0 + 4 * 3
+# Algorithmic bytes of the finest-level down kernel per interior dof (FP32): it reads r and z,
+# plus p' and x on iterations k >= 1, and writes r_new, p, x, the pre-smoothed u and a
+# quarter-size coarse right-hand side (A p is a stencil in LDS, not a stored vector).
+DOWN0_BYTES_K0 = 4 * 2 + 4 * 4 + 1
+DOWN0_BYTES_K = DOWN0_BYTES_K0 + 4 * 2
 HBM_PEAK_GBS = 8000.0
 
 

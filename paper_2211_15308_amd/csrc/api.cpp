@@ -72,9 +72,7 @@ size_t plan_workspace(fdd_problem_s* P, char* base) {
     S.x = (T*)take(esz * v0);
     for (int k = 0; k < 2; ++k) S.r[k] = (T*)take(esz * v0);
     for (int k = 0; k < 2; ++k) S.p[k] = (T*)take(esz * v0);
-    for (int k = 0; k < 2; ++k) S.s[k] = (T*)take(esz * v0);
     S.z = (T*)take(esz * v0);
-    S.w = (T*)take(esz * v0);
     S.mg.u[0] = (T*)take(esz * v0);
     S.mg.e[0] = S.z;
     S.mg.f[0] = nullptr;
@@ -265,7 +263,7 @@ void enqueue_inner_start(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, co
   } else {
     launch_ir_residual(c, t.f, nullptr, nullptr, nullptr, P->u64[0], nullptr, P->s64.r[t.cur_r], 1,
                        tol2, tol2, 1);
-    launch_pcg_init<double>(c, P->s64.mg, P->s64.r[t.cur_r], P->s64.z, P->s64.w);
+    launch_pcg_init<double>(c, P->s64.mg, P->s64.r[t.cur_r], P->s64.z);
   }
 }
 
@@ -275,12 +273,11 @@ void enqueue_inner_more(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, int
   if (!t.fp64) {
     auto& S = P->s32;
     for (int st = 0; st < steps; ++st) {
-      launch_pcg_init<float>(c, S.mg, S.r[t.cur_r], S.z, S.w);
+      launch_pcg_init<float>(c, S.mg, S.r[t.cur_r], S.z);
       const int n_its = its >= 0 ? its : (t.S < 8 ? P->sc->step_its[t.S] : P->sc->its);
       for (int k = 0; k < n_its; ++k) {
-        launch_pcg_iteration<float>(c, S.mg, k, S.x, S.r[t.cur_r], S.r[t.cur_r ^ 1], S.z, S.w,
-                                    S.p[t.cur_p], S.p[t.cur_p ^ 1], S.s[t.cur_p],
-                                    S.s[t.cur_p ^ 1]);
+        launch_pcg_iteration<float>(c, S.mg, k, S.x, S.r[t.cur_r], S.r[t.cur_r ^ 1], S.z,
+                                    S.p[t.cur_p], S.p[t.cur_p ^ 1]);
         t.cur_r ^= 1;
         t.cur_p ^= 1;
       }
@@ -291,9 +288,8 @@ void enqueue_inner_more(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, int
   } else {
     auto& S = P->s64;
     for (int k = 0; k < its; ++k) {
-      launch_pcg_iteration<double>(c, S.mg, t.k, S.x, S.r[t.cur_r], S.r[t.cur_r ^ 1], S.z, S.w,
-                                   S.p[t.cur_p], S.p[t.cur_p ^ 1], S.s[t.cur_p],
-                                   S.s[t.cur_p ^ 1]);
+      launch_pcg_iteration<double>(c, S.mg, t.k, S.x, S.r[t.cur_r], S.r[t.cur_r ^ 1], S.z,
+                                   S.p[t.cur_p], S.p[t.cur_p ^ 1]);
       t.k += 1;
       t.cur_r ^= 1;
       t.cur_p ^= 1;

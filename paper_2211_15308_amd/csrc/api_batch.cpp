@@ -107,7 +107,6 @@ BInst make_inst(const fdd_batch_s* B, int i, const double* b, double* x) {
   for (int k = 0; k < 2; ++k) {
     I.r[k] = P->s32.r[k];
     I.p[k] = P->s32.p[k];
-    I.s[k] = P->s32.s[k];
     I.u64[k] = P->u64[k];
     I.xI[k] = P->xI[k];
     I.xG[k] = P->xG[k];
@@ -115,7 +114,6 @@ BInst make_inst(const fdd_batch_s* B, int i, const double* b, double* x) {
     I.pG[k] = P->pG[k];
   }
   I.z = P->s32.z;
-  I.w = P->s32.w;
   I.dstS = P->dstS;
   I.dstL = P->dstL;
   I.st = P->st;

@@ -49,9 +49,7 @@ struct PcgSet {
   T* x = nullptr;
   T* r[2] = {nullptr, nullptr};
   T* p[2] = {nullptr, nullptr};
-  T* s[2] = {nullptr, nullptr};  // s = A p
   T* z = nullptr;
-  T* w = nullptr;                // w = A z
   MGBuffers<T> mg{};
 };
 

@@ -140,13 +140,13 @@ struct LaunchCtx {
 
 // ---- multigrid-PCG (kernels_mg.hip) --------------------------------------------------------
 template <typename T>
-void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z_out, T* w_out);
-// Iteration k of the inner PCG in its single-reduction (Chronopoulos-Gear) form: z = V r and
-// w = A z come from the previous V-cycle; p = z + beta p', s = w + beta s' (s = A p), x += alpha p,
-// r -= alpha s, then the V-cycle of the new r yields the next z, w and the dots r.z, z.w.
+void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z_out);
+// Iteration k of the inner PCG in its single-reduction (Chronopoulos-Gear) form: z = V r and the
+// dots r.z, z.A z come from the previous V-cycle; p = z + beta p', x += alpha p, r -= alpha A p
+// (A p as a stencil of p), then the V-cycle of the new r yields the next z and dots.
 template <typename T>
 void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
-                          T* r_new, T* z, T* w, T* p_old, T* p_new, T* s_old, T* s_new);
+                          T* r_new, T* z, T* p_old, T* p_new);
 
 // FP64 refinement residual plus its one-block finalize: uout = uin + e (uout = 0 on the first
 // call; a plain copy once the solve has converged), r = f - A uout.
@@ -200,7 +200,7 @@ struct BInst {
   float* f[kMaxLevels];
   float* u[kMaxLevels];
   float* e[kMaxLevels];
-  float *x, *r[2], *p[2], *s[2], *z, *w;
+  float *x, *r[2], *p[2], *z;
   double* u64[2];
   double* xI[2];                      // interior part of the solution, by outer version
   const float* dstS;                  // sine-transform matrix of the first coarse level

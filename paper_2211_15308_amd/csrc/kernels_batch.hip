@@ -64,15 +64,14 @@ __global__ __launch_bounds__(kBlock) void kb_mg_down(const BInst* __restrict__ I
   if (check && level == 1 && pcg_converged(st, red, lead)) return;
   if constexpr (CG) {
     d_mg_down<float, NU, true, TT>(P.r[cur_r], P.u[0], P.f[1], P.nf[0], P.pitch[0],
-                               P.pitch[1], P.w, P.s[cur_p], P.s[cur_p ^ 1],
-                               P.z, P.p[cur_p], P.p[cur_p ^ 1], P.x,
-                               P.r[cur_r ^ 1], st, red, k, tile_x, tile_y, t, lead);
+                                   P.pitch[1], P.z, P.p[cur_p], P.p[cur_p ^ 1], P.x,
+                                   P.r[cur_r ^ 1], st, red, k, tile_x, tile_y, t, lead);
   } else {
     const float* fin = level == 0 ? P.r[cur_r] : P.f[level];
     d_mg_down<float, NU, false, TT>(fin, P.u[level], P.f[level + 1], P.nf[level],
-                                P.pitch[level], P.pitch[level + 1], nullptr, nullptr, nullptr,
-                                nullptr, nullptr, nullptr, nullptr, nullptr, st, red, 0, tile_x,
-                                tile_y, t, lead);
+                                    P.pitch[level], P.pitch[level + 1], nullptr, nullptr,
+                                    nullptr, nullptr, nullptr, st, red, 0, tile_x, tile_y, t,
+                                    lead);
   }
 }
 
@@ -92,13 +91,12 @@ __global__ __launch_bounds__(kBlock) void kb_mg_up(const BInst* __restrict__ I, 
   const bool lead = (t == 0);
   const Reductions red = P.red;
   if constexpr (CG) {
-    d_mg_up<float, NU, true, TT>(P.r[cur_r], P.u[0], P.e[1], P.z, P.w,
-                             P.nf[0], P.pitch[0], P.pitch[1], st, red, kn, count, tile_x, tile_y,
-                             t, lead);
+    d_mg_up<float, NU, true, TT>(P.r[cur_r], P.u[0], P.e[1], P.z, P.nf[0], P.pitch[0],
+                                 P.pitch[1], st, red, kn, count, tile_x, tile_y, t, lead);
   } else {
-    d_mg_up<float, NU, false, TT>(P.f[level], P.u[level], P.e[level + 1],
-                              P.e[level], nullptr, P.nf[level], P.pitch[level],
-                              P.pitch[level + 1], st, red, 0, 0, tile_x, tile_y, t, lead);
+    d_mg_up<float, NU, false, TT>(P.f[level], P.u[level], P.e[level + 1], P.e[level],
+                                  P.nf[level], P.pitch[level], P.pitch[level + 1], st, red, 0, 0,
+                                  tile_x, tile_y, t, lead);
   }
 }
 

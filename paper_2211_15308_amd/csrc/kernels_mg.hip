@@ -34,27 +34,26 @@ namespace fdd {
 template <typename T, int NU, bool CG, int TT = kTile>
 __global__ __launch_bounds__(kBlock) void k_mg_down(
     const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
-    int pc, const T* __restrict__ w, const T* __restrict__ sold, T* __restrict__ snew,
-    const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ x,
-    T* __restrict__ rout, DevState* st, Reductions red, int k, int check) {
+    int pc, const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
+    T* __restrict__ x, T* __restrict__ rout, DevState* st, Reductions red, int k, int check) {
   if (stopped(st)) return;
   if (check && pcg_converged(st, red, block0())) return;
   int tile_x, tile_y;
   const int tile = xcd_tile(&tile_x, &tile_y);
-  d_mg_down<T, NU, CG, TT>(fin, uout, fc, nf, pitch, pc, w, sold, snew, z, pold, pnew, x, rout,
-                           st, red, k, tile_x, tile_y, tile, block0());
+  d_mg_down<T, NU, CG, TT>(fin, uout, fc, nf, pitch, pc, z, pold, pnew, x, rout, st, red, k,
+                           tile_x, tile_y, tile, block0());
 }
 
 template <typename T, int NU, bool CG, int TT = kTile>
 __global__ __launch_bounds__(kBlock) void k_mg_up(
     const T* __restrict__ fin, const T* __restrict__ upre, const T* __restrict__ ec,
-    T* __restrict__ eout, T* __restrict__ wout, int nf, int pitch, int pc, DevState* st,
-    Reductions red, int kn, int count_iteration) {
+    T* __restrict__ eout, int nf, int pitch, int pc, DevState* st, Reductions red, int kn,
+    int count_iteration) {
   if (stopped(st)) return;
   int tile_x, tile_y;
   const int tile = xcd_tile(&tile_x, &tile_y);
-  d_mg_up<T, NU, CG, TT>(fin, upre, ec, eout, wout, nf, pitch, pc, st, red, kn,
-                         count_iteration, tile_x, tile_y, tile, block0());
+  d_mg_up<T, NU, CG, TT>(fin, upre, ec, eout, nf, pitch, pc, st, red, kn, count_iteration,
+                         tile_x, tile_y, tile, block0());
 }
 
 template <typename T, int NU>
@@ -162,9 +161,8 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
     } else {
       hipLaunchKernelGGL((k_mg_down<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0, c.stream,
                          mg.f[l], mg.u[l], mg.f[l + 1], L.nf, L.pitch, c.lev[l + 1].pitch,
-                         (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (const T*)nullptr,
-                         (const T*)nullptr, (T*)nullptr, (T*)nullptr, (T*)nullptr, c.st, c.red, 0,
-                         chk);
+                         (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (T*)nullptr,
+                         (T*)nullptr, c.st, c.red, 0, chk);
     }
   }
   if constexpr (sizeof(T) == 4) {
@@ -186,15 +184,15 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
   int l = fc - 1;
   for (; !kPairs && l >= 1; --l) {
     const Level& L = c.lev[l];
-    hipLaunchKernelGGL((k_mg_up<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0, c.stream, mg.f[l],
-                       mg.u[l], mg.e[l + 1], mg.e[l], (T*)nullptr, L.nf, L.pitch,
-                       c.lev[l + 1].pitch, c.st, c.red, 0, 0);
+    hipLaunchKernelGGL((k_mg_up<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0, c.stream,
+                       mg.f[l], mg.u[l], mg.e[l + 1], mg.e[l], L.nf, L.pitch, c.lev[l + 1].pitch,
+                       c.st, c.red, 0, 0);
   }
   if (kPairs && ntiled % 2 == 1) {
     const Level& L = c.lev[l];
-    hipLaunchKernelGGL((k_mg_up<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0, c.stream, mg.f[l],
-                       mg.u[l], mg.e[l + 1], mg.e[l], (T*)nullptr, L.nf, L.pitch,
-                       c.lev[l + 1].pitch, c.st, c.red, 0, 0);
+    hipLaunchKernelGGL((k_mg_up<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0, c.stream,
+                       mg.f[l], mg.u[l], mg.e[l + 1], mg.e[l], L.nf, L.pitch, c.lev[l + 1].pitch,
+                       c.st, c.red, 0, 0);
     --l;
   }
   if constexpr (kPairs) {
@@ -210,42 +208,40 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
 }
 
 template <typename T, int NU>
-static void pcg_init_nu(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z, T* w) {
+static void pcg_init_nu(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z) {
   const Level& L = c.lev[0];
   hipLaunchKernelGGL((k_mg_down<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, r, mg.u[0],
                      mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)nullptr, (const T*)nullptr,
-                     (T*)nullptr, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (T*)nullptr,
-                     (T*)nullptr, c.st, c.red, 0, 0);
+                     (T*)nullptr, (T*)nullptr, (T*)nullptr, c.st, c.red, 0, 0);
   vcycle_tail_nu<T, NU>(c, mg, 0);
   hipLaunchKernelGGL((k_mg_up<T, NU, true>), tiles(L.nf), tblock(), 0, c.stream, r, mg.u[0],
-                     mg.e[1], z, w, L.nf, L.pitch, c.lev[1].pitch, c.st, c.red, 0, 0);
+                     mg.e[1], z, L.nf, L.pitch, c.lev[1].pitch, c.st, c.red, 0, 0);
 }
 
 template <typename T>
-void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z, T* w) {
-  if (c.nu == 2) pcg_init_nu<T, 2>(c, mg, r, z, w);
-  else pcg_init_nu<T, 1>(c, mg, r, z, w);
+void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z) {
+  if (c.nu == 2) pcg_init_nu<T, 2>(c, mg, r, z);
+  else pcg_init_nu<T, 1>(c, mg, r, z);
 }
 
 template <typename T, int NU>
 static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
-                        T* r_new, T* z, T* w, T* p_old, T* p_new, T* s_old, T* s_new) {
+                        T* r_new, T* z, T* p_old, T* p_new) {
   const Level& L = c.lev[0];
   launch_timed(c.hook, kTimeDown0, k_mg_down<T, NU, true>, tiles(L.nf), tblock(), c.stream,
-               (const T*)r_old, mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)w,
-               (const T*)s_old, s_new, (const T*)z, (const T*)p_old, p_new, x, r_new, c.st, c.red,
-               k, 0);
+               (const T*)r_old, mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)z,
+               (const T*)p_old, p_new, x, r_new, c.st, c.red, k, 0);
   vcycle_tail_nu<T, NU>(c, mg, 1);
   launch_timed(c.hook, kTimeUp0, k_mg_up<T, NU, true>, tiles(L.nf), tblock(), c.stream,
-               (const T*)r_new, (const T*)mg.u[0], (const T*)mg.e[1], z, w, L.nf, L.pitch,
+               (const T*)r_new, (const T*)mg.u[0], (const T*)mg.e[1], z, L.nf, L.pitch,
                c.lev[1].pitch, c.st, c.red, k + 1, 1);
 }
 
 template <typename T>
 void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
-                          T* r_new, T* z, T* w, T* p_old, T* p_new, T* s_old, T* s_new) {
-  if (c.nu == 2) pcg_iter_nu<T, 2>(c, mg, k, x, r_old, r_new, z, w, p_old, p_new, s_old, s_new);
-  else pcg_iter_nu<T, 1>(c, mg, k, x, r_old, r_new, z, w, p_old, p_new, s_old, s_new);
+                          T* r_new, T* z, T* p_old, T* p_new) {
+  if (c.nu == 2) pcg_iter_nu<T, 2>(c, mg, k, x, r_old, r_new, z, p_old, p_new);
+  else pcg_iter_nu<T, 1>(c, mg, k, x, r_old, r_new, z, p_old, p_new);
 }
 
 void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin, const float* e32,
@@ -271,14 +267,12 @@ void launch_warm_alpha(const LaunchCtx& c, const RhsDesc& f, const float* g) {
 }
 
 template void launch_pcg_init<float>(const LaunchCtx&, const MGBuffers<float>&, const float*,
-                                     float*, float*);
+                                     float*);
 template void launch_pcg_init<double>(const LaunchCtx&, const MGBuffers<double>&, const double*,
-                                      double*, double*);
+                                      double*);
 template void launch_pcg_iteration<float>(const LaunchCtx&, const MGBuffers<float>&, int, float*,
-                                          float*, float*, float*, float*, float*, float*, float*,
-                                          float*);
+                                          float*, float*, float*, float*, float*);
 template void launch_pcg_iteration<double>(const LaunchCtx&, const MGBuffers<double>&, int,
-                                           double*, double*, double*, double*, double*, double*,
-                                           double*, double*, double*);
+                                           double*, double*, double*, double*, double*, double*);
 
 }  // namespace fdd

@@ -222,30 +222,32 @@ constexpr int kOwnSlots = kTile * kTile / kBlock;
 
 // Going down one level: u = S^nu(0; f) (red first), r = f - A u, f_c = P^T r.
 // CG = true (level 0, inner PCG iteration k, single-reduction form):
-//   gamma_k = r_k . z_k and delta_k = z_k . w_k come from the partials of the previous V-cycle
+//   gamma_k = r_k . z_k and delta_k = z_k . A z_k come from the partials of the previous V-cycle
 //   (summed here in one pass); beta_k = gamma_k / gamma_{k-1}, alpha_k = gamma_k / (delta_k -
 //   beta_k gamma_k / alpha_{k-1}) (beta_0 = 0, alpha_0 = gamma_0 / delta_0), with gamma_{k-1}
-//   and alpha_{k-1} recorded by the previous iteration.  On the window s_k = w_k + beta_k s_{k-1}
-//   and f = r_{k+1} = r_k - alpha_k s_k; on own points p_k = z_k + beta_k p_{k-1},
-//   x += alpha_k p_k, and r_{k+1}, s_k, p_k are stored; ||r_{k+1}||^2 goes to red.rr.
+//   and alpha_{k-1} recorded by the previous iteration.  p_k = z_k + beta_k p_{k-1} is formed
+//   one cell beyond the window, so that s_k = A p_k is a stencil in LDS (no stored recurrence
+//   for A p); on the window f = r_{k+1} = r_k - alpha_k s_k; on own points x += alpha_k p_k and
+//   r_{k+1}, p_k are stored; ||r_{k+1}||^2 goes to red.rr.
 template <typename T, int NU, bool CG, int TT = kTile>
 __device__ __forceinline__ void d_mg_down(
     const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
-    int pc, const T* __restrict__ w, const T* __restrict__ sold, T* __restrict__ snew,
-    const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew, T* __restrict__ x,
-    T* __restrict__ rout, DevState* st, const Reductions& red, int k, int tile_x, int tile_y,
-    int tile, bool lead) {
+    int pc, const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
+    T* __restrict__ x, T* __restrict__ rout, DevState* st, const Reductions& red, int k,
+    int tile_x, int tile_y, int tile, bool lead) {
   constexpr int H = 2 * NU + 1;
   constexpr int W = TT + 2 * H;
+  constexpr int PW = CG ? W + 2 : 1;  // window of p: one cell beyond the f window
   constexpr int NW = Flat<W>::N;
-  constexpr int NO = CG ? (TT * TT / kBlock) : 1;
+  constexpr int NPW = CG ? Flat<PW>::N : 1;
   __shared__ T sf[W][W + 1];
   __shared__ T su[W][W + 1];
+  __shared__ T sp[PW][PW + 1];
   const int i0 = tile_x * TT, j0 = tile_y * TT;
   const int ib = i0 + 1 - H, jb = j0 + 1 - H;  // global index of window cell (0, 0)
   const int t = flat_tid();
-  T fr[NW], wr[NW], sr[NW];
-  T zr[NO], pr[NO], xr[NO];
+  T fr[NW];
+  T zr[NPW], pr[NPW], xr[NPW];
   // the partials of r.z and z.A z (CG) are loaded first: their sum is needed before any window
   // value, and loads complete in issue order
   constexpr int NP = CG ? 4 : 1;
@@ -266,27 +268,25 @@ __device__ __forceinline__ void d_mg_down(
     const int lj = c / W, li = c % W;
     const int i = ib + li, j = jb + lj;
     const bool in = c < W * W && i >= 1 && i <= nf && j >= 1 && j <= nf;
-    const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
-    fr[q] = in ? ldg(fin, o) : T(0);
-    if (CG) {
-      wr[q] = in ? ldg(w, o) : T(0);
-      sr[q] = (in && k > 0) ? ldg(sold, o) : T(0);
-    }
+    fr[q] = in ? ldg(fin, (unsigned)((j - 1) * pitch + (i - 1))) : T(0);
   }
-  if (CG) {
+  if constexpr (CG) {
 #pragma unroll
-    for (int q = 0; q < NO; ++q) {
+    for (int q = 0; q < NPW; ++q) {
       const int c = t + kBlock * q;
-      const int i = i0 + 1 + (c % TT), j = j0 + 1 + c / TT;
-      const bool in = i <= nf && j <= nf;
+      const int lj = c / PW, li = c % PW;
+      const int i = ib - 1 + li, j = jb - 1 + lj;
+      const bool in = c < PW * PW && i >= 1 && i <= nf && j >= 1 && j <= nf;
       const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+      // own cells of the tile: p window cells H + 1 .. H + TT
+      const bool own = in && li > H && li <= H + TT && lj > H && lj <= H + TT;
       zr[q] = in ? ldg(z, o) : T(0);
       pr[q] = (in && k > 0) ? ldg(pold, o) : T(0);
-      xr[q] = (in && k > 0) ? ldg((const T*)x, o) : T(0);
+      xr[q] = (own && k > 0) ? ldg((const T*)x, o) : T(0);
     }
   }
   T alpha = T(0), beta = T(0);
-  if (CG) {
+  if constexpr (CG) {
     double gam = 0.0, del = 0.0;
 #pragma unroll
     for (int a = 0; a < NP; ++a) {
@@ -318,6 +318,23 @@ __device__ __forceinline__ void d_mg_down(
     }
     alpha = (T)al;
     beta = (T)b;
+    // p_k on its window (zero outside the domain, where z and p_{k-1} are zero); on own cells
+    // p_k and x + alpha_k p_k are stored
+#pragma unroll
+    for (int q = 0; q < NPW; ++q) {
+      const int c = t + kBlock * q;
+      if (c >= PW * PW) continue;
+      const int lj = c / PW, li = c % PW;
+      const T pv = zr[q] + beta * pr[q];
+      sp[lj][li] = pv;
+      const int i = ib - 1 + li, j = jb - 1 + lj;
+      if (li > H && li <= H + TT && lj > H && lj <= H + TT && i <= nf && j <= nf) {
+        const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+        stg(pnew, o, pv);
+        stg(x, o, xr[q] + alpha * pv);
+      }
+    }
+    __syncthreads();
   }
   double rr = 0.0;
 #pragma unroll
@@ -327,33 +344,21 @@ __device__ __forceinline__ void d_mg_down(
     const int lj = c / W, li = c % W;
     const int i = ib + li, j = jb + lj;
     T f = fr[q];
-    if (CG) {
-      const T sv = wr[q] + beta * sr[q];
-      f = f - alpha * sv;
-      const bool own = li >= H && li < H + TT && lj >= H && lj < H + TT && i <= nf &&
-                       j <= nf;
-      if (own) {
-        const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
-        stg(rout, o, f);
-        stg(snew, o, sv);
-        rr += (double)f * (double)f;
+    if constexpr (CG) {
+      if (i >= 1 && i <= nf && j >= 1 && j <= nf) {
+        const int pj = lj + 1, pi = li + 1;
+        const T sv = T(4) * sp[pj][pi] - sp[pj][pi - 1] - sp[pj][pi + 1] - sp[pj - 1][pi] -
+                     sp[pj + 1][pi];
+        f = f - alpha * sv;
+        if (li >= H && li < H + TT && lj >= H && lj < H + TT) {
+          stg(rout, (unsigned)((j - 1) * pitch + (i - 1)), f);
+          rr += (double)f * (double)f;
+        }
       }
     }
     sf[lj][li] = f;
     // first red half-sweep from a zero iterate: u = f / 4 on red points, 0 on black points
     su[lj][li] = is_red(i, j) ? T(0.25) * f : T(0);
-  }
-  if (CG) {
-#pragma unroll
-    for (int q = 0; q < NO; ++q) {
-      const int c = t + kBlock * q;
-      const int i = i0 + 1 + (c % TT), j = j0 + 1 + c / TT;
-      if (i > nf || j > nf) continue;
-      const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
-      const T pv = zr[q] + beta * pr[q];
-      stg(pnew, o, pv);
-      stg(x, o, xr[q] + alpha * pv);
-    }
   }
   __syncthreads();
   tile_sweeps<T, W, 2 * NU - 1>(su, sf, ib, jb, nf, false);  // black, red, black, ...
@@ -395,15 +400,14 @@ __device__ __forceinline__ void d_mg_down(
 }
 
 // Going up one level: u = u_pre + P e_c, then nu (black, red) pairs; result to eout.
-// CG = true (level 0): the result z is kept valid one cell beyond the tile, so that w = A z is
-// formed on own points too; z and w are stored and the block's parts of r . z and z . w go to
+// CG = true (level 0): the result z is kept valid one cell beyond the tile, so that A z is
+// formed on own points too; z is stored and the block's parts of r . z and z . A z go to
 // red.rz[kn & 1] and red.zw[kn & 1] (f is r).
 template <typename T, int NU, bool CG, int TT = kTile>
 __device__ __forceinline__ void d_mg_up(
     const T* __restrict__ fin, const T* __restrict__ upre, const T* __restrict__ ec,
-    T* __restrict__ eout, T* __restrict__ wout, int nf, int pitch, int pc, DevState* st,
-    const Reductions& red, int kn, int count_iteration, int tile_x, int tile_y, int tile,
-    bool lead) {
+    T* __restrict__ eout, int nf, int pitch, int pc, DevState* st, const Reductions& red, int kn,
+    int count_iteration, int tile_x, int tile_y, int tile, bool lead) {
   constexpr int H = 2 * NU + (CG ? 1 : 0);
   constexpr int W = TT + 2 * H;
   constexpr int NW = Flat<W>::N;
@@ -476,7 +480,6 @@ __device__ __forceinline__ void d_mg_up(
     stg(eout, o, zv);
     if (CG) {
       const T wv = T(4) * zv - su[lj][li - 1] - su[lj][li + 1] - su[lj - 1][li] - su[lj + 1][li];
-      stg(wout, o, wv);
       rz += (double)sf[lj][li] * (double)zv;
       zw += (double)zv * (double)wv;
     }
