@@ -258,11 +258,13 @@ void enqueue_inner_start(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, co
   t.S = t.k = 0;
   if (!t.fp64) {
     if (warm) launch_warm_alpha(c, t.f, warm);
+    // (its bookkeeping is done by the first kernel of the PCG run that always follows)
     launch_ir_residual(c, t.f, nullptr, nullptr, nullptr, P->u64[0], P->s32.r[t.cur_r], nullptr, 1,
-                       tol2, step_tau(o) * step_tau(o), 0, warm, warm ? &P->st->warm_alpha : nullptr);
+                       tol2, step_tau(o) * step_tau(o), 0, warm, warm ? &P->st->warm_alpha : nullptr,
+                       false);
   } else {
     launch_ir_residual(c, t.f, nullptr, nullptr, nullptr, P->u64[0], nullptr, P->s64.r[t.cur_r], 1,
-                       tol2, tol2, 1);
+                       tol2, tol2, 1, nullptr, nullptr, false);
     launch_pcg_init<double>(c, P->s64.mg, P->s64.r[t.cur_r], P->s64.z);
   }
 }
@@ -281,8 +283,10 @@ void enqueue_inner_more(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, int
         t.cur_r ^= 1;
         t.cur_p ^= 1;
       }
+      // the next step's first kernel does this residual's bookkeeping; the last one of the
+      // sequence gets a kernel of its own (the host or the outer tail reads its outcome)
       launch_ir_residual(c, t.f, P->u64[t.S & 1], S.x, nullptr, P->u64[(t.S + 1) & 1],
-                         S.r[t.cur_r], nullptr, 0, 0, 0, 0);
+                         S.r[t.cur_r], nullptr, 0, 0, 0, 0, nullptr, nullptr, st == steps - 1);
       t.S += 1;
     }
   } else {

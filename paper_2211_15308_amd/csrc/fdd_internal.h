@@ -148,12 +148,14 @@ template <typename T>
 void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
                           T* r_new, T* z, T* p_old, T* p_new);
 
-// FP64 refinement residual plus its one-block finalize: uout = uin + e (uout = 0 on the first
-// call; a plain copy once the solve has converged), r = f - A uout.
+// FP64 refinement residual: uout = uin + e (uout = 0 on the first call; a plain copy once the
+// solve has converged), r = f - A uout.  The step's bookkeeping (convergence test, state of the
+// next PCG run) is done by the first kernel of the next PCG run; finalize = true adds a one-block
+// kernel for it, for a residual that no PCG run follows in the same launch sequence.
 void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin, const float* e32,
                         const double* e64, double* uout, float* r32, double* r64, int first,
-                        double tol2, double tau2, int pcg_is_final,
-                        const float* warm = nullptr, const double* wscale = nullptr);
+                        double tol2, double tau2, int pcg_is_final, const float* warm,
+                        const double* wscale, bool finalize);
 // Galerkin factor of a learned guess g (FP32 image, pitch nf) for the right-hand side f, into
 // st->warm_alpha (0 when the guess does not lower the energy error).
 void launch_warm_alpha(const LaunchCtx& c, const RhsDesc& f, const float* g);

@@ -35,9 +35,16 @@ template <typename T, int NU, bool CG, int TT = kTile>
 __global__ __launch_bounds__(kBlock) void k_mg_down(
     const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
     int pc, const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
-    T* __restrict__ x, T* __restrict__ rout, DevState* st, Reductions red, int k, int check) {
-  if (stopped(st)) return;
-  if (check && pcg_converged(st, red, block0())) return;
+    T* __restrict__ x, T* __restrict__ rout, DevState* st, Reductions red, int k, int check,
+    int finalize) {
+  if (finalize) {
+    // the kernel that starts a PCG run after a refinement residual also does that step's
+    // bookkeeping (instead of a one-block kernel of its own)
+    if (ir_finalize_here(st, red, block0())) return;
+  } else {
+    if (stopped(st)) return;
+    if (check && pcg_converged(st, red, block0())) return;
+  }
   int tile_x, tile_y;
   const int tile = xcd_tile(&tile_x, &tile_y);
   d_mg_down<T, NU, CG, TT>(fin, uout, fc, nf, pitch, pc, z, pold, pnew, x, rout, st, red, k,
@@ -162,7 +169,7 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
       hipLaunchKernelGGL((k_mg_down<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0, c.stream,
                          mg.f[l], mg.u[l], mg.f[l + 1], L.nf, L.pitch, c.lev[l + 1].pitch,
                          (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (T*)nullptr,
-                         (T*)nullptr, c.st, c.red, 0, chk);
+                         (T*)nullptr, c.st, c.red, 0, chk, 0);
     }
   }
   if constexpr (sizeof(T) == 4) {
@@ -212,7 +219,7 @@ static void pcg_init_nu(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, 
   const Level& L = c.lev[0];
   hipLaunchKernelGGL((k_mg_down<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, r, mg.u[0],
                      mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)nullptr, (const T*)nullptr,
-                     (T*)nullptr, (T*)nullptr, (T*)nullptr, c.st, c.red, 0, 0);
+                     (T*)nullptr, (T*)nullptr, (T*)nullptr, c.st, c.red, 0, 0, 1);
   vcycle_tail_nu<T, NU>(c, mg, 0);
   hipLaunchKernelGGL((k_mg_up<T, NU, true>), tiles(L.nf), tblock(), 0, c.stream, r, mg.u[0],
                      mg.e[1], z, L.nf, L.pitch, c.lev[1].pitch, c.st, c.red, 0, 0);
@@ -230,7 +237,7 @@ static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x,
   const Level& L = c.lev[0];
   launch_timed(c.hook, kTimeDown0, k_mg_down<T, NU, true>, tiles(L.nf), tblock(), c.stream,
                (const T*)r_old, mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)z,
-               (const T*)p_old, p_new, x, r_new, c.st, c.red, k, 0);
+               (const T*)p_old, p_new, x, r_new, c.st, c.red, k, 0, 0);
   vcycle_tail_nu<T, NU>(c, mg, 1);
   launch_timed(c.hook, kTimeUp0, k_mg_up<T, NU, true>, tiles(L.nf), tblock(), c.stream,
                (const T*)r_new, (const T*)mg.u[0], (const T*)mg.e[1], z, L.nf, L.pitch,
@@ -247,7 +254,7 @@ void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* 
 void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin, const float* e32,
                         const double* e64, double* uout, float* r32, double* r64, int first,
                         double tol2, double tau2, int pcg_is_final, const float* warm,
-                        const double* wscale) {
+                        const double* wscale, bool finalize) {
   const Level& L = c.lev[0];
   if (e64 || !e32)
     hipLaunchKernelGGL((k_ir_residual<double>), tiles(L.nf), tblock(), 0, c.stream, f, uin, e64,
@@ -257,7 +264,7 @@ void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin,
     hipLaunchKernelGGL((k_ir_residual<float>), tiles(L.nf), tblock(), 0, c.stream, f, uin, e32,
                        uout, r32, r64, L.nf, L.pitch, first, tol2, tau2, pcg_is_final, c.st,
                        c.red, warm, wscale);
-  hipLaunchKernelGGL(k_ir_finalize, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red);
+  if (finalize) hipLaunchKernelGGL(k_ir_finalize, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red);
 }
 
 void launch_warm_alpha(const LaunchCtx& c, const RhsDesc& f, const float* g) {

@@ -1169,26 +1169,31 @@ __device__ __forceinline__ void d_warm_alpha(DevState* st, const Reductions& red
   }
 }
 
-// One block: reads the refinement residual back from the partials and sets the solve's state
-// for the next PCG run (or ends the solve).
-__device__ __forceinline__ void d_ir_finalize(DevState* st, const Reductions& red) {
-  if (st->solve_done) return;
-  const double res = sum_partials(red.ir, red.nb0);
+// Reads the refinement residual back from the partials and sets the solve's state for the next
+// PCG run (or ends the solve).  Run by every block of the kernel that starts the next PCG run (or
+// by a one-block kernel): all blocks sum the same partials in the same order, so they agree on
+// whether the solve is over, and only the lead block records the state.  Returns true when the
+// solve is over.
+__device__ __forceinline__ bool ir_finalize_here(DevState* st, const Reductions& red, bool lead) {
+  if (st->solve_done) return true;
+  const double r2 = sum_partials(red.ir, red.nb0);
   const double ff = sum_partials(red.ff, red.nb0);
-  if (thread0()) {
-    const double r2 = res;
+  const bool bad = !isfinite(r2);
+  const bool done = bad || r2 <= st->tol2 * ff;
+  if (lead && thread0()) {
     st->ff = ff;
     st->res2 = r2;
     st->rr0 = r2;
     st->inner_done = 0;
     st->pcg_k = 0;
-    if (!isfinite(r2)) {
-      st->breakdown |= 4;
-      st->solve_done = 1;
-    } else if (r2 <= st->tol2 * ff) {
-      st->solve_done = 1;
-    }
+    if (bad) st->breakdown |= 4;
+    if (done) st->solve_done = 1;
   }
+  return done;
+}
+
+__device__ __forceinline__ void d_ir_finalize(DevState* st, const Reductions& red) {
+  (void)ir_finalize_here(st, red, true);
 }
 
 
