@@ -178,7 +178,9 @@ def run_batched(F, args, label, cases, tol_p, max_p):
     for c, s_ in zip(cases, st_t):
         ni = (c["n"] - 1) ** 2
         its, runs = s_["inner_its_total"], s_["refine_steps"]
-        alg += ni * (DOWN0_BYTES_K * (its - runs) + DOWN0_BYTES_K0 * runs)
+        # every PCG run updates on its counted iterations plus the one whose residual met the
+        # run's tolerance; the first update of a run (k = 0) reads no p' and x
+        alg += ni * (DOWN0_BYTES_K * its + DOWN0_BYTES_K0 * runs)
     achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     errs = []
     for i in range(min(3, len(cases))):
@@ -422,17 +424,19 @@ def main():
     ni = (args.n - 1) ** 2
     elem = 4 if prec == F.FDD_MIXED else 8
     # working launches: those that did the update (the others returned at once after their PCG
-    # run had converged); their algorithmic bytes over their own time is the achieved rate
-    alg_bytes = ni * elem / 4 * (DOWN0_BYTES_K * (its - runs) + DOWN0_BYTES_K0 * runs)
+    # run had converged): a run's counted iterations plus the one whose residual met the run's
+    # tolerance, the first (k = 0) reading no p' and x; their algorithmic bytes over their own
+    # time is the achieved rate
+    alg_bytes = ni * elem / 4 * (DOWN0_BYTES_K * its + DOWN0_BYTES_K0 * runs)
     achieved = alg_bytes / (long_ms * 1e-3) / 1e9 if long_ms > 0 else 0.0
     traffic = traffic_from_profile(ROOT, args.nu) if prec == F.FDD_MIXED and args.n == 1024 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": f"k_mg_down<float,{args.nu},true,32> (finest level, PCG update fused)",
                 "launches": launches, "avg_launch_us": 1e3 * tot_ms / max(launches, 1),
-                "working_launches": its, "timed_long_launches": long_n,
+                "working_launches": its + runs, "timed_long_launches": long_n,
                 "avg_working_launch_us": 1e3 * long_ms / max(long_n, 1),
-                "alg_bytes_per_working_launch": alg_bytes / max(its, 1)}
+                "alg_bytes_per_working_launch": alg_bytes / max(its + runs, 1)}
     # parity spot-check of one solve of the first cases against the separable oracle
     from oracle import system
     errs = []
