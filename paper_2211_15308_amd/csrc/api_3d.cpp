@@ -20,10 +20,17 @@ using namespace fdd;
 struct Problem3D {
   int n = 0, nf = 0, nlev = 0, nc = 0;
   int lnf[kMaxLevels] = {};
-  double* u[kMaxLevels] = {};  // level iterates (level 0: z)
-  double* f[kMaxLevels] = {};  // level right-hand sides (level 0: r)
-  double* t[kMaxLevels] = {};  // level residual scratch
-  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  int lc = 1;     // levels lc .. nlev - 1 run in the one-workgroup coarse kernel
+  Cvc3 cvc{};     // their sizes
+  int rows0 = 4;  // rows per block of the level-0 reduction kernels
+  int np0 = 0;    // their partials
+  double* u[kMaxLevels] = {};   // pre-smoothed iterates (level 0: scratch)
+  double* uo[kMaxLevels] = {};  // iterates after the coarse correction, levels < lc (level 0: z)
+  double* f[kMaxLevels] = {};   // right-hand sides of the levels >= 1
+  double* x = nullptr;
+  double* R[2] = {};   // r_k in R[k & 1]
+  double* PB[2] = {};  // p_k in PB[k & 1]
+  double* q = nullptr;
   double* xI = nullptr;  // interior part of the solution, accumulated during the outer PCG
   double *part0 = nullptr, *part1 = nullptr;
   State3* st = nullptr;
@@ -36,21 +43,28 @@ struct Problem3D {
   FaceCG* cg = nullptr;
   int* done = nullptr;
   double *fpart0 = nullptr, *fpart1 = nullptr;
-  double *fy = nullptr, *fr = nullptr, *fp = nullptr, *fq = nullptr, *fz = nullptr, *ft = nullptr;
+  double *fy = nullptr, *fr = nullptr, *fq = nullptr, *fz = nullptr, *ft = nullptr;
+  double* fp[2] = {};  // p_k of the face systems in fp[k & 1]
   double *xG = nullptr, *rG = nullptr, *pG = nullptr, *zG = nullptr, *yG = nullptr, *Hp = nullptr;
   double *ftmp = nullptr, *gpart = nullptr;
   // pinned host mirrors
   State3* hst = nullptr;
   int* hstop = nullptr;
   int* hdone = nullptr;
+  int* hits = nullptr;
   double* hpart = nullptr;
   Shift3* htab = nullptr;
   double* htol = nullptr;
-  // captured chunks of Krylov iterations (replayed on the library stream)
-  hipGraphExec_t g_inner = nullptr;
-  int g_inner_nu = 0;
-  hipGraphExec_t g_face[2] = {nullptr, nullptr};
+  // captured work (replayed on the library stream): the first V-cycle of an interior solve and
+  // one PCG iteration k for each parity of k
+  hipGraphExec_t g_init = nullptr;
+  hipGraphExec_t g_it[2] = {nullptr, nullptr};
+  int g_nu = 0;
+  int pred_its = 8;  // iterations of the last interior solve (enqueued before the first check)
+  // one face-CG iteration k per (batch, parity of k); iterations of the last batch of each kind
+  hipGraphExec_t g_face[2][2] = {};
   int g_face_m[2] = {0, 0};
+  int pred_face[2] = {12, 12};
   bool use_graph = true;
 };
 
@@ -58,7 +72,6 @@ namespace {
 
 constexpr double kFaceTolP = 1e-10;  // shifted solves of the preconditioner (steer the iteration)
 constexpr double kFaceTolH = 1e-13;  // shifted solves of the operator H (enter the solution)
-constexpr int kChunk3 = 4;           // iterations enqueued between convergence checks
 
 size_t vol(int nf) { return (size_t)(nf + 2) * (nf + 2) * (nf + 2); }
 
@@ -75,19 +88,19 @@ size_t plan3(fdd_problem_s* P, char* base) {
   for (int l = 1; l < Q->nlev; ++l) {
     Q->u[l] = (double*)take(8 * vol(Q->lnf[l]));
     Q->f[l] = (double*)take(8 * vol(Q->lnf[l]));
-    Q->t[l] = (double*)take(8 * vol(Q->lnf[l]));
+    if (l < Q->lc) Q->uo[l] = (double*)take(8 * vol(Q->lnf[l]));
   }
-  Q->t[0] = (double*)take(8 * v0);
+  Q->u[0] = (double*)take(8 * v0);
+  Q->uo[0] = (double*)take(8 * v0);
   Q->x = (double*)take(8 * v0);
-  Q->r = (double*)take(8 * v0);
-  Q->z = (double*)take(8 * v0);
-  Q->p = (double*)take(8 * v0);
+  for (int b = 0; b < 2; ++b) {
+    Q->R[b] = (double*)take(8 * v0);
+    Q->PB[b] = (double*)take(8 * v0);
+  }
   Q->q = (double*)take(8 * v0);
   Q->xI = (double*)take(8 * v0);
-  Q->u[0] = Q->z;
-  Q->f[0] = Q->r;
-  Q->part0 = (double*)take(8 * kPart3);
-  Q->part1 = (double*)take(8 * kPart3);
+  Q->part0 = (double*)take(8 * kPart0);
+  Q->part1 = (double*)take(8 * kPart0);
   Q->st = (State3*)take(sizeof(State3));
   Q->stop = (int*)take(sizeof(int));
   const size_t nc3 = (size_t)Q->nc * Q->nc * Q->nc;
@@ -96,10 +109,10 @@ size_t plan3(fdd_problem_s* P, char* base) {
   Q->tabs = (Shift3*)take(2 * sizeof(Shift3));
   Q->cg = (FaceCG*)take(sizeof(FaceCG));
   Q->done = (int*)take(sizeof(int) * kMaxSys3);
-  Q->fpart0 = (double*)take(8 * (size_t)kMaxSys3 * kPartF);
-  Q->fpart1 = (double*)take(8 * (size_t)kMaxSys3 * kPartF);
+  Q->fpart0 = (double*)take(8 * (size_t)kMaxSys3 * kPFS);
+  Q->fpart1 = (double*)take(8 * (size_t)kMaxSys3 * kPFS);
   const size_t ng = (size_t)Q->nf * Q->nf;
-  for (double** v : {&Q->fy, &Q->fr, &Q->fp, &Q->fq, &Q->fz, &Q->ft})
+  for (double** v : {&Q->fy, &Q->fr, &Q->fp[0], &Q->fp[1], &Q->fq, &Q->fz, &Q->ft})
     *v = (double*)take(8 * ng * kMaxSys3);
   for (double** v : {&Q->xG, &Q->rG, &Q->pG, &Q->zG, &Q->yG, &Q->Hp, &Q->ftmp})
     *v = (double*)take(8 * ng);
@@ -152,23 +165,54 @@ std::vector<double> dense_inverse_7pt(int nc) {
   return X;
 }
 
-// V-cycle z = V r on the interior (nu red-black pairs per level)
-void vcycle3(Problem3D* Q, hipStream_t s, int nu) {
-  const int L = Q->nlev;
-  const int* stop = Q->stop;
-  for (int l = 0; l < L - 1; ++l) {
-    const int nf = Q->lnf[l];
-    k3_launch_rb(s, Q->u[l], Q->f[l], nf, 1, 1, stop);
-    for (int sw = 1; sw < 2 * nu; ++sw) k3_launch_rb(s, Q->u[l], Q->f[l], nf, (sw & 1) ? 0 : 1, 0, stop);
-    k3_launch_resid(s, Q->u[l], Q->f[l], Q->t[l], nf, stop);
-    k3_launch_restrict(s, Q->t[l], Q->f[l + 1], nf, Q->lnf[l + 1], stop);
+// V-cycle z = V r on the interior (nu red-black pairs per level: red, black, ... going down,
+// black, red, ... going up).  mode 1: the start of a solve (r_0 in R[0]); mode 2: inside PCG
+// iteration k (r_{k+1} = r_k - alpha_k q formed by the first pass, which leaves it in
+// R[(k + 1) & 1]).  The pass after the first holds the convergence test.  The last pass leaves
+// z in uo[0] and the partials of r . z in part0.
+void vcycle3(Problem3D* Q, hipStream_t s, int nu, int mode, int k) {
+  const int nf = Q->nf, np0 = Q->np0;
+  int* stop = Q->stop;
+  double* f0 = mode == 1 ? Q->R[0] : Q->R[(k + 1) & 1];
+  if (mode == 1)
+    k3_launch_zp(s, 1, f0, Q->u[0], nf, Q->rows0, nullptr, nullptr, nullptr, nullptr, Q->st,
+                 nullptr, 0, Q->part0, stop);
+  else
+    k3_launch_zp(s, 2, Q->R[k & 1], Q->u[0], nf, Q->rows0, Q->q, f0, Q->x, Q->PB[k & 1], Q->st,
+                 Q->part1, np0, Q->part0, stop);
+  int check = mode;
+  for (int sw = 2; sw < 2 * nu; ++sw) {
+    k3_launch_hs(s, Q->u[0], f0, nf, !(sw & 1), check, Q->st, Q->part0, np0, stop);
+    check = 0;
   }
-  k3_launch_coarse(s, Q->f[L - 1], Q->u[L - 1], Q->lnf[L - 1], Q->cinv, stop);
-  for (int l = L - 2; l >= 0; --l) {
-    const int nf = Q->lnf[l];
-    k3_launch_prolong(s, Q->u[l + 1], Q->u[l], nf, Q->lnf[l + 1], stop);
-    for (int sw = 0; sw < 2 * nu; ++sw) k3_launch_rb(s, Q->u[l], Q->f[l], nf, (sw & 1) ? 1 : 0, 0, stop);
+  k3_launch_rr(s, Q->u[0], f0, Q->f[1], nf, Q->lnf[1], check, Q->st, Q->part0, np0, stop);
+  for (int l = 1; l < Q->lc; ++l) {
+    const int n = Q->lnf[l];
+    k3_launch_zp(s, 0, Q->f[l], Q->u[l], n, 4, nullptr, nullptr, nullptr, nullptr, Q->st, nullptr,
+                 0, nullptr, stop);
+    for (int sw = 2; sw < 2 * nu; ++sw)
+      k3_launch_hs(s, Q->u[l], Q->f[l], n, !(sw & 1), 0, Q->st, nullptr, 0, stop);
+    k3_launch_rr(s, Q->u[l], Q->f[l], Q->f[l + 1], n, Q->lnf[l + 1], 0, Q->st, nullptr, 0, stop);
   }
+  k3_launch_cvc(s, Q->f[Q->lc], Q->u[Q->lc], Q->cvc, Q->cinv, nu, stop);
+  auto fin = [&](int l) { return l < Q->lc ? Q->uo[l] : Q->u[l]; };
+  for (int l = Q->lc - 1; l >= 1; --l) {
+    const int n = Q->lnf[l];
+    k3_launch_pr(s, Q->u[l], fin(l + 1), Q->f[l], Q->uo[l], n, Q->lnf[l + 1], stop);
+    for (int sw = 1; sw < 2 * nu; ++sw)
+      k3_launch_hs(s, Q->uo[l], Q->f[l], n, sw & 1, 0, Q->st, nullptr, 0, stop);
+  }
+  k3_launch_pr(s, Q->u[0], fin(1), f0, Q->uo[0], nf, Q->lnf[1], stop);
+  for (int sw = 1; sw + 1 < 2 * nu; ++sw)
+    k3_launch_hs(s, Q->uo[0], f0, nf, sw & 1, 0, Q->st, nullptr, 0, stop);
+  k3_launch_hsz(s, Q->uo[0], f0, nf, Q->rows0, Q->part0, stop);
+}
+
+// PCG iteration k: p_k, q = L7 p_k, then the V-cycle that starts with the residual update
+void iteration3(Problem3D* Q, hipStream_t s, int nu, int k) {
+  k3_launch_apply1(s, Q->uo[0], Q->PB[(k + 1) & 1], Q->PB[k & 1], Q->q, Q->nf, Q->rows0, Q->st,
+                   Q->part0, Q->np0, Q->part1, Q->stop);
+  vcycle3(Q, s, nu, 2, k);
 }
 
 int sync_state(Problem3D* Q, hipStream_t s) {
@@ -192,44 +236,38 @@ int capture(hipStream_t s, Fn fn, hipGraphExec_t* out) {
   return FDD_OK;
 }
 
-// L7 x = f (f from rhs), to ||f - L7 x|| <= tol ||f||; x stays in Q->x (padded)
+// L7 x = f (f from rhs), to ||f - L7 x|| <= tol ||f||; x stays in Q->x (padded).  The
+// iterations of the last solve are enqueued before the state is first read back, then one at a
+// time (an iteration enqueued after convergence returns at once in every pass).
 int interior3(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int maxit, int nu,
               int* its) {
   Problem3D* Q = P->p3;
   const int nf = Q->nf;
-  k3_launch_rhs(s, rhs, Q->r, nf);
+  if (Q->use_graph && Q->g_nu != nu) {
+    for (hipGraphExec_t* g : {&Q->g_init, &Q->g_it[0], &Q->g_it[1]}) {
+      if (*g) (void)hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
+    int rc = capture(s, [&]() { vcycle3(Q, s, nu, 1, 0); }, &Q->g_init);
+    for (int par = 0; par < 2 && !rc; ++par)
+      rc = capture(s, [&]() { iteration3(Q, s, nu, par); }, &Q->g_it[par]);
+    if (rc) return rc;
+    Q->g_nu = nu;
+  }
+  k3_launch_rhs(s, rhs, Q->R[0], nf);
   HIPCHK(hipMemsetAsync(Q->x, 0, 8 * vol(nf), s));
   *Q->htol = tol * tol;
   HIPCHK(hipMemcpyAsync(&Q->st->tol2, Q->htol, sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(Q->stop, 0, sizeof(int), s));
-  vcycle3(Q, s, nu);
-  k3_launch_dot(s, Q->r, Q->r, nf, Q->part0, nullptr);
-  k3_launch_dot(s, Q->r, Q->z, nf, Q->part1, nullptr);
-  k3_launch_scalars(s, Q->st, Q->part0, Q->part1, 0, Q->stop);
-  k3_launch_pupdate(s, Q->p, Q->z, nf, Q->st, 1, Q->stop);
-  int done = 0;
-  auto chunk = [&]() {
-    for (int c = 0; c < kChunk3; ++c) {
-      k3_launch_apply(s, Q->p, Q->q, nf, Q->part0, Q->stop);
-      k3_launch_scalars(s, Q->st, Q->part0, nullptr, 1, Q->stop);
-      k3_launch_update(s, Q->x, Q->r, Q->p, Q->q, nf, Q->st, Q->part0, Q->stop);
-      k3_launch_scalars(s, Q->st, Q->part0, nullptr, 2, Q->stop);
-      vcycle3(Q, s, nu);
-      k3_launch_dot(s, Q->r, Q->z, nf, Q->part0, Q->stop);
-      k3_launch_scalars(s, Q->st, Q->part0, nullptr, 3, Q->stop);
-      k3_launch_pupdate(s, Q->p, Q->z, nf, Q->st, 0, Q->stop);
+  if (Q->use_graph) HIPCHK(hipGraphLaunch(Q->g_init, s));
+  else vcycle3(Q, s, nu, 1, 0);
+  int done = 0, enq = 0;
+  int target = std::min(std::max(Q->pred_its - 1, 1), maxit);
+  while (true) {
+    for (; enq < target; ++enq) {
+      if (Q->use_graph) HIPCHK(hipGraphLaunch(Q->g_it[enq & 1], s));
+      else iteration3(Q, s, nu, enq);
     }
-  };
-  if (Q->use_graph && (!Q->g_inner || Q->g_inner_nu != nu)) {
-    if (Q->g_inner) (void)hipGraphExecDestroy(Q->g_inner);
-    Q->g_inner = nullptr;
-    int rc = capture(s, chunk, &Q->g_inner);
-    if (rc) return rc;
-    Q->g_inner_nu = nu;
-  }
-  for (int it = 0; it < maxit; it += kChunk3) {
-    if (Q->use_graph) HIPCHK(hipGraphLaunch(Q->g_inner, s));
-    else chunk();
     HIPCHK(hipGetLastError());
     int rc = sync_state(Q, s);
     if (rc) return rc;
@@ -237,13 +275,11 @@ int interior3(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int 
       done = 1;
       break;
     }
-  }
-  if (!done) {
-    int rc = sync_state(Q, s);
-    if (rc) return rc;
-    done = *Q->hstop;
+    if (enq >= maxit) break;
+    target = enq + 1;
   }
   if (its) *its = Q->hst->its;
+  if (done && !Q->hst->breakdown) Q->pred_its = std::max(Q->hst->its, 1);
   if (Q->hst->breakdown)
     return fail(Q->hst->breakdown & 4 ? FDD_E_NONFINITE : FDD_E_BREAKDOWN,
                 "3D interior solve: breakdown (flags %d)", Q->hst->breakdown);
@@ -281,18 +317,20 @@ Shift3 table3(const fdd_ratpc_s* t) {
   return T;
 }
 
-// preconditioner of the face systems: z = S D^{-1} S r (batched)
-void face_prec(Problem3D* Q, hipStream_t s, const double* r, double* z, int m, const Shift3* tab,
-               double h) {
+// face-CG iteration k of a batch (both vector passes, then the preconditioner with the test)
+void face_iteration(Problem3D* Q, hipStream_t s, const Shift3* tab, int m, double tol2, int k) {
   const int nf = Q->nf;
-  kf_launch_dst(s, Q->S, r, Q->ft, nf, m, 1, Q->done);
-  kf_launch_dst(s, Q->S, Q->ft, z, nf, m, 0, Q->done);
-  kf_launch_diag(s, z, nf, Q->n, h, m, tab, Q->done);
-  kf_launch_dst(s, Q->S, z, Q->ft, nf, m, 1, Q->done);
-  kf_launch_dst(s, Q->S, Q->ft, z, nf, m, 0, Q->done);
+  const double h = 1.0 / Q->n;
+  kf_launch_apply1(s, Q->fz, Q->fp[(k + 1) & 1], Q->fp[k & 1], Q->fq, nf, h, m, tab, Q->cg,
+                   Q->fpart0, kf_tiles(nf), Q->fpart1, Q->done);
+  kf_launch_axpy1(s, Q->fy, Q->fr, Q->fp[k & 1], Q->fq, nf, m, Q->cg, Q->fpart1, Q->fpart0,
+                  Q->done);
+  kf_launch_prec(s, Q->S, Q->fr, Q->ft, Q->fz, nf, Q->n, h, m, tab, Q->cg, Q->fpart0, tol2, 2,
+                 Q->fpart0, Q->done);
 }
 
-// out = preconditioner (which 0) or H_RA (which 1) applied to `in` (face vectors)
+// out = preconditioner (which 0) or H_RA (which 1) applied to `in` (face vectors).  The
+// iterations of the last batch of the same kind are enqueued before the flags are first read.
 int face_batch(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* T, const double* in,
                double* out) {
   Problem3D* Q = P->p3;
@@ -306,46 +344,45 @@ int face_batch(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* T, const doub
   Shift3* tab = Q->tabs + which;
   HIPCHK(hipMemcpyAsync(tab, Q->htab, sizeof(Shift3), hipMemcpyHostToDevice, s));
   const double tol = which ? kFaceTolH : kFaceTolP;
-  HIPCHK(hipMemsetAsync(Q->done, 0, sizeof(int) * kMaxSys3, s));
-  HIPCHK(hipMemsetAsync(Q->cg, 0, sizeof(FaceCG), s));
-  kf_launch_bcast(s, in, Q->fr, nf, h, m, which);
-  kf_launch_bcast(s, nullptr, Q->fy, nf, h, m, 0);
-  face_prec(Q, s, Q->fr, Q->fz, m, tab, h);
-  kf_launch_dot(s, Q->fr, Q->fr, nf, m, Q->fpart0, nullptr);
-  kf_launch_dot(s, Q->fr, Q->fz, nf, m, Q->fpart1, nullptr);
-  kf_launch_scalars(s, Q->cg, Q->fpart0, Q->fpart1, m, 0, Q->done, tol * tol);
-  kf_launch_axpy(s, nullptr, nullptr, Q->fp, nullptr, Q->fz, nf, m, Q->cg->beta, 1, 1, Q->done);
-  bool all = false;
-  auto chunk = [&]() {
-    for (int c = 0; c < kChunk3; ++c) {
-      kf_launch_apply(s, Q->fp, 0, Q->fq, nf, h, m, tab, Q->fpart0, Q->done);
-      kf_launch_scalars(s, Q->cg, Q->fpart0, nullptr, m, 1, Q->done, tol * tol);
-      kf_launch_axpy(s, Q->fy, Q->fr, Q->fp, Q->fq, nullptr, nf, m, Q->cg->alpha, 0, 0, Q->done);
-      kf_launch_dot(s, Q->fr, Q->fr, nf, m, Q->fpart0, Q->done);
-      kf_launch_scalars(s, Q->cg, Q->fpart0, nullptr, m, 2, Q->done, tol * tol);
-      face_prec(Q, s, Q->fr, Q->fz, m, tab, h);
-      kf_launch_dot(s, Q->fr, Q->fz, nf, m, Q->fpart0, Q->done);
-      kf_launch_scalars(s, Q->cg, Q->fpart0, nullptr, m, 3, Q->done, tol * tol);
-      kf_launch_axpy(s, nullptr, nullptr, Q->fp, nullptr, Q->fz, nf, m, Q->cg->beta, 1, 0, Q->done);
+  const double tol2 = tol * tol;
+  if (Q->use_graph && Q->g_face_m[which] != m) {
+    for (hipGraphExec_t& g : Q->g_face[which]) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
     }
-  };
-  if (Q->use_graph && (!Q->g_face[which] || Q->g_face_m[which] != m)) {
-    if (Q->g_face[which]) (void)hipGraphExecDestroy(Q->g_face[which]);
-    Q->g_face[which] = nullptr;
-    int rc = capture(s, chunk, &Q->g_face[which]);
-    if (rc) return rc;
+    for (int par = 0; par < 2; ++par) {
+      int rc = capture(s, [&]() { face_iteration(Q, s, tab, m, tol2, par); },
+                       &Q->g_face[which][par]);
+      if (rc) return rc;
+    }
     Q->g_face_m[which] = m;
   }
-  for (int it = 0; it < 400 && !all; it += kChunk3) {
-    if (Q->use_graph) HIPCHK(hipGraphLaunch(Q->g_face[which], s));
-    else chunk();
+  HIPCHK(hipMemsetAsync(Q->done, 0, sizeof(int) * kMaxSys3, s));
+  HIPCHK(hipMemsetAsync(Q->cg, 0, sizeof(FaceCG), s));
+  kf_launch_start(s, in, Q->fr, Q->fy, nf, h, m, which, Q->fpart0);
+  kf_launch_prec(s, Q->S, Q->fr, Q->ft, Q->fz, nf, Q->n, h, m, tab, Q->cg, Q->fpart0, tol2, 1,
+                 Q->fpart0, Q->done);
+  constexpr int kMaxFace = 400;
+  bool all = false;
+  int enq = 0, target = std::max(Q->pred_face[which] - 1, 1);
+  while (true) {
+    for (; enq < target; ++enq) {
+      if (Q->use_graph) HIPCHK(hipGraphLaunch(Q->g_face[which][enq & 1], s));
+      else face_iteration(Q, s, tab, m, tol2, enq);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(Q->hdone, Q->done, sizeof(int) * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(Q->hits, Q->cg->its, sizeof(int) * m, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     all = true;
     for (int k = 0; k < m; ++k) all = all && Q->hdone[k];
+    if (all || enq >= kMaxFace) break;
+    target = enq + 1;
   }
   if (!all) return fail(FDD_NOT_CONVERGED, "3D face solves did not converge");
+  int most = 1;
+  for (int k = 0; k < m; ++k) most = std::max(most, Q->hits[k]);
+  Q->pred_face[which] = most;
   kf_launch_combine(s, Q->fy, m, nf, h, tab, which, in, Q->ftmp, out, d0);
   HIPCHK(hipGetLastError());
   return FDD_OK;
@@ -427,7 +464,7 @@ int setup3(const fdd_desc* d, int hip_device, fdd_problem_s* P) {
   int nf = n - 1, l = 0;
   while (true) {
     Q->lnf[l] = nf;
-    if (!(nf & 1) || nf <= 3) break;
+    if (!(nf & 1) || nf <= 1) break;
     nf = (nf - 1) / 2;
     if (++l >= kMaxLevels) {
       delete Q;
@@ -440,6 +477,17 @@ int setup3(const fdd_desc* d, int hip_device, fdd_problem_s* P) {
     delete Q;
     return fail(FDD_E_ARG, "3D: n = %d leaves a %d^3 coarsest grid (max 4^3)", n, Q->nc);
   }
+  // the coarse levels that fit one workgroup's LDS (level 0 always runs on the full grid)
+  Q->lc = 1;
+  while (Q->lc < Q->nlev && Q->lnf[Q->lc] > kCvcMax) ++Q->lc;
+  Q->cvc.nl = Q->nlev - Q->lc;
+  for (int k = 0; k < Q->cvc.nl && k < kCvcLevels; ++k) Q->cvc.lev[k] = Q->lnf[Q->lc + k];
+  if (Q->lc >= Q->nlev || !k3_cvc_fits(Q->cvc)) {
+    delete Q;
+    return fail(FDD_E_ARG, "3D: n = %d: the coarse levels do not fit one workgroup", n);
+  }
+  Q->rows0 = k3_rows_red(Q->nf);
+  Q->np0 = ((Q->nf + Q->rows0 - 1) / Q->rows0) * Q->nf;
   Q->cinv_h = dense_inverse_7pt(Q->nc);
   const int m = Q->nf;
   Q->S_h.resize((size_t)m * m);
@@ -483,6 +531,7 @@ int bind3(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s) {
     HIPCHK(hipHostMalloc((void**)&Q->hst, sizeof(State3), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&Q->hstop, sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&Q->hdone, sizeof(int) * kMaxSys3, hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&Q->hits, sizeof(int) * kMaxSys3, hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&Q->hpart, 8 * 2 * kPart3, hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&Q->htab, sizeof(Shift3), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&Q->htol, sizeof(double), hipHostMallocDefault));
@@ -497,12 +546,14 @@ int bind3(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s) {
 void destroy3(fdd_problem_s* P) {
   Problem3D* Q = P->p3;
   if (!Q) return;
-  for (void* h : {(void*)Q->hst, (void*)Q->hstop, (void*)Q->hdone, (void*)Q->hpart,
+  for (void* h : {(void*)Q->hst, (void*)Q->hstop, (void*)Q->hdone, (void*)Q->hits, (void*)Q->hpart,
                   (void*)Q->htab, (void*)Q->htol})
     if (h) (void)hipHostFree(h);
-  if (Q->g_inner) (void)hipGraphExecDestroy(Q->g_inner);
-  for (auto g : Q->g_face)
+  for (hipGraphExec_t g : {Q->g_init, Q->g_it[0], Q->g_it[1]})
     if (g) (void)hipGraphExecDestroy(g);
+  for (auto& gw : Q->g_face)
+    for (hipGraphExec_t g : gw)
+      if (g) (void)hipGraphExecDestroy(g);
   delete Q;
   P->p3 = nullptr;
 }

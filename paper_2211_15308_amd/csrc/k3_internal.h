@@ -18,11 +18,24 @@ struct Rhs3 {
   double sg;
 };
 
-// device scalars of the interior PCG
+// device scalars of the interior PCG (rho[k & 1] = r_k . z_k)
 struct State3 {
-  double ff, rr, rho, alpha, beta, tol2;
+  double ff, rr, rho[2], tol2;
   int its, breakdown;
 };
+
+// levels of the one-workgroup coarse V-cycle (padded grids of edge lev + 2 in LDS)
+constexpr int kCvcLevels = 4;
+constexpr int kCvcMax = 15;  // finest level it takes
+struct Cvc3 {
+  int nl;
+  int lev[kCvcLevels];
+};
+int k3_cvc_fits(const Cvc3& L);  // the levels fit the kernel's LDS
+
+// block partials of the level-0 reduction kernels (at most ceil(nf / rows) nf < 1024 + nf)
+constexpr int kPart0 = 2048;
+int k3_rows_red(int nf);  // rows per block of the level-0 reduction kernels
 
 // shift table of a face batch: system s is (alpha_s A_G + beta_s M_G) y = rhs, weight coef_s
 struct Shift3 {
@@ -31,47 +44,47 @@ struct Shift3 {
   int m;
 };
 
-// device scalars of a face batch (per system)
+// device scalars of a face batch (per system; rho[k & 1] = r_k . z_k)
 struct FaceCG {
-  double rr0[kMaxSys3], rho[kMaxSys3], alpha[kMaxSys3], beta[kMaxSys3];
+  double rr0[kMaxSys3], rho[2][kMaxSys3];
   int its[kMaxSys3], bad[kMaxSys3];
 };
+constexpr int kPFS = 256;  // partials per system of the face kernels (>= ceil(nf / 16)^2)
 
-void k3_launch_rb(hipStream_t s, double* u, const double* f, int nf, int red, int from_zero,
-                  const int* stop);
-void k3_launch_resid(hipStream_t s, const double* u, const double* f, double* t, int nf,
-                     const int* stop);
-void k3_launch_restrict(hipStream_t s, const double* t, double* fc, int nf, int nc,
-                        const int* stop);
-void k3_launch_prolong(hipStream_t s, const double* ec, double* u, int nf, int nc,
-                       const int* stop);
-void k3_launch_coarse(hipStream_t s, const double* f, double* u, int nc, const double* cinv,
-                      const int* stop);
+// multigrid and PCG kernels of the interior solve (see kernels_3d.hip for what each computes);
+// rows: grid rows per block; pin/np: partials read; part: partials written
+void k3_launch_zp(hipStream_t s, int mode, const double* f, double* u, int nf, int rows,
+                  const double* q, double* rnew, double* x, const double* p, State3* st,
+                  const double* pin, int np, double* part, int* stop);
+void k3_launch_hs(hipStream_t s, double* u, const double* f, int nf, int red, int check,
+                  State3* st, const double* pin, int np, int* stop);
+void k3_launch_rr(hipStream_t s, const double* u, const double* f, double* fc, int nf, int nc,
+                  int check, State3* st, const double* pin, int np, int* stop);
+void k3_launch_pr(hipStream_t s, const double* u, const double* ec, const double* f, double* uo,
+                  int nf, int nc, int* stop);
+void k3_launch_hsz(hipStream_t s, double* u, const double* f, int nf, int rows, double* part,
+                   int* stop);
+void k3_launch_apply1(hipStream_t s, const double* z, const double* pold, double* pnew, double* q,
+                      int nf, int rows, State3* st, const double* pin, int np, double* part,
+                      int* stop);
+void k3_launch_cvc(hipStream_t s, const double* fin, double* uout, const Cvc3& L,
+                   const double* cinv, int nu, int* stop);
 void k3_launch_rhs(hipStream_t s, const Rhs3& rhs, double* f, int nf);
-void k3_launch_dot(hipStream_t s, const double* a, const double* b, int nf, double* part,
-                   const int* stop);
-void k3_launch_apply(hipStream_t s, const double* p, double* q, int nf, double* part,
-                     const int* stop);
-void k3_launch_update(hipStream_t s, double* x, double* r, const double* p, const double* q,
-                      int nf, const State3* st, double* part, const int* stop);
-void k3_launch_pupdate(hipStream_t s, double* p, const double* z, int nf, const State3* st,
-                       int first, const int* stop);
-void k3_launch_scalars(hipStream_t s, State3* st, const double* part0, const double* part1,
-                       int kind, int* stop);
 void k3_launch_gather(hipStream_t s, const double* u, int nf, double* out, const double* xg);
-void kf_launch_apply(hipStream_t s, const double* x, int x_shared, double* y, int nf, double h,
-                     int m, const Shift3* tab, double* part, const int* done);
-void kf_launch_dst(hipStream_t s, const double* S, const double* B, double* C, int nf, int m,
-                   int left, const int* done);
-void kf_launch_diag(hipStream_t s, double* z, int nf, int n, double h, int m, const Shift3* tab,
-                    const int* done);
-void kf_launch_dot(hipStream_t s, const double* a, const double* b, int nf, int m, double* part,
-                   const int* done);
-void kf_launch_axpy(hipStream_t s, double* y, double* r, double* p, const double* q,
-                    const double* z, int nf, int m, const double* coef, int kind, int first,
-                    const int* done);
-void kf_launch_scalars(hipStream_t s, FaceCG* cg, const double* part0, const double* part1, int m,
-                       int kind, int* done, double tol2);
+// batched face CG (kernels_3d.hip): start (r = src or M src, y = 0), the two vector passes of
+// an iteration, and the preconditioner z = S D^{-1} S r (four DST passes; check 1: start test,
+// 2: convergence test, on the |r|^2 partials pin; part: r . z partials, kf_tiles(nf) per system)
+void kf_launch_start(hipStream_t s, const double* src, double* r, double* y, int nf, double h,
+                     int m, int mass, double* part);
+void kf_launch_apply1(hipStream_t s, const double* z, const double* pold, double* pnew, double* q,
+                      int nf, double h, int m, const Shift3* tab, FaceCG* cg, const double* pin,
+                      int cnt, double* part, int* done);
+void kf_launch_axpy1(hipStream_t s, double* y, double* r, const double* p, const double* q, int nf,
+                     int m, FaceCG* cg, const double* pin, double* part, int* done);
+void kf_launch_prec(hipStream_t s, const double* S, const double* r, double* ft, double* z, int nf,
+                    int n, double h, int m, const Shift3* tab, FaceCG* cg, const double* pin,
+                    double tol2, int check, double* part, int* done);
+int kf_tiles(int nf);
 void kf_launch_combine(hipStream_t s, const double* ys, int m, int nf, double h, const Shift3* tab,
                        int op, const double* x, double* tmp, double* out, double d0);
 void kf_launch_schur(hipStream_t s, const double* p, const double* u, int nf, double h, double K,
@@ -86,7 +99,5 @@ void k3_launch_scale_add(hipStream_t s, double* out, const double* u, double c, 
 void kf_launch_rhs_reduce(hipStream_t s, const double* bG, const double* w, int nf, double h,
                           double* g, double* xg);
 void kf_launch_vdot(hipStream_t s, const double* a, const double* b, int64_t N, double* part);
-void kf_launch_bcast(hipStream_t s, const double* src, double* dst, int nf, double h, int m,
-                     int mass);
 
 }  // namespace fdd

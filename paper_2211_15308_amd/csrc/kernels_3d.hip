@@ -50,99 +50,401 @@ __device__ __forceinline__ size_t pidx(int64_t q, int nf, int* i, int* j, int* k
 }
 
 // ---- multigrid -------------------------------------------------------------------------------
+// The level kernels run 64 x 4 threads (one wavefront per row of the block); block (bx, by)
+// covers plane k = by + 1, rows bx * rows + 1 .. (bx + 1) * rows and every column, so the
+// points need no index division and the partials of a reduction kernel number
+// ceil(nf / rows) * nf.
 
-// Half-sweep of colour `red` ((i + j + k) even) of L7 u = f.  from_zero: the first red
-// half-sweep from u = 0 (u = f / 6 on red points, 0 on black ones).
-__global__ __launch_bounds__(kB3) void k3_rb(double* __restrict__ u, const double* __restrict__ f,
-                                            int nf, int red, int from_zero,
-                                            const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  const size_t P = (size_t)nf + 2, PP = P * P;
-  const int64_t N = (int64_t)nf * nf * nf;
-  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
-    int i, j, k;
-    const size_t o = pidx(q, nf, &i, &j, &k);
-    const bool is_red = ((i + j + k) & 1) == 0;
-    if (from_zero) {
-      u[o] = is_red ? f[o] * (1.0 / 6.0) : 0.0;
-    } else if (is_red == (red != 0)) {
+constexpr int kX3 = 64, kY3 = 4;
+
+template <typename Fn>
+__device__ __forceinline__ void for_points(int nf, int rows, Fn&& fn) {
+  const int k = blockIdx.y + 1;
+  const int jb = blockIdx.x * rows;
+  const int je = min(jb + rows, nf);
+  for (int j = jb + 1 + (int)threadIdx.y; j <= je; j += kY3)
+    for (int i = 1 + (int)threadIdx.x; i <= nf; i += kX3) fn(i, j, k);
+}
+
+__device__ __forceinline__ int tid3() { return (int)(threadIdx.y * kX3 + threadIdx.x); }
+__device__ __forceinline__ bool lead3() {
+  return blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && threadIdx.y == 0;
+}
+
+// Sum over the block in a fixed order, broadcast to every thread.
+__device__ __forceinline__ double bsum3(double v) {
+  __shared__ double sh[kY3 + 1];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  __syncthreads();
+  if (threadIdx.x == 0) sh[threadIdx.y] = v;
+  __syncthreads();
+  if (tid3() == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kY3; ++w) s += sh[w];
+    sh[kY3] = s;
+  }
+  __syncthreads();
+  return sh[kY3];
+}
+
+// Sum of np block partials (written by an earlier kernel), the same in every block.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int np) {
+  double a = 0.0;
+  for (int q = tid3(); q < np; q += kX3 * kY3) a += part[q];
+  return bsum3(a);
+}
+
+__device__ __forceinline__ void put_partial(double* part, double v) {
+  v = bsum3(v);
+  if (tid3() == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = v;
+}
+
+__device__ __forceinline__ bool is_red3(int i, int j, int k) { return ((i + j + k) & 1) == 0; }
+
+// Convergence bookkeeping of the interior PCG, done by the first kernel after the residual
+// update (every block sums the same partials and takes the same decision; the lead block
+// records it).  mode 1: start, the partials are |f|^2 (ff = rr = |f|^2, its = 0; f = 0 stops);
+// mode 2: the partials are |r_{k+1}|^2 (its += 1; stop at |r|^2 <= tol^2 |f|^2).
+__device__ __forceinline__ bool k3_check(State3* st, int* stop, const double* part, int np,
+                                         int mode) {
+  const double a = sum_partials(part, np);
+  const bool bad = !isfinite(a);
+  bool halt;
+  if (mode == 1) {
+    halt = bad || a == 0.0;
+    if (lead3()) {
+      st->ff = a;
+      st->rr = a;
+      st->its = 0;
+      st->breakdown = bad ? 4 : 0;
+      if (halt) *stop = 1;
+    }
+  } else {
+    halt = bad || a <= st->tol2 * st->ff;
+    if (lead3()) {
+      st->rr = a;
+      st->its += 1;
+      if (bad) st->breakdown |= 4;
+      if (halt) *stop = 1;
+    }
+  }
+  return halt;
+}
+
+// Going down, first two half-sweeps from u = 0 (red, then black) in one pass: u = f / 6 on red
+// points and, on black points, (f + sum of the six red neighbours' f / 6) / 6.
+// MODE 0: f given.  MODE 1 (level 0, start of a solve): also partials of |f|^2.
+// MODE 2 (level 0, PCG iteration k): alpha_k = rho_k / (p_k . A p_k) from the partials of the
+// previous kernel, f = r_{k+1} = r_k - alpha_k q formed on the fly (q = A p_k), r_{k+1} stored,
+// x += alpha_k p_k, partials of |r_{k+1}|^2.
+template <int MODE>
+__global__ __launch_bounds__(kX3* kY3) void k3_zp(const double* __restrict__ f,
+                                                   double* __restrict__ u, int nf, int rows,
+                                                   const double* __restrict__ qv,
+                                                   double* __restrict__ rnew,
+                                                   double* __restrict__ x,
+                                                   const double* __restrict__ p, State3* st,
+                                                   const double* __restrict__ pin, int np,
+                                                   double* __restrict__ part, int* stop) {
+  if (*stop) return;
+  double al = 0.0;
+  if constexpr (MODE == 2) {
+    const double pq = sum_partials(pin, np);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      if (lead3()) {
+        st->breakdown |= isfinite(pq) ? 1 : 4;
+        *stop = 1;
+      }
+      return;
+    }
+    al = st->rho[st->its & 1] / pq;
+  }
+  const int P = nf + 2, PP = P * P;
+  auto F = [&](int o) -> double {
+    if constexpr (MODE == 2) return f[o] - al * qv[o];
+    else return f[o];
+  };
+  double acc = 0.0;
+  for_points(nf, rows, [&](int i, int j, int k) {
+    const int o = (k * P + j) * P + i;
+    const double fo = F(o);
+    double v;
+    if (is_red3(i, j, k)) {
+      v = fo * (1.0 / 6.0);
+    } else {
+      const double s = F(o - 1) + F(o + 1) + F(o - P) + F(o + P) + F(o - PP) + F(o + PP);
+      v = (fo + s * (1.0 / 6.0)) * (1.0 / 6.0);
+    }
+    u[o] = v;
+    if constexpr (MODE == 2) {
+      rnew[o] = fo;
+      x[o] += al * p[o];
+    }
+    acc += fo * fo;
+  });
+  if constexpr (MODE != 0) put_partial(part, acc);
+}
+
+// Half-sweep of one colour (red: i + j + k even) of L7 u = f, in place; check != 0: first the
+// convergence bookkeeping of k3_check.
+__global__ __launch_bounds__(kX3* kY3) void k3_hs(double* __restrict__ u,
+                                                   const double* __restrict__ f, int nf, int rows,
+                                                   int red, int check, State3* st,
+                                                   const double* __restrict__ pin, int np,
+                                                   int* stop) {
+  if (*stop) return;
+  if (check && k3_check(st, stop, pin, np, check)) return;
+  const int P = nf + 2, PP = P * P;
+  const int want = red ? 0 : 1;
+  for_points(nf, rows, [&](int i, int j, int k) {
+    if (((i + j + k) & 1) != want) return;
+    const int o = (k * P + j) * P + i;
+    u[o] = (f[o] + u[o - 1] + u[o + 1] + u[o - P] + u[o + P] + u[o - PP] + u[o + PP]) *
+           (1.0 / 6.0);
+  });
+}
+
+// Residual and restriction in one pass: f_c(I) = 1/2 [t(2I) + 1/2 sum over the 14 Kuhn-edge
+// neighbours 2I +- d of t], t = f - L7 u formed where it is read (every such fine point is
+// interior).  Grid over the coarse points; check as in k3_hs.
+__global__ __launch_bounds__(kX3* kY3) void k3_rr(const double* __restrict__ u,
+                                                   const double* __restrict__ f,
+                                                   double* __restrict__ fc, int nf, int nc,
+                                                   int rows, int check, State3* st,
+                                                   const double* __restrict__ pin, int np,
+                                                   int* stop) {
+  if (*stop) return;
+  if (check && k3_check(st, stop, pin, np, check)) return;
+  const int P = nf + 2, PP = P * P, Pc = nc + 2;
+  auto T = [&](int o) {
+    return f[o] - (6.0 * u[o] - u[o - 1] - u[o + 1] - u[o - P] - u[o + P] - u[o - PP] -
+                   u[o + PP]);
+  };
+  for_points(nc, rows, [&](int I, int J, int K) {
+    const int o = ((2 * K) * P + 2 * J) * P + 2 * I;
+    // Kuhn edge directions: e1, e2, e3, e1+e2, e1+e3, e2+e3, e1+e2+e3
+    const int d1 = 1, d2 = P, d3 = PP;
+    const double s = T(o + d1) + T(o - d1) + T(o + d2) + T(o - d2) + T(o + d3) + T(o - d3) +
+                     T(o + d1 + d2) + T(o - d1 - d2) + T(o + d1 + d3) + T(o - d1 - d3) +
+                     T(o + d2 + d3) + T(o - d2 - d3) + T(o + d1 + d2 + d3) +
+                     T(o - d1 - d2 - d3);
+    fc[(K * Pc + J) * Pc + I] = 0.5 * (T(o) + 0.5 * s);
+  });
+}
+
+// Going up: v = u + P e_c (a fine node at 2I + d, d in {0,1}^3, takes the mean of the coarse
+// nodes I and I + d), then the first black half-sweep on v, in one pass into uo (uo != u:
+// the black points read their red neighbours' v, formed where they are read).
+__global__ __launch_bounds__(kX3* kY3) void k3_pr(const double* __restrict__ u,
+                                                   const double* __restrict__ ec,
+                                                   const double* __restrict__ f,
+                                                   double* __restrict__ uo, int nf, int nc,
+                                                   int rows, int* stop) {
+  if (*stop) return;
+  const int P = nf + 2, Pc = nc + 2;
+  // valid on the zero border too: the coarse nodes read there lie on the coarse border
+  auto V = [&](int i, int j, int k) {
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int oc = (K * Pc + J) * Pc + I;
+    const int od = ((k & 1) * Pc + (j & 1)) * Pc + (i & 1);
+    const double e = od ? 0.5 * (ec[oc] + ec[oc + od]) : ec[oc];
+    return u[(k * P + j) * P + i] + e;
+  };
+  for_points(nf, rows, [&](int i, int j, int k) {
+    const int o = (k * P + j) * P + i;
+    double v;
+    if (is_red3(i, j, k)) {
+      v = V(i, j, k);
+    } else {
+      v = (f[o] + V(i - 1, j, k) + V(i + 1, j, k) + V(i, j - 1, k) + V(i, j + 1, k) +
+           V(i, j, k - 1) + V(i, j, k + 1)) *
+          (1.0 / 6.0);
+    }
+    uo[o] = v;
+  });
+}
+
+// Last half-sweep of the V-cycle on level 0 (red) with the partials of r . z (f = r, z = u).
+__global__ __launch_bounds__(kX3* kY3) void k3_hsz(double* __restrict__ u,
+                                                    const double* __restrict__ f, int nf,
+                                                    int rows, double* __restrict__ part,
+                                                    int* stop) {
+  if (*stop) return;
+  const int P = nf + 2, PP = P * P;
+  double acc = 0.0;
+  for_points(nf, rows, [&](int i, int j, int k) {
+    const int o = (k * P + j) * P + i;
+    double z = u[o];
+    if (is_red3(i, j, k)) {
+      z = (f[o] + u[o - 1] + u[o + 1] + u[o - P] + u[o + P] + u[o - PP] + u[o + PP]) *
+          (1.0 / 6.0);
+      u[o] = z;
+    }
+    acc += f[o] * z;
+  });
+  put_partial(part, acc);
+}
+
+// PCG iteration k, first pass: rho_k = r_k . z_k from the partials of the V-cycle,
+// beta_k = rho_k / rho_{k-1} (beta_0 = 0), p_k = z_k + beta_k p_{k-1} (stored; also formed at
+// the neighbours), q = L7 p_k, partials of p_k . q.  rho_k is recorded in st->rho[k & 1].
+__global__ __launch_bounds__(kX3* kY3) void k3_apply1(const double* __restrict__ z,
+                                                       const double* __restrict__ pold,
+                                                       double* __restrict__ pnew,
+                                                       double* __restrict__ qv, int nf, int rows,
+                                                       State3* st, const double* __restrict__ pin,
+                                                       int np, double* __restrict__ part,
+                                                       int* stop) {
+  if (*stop) return;
+  const double rz = sum_partials(pin, np);
+  const int it = st->its;
+  if (!(rz > 0.0) || !isfinite(rz)) {
+    if (lead3()) {
+      st->breakdown |= isfinite(rz) ? 1 : 4;
+      *stop = 1;
+    }
+    return;
+  }
+  const double beta = it ? rz / st->rho[(it - 1) & 1] : 0.0;
+  if (lead3()) st->rho[it & 1] = rz;
+  const int P = nf + 2, PP = P * P;
+  auto PV = [&](int o) { return it ? z[o] + beta * pold[o] : z[o]; };
+  double acc = 0.0;
+  for_points(nf, rows, [&](int i, int j, int k) {
+    const int o = (k * P + j) * P + i;
+    const double pv = PV(o);
+    const double q = 6.0 * pv - PV(o - 1) - PV(o + 1) - PV(o - P) - PV(o + P) - PV(o - PP) -
+                     PV(o + PP);
+    pnew[o] = pv;
+    qv[o] = q;
+    acc += pv * q;
+  });
+  put_partial(part, acc);
+}
+
+// Coarse part of the V-cycle in one workgroup: the levels lev[0] > lev[1] > ... > lev[nl - 1]
+// (lev[0] <= kCvcMax) held in LDS, the same smoothing, transfers and dense inverse on the
+// coarsest grid as the level kernels; f of the first level from fin, its result to uout.
+constexpr int kCvcThreads = 1024;
+constexpr int kCvcLds = 11600;  // doubles: u and f of 15, 7, 3 and 1 (padded)
+
+__device__ __forceinline__ int cvc_pad(int q, int nf) {
+  const int i = q % nf + 1, r = q / nf, j = r % nf + 1, k = r / nf + 1;
+  return (k * (nf + 2) + j) * (nf + 2) + i;
+}
+
+__global__ __launch_bounds__(kCvcThreads) void k3_cvc(const double* __restrict__ fin,
+                                                       double* __restrict__ uout, Cvc3 L,
+                                                       const double* __restrict__ cinv, int nu,
+                                                       const int* __restrict__ stop) {
+  if (*stop) return;
+  __shared__ double lds[kCvcLds];
+  const int t = threadIdx.x;
+  // level l: u at U[l], f at Fv[l] (the loops over levels are unrolled: static indices)
+  double* U[kCvcLevels];
+  double* Fv[kCvcLevels];
+  int ed[kCvcLevels];
+  int tot = 0;
+#pragma unroll
+  for (int l = 0; l < kCvcLevels; ++l) {
+    ed[l] = l < L.nl ? L.lev[l] : 0;
+    const int v = (ed[l] + 2) * (ed[l] + 2) * (ed[l] + 2);
+    U[l] = lds + tot;
+    Fv[l] = lds + tot + v;
+    tot += l < L.nl ? 2 * v : 0;
+  }
+  for (int q = t; q < tot; q += kCvcThreads) lds[q] = 0.0;
+  __syncthreads();
+  {
+    const int nf = ed[0], n3 = nf * nf * nf;
+    for (int q = t; q < n3; q += kCvcThreads) {
+      const int o = cvc_pad(q, nf);
+      Fv[0][o] = fin[o];
+    }
+  }
+  __syncthreads();
+  auto half = [&](double* u, const double* f, int nf, int want) {
+    const int P = nf + 2, PP = P * P, n3 = nf * nf * nf;
+    for (int q = t; q < n3; q += kCvcThreads) {
+      const int i = q % nf + 1, r = q / nf, j = r % nf + 1, k = r / nf + 1;
+      if (((i + j + k) & 1) != want) continue;
+      const int o = (k * P + j) * P + i;
       u[o] = (f[o] + u[o - 1] + u[o + 1] + u[o - P] + u[o + P] + u[o - PP] + u[o + PP]) *
              (1.0 / 6.0);
     }
-  }
-}
-
-// t = f - L7 u
-__global__ __launch_bounds__(kB3) void k3_resid(const double* __restrict__ u,
-                                               const double* __restrict__ f,
-                                               double* __restrict__ t, int nf,
-                                               const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  const size_t P = (size_t)nf + 2, PP = P * P;
-  const int64_t N = (int64_t)nf * nf * nf;
-  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
-    int i, j, k;
-    const size_t o = pidx(q, nf, &i, &j, &k);
-    t[o] = f[o] - (6.0 * u[o] - u[o - 1] - u[o + 1] - u[o - P] - u[o + P] - u[o - PP] - u[o + PP]);
-  }
-}
-
-// f_c(I) = 1/2 [t(2I) + 1/2 sum over the 14 Kuhn-edge neighbours 2I +- d of t]
-__global__ __launch_bounds__(kB3) void k3_restrict(const double* __restrict__ t,
-                                                  double* __restrict__ fc, int nf, int nc,
-                                                  const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  const size_t P = (size_t)nf + 2, PP = P * P;
-  const int64_t N = (int64_t)nc * nc * nc;
-  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
-    int I, J, K;
-    const size_t oc = pidx(q, nc, &I, &J, &K);
-    const size_t o = ((size_t)(2 * K) * P + (size_t)(2 * J)) * P + (size_t)(2 * I);
-    // Kuhn edge directions: e1, e2, e3, e1+e2, e1+e3, e2+e3, e1+e2+e3
-    const size_t d1 = 1, d2 = P, d3 = PP;
-    const double s = t[o + d1] + t[o - d1] + t[o + d2] + t[o - d2] + t[o + d3] + t[o - d3] +
-                     t[o + d1 + d2] + t[o - d1 - d2] + t[o + d1 + d3] + t[o - d1 - d3] +
-                     t[o + d2 + d3] + t[o - d2 - d3] + t[o + d1 + d2 + d3] + t[o - d1 - d2 - d3];
-    fc[oc] = 0.5 * (t[o] + 0.5 * s);
-  }
-}
-
-// u += P e_c
-__global__ __launch_bounds__(kB3) void k3_prolong(const double* __restrict__ ec,
-                                                 double* __restrict__ u, int nf, int nc,
-                                                 const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  const size_t Pc = (size_t)nc + 2;
-  const int64_t N = (int64_t)nf * nf * nf;
-  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
-    int i, j, k;
-    const size_t o = pidx(q, nf, &i, &j, &k);
-    const int I = i >> 1, J = j >> 1, K = k >> 1;
-    const size_t oc = ((size_t)K * Pc + (size_t)J) * Pc + (size_t)I;
-    const size_t od = ((size_t)(k & 1) * Pc + (size_t)(j & 1)) * Pc + (size_t)(i & 1);
-    u[o] += od ? 0.5 * (ec[oc] + ec[oc + od]) : ec[oc];
-  }
-}
-
-// coarsest grid: u = C^{-1} f with the dense inverse (nc^3 <= 64 unknowns), one block
-__global__ __launch_bounds__(kB3) void k3_coarse(const double* __restrict__ f,
-                                                double* __restrict__ u, int nc,
-                                                const double* __restrict__ cinv,
-                                                const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  __shared__ double fp[64];
-  const int np = nc * nc * nc;
-  const size_t P = (size_t)nc + 2;
-  auto pad = [&](int q) {
-    const int i = q % nc + 1, j = (q / nc) % nc + 1, k = q / (nc * nc) + 1;
-    return ((size_t)k * P + (size_t)j) * P + (size_t)i;
+    __syncthreads();
   };
-  for (int q = threadIdx.x; q < np; q += kB3) fp[q] = f[pad(q)];
+#pragma unroll
+  for (int l = 0; l + 1 < kCvcLevels; ++l) {
+    if (l + 1 >= L.nl) break;
+    const int nf = ed[l], P = nf + 2, PP = P * P, n3 = nf * nf * nf;
+    double* u = U[l];
+    const double* f = Fv[l];
+    for (int q = t; q < n3; q += kCvcThreads) {
+      const int i = q % nf + 1, r = q / nf, j = r % nf + 1, k = r / nf + 1;
+      const int o = (k * P + j) * P + i;
+      if (((i + j + k) & 1) == 0) {
+        u[o] = f[o] * (1.0 / 6.0);
+      } else {
+        const double s = f[o - 1] + f[o + 1] + f[o - P] + f[o + P] + f[o - PP] + f[o + PP];
+        u[o] = (f[o] + s * (1.0 / 6.0)) * (1.0 / 6.0);
+      }
+    }
+    __syncthreads();
+    for (int sw = 2; sw < 2 * nu; ++sw) half(u, f, nf, (sw & 1) ? 1 : 0);
+    const int nc = ed[l + 1], Pc = nc + 2, nc3 = nc * nc * nc;
+    double* fc = Fv[l + 1];
+    auto T = [&](int o) {
+      return f[o] - (6.0 * u[o] - u[o - 1] - u[o + 1] - u[o - P] - u[o + P] - u[o - PP] -
+                     u[o + PP]);
+    };
+    for (int q = t; q < nc3; q += kCvcThreads) {
+      const int I = q % nc + 1, r = q / nc, J = r % nc + 1, K = r / nc + 1;
+      const int o = ((2 * K) * P + 2 * J) * P + 2 * I;
+      const int d1 = 1, d2 = P, d3 = PP;
+      const double s = T(o + d1) + T(o - d1) + T(o + d2) + T(o - d2) + T(o + d3) + T(o - d3) +
+                       T(o + d1 + d2) + T(o - d1 - d2) + T(o + d1 + d3) + T(o - d1 - d3) +
+                       T(o + d2 + d3) + T(o - d2 - d3) + T(o + d1 + d2 + d3) +
+                       T(o - d1 - d2 - d3);
+      fc[(K * Pc + J) * Pc + I] = 0.5 * (T(o) + 0.5 * s);
+    }
+    __syncthreads();
+  }
+  // coarsest grid: dense inverse of L7
+#pragma unroll
+  for (int l = 0; l < kCvcLevels; ++l) {
+    if (l != L.nl - 1) continue;
+    const int nc = ed[l], np = nc * nc * nc;
+    for (int q = t; q < np; q += kCvcThreads) {
+      double a = 0.0;
+      for (int m = 0; m < np; ++m) a += cinv[q * np + m] * Fv[l][cvc_pad(m, nc)];
+      U[l][cvc_pad(q, nc)] = a;
+    }
+  }
   __syncthreads();
-  for (int q = threadIdx.x; q < np; q += kB3) {
-    double a = 0.0;
-    for (int m = 0; m < np; ++m) a += cinv[(size_t)q * np + m] * fp[m];
-    u[pad(q)] = a;
+#pragma unroll
+  for (int l = kCvcLevels - 2; l >= 0; --l) {
+    if (l + 1 >= L.nl) continue;
+    const int nf = ed[l], P = nf + 2, n3 = nf * nf * nf;
+    const int nc = ed[l + 1], Pc = nc + 2;
+    double* u = U[l];
+    const double* ec = U[l + 1];
+    for (int q = t; q < n3; q += kCvcThreads) {
+      const int i = q % nf + 1, r = q / nf, j = r % nf + 1, k = r / nf + 1;
+      const int I = i >> 1, J = j >> 1, K = k >> 1;
+      const int oc = (K * Pc + J) * Pc + I;
+      const int od = ((k & 1) * Pc + (j & 1)) * Pc + (i & 1);
+      u[(k * P + j) * P + i] += od ? 0.5 * (ec[oc] + ec[oc + od]) : ec[oc];
+    }
+    __syncthreads();
+    for (int sw = 0; sw < 2 * nu; ++sw) half(u, Fv[l], nf, (sw & 1) ? 0 : 1);
+  }
+  {
+    const int nf = ed[0], n3 = nf * nf * nf;
+    for (int q = t; q < n3; q += kCvcThreads) {
+      const int o = cvc_pad(q, nf);
+      uout[o] = U[0][o];
+    }
   }
 }
 
@@ -157,128 +459,6 @@ __global__ __launch_bounds__(kB3) void k3_rhs(Rhs3 rhs, double* __restrict__ f, 
     double v = rhs.b ? rhs.sb * rhs.b[q] : 0.0;
     if (rhs.g && k == nf) v += rhs.sg * rhs.g[(size_t)(j - 1) * nf + (i - 1)];
     f[o] = v;
-  }
-}
-
-// dot-product partials: part[block] = sum of a . b over the block's points
-__global__ __launch_bounds__(kB3) void k3_dot(const double* __restrict__ a,
-                                             const double* __restrict__ b, int nf,
-                                             double* __restrict__ part,
-                                             const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  const int64_t N = (int64_t)nf * nf * nf;
-  double s = 0.0;
-  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
-    int i, j, k;
-    const size_t o = pidx(q, nf, &i, &j, &k);
-    s += a[o] * b[o];
-  }
-  s = block_sum3(s);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// q = L7 p with partials of p . q
-__global__ __launch_bounds__(kB3) void k3_apply(const double* __restrict__ p,
-                                               double* __restrict__ qv, int nf,
-                                               double* __restrict__ part,
-                                               const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  const size_t P = (size_t)nf + 2, PP = P * P;
-  const int64_t N = (int64_t)nf * nf * nf;
-  double s = 0.0;
-  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
-    int i, j, k;
-    const size_t o = pidx(q, nf, &i, &j, &k);
-    const double v = 6.0 * p[o] - p[o - 1] - p[o + 1] - p[o - P] - p[o + P] - p[o - PP] - p[o + PP];
-    qv[o] = v;
-    s += p[o] * v;
-  }
-  s = block_sum3(s);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// x += alpha p, r -= alpha q, partials of r . r
-__global__ __launch_bounds__(kB3) void k3_update(double* __restrict__ x, double* __restrict__ r,
-                                                const double* __restrict__ p,
-                                                const double* __restrict__ qv, int nf,
-                                                const State3* __restrict__ st,
-                                                double* __restrict__ part,
-                                                const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  const double al = st->alpha;
-  const int64_t N = (int64_t)nf * nf * nf;
-  double s = 0.0;
-  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
-    int i, j, k;
-    const size_t o = pidx(q, nf, &i, &j, &k);
-    x[o] += al * p[o];
-    const double rv = r[o] - al * qv[o];
-    r[o] = rv;
-    s += rv * rv;
-  }
-  s = block_sum3(s);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// p = z + beta p (beta = 0: p = z)
-__global__ __launch_bounds__(kB3) void k3_pupdate(double* __restrict__ p,
-                                                 const double* __restrict__ z, int nf,
-                                                 const State3* __restrict__ st, int first,
-                                                 const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  const double be = first ? 0.0 : st->beta;
-  const int64_t N = (int64_t)nf * nf * nf;
-  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
-    int i, j, k;
-    const size_t o = pidx(q, nf, &i, &j, &k);
-    p[o] = z[o] + be * p[o];
-  }
-}
-
-// Scalar steps of the PCG, one thread block.  kind 0: start (ff = |f|^2 = rr0, rho = r.z);
-// 1: alpha = rho / p.q; 2: convergence test on |r|^2; 3: beta = rho_new / rho (rho_new = r.z).
-__global__ __launch_bounds__(kB3) void k3_scalars(State3* __restrict__ st, const double* part0,
-                                                 const double* part1, int nb, int kind,
-                                                 int* __restrict__ stop) {
-  if (kind != 0 && *stop) return;
-  double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < nb; k += kB3) {
-    a += part0[k];
-    if (part1) b += part1[k];
-  }
-  a = block_sum3(a);
-  b = block_sum3(b);
-  if (threadIdx.x != 0) return;
-  if (kind == 0) {
-    st->ff = a;
-    st->rr = a;
-    st->rho = b;
-    st->its = 0;
-    st->breakdown = 0;
-    *stop = (a == 0.0) ? 1 : 0;
-    if (!isfinite(a) || !isfinite(b)) {
-      st->breakdown = 4;
-      *stop = 1;
-    }
-  } else if (kind == 1) {
-    const bool ok = a > 0.0 && isfinite(a);
-    st->alpha = ok ? st->rho / a : 0.0;
-    if (!ok) {
-      st->breakdown = isfinite(a) ? 1 : 4;
-      *stop = 1;
-    }
-  } else if (kind == 2) {
-    st->rr = a;
-    st->its += 1;
-    if (!isfinite(a)) {
-      st->breakdown = 4;
-      *stop = 1;
-    } else if (a <= st->tol2 * st->ff) {
-      *stop = 1;
-    }
-  } else {
-    st->beta = a / st->rho;
-    st->rho = a;
   }
 }
 
@@ -302,49 +482,179 @@ __global__ __launch_bounds__(kB3) void k3_gather(const double* __restrict__ u, i
 // ---- interface (face) operators -------------------------------------------------------------
 // Face vectors are compact (nf x nf, x fastest); system s of a batch at offset s * nf^2.
 
+// ---- batched face CG ------------------------------------------------------------------------
+// System s of a batch solves (alpha_s A_G + beta_s M_G) y_s = r_s by PCG with the preconditioner
+// S D_s^{-1} S (S the orthonormal DST-I matrix, D_s the part of the operator diagonal in the
+// sine basis).  One iteration is six passes: kf_apply1 (p, q = B_s p), kf_axpy1 (y, r),
+// then the preconditioner as four DST passes, the first of which takes the convergence test and
+// the last of which leaves the partials of r . z.  The scalars are summed by the pass that
+// uses them (every block of a system sums the same partials; block 0 records them), and a
+// system whose test is met is skipped by every later pass.  Partials of system s are at
+// part[s * kPFS + b].
+
+__device__ __forceinline__ double sys_sum(const double* __restrict__ part, int s, int cnt) {
+  __shared__ double sh;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < cnt; b += kB3) a += part[(size_t)s * kPFS + b];
+  a = block_sum3(a);
+  if (threadIdx.x == 0) sh = a;
+  __syncthreads();
+  const double r = sh;
+  __syncthreads();
+  return r;
+}
+
 __device__ __forceinline__ double face_at(const double* v, int nf, int i, int j) {
   return (i >= 0 && i < nf && j >= 0 && j < nf) ? v[(size_t)j * nf + i] : 0.0;
 }
 
-// y = (alpha A_G + beta M_G) x for every system (alpha, beta from the shift table; mode_mass
-// != 0: the input of every system is M_G x0 of one shared vector x0 is applied instead).
-__global__ __launch_bounds__(kB3) void kf_apply(const double* __restrict__ x, int x_shared,
-                                               double* __restrict__ y, int nf, double h,
-                                               const Shift3* __restrict__ tab,
-                                               double* __restrict__ part,
-                                               const int* __restrict__ done) {
+// r_s = src (mass = 0) or M_G src (mass = 1), y_s = 0, partials of |r_s|^2
+__global__ __launch_bounds__(kB3) void kf_start(const double* __restrict__ src,
+                                               double* __restrict__ r, double* __restrict__ y,
+                                               int nf, double h, int mass,
+                                               double* __restrict__ part) {
   const int s = blockIdx.y;
-  if (done && done[s]) return;
-  const double al = tab->alpha[s], be = tab->beta[s];
-  const double* xs = x + (x_shared ? 0 : (size_t)s * nf * nf);
-  double* ys = y + (size_t)s * nf * nf;
-  const double m0 = h * h / 12.0;
   const int64_t N = (int64_t)nf * nf;
+  const double m0 = h * h / 12.0;
+  double acc = 0.0;
+  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
+    double v = src[q];
+    if (mass) {
+      const int i = (int)(q % nf), j = (int)(q / nf);
+      v = m0 * (6.0 * src[q] + face_at(src, nf, i + 1, j) + face_at(src, nf, i - 1, j) +
+                face_at(src, nf, i, j + 1) + face_at(src, nf, i, j - 1) +
+                face_at(src, nf, i + 1, j + 1) + face_at(src, nf, i - 1, j - 1));
+    }
+    r[(size_t)s * N + q] = v;
+    y[(size_t)s * N + q] = 0.0;
+    acc += v * v;
+  }
+  acc = block_sum3(acc);
+  if (threadIdx.x == 0) part[(size_t)s * kPFS + blockIdx.x] = acc;
+}
+
+// rho_k = r . z (cnt partials), beta = rho_k / rho_{k-1} (0 at k = 0), p_k = z + beta p_{k-1}
+// (formed at the neighbours too), q = (alpha A_G + beta_s M_G) p_k, partials of p_k . q
+__global__ __launch_bounds__(kB3) void kf_apply1(const double* __restrict__ z,
+                                                const double* __restrict__ pold,
+                                                double* __restrict__ pnew,
+                                                double* __restrict__ qv, int nf, double h,
+                                                const Shift3* __restrict__ tab,
+                                                FaceCG* __restrict__ cg,
+                                                const double* __restrict__ pin, int cnt,
+                                                double* __restrict__ part,
+                                                int* __restrict__ done) {
+  const int s = blockIdx.y;
+  if (done[s]) return;
+  const double rz = sys_sum(pin, s, cnt);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (!(rz > 0.0) || !isfinite(rz)) {
+    if (lead) {
+      cg->bad[s] = 1;
+      done[s] = 1;
+    }
+    return;
+  }
+  const int it = cg->its[s];
+  const double be = it ? rz / cg->rho[(it - 1) & 1][s] : 0.0;
+  if (lead) cg->rho[it & 1][s] = rz;
+  const double al = tab->alpha[s], bm = tab->beta[s];
+  const int64_t N = (int64_t)nf * nf;
+  const double* zs = z + (size_t)s * N;
+  const double* ps = pold + (size_t)s * N;
+  const double m0 = h * h / 12.0;
+  auto P = [&](int i, int j) {
+    return it ? face_at(zs, nf, i, j) + be * face_at(ps, nf, i, j) : face_at(zs, nf, i, j);
+  };
   double acc = 0.0;
   for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
     const int i = (int)(q % nf), j = (int)(q / nf);
-    const double c = xs[q];
-    const double e = face_at(xs, nf, i + 1, j), w = face_at(xs, nf, i - 1, j);
-    const double no = face_at(xs, nf, i, j + 1), so = face_at(xs, nf, i, j - 1);
-    const double ne = face_at(xs, nf, i + 1, j + 1), sw = face_at(xs, nf, i - 1, j - 1);
+    const double c = P(i, j);
+    const double e = P(i + 1, j), w = P(i - 1, j), no = P(i, j + 1), so = P(i, j - 1);
+    const double ne = P(i + 1, j + 1), sw = P(i - 1, j - 1);
     const double a = 4.0 * c - e - w - no - so;
     const double m = m0 * (6.0 * c + e + w + no + so + ne + sw);
-    const double v = al * a + be * m;
-    ys[q] = v;
+    const double v = al * a + bm * m;
+    pnew[(size_t)s * N + q] = c;
+    qv[(size_t)s * N + q] = v;
     acc += c * v;
   }
   acc = block_sum3(acc);
-  if (part && threadIdx.x == 0) part[(size_t)s * gridDim.x + blockIdx.x] = acc;
+  if (threadIdx.x == 0) part[(size_t)s * kPFS + blockIdx.x] = acc;
 }
 
-// C_s = S B_s (left) or B_s S (right) for every system s, S the symmetric DST matrix (nf x nf).
-// 16 x 16 output tiles, LDS-staged 16-wide panels.
-__global__ __launch_bounds__(256) void kf_dst(const double* __restrict__ S,
-                                             const double* __restrict__ B,
-                                             double* __restrict__ C, int nf, int left,
-                                             const int* __restrict__ done) {
+// alpha_k = rho_k / (p_k . q) (kPartF partials), y += alpha_k p_k, r -= alpha_k q, partials of |r|^2
+__global__ __launch_bounds__(kB3) void kf_axpy1(double* __restrict__ y, double* __restrict__ r,
+                                               const double* __restrict__ p,
+                                               const double* __restrict__ qv, int nf,
+                                               FaceCG* __restrict__ cg,
+                                               const double* __restrict__ pin,
+                                               double* __restrict__ part,
+                                               int* __restrict__ done) {
+  const int s = blockIdx.y;
+  if (done[s]) return;
+  const double pq = sys_sum(pin, s, kPartF);
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      cg->bad[s] = 1;
+      done[s] = 1;
+    }
+    return;
+  }
+  const double al = cg->rho[cg->its[s] & 1][s] / pq;
+  const int64_t N = (int64_t)nf * nf;
+  const size_t off = (size_t)s * N;
+  double acc = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)kB3 + threadIdx.x; t < N; t += (int64_t)gridDim.x * kB3) {
+    y[off + t] += al * p[off + t];
+    const double rv = r[off + t] - al * qv[off + t];
+    r[off + t] = rv;
+    acc += rv * rv;
+  }
+  acc = block_sum3(acc);
+  if (threadIdx.x == 0) part[(size_t)s * kPFS + blockIdx.x] = acc;
+}
+
+// C_s = S B_s (LEFT) or B_s S, S the symmetric DST matrix (nf x nf); 16 x 16 output tiles,
+// LDS-staged 16-wide panels.  CHECK 1 / 2: first the start / convergence test of system s on
+// the kPartF partials of |r|^2 (rr0 = |r_0|^2, its = 0 / its += 1, stop at
+// |r|^2 <= tol2 rr0).  EPI 1: C /= alpha lambda(a, b) + beta mu(a, b) (the spectral scaling,
+// a the column and b the row index, 1-based); EPI 2: partials of r . C over the tile.
+template <bool LEFT, int CHECK, int EPI>
+__global__ __launch_bounds__(256) void kf_dst2(const double* __restrict__ S,
+                                              const double* __restrict__ B,
+                                              double* __restrict__ C, int nf, int n, double h,
+                                              const Shift3* __restrict__ tab,
+                                              FaceCG* __restrict__ cg,
+                                              const double* __restrict__ pin, double tol2,
+                                              const double* __restrict__ r,
+                                              double* __restrict__ part,
+                                              int* __restrict__ done) {
   const int s = blockIdx.z;
-  if (done && done[s]) return;
+  if (done[s]) return;
+  if constexpr (CHECK != 0) {
+    const double a = sys_sum(pin, s, kPartF);
+    const bool lead = blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+    const bool bad = !isfinite(a);
+    bool halt;
+    if constexpr (CHECK == 1) {
+      halt = bad || a == 0.0;
+      if (lead) {
+        cg->rr0[s] = a;
+        cg->its[s] = 0;
+      }
+    } else {
+      halt = bad || a <= tol2 * cg->rr0[s];
+      if (lead) cg->its[s] += 1;
+    }
+    if (halt) {
+      if (lead) {
+        if (bad) cg->bad[s] = 1;
+        done[s] = 1;
+      }
+      return;
+    }
+  }
   const double* Bs = B + (size_t)s * nf * nf;
   double* Cs = C + (size_t)s * nf * nf;
   __shared__ double ta[16][17], tb[16][17];
@@ -353,9 +663,8 @@ __global__ __launch_bounds__(256) void kf_dst(const double* __restrict__ S,
   // rows index j (the slow direction), columns index i
   double acc = 0.0;
   for (int k0 = 0; k0 < nf; k0 += 16) {
-    // left: C[row][col] = sum_k S[row][k] B[k][col];  right: C[row][col] = sum_k B[row][k] S[k][col]
     const int ka = k0 + tx, kb = k0 + ty;
-    if (left) {
+    if (LEFT) {
       ta[ty][tx] = (row < nf && ka < nf) ? S[(size_t)row * nf + ka] : 0.0;
       tb[ty][tx] = (kb < nf && col < nf) ? Bs[(size_t)kb * nf + col] : 0.0;
     } else {
@@ -367,108 +676,18 @@ __global__ __launch_bounds__(256) void kf_dst(const double* __restrict__ S,
     for (int k = 0; k < 16; ++k) acc += ta[ty][k] * tb[k][tx];
     __syncthreads();
   }
-  if (row < nf && col < nf) Cs[(size_t)row * nf + col] = acc;
-}
-
-// spectral scaling of the preconditioner: z_hat(a, b) /= (alpha lambda(a, b) + beta mu(a, b))
-__global__ __launch_bounds__(kB3) void kf_diag(double* __restrict__ z, int nf, int n, double h,
-                                              const Shift3* __restrict__ tab,
-                                              const int* __restrict__ done) {
-  const int s = blockIdx.y;
-  if (done && done[s]) return;
-  const double al = tab->alpha[s], be = tab->beta[s];
-  double* zs = z + (size_t)s * nf * nf;
-  const int64_t N = (int64_t)nf * nf;
-  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
-    const int a = (int)(q % nf) + 1, b = (int)(q / nf) + 1;
-    const double ca = cos(M_PI * a / n), cb = cos(M_PI * b / n);
+  const bool in = row < nf && col < nf;
+  if constexpr (EPI == 1) {
+    const double ca = cos(M_PI * (col + 1) / n), cb = cos(M_PI * (row + 1) / n);
     const double lam = 4.0 - 2.0 * ca - 2.0 * cb;
     const double mu = h * h / 12.0 * (6.0 + 2.0 * ca + 2.0 * cb + 2.0 * ca * cb);
-    zs[q] /= (al * lam + be * mu);
+    acc /= tab->alpha[s] * lam + tab->beta[s] * mu;
   }
-}
-
-// per-system dot partials: part[s][block] = sum a_s . b_s
-__global__ __launch_bounds__(kB3) void kf_dot(const double* __restrict__ a,
-                                             const double* __restrict__ b, int nf,
-                                             double* __restrict__ part,
-                                             const int* __restrict__ done) {
-  const int s = blockIdx.y;
-  if (done && done[s]) return;
-  const double* as = a + (size_t)s * nf * nf;
-  const double* bs = b + (size_t)s * nf * nf;
-  const int64_t N = (int64_t)nf * nf;
-  double acc = 0.0;
-  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3)
-    acc += as[q] * bs[q];
-  acc = block_sum3(acc);
-  if (threadIdx.x == 0) part[(size_t)s * gridDim.x + blockIdx.x] = acc;
-}
-
-// y_s += alpha_s p_s, r_s -= alpha_s q_s (kind 0); p_s = z_s + beta_s p_s (kind 1, first: p = z)
-__global__ __launch_bounds__(kB3) void kf_axpy(double* __restrict__ y, double* __restrict__ r,
-                                              double* __restrict__ p,
-                                              const double* __restrict__ q,
-                                              const double* __restrict__ z, int nf,
-                                              const double* __restrict__ coef, int kind,
-                                              int first, const int* __restrict__ done) {
-  const int s = blockIdx.y;
-  if (done && done[s]) return;
-  const size_t off = (size_t)s * nf * nf;
-  const int64_t N = (int64_t)nf * nf;
-  const double c = (kind == 1 && first) ? 0.0 : coef[s];
-  for (int64_t t = blockIdx.x * (int64_t)kB3 + threadIdx.x; t < N; t += (int64_t)gridDim.x * kB3) {
-    if (kind == 0) {
-      y[off + t] += c * p[off + t];
-      r[off + t] -= c * q[off + t];
-    } else {
-      p[off + t] = z[off + t] + c * p[off + t];
-    }
-  }
-}
-
-// Per-system CG scalars, one block per system.  kind 0: start (rr0 = r.r, rho = r.z);
-// 1: alpha = rho / p.q; 2: convergence test on r.r; 3: beta = rho_new / rho (rho_new = r.z).
-__global__ __launch_bounds__(kB3) void kf_scalars(FaceCG* __restrict__ cg, const double* part0,
-                                                 const double* part1, int nb, int kind,
-                                                 int* __restrict__ done, double tol2) {
-  const int s = blockIdx.x;
-  if (kind != 0 && done[s]) return;
-  double a = 0.0, b = 0.0;
-  for (int k = threadIdx.x; k < nb; k += kB3) {
-    a += part0[(size_t)s * nb + k];
-    if (part1) b += part1[(size_t)s * nb + k];
-  }
-  a = block_sum3(a);
-  b = block_sum3(b);
-  if (threadIdx.x != 0) return;
-  if (kind == 0) {
-    cg->rr0[s] = a;
-    cg->rho[s] = b;
-    cg->its[s] = 0;
-    done[s] = (a == 0.0) ? 1 : 0;
-    if (!isfinite(a) || !isfinite(b)) {
-      cg->bad[s] = 1;
-      done[s] = 1;
-    }
-  } else if (kind == 1) {
-    const bool ok = a > 0.0 && isfinite(a);
-    cg->alpha[s] = ok ? cg->rho[s] / a : 0.0;
-    if (!ok) {
-      cg->bad[s] = 1;
-      done[s] = 1;
-    }
-  } else if (kind == 2) {
-    cg->its[s] += 1;
-    if (!isfinite(a)) {
-      cg->bad[s] = 1;
-      done[s] = 1;
-    } else if (a <= tol2 * cg->rr0[s]) {
-      done[s] = 1;
-    }
-  } else {
-    cg->beta[s] = a / cg->rho[s];
-    cg->rho[s] = a;
+  if (in) Cs[(size_t)row * nf + col] = acc;
+  if constexpr (EPI == 2) {
+    double d = in ? r[(size_t)s * nf * nf + (size_t)row * nf + col] * acc : 0.0;
+    d = block_sum3(d);
+    if (threadIdx.x == 0) part[(size_t)s * kPFS + blockIdx.y * gridDim.x + blockIdx.x] = d;
   }
 }
 
@@ -621,29 +840,6 @@ __global__ __launch_bounds__(kB3) void kf_vdot(const double* __restrict__ a,
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-// dst_s = src (mass = 0), M src (mass = 1) or 0 (src = null), for every system s
-__global__ __launch_bounds__(kB3) void kf_bcast(const double* __restrict__ src,
-                                               double* __restrict__ dst, int nf, double h,
-                                               int mass) {
-  const int s = blockIdx.y;
-  const int64_t N = (int64_t)nf * nf;
-  const double m0 = h * h / 12.0;
-  for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
-    double v = 0.0;
-    if (src) {
-      if (mass) {
-        const int i = (int)(q % nf), j = (int)(q / nf);
-        v = m0 * (6.0 * src[q] + face_at(src, nf, i + 1, j) + face_at(src, nf, i - 1, j) +
-                  face_at(src, nf, i, j + 1) + face_at(src, nf, i, j - 1) +
-                  face_at(src, nf, i + 1, j + 1) + face_at(src, nf, i - 1, j - 1));
-      } else {
-        v = src[q];
-      }
-    }
-    dst[(size_t)s * N + q] = v;
-  }
-}
-
 // ---- launchers -------------------------------------------------------------------------------
 
 static inline int grid_for(int64_t N, int cap = kPart3) {
@@ -651,87 +847,102 @@ static inline int grid_for(int64_t N, int cap = kPart3) {
   return (int)(g < cap ? (g < 1 ? 1 : g) : cap);
 }
 
-void k3_launch_rb(hipStream_t s, double* u, const double* f, int nf, int red, int from_zero,
-                  const int* stop) {
-  hipLaunchKernelGGL(k3_rb, dim3(grid_for((int64_t)nf * nf * nf, 4096)), dim3(kB3), 0, s, u, f, nf,
-                     red, from_zero, stop);
+int k3_rows_red(int nf) {
+  int r = (nf * nf + 1023) / 1024;
+  r = r < 4 ? 4 : r;
+  return (r + 3) & ~3;
 }
-void k3_launch_resid(hipStream_t s, const double* u, const double* f, double* t, int nf,
-                     const int* stop) {
-  hipLaunchKernelGGL(k3_resid, dim3(grid_for((int64_t)nf * nf * nf, 4096)), dim3(kB3), 0, s, u, f,
-                     t, nf, stop);
+
+int k3_cvc_fits(const Cvc3& L) {
+  if (L.nl < 1 || L.nl > kCvcLevels || L.lev[0] > kCvcMax) return 0;
+  int tot = 0;
+  for (int l = 0; l < L.nl; ++l) tot += 2 * (L.lev[l] + 2) * (L.lev[l] + 2) * (L.lev[l] + 2);
+  return tot <= kCvcLds;
 }
-void k3_launch_restrict(hipStream_t s, const double* t, double* fc, int nf, int nc,
-                        const int* stop) {
-  hipLaunchKernelGGL(k3_restrict, dim3(grid_for((int64_t)nc * nc * nc, 4096)), dim3(kB3), 0, s, t,
-                     fc, nf, nc, stop);
+
+static inline dim3 grid3(int nf, int rows) { return dim3((nf + rows - 1) / rows, nf); }
+static const dim3 kBlk3(kX3, kY3);
+
+void k3_launch_zp(hipStream_t s, int mode, const double* f, double* u, int nf, int rows,
+                  const double* q, double* rnew, double* x, const double* p, State3* st,
+                  const double* pin, int np, double* part, int* stop) {
+  if (mode == 0)
+    hipLaunchKernelGGL(k3_zp<0>, grid3(nf, rows), kBlk3, 0, s, f, u, nf, rows, q, rnew, x, p, st,
+                       pin, np, part, stop);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k3_zp<1>, grid3(nf, rows), kBlk3, 0, s, f, u, nf, rows, q, rnew, x, p, st,
+                       pin, np, part, stop);
+  else
+    hipLaunchKernelGGL(k3_zp<2>, grid3(nf, rows), kBlk3, 0, s, f, u, nf, rows, q, rnew, x, p, st,
+                       pin, np, part, stop);
 }
-void k3_launch_prolong(hipStream_t s, const double* ec, double* u, int nf, int nc,
-                       const int* stop) {
-  hipLaunchKernelGGL(k3_prolong, dim3(grid_for((int64_t)nf * nf * nf, 4096)), dim3(kB3), 0, s, ec,
-                     u, nf, nc, stop);
+void k3_launch_hs(hipStream_t s, double* u, const double* f, int nf, int red, int check,
+                  State3* st, const double* pin, int np, int* stop) {
+  hipLaunchKernelGGL(k3_hs, grid3(nf, 4), kBlk3, 0, s, u, f, nf, 4, red, check, st, pin, np, stop);
 }
-void k3_launch_coarse(hipStream_t s, const double* f, double* u, int nc, const double* cinv,
-                      const int* stop) {
-  hipLaunchKernelGGL(k3_coarse, dim3(1), dim3(kB3), 0, s, f, u, nc, cinv, stop);
+void k3_launch_rr(hipStream_t s, const double* u, const double* f, double* fc, int nf, int nc,
+                  int check, State3* st, const double* pin, int np, int* stop) {
+  hipLaunchKernelGGL(k3_rr, grid3(nc, 4), kBlk3, 0, s, u, f, fc, nf, nc, 4, check, st, pin, np,
+                     stop);
+}
+void k3_launch_pr(hipStream_t s, const double* u, const double* ec, const double* f, double* uo,
+                  int nf, int nc, int* stop) {
+  hipLaunchKernelGGL(k3_pr, grid3(nf, 4), kBlk3, 0, s, u, ec, f, uo, nf, nc, 4, stop);
+}
+void k3_launch_hsz(hipStream_t s, double* u, const double* f, int nf, int rows, double* part,
+                   int* stop) {
+  hipLaunchKernelGGL(k3_hsz, grid3(nf, rows), kBlk3, 0, s, u, f, nf, rows, part, stop);
+}
+void k3_launch_apply1(hipStream_t s, const double* z, const double* pold, double* pnew, double* q,
+                      int nf, int rows, State3* st, const double* pin, int np, double* part,
+                      int* stop) {
+  hipLaunchKernelGGL(k3_apply1, grid3(nf, rows), kBlk3, 0, s, z, pold, pnew, q, nf, rows, st, pin,
+                     np, part, stop);
+}
+void k3_launch_cvc(hipStream_t s, const double* fin, double* uout, const Cvc3& L,
+                   const double* cinv, int nu, int* stop) {
+  hipLaunchKernelGGL(k3_cvc, dim3(1), dim3(kCvcThreads), 0, s, fin, uout, L, cinv, nu, stop);
 }
 void k3_launch_rhs(hipStream_t s, const Rhs3& rhs, double* f, int nf) {
   hipLaunchKernelGGL(k3_rhs, dim3(grid_for((int64_t)nf * nf * nf, 4096)), dim3(kB3), 0, s, rhs, f,
                      nf);
 }
-void k3_launch_dot(hipStream_t s, const double* a, const double* b, int nf, double* part,
-                   const int* stop) {
-  hipLaunchKernelGGL(k3_dot, dim3(kPart3), dim3(kB3), 0, s, a, b, nf, part, stop);
-}
-void k3_launch_apply(hipStream_t s, const double* p, double* q, int nf, double* part,
-                     const int* stop) {
-  hipLaunchKernelGGL(k3_apply, dim3(kPart3), dim3(kB3), 0, s, p, q, nf, part, stop);
-}
-void k3_launch_update(hipStream_t s, double* x, double* r, const double* p, const double* q,
-                      int nf, const State3* st, double* part, const int* stop) {
-  hipLaunchKernelGGL(k3_update, dim3(kPart3), dim3(kB3), 0, s, x, r, p, q, nf, st, part, stop);
-}
-void k3_launch_pupdate(hipStream_t s, double* p, const double* z, int nf, const State3* st,
-                       int first, const int* stop) {
-  hipLaunchKernelGGL(k3_pupdate, dim3(grid_for((int64_t)nf * nf * nf, 4096)), dim3(kB3), 0, s, p,
-                     z, nf, st, first, stop);
-}
-void k3_launch_scalars(hipStream_t s, State3* st, const double* part0, const double* part1,
-                       int kind, int* stop) {
-  hipLaunchKernelGGL(k3_scalars, dim3(1), dim3(kB3), 0, s, st, part0, part1, kPart3, kind, stop);
-}
 void k3_launch_gather(hipStream_t s, const double* u, int nf, double* out, const double* xg) {
   hipLaunchKernelGGL(k3_gather, dim3(grid_for((int64_t)nf * nf * nf + nf * nf, 4096)), dim3(kB3),
                      0, s, u, nf, out, xg);
 }
-void kf_launch_apply(hipStream_t s, const double* x, int x_shared, double* y, int nf, double h,
-                     int m, const Shift3* tab, double* part, const int* done) {
-  hipLaunchKernelGGL(kf_apply, dim3(kPartF, m), dim3(kB3), 0, s, x, x_shared, y, nf, h, tab, part,
+void kf_launch_start(hipStream_t s, const double* src, double* r, double* y, int nf, double h,
+                     int m, int mass, double* part) {
+  hipLaunchKernelGGL(kf_start, dim3(kPartF, m), dim3(kB3), 0, s, src, r, y, nf, h, mass, part);
+}
+void kf_launch_apply1(hipStream_t s, const double* z, const double* pold, double* pnew, double* q,
+                      int nf, double h, int m, const Shift3* tab, FaceCG* cg, const double* pin,
+                      int cnt, double* part, int* done) {
+  hipLaunchKernelGGL(kf_apply1, dim3(kPartF, m), dim3(kB3), 0, s, z, pold, pnew, q, nf, h, tab, cg,
+                     pin, cnt, part, done);
+}
+void kf_launch_axpy1(hipStream_t s, double* y, double* r, const double* p, const double* q, int nf,
+                     int m, FaceCG* cg, const double* pin, double* part, int* done) {
+  hipLaunchKernelGGL(kf_axpy1, dim3(kPartF, m), dim3(kB3), 0, s, y, r, p, q, nf, cg, pin, part,
                      done);
 }
-void kf_launch_dst(hipStream_t s, const double* S, const double* B, double* C, int nf, int m,
-                   int left, const int* done) {
+int kf_tiles(int nf) { return ((nf + 15) / 16) * ((nf + 15) / 16); }
+void kf_launch_prec(hipStream_t s, const double* S, const double* r, double* ft, double* z, int nf,
+                    int n, double h, int m, const Shift3* tab, FaceCG* cg, const double* pin,
+                    double tol2, int check, double* part, int* done) {
   const dim3 g((nf + 15) / 16, (nf + 15) / 16, m);
-  hipLaunchKernelGGL(kf_dst, g, dim3(256), 0, s, S, B, C, nf, left, done);
-}
-void kf_launch_diag(hipStream_t s, double* z, int nf, int n, double h, int m, const Shift3* tab,
-                    const int* done) {
-  hipLaunchKernelGGL(kf_diag, dim3(kPartF, m), dim3(kB3), 0, s, z, nf, n, h, tab, done);
-}
-void kf_launch_dot(hipStream_t s, const double* a, const double* b, int nf, int m, double* part,
-                   const int* done) {
-  hipLaunchKernelGGL(kf_dot, dim3(kPartF, m), dim3(kB3), 0, s, a, b, nf, part, done);
-}
-void kf_launch_axpy(hipStream_t s, double* y, double* r, double* p, const double* q,
-                    const double* z, int nf, int m, const double* coef, int kind, int first,
-                    const int* done) {
-  hipLaunchKernelGGL(kf_axpy, dim3(kPartF, m), dim3(kB3), 0, s, y, r, p, q, z, nf, coef, kind,
-                     first, done);
-}
-void kf_launch_scalars(hipStream_t s, FaceCG* cg, const double* part0, const double* part1, int m,
-                       int kind, int* done, double tol2) {
-  hipLaunchKernelGGL(kf_scalars, dim3(m), dim3(kB3), 0, s, cg, part0, part1, kPartF, kind, done,
-                     tol2);
+  if (check == 1)
+    hipLaunchKernelGGL((kf_dst2<true, 1, 0>), g, dim3(256), 0, s, S, r, ft, nf, n, h, tab, cg, pin,
+                       tol2, nullptr, nullptr, done);
+  else
+    hipLaunchKernelGGL((kf_dst2<true, 2, 0>), g, dim3(256), 0, s, S, r, ft, nf, n, h, tab, cg, pin,
+                       tol2, nullptr, nullptr, done);
+  hipLaunchKernelGGL((kf_dst2<false, 0, 1>), g, dim3(256), 0, s, S, ft, z, nf, n, h, tab, cg,
+                     nullptr, tol2, nullptr, nullptr, done);
+  hipLaunchKernelGGL((kf_dst2<true, 0, 0>), g, dim3(256), 0, s, S, z, ft, nf, n, h, tab, cg,
+                     nullptr, tol2, nullptr, nullptr, done);
+  hipLaunchKernelGGL((kf_dst2<false, 0, 2>), g, dim3(256), 0, s, S, ft, z, nf, n, h, tab, cg,
+                     nullptr, tol2, r, part, done);
 }
 void kf_launch_combine(hipStream_t s, const double* ys, int m, int nf, double h, const Shift3* tab,
                        int op, const double* x, double* tmp, double* out, double d0) {
@@ -761,10 +972,6 @@ void kf_launch_rhs_reduce(hipStream_t s, const double* bG, const double* w, int 
                           double* g, double* xg) {
   hipLaunchKernelGGL(kf_rhs_reduce, dim3(grid_for((int64_t)nf * nf, 1024)), dim3(kB3), 0, s, bG, w,
                      nf, h, g, xg);
-}
-void kf_launch_bcast(hipStream_t s, const double* src, double* dst, int nf, double h, int m,
-                     int mass) {
-  hipLaunchKernelGGL(kf_bcast, dim3(kPartF, m), dim3(kB3), 0, s, src, dst, nf, h, mass);
 }
 void kf_launch_vdot(hipStream_t s, const double* a, const double* b, int64_t N, double* part) {
   hipLaunchKernelGGL(kf_vdot, dim3(kPart3), dim3(kB3), 0, s, a, b, N, part);
