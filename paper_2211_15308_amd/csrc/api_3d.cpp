@@ -17,6 +17,31 @@
 
 using namespace fdd;
 
+// Captured runs of a Krylov iteration k: one iteration for each parity of k, and 4 and 8
+// iterations from an even k (the buffers alternate with the parity of k).
+struct Chunks {
+  hipGraphExec_t one[2] = {nullptr, nullptr};
+  hipGraphExec_t four = nullptr, eight = nullptr;
+  void clear() {
+    for (hipGraphExec_t* g : {&one[0], &one[1], &four, &eight}) {
+      if (*g) (void)hipGraphExecDestroy(*g);
+      *g = nullptr;
+    }
+  }
+};
+
+// buffers of one face batch (device, except the pinned read-back mirrors)
+struct FaceBufs {
+  double *r = nullptr, *y = nullptr, *z = nullptr, *q = nullptr, *t = nullptr, *tmp = nullptr;
+  double* p[2] = {};  // p_k in p[k & 1]
+  double *part0 = nullptr, *part1 = nullptr;
+  FaceCG* cg = nullptr;
+  int* done = nullptr;
+  int* hdone = nullptr;
+  int* hits = nullptr;
+  int enq = 0;  // iterations enqueued
+};
+
 struct Problem3D {
   int n = 0, nf = 0, nlev = 0, nc = 0;
   int lnf[kMaxLevels] = {};
@@ -40,32 +65,30 @@ struct Problem3D {
   double* S = nullptr;  // DST-I matrix of the face, nf x nf
   std::vector<double> S_h;
   Shift3* tabs = nullptr;  // [0] preconditioner batch, [1] operator batch
-  FaceCG* cg = nullptr;
-  int* done = nullptr;
-  double *fpart0 = nullptr, *fpart1 = nullptr;
-  double *fy = nullptr, *fr = nullptr, *fq = nullptr, *fz = nullptr, *ft = nullptr;
-  double* fp[2] = {};  // p_k of the face systems in fp[k & 1]
+  FaceBufs fb[2];  // [0] preconditioner batch, [1] operator batch
   double *xG = nullptr, *rG = nullptr, *pG = nullptr, *zG = nullptr, *yG = nullptr, *Hp = nullptr;
-  double *ftmp = nullptr, *gpart = nullptr;
+  double* gpart = nullptr;
   // pinned host mirrors
   State3* hst = nullptr;
   int* hstop = nullptr;
-  int* hdone = nullptr;
-  int* hits = nullptr;
   double* hpart = nullptr;
-  Shift3* htab = nullptr;
+  Shift3* htab = nullptr;  // [2]
   double* htol = nullptr;
   // captured work (replayed on the library stream): the first V-cycle of an interior solve and
   // one PCG iteration k for each parity of k
   hipGraphExec_t g_init = nullptr;
-  hipGraphExec_t g_it[2] = {nullptr, nullptr};
+  Chunks g_it;
   int g_nu = 0;
   int pred_its = 8;  // iterations of the last interior solve (enqueued before the first check)
   // one face-CG iteration k per (batch, parity of k); iterations of the last batch of each kind
-  hipGraphExec_t g_face[2][2] = {};
+  Chunks g_face[2];
   int g_face_m[2] = {0, 0};
   int pred_face[2] = {12, 12};
   bool use_graph = true;
+  // second stream (the H batch runs on it beside the interior solve of a Schur product)
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int enq = 0;  // interior iterations enqueued
 };
 
 namespace {
@@ -107,14 +130,17 @@ size_t plan3(fdd_problem_s* P, char* base) {
   Q->cinv = (double*)take(8 * nc3 * nc3);
   Q->S = (double*)take(8 * (size_t)Q->nf * Q->nf);
   Q->tabs = (Shift3*)take(2 * sizeof(Shift3));
-  Q->cg = (FaceCG*)take(sizeof(FaceCG));
-  Q->done = (int*)take(sizeof(int) * kMaxSys3);
-  Q->fpart0 = (double*)take(8 * (size_t)kMaxSys3 * kPFS);
-  Q->fpart1 = (double*)take(8 * (size_t)kMaxSys3 * kPFS);
   const size_t ng = (size_t)Q->nf * Q->nf;
-  for (double** v : {&Q->fy, &Q->fr, &Q->fp[0], &Q->fp[1], &Q->fq, &Q->fz, &Q->ft})
-    *v = (double*)take(8 * ng * kMaxSys3);
-  for (double** v : {&Q->xG, &Q->rG, &Q->pG, &Q->zG, &Q->yG, &Q->Hp, &Q->ftmp})
+  for (FaceBufs& B : Q->fb) {
+    B.cg = (FaceCG*)take(sizeof(FaceCG));
+    B.done = (int*)take(sizeof(int) * kMaxSys3);
+    B.part0 = (double*)take(8 * (size_t)kMaxSys3 * kPFS);
+    B.part1 = (double*)take(8 * (size_t)kMaxSys3 * kPFS);
+    for (double** v : {&B.y, &B.r, &B.p[0], &B.p[1], &B.q, &B.z, &B.t})
+      *v = (double*)take(8 * ng * kMaxSys3);
+    B.tmp = (double*)take(8 * ng);
+  }
+  for (double** v : {&Q->xG, &Q->rG, &Q->pG, &Q->zG, &Q->yG, &Q->Hp})
     *v = (double*)take(8 * ng);
   Q->gpart = (double*)take(8 * 2 * kPart3);
   return align_up(off, 256);
@@ -236,21 +262,53 @@ int capture(hipStream_t s, Fn fn, hipGraphExec_t* out) {
   return FDD_OK;
 }
 
+// Captures the chunks of iteration it(k).
+template <typename It>
+int capture_chunks(hipStream_t s, It it, Chunks* c) {
+  c->clear();
+  int rc = FDD_OK;
+  for (int par = 0; par < 2 && !rc; ++par) rc = capture(s, [&]() { it(par); }, &c->one[par]);
+  if (!rc) rc = capture(s, [&]() { for (int k = 0; k < 4; ++k) it(k); }, &c->four);
+  if (!rc) rc = capture(s, [&]() { for (int k = 0; k < 8; ++k) it(k); }, &c->eight);
+  return rc;
+}
+
+// Enqueues iterations k0 .. k1 - 1 (captured chunks, or it(k) launched one by one).
+template <typename It>
+int enqueue_iterations(hipStream_t s, bool graphs, const Chunks& c, It it, int k0, int k1) {
+  int k = k0;
+  while (k < k1) {
+    if (!graphs) {
+      it(k);
+      ++k;
+    } else if (!(k & 1) && k1 - k >= 8) {
+      HIPCHK(hipGraphLaunch(c.eight, s));
+      k += 8;
+    } else if (!(k & 1) && k1 - k >= 4) {
+      HIPCHK(hipGraphLaunch(c.four, s));
+      k += 4;
+    } else {
+      HIPCHK(hipGraphLaunch(c.one[k & 1], s));
+      ++k;
+    }
+  }
+  return FDD_OK;
+}
+
 // L7 x = f (f from rhs), to ||f - L7 x|| <= tol ||f||; x stays in Q->x (padded).  The
-// iterations of the last solve are enqueued before the state is first read back, then one at a
-// time (an iteration enqueued after convergence returns at once in every pass).
-int interior3(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int maxit, int nu,
-              int* its) {
+// iterations of the last solve are enqueued first (interior_start), then the state is read back
+// and one iteration at a time is added until the test is met (interior_finish; an iteration
+// enqueued after convergence returns at once in every pass).
+int interior_start(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int maxit,
+                   int nu) {
   Problem3D* Q = P->p3;
   const int nf = Q->nf;
+  auto it = [&](int k) { iteration3(Q, s, nu, k); };
   if (Q->use_graph && Q->g_nu != nu) {
-    for (hipGraphExec_t* g : {&Q->g_init, &Q->g_it[0], &Q->g_it[1]}) {
-      if (*g) (void)hipGraphExecDestroy(*g);
-      *g = nullptr;
-    }
+    if (Q->g_init) (void)hipGraphExecDestroy(Q->g_init);
+    Q->g_init = nullptr;
     int rc = capture(s, [&]() { vcycle3(Q, s, nu, 1, 0); }, &Q->g_init);
-    for (int par = 0; par < 2 && !rc; ++par)
-      rc = capture(s, [&]() { iteration3(Q, s, nu, par); }, &Q->g_it[par]);
+    if (!rc) rc = capture_chunks(s, it, &Q->g_it);
     if (rc) return rc;
     Q->g_nu = nu;
   }
@@ -261,22 +319,29 @@ int interior3(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int 
   HIPCHK(hipMemsetAsync(Q->stop, 0, sizeof(int), s));
   if (Q->use_graph) HIPCHK(hipGraphLaunch(Q->g_init, s));
   else vcycle3(Q, s, nu, 1, 0);
-  int done = 0, enq = 0;
-  int target = std::min(std::max(Q->pred_its - 1, 1), maxit);
+  Q->enq = std::min(std::max(Q->pred_its - 1, 1), maxit);
+  int rc = enqueue_iterations(s, Q->use_graph, Q->g_it, it, 0, Q->enq);
+  if (rc) return rc;
+  HIPCHK(hipGetLastError());
+  return FDD_OK;
+}
+
+int interior_finish(fdd_problem_s* P, hipStream_t s, int maxit, int nu, int* its) {
+  Problem3D* Q = P->p3;
+  auto it = [&](int k) { iteration3(Q, s, nu, k); };
+  int done = 0;
   while (true) {
-    for (; enq < target; ++enq) {
-      if (Q->use_graph) HIPCHK(hipGraphLaunch(Q->g_it[enq & 1], s));
-      else iteration3(Q, s, nu, enq);
-    }
-    HIPCHK(hipGetLastError());
     int rc = sync_state(Q, s);
     if (rc) return rc;
     if (*Q->hstop) {
       done = 1;
       break;
     }
-    if (enq >= maxit) break;
-    target = enq + 1;
+    if (Q->enq >= maxit) break;
+    rc = enqueue_iterations(s, Q->use_graph, Q->g_it, it, Q->enq, Q->enq + 1);
+    if (rc) return rc;
+    ++Q->enq;
+    HIPCHK(hipGetLastError());
   }
   if (its) *its = Q->hst->its;
   if (done && !Q->hst->breakdown) Q->pred_its = std::max(Q->hst->its, 1);
@@ -287,6 +352,12 @@ int interior3(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int 
     return fail(FDD_NOT_CONVERGED, "3D interior solve: %d iterations, residual %.3e of %.3e",
                 Q->hst->its, std::sqrt(Q->hst->rr), std::sqrt(Q->hst->ff));
   return FDD_OK;
+}
+
+int interior3(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int maxit, int nu,
+              int* its) {
+  int rc = interior_start(P, s, rhs, tol, maxit, nu);
+  return rc ? rc : interior_finish(P, s, maxit, nu, its);
 }
 
 Shift3 table3(const fdd_ratpc_s* t) {
@@ -318,74 +389,96 @@ Shift3 table3(const fdd_ratpc_s* t) {
 }
 
 // face-CG iteration k of a batch (both vector passes, then the preconditioner with the test)
-void face_iteration(Problem3D* Q, hipStream_t s, const Shift3* tab, int m, double tol2, int k) {
+void face_iteration(Problem3D* Q, FaceBufs& B, hipStream_t s, const Shift3* tab, int m,
+                    double tol2, int k) {
   const int nf = Q->nf;
   const double h = 1.0 / Q->n;
-  kf_launch_apply1(s, Q->fz, Q->fp[(k + 1) & 1], Q->fp[k & 1], Q->fq, nf, h, m, tab, Q->cg,
-                   Q->fpart0, kf_tiles(nf), Q->fpart1, Q->done);
-  kf_launch_axpy1(s, Q->fy, Q->fr, Q->fp[k & 1], Q->fq, nf, m, Q->cg, Q->fpart1, Q->fpart0,
-                  Q->done);
-  kf_launch_prec(s, Q->S, Q->fr, Q->ft, Q->fz, nf, Q->n, h, m, tab, Q->cg, Q->fpart0, tol2, 2,
-                 Q->fpart0, Q->done);
+  kf_launch_apply1(s, B.z, B.p[(k + 1) & 1], B.p[k & 1], B.q, nf, h, m, tab, B.cg, B.part0,
+                   kf_tiles(nf), B.part1, B.done);
+  kf_launch_axpy1(s, B.y, B.r, B.p[k & 1], B.q, nf, m, B.cg, B.part1, B.part0, B.done);
+  kf_launch_prec(s, Q->S, B.r, B.t, B.z, nf, Q->n, h, m, tab, B.cg, B.part0, tol2, 2, B.part0,
+                 B.done);
 }
 
 // out = preconditioner (which 0) or H_RA (which 1) applied to `in` (face vectors).  The
-// iterations of the last batch of the same kind are enqueued before the flags are first read.
-int face_batch(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* T, const double* in,
-               double* out) {
+// iterations of the last batch of the same kind are enqueued first (face_start), then the flags
+// are read back and one iteration at a time is added until every system has converged
+// (face_finish).
+struct FaceRun {
+  int which, m;
+  double tol2;
+  Shift3* tab;
+};
+
+int face_start(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* T, const double* in,
+               FaceRun* run) {
   Problem3D* Q = P->p3;
   const int nf = Q->nf;
   const double h = 1.0 / Q->n;
   const int which = T->which == FDD_RA_OPERATOR ? 1 : 0;
-  *Q->htab = table3(T);
-  const int m = Q->htab->m;
+  const Shift3 tabh = table3(T);
+  const int m = tabh.m;
   if (m > kMaxSys3) return fail(FDD_E_RA, "%d shifted systems exceed the batch limit %d", m, kMaxSys3);
-  const double d0 = Q->htab->d0;
+  Q->htab[which] = tabh;
   Shift3* tab = Q->tabs + which;
-  HIPCHK(hipMemcpyAsync(tab, Q->htab, sizeof(Shift3), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(tab, Q->htab + which, sizeof(Shift3), hipMemcpyHostToDevice, s));
   const double tol = which ? kFaceTolH : kFaceTolP;
   const double tol2 = tol * tol;
+  *run = FaceRun{which, m, tol2, tab};
+  FaceBufs& B = Q->fb[which];
+  auto it = [&](int k) { face_iteration(Q, B, s, tab, m, tol2, k); };
   if (Q->use_graph && Q->g_face_m[which] != m) {
-    for (hipGraphExec_t& g : Q->g_face[which]) {
-      if (g) (void)hipGraphExecDestroy(g);
-      g = nullptr;
-    }
-    for (int par = 0; par < 2; ++par) {
-      int rc = capture(s, [&]() { face_iteration(Q, s, tab, m, tol2, par); },
-                       &Q->g_face[which][par]);
-      if (rc) return rc;
-    }
+    int rc = capture_chunks(s, it, &Q->g_face[which]);
+    if (rc) return rc;
     Q->g_face_m[which] = m;
   }
-  HIPCHK(hipMemsetAsync(Q->done, 0, sizeof(int) * kMaxSys3, s));
-  HIPCHK(hipMemsetAsync(Q->cg, 0, sizeof(FaceCG), s));
-  kf_launch_start(s, in, Q->fr, Q->fy, nf, h, m, which, Q->fpart0);
-  kf_launch_prec(s, Q->S, Q->fr, Q->ft, Q->fz, nf, Q->n, h, m, tab, Q->cg, Q->fpart0, tol2, 1,
-                 Q->fpart0, Q->done);
+  HIPCHK(hipMemsetAsync(B.done, 0, sizeof(int) * kMaxSys3, s));
+  HIPCHK(hipMemsetAsync(B.cg, 0, sizeof(FaceCG), s));
+  kf_launch_start(s, in, B.r, B.y, nf, h, m, which, B.part0);
+  kf_launch_prec(s, Q->S, B.r, B.t, B.z, nf, Q->n, h, m, tab, B.cg, B.part0, tol2, 1, B.part0,
+                 B.done);
+  B.enq = std::max(Q->pred_face[which] - 1, 1);
+  int rc = enqueue_iterations(s, Q->use_graph, Q->g_face[which], it, 0, B.enq);
+  if (rc) return rc;
+  HIPCHK(hipGetLastError());
+  return FDD_OK;
+}
+
+int face_finish(fdd_problem_s* P, hipStream_t s, const FaceRun& run, const double* in,
+                double* out) {
+  Problem3D* Q = P->p3;
+  const int nf = Q->nf, m = run.m, which = run.which;
+  const double h = 1.0 / Q->n;
+  FaceBufs& B = Q->fb[which];
+  auto it = [&](int k) { face_iteration(Q, B, s, run.tab, m, run.tol2, k); };
   constexpr int kMaxFace = 400;
   bool all = false;
-  int enq = 0, target = std::max(Q->pred_face[which] - 1, 1);
   while (true) {
-    for (; enq < target; ++enq) {
-      if (Q->use_graph) HIPCHK(hipGraphLaunch(Q->g_face[which][enq & 1], s));
-      else face_iteration(Q, s, tab, m, tol2, enq);
-    }
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(Q->hdone, Q->done, sizeof(int) * m, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(Q->hits, Q->cg->its, sizeof(int) * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(B.hdone, B.done, sizeof(int) * m, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(B.hits, B.cg->its, sizeof(int) * m, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     all = true;
-    for (int k = 0; k < m; ++k) all = all && Q->hdone[k];
-    if (all || enq >= kMaxFace) break;
-    target = enq + 1;
+    for (int k = 0; k < m; ++k) all = all && B.hdone[k];
+    if (all || B.enq >= kMaxFace) break;
+    int rc = enqueue_iterations(s, Q->use_graph, Q->g_face[which], it, B.enq, B.enq + 1);
+    if (rc) return rc;
+    ++B.enq;
+    HIPCHK(hipGetLastError());
   }
   if (!all) return fail(FDD_NOT_CONVERGED, "3D face solves did not converge");
   int most = 1;
-  for (int k = 0; k < m; ++k) most = std::max(most, Q->hits[k]);
+  for (int k = 0; k < m; ++k) most = std::max(most, B.hits[k]);
   Q->pred_face[which] = most;
-  kf_launch_combine(s, Q->fy, m, nf, h, tab, which, in, Q->ftmp, out, d0);
+  kf_launch_combine(s, B.y, m, nf, h, run.tab, which, in, B.tmp, out, Q->htab[which].d0);
   HIPCHK(hipGetLastError());
   return FDD_OK;
+}
+
+int face_batch(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* T, const double* in,
+               double* out) {
+  FaceRun run{};
+  int rc = face_start(P, s, T, in, &run);
+  return rc ? rc : face_finish(P, s, run, in, out);
 }
 
 double face_dot(Problem3D* Q, hipStream_t s, const double* a, const double* b, int* rc) {
@@ -405,9 +498,24 @@ double face_dot(Problem3D* Q, hipStream_t s, const double* a, const double* b, i
 int schur3(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* HT, const double* p, double* y,
            const fdd_opts& o, int* its, double* pq) {
   Problem3D* Q = P->p3;
-  int rc = interior3(P, s, Rhs3{nullptr, 0.0, p, 1.0}, o.inner_rtol, o.inner_maxit, o.mg_nu, its);
+  // the interior solve on s and the H batch on the second stream run at the same time
+  if (!Q->s2) {
+    HIPCHK(hipStreamCreateWithFlags(&Q->s2, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&Q->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&Q->ev_join, hipEventDisableTiming));
+  }
+  HIPCHK(hipEventRecord(Q->ev_fork, s));
+  HIPCHK(hipStreamWaitEvent(Q->s2, Q->ev_fork, 0));
+  const Rhs3 lift{nullptr, 0.0, p, 1.0};
+  int rc = interior_start(P, s, lift, o.inner_rtol, o.inner_maxit, o.mg_nu);
+  FaceRun run{};
+  if (!rc) rc = face_start(P, Q->s2, HT, p, &run);
+  if (!rc) rc = interior_finish(P, s, o.inner_maxit, o.mg_nu, its);
+  if (!rc) rc = face_finish(P, Q->s2, run, p, Q->Hp);
+  // join in every case, so that no work of the second stream outlives the call unordered
+  (void)hipEventRecord(Q->ev_join, Q->s2);
+  (void)hipStreamWaitEvent(s, Q->ev_join, 0);
   if (rc) return rc;
-  if ((rc = face_batch(P, s, HT, p, Q->Hp))) return rc;
   kf_launch_schur(s, p, Q->x, Q->nf, 1.0 / Q->n, P->K, P->gamma, Q->Hp, y, Q->gpart);
   HIPCHK(hipGetLastError());
   if (pq) {
@@ -530,10 +638,12 @@ int bind3(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s) {
   if (!Q->hst) {
     HIPCHK(hipHostMalloc((void**)&Q->hst, sizeof(State3), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&Q->hstop, sizeof(int), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&Q->hdone, sizeof(int) * kMaxSys3, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&Q->hits, sizeof(int) * kMaxSys3, hipHostMallocDefault));
+    for (FaceBufs& B : Q->fb) {
+      HIPCHK(hipHostMalloc((void**)&B.hdone, sizeof(int) * kMaxSys3, hipHostMallocDefault));
+      HIPCHK(hipHostMalloc((void**)&B.hits, sizeof(int) * kMaxSys3, hipHostMallocDefault));
+    }
     HIPCHK(hipHostMalloc((void**)&Q->hpart, 8 * 2 * kPart3, hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&Q->htab, sizeof(Shift3), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&Q->htab, 2 * sizeof(Shift3), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&Q->htol, sizeof(double), hipHostMallocDefault));
   }
   HIPCHK(hipMemsetAsync(P->ws, 0, need, s));
@@ -546,14 +656,16 @@ int bind3(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s) {
 void destroy3(fdd_problem_s* P) {
   Problem3D* Q = P->p3;
   if (!Q) return;
-  for (void* h : {(void*)Q->hst, (void*)Q->hstop, (void*)Q->hdone, (void*)Q->hits, (void*)Q->hpart,
-                  (void*)Q->htab, (void*)Q->htol})
+  for (void* h : {(void*)Q->hst, (void*)Q->hstop, (void*)Q->fb[0].hdone, (void*)Q->fb[0].hits,
+                  (void*)Q->fb[1].hdone, (void*)Q->fb[1].hits, (void*)Q->hpart, (void*)Q->htab,
+                  (void*)Q->htol})
     if (h) (void)hipHostFree(h);
-  for (hipGraphExec_t g : {Q->g_init, Q->g_it[0], Q->g_it[1]})
-    if (g) (void)hipGraphExecDestroy(g);
-  for (auto& gw : Q->g_face)
-    for (hipGraphExec_t g : gw)
-      if (g) (void)hipGraphExecDestroy(g);
+  if (Q->g_init) (void)hipGraphExecDestroy(Q->g_init);
+  Q->g_it.clear();
+  for (Chunks& c : Q->g_face) c.clear();
+  if (Q->ev_fork) (void)hipEventDestroy(Q->ev_fork);
+  if (Q->ev_join) (void)hipEventDestroy(Q->ev_join);
+  if (Q->s2) (void)hipStreamDestroy(Q->s2);
   delete Q;
   P->p3 = nullptr;
 }

@@ -328,9 +328,14 @@ __global__ __launch_bounds__(kX3* kY3) void k3_apply1(const double* __restrict__
 constexpr int kCvcThreads = 1024;
 constexpr int kCvcLds = 11600;  // doubles: u and f of 15, 7, 3 and 1 (padded)
 
-__device__ __forceinline__ int cvc_pad(int q, int nf) {
-  const int i = q % nf + 1, r = q / nf, j = r % nf + 1, k = r / nf + 1;
-  return (k * (nf + 2) + j) * (nf + 2) + i;
+// Thread t of the workgroup takes the points (i, j, k) = (t % 16, (t / 16) % 16, t / 256 + 4 m)
+// + 1 of a level (every level it holds has at most 15 points a side).
+template <typename Fn>
+__device__ __forceinline__ void cvc_points(int nf, Fn&& fn) {
+  const int t = threadIdx.x;
+  const int i = (t & 15) + 1, j = ((t >> 4) & 15) + 1;
+  if (i > nf || j > nf) return;
+  for (int k = (t >> 8) + 1; k <= nf; k += kCvcThreads / 256) fn(i, j, k);
 }
 
 __global__ __launch_bounds__(kCvcThreads) void k3_cvc(const double* __restrict__ fin,
@@ -356,32 +361,30 @@ __global__ __launch_bounds__(kCvcThreads) void k3_cvc(const double* __restrict__
   for (int q = t; q < tot; q += kCvcThreads) lds[q] = 0.0;
   __syncthreads();
   {
-    const int nf = ed[0], n3 = nf * nf * nf;
-    for (int q = t; q < n3; q += kCvcThreads) {
-      const int o = cvc_pad(q, nf);
+    const int P = ed[0] + 2;
+    cvc_points(ed[0], [&](int i, int j, int k) {
+      const int o = (k * P + j) * P + i;
       Fv[0][o] = fin[o];
-    }
+    });
   }
   __syncthreads();
   auto half = [&](double* u, const double* f, int nf, int want) {
-    const int P = nf + 2, PP = P * P, n3 = nf * nf * nf;
-    for (int q = t; q < n3; q += kCvcThreads) {
-      const int i = q % nf + 1, r = q / nf, j = r % nf + 1, k = r / nf + 1;
-      if (((i + j + k) & 1) != want) continue;
+    const int P = nf + 2, PP = P * P;
+    cvc_points(nf, [&](int i, int j, int k) {
+      if (((i + j + k) & 1) != want) return;
       const int o = (k * P + j) * P + i;
       u[o] = (f[o] + u[o - 1] + u[o + 1] + u[o - P] + u[o + P] + u[o - PP] + u[o + PP]) *
              (1.0 / 6.0);
-    }
+    });
     __syncthreads();
   };
 #pragma unroll
   for (int l = 0; l + 1 < kCvcLevels; ++l) {
     if (l + 1 >= L.nl) break;
-    const int nf = ed[l], P = nf + 2, PP = P * P, n3 = nf * nf * nf;
+    const int nf = ed[l], P = nf + 2, PP = P * P;
     double* u = U[l];
     const double* f = Fv[l];
-    for (int q = t; q < n3; q += kCvcThreads) {
-      const int i = q % nf + 1, r = q / nf, j = r % nf + 1, k = r / nf + 1;
+    cvc_points(nf, [&](int i, int j, int k) {
       const int o = (k * P + j) * P + i;
       if (((i + j + k) & 1) == 0) {
         u[o] = f[o] * (1.0 / 6.0);
@@ -389,17 +392,16 @@ __global__ __launch_bounds__(kCvcThreads) void k3_cvc(const double* __restrict__
         const double s = f[o - 1] + f[o + 1] + f[o - P] + f[o + P] + f[o - PP] + f[o + PP];
         u[o] = (f[o] + s * (1.0 / 6.0)) * (1.0 / 6.0);
       }
-    }
+    });
     __syncthreads();
     for (int sw = 2; sw < 2 * nu; ++sw) half(u, f, nf, (sw & 1) ? 1 : 0);
-    const int nc = ed[l + 1], Pc = nc + 2, nc3 = nc * nc * nc;
+    const int nc = ed[l + 1], Pc = nc + 2;
     double* fc = Fv[l + 1];
     auto T = [&](int o) {
       return f[o] - (6.0 * u[o] - u[o - 1] - u[o + 1] - u[o - P] - u[o + P] - u[o - PP] -
                      u[o + PP]);
     };
-    for (int q = t; q < nc3; q += kCvcThreads) {
-      const int I = q % nc + 1, r = q / nc, J = r % nc + 1, K = r / nc + 1;
+    cvc_points(nc, [&](int I, int J, int K) {
       const int o = ((2 * K) * P + 2 * J) * P + 2 * I;
       const int d1 = 1, d2 = P, d3 = PP;
       const double s = T(o + d1) + T(o - d1) + T(o + d2) + T(o - d2) + T(o + d3) + T(o - d3) +
@@ -407,44 +409,48 @@ __global__ __launch_bounds__(kCvcThreads) void k3_cvc(const double* __restrict__
                        T(o + d2 + d3) + T(o - d2 - d3) + T(o + d1 + d2 + d3) +
                        T(o - d1 - d2 - d3);
       fc[(K * Pc + J) * Pc + I] = 0.5 * (T(o) + 0.5 * s);
-    }
+    });
     __syncthreads();
   }
-  // coarsest grid: dense inverse of L7
+  // coarsest grid: dense inverse of L7 (unknowns in the order (k * nc + j) * nc + i, 0-based)
 #pragma unroll
   for (int l = 0; l < kCvcLevels; ++l) {
     if (l != L.nl - 1) continue;
-    const int nc = ed[l], np = nc * nc * nc;
-    for (int q = t; q < np; q += kCvcThreads) {
+    const int nc = ed[l], np = nc * nc * nc, Pc = nc + 2;
+    cvc_points(nc, [&](int i, int j, int k) {
+      const int row = ((k - 1) * nc + (j - 1)) * nc + (i - 1);
       double a = 0.0;
-      for (int m = 0; m < np; ++m) a += cinv[q * np + m] * Fv[l][cvc_pad(m, nc)];
-      U[l][cvc_pad(q, nc)] = a;
-    }
+      for (int kk = 1; kk <= nc; ++kk)
+        for (int jj = 1; jj <= nc; ++jj)
+          for (int ii = 1; ii <= nc; ++ii)
+            a += cinv[row * np + ((kk - 1) * nc + (jj - 1)) * nc + (ii - 1)] *
+                 Fv[l][(kk * Pc + jj) * Pc + ii];
+      U[l][(k * Pc + j) * Pc + i] = a;
+    });
   }
   __syncthreads();
 #pragma unroll
   for (int l = kCvcLevels - 2; l >= 0; --l) {
     if (l + 1 >= L.nl) continue;
-    const int nf = ed[l], P = nf + 2, n3 = nf * nf * nf;
+    const int nf = ed[l], P = nf + 2;
     const int nc = ed[l + 1], Pc = nc + 2;
     double* u = U[l];
     const double* ec = U[l + 1];
-    for (int q = t; q < n3; q += kCvcThreads) {
-      const int i = q % nf + 1, r = q / nf, j = r % nf + 1, k = r / nf + 1;
+    cvc_points(nf, [&](int i, int j, int k) {
       const int I = i >> 1, J = j >> 1, K = k >> 1;
       const int oc = (K * Pc + J) * Pc + I;
       const int od = ((k & 1) * Pc + (j & 1)) * Pc + (i & 1);
       u[(k * P + j) * P + i] += od ? 0.5 * (ec[oc] + ec[oc + od]) : ec[oc];
-    }
+    });
     __syncthreads();
     for (int sw = 0; sw < 2 * nu; ++sw) half(u, Fv[l], nf, (sw & 1) ? 0 : 1);
   }
   {
-    const int nf = ed[0], n3 = nf * nf * nf;
-    for (int q = t; q < n3; q += kCvcThreads) {
-      const int o = cvc_pad(q, nf);
+    const int P = ed[0] + 2;
+    cvc_points(ed[0], [&](int i, int j, int k) {
+      const int o = (k * P + j) * P + i;
       uout[o] = U[0][o];
-    }
+    });
   }
 }
 
