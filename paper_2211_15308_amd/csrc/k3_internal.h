@@ -49,7 +49,9 @@ struct FaceCG {
   double rr0[kMaxSys3], rho[2][kMaxSys3];
   int its[kMaxSys3], bad[kMaxSys3];
 };
-constexpr int kPFS = 256;  // partials per system of the face kernels (>= ceil(nf / 16)^2)
+constexpr int kPFS = 256;       // partials per system of the face kernels (>= 64 and ceil(nf / 32)^2)
+constexpr int kFaceMax = 255;  // largest face edge nf (n <= 256)
+constexpr int kFaceRows = 256; // kFaceMax rounded up to whole row groups of 16
 
 // multigrid and PCG kernels of the interior solve (see kernels_3d.hip for what each computes);
 // rows: grid rows per block; pin/np: partials read; part: partials written

@@ -846,6 +846,100 @@ __global__ __launch_bounds__(kB3) void kf_vdot(const double* __restrict__ a,
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// Middle pass of the preconditioner when nf = 2^K - 1, on W = r S (the sine transform along x,
+// by kf_dst2): for each column a, the tridiagonal system along y
+// (alpha (4 - 2 c_a) + beta h^2/12 (6 + 2 c_a)) w_j + (-alpha + beta h^2/12 (1 + c_a))
+// (w_{j-1} + w_{j+1}) = W_j, c_a = cos(pi a / n), zero beyond the ends, in place.  Its sine
+// transform along y is the spectral scaling of kf_dst2 (EPI 1), so the three passes apply the
+// same preconditioner as the four.  With 2^K - 1 rows, cyclic reduction keeps one (d, e) pair
+// per level: d' = d - 2 e^2 / d, e' = -e^2 / d (diagonal dominance is kept).  A block takes a
+// panel of 16 columns of one system, held in LDS.  CHECK as in kf_dst2.
+template <int CHECK>
+__global__ __launch_bounds__(256) void kf_cr(double* __restrict__ w, int nf, int K, int n,
+                                            double h, const Shift3* __restrict__ tab,
+                                            FaceCG* __restrict__ cg,
+                                            const double* __restrict__ pin, double tol2,
+                                            int* __restrict__ done) {
+  const int s = blockIdx.y;
+  if (done[s]) return;
+  if constexpr (CHECK != 0) {
+    const double a = sys_sum(pin, s, kPartF);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool bad = !isfinite(a);
+    bool halt;
+    if constexpr (CHECK == 1) {
+      halt = bad || a == 0.0;
+      if (lead) {
+        cg->rr0[s] = a;
+        cg->its[s] = 0;
+      }
+    } else {
+      halt = bad || a <= tol2 * cg->rr0[s];
+      if (lead) cg->its[s] += 1;
+    }
+    if (halt) {
+      if (lead) {
+        if (bad) cg->bad[s] = 1;
+        done[s] = 1;
+      }
+      return;
+    }
+  }
+  __shared__ double sW[kFaceRows][17];  // row J = j + 1 of the reduction at sW[j]
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int col = blockIdx.x * 16 + tx;
+  double* ws = w + (size_t)s * nf * nf;
+  if (col < nf)
+    for (int j = ty; j < nf; j += 16) sW[j][tx] = ws[(size_t)j * nf + col];
+  double dl[8], el[8];
+  {
+    const double ca = cos(M_PI * (col + 1) / n);
+    const double al = tab->alpha[s], be = tab->beta[s], m0 = h * h / 12.0;
+    dl[0] = al * (4.0 - 2.0 * ca) + be * m0 * (6.0 + 2.0 * ca);
+    el[0] = -al + be * m0 * (1.0 + ca);
+#pragma unroll
+    for (int l = 0; l + 1 < 8; ++l) {
+      const double q = el[l] * el[l] / dl[l];
+      dl[l + 1] = dl[l] - 2.0 * q;
+      el[l + 1] = -q;
+    }
+  }
+  __syncthreads();
+  // forward reduction: level l = 0 .. K - 2 updates the rows J that are multiples of 2^(l+1)
+#pragma unroll
+  for (int l = 0; l < 7; ++l) {
+    if (l + 2 > K) break;
+    const int st = 1 << l;
+    const double g = el[l] / dl[l];
+    if (col < nf)
+      for (int J = 2 * st * (ty + 1); J <= nf; J += 2 * st * 16)
+        sW[J - 1][tx] -= g * (sW[J - st - 1][tx] + sW[J + st - 1][tx]);
+    __syncthreads();
+  }
+  // the middle row, then back substitution on the odd multiples of 2^l
+  if (col < nf && ty == 0) {
+    const int J = 1 << (K - 1);
+#pragma unroll
+    for (int l = 0; l < 8; ++l)
+      if (l == K - 1) sW[J - 1][tx] /= dl[l];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int l = 6; l >= 0; --l) {
+    if (l + 2 > K) continue;
+    const int st = 1 << l;
+    if (col < nf)
+      for (int J = st * (2 * ty + 1); J <= nf; J += 2 * st * 16) {
+        const double lo = J - st >= 1 ? sW[J - st - 1][tx] : 0.0;
+        const double hi = J + st <= nf ? sW[J + st - 1][tx] : 0.0;
+        sW[J - 1][tx] = (sW[J - 1][tx] - el[l] * (lo + hi)) / dl[l];
+      }
+    __syncthreads();
+  }
+  if (col < nf)
+    for (int j = ty; j < nf; j += 16) ws[(size_t)j * nf + col] = sW[j][tx];
+}
+
 // ---- launchers -------------------------------------------------------------------------------
 
 static inline int grid_for(int64_t N, int cap = kPart3) {
@@ -933,10 +1027,31 @@ void kf_launch_axpy1(hipStream_t s, double* y, double* r, const double* p, const
                      done);
 }
 int kf_tiles(int nf) { return ((nf + 15) / 16) * ((nf + 15) / 16); }
+int kf_cr_levels(int nf) {
+  for (int K = 1; K <= 8; ++K)
+    if (nf == (1 << K) - 1) return K;
+  return 0;
+}
 void kf_launch_prec(hipStream_t s, const double* S, const double* r, double* ft, double* z, int nf,
                     int n, double h, int m, const Shift3* tab, FaceCG* cg, const double* pin,
                     double tol2, int check, double* part, int* done) {
   const dim3 g((nf + 15) / 16, (nf + 15) / 16, m);
+  const int K = kf_cr_levels(nf);
+  if (K >= 2 && nf <= kFaceMax) {
+    // x transform, tridiagonal solves along y, inverse x transform
+    const dim3 gp((nf + 15) / 16, m);
+    if (check == 1)
+      hipLaunchKernelGGL((kf_dst2<false, 1, 0>), g, dim3(256), 0, s, S, r, ft, nf, n, h, tab, cg,
+                         pin, tol2, nullptr, nullptr, done);
+    else
+      hipLaunchKernelGGL((kf_dst2<false, 2, 0>), g, dim3(256), 0, s, S, r, ft, nf, n, h, tab, cg,
+                         pin, tol2, nullptr, nullptr, done);
+    hipLaunchKernelGGL(kf_cr<0>, gp, dim3(256), 0, s, ft, nf, K, n, h, tab, cg, nullptr, tol2,
+                       done);
+    hipLaunchKernelGGL((kf_dst2<false, 0, 2>), g, dim3(256), 0, s, S, ft, z, nf, n, h, tab, cg,
+                       nullptr, tol2, r, part, done);
+    return;
+  }
   if (check == 1)
     hipLaunchKernelGGL((kf_dst2<true, 1, 0>), g, dim3(256), 0, s, S, r, ft, nf, n, h, tab, cg, pin,
                        tol2, nullptr, nullptr, done);
