@@ -7,14 +7,18 @@
 // 2I + d, d in {0,1}^3, takes the mean of the coarse nodes I and I + d: every such d is an edge
 // direction of the Kuhn mesh), restriction = its transpose times 1/2 (the Galerkin coarse
 // operator P^T L7 P is 2 L7), and a dense inverse on the coarsest grid.  Grids are stored with a
-// one-cell zero border, (nf + 2)^3 cells, x fastest, so stencils need no bounds tests.
+// one-cell zero border, (nf + 2)^3 cells, x fastest, so stencils need no bounds tests.  The
+// passes are fused so that one PCG iteration takes few launches: the PCG update with the first
+// two half-sweeps, the residual with the restriction, the prolongation with the first sweep
+// after it, and every level of at most 15^3 points inside one workgroup.
 //
 // Interface: A_G is the 2D 5-point stencil on the (n-1)^2 face nodes and M_G the consistent P1
 // mass of the face triangles, (h^2 / 12) (6, 1 on the x, y and (1,1) diagonal neighbours).  The
 // shifted systems (alpha A_G + beta M_G) y = r of the rational approximation (eq. (RA)) are
 // solved all at once (one grid dimension per system) by CG preconditioned with the operator in
 // which M_G is replaced by its part diagonal in the sine basis; that preconditioner is applied
-// as S D S with S the orthonormal DST-I matrix, i.e. two batched dense FP64 GEMMs.
+// as S D S with S the orthonormal DST-I matrix (batched dense FP64 GEMMs), or, when
+// nf = 2^K - 1, as a transform along x, tridiagonal solves along y and the inverse transform.
 //
 // Scalars of the Krylov methods live on the device; dot products are summed from per-block
 // partials in a fixed order (deterministic).
