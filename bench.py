@@ -298,7 +298,8 @@ def run_learned(F, args, sizes=(256, 512, 1024), mus=(1e-3, 1.0)):
 
 
 def run_3d(F, args, sizes=(32, 64, 128), mus=(1e-4, 1.0, 1e2), reps=2):
-    """3D unit cube (Kuhn tetrahedra), Gamma = top face, K = 1: solves/s per (n, mu), FP64."""
+    """3D unit cube (Kuhn tetrahedra), Gamma = top face, K = 1: solves/s per (n, mu); FP64 outer
+    PCG and face solves, FP32 multigrid-PCG inside FP64 refinement for the interior."""
     import torch
 
     import workloads
@@ -321,7 +322,8 @@ def run_3d(F, args, sizes=(32, 64, 128), mus=(1e-4, 1.0, 1e2), reps=2):
             el = (time.perf_counter() - t0) / reps
             chk = P.solve(TP, TH, b, x, F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol,
                                                         check_true_residual=1))
-            out.append({"n": n, "K": 1.0, "mu": mu, "dofs": P.N, "solves_per_s": 1.0 / el,
+            out.append({"n": n, "K": 1.0, "mu": mu, "dofs": P.N, "precision": "mixed",
+                        "solves_per_s": 1.0 / el,
                         "outer_its": st["outer_its"], "inner_its": st["inner_its_total"],
                         "poles_P": TP.query()["m"], "poles_H": TH.query()["m"],
                         "true_rel_res": chk["true_rel_res"]})

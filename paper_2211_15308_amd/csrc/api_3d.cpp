@@ -44,6 +44,24 @@ struct FaceBufs {
   int enq = 0;  // iterations enqueued
 };
 
+// multigrid-PCG of the interior in precision R: level iterates and right-hand sides, the PCG
+// vectors (r_k in Rv[k & 1], p_k in PB[k & 1]) and its captured work (the first V-cycle of a run;
+// chunks of iterations); pred = iterations of the last run (enqueued before the first check)
+template <typename R>
+struct Mg3 {
+  R* u[kMaxLevels] = {};   // pre-smoothed iterates (level 0: scratch)
+  R* uo[kMaxLevels] = {};  // iterates after the coarse correction, levels < lc (level 0: z)
+  R* f[kMaxLevels] = {};   // right-hand sides of the levels >= 1
+  R* x = nullptr;
+  R* Rv[2] = {};
+  R* PB[2] = {};
+  R* q = nullptr;
+  hipGraphExec_t g_init = nullptr;
+  Chunks g_it;
+  int g_nu = 0;
+  int pred = 8;
+};
+
 struct Problem3D {
   int n = 0, nf = 0, nlev = 0, nc = 0;
   int lnf[kMaxLevels] = {};
@@ -51,13 +69,12 @@ struct Problem3D {
   Cvc3 cvc{};     // their sizes
   int rows0 = 4;  // rows per block of the level-0 reduction kernels
   int np0 = 0;    // their partials
-  double* u[kMaxLevels] = {};   // pre-smoothed iterates (level 0: scratch)
-  double* uo[kMaxLevels] = {};  // iterates after the coarse correction, levels < lc (level 0: z)
-  double* f[kMaxLevels] = {};   // right-hand sides of the levels >= 1
-  double* x = nullptr;
-  double* R[2] = {};   // r_k in R[k & 1]
-  double* PB[2] = {};  // p_k in PB[k & 1]
-  double* q = nullptr;
+  Mg3<double> m64;  // FP64 multigrid-PCG
+  Mg3<float> m32;   // FP32 multigrid-PCG inside FP64 refinement
+  double* F64 = nullptr;        // FP64 right-hand side of a refined solve (padded)
+  double* X64[2] = {};          // its FP64 iterates (x' = x + e written to the other buffer)
+  int xcur = 0;
+  double* x = nullptr;          // the last interior solution (FP64, padded)
   double* xI = nullptr;  // interior part of the solution, accumulated during the outer PCG
   double *part0 = nullptr, *part1 = nullptr;
   State3* st = nullptr;
@@ -75,13 +92,11 @@ struct Problem3D {
   int* hstop = nullptr;
   double* hpart = nullptr;
   Shift3* htab = nullptr;  // [2]
-  double* htol = nullptr;
-  // captured work (replayed on the library stream): the first V-cycle of an interior solve and
-  // one PCG iteration k for each parity of k
-  hipGraphExec_t g_init = nullptr;
-  Chunks g_it;
-  int g_nu = 0;
-  int pred_its = 8;  // iterations of the last interior solve (enqueued before the first check)
+
+  bool mixed = false;  // the running interior solve refines an FP32 multigrid-PCG
+  int maxit = 0, nu = 1;
+  int steps = 0;       // refinement steps enqueued after the first
+  int runs_pred = 2;   // FP32 runs of the last refined solve
   // one face-CG iteration k per (batch, parity of k); iterations of the last batch of each kind
   Chunks g_face[2];
   int g_face_m[2] = {0, 0};
@@ -110,19 +125,27 @@ size_t plan3(fdd_problem_s* P, char* base) {
     return p;
   };
   const size_t v0 = vol(Q->nf);
-  for (int l = 1; l < Q->nlev; ++l) {
-    Q->u[l] = (double*)take(8 * vol(Q->lnf[l]));
-    Q->f[l] = (double*)take(8 * vol(Q->lnf[l]));
-    if (l < Q->lc) Q->uo[l] = (double*)take(8 * vol(Q->lnf[l]));
-  }
-  Q->u[0] = (double*)take(8 * v0);
-  Q->uo[0] = (double*)take(8 * v0);
-  Q->x = (double*)take(8 * v0);
-  for (int b = 0; b < 2; ++b) {
-    Q->R[b] = (double*)take(8 * v0);
-    Q->PB[b] = (double*)take(8 * v0);
-  }
-  Q->q = (double*)take(8 * v0);
+  auto mg = [&](auto& M, size_t w) {
+    for (int l = 1; l < Q->nlev; ++l) {
+      M.u[l] = (decltype(M.x))take(w * vol(Q->lnf[l]));
+      M.f[l] = (decltype(M.x))take(w * vol(Q->lnf[l]));
+      if (l < Q->lc) M.uo[l] = (decltype(M.x))take(w * vol(Q->lnf[l]));
+    }
+    M.u[0] = (decltype(M.x))take(w * v0);
+    M.uo[0] = (decltype(M.x))take(w * v0);
+    M.x = (decltype(M.x))take(w * v0);
+    for (int b = 0; b < 2; ++b) {
+      M.Rv[b] = (decltype(M.x))take(w * v0);
+      M.PB[b] = (decltype(M.x))take(w * v0);
+    }
+    M.q = (decltype(M.x))take(w * v0);
+  };
+  mg(Q->m64, 8);
+  mg(Q->m32, 4);
+  Q->F64 = (double*)take(8 * v0);
+  Q->X64[0] = (double*)take(8 * v0);
+  Q->X64[1] = (double*)take(8 * v0);
+  Q->x = Q->m64.x;
   Q->xI = (double*)take(8 * v0);
   Q->part0 = (double*)take(8 * kPart0);
   Q->part1 = (double*)take(8 * kPart0);
@@ -194,53 +217,56 @@ std::vector<double> dense_inverse_7pt(int nc) {
 }
 
 // V-cycle z = V r on the interior (nu red-black pairs per level: red, black, ... going down,
-// black, red, ... going up).  mode 1: the start of a solve (r_0 in R[0]); mode 2: inside PCG
-// iteration k (r_{k+1} = r_k - alpha_k q formed by the first pass, which leaves it in
-// R[(k + 1) & 1]).  The pass after the first holds the convergence test.  The last pass leaves
+// black, red, ... going up).  mode 1: the start of a run (r_0 in Rv[0]; its |r_0|^2 partials
+// come from the first pass, or, for a refined run, from the refinement step); mode 2: inside
+// PCG iteration k (r_{k+1} = r_k - alpha_k q formed by the first pass, which leaves it in
+// Rv[(k + 1) & 1]).  The pass after the first holds the convergence test.  The last pass leaves
 // z in uo[0] and the partials of r . z in part0.
-void vcycle3(Problem3D* Q, hipStream_t s, int nu, int mode, int k) {
+template <typename R>
+void vcycle3(Problem3D* Q, Mg3<R>& M, hipStream_t s, int nu, int mode, int k, bool refined) {
   const int nf = Q->nf, np0 = Q->np0;
   int* stop = Q->stop;
-  double* f0 = mode == 1 ? Q->R[0] : Q->R[(k + 1) & 1];
+  R* f0 = mode == 1 ? M.Rv[0] : M.Rv[(k + 1) & 1];
   if (mode == 1)
-    k3_launch_zp(s, 1, f0, Q->u[0], nf, Q->rows0, nullptr, nullptr, nullptr, nullptr, Q->st,
-                 nullptr, 0, Q->part0, stop);
+    k3_launch_zp<R>(s, refined ? 0 : 1, f0, M.u[0], nf, Q->rows0, nullptr, nullptr, nullptr,
+                    nullptr, Q->st, nullptr, 0, Q->part0, stop);
   else
-    k3_launch_zp(s, 2, Q->R[k & 1], Q->u[0], nf, Q->rows0, Q->q, f0, Q->x, Q->PB[k & 1], Q->st,
-                 Q->part1, np0, Q->part0, stop);
+    k3_launch_zp<R>(s, 2, M.Rv[k & 1], M.u[0], nf, Q->rows0, M.q, f0, M.x, M.PB[k & 1], Q->st,
+                    Q->part1, np0, Q->part0, stop);
   int check = mode;
   for (int sw = 2; sw < 2 * nu; ++sw) {
-    k3_launch_hs(s, Q->u[0], f0, nf, !(sw & 1), check, Q->st, Q->part0, np0, stop);
+    k3_launch_hs<R>(s, M.u[0], f0, nf, !(sw & 1), check, Q->st, Q->part0, np0, stop);
     check = 0;
   }
-  k3_launch_rr(s, Q->u[0], f0, Q->f[1], nf, Q->lnf[1], check, Q->st, Q->part0, np0, stop);
+  k3_launch_rr<R>(s, M.u[0], f0, M.f[1], nf, Q->lnf[1], check, Q->st, Q->part0, np0, stop);
   for (int l = 1; l < Q->lc; ++l) {
     const int n = Q->lnf[l];
-    k3_launch_zp(s, 0, Q->f[l], Q->u[l], n, 4, nullptr, nullptr, nullptr, nullptr, Q->st, nullptr,
-                 0, nullptr, stop);
+    k3_launch_zp<R>(s, 0, M.f[l], M.u[l], n, 4, nullptr, nullptr, nullptr, nullptr, Q->st,
+                    nullptr, 0, nullptr, stop);
     for (int sw = 2; sw < 2 * nu; ++sw)
-      k3_launch_hs(s, Q->u[l], Q->f[l], n, !(sw & 1), 0, Q->st, nullptr, 0, stop);
-    k3_launch_rr(s, Q->u[l], Q->f[l], Q->f[l + 1], n, Q->lnf[l + 1], 0, Q->st, nullptr, 0, stop);
+      k3_launch_hs<R>(s, M.u[l], M.f[l], n, !(sw & 1), 0, Q->st, nullptr, 0, stop);
+    k3_launch_rr<R>(s, M.u[l], M.f[l], M.f[l + 1], n, Q->lnf[l + 1], 0, Q->st, nullptr, 0, stop);
   }
-  k3_launch_cvc(s, Q->f[Q->lc], Q->u[Q->lc], Q->cvc, Q->cinv, nu, stop);
-  auto fin = [&](int l) { return l < Q->lc ? Q->uo[l] : Q->u[l]; };
+  k3_launch_cvc<R>(s, M.f[Q->lc], M.u[Q->lc], Q->cvc, Q->cinv, nu, stop);
+  auto fin = [&](int l) { return l < Q->lc ? M.uo[l] : M.u[l]; };
   for (int l = Q->lc - 1; l >= 1; --l) {
     const int n = Q->lnf[l];
-    k3_launch_pr(s, Q->u[l], fin(l + 1), Q->f[l], Q->uo[l], n, Q->lnf[l + 1], stop);
+    k3_launch_pr<R>(s, M.u[l], fin(l + 1), M.f[l], M.uo[l], n, Q->lnf[l + 1], stop);
     for (int sw = 1; sw < 2 * nu; ++sw)
-      k3_launch_hs(s, Q->uo[l], Q->f[l], n, sw & 1, 0, Q->st, nullptr, 0, stop);
+      k3_launch_hs<R>(s, M.uo[l], M.f[l], n, sw & 1, 0, Q->st, nullptr, 0, stop);
   }
-  k3_launch_pr(s, Q->u[0], fin(1), f0, Q->uo[0], nf, Q->lnf[1], stop);
+  k3_launch_pr<R>(s, M.u[0], fin(1), f0, M.uo[0], nf, Q->lnf[1], stop);
   for (int sw = 1; sw + 1 < 2 * nu; ++sw)
-    k3_launch_hs(s, Q->uo[0], f0, nf, sw & 1, 0, Q->st, nullptr, 0, stop);
-  k3_launch_hsz(s, Q->uo[0], f0, nf, Q->rows0, Q->part0, stop);
+    k3_launch_hs<R>(s, M.uo[0], f0, nf, sw & 1, 0, Q->st, nullptr, 0, stop);
+  k3_launch_hsz<R>(s, M.uo[0], f0, nf, Q->rows0, Q->part0, stop);
 }
 
 // PCG iteration k: p_k, q = L7 p_k, then the V-cycle that starts with the residual update
-void iteration3(Problem3D* Q, hipStream_t s, int nu, int k) {
-  k3_launch_apply1(s, Q->uo[0], Q->PB[(k + 1) & 1], Q->PB[k & 1], Q->q, Q->nf, Q->rows0, Q->st,
-                   Q->part0, Q->np0, Q->part1, Q->stop);
-  vcycle3(Q, s, nu, 2, k);
+template <typename R>
+void iteration3(Problem3D* Q, Mg3<R>& M, hipStream_t s, int nu, int k) {
+  k3_launch_apply1<R>(s, M.uo[0], M.PB[(k + 1) & 1], M.PB[k & 1], M.q, Q->nf, Q->rows0, Q->st,
+                      Q->part0, Q->np0, Q->part1, Q->stop);
+  vcycle3<R>(Q, M, s, nu, 2, k, false);
 }
 
 int sync_state(Problem3D* Q, hipStream_t s) {
@@ -297,69 +323,134 @@ int enqueue_iterations(hipStream_t s, bool graphs, const Chunks& c, It it, int k
   return FDD_OK;
 }
 
-// L7 x = f (f from rhs), to ||f - L7 x|| <= tol ||f||; x stays in Q->x (padded).  The
-// iterations of the last solve are enqueued first (interior_start), then the state is read back
-// and one iteration at a time is added until the test is met (interior_finish; an iteration
-// enqueued after convergence returns at once in every pass).
-int interior_start(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int maxit,
-                   int nu) {
-  Problem3D* Q = P->p3;
-  const int nf = Q->nf;
-  auto it = [&](int k) { iteration3(Q, s, nu, k); };
-  if (Q->use_graph && Q->g_nu != nu) {
-    if (Q->g_init) (void)hipGraphExecDestroy(Q->g_init);
-    Q->g_init = nullptr;
-    int rc = capture(s, [&]() { vcycle3(Q, s, nu, 1, 0); }, &Q->g_init);
-    if (!rc) rc = capture_chunks(s, it, &Q->g_it);
+// L7 x = f (f from rhs), to ||f - L7 x|| <= tol ||f||; x is left in Q->x (padded FP64).  Mixed
+// precision: runs of FP32 multigrid-PCG, each to a residual reduction of step_rtol, inside FP64
+// iterative refinement (k3_ir: x += e, r = f - L7 x in FP64, the next run's right-hand side; the
+// run that starts on a small enough r ends the solve at once); FP64: one run.  The runs and
+// iterations of the last solve are enqueued before the state is first read back (a run cut
+// short by the next refinement step leaves a valid, smaller correction; an iteration enqueued
+// after its run stopped returns at once in every pass), then one iteration, or one more
+// refinement step, at a time.
+template <typename R>
+int run_start(Problem3D* Q, Mg3<R>& M, hipStream_t s, bool refined, int iters) {
+  const int nu = Q->nu;
+  auto it = [&](int k) { iteration3<R>(Q, M, s, nu, k); };
+  if (Q->use_graph && M.g_nu != nu) {
+    if (M.g_init) (void)hipGraphExecDestroy(M.g_init);
+    M.g_init = nullptr;
+    int rc = capture(s, [&]() { vcycle3<R>(Q, M, s, nu, 1, 0, refined); }, &M.g_init);
+    if (!rc) rc = capture_chunks(s, it, &M.g_it);
     if (rc) return rc;
-    Q->g_nu = nu;
+    M.g_nu = nu;
   }
-  k3_launch_rhs(s, rhs, Q->R[0], nf);
-  HIPCHK(hipMemsetAsync(Q->x, 0, 8 * vol(nf), s));
-  *Q->htol = tol * tol;
-  HIPCHK(hipMemcpyAsync(&Q->st->tol2, Q->htol, sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(M.x, 0, sizeof(R) * vol(Q->nf), s));
   HIPCHK(hipMemsetAsync(Q->stop, 0, sizeof(int), s));
-  if (Q->use_graph) HIPCHK(hipGraphLaunch(Q->g_init, s));
-  else vcycle3(Q, s, nu, 1, 0);
-  Q->enq = std::min(std::max(Q->pred_its - 1, 1), maxit);
-  int rc = enqueue_iterations(s, Q->use_graph, Q->g_it, it, 0, Q->enq);
+  if (Q->use_graph) HIPCHK(hipGraphLaunch(M.g_init, s));
+  else vcycle3<R>(Q, M, s, nu, 1, 0, refined);
+  Q->enq = iters;
+  int rc = enqueue_iterations(s, Q->use_graph, M.g_it, it, 0, iters);
   if (rc) return rc;
   HIPCHK(hipGetLastError());
   return FDD_OK;
 }
 
-int interior_finish(fdd_problem_s* P, hipStream_t s, int maxit, int nu, int* its) {
+// refinement step after the first: x += e, r = F - L7 x, then a new FP32 run with `iters`
+// iterations enqueued
+int refine_step(Problem3D* Q, hipStream_t s, int iters) {
+  k3_launch_ir(s, 0, Q->F64, Q->X64[Q->xcur], Q->m32.x, Q->X64[Q->xcur ^ 1], Q->m32.Rv[0], Q->nf,
+               Q->rows0, Q->st, Q->part0);
+  Q->xcur ^= 1;
+  ++Q->steps;
+  return run_start<float>(Q, Q->m32, s, true, iters);
+}
+
+int interior_start(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int maxit,
+                   int nu, bool mixed, double step_rtol) {
   Problem3D* Q = P->p3;
-  auto it = [&](int k) { iteration3(Q, s, nu, k); };
+  const int nf = Q->nf;
+  Q->mixed = mixed;
+  Q->maxit = maxit;
+  Q->nu = nu;
+  State3& h = *Q->hst;
+  h = State3{};
+  h.tol2 = mixed ? step_rtol * step_rtol : tol * tol;
+  h.tol2s = tol * tol;
+  HIPCHK(hipMemcpyAsync(Q->st, Q->hst, sizeof(State3), hipMemcpyHostToDevice, s));
+  if (!mixed) {
+    k3_launch_rhs(s, rhs, Q->m64.Rv[0], nf);
+    return run_start<double>(Q, Q->m64, s, false, std::min(std::max(Q->m64.pred - 1, 1), maxit));
+  }
+  k3_launch_rhs(s, rhs, Q->F64, nf);
+  HIPCHK(hipMemsetAsync(Q->X64[0], 0, 8 * vol(nf), s));
+  Q->xcur = 0;
+  Q->steps = 0;
+  k3_launch_ir(s, 1, Q->F64, nullptr, nullptr, nullptr, Q->m32.Rv[0], nf, Q->rows0, Q->st,
+               Q->part0);
+  const int per = std::min(std::max(Q->m32.pred, 1), maxit);
+  int rc = run_start<float>(Q, Q->m32, s, true, per);
+  // the further runs the last solve took, then the step expected to end the solve
+  for (int r = 1; r < Q->runs_pred && !rc; ++r) rc = refine_step(Q, s, per);
+  if (!rc) rc = refine_step(Q, s, 0);
+  return rc;
+}
+
+int interior_finish(fdd_problem_s* P, hipStream_t s, int* its) {
+  Problem3D* Q = P->p3;
+  constexpr int kMaxRefine = 12;
   int done = 0;
   while (true) {
     int rc = sync_state(Q, s);
     if (rc) return rc;
-    if (*Q->hstop) {
+    const State3& h = *Q->hst;
+    if (h.breakdown) break;
+    if (*Q->hstop && (!Q->mixed || h.done)) {
       done = 1;
       break;
     }
-    if (Q->enq >= maxit) break;
-    rc = enqueue_iterations(s, Q->use_graph, Q->g_it, it, Q->enq, Q->enq + 1);
+    if (h.its_total >= Q->maxit) break;
+    if (*Q->hstop) {
+      // the last run stopped short of the solve's tolerance: one more refinement step
+      if (Q->steps >= kMaxRefine) break;
+      rc = refine_step(Q, s, std::min(std::max(Q->m32.pred, 1), Q->maxit - h.its_total));
+      if (rc) return rc;
+      continue;
+    }
+    auto it = [&](int k) {
+      if (Q->mixed) iteration3<float>(Q, Q->m32, s, Q->nu, k);
+      else iteration3<double>(Q, Q->m64, s, Q->nu, k);
+    };
+    rc = enqueue_iterations(s, Q->use_graph, Q->mixed ? Q->m32.g_it : Q->m64.g_it, it, Q->enq,
+                            Q->enq + 1);
     if (rc) return rc;
     ++Q->enq;
     HIPCHK(hipGetLastError());
   }
-  if (its) *its = Q->hst->its;
-  if (done && !Q->hst->breakdown) Q->pred_its = std::max(Q->hst->its, 1);
-  if (Q->hst->breakdown)
-    return fail(Q->hst->breakdown & 4 ? FDD_E_NONFINITE : FDD_E_BREAKDOWN,
-                "3D interior solve: breakdown (flags %d)", Q->hst->breakdown);
+  const State3& h = *Q->hst;
+  if (Q->mixed) {
+    // runs that iterated: every refinement step but the one that ended the solve
+    const int runs = std::max(h.run + (done ? 0 : 1), 1);
+    if (done && h.its_total > 0) {
+      Q->runs_pred = runs;
+      Q->m32.pred = (h.its_total + runs - 1) / runs;
+    }
+  } else if (done && h.its > 0) {
+    Q->m64.pred = h.its;
+  }
+  Q->x = Q->mixed ? Q->X64[Q->xcur] : Q->m64.x;
+  if (its) *its = h.its_total;
+  if (h.breakdown)
+    return fail(h.breakdown & 4 ? FDD_E_NONFINITE : FDD_E_BREAKDOWN,
+                "3D interior solve: breakdown (flags %d)", h.breakdown);
   if (!done)
     return fail(FDD_NOT_CONVERGED, "3D interior solve: %d iterations, residual %.3e of %.3e",
-                Q->hst->its, std::sqrt(Q->hst->rr), std::sqrt(Q->hst->ff));
+                h.its_total, std::sqrt(h.rr), std::sqrt(h.F2));
   return FDD_OK;
 }
 
-int interior3(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol, int maxit, int nu,
-              int* its) {
-  int rc = interior_start(P, s, rhs, tol, maxit, nu);
-  return rc ? rc : interior_finish(P, s, maxit, nu, its);
+int interior3(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, const fdd_opts& o, int* its) {
+  int rc = interior_start(P, s, rhs, o.inner_rtol, o.inner_maxit, o.mg_nu,
+                          o.precision == FDD_MIXED, o.step_rtol);
+  return rc ? rc : interior_finish(P, s, its);
 }
 
 Shift3 table3(const fdd_ratpc_s* t) {
@@ -509,10 +600,11 @@ int schur3(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* HT, const double*
   HIPCHK(hipEventRecord(Q->ev_fork, s));
   HIPCHK(hipStreamWaitEvent(Q->s2, Q->ev_fork, 0));
   const Rhs3 lift{nullptr, 0.0, p, 1.0};
-  int rc = interior_start(P, s, lift, o.inner_rtol, o.inner_maxit, o.mg_nu);
+  int rc = interior_start(P, s, lift, o.inner_rtol, o.inner_maxit, o.mg_nu,
+                          o.precision == FDD_MIXED, o.step_rtol);
   FaceRun run{};
   if (!rc) rc = face_start(P, Q->s2, HT, p, &run);
-  if (!rc) rc = interior_finish(P, s, o.inner_maxit, o.mg_nu, its);
+  if (!rc) rc = interior_finish(P, s, its);
   if (!rc) rc = face_finish(P, Q->s2, run, p, Q->Hp);
   // join in every case, so that no work of the second stream outlives the call unordered
   (void)hipEventRecord(Q->ev_join, Q->s2);
@@ -646,7 +738,6 @@ int bind3(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s) {
     }
     HIPCHK(hipHostMalloc((void**)&Q->hpart, 8 * 2 * kPart3, hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&Q->htab, 2 * sizeof(Shift3), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&Q->htol, sizeof(double), hipHostMallocDefault));
   }
   HIPCHK(hipMemsetAsync(P->ws, 0, need, s));
   HIPCHK(hipMemcpyAsync(Q->cinv, Q->cinv_h.data(), 8 * Q->cinv_h.size(), hipMemcpyHostToDevice, s));
@@ -660,10 +751,12 @@ void destroy3(fdd_problem_s* P) {
   if (!Q) return;
   for (void* h : {(void*)Q->hst, (void*)Q->hstop, (void*)Q->fb[0].hdone, (void*)Q->fb[0].hits,
                   (void*)Q->fb[1].hdone, (void*)Q->fb[1].hits, (void*)Q->hpart, (void*)Q->htab,
-                  (void*)Q->htol})
+})
     if (h) (void)hipHostFree(h);
-  if (Q->g_init) (void)hipGraphExecDestroy(Q->g_init);
-  Q->g_it.clear();
+  for (hipGraphExec_t g : {Q->m64.g_init, Q->m32.g_init})
+    if (g) (void)hipGraphExecDestroy(g);
+  Q->m64.g_it.clear();
+  Q->m32.g_it.clear();
   for (Chunks& c : Q->g_face) c.clear();
   if (Q->ev_fork) (void)hipEventDestroy(Q->ev_fork);
   if (Q->ev_join) (void)hipEventDestroy(Q->ev_join);
@@ -680,7 +773,7 @@ int interior_solve3(fdd_problem_s* P, const double* f, double* u, const fdd_opts
   const hipStream_t s = ls.s;
   Q->use_graph = o.use_graph != 0;
   // A_II u = f with A_II = h L7
-  int rc = interior3(P, s, Rhs3{f, 1.0 / P->h, nullptr, 0.0}, o.inner_rtol, o.inner_maxit, o.mg_nu,
+  int rc = interior3(P, s, Rhs3{f, 1.0 / P->h, nullptr, 0.0}, o,
                      its);
   if (rc < 0) return rc;
   k3_launch_gather(s, Q->x, Q->nf, u, nullptr);
@@ -743,7 +836,7 @@ int solve3(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, const
   };
   auto inner = [&](const Rhs3& rhs) {
     int its = 0;
-    int rc = interior3(P, s, rhs, o.inner_rtol, o.inner_maxit, o.mg_nu, &its);
+    int rc = interior3(P, s, rhs, o, &its);
     st.inner_solves += 1;
     st.inner_its_total += its;
     st.inner_its_max = std::max(st.inner_its_max, its);

@@ -18,10 +18,14 @@ struct Rhs3 {
   double sg;
 };
 
-// device scalars of the interior PCG (rho[k & 1] = r_k . z_k)
+// device scalars of the interior solve: the PCG run (rho[k & 1] = r_k . z_k; ff = |r_0|^2 of the
+// run, its = iterations of the run) and, around it, the FP64 refinement (F2 = |F|^2 of the right-
+// hand side, run = refinement step; done: the solve has converged; its_total = iterations of all
+// runs).  A run stops at
+// |r|^2 <= max(tol2 ff, tol2s F2); the solve at |F - L7 x|^2 <= tol2s F2.
 struct State3 {
-  double ff, rr, rho[2], tol2;
-  int its, breakdown;
+  double ff, rr, rho[2], tol2, tol2s, F2;
+  int its, breakdown, run, done, its_total;
 };
 
 // levels of the one-workgroup coarse V-cycle (padded grids of edge lev + 2 in LDS)
@@ -53,24 +57,32 @@ constexpr int kPFS = 256;       // partials per system of the face kernels (>= 6
 constexpr int kFaceMax = 255;  // largest face edge nf (n <= 256)
 constexpr int kFaceRows = 256; // kFaceMax rounded up to whole row groups of 16
 
-// multigrid and PCG kernels of the interior solve (see kernels_3d.hip for what each computes);
-// rows: grid rows per block; pin/np: partials read; part: partials written
-void k3_launch_zp(hipStream_t s, int mode, const double* f, double* u, int nf, int rows,
-                  const double* q, double* rnew, double* x, const double* p, State3* st,
-                  const double* pin, int np, double* part, int* stop);
-void k3_launch_hs(hipStream_t s, double* u, const double* f, int nf, int red, int check,
+// multigrid and PCG kernels of the interior solve (see kernels_3d.hip for what each computes), in
+// the working precision R (float: inside FP64 refinement; double); rows: grid rows per block;
+// pin/np: partials read; part: partials written
+template <typename R>
+void k3_launch_zp(hipStream_t s, int mode, const R* f, R* u, int nf, int rows, const R* q, R* rnew,
+                  R* x, const R* p, State3* st, const double* pin, int np, double* part, int* stop);
+template <typename R>
+void k3_launch_hs(hipStream_t s, R* u, const R* f, int nf, int red, int check, State3* st,
+                  const double* pin, int np, int* stop);
+template <typename R>
+void k3_launch_rr(hipStream_t s, const R* u, const R* f, R* fc, int nf, int nc, int check,
                   State3* st, const double* pin, int np, int* stop);
-void k3_launch_rr(hipStream_t s, const double* u, const double* f, double* fc, int nf, int nc,
-                  int check, State3* st, const double* pin, int np, int* stop);
-void k3_launch_pr(hipStream_t s, const double* u, const double* ec, const double* f, double* uo,
-                  int nf, int nc, int* stop);
-void k3_launch_hsz(hipStream_t s, double* u, const double* f, int nf, int rows, double* part,
-                   int* stop);
-void k3_launch_apply1(hipStream_t s, const double* z, const double* pold, double* pnew, double* q,
-                      int nf, int rows, State3* st, const double* pin, int np, double* part,
-                      int* stop);
-void k3_launch_cvc(hipStream_t s, const double* fin, double* uout, const Cvc3& L,
-                   const double* cinv, int nu, int* stop);
+template <typename R>
+void k3_launch_pr(hipStream_t s, const R* u, const R* ec, const R* f, R* uo, int nf, int nc,
+                  int* stop);
+template <typename R>
+void k3_launch_hsz(hipStream_t s, R* u, const R* f, int nf, int rows, double* part, int* stop);
+template <typename R>
+void k3_launch_apply1(hipStream_t s, const R* z, const R* pold, R* pnew, R* q, int nf, int rows,
+                      State3* st, const double* pin, int np, double* part, int* stop);
+template <typename R>
+void k3_launch_cvc(hipStream_t s, const R* fin, R* uout, const Cvc3& L, const double* cinv,
+                   int nu, int* stop);
+// FP64 refinement step (first: r = F; else x' = x + e, r = F - L7 x'), r also as FP32
+void k3_launch_ir(hipStream_t s, int first, const double* F, const double* xin, const float* e,
+                  double* xout, float* r32, int nf, int rows, State3* st, double* part);
 void k3_launch_rhs(hipStream_t s, const Rhs3& rhs, double* f, int nf);
 void k3_launch_gather(hipStream_t s, const double* u, int nf, double* out, const double* xg);
 // batched face CG (kernels_3d.hip): start (r = src or M src, y = 0), the two vector passes of

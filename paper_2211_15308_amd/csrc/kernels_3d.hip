@@ -105,29 +105,36 @@ __device__ __forceinline__ void put_partial(double* part, double v) {
 
 __device__ __forceinline__ bool is_red3(int i, int j, int k) { return ((i + j + k) & 1) == 0; }
 
-// Convergence bookkeeping of the interior PCG, done by the first kernel after the residual
+// Convergence bookkeeping of the interior solve, done by the first kernel after the residual
 // update (every block sums the same partials and takes the same decision; the lead block
-// records it).  mode 1: start, the partials are |f|^2 (ff = rr = |f|^2, its = 0; f = 0 stops);
-// mode 2: the partials are |r_{k+1}|^2 (its += 1; stop at |r|^2 <= tol^2 |f|^2).
+// records it).  mode 1: start of a run, the partials are |r_0|^2 of its right-hand side (on the
+// first run |F|^2, recorded as F2; on later runs the FP64 refinement residual, which ends the
+// solve once |r_0|^2 <= tol2s F2; r_0 = 0 ends it too); mode 2: the partials are |r_{k+1}|^2
+// (its += 1; the run stops at |r|^2 <= max(tol2 ff, tol2s F2)).
 __device__ __forceinline__ bool k3_check(State3* st, int* stop, const double* part, int np,
                                          int mode) {
   const double a = sum_partials(part, np);
   const bool bad = !isfinite(a);
   bool halt;
   if (mode == 1) {
-    halt = bad || a == 0.0;
+    const bool first = st->run == 0;
+    const bool solved = a == 0.0 || (!first && a <= st->tol2s * st->F2);
+    halt = bad || solved;
     if (lead3()) {
+      if (first) st->F2 = a;
       st->ff = a;
       st->rr = a;
       st->its = 0;
-      st->breakdown = bad ? 4 : 0;
+      if (bad) st->breakdown |= 4;
+      if (solved) st->done = 1;
       if (halt) *stop = 1;
     }
   } else {
-    halt = bad || a <= st->tol2 * st->ff;
+    halt = bad || a <= fmax(st->tol2 * st->ff, st->tol2s * st->F2);
     if (lead3()) {
       st->rr = a;
       st->its += 1;
+      st->its_total += 1;
       if (bad) st->breakdown |= 4;
       if (halt) *stop = 1;
     }
@@ -137,21 +144,19 @@ __device__ __forceinline__ bool k3_check(State3* st, int* stop, const double* pa
 
 // Going down, first two half-sweeps from u = 0 (red, then black) in one pass: u = f / 6 on red
 // points and, on black points, (f + sum of the six red neighbours' f / 6) / 6.
-// MODE 0: f given.  MODE 1 (level 0, start of a solve): also partials of |f|^2.
+// MODE 0: f given.  MODE 1 (level 0, start of a run): also partials of |f|^2.
 // MODE 2 (level 0, PCG iteration k): alpha_k = rho_k / (p_k . A p_k) from the partials of the
 // previous kernel, f = r_{k+1} = r_k - alpha_k q formed on the fly (q = A p_k), r_{k+1} stored,
-// x += alpha_k p_k, partials of |r_{k+1}|^2.
-template <int MODE>
-__global__ __launch_bounds__(kX3* kY3) void k3_zp(const double* __restrict__ f,
-                                                   double* __restrict__ u, int nf, int rows,
-                                                   const double* __restrict__ qv,
-                                                   double* __restrict__ rnew,
-                                                   double* __restrict__ x,
-                                                   const double* __restrict__ p, State3* st,
+// x += alpha_k p_k, partials of |r_{k+1}|^2.  R: the working precision (partials in FP64).
+template <typename R, int MODE>
+__global__ __launch_bounds__(kX3* kY3) void k3_zp(const R* __restrict__ f, R* __restrict__ u,
+                                                   int nf, int rows, const R* __restrict__ qv,
+                                                   R* __restrict__ rnew, R* __restrict__ x,
+                                                   const R* __restrict__ p, State3* st,
                                                    const double* __restrict__ pin, int np,
                                                    double* __restrict__ part, int* stop) {
   if (*stop) return;
-  double al = 0.0;
+  R al = R(0);
   if constexpr (MODE == 2) {
     const double pq = sum_partials(pin, np);
     if (!(pq > 0.0) || !isfinite(pq)) {
@@ -161,130 +166,132 @@ __global__ __launch_bounds__(kX3* kY3) void k3_zp(const double* __restrict__ f,
       }
       return;
     }
-    al = st->rho[st->its & 1] / pq;
+    al = R(st->rho[st->its & 1] / pq);
   }
   const int P = nf + 2, PP = P * P;
-  auto F = [&](int o) -> double {
+  const R sixth = R(1) / R(6);
+  auto F = [&](int o) -> R {
     if constexpr (MODE == 2) return f[o] - al * qv[o];
     else return f[o];
   };
   double acc = 0.0;
   for_points(nf, rows, [&](int i, int j, int k) {
     const int o = (k * P + j) * P + i;
-    const double fo = F(o);
-    double v;
+    const R fo = F(o);
+    R v;
     if (is_red3(i, j, k)) {
-      v = fo * (1.0 / 6.0);
+      v = fo * sixth;
     } else {
-      const double s = F(o - 1) + F(o + 1) + F(o - P) + F(o + P) + F(o - PP) + F(o + PP);
-      v = (fo + s * (1.0 / 6.0)) * (1.0 / 6.0);
+      const R s = F(o - 1) + F(o + 1) + F(o - P) + F(o + P) + F(o - PP) + F(o + PP);
+      v = (fo + s * sixth) * sixth;
     }
     u[o] = v;
     if constexpr (MODE == 2) {
       rnew[o] = fo;
       x[o] += al * p[o];
     }
-    acc += fo * fo;
+    acc += (double)fo * (double)fo;
   });
   if constexpr (MODE != 0) put_partial(part, acc);
 }
 
 // Half-sweep of one colour (red: i + j + k even) of L7 u = f, in place; check != 0: first the
 // convergence bookkeeping of k3_check.
-__global__ __launch_bounds__(kX3* kY3) void k3_hs(double* __restrict__ u,
-                                                   const double* __restrict__ f, int nf, int rows,
-                                                   int red, int check, State3* st,
-                                                   const double* __restrict__ pin, int np,
-                                                   int* stop) {
+template <typename R>
+__global__ __launch_bounds__(kX3* kY3) void k3_hs(R* __restrict__ u, const R* __restrict__ f,
+                                                   int nf, int rows, int red, int check,
+                                                   State3* st, const double* __restrict__ pin,
+                                                   int np, int* stop) {
   if (*stop) return;
   if (check && k3_check(st, stop, pin, np, check)) return;
   const int P = nf + 2, PP = P * P;
   const int want = red ? 0 : 1;
+  const R sixth = R(1) / R(6);
   for_points(nf, rows, [&](int i, int j, int k) {
     if (((i + j + k) & 1) != want) return;
     const int o = (k * P + j) * P + i;
-    u[o] = (f[o] + u[o - 1] + u[o + 1] + u[o - P] + u[o + P] + u[o - PP] + u[o + PP]) *
-           (1.0 / 6.0);
+    u[o] = (f[o] + u[o - 1] + u[o + 1] + u[o - P] + u[o + P] + u[o - PP] + u[o + PP]) * sixth;
   });
 }
 
 // Residual and restriction in one pass: f_c(I) = 1/2 [t(2I) + 1/2 sum over the 14 Kuhn-edge
 // neighbours 2I +- d of t], t = f - L7 u formed where it is read (every such fine point is
 // interior).  Grid over the coarse points; check as in k3_hs.
-__global__ __launch_bounds__(kX3* kY3) void k3_rr(const double* __restrict__ u,
-                                                   const double* __restrict__ f,
-                                                   double* __restrict__ fc, int nf, int nc,
-                                                   int rows, int check, State3* st,
+template <typename R>
+__global__ __launch_bounds__(kX3* kY3) void k3_rr(const R* __restrict__ u, const R* __restrict__ f,
+                                                   R* __restrict__ fc, int nf, int nc, int rows,
+                                                   int check, State3* st,
                                                    const double* __restrict__ pin, int np,
                                                    int* stop) {
   if (*stop) return;
   if (check && k3_check(st, stop, pin, np, check)) return;
   const int P = nf + 2, PP = P * P, Pc = nc + 2;
-  auto T = [&](int o) {
-    return f[o] - (6.0 * u[o] - u[o - 1] - u[o + 1] - u[o - P] - u[o + P] - u[o - PP] -
+  auto res = [&](int o) {
+    return f[o] - (R(6) * u[o] - u[o - 1] - u[o + 1] - u[o - P] - u[o + P] - u[o - PP] -
                    u[o + PP]);
   };
   for_points(nc, rows, [&](int I, int J, int K) {
     const int o = ((2 * K) * P + 2 * J) * P + 2 * I;
     // Kuhn edge directions: e1, e2, e3, e1+e2, e1+e3, e2+e3, e1+e2+e3
     const int d1 = 1, d2 = P, d3 = PP;
-    const double s = T(o + d1) + T(o - d1) + T(o + d2) + T(o - d2) + T(o + d3) + T(o - d3) +
-                     T(o + d1 + d2) + T(o - d1 - d2) + T(o + d1 + d3) + T(o - d1 - d3) +
-                     T(o + d2 + d3) + T(o - d2 - d3) + T(o + d1 + d2 + d3) +
-                     T(o - d1 - d2 - d3);
-    fc[(K * Pc + J) * Pc + I] = 0.5 * (T(o) + 0.5 * s);
+    const R s = res(o + d1) + res(o - d1) + res(o + d2) + res(o - d2) + res(o + d3) +
+                res(o - d3) + res(o + d1 + d2) + res(o - d1 - d2) + res(o + d1 + d3) +
+                res(o - d1 - d3) + res(o + d2 + d3) + res(o - d2 - d3) + res(o + d1 + d2 + d3) +
+                res(o - d1 - d2 - d3);
+    fc[(K * Pc + J) * Pc + I] = R(0.5) * (res(o) + R(0.5) * s);
   });
 }
 
 // Going up: v = u + P e_c (a fine node at 2I + d, d in {0,1}^3, takes the mean of the coarse
 // nodes I and I + d), then the first black half-sweep on v, in one pass into uo (uo != u:
 // the black points read their red neighbours' v, formed where they are read).
-__global__ __launch_bounds__(kX3* kY3) void k3_pr(const double* __restrict__ u,
-                                                   const double* __restrict__ ec,
-                                                   const double* __restrict__ f,
-                                                   double* __restrict__ uo, int nf, int nc,
-                                                   int rows, int* stop) {
+template <typename R>
+__global__ __launch_bounds__(kX3* kY3) void k3_pr(const R* __restrict__ u,
+                                                   const R* __restrict__ ec,
+                                                   const R* __restrict__ f, R* __restrict__ uo,
+                                                   int nf, int nc, int rows, int* stop) {
   if (*stop) return;
   const int P = nf + 2, Pc = nc + 2;
+  const R sixth = R(1) / R(6);
   // valid on the zero border too: the coarse nodes read there lie on the coarse border
   auto V = [&](int i, int j, int k) {
     const int I = i >> 1, J = j >> 1, K = k >> 1;
     const int oc = (K * Pc + J) * Pc + I;
     const int od = ((k & 1) * Pc + (j & 1)) * Pc + (i & 1);
-    const double e = od ? 0.5 * (ec[oc] + ec[oc + od]) : ec[oc];
+    const R e = od ? R(0.5) * (ec[oc] + ec[oc + od]) : ec[oc];
     return u[(k * P + j) * P + i] + e;
   };
   for_points(nf, rows, [&](int i, int j, int k) {
     const int o = (k * P + j) * P + i;
-    double v;
+    R v;
     if (is_red3(i, j, k)) {
       v = V(i, j, k);
     } else {
       v = (f[o] + V(i - 1, j, k) + V(i + 1, j, k) + V(i, j - 1, k) + V(i, j + 1, k) +
            V(i, j, k - 1) + V(i, j, k + 1)) *
-          (1.0 / 6.0);
+          sixth;
     }
     uo[o] = v;
   });
 }
 
 // Last half-sweep of the V-cycle on level 0 (red) with the partials of r . z (f = r, z = u).
-__global__ __launch_bounds__(kX3* kY3) void k3_hsz(double* __restrict__ u,
-                                                    const double* __restrict__ f, int nf,
-                                                    int rows, double* __restrict__ part,
+template <typename R>
+__global__ __launch_bounds__(kX3* kY3) void k3_hsz(R* __restrict__ u, const R* __restrict__ f,
+                                                    int nf, int rows, double* __restrict__ part,
                                                     int* stop) {
   if (*stop) return;
   const int P = nf + 2, PP = P * P;
+  const R sixth = R(1) / R(6);
   double acc = 0.0;
   for_points(nf, rows, [&](int i, int j, int k) {
     const int o = (k * P + j) * P + i;
-    double z = u[o];
+    R z = u[o];
     if (is_red3(i, j, k)) {
-      z = (f[o] + u[o - 1] + u[o + 1] + u[o - P] + u[o + P] + u[o - PP] + u[o + PP]) *
-          (1.0 / 6.0);
+      z = (f[o] + u[o - 1] + u[o + 1] + u[o - P] + u[o + P] + u[o - PP] + u[o + PP]) * sixth;
       u[o] = z;
     }
-    acc += f[o] * z;
+    acc += (double)f[o] * (double)z;
   });
   put_partial(part, acc);
 }
@@ -292,13 +299,13 @@ __global__ __launch_bounds__(kX3* kY3) void k3_hsz(double* __restrict__ u,
 // PCG iteration k, first pass: rho_k = r_k . z_k from the partials of the V-cycle,
 // beta_k = rho_k / rho_{k-1} (beta_0 = 0), p_k = z_k + beta_k p_{k-1} (stored; also formed at
 // the neighbours), q = L7 p_k, partials of p_k . q.  rho_k is recorded in st->rho[k & 1].
-__global__ __launch_bounds__(kX3* kY3) void k3_apply1(const double* __restrict__ z,
-                                                       const double* __restrict__ pold,
-                                                       double* __restrict__ pnew,
-                                                       double* __restrict__ qv, int nf, int rows,
-                                                       State3* st, const double* __restrict__ pin,
-                                                       int np, double* __restrict__ part,
-                                                       int* stop) {
+template <typename R>
+__global__ __launch_bounds__(kX3* kY3) void k3_apply1(const R* __restrict__ z,
+                                                       const R* __restrict__ pold,
+                                                       R* __restrict__ pnew, R* __restrict__ qv,
+                                                       int nf, int rows, State3* st,
+                                                       const double* __restrict__ pin, int np,
+                                                       double* __restrict__ part, int* stop) {
   if (*stop) return;
   const double rz = sum_partials(pin, np);
   const int it = st->its;
@@ -309,19 +316,51 @@ __global__ __launch_bounds__(kX3* kY3) void k3_apply1(const double* __restrict__
     }
     return;
   }
-  const double beta = it ? rz / st->rho[(it - 1) & 1] : 0.0;
+  const R beta = it ? R(rz / st->rho[(it - 1) & 1]) : R(0);
   if (lead3()) st->rho[it & 1] = rz;
   const int P = nf + 2, PP = P * P;
   auto PV = [&](int o) { return it ? z[o] + beta * pold[o] : z[o]; };
   double acc = 0.0;
   for_points(nf, rows, [&](int i, int j, int k) {
     const int o = (k * P + j) * P + i;
-    const double pv = PV(o);
-    const double q = 6.0 * pv - PV(o - 1) - PV(o + 1) - PV(o - P) - PV(o + P) - PV(o - PP) -
-                     PV(o + PP);
+    const R pv = PV(o);
+    const R q = R(6) * pv - PV(o - 1) - PV(o + 1) - PV(o - P) - PV(o + P) - PV(o - PP) -
+                PV(o + PP);
     pnew[o] = pv;
     qv[o] = q;
-    acc += pv * q;
+    acc += (double)pv * (double)q;
+  });
+  put_partial(part, acc);
+}
+
+// FP64 iterative refinement around the working-precision PCG (level 0, padded grids):
+// FIRST: r = F (x = 0); otherwise x' = x + e (formed at the neighbours too) is stored,
+// r = F - L7 x' (FP64) and the refinement step count st->run is advanced.  r is stored in the
+// working precision as the next run's right-hand side and the partials of |r|^2 (FP64) go to
+// part.
+template <bool FIRST>
+__global__ __launch_bounds__(kX3* kY3) void k3_ir(const double* __restrict__ F,
+                                                   const double* __restrict__ xin,
+                                                   const float* __restrict__ e,
+                                                   double* __restrict__ xout,
+                                                   float* __restrict__ r32, int nf, int rows,
+                                                   State3* st, double* __restrict__ part) {
+  if (!FIRST && lead3()) st->run += 1;
+  const int P = nf + 2, PP = P * P;
+  auto X = [&](int o) { return xin[o] + (double)e[o]; };
+  double acc = 0.0;
+  for_points(nf, rows, [&](int i, int j, int k) {
+    const int o = (k * P + j) * P + i;
+    double r;
+    if constexpr (FIRST) {
+      r = F[o];
+    } else {
+      const double xo = X(o);
+      xout[o] = xo;
+      r = F[o] - (6.0 * xo - X(o - 1) - X(o + 1) - X(o - P) - X(o + P) - X(o - PP) - X(o + PP));
+    }
+    r32[o] = (float)r;
+    acc += r * r;
   });
   put_partial(part, acc);
 }
@@ -342,16 +381,18 @@ __device__ __forceinline__ void cvc_points(int nf, Fn&& fn) {
   for (int k = (t >> 8) + 1; k <= nf; k += kCvcThreads / 256) fn(i, j, k);
 }
 
-__global__ __launch_bounds__(kCvcThreads) void k3_cvc(const double* __restrict__ fin,
-                                                       double* __restrict__ uout, Cvc3 L,
+template <typename R>
+__global__ __launch_bounds__(kCvcThreads) void k3_cvc(const R* __restrict__ fin,
+                                                       R* __restrict__ uout, Cvc3 L,
                                                        const double* __restrict__ cinv, int nu,
                                                        const int* __restrict__ stop) {
   if (*stop) return;
-  __shared__ double lds[kCvcLds];
+  __shared__ R lds[kCvcLds];
+  const R sixth = R(1) / R(6);
   const int t = threadIdx.x;
   // level l: u at U[l], f at Fv[l] (the loops over levels are unrolled: static indices)
-  double* U[kCvcLevels];
-  double* Fv[kCvcLevels];
+  R* U[kCvcLevels];
+  R* Fv[kCvcLevels];
   int ed[kCvcLevels];
   int tot = 0;
 #pragma unroll
@@ -362,7 +403,7 @@ __global__ __launch_bounds__(kCvcThreads) void k3_cvc(const double* __restrict__
     Fv[l] = lds + tot + v;
     tot += l < L.nl ? 2 * v : 0;
   }
-  for (int q = t; q < tot; q += kCvcThreads) lds[q] = 0.0;
+  for (int q = t; q < tot; q += kCvcThreads) lds[q] = R(0);
   __syncthreads();
   {
     const int P = ed[0] + 2;
@@ -372,13 +413,12 @@ __global__ __launch_bounds__(kCvcThreads) void k3_cvc(const double* __restrict__
     });
   }
   __syncthreads();
-  auto half = [&](double* u, const double* f, int nf, int want) {
+  auto half = [&](R* u, const R* f, int nf, int want) {
     const int P = nf + 2, PP = P * P;
     cvc_points(nf, [&](int i, int j, int k) {
       if (((i + j + k) & 1) != want) return;
       const int o = (k * P + j) * P + i;
-      u[o] = (f[o] + u[o - 1] + u[o + 1] + u[o - P] + u[o + P] + u[o - PP] + u[o + PP]) *
-             (1.0 / 6.0);
+      u[o] = (f[o] + u[o - 1] + u[o + 1] + u[o - P] + u[o + P] + u[o - PP] + u[o + PP]) * sixth;
     });
     __syncthreads();
   };
@@ -386,33 +426,33 @@ __global__ __launch_bounds__(kCvcThreads) void k3_cvc(const double* __restrict__
   for (int l = 0; l + 1 < kCvcLevels; ++l) {
     if (l + 1 >= L.nl) break;
     const int nf = ed[l], P = nf + 2, PP = P * P;
-    double* u = U[l];
-    const double* f = Fv[l];
+    R* u = U[l];
+    const R* f = Fv[l];
     cvc_points(nf, [&](int i, int j, int k) {
       const int o = (k * P + j) * P + i;
       if (((i + j + k) & 1) == 0) {
-        u[o] = f[o] * (1.0 / 6.0);
+        u[o] = f[o] * sixth;
       } else {
-        const double s = f[o - 1] + f[o + 1] + f[o - P] + f[o + P] + f[o - PP] + f[o + PP];
-        u[o] = (f[o] + s * (1.0 / 6.0)) * (1.0 / 6.0);
+        const R s = f[o - 1] + f[o + 1] + f[o - P] + f[o + P] + f[o - PP] + f[o + PP];
+        u[o] = (f[o] + s * sixth) * sixth;
       }
     });
     __syncthreads();
     for (int sw = 2; sw < 2 * nu; ++sw) half(u, f, nf, (sw & 1) ? 1 : 0);
     const int nc = ed[l + 1], Pc = nc + 2;
-    double* fc = Fv[l + 1];
+    R* fc = Fv[l + 1];
     auto T = [&](int o) {
-      return f[o] - (6.0 * u[o] - u[o - 1] - u[o + 1] - u[o - P] - u[o + P] - u[o - PP] -
+      return f[o] - (R(6) * u[o] - u[o - 1] - u[o + 1] - u[o - P] - u[o + P] - u[o - PP] -
                      u[o + PP]);
     };
     cvc_points(nc, [&](int I, int J, int K) {
       const int o = ((2 * K) * P + 2 * J) * P + 2 * I;
       const int d1 = 1, d2 = P, d3 = PP;
-      const double s = T(o + d1) + T(o - d1) + T(o + d2) + T(o - d2) + T(o + d3) + T(o - d3) +
+      const R s = T(o + d1) + T(o - d1) + T(o + d2) + T(o - d2) + T(o + d3) + T(o - d3) +
                        T(o + d1 + d2) + T(o - d1 - d2) + T(o + d1 + d3) + T(o - d1 - d3) +
                        T(o + d2 + d3) + T(o - d2 - d3) + T(o + d1 + d2 + d3) +
                        T(o - d1 - d2 - d3);
-      fc[(K * Pc + J) * Pc + I] = 0.5 * (T(o) + 0.5 * s);
+      fc[(K * Pc + J) * Pc + I] = R(0.5) * (T(o) + R(0.5) * s);
     });
     __syncthreads();
   }
@@ -429,7 +469,7 @@ __global__ __launch_bounds__(kCvcThreads) void k3_cvc(const double* __restrict__
           for (int ii = 1; ii <= nc; ++ii)
             a += cinv[row * np + ((kk - 1) * nc + (jj - 1)) * nc + (ii - 1)] *
                  Fv[l][(kk * Pc + jj) * Pc + ii];
-      U[l][(k * Pc + j) * Pc + i] = a;
+      U[l][(k * Pc + j) * Pc + i] = (R)a;
     });
   }
   __syncthreads();
@@ -438,13 +478,13 @@ __global__ __launch_bounds__(kCvcThreads) void k3_cvc(const double* __restrict__
     if (l + 1 >= L.nl) continue;
     const int nf = ed[l], P = nf + 2;
     const int nc = ed[l + 1], Pc = nc + 2;
-    double* u = U[l];
-    const double* ec = U[l + 1];
+    R* u = U[l];
+    const R* ec = U[l + 1];
     cvc_points(nf, [&](int i, int j, int k) {
       const int I = i >> 1, J = j >> 1, K = k >> 1;
       const int oc = (K * Pc + J) * Pc + I;
       const int od = ((k & 1) * Pc + (j & 1)) * Pc + (i & 1);
-      u[(k * P + j) * P + i] += od ? 0.5 * (ec[oc] + ec[oc + od]) : ec[oc];
+      u[(k * P + j) * P + i] += od ? R(0.5) * (ec[oc] + ec[oc + od]) : ec[oc];
     });
     __syncthreads();
     for (int sw = 0; sw < 2 * nu; ++sw) half(u, Fv[l], nf, (sw & 1) ? 0 : 1);
@@ -967,46 +1007,76 @@ int k3_cvc_fits(const Cvc3& L) {
 static inline dim3 grid3(int nf, int rows) { return dim3((nf + rows - 1) / rows, nf); }
 static const dim3 kBlk3(kX3, kY3);
 
-void k3_launch_zp(hipStream_t s, int mode, const double* f, double* u, int nf, int rows,
-                  const double* q, double* rnew, double* x, const double* p, State3* st,
-                  const double* pin, int np, double* part, int* stop) {
+template <typename R>
+void k3_launch_zp(hipStream_t s, int mode, const R* f, R* u, int nf, int rows, const R* q, R* rnew,
+                  R* x, const R* p, State3* st, const double* pin, int np, double* part,
+                  int* stop) {
   if (mode == 0)
-    hipLaunchKernelGGL(k3_zp<0>, grid3(nf, rows), kBlk3, 0, s, f, u, nf, rows, q, rnew, x, p, st,
-                       pin, np, part, stop);
+    hipLaunchKernelGGL((k3_zp<R, 0>), grid3(nf, rows), kBlk3, 0, s, f, u, nf, rows, q, rnew, x, p,
+                       st, pin, np, part, stop);
   else if (mode == 1)
-    hipLaunchKernelGGL(k3_zp<1>, grid3(nf, rows), kBlk3, 0, s, f, u, nf, rows, q, rnew, x, p, st,
-                       pin, np, part, stop);
+    hipLaunchKernelGGL((k3_zp<R, 1>), grid3(nf, rows), kBlk3, 0, s, f, u, nf, rows, q, rnew, x, p,
+                       st, pin, np, part, stop);
   else
-    hipLaunchKernelGGL(k3_zp<2>, grid3(nf, rows), kBlk3, 0, s, f, u, nf, rows, q, rnew, x, p, st,
-                       pin, np, part, stop);
+    hipLaunchKernelGGL((k3_zp<R, 2>), grid3(nf, rows), kBlk3, 0, s, f, u, nf, rows, q, rnew, x, p,
+                       st, pin, np, part, stop);
 }
-void k3_launch_hs(hipStream_t s, double* u, const double* f, int nf, int red, int check,
-                  State3* st, const double* pin, int np, int* stop) {
-  hipLaunchKernelGGL(k3_hs, grid3(nf, 4), kBlk3, 0, s, u, f, nf, 4, red, check, st, pin, np, stop);
-}
-void k3_launch_rr(hipStream_t s, const double* u, const double* f, double* fc, int nf, int nc,
-                  int check, State3* st, const double* pin, int np, int* stop) {
-  hipLaunchKernelGGL(k3_rr, grid3(nc, 4), kBlk3, 0, s, u, f, fc, nf, nc, 4, check, st, pin, np,
+template <typename R>
+void k3_launch_hs(hipStream_t s, R* u, const R* f, int nf, int red, int check, State3* st,
+                  const double* pin, int np, int* stop) {
+  hipLaunchKernelGGL(k3_hs<R>, grid3(nf, 4), kBlk3, 0, s, u, f, nf, 4, red, check, st, pin, np,
                      stop);
 }
-void k3_launch_pr(hipStream_t s, const double* u, const double* ec, const double* f, double* uo,
-                  int nf, int nc, int* stop) {
-  hipLaunchKernelGGL(k3_pr, grid3(nf, 4), kBlk3, 0, s, u, ec, f, uo, nf, nc, 4, stop);
+template <typename R>
+void k3_launch_rr(hipStream_t s, const R* u, const R* f, R* fc, int nf, int nc, int check,
+                  State3* st, const double* pin, int np, int* stop) {
+  hipLaunchKernelGGL(k3_rr<R>, grid3(nc, 4), kBlk3, 0, s, u, f, fc, nf, nc, 4, check, st, pin, np,
+                     stop);
 }
-void k3_launch_hsz(hipStream_t s, double* u, const double* f, int nf, int rows, double* part,
-                   int* stop) {
-  hipLaunchKernelGGL(k3_hsz, grid3(nf, rows), kBlk3, 0, s, u, f, nf, rows, part, stop);
+template <typename R>
+void k3_launch_pr(hipStream_t s, const R* u, const R* ec, const R* f, R* uo, int nf, int nc,
+                  int* stop) {
+  hipLaunchKernelGGL(k3_pr<R>, grid3(nf, 4), kBlk3, 0, s, u, ec, f, uo, nf, nc, 4, stop);
 }
-void k3_launch_apply1(hipStream_t s, const double* z, const double* pold, double* pnew, double* q,
-                      int nf, int rows, State3* st, const double* pin, int np, double* part,
-                      int* stop) {
-  hipLaunchKernelGGL(k3_apply1, grid3(nf, rows), kBlk3, 0, s, z, pold, pnew, q, nf, rows, st, pin,
-                     np, part, stop);
+template <typename R>
+void k3_launch_hsz(hipStream_t s, R* u, const R* f, int nf, int rows, double* part, int* stop) {
+  hipLaunchKernelGGL(k3_hsz<R>, grid3(nf, rows), kBlk3, 0, s, u, f, nf, rows, part, stop);
 }
-void k3_launch_cvc(hipStream_t s, const double* fin, double* uout, const Cvc3& L,
-                   const double* cinv, int nu, int* stop) {
-  hipLaunchKernelGGL(k3_cvc, dim3(1), dim3(kCvcThreads), 0, s, fin, uout, L, cinv, nu, stop);
+template <typename R>
+void k3_launch_apply1(hipStream_t s, const R* z, const R* pold, R* pnew, R* q, int nf, int rows,
+                      State3* st, const double* pin, int np, double* part, int* stop) {
+  hipLaunchKernelGGL(k3_apply1<R>, grid3(nf, rows), kBlk3, 0, s, z, pold, pnew, q, nf, rows, st,
+                     pin, np, part, stop);
 }
+template <typename R>
+void k3_launch_cvc(hipStream_t s, const R* fin, R* uout, const Cvc3& L, const double* cinv,
+                   int nu, int* stop) {
+  hipLaunchKernelGGL(k3_cvc<R>, dim3(1), dim3(kCvcThreads), 0, s, fin, uout, L, cinv, nu, stop);
+}
+void k3_launch_ir(hipStream_t s, int first, const double* F, const double* xin, const float* e,
+                  double* xout, float* r32, int nf, int rows, State3* st, double* part) {
+  if (first)
+    hipLaunchKernelGGL(k3_ir<true>, grid3(nf, rows), kBlk3, 0, s, F, xin, e, xout, r32, nf, rows,
+                       st, part);
+  else
+    hipLaunchKernelGGL(k3_ir<false>, grid3(nf, rows), kBlk3, 0, s, F, xin, e, xout, r32, nf, rows,
+                       st, part);
+}
+#define K3_INSTANTIATE(R)                                                                        \
+  template void k3_launch_zp<R>(hipStream_t, int, const R*, R*, int, int, const R*, R*, R*,     \
+                                const R*, State3*, const double*, int, double*, int*);          \
+  template void k3_launch_hs<R>(hipStream_t, R*, const R*, int, int, int, State3*,              \
+                                const double*, int, int*);                                      \
+  template void k3_launch_rr<R>(hipStream_t, const R*, const R*, R*, int, int, int, State3*,    \
+                                const double*, int, int*);                                      \
+  template void k3_launch_pr<R>(hipStream_t, const R*, const R*, const R*, R*, int, int, int*); \
+  template void k3_launch_hsz<R>(hipStream_t, R*, const R*, int, int, double*, int*);           \
+  template void k3_launch_apply1<R>(hipStream_t, const R*, const R*, R*, R*, int, int, State3*, \
+                                    const double*, int, double*, int*);                         \
+  template void k3_launch_cvc<R>(hipStream_t, const R*, R*, const Cvc3&, const double*, int, int*);
+K3_INSTANTIATE(float)
+K3_INSTANTIATE(double)
+#undef K3_INSTANTIATE
 void k3_launch_rhs(hipStream_t s, const Rhs3& rhs, double* f, int nf) {
   hipLaunchKernelGGL(k3_rhs, dim3(grid_for((int64_t)nf * nf * nf, 4096)), dim3(kB3), 0, s, rhs, f,
                      nf);
