@@ -3,8 +3,9 @@
 // interface Schur complement, interior solves by multigrid-preconditioned CG, the rational
 // preconditioner and operator of eq. (RA).  In 3D every interior block is h L7 (L7 the 7-point
 // stencil), the Gamma row of the stiffness is h (3, -1/2 x 4 in the face, -1 below), and the
-// shifted interface systems are 2D face problems solved by batched CG (kernels_3d.hip).  All
-// arithmetic is FP64.  Krylov iterations are replayed from captured graphs; the host enqueues
+// shifted interface systems are 2D face problems solved by batched CG (kernels_3d.hip).  The
+// interface work is FP64; interior solves run FP32 multigrid-PCG inside FP64 iterative refinement
+// (or FP64 multigrid-PCG).  Krylov iterations are replayed from captured graphs; the host enqueues
 // as many as the previous solve of the same kind took, then reads the device flags and adds
 // one iteration at a time.
 #include <algorithm>

@@ -1,4 +1,5 @@
-// The 3D solver's kernels (unit cube, Kuhn tetrahedra, Gamma the face z = 1), FP64, for gfx950.
+// The 3D solver's kernels (unit cube, Kuhn tetrahedra, Gamma the face z = 1) for gfx950: interface
+// work in FP64, the interior multigrid-PCG in FP32 (inside FP64 refinement) or FP64.
 //
 // Interior block: on the uniform Kuhn mesh the P1 stiffness of an interior node is h times the
 // 7-point stencil (6, -1 x 6), so A_II = h L7 and every interior solve is a solve with L7.  It
