@@ -667,7 +667,8 @@ int setup3(const fdd_desc* d, int hip_device, fdd_problem_s* P) {
   int nf = n - 1, l = 0;
   while (true) {
     Q->lnf[l] = nf;
-    if (!(nf & 1) || nf <= 1) break;
+    // coarsest: 3^3 (dense inverse), or 1 below a finest level of 3^3
+    if (!(nf & 1) || nf <= 1 || (nf <= 3 && l > 0)) break;
     nf = (nf - 1) / 2;
     if (++l >= kMaxLevels) {
       delete Q;

@@ -6,7 +6,7 @@
 
 namespace fdd {
 
-constexpr int kPart3 = 1024;  // blocks (and partials) of the interior dot-product kernels
+constexpr int kPart3 = 1024;  // blocks (and partials) of the face-vector and full-operator reductions
 constexpr int kPartF = 64;    // blocks per system of the face kernels
 constexpr int kMaxSys3 = 80;  // shifted systems in one face batch
 
@@ -21,8 +21,7 @@ struct Rhs3 {
 // device scalars of the interior solve: the PCG run (rho[k & 1] = r_k . z_k; ff = |r_0|^2 of the
 // run, its = iterations of the run) and, around it, the FP64 refinement (F2 = |F|^2 of the right-
 // hand side, run = refinement step; done: the solve has converged; its_total = iterations of all
-// runs).  A run stops at
-// |r|^2 <= max(tol2 ff, tol2s F2); the solve at |F - L7 x|^2 <= tol2s F2.
+// runs).  A run stops at |r|^2 <= max(tol2 ff, tol2s F2); the solve at |F - L7 x|^2 <= tol2s F2.
 struct State3 {
   double ff, rr, rho[2], tol2, tol2s, F2;
   int its, breakdown, run, done, its_total;
@@ -53,9 +52,9 @@ struct FaceCG {
   double rr0[kMaxSys3], rho[2][kMaxSys3];
   int its[kMaxSys3], bad[kMaxSys3];
 };
-constexpr int kPFS = 256;       // partials per system of the face kernels (>= 64 and ceil(nf / 32)^2)
+constexpr int kPFS = 256;      // partials per system of the face kernels (>= 64 and ceil(nf / 16)^2)
 constexpr int kFaceMax = 255;  // largest face edge nf (n <= 256)
-constexpr int kFaceRows = 256; // kFaceMax rounded up to whole row groups of 16
+constexpr int kFaceRows = 256;  // kFaceMax rounded up to whole row groups of 16
 
 // multigrid and PCG kernels of the interior solve (see kernels_3d.hip for what each computes), in
 // the working precision R (float: inside FP64 refinement; double); rows: grid rows per block;

@@ -370,7 +370,8 @@ __global__ __launch_bounds__(kX3* kY3) void k3_ir(const double* __restrict__ F,
 // (lev[0] <= kCvcMax) held in LDS, the same smoothing, transfers and dense inverse on the
 // coarsest grid as the level kernels; f of the first level from fin, its result to uout.
 constexpr int kCvcThreads = 1024;
-constexpr int kCvcLds = 11600;  // doubles: u and f of 15, 7, 3 and 1 (padded)
+constexpr int kCvcLds = 11600;  // elements: u and f of 15, 7, 3 and 1 (padded)
+constexpr int kCvcDense = 729;  // dense coarsest inverses up to 3^3 unknowns are staged in LDS
 
 // Thread t of the workgroup takes the points (i, j, k) = (t % 16, (t / 16) % 16, t / 256 + 4 m)
 // + 1 of a level (every level it holds has at most 15 points a side).
@@ -389,6 +390,7 @@ __global__ __launch_bounds__(kCvcThreads) void k3_cvc(const R* __restrict__ fin,
                                                        const int* __restrict__ stop) {
   if (*stop) return;
   __shared__ R lds[kCvcLds];
+  __shared__ R tr[(kCvcMax + 2) * (kCvcMax + 2) * (kCvcMax + 2)];  // residual of a level
   const R sixth = R(1) / R(6);
   const int t = threadIdx.x;
   // level l: u at U[l], f at Fv[l] (the loops over levels are unrolled: static indices)
@@ -405,6 +407,13 @@ __global__ __launch_bounds__(kCvcThreads) void k3_cvc(const R* __restrict__ fin,
     tot += l < L.nl ? 2 * v : 0;
   }
   for (int q = t; q < tot; q += kCvcThreads) lds[q] = R(0);
+  // the dense inverse of the coarsest grid, staged in LDS when it is small (<= 27^2 entries)
+  __shared__ double sC[kCvcDense];
+  const int npc = ed[L.nl - 1] * ed[L.nl - 1] * ed[L.nl - 1];
+  const bool staged = npc * npc <= kCvcDense;
+  if (staged)
+    for (int q = t; q < npc * npc; q += kCvcThreads) sC[q] = cinv[q];
+  const double* C = staged ? sC : cinv;
   __syncthreads();
   {
     const int P = ed[0] + 2;
@@ -440,38 +449,47 @@ __global__ __launch_bounds__(kCvcThreads) void k3_cvc(const R* __restrict__ fin,
     });
     __syncthreads();
     for (int sw = 2; sw < 2 * nu; ++sw) half(u, f, nf, (sw & 1) ? 1 : 0);
+    // residual t = f - L7 u once per point, then the restriction from t
+    cvc_points(nf, [&](int i, int j, int k) {
+      const int o = (k * P + j) * P + i;
+      tr[o] = f[o] - (R(6) * u[o] - u[o - 1] - u[o + 1] - u[o - P] - u[o + P] - u[o - PP] -
+                      u[o + PP]);
+    });
+    __syncthreads();
     const int nc = ed[l + 1], Pc = nc + 2;
     R* fc = Fv[l + 1];
-    auto T = [&](int o) {
-      return f[o] - (R(6) * u[o] - u[o - 1] - u[o + 1] - u[o - P] - u[o + P] - u[o - PP] -
-                     u[o + PP]);
-    };
     cvc_points(nc, [&](int I, int J, int K) {
       const int o = ((2 * K) * P + 2 * J) * P + 2 * I;
       const int d1 = 1, d2 = P, d3 = PP;
-      const R s = T(o + d1) + T(o - d1) + T(o + d2) + T(o - d2) + T(o + d3) + T(o - d3) +
-                       T(o + d1 + d2) + T(o - d1 - d2) + T(o + d1 + d3) + T(o - d1 - d3) +
-                       T(o + d2 + d3) + T(o - d2 - d3) + T(o + d1 + d2 + d3) +
-                       T(o - d1 - d2 - d3);
-      fc[(K * Pc + J) * Pc + I] = R(0.5) * (T(o) + R(0.5) * s);
+      const R s = tr[o + d1] + tr[o - d1] + tr[o + d2] + tr[o - d2] + tr[o + d3] + tr[o - d3] +
+                  tr[o + d1 + d2] + tr[o - d1 - d2] + tr[o + d1 + d3] + tr[o - d1 - d3] +
+                  tr[o + d2 + d3] + tr[o - d2 - d3] + tr[o + d1 + d2 + d3] + tr[o - d1 - d2 - d3];
+      fc[(K * Pc + J) * Pc + I] = R(0.5) * (tr[o] + R(0.5) * s);
     });
     __syncthreads();
   }
-  // coarsest grid: dense inverse of L7 (unknowns in the order (k * nc + j) * nc + i, 0-based)
+  // coarsest grid: dense inverse of L7 (unknowns in the order (k * nc + j) * nc + i, 0-based);
+  // up to 32 unknowns, row r is a dot product over the lanes of a half wavefront
 #pragma unroll
   for (int l = 0; l < kCvcLevels; ++l) {
     if (l != L.nl - 1) continue;
     const int nc = ed[l], np = nc * nc * nc, Pc = nc + 2;
-    cvc_points(nc, [&](int i, int j, int k) {
-      const int row = ((k - 1) * nc + (j - 1)) * nc + (i - 1);
-      double a = 0.0;
-      for (int kk = 1; kk <= nc; ++kk)
-        for (int jj = 1; jj <= nc; ++jj)
-          for (int ii = 1; ii <= nc; ++ii)
-            a += cinv[row * np + ((kk - 1) * nc + (jj - 1)) * nc + (ii - 1)] *
-                 Fv[l][(kk * Pc + jj) * Pc + ii];
-      U[l][(k * Pc + j) * Pc + i] = (R)a;
-    });
+    auto pad = [&](int q) {
+      return (((q / (nc * nc)) + 1) * Pc + (q / nc) % nc + 1) * Pc + q % nc + 1;
+    };
+    if (np <= 32) {
+      const int r = 2 * (t >> 6) + ((t >> 5) & 1), c = t & 31;
+      double v = (r < np && c < np) ? C[r * np + c] * (double)Fv[l][pad(c)] : 0.0;
+      for (int o = 16; o > 0; o >>= 1) v += __shfl_down(v, o, 32);
+      if (r < np && c == 0) U[l][pad(r)] = (R)v;
+    } else {
+      cvc_points(nc, [&](int i, int j, int k) {
+        const int row = ((k - 1) * nc + (j - 1)) * nc + (i - 1);
+        double a = 0.0;
+        for (int q = 0; q < np; ++q) a += C[row * np + q] * (double)Fv[l][pad(q)];
+        U[l][(k * Pc + j) * Pc + i] = (R)a;
+      });
+    }
   }
   __syncthreads();
 #pragma unroll
