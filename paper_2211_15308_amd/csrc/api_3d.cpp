@@ -98,6 +98,7 @@ struct Problem3D {
   int maxit = 0, nu = 1;
   int steps = 0;       // refinement steps enqueued after the first
   int runs_pred = 2;   // FP32 runs of the last refined solve
+  int run_pred[kRuns3] = {8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 8};  // its iterations per run
   // one face-CG iteration k per (batch, parity of k); iterations of the last batch of each kind
   Chunks g_face[2];
   int g_face_m[2] = {0, 0};
@@ -387,10 +388,12 @@ int interior_start(fdd_problem_s* P, hipStream_t s, const Rhs3& rhs, double tol,
   Q->steps = 0;
   k3_launch_ir(s, 1, Q->F64, nullptr, nullptr, nullptr, Q->m32.Rv[0], nf, Q->rows0, Q->st,
                Q->part0);
-  const int per = std::min(std::max(Q->m32.pred, 1), maxit);
-  int rc = run_start<float>(Q, Q->m32, s, true, per);
+  // each run gets one iteration more than it took in the last solve, so that a run is rarely
+  // cut short by the next step (which stays correct, but makes the iterates depend on history)
+  auto budget = [&](int r) { return std::min(Q->run_pred[std::min(r, kRuns3 - 1)] + 1, maxit); };
+  int rc = run_start<float>(Q, Q->m32, s, true, budget(0));
   // the further runs the last solve took, then the step expected to end the solve
-  for (int r = 1; r < Q->runs_pred && !rc; ++r) rc = refine_step(Q, s, per);
+  for (int r = 1; r < Q->runs_pred && !rc; ++r) rc = refine_step(Q, s, budget(r));
   if (!rc) rc = refine_step(Q, s, 0);
   return rc;
 }
@@ -412,7 +415,8 @@ int interior_finish(fdd_problem_s* P, hipStream_t s, int* its) {
     if (*Q->hstop) {
       // the last run stopped short of the solve's tolerance: one more refinement step
       if (Q->steps >= kMaxRefine) break;
-      rc = refine_step(Q, s, std::min(std::max(Q->m32.pred, 1), Q->maxit - h.its_total));
+      rc = refine_step(Q, s, std::min(Q->run_pred[std::min(Q->steps + 1, kRuns3 - 1)] + 1,
+                                      Q->maxit - h.its_total));
       if (rc) return rc;
       continue;
     }
@@ -429,10 +433,9 @@ int interior_finish(fdd_problem_s* P, hipStream_t s, int* its) {
   const State3& h = *Q->hst;
   if (Q->mixed) {
     // runs that iterated: every refinement step but the one that ended the solve
-    const int runs = std::max(h.run + (done ? 0 : 1), 1);
     if (done && h.its_total > 0) {
-      Q->runs_pred = runs;
-      Q->m32.pred = (h.its_total + runs - 1) / runs;
+      Q->runs_pred = std::max(std::min(h.run, kRuns3), 1);
+      for (int r = 0; r < Q->runs_pred; ++r) Q->run_pred[r] = std::max(h.run_its[r], 1);
     }
   } else if (done && h.its > 0) {
     Q->m64.pred = h.its;

@@ -22,9 +22,11 @@ struct Rhs3 {
 // run, its = iterations of the run) and, around it, the FP64 refinement (F2 = |F|^2 of the right-
 // hand side, run = refinement step; done: the solve has converged; its_total = iterations of all
 // runs).  A run stops at |r|^2 <= max(tol2 ff, tol2s F2); the solve at |F - L7 x|^2 <= tol2s F2.
+constexpr int kRuns3 = 12;  // refinement steps of one interior solve at most
 struct State3 {
   double ff, rr, rho[2], tol2, tol2s, F2;
   int its, breakdown, run, done, its_total;
+  int run_its[kRuns3];  // iterations of each run (recorded when the next step starts)
 };
 
 // levels of the one-workgroup coarse V-cycle (padded grids of edge lev + 2 in LDS)

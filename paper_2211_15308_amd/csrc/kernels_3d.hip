@@ -346,7 +346,10 @@ __global__ __launch_bounds__(kX3* kY3) void k3_ir(const double* __restrict__ F,
                                                    double* __restrict__ xout,
                                                    float* __restrict__ r32, int nf, int rows,
                                                    State3* st, double* __restrict__ part) {
-  if (!FIRST && lead3()) st->run += 1;
+  if (!FIRST && lead3()) {
+    if (st->run < kRuns3) st->run_its[st->run] = st->its;
+    st->run += 1;
+  }
   const int P = nf + 2, PP = P * P;
   auto X = [&](int o) { return xin[o] + (double)e[o]; };
   double acc = 0.0;

@@ -177,3 +177,29 @@ def test_solve_3d_n64_true_residual():
     print(f"[3d solve] n={n}: outer {st['outer_its']} inner {st['inner_its_total']} true res "
           f"{st['true_rel_res']:.2e} {st['t_solve_ms']:.1f} ms", flush=True)
     assert st["true_rel_res"] <= 1e-7
+
+
+@pytest.mark.parametrize("precision", [F.FDD_MIXED, F.FDD_FP64])
+def test_solve_3d_graph_replay_matches_eager_launches(precision):
+    # the captured iteration chunks and the eager launches run the same kernels in the same
+    # order: identical iterates, bit for bit, when every run ends on its own test (FP64: one run
+    # per interior solve).  Mixed precision enqueues the next refinement step after as many
+    # iterations as the previous solve's run took plus one, so a run can be cut short by it
+    # (still converging to the tolerance): there the solutions agree to the tolerance.
+    n, K, mu = 16, 1.0, 1e-2
+    print(f"[3d graph vs eager] n={n} precision={precision}", flush=True)
+    P = make3(n, K, mu)
+    TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+    TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+    b = dev(workloads.rhs(3, n, 3200))
+    xs, sts = [], []
+    for use_graph in (1, 0, 1):
+        x = torch.zeros_like(b)
+        sts.append(P.solve(TP, TH, b, x, F.opts_default(precision=precision, use_graph=use_graph)))
+        xs.append(host(x))
+    assert sts[0]["outer_its"] == sts[1]["outer_its"] == sts[2]["outer_its"]
+    if precision == F.FDD_FP64:
+        assert sts[0]["inner_its_total"] == sts[1]["inner_its_total"] == sts[2]["inner_its_total"]
+        assert np.array_equal(xs[0], xs[1]) and np.array_equal(xs[0], xs[2])
+    else:
+        assert rel(xs[1], xs[0]) <= 1e-9 and rel(xs[2], xs[0]) <= 1e-9
