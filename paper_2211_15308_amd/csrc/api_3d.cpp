@@ -35,7 +35,8 @@ struct Chunks {
 
 // buffers of one face batch (device, except the pinned read-back mirrors)
 struct FaceBufs {
-  double *r = nullptr, *y = nullptr, *z = nullptr, *q = nullptr, *t = nullptr, *tmp = nullptr;
+  double *y = nullptr, *z = nullptr, *q = nullptr, *t = nullptr, *tmp = nullptr;
+  double* r[2] = {};  // r_k in r[k & 1]
   double* p[2] = {};  // p_k in p[k & 1]
   double *part0 = nullptr, *part1 = nullptr;
   FaceCG* cg = nullptr;
@@ -163,7 +164,7 @@ size_t plan3(fdd_problem_s* P, char* base) {
     B.done = (int*)take(sizeof(int) * kMaxSys3);
     B.part0 = (double*)take(8 * (size_t)kMaxSys3 * kPFS);
     B.part1 = (double*)take(8 * (size_t)kMaxSys3 * kPFS);
-    for (double** v : {&B.y, &B.r, &B.p[0], &B.p[1], &B.q, &B.z, &B.t})
+    for (double** v : {&B.y, &B.r[0], &B.r[1], &B.p[0], &B.p[1], &B.q, &B.z, &B.t})
       *v = (double*)take(8 * ng * kMaxSys3);
     B.tmp = (double*)take(8 * ng);
   }
@@ -492,9 +493,8 @@ void face_iteration(Problem3D* Q, FaceBufs& B, hipStream_t s, const Shift3* tab,
   const double h = 1.0 / Q->n;
   kf_launch_apply1(s, B.z, B.p[(k + 1) & 1], B.p[k & 1], B.q, nf, h, m, tab, B.cg, B.part0,
                    kf_tiles(nf), B.part1, B.done);
-  kf_launch_axpy1(s, B.y, B.r, B.p[k & 1], B.q, nf, m, B.cg, B.part1, B.part0, B.done);
-  kf_launch_prec(s, Q->S, B.r, B.t, B.z, nf, Q->n, h, m, tab, B.cg, B.part0, tol2, 2, B.part0,
-                 B.done);
+  kf_launch_face_update_prec(s, Q->S, B.r[k & 1], B.r[(k + 1) & 1], B.q, B.p[k & 1], B.y, B.t,
+                             B.z, nf, Q->n, h, m, tab, B.cg, B.part1, tol2, B.part0, B.done);
 }
 
 // out = preconditioner (which 0) or H_RA (which 1) applied to `in` (face vectors).  The
@@ -531,8 +531,8 @@ int face_start(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* T, const doub
   }
   HIPCHK(hipMemsetAsync(B.done, 0, sizeof(int) * kMaxSys3, s));
   HIPCHK(hipMemsetAsync(B.cg, 0, sizeof(FaceCG), s));
-  kf_launch_start(s, in, B.r, B.y, nf, h, m, which, B.part0);
-  kf_launch_prec(s, Q->S, B.r, B.t, B.z, nf, Q->n, h, m, tab, B.cg, B.part0, tol2, 1, B.part0,
+  kf_launch_start(s, in, B.r[0], B.y, nf, h, m, which, B.part0);
+  kf_launch_prec(s, Q->S, B.r[0], B.t, B.z, nf, Q->n, h, m, tab, B.cg, B.part0, tol2, 1, B.part0,
                  B.done);
   B.enq = std::max(Q->pred_face[which] - 1, 1);
   int rc = enqueue_iterations(s, Q->use_graph, Q->g_face[which], it, 0, B.enq);

@@ -94,8 +94,12 @@ void kf_launch_start(hipStream_t s, const double* src, double* r, double* y, int
 void kf_launch_apply1(hipStream_t s, const double* z, const double* pold, double* pnew, double* q,
                       int nf, double h, int m, const Shift3* tab, FaceCG* cg, const double* pin,
                       int cnt, double* part, int* done);
-void kf_launch_axpy1(hipStream_t s, double* y, double* r, const double* p, const double* q, int nf,
-                     int m, FaceCG* cg, const double* pin, double* part, int* done);
+// the rest of a face-CG iteration after kf_launch_apply1: y += alpha p, r' = r - alpha q (pq: the
+// p . q partials), the convergence test, z = preconditioner(r'), r' . z partials to part
+void kf_launch_face_update_prec(hipStream_t s, const double* S, const double* r, double* rnew,
+                                const double* q, const double* p, double* y, double* ft, double* z,
+                                int nf, int n, double h, int m, const Shift3* tab, FaceCG* cg,
+                                const double* pq, double tol2, double* part, int* done);
 void kf_launch_prec(hipStream_t s, const double* S, const double* r, double* ft, double* z, int nf,
                     int n, double h, int m, const Shift3* tab, FaceCG* cg, const double* pin,
                     double tol2, int check, double* part, int* done);

@@ -557,12 +557,14 @@ __global__ __launch_bounds__(kB3) void k3_gather(const double* __restrict__ u, i
 // ---- batched face CG ------------------------------------------------------------------------
 // System s of a batch solves (alpha_s A_G + beta_s M_G) y_s = r_s by PCG with the preconditioner
 // S D_s^{-1} S (S the orthonormal DST-I matrix, D_s the part of the operator diagonal in the
-// sine basis).  One iteration is six passes: kf_apply1 (p, q = B_s p), kf_axpy1 (y, r),
-// then the preconditioner as four DST passes, the first of which takes the convergence test and
-// the last of which leaves the partials of r . z.  The scalars are summed by the pass that
-// uses them (every block of a system sums the same partials; block 0 records them), and a
-// system whose test is met is skipped by every later pass.  Partials of system s are at
-// part[s * kPFS + b].
+// sine basis).  An iteration is kf_apply1 (p, q = B_s p), the update y += alpha p,
+// r' = r - alpha q (r in two buffers by the parity of the iteration), the convergence test and
+// the preconditioner, whose last pass leaves the partials of r' . z.  When nf = 2^K - 1 that is
+// three passes (kf_dst2u: update and transform along x; kf_cr: test and tridiagonal solves
+// along y; kf_dst2: inverse transform), else kf_axpy1 and four DST passes (the first takes the
+// test).  The scalars are summed by the pass that uses them (every block of a system sums the
+// same partials; block 0 records them), and a system whose test is met is skipped by every
+// later pass.  Partials of system s are at part[s * kPFS + b].
 
 __device__ __forceinline__ double sys_sum(const double* __restrict__ part, int s, int cnt) {
   __shared__ double sh;
@@ -655,8 +657,10 @@ __global__ __launch_bounds__(kB3) void kf_apply1(const double* __restrict__ z,
   if (threadIdx.x == 0) part[(size_t)s * kPFS + blockIdx.x] = acc;
 }
 
-// alpha_k = rho_k / (p_k . q) (kPartF partials), y += alpha_k p_k, r -= alpha_k q, partials of |r|^2
-__global__ __launch_bounds__(kB3) void kf_axpy1(double* __restrict__ y, double* __restrict__ r,
+// alpha_k = rho_k / (p_k . q) (kPartF partials), y += alpha_k p_k, r' = r - alpha_k q, partials of
+// |r'|^2
+__global__ __launch_bounds__(kB3) void kf_axpy1(double* __restrict__ y, const double* __restrict__ r,
+                                               double* __restrict__ rnew,
                                                const double* __restrict__ p,
                                                const double* __restrict__ qv, int nf,
                                                FaceCG* __restrict__ cg,
@@ -680,11 +684,69 @@ __global__ __launch_bounds__(kB3) void kf_axpy1(double* __restrict__ y, double* 
   for (int64_t t = blockIdx.x * (int64_t)kB3 + threadIdx.x; t < N; t += (int64_t)gridDim.x * kB3) {
     y[off + t] += al * p[off + t];
     const double rv = r[off + t] - al * qv[off + t];
-    r[off + t] = rv;
+    rnew[off + t] = rv;
     acc += rv * rv;
   }
   acc = block_sum3(acc);
   if (threadIdx.x == 0) part[(size_t)s * kPFS + blockIdx.x] = acc;
+}
+
+// The update of kf_axpy1 fused into the sine transform along x that starts the preconditioner
+// (cyclic-reduction path): W = r' S with r' = r - alpha_k q formed while the row panels of r are
+// loaded.  The blocks of the first column tile load every column of their 16-row band, so they
+// store r', update y += alpha_k p_k and leave the band's |r'|^2 partial (ceil(nf / 16) per
+// system); the convergence test follows in kf_cr.
+__global__ __launch_bounds__(256) void kf_dst2u(const double* __restrict__ S,
+                                               const double* __restrict__ r,
+                                               const double* __restrict__ qv,
+                                               const double* __restrict__ p,
+                                               double* __restrict__ rnew, double* __restrict__ y,
+                                               double* __restrict__ W, int nf,
+                                               FaceCG* __restrict__ cg,
+                                               const double* __restrict__ pin,
+                                               double* __restrict__ part,
+                                               int* __restrict__ done) {
+  const int s = blockIdx.z;
+  if (done[s]) return;
+  const double pq = sys_sum(pin, s, kPartF);
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+      cg->bad[s] = 1;
+      done[s] = 1;
+    }
+    return;
+  }
+  const double al = cg->rho[cg->its[s] & 1][s] / pq;
+  const size_t off = (size_t)s * nf * nf;
+  const bool writer = blockIdx.x == 0;
+  __shared__ double ta[16][17], tb[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int col = blockIdx.x * 16 + tx, row = blockIdx.y * 16 + ty;
+  double acc = 0.0, rr = 0.0;
+  for (int k0 = 0; k0 < nf; k0 += 16) {
+    const int ka = k0 + tx, kb = k0 + ty;
+    double v = 0.0;
+    if (row < nf && ka < nf) {
+      const size_t o = off + (size_t)row * nf + ka;
+      v = r[o] - al * qv[o];
+      if (writer) {
+        y[o] += al * p[o];
+        rnew[o] = v;
+        rr += v * v;
+      }
+    }
+    ta[ty][tx] = v;
+    tb[ty][tx] = (kb < nf && col < nf) ? S[(size_t)kb * nf + col] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += ta[ty][k] * tb[k][tx];
+    __syncthreads();
+  }
+  if (row < nf && col < nf) W[off + (size_t)row * nf + col] = acc;
+  if (writer) {
+    rr = block_sum3(rr);
+    if (threadIdx.x == 0) part[(size_t)s * kPFS + blockIdx.y] = rr;
+  }
 }
 
 // C_s = S B_s (LEFT) or B_s S, S the symmetric DST matrix (nf x nf); 16 x 16 output tiles,
@@ -919,17 +981,17 @@ __global__ __launch_bounds__(kB3) void kf_vdot(const double* __restrict__ a,
 // transform along y is the spectral scaling of kf_dst2 (EPI 1), so the three passes apply the
 // same preconditioner as the four.  With 2^K - 1 rows, cyclic reduction keeps one (d, e) pair
 // per level: d' = d - 2 e^2 / d, e' = -e^2 / d (diagonal dominance is kept).  A block takes a
-// panel of 16 columns of one system, held in LDS.  CHECK as in kf_dst2.
+// panel of 16 columns of one system, held in LDS.  CHECK as in kf_dst2, on cnt partials.
 template <int CHECK>
 __global__ __launch_bounds__(256) void kf_cr(double* __restrict__ w, int nf, int K, int n,
                                             double h, const Shift3* __restrict__ tab,
                                             FaceCG* __restrict__ cg,
-                                            const double* __restrict__ pin, double tol2,
+                                            const double* __restrict__ pin, int cnt, double tol2,
                                             int* __restrict__ done) {
   const int s = blockIdx.y;
   if (done[s]) return;
   if constexpr (CHECK != 0) {
-    const double a = sys_sum(pin, s, kPartF);
+    const double a = sys_sum(pin, s, cnt);
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     const bool bad = !isfinite(a);
     bool halt;
@@ -1117,11 +1179,7 @@ void kf_launch_apply1(hipStream_t s, const double* z, const double* pold, double
   hipLaunchKernelGGL(kf_apply1, dim3(kPartF, m), dim3(kB3), 0, s, z, pold, pnew, q, nf, h, tab, cg,
                      pin, cnt, part, done);
 }
-void kf_launch_axpy1(hipStream_t s, double* y, double* r, const double* p, const double* q, int nf,
-                     int m, FaceCG* cg, const double* pin, double* part, int* done) {
-  hipLaunchKernelGGL(kf_axpy1, dim3(kPartF, m), dim3(kB3), 0, s, y, r, p, q, nf, cg, pin, part,
-                     done);
-}
+
 int kf_tiles(int nf) { return ((nf + 15) / 16) * ((nf + 15) / 16); }
 int kf_cr_levels(int nf) {
   for (int K = 1; K <= 8; ++K)
@@ -1142,7 +1200,7 @@ void kf_launch_prec(hipStream_t s, const double* S, const double* r, double* ft,
     else
       hipLaunchKernelGGL((kf_dst2<false, 2, 0>), g, dim3(256), 0, s, S, r, ft, nf, n, h, tab, cg,
                          pin, tol2, nullptr, nullptr, done);
-    hipLaunchKernelGGL(kf_cr<0>, gp, dim3(256), 0, s, ft, nf, K, n, h, tab, cg, nullptr, tol2,
+    hipLaunchKernelGGL(kf_cr<0>, gp, dim3(256), 0, s, ft, nf, K, n, h, tab, cg, nullptr, 0, tol2,
                        done);
     hipLaunchKernelGGL((kf_dst2<false, 0, 2>), g, dim3(256), 0, s, S, ft, z, nf, n, h, tab, cg,
                        nullptr, tol2, r, part, done);
@@ -1160,6 +1218,26 @@ void kf_launch_prec(hipStream_t s, const double* S, const double* r, double* ft,
                      nullptr, tol2, nullptr, nullptr, done);
   hipLaunchKernelGGL((kf_dst2<false, 0, 2>), g, dim3(256), 0, s, S, ft, z, nf, n, h, tab, cg,
                      nullptr, tol2, r, part, done);
+}
+void kf_launch_face_update_prec(hipStream_t s, const double* S, const double* r, double* rnew,
+                                const double* q, const double* p, double* y, double* ft, double* z,
+                                int nf, int n, double h, int m, const Shift3* tab, FaceCG* cg,
+                                const double* pq, double tol2, double* part, int* done) {
+  const int K = kf_cr_levels(nf);
+  if (K >= 2 && nf <= kFaceMax) {
+    // update fused into the x transform; test in the cyclic reduction; inverse x transform
+    const dim3 g((nf + 15) / 16, (nf + 15) / 16, m), gp((nf + 15) / 16, m);
+    hipLaunchKernelGGL(kf_dst2u, g, dim3(256), 0, s, S, r, q, p, rnew, y, ft, nf, cg, pq, part,
+                       done);
+    hipLaunchKernelGGL(kf_cr<2>, gp, dim3(256), 0, s, ft, nf, K, n, h, tab, cg, part,
+                       (nf + 15) / 16, tol2, done);
+    hipLaunchKernelGGL((kf_dst2<false, 0, 2>), g, dim3(256), 0, s, S, ft, z, nf, n, h, tab, cg,
+                       nullptr, tol2, rnew, part, done);
+    return;
+  }
+  hipLaunchKernelGGL(kf_axpy1, dim3(kPartF, m), dim3(kB3), 0, s, y, r, rnew, p, q, nf, cg, pq,
+                     part, done);
+  kf_launch_prec(s, S, rnew, ft, z, nf, n, h, m, tab, cg, part, tol2, 2, part, done);
 }
 void kf_launch_combine(hipStream_t s, const double* ys, int m, int nf, double h, const Shift3* tab,
                        int op, const double* x, double* tmp, double* out, double d0) {
