@@ -266,24 +266,26 @@ static inline dim3 tb() { return dim3(32, kBlock / 32); }
 
 template <int NU>
 static void b_tail(const BatchCtx& c, int check) {
-  for (int l = 1; l < c.max_tiled; ++l)
-    if (c.tiles_total[l] > 0)
-      if (c.tile_edge[l] == kMidTile)
-        hipLaunchKernelGGL((kb_mg_down<NU, false, kMidTile>), dim3(c.tiles_total[l]), tb(), 0,
-                           c.stream, c.inst, c.lists, l, 0, 0, 0, check, c.skip_done);
-      else
-        hipLaunchKernelGGL((kb_mg_down<NU, false, kTile>), dim3(c.tiles_total[l]), tb(), 0,
-                           c.stream, c.inst, c.lists, l, 0, 0, 0, check, c.skip_done);
+  for (int l = 1; l < c.max_tiled; ++l) {
+    if (c.tiles_total[l] == 0) continue;
+    if (c.tile_edge[l] == kMidTile)
+      hipLaunchKernelGGL((kb_mg_down<NU, false, kMidTile>), dim3(c.tiles_total[l]), tb(), 0,
+                         c.stream, c.inst, c.lists, l, 0, 0, 0, check, c.skip_done);
+    else
+      hipLaunchKernelGGL((kb_mg_down<NU, false, kTile>), dim3(c.tiles_total[l]), tb(), 0,
+                         c.stream, c.inst, c.lists, l, 0, 0, 0, check, c.skip_done);
+  }
   launch_timed(c.hook, kTimeCoarse, kb_coarse, dim3(c.lists.ninst), dim3(kCoarseThreads),
                c.stream, c.inst, check, c.skip_done);
-  for (int l = c.max_tiled - 1; l >= 1; --l)
-    if (c.tiles_total[l] > 0)
-      if (c.tile_edge[l] == kMidTile)
-        hipLaunchKernelGGL((kb_mg_up<NU, false, kMidTile>), dim3(c.tiles_total[l]), tb(), 0,
-                           c.stream, c.inst, c.lists, l, 0, 0, 0, c.skip_done);
-      else
-        hipLaunchKernelGGL((kb_mg_up<NU, false, kTile>), dim3(c.tiles_total[l]), tb(), 0,
-                           c.stream, c.inst, c.lists, l, 0, 0, 0, c.skip_done);
+  for (int l = c.max_tiled - 1; l >= 1; --l) {
+    if (c.tiles_total[l] == 0) continue;
+    if (c.tile_edge[l] == kMidTile)
+      hipLaunchKernelGGL((kb_mg_up<NU, false, kMidTile>), dim3(c.tiles_total[l]), tb(), 0,
+                         c.stream, c.inst, c.lists, l, 0, 0, 0, c.skip_done);
+    else
+      hipLaunchKernelGGL((kb_mg_up<NU, false, kTile>), dim3(c.tiles_total[l]), tb(), 0,
+                         c.stream, c.inst, c.lists, l, 0, 0, 0, c.skip_done);
+  }
 }
 
 template <int NU>

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_cnn_features(const double* __restrict__
   red[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
   const double rms = sqrt(red[0] / m);
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256) void k_cnn_mse(const float* __restrict__ out,
   red[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
   if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
