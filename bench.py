@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D cases")
     ap.add_argument("--cnn-only", action="store_true", help="only time the warm-start network kernels")
     ap.add_argument("--only-3d", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="the 2D parameter sweep: n in {128, ..., 2048} x K x mu, per-case counts, "
+                         "solves/s and error against the oracle")
     ap.add_argument("--only-batched", action="store_true",
                     help="skip the headline single-problem run (for profiling the batched kernels)")
     return ap.parse_args()
@@ -121,6 +124,27 @@ def kernel_source_sha(root):
     return h.hexdigest()
 
 
+class OracleLeg:
+    """The benchmark's use of the oracle, in one place after the GPU legs: the CPU baseline (timed
+    by cpu_baseline) and the parity spot-checks of GPU solutions.  The GPU legs only copy the
+    right-hand side and solution to the host and name the slot (a dict key or list index of the
+    output) that receives the relative error; run() fills the slots."""
+
+    def __init__(self):
+        self.items = []
+
+    def check(self, slot, key, n, K, mu, b, x):
+        self.items.append((slot, key, n, K, mu, b.detach().cpu().numpy(), x.detach().cpu().numpy()))
+
+    def run(self):
+        import numpy as np
+        from oracle import system
+        for slot, key, n, K, mu, b, x in self.items:
+            xr = system.solve_dst_2d(n, K, mu, b)
+            slot[key] = float(np.linalg.norm(x - xr) / np.linalg.norm(xr))
+        self.items = []
+
+
 def setup_instances(F, cases, tol_p, max_p, tol_h, threads=8):
     """Problems and rational tables of a batch (host work, run on a thread pool), workspaces bound."""
     from concurrent.futures import ThreadPoolExecutor
@@ -138,14 +162,13 @@ def setup_instances(F, cases, tol_p, max_p, tol_h, threads=8):
     return out
 
 
-def run_batched(F, args, label, cases, tol_p, max_p):
+def run_batched(F, args, label, cases, tol_p, max_p, leg):
     """Instance solves/s of one batch; roofline of the batched finest-level down kernel."""
     import numpy as np
     import torch
 
     import workloads
     import paper_2211_15308_amd.fdd as FF
-    from oracle import system
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     inst = setup_instances(F, cases, tol_p, max_p, 1e-12)
@@ -182,11 +205,10 @@ def run_batched(F, args, label, cases, tol_p, max_p):
         # run's tolerance; the first update of a run (k = 0) reads no p' and x
         alg += ni * (DOWN0_BYTES_K * its + DOWN0_BYTES_K0 * runs)
     achieved = alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    errs = []
-    for i in range(min(3, len(cases))):
+    errs = [None] * min(3, len(cases))
+    for i in range(len(errs)):
         c = cases[i]
-        xr = system.solve_dst_2d(c["n"], c["K"], c["mu"], bs[i].cpu().numpy())
-        errs.append(float(np.linalg.norm(xs[i].cpu().numpy() - xr) / np.linalg.norm(xr)))
+        leg.check(errs, i, c["n"], c["K"], c["mu"], bs[i], xs[i])
     outer = [s_["outer_its"] for s_ in st]
     return {
         "label": label, "value": value, "unit": "instance solves/s", "instances": len(cases),
@@ -249,14 +271,12 @@ def cnn_timing(F, theta, reps=10):
     return out
 
 
-def run_learned(F, args, sizes=(256, 512, 1024), mus=(1e-3, 1.0)):
+def run_learned(F, args, leg, sizes=(256, 512, 1024), mus=(1e-3, 1.0)):
     """Plain zero-guess vs learned-warm-start solves at K = 1 (same rtol): solves/s, inner its."""
-    import numpy as np
     import torch
 
     import workloads
     from paper_2211_15308_amd import train_warmstart
-    from oracle import system
     path = args.weights or train_warmstart.DEFAULT_OUT
     if not os.path.exists(path):
         return {"skipped": f"no trained weights at {os.path.relpath(path, ROOT)}"}
@@ -288,13 +308,48 @@ def run_learned(F, args, sizes=(256, 512, 1024), mus=(1e-3, 1.0)):
                     st = P.solve(TP, TH, b, x, opts)
                 torch.cuda.synchronize()
                 el = time.perf_counter() - t0
-                xr = system.solve_dst_2d(n, 1.0, mu, b.cpu().numpy())
                 row[label] = {"solves_per_s": args.learned_steps / el, "outer_its": st["outer_its"],
                               "inner_its": st["inner_its_total"], "warm_accepted": st["warm_accepted"],
-                              "warm_starts": st["warm_starts"],
-                              "rel_err_vs_oracle": float(np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr))}
+                              "warm_starts": st["warm_starts"], "rel_err_vs_oracle": None}
+                leg.check(row[label], "rel_err_vs_oracle", n, 1.0, mu, b, x)
             res["cases"].append(row)
     return res
+
+
+def run_sweep(F, args, leg, sizes=(128, 256, 512, 1024, 2048)):
+    """2D sweep n x K in {1, 1e-2, 1e-4} x mu in {1e-6, 1e-3, 1, 1e3} (seed 1000 + index): outer and
+    inner iterations, solves/s (one warm-up and two timed solves) and the error of the solution."""
+    import torch
+
+    import workloads
+    out = []
+    idx = 0
+    for n in sizes:
+        for K in (1.0, 1e-2, 1e-4):
+            for mu in (1e-6, 1e-3, 1.0, 1e3):
+                P = F.setup_mesh(n, K, mu)
+                P.bind_workspace()
+                TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+                TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+                b = torch.as_tensor(workloads.rhs(2, n, 1000 + idx), dtype=torch.float64, device="cuda")
+                x = torch.zeros_like(b)
+                opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, mg_nu=args.nu)
+                P.solve(TP, TH, b, x, opts)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(2):
+                    st = P.solve(TP, TH, b, x, opts)
+                torch.cuda.synchronize()
+                el = (time.perf_counter() - t0) / 2
+                row = {"n": n, "K": K, "mu": mu, "solves_per_s": 1.0 / el, "outer_its": st["outer_its"],
+                       "inner_its": st["inner_its_total"], "poles_P": TP.query()["m"],
+                       "poles_H": TH.query()["m"], "rel_err_vs_oracle": None}
+                leg.check(row, "rel_err_vs_oracle", n, K, mu, b, x)
+                out.append(row)
+                print(f"[sweep] n={n} K={K:g} mu={mu:g}: {row['solves_per_s']:.1f} solves/s, "
+                      f"outer {row['outer_its']}, inner {row['inner_its']}", file=sys.stderr, flush=True)
+                idx += 1
+    return out
 
 
 def run_3d(F, args, sizes=(32, 64, 128), mus=(1e-4, 1.0, 1e2), reps=2):
@@ -356,17 +411,29 @@ def main():
     if args.only_3d:
         print(json.dumps({"three_d": run_3d(F, args)}))
         return
+    if args.sweep:
+        leg = OracleLeg()
+        res = run_sweep(F, args, leg)
+        leg.run()
+        print(json.dumps({"sweep": res}))
+        return
     if args.learned == "only":
-        print(json.dumps({"learned": run_learned(F, args)}))
+        leg = OracleLeg()
+        res = run_learned(F, args, leg)
+        leg.run()
+        print(json.dumps({"learned": res}))
         return
     if args.only_batched:
         res = {}
+        leg = OracleLeg()
         if args.batched in ("all", "1024"):
             res["batched_1024"] = run_batched(F, args, "32 instances, n=1024",
-                                              workloads.batch_instances(count=32, seed=4, sizes=[1024]), 1e-12, 64)
+                                              workloads.batch_instances(count=32, seed=4, sizes=[1024]), 1e-12, 64,
+                                              leg)
         if args.batched in ("all", "c4"):
             res["c4"] = run_batched(F, args, "256 instances, n in {64,...,512}",
-                                    workloads.batch_instances(count=256, seed=4), 1e-8, 20)
+                                    workloads.batch_instances(count=256, seed=4), 1e-8, 20, leg)
+        leg.run()
         print(json.dumps(res))
         return
     if args.pmc_mode:
@@ -440,21 +507,20 @@ def main():
                 "avg_working_launch_us": 1e3 * long_ms / max(long_n, 1),
                 "alg_bytes_per_working_launch": alg_bytes / max(its + runs, 1)}
     # parity spot-check of one solve of the first cases against the separable oracle
-    from oracle import system
-    errs = []
-    for ci, (P, TP, TH, b, x, K, mu) in enumerate(probs):
-        if ci >= 3:
-            break
+    leg = OracleLeg()
+    errs = [None] * min(3, len(probs))
+    for ci in range(len(errs)):
+        P, TP, TH, b, x, K, mu = probs[ci]
         P.solve(TP, TH, b, x, opts)
-        xr = system.solve_dst_2d(args.n, K, mu, b.cpu().numpy())
-        errs.append(float(np.linalg.norm(x.cpu().numpy() - xr) / np.linalg.norm(xr)))
+        leg.check(errs, ci, args.n, K, mu, b, x)
     batched = {}
     if args.batched in ("all", "1024"):
         batched["batched_1024"] = run_batched(F, args, "32 instances, n=1024",
-                                              workloads.batch_instances(count=32, seed=4, sizes=[1024]), 1e-12, 64)
+                                              workloads.batch_instances(count=32, seed=4, sizes=[1024]), 1e-12, 64,
+                                              leg)
     if args.batched in ("all", "c4"):
         batched["c4"] = run_batched(F, args, "256 instances, n in {64,...,512}",
-                                    workloads.batch_instances(count=256, seed=4), 1e-8, 20)
+                                    workloads.batch_instances(count=256, seed=4), 1e-8, 20, leg)
     out = {
         "metric": "Schur-PCG solves/s, 2D 1024^2 P1 @1e-8 (plain)",
         "value": value,
@@ -476,13 +542,17 @@ def main():
         "inner_its": [s["inner"] for s in stats[: len(case_list)]],
         "rel_err_vs_oracle": errs,
         "roofline": roofline,
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(args, case_list),
+        "cpu_baseline": None,
     }
     out.update(batched)
     if args.learned == "auto":
-        out["learned"] = run_learned(F, args)
+        out["learned"] = run_learned(F, args, leg)
     if not args.no_3d:
         out["three_d"] = run_3d(F, args)
+    # the oracle leg, after every GPU measurement: parity spot-checks and the CPU baseline
+    leg.run()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, case_list)
     print(json.dumps(out))
 
 
