@@ -92,8 +92,17 @@ __device__ __forceinline__ void d_iface_combine(
     double rtol2) {
   __shared__ double sd[kIfaceMaxN];
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    // the systems' terms are summed in system order; their loads are issued eight at a time
     double v = 0.0;
-    for (int kk = 0; kk < m; ++kk) v += scratch[(size_t)kk * n + i];
+    int kk = 0;
+    for (; kk + 8 <= m; kk += 8) {
+      double t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = scratch[(size_t)(kk + q) * n + i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v += t[q];
+    }
+    for (; kk < m; ++kk) v += scratch[(size_t)kk * n + i];
     sd[i] = v;
   }
   __syncthreads();
