@@ -833,8 +833,17 @@ __global__ __launch_bounds__(kB3) void kf_combine(const double* __restrict__ ys,
                                                  double* __restrict__ out) {
   const int64_t N = (int64_t)nf * nf;
   for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
+    // summed in system order; the loads are issued eight at a time
     double v = 0.0;
-    for (int s = 0; s < m; ++s) v += tab->coef[s] * ys[(size_t)s * N + q];
+    int s = 0;
+    for (; s + 8 <= m; s += 8) {
+      double t[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) t[k] = ys[(size_t)(s + k) * N + q];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v += tab->coef[s + k] * t[k];
+    }
+    for (; s < m; ++s) v += tab->coef[s] * ys[(size_t)s * N + q];
     if (op) tmp[q] = v;
     else out[q] = v;
   }
