@@ -13,6 +13,8 @@ constexpr int kMaxPoles = 64;
 constexpr int kTile = 32;            // fine-grid tile edge of the fused multigrid kernels
 constexpr int kMidTile = 16;         // tile edge of an intermediate level (latency-bound: small
                                      // tiles spread it over more compute units)
+constexpr int kPresumTiles = 2048;  // above this many level-0 tiles the inner-PCG dot products
+                                     // are summed by a pass of their own
 constexpr int kBlock = 256;          // threads per block of the tiled kernels
 constexpr int kCoarseThreads = 1024; // threads of the single-workgroup coarse V-cycle
 constexpr int kMaxCoarsestNf = 16;   // dense inverse on the coarsest grid up to 16 x 16 points
@@ -52,6 +54,8 @@ struct DevState {
   double cg_alpha[2];  // step length of the inner PCG, by iteration parity
   double cg_gam[2];    // r . z of the inner PCG, by iteration parity
   double warm_alpha;   // Galerkin factor of the learned initial guess (0: not used)
+  double dots[2];      // r . z and z . A z for the next inner PCG update, when a separate
+                       // pass sums their partials (large grids, batches)
   // counters / flags
   int inner_done;    // the running multigrid-PCG has converged (or broke down)
   int solve_done;    // the interior solve has met its tolerance

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void kb_mg_down(const BInst* __restrict__ I
   if constexpr (CG) {
     d_mg_down<float, NU, true, TT>(P.r[cur_r], P.u[0], P.f[1], P.nf[0], P.pitch[0],
                                    P.pitch[1], P.z, P.p[cur_p], P.p[cur_p ^ 1], P.x,
-                                   P.r[cur_r ^ 1], st, red, k, tile_x, tile_y, t, lead);
+                                   P.r[cur_r ^ 1], st, red, k, tile_x, tile_y, t, lead, true);
   } else {
     const float* fin = level == 0 ? P.r[cur_r] : P.f[level];
     d_mg_down<float, NU, false, TT>(fin, P.u[level], P.f[level + 1], P.nf[level],
@@ -73,6 +73,16 @@ __global__ __launch_bounds__(kBlock) void kb_mg_down(const BInst* __restrict__ I
                                     nullptr, nullptr, nullptr, st, red, 0, tile_x, tile_y, t,
                                     lead);
   }
+}
+
+// The two dot products of every instance's next PCG update, one block per instance (the
+// level-0 down kernel then reads two scalars instead of summing every tile's partials).
+__global__ __launch_bounds__(kBlock) void kb_dots(const BInst* __restrict__ I, int k,
+                                                  int skip_done) {
+  const BInst& P = I[blockIdx.x];
+  DevState* st = P.st;
+  if (inst_idle(st, skip_done) || stopped(st)) return;
+  d_sum_dots(P.red, k, st);
 }
 
 template <int NU, bool CG, int TT>
@@ -297,6 +307,7 @@ static void b_step(const BatchCtx& c, int rhs, int ver, int its, int S, int& cur
   hipLaunchKernelGGL((kb_mg_up<NU, true, kTile>), dim3(c.tiles_total[0]), tb(), 0, c.stream,
                      c.inst, c.lists, 0, 0, 0, cur_r, c.skip_done);
   for (int k = 0; k < its; ++k) {
+    hipLaunchKernelGGL(kb_dots, dim3(c.lists.ninst), tb(), 0, c.stream, c.inst, k, c.skip_done);
     launch_timed(c.hook, kTimeDown0, kb_mg_down<NU, true, kTile>, dim3(c.tiles_total[0]), tb(),
                  c.stream,
                  c.inst, c.lists, 0, k, cur_r, cur_p, 0, c.skip_done);

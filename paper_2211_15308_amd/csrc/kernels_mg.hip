@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_down(
     const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
     int pc, const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
     T* __restrict__ x, T* __restrict__ rout, DevState* st, Reductions red, int k, int check,
-    int finalize) {
+    int finalize, int presum) {
   if (finalize) {
     // the kernel that starts a PCG run after a refinement residual also does that step's
     // bookkeeping (instead of a one-block kernel of its own)
@@ -48,7 +48,12 @@ __global__ __launch_bounds__(kBlock) void k_mg_down(
   int tile_x, tile_y;
   const int tile = xcd_tile(&tile_x, &tile_y);
   d_mg_down<T, NU, CG, TT>(fin, uout, fc, nf, pitch, pc, z, pold, pnew, x, rout, st, red, k,
-                           tile_x, tile_y, tile, block0());
+                           tile_x, tile_y, tile, block0(), presum != 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_dots(DevState* st, Reductions red, int k) {
+  if (stopped(st)) return;
+  d_sum_dots(red, k, st);
 }
 
 template <typename T, int NU, bool CG, int TT = kTile>
@@ -169,7 +174,7 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
       hipLaunchKernelGGL((k_mg_down<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0, c.stream,
                          mg.f[l], mg.u[l], mg.f[l + 1], L.nf, L.pitch, c.lev[l + 1].pitch,
                          (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (T*)nullptr,
-                         (T*)nullptr, c.st, c.red, 0, chk, 0);
+                         (T*)nullptr, c.st, c.red, 0, chk, 0, 0);
     }
   }
   if constexpr (sizeof(T) == 4) {
@@ -219,7 +224,7 @@ static void pcg_init_nu(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, 
   const Level& L = c.lev[0];
   hipLaunchKernelGGL((k_mg_down<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, r, mg.u[0],
                      mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)nullptr, (const T*)nullptr,
-                     (T*)nullptr, (T*)nullptr, (T*)nullptr, c.st, c.red, 0, 0, 1);
+                     (T*)nullptr, (T*)nullptr, (T*)nullptr, c.st, c.red, 0, 0, 1, 0);
   vcycle_tail_nu<T, NU>(c, mg, 0);
   hipLaunchKernelGGL((k_mg_up<T, NU, true>), tiles(L.nf), tblock(), 0, c.stream, r, mg.u[0],
                      mg.e[1], z, L.nf, L.pitch, c.lev[1].pitch, c.st, c.red, 0, 0);
@@ -235,9 +240,13 @@ template <typename T, int NU>
 static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
                         T* r_new, T* z, T* p_old, T* p_new) {
   const Level& L = c.lev[0];
+  // beyond kPresumTiles tiles the dot products are summed once, by one block, instead of by
+  // every block of the down kernel (same order, same values)
+  const int presum = c.red.nb0 > kPresumTiles ? 1 : 0;
+  if (presum) hipLaunchKernelGGL(k_sum_dots, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red, k);
   launch_timed(c.hook, kTimeDown0, k_mg_down<T, NU, true>, tiles(L.nf), tblock(), c.stream,
                (const T*)r_old, mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)z,
-               (const T*)p_old, p_new, x, r_new, c.st, c.red, k, 0, 0);
+               (const T*)p_old, p_new, x, r_new, c.st, c.red, k, 0, 0, presum);
   vcycle_tail_nu<T, NU>(c, mg, 1);
   launch_timed(c.hook, kTimeUp0, k_mg_up<T, NU, true>, tiles(L.nf), tblock(), c.stream,
                (const T*)r_new, (const T*)mg.u[0], (const T*)mg.e[1], z, L.nf, L.pitch,

@@ -197,6 +197,25 @@ __device__ __forceinline__ void block_sum2(double& a, double& b) {
   b = sh[1][kBlock / 64];
 }
 
+// r . z and z . A z of inner PCG iteration k from the level-0 partials, summed by one block of
+// kBlock threads in the order every block of the level-0 down kernel would use, into st->dots.
+// On large grids (and batches) this pass replaces the per-block sums of that kernel, whose L2
+// reads grow with the square of the tile count.
+__device__ __forceinline__ void d_sum_dots(const Reductions& red, int k, DevState* st) {
+  const double* rzp = (k & 1) ? red.rz[1] : red.rz[0];
+  const double* zwp = (k & 1) ? red.zw[1] : red.zw[0];
+  double gam = 0.0, del = 0.0;
+  for (int q = flat_tid(); q < red.nb0; q += kBlock) {
+    gam += ldg(rzp, (unsigned)q);
+    del += ldg(zwp, (unsigned)q);
+  }
+  block_sum2(gam, del);
+  if (thread0()) {
+    st->dots[0] = gam;
+    st->dots[1] = del;
+  }
+}
+
 // --------------------------------------------------------------------------------------------
 // fused level kernels
 // --------------------------------------------------------------------------------------------
@@ -234,7 +253,7 @@ __device__ __forceinline__ void d_mg_down(
     const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
     int pc, const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
     T* __restrict__ x, T* __restrict__ rout, DevState* st, const Reductions& red, int k,
-    int tile_x, int tile_y, int tile, bool lead) {
+    int tile_x, int tile_y, int tile, bool lead, bool presum = false) {
   constexpr int H = 2 * NU + 1;
   constexpr int W = TT + 2 * H;
   constexpr int PW = CG ? W + 2 : 1;  // window of p: one cell beyond the f window
@@ -249,7 +268,8 @@ __device__ __forceinline__ void d_mg_down(
   T fr[NW];
   T zr[NPW], pr[NPW], xr[NPW];
   // the partials of r.z and z.A z (CG) are loaded first: their sum is needed before any window
-  // value, and loads complete in issue order
+  // value, and loads complete in issue order (presum: d_sum_dots has summed them, in the same
+  // order, into st->dots)
   constexpr int NP = CG ? 4 : 1;
   double rzr[NP], zwr[NP];
   // (parity selects, not indexing: a runtime index into the struct would put it in scratch)
@@ -258,7 +278,7 @@ __device__ __forceinline__ void d_mg_down(
 #pragma unroll
   for (int a = 0; a < NP; ++a) {
     const int q = t + kBlock * a;
-    const bool ok = CG && q < red.nb0;
+    const bool ok = CG && !presum && q < red.nb0;
     rzr[a] = ok ? ldg(rzp, (unsigned)q) : 0.0;
     zwr[a] = ok ? ldg(zwp, (unsigned)q) : 0.0;
   }
@@ -288,16 +308,21 @@ __device__ __forceinline__ void d_mg_down(
   T alpha = T(0), beta = T(0);
   if constexpr (CG) {
     double gam = 0.0, del = 0.0;
+    if (presum) {
+      gam = st->dots[0];
+      del = st->dots[1];
+    } else {
 #pragma unroll
-    for (int a = 0; a < NP; ++a) {
-      gam += rzr[a];
-      del += zwr[a];
+      for (int a = 0; a < NP; ++a) {
+        gam += rzr[a];
+        del += zwr[a];
+      }
+      for (int q = t + kBlock * NP; q < red.nb0; q += kBlock) {
+        gam += ldg(rzp, (unsigned)q);
+        del += ldg(zwp, (unsigned)q);
+      }
+      block_sum2(gam, del);
     }
-    for (int q = t + kBlock * NP; q < red.nb0; q += kBlock) {
-      gam += ldg(rzp, (unsigned)q);
-      del += ldg(zwp, (unsigned)q);
-    }
-    block_sum2(gam, del);
     double b = 0.0, den = del;
     if (k > 0) {
       b = gam / st->cg_gam[(k - 1) & 1];
