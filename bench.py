@@ -110,7 +110,8 @@ def traffic_from_profile(root, nu):
         sha = kernel_source_sha(root)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_sources_sha256") != sha or rec.get("kernel") != f"void fdd::k_mg_down<float, {nu}, true, 32>":
+    kname = f"void fdd::k_mg_down<float, {nu}, true, 32>"
+    if rec.get("kernel_sources_sha256") != sha or rec.get("kernel") != kname:
         return None
     return rec.get("traffic_bytes_per_launch")
 

@@ -2,6 +2,8 @@
 // stencil 4, -1, -1, -1, -1), shared by the single-instance kernels (kernels_mg.hip) and the
 // batched kernels (kernels_batch.hip).  See kernels_mg.hip for the method.
 #pragma once
+#include <type_traits>
+
 #include "fdd_internal.h"
 
 namespace fdd {
@@ -105,7 +107,7 @@ __device__ __forceinline__ bool pcg_converged(DevState* st, const Reductions& re
 // LDS once; the new values go to LDS for the neighbouring threads and a barrier ends it.  Cells of
 // one colour only read the other colour, so reads and writes of a half-sweep do not conflict.
 // The update is u = (f + u_w + u_e + u_s + u_n) / 4 in that order of summation.
-template <typename T, int W, int NS, int NT = kBlock>
+template <typename T, int W, int NS, int NT = kBlock, bool EDGE = true>
 __device__ __forceinline__ void tile_sweeps(T (*su)[W + 1], const T (*sf)[W + 1], int ib, int jb,
                                             int nf, bool red_first) {
   constexpr int R = W - 2;  // updated rows and columns: 1 .. R (R even)
@@ -125,9 +127,9 @@ __device__ __forceinline__ void tile_sweeps(T (*su)[W + 1], const T (*sf)[W + 1]
 #pragma unroll
   for (int k = 0; k < SEG; ++k) {
     const int lj = lj0 + k, j = jb + lj;
-    const bool rowok = act && lj <= R && j >= 1 && j <= nf;
-    ma[k] = rowok && ia >= 1 && ia <= nf;
-    mb[k] = rowok && ia + 1 >= 1 && ia + 1 <= nf;
+    const bool rowok = act && lj <= R && (!EDGE || (j >= 1 && j <= nf));
+    ma[k] = rowok && (!EDGE || (ia >= 1 && ia <= nf));
+    mb[k] = rowok && (!EDGE || (ia + 1 >= 1 && ia + 1 <= nf));
     const int lr = rowc(lj);
     fa[k] = sf[lr][la];
     fb[k] = sf[lr][la + 1];
@@ -216,6 +218,26 @@ __device__ __forceinline__ void d_sum_dots(const Reductions& red, int k, DevStat
   }
 }
 
+// Inside the grid (1..nf in both directions); always true for the bodies of interior tiles.
+template <bool EDGE>
+__device__ __forceinline__ bool in_grid(int i, int j, int nf) {
+  return !EDGE || (i >= 1 && i <= nf && j >= 1 && j <= nf);
+}
+
+// True if every cell a tiled level kernel with halo H touches for this tile lies inside the grid:
+// the window, one ring beyond it (the PCG update's p) and the coarse patch of the prolongation.
+// Such tiles (all but the outermost ring of tiles) run the kernel body without its per-cell
+// domain tests (EDGE = false); the arithmetic is the same.
+template <int H, int TT>
+__device__ __forceinline__ bool tile_inner(int tile_x, int tile_y, int nf) {
+  constexpr int W = TT + 2 * H;
+  constexpr int CW = W / 2 + 2;
+  const int ib = tile_x * TT + 1 - H, jb = tile_y * TT + 1 - H;
+  const int nc = (nf - 1) >> 1;
+  return ib >= 2 && jb >= 2 && ib + W <= nf && jb + W <= nf && (ib >> 1) + CW - 1 <= nc &&
+         (jb >> 1) + CW - 1 <= nc;
+}
+
 // --------------------------------------------------------------------------------------------
 // fused level kernels
 // --------------------------------------------------------------------------------------------
@@ -248,8 +270,8 @@ constexpr int kOwnSlots = kTile * kTile / kBlock;
 //   one cell beyond the window, so that s_k = A p_k is a stencil in LDS (no stored recurrence
 //   for A p); on the window f = r_{k+1} = r_k - alpha_k s_k; on own points x += alpha_k p_k and
 //   r_{k+1}, p_k are stored; ||r_{k+1}||^2 goes to red.rr.
-template <typename T, int NU, bool CG, int TT = kTile>
-__device__ __forceinline__ void d_mg_down(
+template <typename T, int NU, bool CG, int TT, bool EDGE>
+__device__ __forceinline__ void d_mg_down_body(T* sf_, T* su_, T* s3_,
     const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
     int pc, const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
     T* __restrict__ x, T* __restrict__ rout, DevState* st, const Reductions& red, int k,
@@ -259,9 +281,9 @@ __device__ __forceinline__ void d_mg_down(
   constexpr int PW = CG ? W + 2 : 1;  // window of p: one cell beyond the f window
   constexpr int NW = Flat<W>::N;
   constexpr int NPW = CG ? Flat<PW>::N : 1;
-  __shared__ T sf[W][W + 1];
-  __shared__ T su[W][W + 1];
-  __shared__ T sp[PW][PW + 1];
+  auto sf = reinterpret_cast<T(*)[W + 1]>(sf_);
+  auto su = reinterpret_cast<T(*)[W + 1]>(su_);
+  auto sp = reinterpret_cast<T(*)[PW + 1]>(s3_);
   const int i0 = tile_x * TT, j0 = tile_y * TT;
   const int ib = i0 + 1 - H, jb = j0 + 1 - H;  // global index of window cell (0, 0)
   const int t = flat_tid();
@@ -287,7 +309,7 @@ __device__ __forceinline__ void d_mg_down(
     const int c = t + kBlock * q;
     const int lj = c / W, li = c % W;
     const int i = ib + li, j = jb + lj;
-    const bool in = c < W * W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+    const bool in = c < W * W && in_grid<EDGE>(i, j, nf);
     fr[q] = in ? ldg(fin, (unsigned)((j - 1) * pitch + (i - 1))) : T(0);
   }
   if constexpr (CG) {
@@ -296,7 +318,7 @@ __device__ __forceinline__ void d_mg_down(
       const int c = t + kBlock * q;
       const int lj = c / PW, li = c % PW;
       const int i = ib - 1 + li, j = jb - 1 + lj;
-      const bool in = c < PW * PW && i >= 1 && i <= nf && j >= 1 && j <= nf;
+      const bool in = c < PW * PW && in_grid<EDGE>(i, j, nf);
       const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
       // own cells of the tile: p window cells H + 1 .. H + TT
       const bool own = in && li > H && li <= H + TT && lj > H && lj <= H + TT;
@@ -353,7 +375,7 @@ __device__ __forceinline__ void d_mg_down(
       const T pv = zr[q] + beta * pr[q];
       sp[lj][li] = pv;
       const int i = ib - 1 + li, j = jb - 1 + lj;
-      if (li > H && li <= H + TT && lj > H && lj <= H + TT && i <= nf && j <= nf) {
+      if (li > H && li <= H + TT && lj > H && lj <= H + TT && (!EDGE || (i <= nf && j <= nf))) {
         const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
         stg(pnew, o, pv);
         stg(x, o, xr[q] + alpha * pv);
@@ -370,7 +392,7 @@ __device__ __forceinline__ void d_mg_down(
     const int i = ib + li, j = jb + lj;
     T f = fr[q];
     if constexpr (CG) {
-      if (i >= 1 && i <= nf && j >= 1 && j <= nf) {
+      if (in_grid<EDGE>(i, j, nf)) {
         const int pj = lj + 1, pi = li + 1;
         const T sv = T(4) * sp[pj][pi] - sp[pj][pi - 1] - sp[pj][pi + 1] - sp[pj - 1][pi] -
                      sp[pj + 1][pi];
@@ -386,7 +408,7 @@ __device__ __forceinline__ void d_mg_down(
     su[lj][li] = is_red(i, j) ? T(0.25) * f : T(0);
   }
   __syncthreads();
-  tile_sweeps<T, W, 2 * NU - 1>(su, sf, ib, jb, nf, false);  // black, red, black, ...
+  tile_sweeps<T, W, 2 * NU - 1, kBlock, EDGE>(su, sf, ib, jb, nf, false);  // black, red, ...
   // residual, in place of f, on the cells the restriction reads (window rows and columns
   // H .. H + TT); each reads its own f and the neighbours' u
   constexpr int RW = TT + 1;
@@ -402,10 +424,11 @@ __device__ __forceinline__ void d_mg_down(
     constexpr int TC = TT / 2;
     static_assert(TC * TC <= kBlock, "at most one coarse point per thread");
     const int J = (j0 >> 1) + 1 + t / TC, I = (i0 >> 1) + 1 + t % TC;
-    if (t < TC * TC && J <= nc && I <= nc) {
+    if (t < TC * TC && (!EDGE || (J <= nc && I <= nc))) {
       const int li = 2 * I - ib, lj = 2 * J - jb;
       const T v = sf[lj][li] + T(0.5) * (sf[lj][li - 1] + sf[lj][li + 1] + sf[lj - 1][li] +
-                                         sf[lj + 1][li] + sf[lj - 1][li - 1] + sf[lj + 1][li + 1]);
+                                         sf[lj + 1][li] + sf[lj - 1][li - 1] +
+                                         sf[lj + 1][li + 1]);
       stg(fc, (unsigned)((J - 1) * pc + (I - 1)), v);
     }
   }
@@ -415,7 +438,7 @@ __device__ __forceinline__ void d_mg_down(
     const int c = t + kBlock * q;
     const int bi = c % TT, bj = c / TT;
     const int i = i0 + 1 + bi, j = j0 + 1 + bj;
-    if (j > nf || i > nf) continue;
+    if (EDGE && (j > nf || i > nf)) continue;
     stg(uout, (unsigned)((j - 1) * pitch + (i - 1)), su[bj + H][bi + H]);
   }
   if (CG) {
@@ -424,12 +447,36 @@ __device__ __forceinline__ void d_mg_down(
   }
 }
 
+// The body above for one tile; interior tiles take it without the per-cell domain tests (both
+// variants share the LDS windows).
+template <typename T, int NU, bool CG, int TT = kTile>
+__device__ __forceinline__ void d_mg_down(
+    const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
+    int pc, const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
+    T* __restrict__ x, T* __restrict__ rout, DevState* st, const Reductions& red, int k,
+    int tile_x, int tile_y, int tile, bool lead, bool presum = false) {
+  constexpr int H = 2 * NU + 1;
+  constexpr int W = TT + 2 * H;
+  constexpr int PW = CG ? W + 2 : 1;
+  __shared__ T sf[W][W + 1];
+  __shared__ T su[W][W + 1];
+  __shared__ T sp[PW][PW + 1];
+  if (tile_inner<H, TT>(tile_x, tile_y, nf))
+    d_mg_down_body<T, NU, CG, TT, false>(&sf[0][0], &su[0][0], &sp[0][0], fin, uout, fc, nf,
+                                         pitch, pc, z, pold, pnew, x, rout, st, red, k, tile_x,
+                                         tile_y, tile, lead, presum);
+  else
+    d_mg_down_body<T, NU, CG, TT, true>(&sf[0][0], &su[0][0], &sp[0][0], fin, uout, fc, nf,
+                                        pitch, pc, z, pold, pnew, x, rout, st, red, k, tile_x,
+                                        tile_y, tile, lead, presum);
+}
+
 // Going up one level: u = u_pre + P e_c, then nu (black, red) pairs; result to eout.
 // CG = true (level 0): the result z is kept valid one cell beyond the tile, so that A z is
 // formed on own points too; z is stored and the block's parts of r . z and z . A z go to
 // red.rz[kn & 1] and red.zw[kn & 1] (f is r).
-template <typename T, int NU, bool CG, int TT = kTile>
-__device__ __forceinline__ void d_mg_up(
+template <typename T, int NU, bool CG, int TT, bool EDGE>
+__device__ __forceinline__ void d_mg_up_body(T* sf_, T* su_, T* s3_,
     const T* __restrict__ fin, const T* __restrict__ upre, const T* __restrict__ ec,
     T* __restrict__ eout, int nf, int pitch, int pc, DevState* st, const Reductions& red, int kn,
     int count_iteration, int tile_x, int tile_y, int tile, bool lead) {
@@ -438,9 +485,9 @@ __device__ __forceinline__ void d_mg_up(
   constexpr int NW = Flat<W>::N;
   constexpr int CW = W / 2 + 2;  // coarse patch edge
   constexpr int NC = Flat<CW>::N;
-  __shared__ T sf[W][W + 1];
-  __shared__ T su[W][W + 1];
-  __shared__ T sc[CW][CW + 1];
+  auto sf = reinterpret_cast<T(*)[W + 1]>(sf_);
+  auto su = reinterpret_cast<T(*)[W + 1]>(su_);
+  auto sc = reinterpret_cast<T(*)[CW + 1]>(s3_);
   const int i0 = tile_x * TT, j0 = tile_y * TT;
   const int ib = i0 + 1 - H, jb = j0 + 1 - H;
   const int Ib = ib >> 1, Jb = jb >> 1;  // floor (arithmetic shift)
@@ -452,7 +499,7 @@ __device__ __forceinline__ void d_mg_up(
     const int c = t + kBlock * q;
     const int lj = c / W, li = c % W;
     const int i = ib + li, j = jb + lj;
-    const bool in = c < W * W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+    const bool in = c < W * W && in_grid<EDGE>(i, j, nf);
     const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
     fr[q] = in ? ldg(fin, o) : T(0);
     ur[q] = in ? ldg(upre, o) : T(0);
@@ -462,7 +509,7 @@ __device__ __forceinline__ void d_mg_up(
     const int c = t + kBlock * q;
     const int lj = c / CW, li = c % CW;
     const int I = Ib + li, J = Jb + lj;
-    const bool in = c < CW * CW && I >= 1 && I <= nc && J >= 1 && J <= nc;
+    const bool in = c < CW * CW && (!EDGE || (I >= 1 && I <= nc && J >= 1 && J <= nc));
     cr[q] = in ? ldg(ec, (unsigned)((J - 1) * pc + (I - 1))) : T(0);
   }
 #pragma unroll
@@ -478,7 +525,7 @@ __device__ __forceinline__ void d_mg_up(
     const int lj = c / W, li = c % W;
     const int i = ib + li, j = jb + lj;
     T u = T(0);
-    if (i >= 1 && i <= nf && j >= 1 && j <= nf) {
+    if (in_grid<EDGE>(i, j, nf)) {
       // P1 interpolation of the coarse correction (nested diagonal-split meshes): the mean of
       // the coarse values at (i >> 1, j >> 1) and at that point shifted by the parities of
       // (i, j); at coincident points both are the same value, and 0.5 (a + a) = a exactly.
@@ -491,14 +538,14 @@ __device__ __forceinline__ void d_mg_up(
     su[lj][li] = u;
   }
   __syncthreads();
-  tile_sweeps<T, W, 2 * NU>(su, sf, ib, jb, nf, false);  // black, red, ...
+  tile_sweeps<T, W, 2 * NU, kBlock, EDGE>(su, sf, ib, jb, nf, false);  // black, red, ...
   double rz = 0.0, zw = 0.0;
 #pragma unroll
   for (int q = 0; q < (TT * TT / kBlock); ++q) {
     const int c = t + kBlock * q;
     const int bi = c % TT, bj = c / TT;
     const int i = i0 + 1 + bi, j = j0 + 1 + bj;
-    if (j > nf || i > nf) continue;
+    if (EDGE && (j > nf || i > nf)) continue;
     const int lj = bj + H, li = bi + H;
     const T zv = su[lj][li];
     const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
@@ -522,6 +569,29 @@ __device__ __forceinline__ void d_mg_up(
     }
   }
 }
+
+// The body above for one tile; interior tiles take it without the per-cell domain tests.
+template <typename T, int NU, bool CG, int TT = kTile>
+__device__ __forceinline__ void d_mg_up(
+    const T* __restrict__ fin, const T* __restrict__ upre, const T* __restrict__ ec,
+    T* __restrict__ eout, int nf, int pitch, int pc, DevState* st, const Reductions& red, int kn,
+    int count_iteration, int tile_x, int tile_y, int tile, bool lead) {
+  constexpr int H = 2 * NU + (CG ? 1 : 0);
+  constexpr int W = TT + 2 * H;
+  constexpr int CW = W / 2 + 2;
+  __shared__ T sf[W][W + 1];
+  __shared__ T su[W][W + 1];
+  __shared__ T sc[CW][CW + 1];
+  if (tile_inner<H, TT>(tile_x, tile_y, nf))
+    d_mg_up_body<T, NU, CG, TT, false>(&sf[0][0], &su[0][0], &sc[0][0], fin, upre, ec, eout, nf,
+                                       pitch, pc, st, red, kn, count_iteration, tile_x, tile_y,
+                                       tile, lead);
+  else
+    d_mg_up_body<T, NU, CG, TT, true>(&sf[0][0], &su[0][0], &sc[0][0], fin, upre, ec, eout, nf,
+                                      pitch, pc, st, red, kn, count_iteration, tile_x, tile_y,
+                                      tile, lead);
+}
+
 
 // --------------------------------------------------------------------------------------------
 // two intermediate levels in one kernel
