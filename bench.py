@@ -110,7 +110,7 @@ def traffic_from_profile(root, nu):
         sha = kernel_source_sha(root)
     except (OSError, ValueError):
         return None
-    kname = f"void fdd::k_mg_down<float, {nu}, true, 32>"
+    kname = f"void fdd::k_mg_down<float, {nu}, true, 32, true>"
     if rec.get("kernel_sources_sha256") != sha or rec.get("kernel") != kname:
         return None
     return rec.get("traffic_bytes_per_launch")
@@ -502,7 +502,7 @@ def main():
     traffic = traffic_from_profile(ROOT, args.nu) if prec == F.FDD_MIXED and args.n == 1024 else None
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": f"k_mg_down<float,{args.nu},true,32> (finest level, PCG update fused)",
+                "kernel": f"k_mg_down<float,{args.nu},true,32,true> (finest level, PCG update fused)",
                 "launches": launches, "avg_launch_us": 1e3 * tot_ms / max(launches, 1),
                 "working_launches": its + runs, "timed_long_launches": long_n,
                 "avg_working_launch_us": 1e3 * long_ms / max(long_n, 1),

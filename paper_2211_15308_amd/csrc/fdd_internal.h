@@ -15,6 +15,7 @@ constexpr int kMidTile = 16;         // tile edge of an intermediate level (late
                                      // tiles spread it over more compute units)
 constexpr int kPresumTiles = 2048;  // above this many level-0 tiles the inner-PCG dot products
                                      // are summed by a pass of their own
+constexpr int kResidentTiles = 1024; // level-0 tiles that are all in flight at once (4 per CU)
 constexpr int kBlock = 256;          // threads per block of the tiled kernels
 constexpr int kCoarseThreads = 1024; // threads of the single-workgroup coarse V-cycle
 constexpr int kMaxCoarsestNf = 16;   // dense inverse on the coarsest grid up to 16 x 16 points

@@ -31,7 +31,7 @@ namespace fdd {
 // single-instance kernels
 // --------------------------------------------------------------------------------------------
 
-template <typename T, int NU, bool CG, int TT = kTile>
+template <typename T, int NU, bool CG, int TT = kTile, bool RESIDENT = false>
 __global__ __launch_bounds__(kBlock) void k_mg_down(
     const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
     int pc, const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
@@ -47,8 +47,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_down(
   }
   int tile_x, tile_y;
   const int tile = xcd_tile(&tile_x, &tile_y);
-  d_mg_down<T, NU, CG, TT>(fin, uout, fc, nf, pitch, pc, z, pold, pnew, x, rout, st, red, k,
-                           tile_x, tile_y, tile, block0(), presum != 0);
+  d_mg_down<T, NU, CG, TT, RESIDENT>(fin, uout, fc, nf, pitch, pc, z, pold, pnew, x, rout, st,
+                                     red, k, tile_x, tile_y, tile, block0(), presum != 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum_dots(DevState* st, Reductions red, int k) {
@@ -244,9 +244,17 @@ static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x,
   // every block of the down kernel (same order, same values)
   const int presum = c.red.nb0 > kPresumTiles ? 1 : 0;
   if (presum) hipLaunchKernelGGL(k_sum_dots, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red, k);
-  launch_timed(c.hook, kTimeDown0, k_mg_down<T, NU, true>, tiles(L.nf), tblock(), c.stream,
-               (const T*)r_old, mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)z,
-               (const T*)p_old, p_new, x, r_new, c.st, c.red, k, 0, 0, presum);
+  // FP32 grids of at most kResidentTiles tiles run the down kernel's RESIDENT form (every tile
+  // in flight at once, four blocks per compute unit)
+  if (sizeof(T) != 4 || c.red.nb0 > kResidentTiles) {
+    launch_timed(c.hook, kTimeDown0, k_mg_down<T, NU, true, kTile, false>, tiles(L.nf), tblock(),
+                 c.stream, (const T*)r_old, mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch,
+                 (const T*)z, (const T*)p_old, p_new, x, r_new, c.st, c.red, k, 0, 0, presum);
+  } else {
+    launch_timed(c.hook, kTimeDown0, k_mg_down<T, NU, true, kTile, true>, tiles(L.nf), tblock(),
+                 c.stream, (const T*)r_old, mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch,
+                 (const T*)z, (const T*)p_old, p_new, x, r_new, c.st, c.red, k, 0, 0, presum);
+  }
   vcycle_tail_nu<T, NU>(c, mg, 1);
   launch_timed(c.hook, kTimeUp0, k_mg_up<T, NU, true>, tiles(L.nf), tblock(), c.stream,
                (const T*)r_new, (const T*)mg.u[0], (const T*)mg.e[1], z, L.nf, L.pitch,

@@ -270,7 +270,7 @@ constexpr int kOwnSlots = kTile * kTile / kBlock;
 //   one cell beyond the window, so that s_k = A p_k is a stencil in LDS (no stored recurrence
 //   for A p); on the window f = r_{k+1} = r_k - alpha_k s_k; on own points x += alpha_k p_k and
 //   r_{k+1}, p_k are stored; ||r_{k+1}||^2 goes to red.rr.
-template <typename T, int NU, bool CG, int TT, bool EDGE>
+template <typename T, int NU, bool CG, int TT, bool EDGE, bool RESIDENT>
 __device__ __forceinline__ void d_mg_down_body(T* sf_, T* su_, T* s3_,
     const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
     int pc, const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
@@ -287,6 +287,15 @@ __device__ __forceinline__ void d_mg_down_body(T* sf_, T* su_, T* s3_,
   const int i0 = tile_x * TT, j0 = tile_y * TT;
   const int ib = i0 + 1 - H, jb = j0 + 1 - H;  // global index of window cell (0, 0)
   const int t = flat_tid();
+  // RESIDENT (every tile of the grid runs at once): with the thread range known, the compiler
+  // computes every window offset up front, in about twice the registers, which shortens the
+  // critical path of a block but would cost occupancy when tiles queue for compute units
+  if constexpr (RESIDENT) __builtin_assume(t >= 0 && t < kBlock);
+  // element offsets as a block-uniform base plus a small per-cell part (row index times pitch:
+  // a 24-bit product, as every vector here has fewer than 2^29 elements)
+  const unsigned rb = (unsigned)((jb - 1) * pitch + (ib - 1));  // f window cell (0, 0)
+  const unsigned rbp = rb - (unsigned)pitch - 1u;                 // p window cell (0, 0)
+  const unsigned ro = (unsigned)(j0 * pitch + i0);               // own cell (0, 0)
   T fr[NW];
   T zr[NPW], pr[NPW], xr[NPW];
   // the partials of r.z and z.A z (CG) are loaded first: their sum is needed before any window
@@ -310,7 +319,7 @@ __device__ __forceinline__ void d_mg_down_body(T* sf_, T* su_, T* s3_,
     const int lj = c / W, li = c % W;
     const int i = ib + li, j = jb + lj;
     const bool in = c < W * W && in_grid<EDGE>(i, j, nf);
-    fr[q] = in ? ldg(fin, (unsigned)((j - 1) * pitch + (i - 1))) : T(0);
+    fr[q] = in ? ldg(fin, rb + (__umul24(lj, pitch) + li)) : T(0);
   }
   if constexpr (CG) {
 #pragma unroll
@@ -319,7 +328,7 @@ __device__ __forceinline__ void d_mg_down_body(T* sf_, T* su_, T* s3_,
       const int lj = c / PW, li = c % PW;
       const int i = ib - 1 + li, j = jb - 1 + lj;
       const bool in = c < PW * PW && in_grid<EDGE>(i, j, nf);
-      const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+      const unsigned o = rbp + (__umul24(lj, pitch) + li);
       // own cells of the tile: p window cells H + 1 .. H + TT
       const bool own = in && li > H && li <= H + TT && lj > H && lj <= H + TT;
       zr[q] = in ? ldg(z, o) : T(0);
@@ -376,7 +385,7 @@ __device__ __forceinline__ void d_mg_down_body(T* sf_, T* su_, T* s3_,
       sp[lj][li] = pv;
       const int i = ib - 1 + li, j = jb - 1 + lj;
       if (li > H && li <= H + TT && lj > H && lj <= H + TT && (!EDGE || (i <= nf && j <= nf))) {
-        const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+        const unsigned o = rbp + (__umul24(lj, pitch) + li);
         stg(pnew, o, pv);
         stg(x, o, xr[q] + alpha * pv);
       }
@@ -398,7 +407,7 @@ __device__ __forceinline__ void d_mg_down_body(T* sf_, T* su_, T* s3_,
                      sp[pj + 1][pi];
         f = f - alpha * sv;
         if (li >= H && li < H + TT && lj >= H && lj < H + TT) {
-          stg(rout, (unsigned)((j - 1) * pitch + (i - 1)), f);
+          stg(rout, rb + (__umul24(lj, pitch) + li), f);
           rr += (double)f * (double)f;
         }
       }
@@ -429,7 +438,7 @@ __device__ __forceinline__ void d_mg_down_body(T* sf_, T* su_, T* s3_,
       const T v = sf[lj][li] + T(0.5) * (sf[lj][li - 1] + sf[lj][li + 1] + sf[lj - 1][li] +
                                          sf[lj + 1][li] + sf[lj - 1][li - 1] +
                                          sf[lj + 1][li + 1]);
-      stg(fc, (unsigned)((J - 1) * pc + (I - 1)), v);
+      stg(fc, (unsigned)((j0 >> 1) * pc + (i0 >> 1)) + (__umul24(t / TC, pc) + t % TC), v);
     }
   }
   // store the pre-smoothed iterate on own points
@@ -439,7 +448,7 @@ __device__ __forceinline__ void d_mg_down_body(T* sf_, T* su_, T* s3_,
     const int bi = c % TT, bj = c / TT;
     const int i = i0 + 1 + bi, j = j0 + 1 + bj;
     if (EDGE && (j > nf || i > nf)) continue;
-    stg(uout, (unsigned)((j - 1) * pitch + (i - 1)), su[bj + H][bi + H]);
+    stg(uout, ro + (__umul24(bj, pitch) + bi), su[bj + H][bi + H]);
   }
   if (CG) {
     const double tot = block_sum_all(rr);
@@ -449,7 +458,7 @@ __device__ __forceinline__ void d_mg_down_body(T* sf_, T* su_, T* s3_,
 
 // The body above for one tile; interior tiles take it without the per-cell domain tests (both
 // variants share the LDS windows).
-template <typename T, int NU, bool CG, int TT = kTile>
+template <typename T, int NU, bool CG, int TT = kTile, bool RESIDENT = false>
 __device__ __forceinline__ void d_mg_down(
     const T* __restrict__ fin, T* __restrict__ uout, T* __restrict__ fc, int nf, int pitch,
     int pc, const T* __restrict__ z, const T* __restrict__ pold, T* __restrict__ pnew,
@@ -462,13 +471,13 @@ __device__ __forceinline__ void d_mg_down(
   __shared__ T su[W][W + 1];
   __shared__ T sp[PW][PW + 1];
   if (tile_inner<H, TT>(tile_x, tile_y, nf))
-    d_mg_down_body<T, NU, CG, TT, false>(&sf[0][0], &su[0][0], &sp[0][0], fin, uout, fc, nf,
-                                         pitch, pc, z, pold, pnew, x, rout, st, red, k, tile_x,
-                                         tile_y, tile, lead, presum);
+    d_mg_down_body<T, NU, CG, TT, false, RESIDENT>(&sf[0][0], &su[0][0], &sp[0][0], fin, uout,
+                                                   fc, nf, pitch, pc, z, pold, pnew, x, rout, st,
+                                                   red, k, tile_x, tile_y, tile, lead, presum);
   else
-    d_mg_down_body<T, NU, CG, TT, true>(&sf[0][0], &su[0][0], &sp[0][0], fin, uout, fc, nf,
-                                        pitch, pc, z, pold, pnew, x, rout, st, red, k, tile_x,
-                                        tile_y, tile, lead, presum);
+    d_mg_down_body<T, NU, CG, TT, true, RESIDENT>(&sf[0][0], &su[0][0], &sp[0][0], fin, uout, fc,
+                                                  nf, pitch, pc, z, pold, pnew, x, rout, st, red,
+                                                  k, tile_x, tile_y, tile, lead, presum);
 }
 
 // Going up one level: u = u_pre + P e_c, then nu (black, red) pairs; result to eout.
@@ -493,6 +502,12 @@ __device__ __forceinline__ void d_mg_up_body(T* sf_, T* su_, T* s3_,
   const int Ib = ib >> 1, Jb = jb >> 1;  // floor (arithmetic shift)
   const int nc = (nf - 1) >> 1;
   const int t = flat_tid();
+  __builtin_assume(t >= 0 && t < kBlock);
+  // element offsets as a block-uniform base plus a small per-cell part (row index times pitch:
+  // a 24-bit product, as every vector here has fewer than 2^29 elements)
+  const unsigned rb = (unsigned)((jb - 1) * pitch + (ib - 1));  // window cell (0, 0)
+  const unsigned rc = (unsigned)((Jb - 1) * pc + (Ib - 1));     // coarse patch cell (0, 0)
+  const unsigned ro = (unsigned)(j0 * pitch + i0);              // own cell (0, 0)
   T fr[NW], ur[NW], cr[NC];
 #pragma unroll
   for (int q = 0; q < NW; ++q) {
@@ -500,7 +515,7 @@ __device__ __forceinline__ void d_mg_up_body(T* sf_, T* su_, T* s3_,
     const int lj = c / W, li = c % W;
     const int i = ib + li, j = jb + lj;
     const bool in = c < W * W && in_grid<EDGE>(i, j, nf);
-    const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+    const unsigned o = rb + (__umul24(lj, pitch) + li);
     fr[q] = in ? ldg(fin, o) : T(0);
     ur[q] = in ? ldg(upre, o) : T(0);
   }
@@ -510,7 +525,7 @@ __device__ __forceinline__ void d_mg_up_body(T* sf_, T* su_, T* s3_,
     const int lj = c / CW, li = c % CW;
     const int I = Ib + li, J = Jb + lj;
     const bool in = c < CW * CW && (!EDGE || (I >= 1 && I <= nc && J >= 1 && J <= nc));
-    cr[q] = in ? ldg(ec, (unsigned)((J - 1) * pc + (I - 1))) : T(0);
+    cr[q] = in ? ldg(ec, rc + (__umul24(lj, pc) + li)) : T(0);
   }
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
@@ -530,7 +545,7 @@ __device__ __forceinline__ void d_mg_up_body(T* sf_, T* su_, T* s3_,
       // the coarse values at (i >> 1, j >> 1) and at that point shifted by the parities of
       // (i, j); at coincident points both are the same value, and 0.5 (a + a) = a exactly.
       // Branch-free, so the reads of all window slots are issued together.
-      const int ci = (i >> 1) - Ib, cj = (j >> 1) - Jb;
+      const int ci = (li + (ib & 1)) >> 1, cj = (lj + (jb & 1)) >> 1;  // (i >> 1) - Ib, ...
       const T e = T(0.5) * (sc[cj][ci] + sc[cj + (j & 1)][ci + (i & 1)]);
       u = ur[q] + e;
     }
@@ -548,7 +563,7 @@ __device__ __forceinline__ void d_mg_up_body(T* sf_, T* su_, T* s3_,
     if (EDGE && (j > nf || i > nf)) continue;
     const int lj = bj + H, li = bi + H;
     const T zv = su[lj][li];
-    const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
+    const unsigned o = ro + (__umul24(bj, pitch) + bi);
     stg(eout, o, zv);
     if (CG) {
       const T wv = T(4) * zv - su[lj][li - 1] - su[lj][li + 1] - su[lj - 1][li] - su[lj + 1][li];
