@@ -171,8 +171,11 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
                            (const float*)mg.f[l], mg.u[l], mg.f[l + 1], mg.u[l + 1], mg.f[l + 2],
                            L.nf, L.pitch, c.lev[l + 1].pitch, c.lev[l + 2].pitch, c.st, c.red, chk);
     } else {
-      hipLaunchKernelGGL((k_mg_down<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0, c.stream,
-                         mg.f[l], mg.u[l], mg.f[l + 1], L.nf, L.pitch, c.lev[l + 1].pitch,
+      // (in FP32 a level that runs alone is the last tiled one, at most 127^2 points: 64 tiles,
+      // all in flight at once)
+      hipLaunchKernelGGL((k_mg_down<T, NU, false, kMidTile, sizeof(T) == 4>), mtiles(L.nf),
+                         tblock(), 0, c.stream, mg.f[l], mg.u[l], mg.f[l + 1], L.nf, L.pitch,
+                         c.lev[l + 1].pitch,
                          (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (T*)nullptr,
                          (T*)nullptr, c.st, c.red, 0, chk, 0, 0);
     }

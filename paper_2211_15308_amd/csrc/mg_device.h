@@ -647,6 +647,8 @@ __device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __res
   __shared__ T sf1[W1][W1 + 1];
   __shared__ T su1[W1][W1 + 1];
   const int t = flat_tid();
+  // one block per compute unit, every block in flight: the thread range is known to the compiler
+  __builtin_assume(t >= 0 && t < kPairThreads);
   const int nf1 = (nf0 - 1) >> 1;
   const int I0 = tile_x * kPairTile, J0 = tile_y * kPairTile;
   const int Ib = I0 + 1 - H1, Jb = J0 + 1 - H1;          // level-(l+1) window origin
@@ -658,7 +660,7 @@ __device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __res
     const int lj = c / W0, li = c % W0;
     const int i = ib0 + li, j = jb0 + lj;
     const bool in = c < W0 * W0 && i >= 1 && i <= nf0 && j >= 1 && j <= nf0;
-    fr[q] = in ? ldg(fin0, (unsigned)((j - 1) * p0 + (i - 1))) : T(0);
+    fr[q] = in ? ldg(fin0, (__umul24(j - 1, p0) + (i - 1))) : T(0);
   }
 #pragma unroll
   for (int q = 0; q < G::N0; ++q) {
@@ -683,7 +685,7 @@ __device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __res
     const int bi = c % (2 * kPairTile), bj = c / (2 * kPairTile);
     const int i = 2 * I0 + 1 + bi, j = 2 * J0 + 1 + bj;
     if (i <= nf0 && j <= nf0)
-      stg(uout0, (unsigned)((j - 1) * p0 + (i - 1)), su0[j - jb0][i - ib0]);
+      stg(uout0, (__umul24(j - 1, p0) + (i - 1)), su0[j - jb0][i - ib0]);
   }
   __syncthreads();
   // f_{l+1} on the level-(l+1) window (zero outside the level), stored on the tile; red start
@@ -696,7 +698,7 @@ __device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __res
       v = sf0[lj][li] + T(0.5) * (sf0[lj][li - 1] + sf0[lj][li + 1] + sf0[lj - 1][li] +
                                   sf0[lj + 1][li] + sf0[lj - 1][li - 1] + sf0[lj + 1][li + 1]);
       if (LI >= H1 && LI < H1 + kPairTile && LJ >= H1 && LJ < H1 + kPairTile)
-        stg(fout1, (unsigned)((J - 1) * p1 + (I - 1)), v);
+        stg(fout1, (__umul24(J - 1, p1) + (I - 1)), v);
     }
     sf1[LJ][LI] = v;
     su1[LJ][LI] = is_red(I, J) ? T(0.25) * v : T(0);
@@ -720,14 +722,14 @@ __device__ __forceinline__ void d_pair_down(const T* __restrict__ fin0, T* __res
         const T v = sf1[lj][li] + T(0.5) * (sf1[lj][li - 1] + sf1[lj][li + 1] + sf1[lj - 1][li] +
                                             sf1[lj + 1][li] + sf1[lj - 1][li - 1] +
                                             sf1[lj + 1][li + 1]);
-        stg(fout2, (unsigned)((J - 1) * p2 + (I - 1)), v);
+        stg(fout2, (__umul24(J - 1, p2) + (I - 1)), v);
       }
     }
   }
   for (int c = t; c < kPairTile * kPairTile; c += kPairThreads) {
     const int bi = c % kPairTile, bj = c / kPairTile;
     const int I = I0 + 1 + bi, J = J0 + 1 + bj;
-    if (I <= nf1 && J <= nf1) stg(uout1, (unsigned)((J - 1) * p1 + (I - 1)), su1[bj + H1][bi + H1]);
+    if (I <= nf1 && J <= nf1) stg(uout1, (__umul24(J - 1, p1) + (I - 1)), su1[bj + H1][bi + H1]);
   }
 }
 
@@ -759,6 +761,8 @@ __device__ __forceinline__ void d_pair_up(const T* __restrict__ f0, const T* __r
   __shared__ T su1[W1][W1 + 1];
   __shared__ T sc2[CW2][CW2 + 1];
   const int t = flat_tid();
+  // one block per compute unit, every block in flight: the thread range is known to the compiler
+  __builtin_assume(t >= 0 && t < kPairThreads);
   const int nf1 = (nf0 - 1) >> 1, nf2 = (nf1 - 1) >> 1;
   const int I0 = tile_x * kPairTile, J0 = tile_y * kPairTile;
   const int ib0 = 2 * I0 + 1 - H, jb0 = 2 * J0 + 1 - H;  // level-l window origin
@@ -771,14 +775,14 @@ __device__ __forceinline__ void d_pair_up(const T* __restrict__ f0, const T* __r
     const int c = t + kPairThreads * q;
     const int I = Ic2 + c % CW2, J = Jc2 + c / CW2;
     const bool in = c < CW2 * CW2 && I >= 1 && I <= nf2 && J >= 1 && J <= nf2;
-    c2r[q] = in ? ldg(e2, (unsigned)((J - 1) * p2 + (I - 1))) : T(0);
+    c2r[q] = in ? ldg(e2, (__umul24(J - 1, p2) + (I - 1))) : T(0);
   }
 #pragma unroll
   for (int q = 0; q < G::N1; ++q) {
     const int c = t + kPairThreads * q;
     const int i = ib1 + c % W1, j = jb1 + c / W1;
     const bool in = c < W1 * W1 && i >= 1 && i <= nf1 && j >= 1 && j <= nf1;
-    const unsigned o = (unsigned)((j - 1) * p1 + (i - 1));
+    const unsigned o = (__umul24(j - 1, p1) + (i - 1));
     f1r[q] = in ? ldg(f1, o) : T(0);
     u1r[q] = in ? ldg(u1pre, o) : T(0);
   }
@@ -787,7 +791,7 @@ __device__ __forceinline__ void d_pair_up(const T* __restrict__ f0, const T* __r
     const int c = t + kPairThreads * q;
     const int i = ib0 + c % W0, j = jb0 + c / W0;
     const bool in = c < W0 * W0 && i >= 1 && i <= nf0 && j >= 1 && j <= nf0;
-    const unsigned o = (unsigned)((j - 1) * p0 + (i - 1));
+    const unsigned o = (__umul24(j - 1, p0) + (i - 1));
     f0r[q] = in ? ldg(f0, o) : T(0);
     u0r[q] = in ? ldg(u0pre, o) : T(0);
   }
@@ -838,7 +842,7 @@ __device__ __forceinline__ void d_pair_up(const T* __restrict__ f0, const T* __r
     const int bi = c % (2 * kPairTile), bj = c / (2 * kPairTile);
     const int i = 2 * I0 + 1 + bi, j = 2 * J0 + 1 + bj;
     if (i <= nf0 && j <= nf0)
-      stg(eout0, (unsigned)((j - 1) * p0 + (i - 1)), su0[bj + H][bi + H]);
+      stg(eout0, (__umul24(j - 1, p0) + (i - 1)), su0[bj + H][bi + H]);
   }
 }
 
