@@ -278,8 +278,9 @@ void enqueue_inner_more(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, int
       launch_pcg_init<float>(c, S.mg, S.r[t.cur_r], S.z);
       const int n_its = its >= 0 ? its : (t.S < 8 ? P->sc->step_its[t.S] : P->sc->its);
       for (int k = 0; k < n_its; ++k) {
+        // the refinement residual follows the last iteration: it needs no new z
         launch_pcg_iteration<float>(c, S.mg, k, S.x, S.r[t.cur_r], S.r[t.cur_r ^ 1], S.z,
-                                    S.p[t.cur_p], S.p[t.cur_p ^ 1]);
+                                    S.p[t.cur_p], S.p[t.cur_p ^ 1], k == n_its - 1);
         t.cur_r ^= 1;
         t.cur_p ^= 1;
       }

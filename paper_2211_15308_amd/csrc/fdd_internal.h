@@ -149,9 +149,11 @@ void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* 
 // Iteration k of the inner PCG in its single-reduction (Chronopoulos-Gear) form: z = V r and the
 // dots r.z, z.A z come from the previous V-cycle; p = z + beta p', x += alpha p, r -= alpha A p
 // (A p as a stencil of p), then the V-cycle of the new r yields the next z and dots.
+// update_only (the last scheduled iteration of a run that a refinement residual follows): the
+// update and the convergence test only; the next z would not be used.
 template <typename T>
 void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
-                          T* r_new, T* z, T* p_old, T* p_new);
+                          T* r_new, T* z, T* p_old, T* p_new, bool update_only = false);
 
 // FP64 refinement residual: uout = uin + e (uout = 0 on the first call; a plain copy once the
 // solve has converged), r = f - A uout.  The step's bookkeeping (convergence test, state of the

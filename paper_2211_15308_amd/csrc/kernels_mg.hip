@@ -56,6 +56,18 @@ __global__ __launch_bounds__(kBlock) void k_sum_dots(DevState* st, Reductions re
   d_sum_dots(red, k, st);
 }
 
+// Convergence test after the last scheduled update of a PCG run (in place of the V-cycle that
+// would follow it).  A run that has not converged counts the iteration, so that its recorded
+// length tells the schedule that this run needed more.
+__global__ __launch_bounds__(kBlock) void k_run_check(DevState* st, Reductions red) {
+  if (stopped(st)) return;
+  if (!pcg_converged(st, red, true) && thread0()) {
+    st->inner_its += 1;
+    st->pcg_k += 1;
+    st->run_its_max = max(st->run_its_max, st->pcg_k);
+  }
+}
+
 template <typename T, int NU, bool CG, int TT = kTile>
 __global__ __launch_bounds__(kBlock) void k_mg_up(
     const T* __restrict__ fin, const T* __restrict__ upre, const T* __restrict__ ec,
@@ -241,7 +253,7 @@ void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* 
 
 template <typename T, int NU>
 static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
-                        T* r_new, T* z, T* p_old, T* p_new) {
+                        T* r_new, T* z, T* p_old, T* p_new, bool update_only) {
   const Level& L = c.lev[0];
   // beyond kPresumTiles tiles the dot products are summed once, by one block, instead of by
   // every block of the down kernel (same order, same values)
@@ -249,14 +261,20 @@ static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x,
   if (presum) hipLaunchKernelGGL(k_sum_dots, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red, k);
   // FP32 grids of at most kResidentTiles tiles run the down kernel's RESIDENT form (every tile
   // in flight at once, four blocks per compute unit)
-  if (sizeof(T) != 4 || c.red.nb0 > kResidentTiles) {
-    launch_timed(c.hook, kTimeDown0, k_mg_down<T, NU, true, kTile, false>, tiles(L.nf), tblock(),
-                 c.stream, (const T*)r_old, mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch,
-                 (const T*)z, (const T*)p_old, p_new, x, r_new, c.st, c.red, k, 0, 0, presum);
+  auto down0 = [&](auto kernel) {
+    launch_timed(c.hook, kTimeDown0, kernel, tiles(L.nf), tblock(), c.stream, (const T*)r_old,
+                 mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)z, (const T*)p_old,
+                 p_new, x, r_new, c.st, c.red, k, 0, 0, presum);
+  };
+  if constexpr (sizeof(T) == 4) {
+    if (c.red.nb0 <= kResidentTiles) down0(k_mg_down<T, NU, true, kTile, true>);
+    else down0(k_mg_down<T, NU, true, kTile, false>);
   } else {
-    launch_timed(c.hook, kTimeDown0, k_mg_down<T, NU, true, kTile, true>, tiles(L.nf), tblock(),
-                 c.stream, (const T*)r_old, mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch,
-                 (const T*)z, (const T*)p_old, p_new, x, r_new, c.st, c.red, k, 0, 0, presum);
+    down0(k_mg_down<T, NU, true, kTile, false>);
+  }
+  if (update_only) {
+    hipLaunchKernelGGL(k_run_check, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red);
+    return;
   }
   vcycle_tail_nu<T, NU>(c, mg, 1);
   launch_timed(c.hook, kTimeUp0, k_mg_up<T, NU, true>, tiles(L.nf), tblock(), c.stream,
@@ -266,9 +284,9 @@ static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x,
 
 template <typename T>
 void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
-                          T* r_new, T* z, T* p_old, T* p_new) {
-  if (c.nu == 2) pcg_iter_nu<T, 2>(c, mg, k, x, r_old, r_new, z, p_old, p_new);
-  else pcg_iter_nu<T, 1>(c, mg, k, x, r_old, r_new, z, p_old, p_new);
+                          T* r_new, T* z, T* p_old, T* p_new, bool update_only) {
+  if (c.nu == 2) pcg_iter_nu<T, 2>(c, mg, k, x, r_old, r_new, z, p_old, p_new, update_only);
+  else pcg_iter_nu<T, 1>(c, mg, k, x, r_old, r_new, z, p_old, p_new, update_only);
 }
 
 void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin, const float* e32,
@@ -298,8 +316,9 @@ template void launch_pcg_init<float>(const LaunchCtx&, const MGBuffers<float>&, 
 template void launch_pcg_init<double>(const LaunchCtx&, const MGBuffers<double>&, const double*,
                                       double*);
 template void launch_pcg_iteration<float>(const LaunchCtx&, const MGBuffers<float>&, int, float*,
-                                          float*, float*, float*, float*, float*);
+                                          float*, float*, float*, float*, float*, bool);
 template void launch_pcg_iteration<double>(const LaunchCtx&, const MGBuffers<double>&, int,
-                                           double*, double*, double*, double*, double*, double*);
+                                           double*, double*, double*, double*, double*, double*,
+                                           bool);
 
 }  // namespace fdd
