@@ -85,6 +85,20 @@ __global__ __launch_bounds__(kBlock) void kb_dots(const BInst* __restrict__ I, i
   d_sum_dots(P.red, k, st);
 }
 
+// Convergence test of every instance after the last scheduled update of its PCG run (in place of
+// the V-cycle that would follow it); a run that has not converged counts the iteration.
+__global__ __launch_bounds__(kBlock) void kb_run_check(const BInst* __restrict__ I,
+                                                       int skip_done) {
+  const BInst& P = I[blockIdx.x];
+  DevState* st = P.st;
+  if (inst_idle(st, skip_done) || stopped(st)) return;
+  if (!pcg_converged(st, P.red, true) && thread0()) {
+    st->inner_its += 1;
+    st->pcg_k += 1;
+    st->run_its_max = max(st->run_its_max, st->pcg_k);
+  }
+}
+
 template <int NU, bool CG, int TT>
 __global__ __launch_bounds__(kBlock) void kb_mg_up(const BInst* __restrict__ I, BLists L,
                                                    int level, int kn, int count, int cur_r,
@@ -311,6 +325,14 @@ static void b_step(const BatchCtx& c, int rhs, int ver, int its, int S, int& cur
     launch_timed(c.hook, kTimeDown0, kb_mg_down<NU, true, kTile>, dim3(c.tiles_total[0]), tb(),
                  c.stream,
                  c.inst, c.lists, 0, k, cur_r, cur_p, 0, c.skip_done);
+    if (k == its - 1) {
+      // the refinement residual follows: no V-cycle for a z that would not be used
+      hipLaunchKernelGGL(kb_run_check, dim3(c.lists.ninst), tb(), 0, c.stream, c.inst,
+                         c.skip_done);
+      cur_r ^= 1;
+      cur_p ^= 1;
+      break;
+    }
     b_tail<NU>(c, 1);
     launch_timed(c.hook, kTimeUp0, kb_mg_up<NU, true, kTile>, dim3(c.tiles_total[0]), tb(),
                  c.stream,
