@@ -104,6 +104,19 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_up(
 }
 
 template <typename T, int NU>
+__global__ __launch_bounds__(kPairThreads) void k_triple_up(
+    const T* __restrict__ f0, const T* __restrict__ u0pre, const T* __restrict__ f1,
+    const T* __restrict__ u1pre, const T* __restrict__ f2, const T* __restrict__ u2pre,
+    const T* __restrict__ e3, T* __restrict__ eout0, int nf0, int p0, int p1, int p2, int p3,
+    DevState* st) {
+  if (stopped(st)) return;
+  int tile_x, tile_y;
+  (void)xcd_tile(&tile_x, &tile_y);
+  d_triple_up<T, NU>(f0, u0pre, f1, u1pre, f2, u2pre, e3, eout0, nf0, p0, p1, p2, p3, tile_x,
+                     tile_y);
+}
+
+template <typename T, int NU>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(
     const T* __restrict__ fin, int pin, T* __restrict__ eout, LaunchLevels lv,
     const T* __restrict__ cinv, DevState* st, Reductions red, int check) {
@@ -216,11 +229,25 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
                        c.st, c.red, 0, 0);
   }
   if (kPairs && ntiled % 2 == 1) {
-    const Level& L = c.lev[l];
-    hipLaunchKernelGGL((k_mg_up<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0, c.stream,
-                       mg.f[l], mg.u[l], mg.e[l + 1], mg.e[l], L.nf, L.pitch, c.lev[l + 1].pitch,
-                       c.st, c.red, 0, 0);
-    --l;
+    if constexpr (kPairs) {
+      if (ntiled >= 3) {
+        // the level that ran alone and the pair above it, in one kernel
+        const int a = l - 2;
+        hipLaunchKernelGGL((k_triple_up<float, NU>), ptiles(c.lev[a + 1].nf), pblock, 0,
+                           c.stream, (const float*)mg.f[a], (const float*)mg.u[a],
+                           (const float*)mg.f[a + 1], (const float*)mg.u[a + 1],
+                           (const float*)mg.f[a + 2], (const float*)mg.u[a + 2],
+                           (const float*)mg.e[a + 3], mg.e[a], c.lev[a].nf, c.lev[a].pitch,
+                           c.lev[a + 1].pitch, c.lev[a + 2].pitch, c.lev[a + 3].pitch, c.st);
+        l -= 3;
+      } else {
+        const Level& L = c.lev[l];
+        hipLaunchKernelGGL((k_mg_up<T, NU, false, kMidTile>), mtiles(L.nf), tblock(), 0,
+                           c.stream, mg.f[l], mg.u[l], mg.e[l + 1], mg.e[l], L.nf, L.pitch,
+                           c.lev[l + 1].pitch, c.st, c.red, 0, 0);
+        --l;
+      }
+    }
   }
   if constexpr (kPairs) {
     for (; l >= 2; l -= 2) {
