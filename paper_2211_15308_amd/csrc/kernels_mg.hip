@@ -103,17 +103,17 @@ __global__ __launch_bounds__(kPairThreads) void k_pair_up(
   d_pair_up<T, NU>(f0, u0pre, f1, u1pre, e2, eout0, nf0, p0, p1, p2, tile_x, tile_y);
 }
 
-template <typename T, int NU>
+template <int NU>
 __global__ __launch_bounds__(kPairThreads) void k_triple_up(
-    const T* __restrict__ f0, const T* __restrict__ u0pre, const T* __restrict__ f1,
-    const T* __restrict__ u1pre, const T* __restrict__ f2, const T* __restrict__ u2pre,
-    const T* __restrict__ e3, T* __restrict__ eout0, int nf0, int p0, int p1, int p2, int p3,
-    DevState* st) {
+    const float* __restrict__ f0, const float* __restrict__ u0pre, const float* __restrict__ f1,
+    const float* __restrict__ u1pre, const float* __restrict__ f2, const float* __restrict__ u2pre,
+    const float* __restrict__ f3, const float* __restrict__ S, const float* __restrict__ lam,
+    float* __restrict__ eout0, int nf0, int p0, int p1, int p2, int p3, DevState* st) {
   if (stopped(st)) return;
   int tile_x, tile_y;
   (void)xcd_tile(&tile_x, &tile_y);
-  d_triple_up<T, NU>(f0, u0pre, f1, u1pre, f2, u2pre, e3, eout0, nf0, p0, p1, p2, p3, tile_x,
-                     tile_y);
+  d_triple_up<NU>(f0, u0pre, f1, u1pre, f2, u2pre, f3, S, lam, eout0, nf0, p0, p1, p2, p3, tile_x,
+                  tile_y);
 }
 
 template <typename T, int NU>
@@ -205,10 +205,14 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
                          (T*)nullptr, c.st, c.red, 0, chk, 0, 0);
     }
   }
+  // (FP32 with an odd number of at least three tiled levels: the coarse solve runs inside the
+  // three-level up kernel)
+  const bool triple = kPairs && fc - 1 >= 3 && (fc - 1) % 2 == 1;
   if constexpr (sizeof(T) == 4) {
-    launch_timed(c.hook, kTimeCoarse, k_coarse_dst, dim3(1), dim3(kCoarseThreads), c.stream,
-                 (const float*)mg.f[fc], c.lev[fc].pitch, (float*)mg.e[fc], c.lev[fc].nf, c.dst_S,
-                 c.dst_lam, c.st, c.red, fc == 1 ? check : 0);
+    if (!triple)
+      launch_timed(c.hook, kTimeCoarse, k_coarse_dst, dim3(1), dim3(kCoarseThreads), c.stream,
+                   (const float*)mg.f[fc], c.lev[fc].pitch, (float*)mg.e[fc], c.lev[fc].nf,
+                   c.dst_S, c.dst_lam, c.st, c.red, fc == 1 ? check : 0);
   } else {
     LaunchLevels lv;
     lv.first = fc;
@@ -231,14 +235,15 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
   if (kPairs && ntiled % 2 == 1) {
     if constexpr (kPairs) {
       if (ntiled >= 3) {
-        // the level that ran alone and the pair above it, in one kernel
+        // the coarse solve, the level that ran alone and the pair above it, in one kernel
         const int a = l - 2;
-        hipLaunchKernelGGL((k_triple_up<float, NU>), ptiles(c.lev[a + 1].nf), pblock, 0,
-                           c.stream, (const float*)mg.f[a], (const float*)mg.u[a],
+        hipLaunchKernelGGL((k_triple_up<NU>), ptiles(c.lev[a + 1].nf), pblock, 0, c.stream,
+                           (const float*)mg.f[a], (const float*)mg.u[a],
                            (const float*)mg.f[a + 1], (const float*)mg.u[a + 1],
                            (const float*)mg.f[a + 2], (const float*)mg.u[a + 2],
-                           (const float*)mg.e[a + 3], mg.e[a], c.lev[a].nf, c.lev[a].pitch,
-                           c.lev[a + 1].pitch, c.lev[a + 2].pitch, c.lev[a + 3].pitch, c.st);
+                           (const float*)mg.f[a + 3], c.dst_S, c.dst_lam, mg.e[a], c.lev[a].nf,
+                           c.lev[a].pitch, c.lev[a + 1].pitch, c.lev[a + 2].pitch,
+                           c.lev[a + 3].pitch, c.st);
         l -= 3;
       } else {
         const Level& L = c.lev[l];

@@ -846,152 +846,6 @@ __device__ __forceinline__ void d_pair_up(const T* __restrict__ f0, const T* __r
   }
 }
 
-// Three levels going up: level l+2 as the intermediate-level up kernel does (u_{l+2} =
-// u_{l+2,pre} + P e_{l+3}, 2 nu half-sweeps), on a window whose valid part covers the coarse
-// patch that level l+1 interpolates from; then levels l+1 and l as d_pair_up.  It replaces that
-// kernel and the pair kernel above it (one launch fewer per V-cycle where the last tiled level
-// runs alone); every cell sees the same operations, so the results are bit-identical.
-template <int NU>
-struct TripleUp {
-  using G = PairUp<NU>;
-  static constexpr int H = G::H;
-  static constexpr int W2r = G::CW2 + 2 * H;            // level-(l+2) window around the patch
-  static constexpr int W2 = W2r + (W2r & 1);             // (even: the sweeps take column pairs)
-  static constexpr int CW3 = W2 / 2 + 2;                 // coarse patch of level l+3
-  static constexpr int N2 = (W2 * W2 + kPairThreads - 1) / kPairThreads;
-  static constexpr int N3 = (CW3 * CW3 + kPairThreads - 1) / kPairThreads;
-};
-
-template <typename T, int NU>
-__device__ __forceinline__ void d_triple_up(const T* __restrict__ f0, const T* __restrict__ u0pre,
-                                            const T* __restrict__ f1, const T* __restrict__ u1pre,
-                                            const T* __restrict__ f2, const T* __restrict__ u2pre,
-                                            const T* __restrict__ e3, T* __restrict__ eout0,
-                                            int nf0, int p0, int p1, int p2, int p3, int tile_x,
-                                            int tile_y) {
-  using G = PairUp<NU>;
-  using G3 = TripleUp<NU>;
-  constexpr int H = G::H, W0 = G::W0, W1 = G::W1, CW2 = G::CW2, W2 = G3::W2, CW3 = G3::CW3;
-  __shared__ T sf0[W0][W0 + 1];
-  __shared__ T su0[W0][W0 + 1];
-  __shared__ T sf1[W1][W1 + 1];
-  __shared__ T su1[W1][W1 + 1];
-  __shared__ T sf2[W2][W2 + 1];
-  __shared__ T su2[W2][W2 + 1];
-  __shared__ T sc3[CW3][CW3 + 1];
-  const int t = flat_tid();
-  __builtin_assume(t >= 0 && t < kPairThreads);
-  const int nf1 = (nf0 - 1) >> 1, nf2 = (nf1 - 1) >> 1, nf3 = (nf2 - 1) >> 1;
-  const int I0 = tile_x * kPairTile, J0 = tile_y * kPairTile;
-  const int ib0 = 2 * I0 + 1 - H, jb0 = 2 * J0 + 1 - H;  // level-l window origin
-  const int Ic = ib0 >> 1, Jc = jb0 >> 1;                // its coarse patch origin (floor)
-  const int ib1 = Ic - H, jb1 = Jc - H;                  // level-(l+1) window origin
-  const int Ic2 = ib1 >> 1, Jc2 = jb1 >> 1;              // coarse patch of level l+2
-  const int ib2 = Ic2 - H, jb2 = Jc2 - H;                // level-(l+2) window origin
-  const int Ic3 = ib2 >> 1, Jc3 = jb2 >> 1;              // coarse patch of level l+3
-  T f2r[G3::N2], u2r[G3::N2], c3r[G3::N3], f1r[G::N1], u1r[G::N1], f0r[G::N0], u0r[G::N0];
-#pragma unroll
-  for (int q = 0; q < G3::N3; ++q) {
-    const int c = t + kPairThreads * q;
-    const int I = Ic3 + c % CW3, J = Jc3 + c / CW3;
-    const bool in = c < CW3 * CW3 && I >= 1 && I <= nf3 && J >= 1 && J <= nf3;
-    c3r[q] = in ? ldg(e3, (__umul24(J - 1, p3) + (I - 1))) : T(0);
-  }
-#pragma unroll
-  for (int q = 0; q < G3::N2; ++q) {
-    const int c = t + kPairThreads * q;
-    const int i = ib2 + c % W2, j = jb2 + c / W2;
-    const bool in = c < W2 * W2 && i >= 1 && i <= nf2 && j >= 1 && j <= nf2;
-    const unsigned o = (__umul24(j - 1, p2) + (i - 1));
-    f2r[q] = in ? ldg(f2, o) : T(0);
-    u2r[q] = in ? ldg(u2pre, o) : T(0);
-  }
-#pragma unroll
-  for (int q = 0; q < G::N1; ++q) {
-    const int c = t + kPairThreads * q;
-    const int i = ib1 + c % W1, j = jb1 + c / W1;
-    const bool in = c < W1 * W1 && i >= 1 && i <= nf1 && j >= 1 && j <= nf1;
-    const unsigned o = (__umul24(j - 1, p1) + (i - 1));
-    f1r[q] = in ? ldg(f1, o) : T(0);
-    u1r[q] = in ? ldg(u1pre, o) : T(0);
-  }
-#pragma unroll
-  for (int q = 0; q < G::N0; ++q) {
-    const int c = t + kPairThreads * q;
-    const int i = ib0 + c % W0, j = jb0 + c / W0;
-    const bool in = c < W0 * W0 && i >= 1 && i <= nf0 && j >= 1 && j <= nf0;
-    const unsigned o = (__umul24(j - 1, p0) + (i - 1));
-    f0r[q] = in ? ldg(f0, o) : T(0);
-    u0r[q] = in ? ldg(u0pre, o) : T(0);
-  }
-#pragma unroll
-  for (int q = 0; q < G3::N3; ++q) {
-    const int c = t + kPairThreads * q;
-    if (c < CW3 * CW3) sc3[c / CW3][c % CW3] = c3r[q];
-  }
-  __syncthreads();
-  // level l+2: prolongation of e_{l+3} plus the pre-smoothed iterate, 2 nu half-sweeps
-#pragma unroll
-  for (int q = 0; q < G3::N2; ++q) {
-    const int c = t + kPairThreads * q;
-    if (c >= W2 * W2) continue;
-    const int lj = c / W2, li = c % W2;
-    const int i = ib2 + li, j = jb2 + lj;
-    T u = T(0);
-    if (i >= 1 && i <= nf2 && j >= 1 && j <= nf2) {
-      const int ci = (i >> 1) - Ic3, cj = (j >> 1) - Jc3;
-      const T e = T(0.5) * (sc3[cj][ci] + sc3[cj + (j & 1)][ci + (i & 1)]);
-      u = u2r[q] + e;
-    }
-    sf2[lj][li] = f2r[q];
-    su2[lj][li] = u;
-  }
-  __syncthreads();
-  tile_sweeps<T, W2, 2 * NU, kPairThreads>(su2, sf2, ib2, jb2, nf2, false);  // black, red, ...
-  // level l+1: the corrected level-(l+2) values on its patch are su2[H + c][H + d]
-#pragma unroll
-  for (int q = 0; q < G::N1; ++q) {
-    const int c = t + kPairThreads * q;
-    if (c >= W1 * W1) continue;
-    const int lj = c / W1, li = c % W1;
-    const int i = ib1 + li, j = jb1 + lj;
-    T u = T(0);
-    if (i >= 1 && i <= nf1 && j >= 1 && j <= nf1) {
-      const int ci = H + (i >> 1) - Ic2, cj = H + (j >> 1) - Jc2;
-      const T e = T(0.5) * (su2[cj][ci] + su2[cj + (j & 1)][ci + (i & 1)]);
-      u = u1r[q] + e;
-    }
-    sf1[lj][li] = f1r[q];
-    su1[lj][li] = u;
-  }
-  __syncthreads();
-  tile_sweeps<T, W1, 2 * NU, kPairThreads>(su1, sf1, ib1, jb1, nf1, false);
-  // level l
-#pragma unroll
-  for (int q = 0; q < G::N0; ++q) {
-    const int c = t + kPairThreads * q;
-    if (c >= W0 * W0) continue;
-    const int lj = c / W0, li = c % W0;
-    const int i = ib0 + li, j = jb0 + lj;
-    T u = T(0);
-    if (i >= 1 && i <= nf0 && j >= 1 && j <= nf0) {
-      const int ci = H + (i >> 1) - Ic, cj = H + (j >> 1) - Jc;
-      const T e = T(0.5) * (su1[cj][ci] + su1[cj + (j & 1)][ci + (i & 1)]);
-      u = u0r[q] + e;
-    }
-    sf0[lj][li] = f0r[q];
-    su0[lj][li] = u;
-  }
-  __syncthreads();
-  tile_sweeps<T, W0, 2 * NU, kPairThreads>(su0, sf0, ib0, jb0, nf0, false);
-  for (int c = t; c < 4 * kPairTile * kPairTile; c += kPairThreads) {
-    const int bi = c % (2 * kPairTile), bj = c / (2 * kPairTile);
-    const int i = 2 * I0 + 1 + bi, j = 2 * J0 + 1 + bj;
-    if (i <= nf0 && j <= nf0)
-      stg(eout0, (__umul24(j - 1, p0) + (i - 1)), su0[bj + H][bi + H]);
-  }
-}
-
 // --------------------------------------------------------------------------------------------
 // coarse levels in one workgroup
 // --------------------------------------------------------------------------------------------
@@ -1269,6 +1123,194 @@ __device__ __forceinline__ void d_coarse_dst(const float* __restrict__ fin, int 
   for (int q = 0; q < 4; ++q) {
     const int p = row0 + q;
     if (p < m && col < m) stg(eout, (unsigned)(p * pin + col), acc[q]);
+  }
+}
+
+// The coarse solve and three levels going up, in FP32: every block first solves the coarse level
+// l+3 (m x m points) exactly by sine transforms, as d_coarse_dst does, into LDS; then level l+2
+// as the intermediate-level up kernel does (u_{l+2} = u_{l+2,pre} + P e_{l+3}, 2 nu half-sweeps),
+// on a window whose valid part covers the coarse patch that level l+1 interpolates from; then
+// levels l+1 and l as d_pair_up.  It replaces the coarse kernel, that up kernel and the pair
+// kernel above it (two launches fewer per V-cycle where the last tiled level runs alone); each
+// block repeats the coarse solve (a few microseconds of matrix-core work, in parallel on every
+// compute unit) instead of waiting for it.  Every value sees the same operations as in the
+// separate kernels, so the results are bit-identical.
+template <int NU>
+struct TripleUp {
+  using G = PairUp<NU>;
+  static constexpr int H = G::H;
+  static constexpr int W2r = G::CW2 + 2 * H;            // level-(l+2) window around the patch
+  static constexpr int W2 = W2r + (W2r & 1);             // (even: the sweeps take column pairs)
+  static constexpr int N2 = (W2 * W2 + kPairThreads - 1) / kPairThreads;
+};
+
+template <int NU>
+__device__ __forceinline__ void d_triple_up(
+    const float* __restrict__ f0, const float* __restrict__ u0pre, const float* __restrict__ f1,
+    const float* __restrict__ u1pre, const float* __restrict__ f2, const float* __restrict__ u2pre,
+    const float* __restrict__ f3, const float* __restrict__ Sg, const float* __restrict__ lamg,
+    float* __restrict__ eout0, int nf0, int p0, int p1, int p2, int p3, int tile_x, int tile_y) {
+  using T = float;
+  using G = PairUp<NU>;
+  using G3 = TripleUp<NU>;
+  constexpr int H = G::H, W0 = G::W0, W1 = G::W1, W2 = G3::W2;
+  static_assert(kPairThreads == 1024 && kDstN == 64, "16 waves, 4 x 4 tiles of 16 x 16");
+  constexpr int Q = kDstN * kDstN / kPairThreads;
+  __shared__ T sf0[W0][W0 + 1];
+  __shared__ T su0[W0][W0 + 1];
+  __shared__ T sf1[W1][W1 + 1];
+  __shared__ T su1[W1][W1 + 1];
+  __shared__ T sf2[W2][W2 + 1];
+  __shared__ T su2[W2][W2 + 1];
+  __shared__ float sS[kDstN * kDstP];
+  __shared__ float sX[kDstN * kDstP];
+  __shared__ float sY[kDstN * kDstP];
+  __shared__ float sl[kDstN];
+  __shared__ float se[kDstN + 1][kDstN + 2];  // e_{l+3} by coarse index, zero ring
+  const int t = flat_tid();
+  __builtin_assume(t >= 0 && t < kPairThreads);
+  const int nf1 = (nf0 - 1) >> 1, nf2 = (nf1 - 1) >> 1, nf3 = (nf2 - 1) >> 1;
+  const int I0 = tile_x * kPairTile, J0 = tile_y * kPairTile;
+  const int ib0 = 2 * I0 + 1 - H, jb0 = 2 * J0 + 1 - H;  // level-l window origin
+  const int Ic = ib0 >> 1, Jc = jb0 >> 1;                // its coarse patch origin (floor)
+  const int ib1 = Ic - H, jb1 = Jc - H;                  // level-(l+1) window origin
+  const int Ic2 = ib1 >> 1, Jc2 = jb1 >> 1;              // coarse patch of level l+2
+  const int ib2 = Ic2 - H, jb2 = Jc2 - H;                // level-(l+2) window origin
+  const int m = nf3;                                     // coarse level: m x m points
+  float sv[Q], fv[Q];
+  T f2r[G3::N2], u2r[G3::N2], f1r[G::N1], u1r[G::N1], f0r[G::N0], u0r[G::N0];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = t + kPairThreads * q;
+    const int row = idx / kDstN, col = idx % kDstN;
+    sv[q] = ldg(Sg, (unsigned)idx);
+    fv[q] = (row < m && col < m) ? ldg(f3, (unsigned)(row * p3 + col)) : 0.f;
+  }
+  const float lv = t < kDstN ? ldg(lamg, (unsigned)t) : 0.f;
+#pragma unroll
+  for (int q = 0; q < G3::N2; ++q) {
+    const int c = t + kPairThreads * q;
+    const int i = ib2 + c % W2, j = jb2 + c / W2;
+    const bool in = c < W2 * W2 && i >= 1 && i <= nf2 && j >= 1 && j <= nf2;
+    const unsigned o = (__umul24(j - 1, p2) + (i - 1));
+    f2r[q] = in ? ldg(f2, o) : T(0);
+    u2r[q] = in ? ldg(u2pre, o) : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < G::N1; ++q) {
+    const int c = t + kPairThreads * q;
+    const int i = ib1 + c % W1, j = jb1 + c / W1;
+    const bool in = c < W1 * W1 && i >= 1 && i <= nf1 && j >= 1 && j <= nf1;
+    const unsigned o = (__umul24(j - 1, p1) + (i - 1));
+    f1r[q] = in ? ldg(f1, o) : T(0);
+    u1r[q] = in ? ldg(u1pre, o) : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < G::N0; ++q) {
+    const int c = t + kPairThreads * q;
+    const int i = ib0 + c % W0, j = jb0 + c / W0;
+    const bool in = c < W0 * W0 && i >= 1 && i <= nf0 && j >= 1 && j <= nf0;
+    const unsigned o = (__umul24(j - 1, p0) + (i - 1));
+    f0r[q] = in ? ldg(f0, o) : T(0);
+    u0r[q] = in ? ldg(u0pre, o) : T(0);
+  }
+  // the coarse solve e = S ((S F S) ./ (c_p + c_q)) S, as in d_coarse_dst
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = t + kPairThreads * q;
+    const int row = idx / kDstN, col = idx % kDstN;
+    sS[row * kDstP + col] = sv[q];
+    sX[row * kDstP + col] = fv[q];
+  }
+  if (t < kDstN) sl[t] = lv;
+  for (int c = t; c < (kDstN + 1) * (kDstN + 2); c += kPairThreads) (&se[0][0])[c] = 0.f;
+  __syncthreads();
+  {
+    const int w = t >> 6, lane = t & 63;
+    const int ti = w >> 2, tj = w & 3;
+    const int col = 16 * tj + (lane & 15), row0 = 16 * ti + 4 * (lane >> 4);
+    dst_f4 acc = dst_tile(sS, sX, ti, tj, lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sY[(row0 + q) * kDstP + col] = acc[q];
+    __syncthreads();
+    acc = dst_tile(sY, sS, ti, tj, lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int p = row0 + q;
+      sX[p * kDstP + col] = (p < m && col < m) ? acc[q] / (sl[p] + sl[col]) : 0.f;
+    }
+    __syncthreads();
+    acc = dst_tile(sS, sX, ti, tj, lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sY[(row0 + q) * kDstP + col] = acc[q];
+    __syncthreads();
+    acc = dst_tile(sY, sS, ti, tj, lane);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int p = row0 + q;
+      if (p < m && col < m) se[p + 1][col + 1] = acc[q];
+    }
+  }
+  __syncthreads();
+  // level l+2: prolongation of e_{l+3} plus the pre-smoothed iterate, 2 nu half-sweeps
+#pragma unroll
+  for (int q = 0; q < G3::N2; ++q) {
+    const int c = t + kPairThreads * q;
+    if (c >= W2 * W2) continue;
+    const int lj = c / W2, li = c % W2;
+    const int i = ib2 + li, j = jb2 + lj;
+    T u = T(0);
+    if (i >= 1 && i <= nf2 && j >= 1 && j <= nf2) {
+      const int ci = i >> 1, cj = j >> 1;
+      const T e = T(0.5) * (se[cj][ci] + se[cj + (j & 1)][ci + (i & 1)]);
+      u = u2r[q] + e;
+    }
+    sf2[lj][li] = f2r[q];
+    su2[lj][li] = u;
+  }
+  __syncthreads();
+  tile_sweeps<T, W2, 2 * NU, kPairThreads>(su2, sf2, ib2, jb2, nf2, false);  // black, red, ...
+  // level l+1: the corrected level-(l+2) values on its patch are su2[H + c][H + d]
+#pragma unroll
+  for (int q = 0; q < G::N1; ++q) {
+    const int c = t + kPairThreads * q;
+    if (c >= W1 * W1) continue;
+    const int lj = c / W1, li = c % W1;
+    const int i = ib1 + li, j = jb1 + lj;
+    T u = T(0);
+    if (i >= 1 && i <= nf1 && j >= 1 && j <= nf1) {
+      const int ci = H + (i >> 1) - Ic2, cj = H + (j >> 1) - Jc2;
+      const T e = T(0.5) * (su2[cj][ci] + su2[cj + (j & 1)][ci + (i & 1)]);
+      u = u1r[q] + e;
+    }
+    sf1[lj][li] = f1r[q];
+    su1[lj][li] = u;
+  }
+  __syncthreads();
+  tile_sweeps<T, W1, 2 * NU, kPairThreads>(su1, sf1, ib1, jb1, nf1, false);
+  // level l
+#pragma unroll
+  for (int q = 0; q < G::N0; ++q) {
+    const int c = t + kPairThreads * q;
+    if (c >= W0 * W0) continue;
+    const int lj = c / W0, li = c % W0;
+    const int i = ib0 + li, j = jb0 + lj;
+    T u = T(0);
+    if (i >= 1 && i <= nf0 && j >= 1 && j <= nf0) {
+      const int ci = H + (i >> 1) - Ic, cj = H + (j >> 1) - Jc;
+      const T e = T(0.5) * (su1[cj][ci] + su1[cj + (j & 1)][ci + (i & 1)]);
+      u = u0r[q] + e;
+    }
+    sf0[lj][li] = f0r[q];
+    su0[lj][li] = u;
+  }
+  __syncthreads();
+  tile_sweeps<T, W0, 2 * NU, kPairThreads>(su0, sf0, ib0, jb0, nf0, false);
+  for (int c = t; c < 4 * kPairTile * kPairTile; c += kPairThreads) {
+    const int bi = c % (2 * kPairTile), bj = c / (2 * kPairTile);
+    const int i = 2 * I0 + 1 + bi, j = 2 * J0 + 1 + bj;
+    if (i <= nf0 && j <= nf0)
+      stg(eout0, (__umul24(j - 1, p0) + (i - 1)), su0[bj + H][bi + H]);
   }
 }
 
