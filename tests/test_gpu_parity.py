@@ -195,6 +195,29 @@ def test_solve_against_separable_oracle(n, K, mu, back_solve):
     assert st["outer_its"] <= 20
 
 
+@pytest.mark.parametrize("nu", [1, 2])
+@pytest.mark.parametrize("n", [640, 768])
+def test_solve_three_level_up_with_a_small_coarse_level(n, nu):
+    # 767 -> (383, 191) -> 95 -> 47 and 639 -> (319, 159) -> 79 -> 39: the three-level up kernel
+    # (coarse solve inside every block) with a coarse level below 63^2, so its sine transforms run
+    # on zero-padded 64 x 64 arrays
+    K, mu = 1.0, 1e-3
+    print(f"[solve three-level up] n={n} nu={nu}", flush=True)
+    P = make(n, K, mu)
+    TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+    TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+    b = workloads.rhs(2, n, 7000 + n + nu)
+    x = torch.zeros_like(dev(b))
+    st = P.solve(TP, TH, dev(b), x, F.opts_default(mg_nu=nu, check_true_residual=1))
+    x_ref = system.solve_dst_2d(n, K, mu, b)
+    err = rel(host(x), x_ref)
+    print(f"  rel err {err:.3e}  outer {st['outer_its']} inner {st['inner_its_total']} "
+          f"true res {st['true_rel_res']:.2e}", flush=True)
+    assert st["status"] == F.FDD_OK
+    assert err <= 1e-6
+    assert st["true_rel_res"] <= 1e-7
+
+
 @pytest.mark.parametrize("n", [1024, 2048])
 def test_solve_full_size_at_bench_settings(n):
     # the benchmark's launch configuration: mixed precision, outer rtol 1e-8, inner rtol 1e-10
