@@ -1065,36 +1065,42 @@ __device__ __forceinline__ dst_f4 dst_tile(const float* A, const float* B, int t
   return acc;
 }
 
-// e = A^{-1} f on the m x m level (m <= kDstN - 1); f and e in global memory with row pitch pin.
-// Needs kCoarseThreads = 1024 threads (16 waves).
-__device__ __forceinline__ void d_coarse_dst(const float* __restrict__ fin, int pin,
-                                             float* __restrict__ eout, int m,
-                                             const float* __restrict__ Sg,
-                                             const float* __restrict__ lamg) {
-  static_assert(kCoarseThreads == 1024 && kDstN == 64, "16 waves, 4 x 4 tiles of 16 x 16");
-  __shared__ float sS[kDstN * kDstP];
-  __shared__ float sX[kDstN * kDstP];
-  __shared__ float sY[kDstN * kDstP];
-  __shared__ float sl[kDstN];
-  const int t = threadIdx.x;
-  constexpr int Q = kDstN * kDstN / kCoarseThreads;
-  float sv[Q], fv[Q];
+// Operands of the sine-transform solve, loaded into registers by 1024 threads (S, the right-hand
+// side f of the m x m level with row pitch pin, zero-padded to kDstN x kDstN, and the symbols).
+struct DstIn {
+  static constexpr int Q = kDstN * kDstN / 1024;
+  float sv[Q], fv[Q], lv;
+};
+__device__ __forceinline__ void dst_load(DstIn& in, const float* __restrict__ fin, int pin, int m,
+                                         const float* __restrict__ Sg,
+                                         const float* __restrict__ lamg, int t) {
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int idx = t + kCoarseThreads * q;
+  for (int q = 0; q < DstIn::Q; ++q) {
+    const int idx = t + 1024 * q;
     const int row = idx / kDstN, col = idx % kDstN;
-    sv[q] = ldg(Sg, (unsigned)idx);
-    fv[q] = (row < m && col < m) ? ldg(fin, (unsigned)(row * pin + col)) : 0.f;
+    in.sv[q] = ldg(Sg, (unsigned)idx);
+    in.fv[q] = (row < m && col < m) ? ldg(fin, (unsigned)(row * pin + col)) : 0.f;
   }
-  const float lv = t < kDstN ? ldg(lamg, (unsigned)t) : 0.f;
+  in.lv = t < kDstN ? ldg(lamg, (unsigned)t) : 0.f;
+}
+
+// e = A^{-1} f on the m x m level (m <= kDstN - 1) from the loaded operands, in the LDS arrays
+// sS, sX, sY (kDstN x kDstP each) and sl (kDstN); needs 1024 threads (16 waves, each owning a
+// 16 x 16 tile of every product).  e(p, q) goes to out[(p + off) * opitch + q + off], a global
+// array (GLOBAL) or an LDS one.
+template <bool GLOBAL>
+__device__ __forceinline__ void dst_solve(const DstIn& in, float* sS, float* sX, float* sY,
+                                          float* sl, int m, int t, float* out, int opitch,
+                                          int off) {
+  static_assert(kDstN == 64, "4 x 4 tiles of 16 x 16");
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int idx = t + kCoarseThreads * q;
+  for (int q = 0; q < DstIn::Q; ++q) {
+    const int idx = t + 1024 * q;
     const int row = idx / kDstN, col = idx % kDstN;
-    sS[row * kDstP + col] = sv[q];
-    sX[row * kDstP + col] = fv[q];
+    sS[row * kDstP + col] = in.sv[q];
+    sX[row * kDstP + col] = in.fv[q];
   }
-  if (t < kDstN) sl[t] = lv;
+  if (t < kDstN) sl[t] = in.lv;
   __syncthreads();
   const int w = t >> 6, lane = t & 63;
   const int ti = w >> 2, tj = w & 3;
@@ -1122,8 +1128,29 @@ __device__ __forceinline__ void d_coarse_dst(const float* __restrict__ fin, int 
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int p = row0 + q;
-    if (p < m && col < m) stg(eout, (unsigned)(p * pin + col), acc[q]);
+    if (p < m && col < m) {
+      const unsigned o = (unsigned)((p + off) * opitch + col + off);
+      if constexpr (GLOBAL) stg(out, o, acc[q]);
+      else out[o] = acc[q];
+    }
   }
+}
+
+// e = A^{-1} f on the m x m level (m <= kDstN - 1); f and e in global memory with row pitch pin.
+// Needs kCoarseThreads = 1024 threads (16 waves).
+__device__ __forceinline__ void d_coarse_dst(const float* __restrict__ fin, int pin,
+                                             float* __restrict__ eout, int m,
+                                             const float* __restrict__ Sg,
+                                             const float* __restrict__ lamg) {
+  static_assert(kCoarseThreads == 1024, "16 waves");
+  __shared__ float sS[kDstN * kDstP];
+  __shared__ float sX[kDstN * kDstP];
+  __shared__ float sY[kDstN * kDstP];
+  __shared__ float sl[kDstN];
+  const int t = threadIdx.x;
+  DstIn in;
+  dst_load(in, fin, pin, m, Sg, lamg, t);
+  dst_solve<true>(in, sS, sX, sY, sl, m, t, eout, pin, 0);
 }
 
 // The coarse solve and three levels going up, in FP32: every block first solves the coarse level
@@ -1154,8 +1181,7 @@ __device__ __forceinline__ void d_triple_up(
   using G = PairUp<NU>;
   using G3 = TripleUp<NU>;
   constexpr int H = G::H, W0 = G::W0, W1 = G::W1, W2 = G3::W2;
-  static_assert(kPairThreads == 1024 && kDstN == 64, "16 waves, 4 x 4 tiles of 16 x 16");
-  constexpr int Q = kDstN * kDstN / kPairThreads;
+  static_assert(kPairThreads == 1024, "16 waves");
   __shared__ T sf0[W0][W0 + 1];
   __shared__ T su0[W0][W0 + 1];
   __shared__ T sf1[W1][W1 + 1];
@@ -1177,16 +1203,9 @@ __device__ __forceinline__ void d_triple_up(
   const int Ic2 = ib1 >> 1, Jc2 = jb1 >> 1;              // coarse patch of level l+2
   const int ib2 = Ic2 - H, jb2 = Jc2 - H;                // level-(l+2) window origin
   const int m = nf3;                                     // coarse level: m x m points
-  float sv[Q], fv[Q];
+  DstIn din;
+  dst_load(din, f3, p3, m, Sg, lamg, t);
   T f2r[G3::N2], u2r[G3::N2], f1r[G::N1], u1r[G::N1], f0r[G::N0], u0r[G::N0];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int idx = t + kPairThreads * q;
-    const int row = idx / kDstN, col = idx % kDstN;
-    sv[q] = ldg(Sg, (unsigned)idx);
-    fv[q] = (row < m && col < m) ? ldg(f3, (unsigned)(row * p3 + col)) : 0.f;
-  }
-  const float lv = t < kDstN ? ldg(lamg, (unsigned)t) : 0.f;
 #pragma unroll
   for (int q = 0; q < G3::N2; ++q) {
     const int c = t + kPairThreads * q;
@@ -1214,43 +1233,9 @@ __device__ __forceinline__ void d_triple_up(
     f0r[q] = in ? ldg(f0, o) : T(0);
     u0r[q] = in ? ldg(u0pre, o) : T(0);
   }
-  // the coarse solve e = S ((S F S) ./ (c_p + c_q)) S, as in d_coarse_dst
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int idx = t + kPairThreads * q;
-    const int row = idx / kDstN, col = idx % kDstN;
-    sS[row * kDstP + col] = sv[q];
-    sX[row * kDstP + col] = fv[q];
-  }
-  if (t < kDstN) sl[t] = lv;
+  // the coarse solve, as in d_coarse_dst, into se (zero ring)
   for (int c = t; c < (kDstN + 1) * (kDstN + 2); c += kPairThreads) (&se[0][0])[c] = 0.f;
-  __syncthreads();
-  {
-    const int w = t >> 6, lane = t & 63;
-    const int ti = w >> 2, tj = w & 3;
-    const int col = 16 * tj + (lane & 15), row0 = 16 * ti + 4 * (lane >> 4);
-    dst_f4 acc = dst_tile(sS, sX, ti, tj, lane);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sY[(row0 + q) * kDstP + col] = acc[q];
-    __syncthreads();
-    acc = dst_tile(sY, sS, ti, tj, lane);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int p = row0 + q;
-      sX[p * kDstP + col] = (p < m && col < m) ? acc[q] / (sl[p] + sl[col]) : 0.f;
-    }
-    __syncthreads();
-    acc = dst_tile(sS, sX, ti, tj, lane);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sY[(row0 + q) * kDstP + col] = acc[q];
-    __syncthreads();
-    acc = dst_tile(sY, sS, ti, tj, lane);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int p = row0 + q;
-      if (p < m && col < m) se[p + 1][col + 1] = acc[q];
-    }
-  }
+  dst_solve<false>(din, sS, sX, sY, sl, m, t, &se[0][0], kDstN + 2, 1);
   __syncthreads();
   // level l+2: prolongation of e_{l+3} plus the pre-smoothed iterate, 2 nu half-sweeps
 #pragma unroll
