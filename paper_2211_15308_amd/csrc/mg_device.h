@@ -1339,23 +1339,44 @@ __device__ __forceinline__ void d_ir_residual(
   constexpr int RY = Slots<W>::RY, RX = Slots<W>::RX;
   // first call: u = 0, or u = s g for a learned guess g (compact FP32 image) with scale s
   const double ws = (first && warm) ? *wscale : 0.0;
+  // window loads at clamped offsets (cells outside the grid read element 0 and are zeroed), all
+  // issued before any is used: one memory latency for the window, not one per slot
   double ur[RY][RX];
+  if (!first) {
+    double ua[RY][RX];
+    E ea[RY][RX];
 #pragma unroll
-  for (int a = 0; a < RY; ++a) {
+    for (int a = 0; a < RY; ++a)
 #pragma unroll
-    for (int b = 0; b < RX; ++b) {
-      const int lj = threadIdx.y + 8 * a, li = threadIdx.x + 32 * b;
-      const int i = i0 + li, j = j0 + lj;
-      const bool cell = lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
-      const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
-      double uv = 0.0;
-      if (!first) {
-        if (cell) uv = ldg(uin, o) + (double)ldg(e, o);
-      } else if (warm) {
-        if (cell) uv = ws * (double)ldg(warm, (unsigned)((j - 1) * nf + (i - 1)));
+      for (int b = 0; b < RX; ++b) {
+        const int lj = threadIdx.y + 8 * a, li = threadIdx.x + 32 * b;
+        const int i = i0 + li, j = j0 + lj;
+        const bool cell = lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+        const unsigned o = cell ? (unsigned)((j - 1) * pitch + (i - 1)) : 0u;
+        ua[a][b] = ldg(uin, o);
+        ea[a][b] = ldg(e, o);
       }
-      ur[a][b] = uv;
-    }
+#pragma unroll
+    for (int a = 0; a < RY; ++a)
+#pragma unroll
+      for (int b = 0; b < RX; ++b) {
+        const int lj = threadIdx.y + 8 * a, li = threadIdx.x + 32 * b;
+        const int i = i0 + li, j = j0 + lj;
+        const bool cell = lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+        ur[a][b] = cell ? ua[a][b] + (double)ea[a][b] : 0.0;
+      }
+  } else {
+    float wa[RY][RX];
+#pragma unroll
+    for (int a = 0; a < RY; ++a)
+#pragma unroll
+      for (int b = 0; b < RX; ++b) {
+        const int lj = threadIdx.y + 8 * a, li = threadIdx.x + 32 * b;
+        const int i = i0 + li, j = j0 + lj;
+        const bool cell = lj < W && li < W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+        wa[a][b] = warm ? ldg(warm, cell ? (unsigned)((j - 1) * nf + (i - 1)) : 0u) : 0.f;
+        ur[a][b] = (warm && cell) ? ws * (double)wa[a][b] : 0.0;
+      }
   }
 #pragma unroll
   for (int a = 0; a < RY; ++a)
@@ -1365,16 +1386,30 @@ __device__ __forceinline__ void d_ir_residual(
       if (lj < W && li < W) su[lj][li] = ur[a][b];
     }
   __syncthreads();
+  // own cells: column threadIdx.x, rows threadIdx.y + 8 q (32 x 8 threads); the right-hand side
+  // of all of them is loaded first (clamped offsets, as above)
+  constexpr int NQ = kTile / 8;
+  double fb[NQ];
+  const double gv = f.g ? ldg(f.g, (unsigned)min(i0 + (int)threadIdx.x, nf - 1)) : 0.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = i0 + 1 + (int)threadIdx.x, j = j0 + 1 + (int)threadIdx.y + 8 * q;
+    const bool own = i <= nf && j <= nf;
+    fb[q] = f.b ? ldg(f.b, own ? (unsigned)((j - 1) * nf + (i - 1)) : 0u) : 0.0;
+  }
   double rr = 0.0, fsq = 0.0;
-  for (int b = threadIdx.y; b < kTile; b += blockDim.y) {
-    const int j = j0 + 1 + b;
-    if (j > nf) continue;
-    for (int a = threadIdx.x; a < kTile; a += blockDim.x) {
-      const int i = i0 + 1 + a;
-      if (i > nf) continue;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int b = (int)threadIdx.y + 8 * q, a = (int)threadIdx.x;
+    const int j = j0 + 1 + b, i = i0 + 1 + a;
+    if (j > nf || i > nf) continue;
+    {
       const int li = a + 1, lj = b + 1;
       const double u = su[lj][li];
-      const double fv = rhs_at(f, nf, i, j);
+      // f = sb b + (on the row next to Gamma) sg g, in that order
+      double fv = 0.0;
+      if (f.b) fv = f.sb * fb[q];
+      if (f.g && j == nf) fv += f.sg * gv;
       const double r = fv - (4.0 * u - su[lj][li - 1] - su[lj][li + 1] - su[lj - 1][li] -
                              su[lj + 1][li]);
       const unsigned o = (unsigned)((j - 1) * pitch + (i - 1));
