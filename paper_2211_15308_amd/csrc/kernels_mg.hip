@@ -269,9 +269,18 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
 template <typename T, int NU>
 static void pcg_init_nu(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z) {
   const Level& L = c.lev[0];
-  hipLaunchKernelGGL((k_mg_down<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, r, mg.u[0],
-                     mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)nullptr, (const T*)nullptr,
-                     (T*)nullptr, (T*)nullptr, (T*)nullptr, c.st, c.red, 0, 0, 1, 0);
+  // (FP32 grids of at most kResidentTiles tiles: the RESIDENT form, as in the iterations)
+  auto down0 = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, tiles(L.nf), tblock(), 0, c.stream, r, mg.u[0], mg.f[1], L.nf,
+                       L.pitch, c.lev[1].pitch, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
+                       (T*)nullptr, (T*)nullptr, c.st, c.red, 0, 0, 1, 0);
+  };
+  if constexpr (sizeof(T) == 4) {
+    if (c.red.nb0 <= kResidentTiles) down0(k_mg_down<T, NU, false, kTile, true>);
+    else down0(k_mg_down<T, NU, false, kTile, false>);
+  } else {
+    down0(k_mg_down<T, NU, false, kTile, false>);
+  }
   vcycle_tail_nu<T, NU>(c, mg, 0);
   hipLaunchKernelGGL((k_mg_up<T, NU, true>), tiles(L.nf), tblock(), 0, c.stream, r, mg.u[0],
                      mg.e[1], z, L.nf, L.pitch, c.lev[1].pitch, c.st, c.red, 0, 0);
