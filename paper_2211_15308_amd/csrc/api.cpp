@@ -287,7 +287,8 @@ void enqueue_inner_more(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, int
       // the next step's first kernel does this residual's bookkeeping; the last one of the
       // sequence gets a kernel of its own (the host or the outer tail reads its outcome)
       launch_ir_residual(c, t.f, P->u64[t.S & 1], S.x, nullptr, P->u64[(t.S + 1) & 1],
-                         S.r[t.cur_r], nullptr, 0, 0, 0, 0, nullptr, nullptr, st == steps - 1);
+                         S.r[t.cur_r], nullptr, 0, 0, 0, 0, nullptr, nullptr, st == steps - 1,
+                         n_its > 0);
       t.S += 1;
     }
   } else {

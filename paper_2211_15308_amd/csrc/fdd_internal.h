@@ -150,7 +150,7 @@ void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* 
 // dots r.z, z.A z come from the previous V-cycle; p = z + beta p', x += alpha p, r -= alpha A p
 // (A p as a stencil of p), then the V-cycle of the new r yields the next z and dots.
 // update_only (the last scheduled iteration of a run that a refinement residual follows): the
-// update and the convergence test only; the next z would not be used.
+// update only; the next z would not be used, and the residual takes the convergence test.
 template <typename T>
 void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
                           T* r_new, T* z, T* p_old, T* p_new, bool update_only = false);
@@ -158,11 +158,12 @@ void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* 
 // FP64 refinement residual: uout = uin + e (uout = 0 on the first call; a plain copy once the
 // solve has converged), r = f - A uout.  The step's bookkeeping (convergence test, state of the
 // next PCG run) is done by the first kernel of the next PCG run; finalize = true adds a one-block
-// kernel for it, for a residual that no PCG run follows in the same launch sequence.
+// kernel for it, for a residual that no PCG run follows in the same launch sequence.  run_check:
+// the run before it ended with an update-only iteration, whose convergence test it takes.
 void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin, const float* e32,
                         const double* e64, double* uout, float* r32, double* r64, int first,
                         double tol2, double tau2, int pcg_is_final, const float* warm,
-                        const double* wscale, bool finalize);
+                        const double* wscale, bool finalize, bool run_check = false);
 // Galerkin factor of a learned guess g (FP32 image, pitch nf) for the right-hand side f, into
 // st->warm_alpha (0 when the guess does not lower the energy error).
 void launch_warm_alpha(const LaunchCtx& c, const RhsDesc& f, const float* g);

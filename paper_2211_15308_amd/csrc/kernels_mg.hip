@@ -56,18 +56,6 @@ __global__ __launch_bounds__(kBlock) void k_sum_dots(DevState* st, Reductions re
   d_sum_dots(red, k, st);
 }
 
-// Convergence test after the last scheduled update of a PCG run (in place of the V-cycle that
-// would follow it).  A run that has not converged counts the iteration, so that its recorded
-// length tells the schedule that this run needed more.
-__global__ __launch_bounds__(kBlock) void k_run_check(DevState* st, Reductions red) {
-  if (stopped(st)) return;
-  if (!pcg_converged(st, red, true) && thread0()) {
-    st->inner_its += 1;
-    st->pcg_k += 1;
-    st->run_its_max = max(st->run_its_max, st->pcg_k);
-  }
-}
-
 template <typename T, int NU, bool CG, int TT = kTile>
 __global__ __launch_bounds__(kBlock) void k_mg_up(
     const T* __restrict__ fin, const T* __restrict__ upre, const T* __restrict__ ec,
@@ -139,11 +127,11 @@ __global__ __launch_bounds__(kBlock) void k_ir_residual(
     RhsDesc f, const double* __restrict__ uin, const E* __restrict__ e, double* __restrict__ uout,
     float* __restrict__ r32, double* __restrict__ r64, int nf, int pitch, int first, double tol2,
     double tau2, int pcg_is_final, DevState* st, Reductions red, const float* __restrict__ warm,
-    const double* __restrict__ wscale) {
+    const double* __restrict__ wscale, int run_check) {
   int tile_x, tile_y;
   const int tile = xcd_tile(&tile_x, &tile_y);
   d_ir_residual<E>(f, uin, e, uout, r32, r64, nf, pitch, first, tol2, tau2, pcg_is_final, st, red,
-                   tile_x, tile_y, tile, block0(), warm, wscale);
+                   tile_x, tile_y, tile, block0(), warm, wscale, run_check != 0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_warm_dots(RhsDesc f, const float* __restrict__ g,
@@ -313,10 +301,7 @@ static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x,
   } else {
     down0(k_mg_down<T, NU, true, kTile, false>);
   }
-  if (update_only) {
-    hipLaunchKernelGGL(k_run_check, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red);
-    return;
-  }
+  if (update_only) return;  // the refinement residual that follows takes the run's test
   vcycle_tail_nu<T, NU>(c, mg, 1);
   launch_timed(c.hook, kTimeUp0, k_mg_up<T, NU, true>, tiles(L.nf), tblock(), c.stream,
                (const T*)r_new, (const T*)mg.u[0], (const T*)mg.e[1], z, L.nf, L.pitch,
@@ -333,16 +318,16 @@ void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* 
 void launch_ir_residual(const LaunchCtx& c, const RhsDesc& f, const double* uin, const float* e32,
                         const double* e64, double* uout, float* r32, double* r64, int first,
                         double tol2, double tau2, int pcg_is_final, const float* warm,
-                        const double* wscale, bool finalize) {
+                        const double* wscale, bool finalize, bool run_check) {
   const Level& L = c.lev[0];
   if (e64 || !e32)
     hipLaunchKernelGGL((k_ir_residual<double>), tiles(L.nf), tblock(), 0, c.stream, f, uin, e64,
                        uout, r32, r64, L.nf, L.pitch, first, tol2, tau2, pcg_is_final, c.st,
-                       c.red, warm, wscale);
+                       c.red, warm, wscale, run_check ? 1 : 0);
   else
     hipLaunchKernelGGL((k_ir_residual<float>), tiles(L.nf), tblock(), 0, c.stream, f, uin, e32,
                        uout, r32, r64, L.nf, L.pitch, first, tol2, tau2, pcg_is_final, c.st,
-                       c.red, warm, wscale);
+                       c.red, warm, wscale, run_check ? 1 : 0);
   if (finalize) hipLaunchKernelGGL(k_ir_finalize, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red);
 }
 

@@ -1319,7 +1319,8 @@ __device__ __forceinline__ void d_ir_residual(
     double* __restrict__ uout, float* __restrict__ r32, double* __restrict__ r64, int nf,
     int pitch, int first, double tol2, double tau2, int pcg_is_final, DevState* st,
     const Reductions& red, int tile_x, int tile_y, int tile, bool lead,
-    const float* __restrict__ warm = nullptr, const double* __restrict__ wscale = nullptr) {
+    const float* __restrict__ warm = nullptr, const double* __restrict__ wscale = nullptr,
+    bool run_check = false) {
   constexpr int W = kTile + 2;
   __shared__ double su[W][W + 1];
   const int i0 = tile_x * kTile, j0 = tile_y * kTile;
@@ -1335,6 +1336,16 @@ __device__ __forceinline__ void d_ir_residual(
       }
     }
     return;
+  }
+  // run_check: the PCG run that ends here stopped after an update without a V-cycle; the lead
+  // block takes its convergence test (a run that has not converged counts the iteration, so
+  // that its recorded length tells the schedule that it needed more)
+  if (run_check && lead && !stopped(st)) {
+    if (!pcg_converged(st, red, true) && thread0()) {
+      st->inner_its += 1;
+      st->pcg_k += 1;
+      st->run_its_max = max(st->run_its_max, st->pcg_k);
+    }
   }
   constexpr int RY = Slots<W>::RY, RX = Slots<W>::RX;
   // first call: u = 0, or u = s g for a learned guess g (compact FP32 image) with scale s
