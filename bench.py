@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--inner-rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-pf-n", type=int, default=256,
+                    help="n of the paper-faithful CPU solver (sparse-LU Schur PCG) in the CPU baseline; 0: skip")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="only the CPU baselines (no GPU work): the DST and paper-faithful oracle solvers")
     ap.add_argument("--cases", default="all", help="'all' or 'K,mu'")
     ap.add_argument("--eager", action="store_true", help="launch kernels eagerly (no hipGraph replay)")
     ap.add_argument("--pmc-mode", action="store_true",
@@ -72,26 +76,125 @@ def cases(args):
     return [(K, mu) for K in (1.0, 1e-2, 1e-4) for mu in (1e-6, 1e-3, 1.0, 1e3)]
 
 
-def cpu_baseline(args, case_list):
-    """The oracle's exact separable solver, timed on this host on a bounded sample of the cases.
+SEEDS_PER_CASE = 3
 
-    scipy.fft runs single-threaded by default and the banded solves are sequential, so the
-    oracle uses one core.
-    """
+
+def calibration_seed(ci):
+    """Right-hand side of case ci solved during set-up only (never timed)."""
+    return 1000 + ci
+
+
+def timed_seed(ci, k):
+    """The k-th timed right-hand side of case ci."""
+    return 1100 + SEEDS_PER_CASE * ci + k
+
+
+def host_info():
+    """The host the CPU numbers were taken on: usable cores, CPU model, BLAS/FFT thread settings."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cores_available": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_dst_rate(n, cases, seconds):
+    """Solves/s of the oracle's separable sine-transform solver over a bounded sample of cases
+    [(K, mu, seed)] (scipy.fft single-threaded by default; banded solves sequential: one core)."""
     import workloads
     from oracle import system
-    n = args.n
     t0 = time.perf_counter()
     done = 0
-    while time.perf_counter() - t0 < args.cpu_seconds:
-        K, mu = case_list[done % len(case_list)]
-        b = workloads.rhs(2, n, 1000 + done % len(case_list))
-        system.solve_dst_2d(n, K, mu, b)
+    while time.perf_counter() - t0 < seconds or done == 0:
+        K, mu, seed = cases[done % len(cases)]
+        system.solve_dst_2d(n, K, mu, workloads.rhs(2, n, seed))
         done += 1
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} solves of the 2D n={n} problem by the oracle's separable sine-transform "
-                      f"solver (FP64, numpy/scipy, one thread), cycling the same (K, mu) cases, {dt:.1f} s"}
+    return done / dt, done, dt
+
+
+def cpu_paper_faithful(n, K, mu, seed, rtol):
+    """The paper's CPU solver shape: Schur-complement PCG (FP64, x0 = 0) with the interior block
+    factorized once by sparse LU (SuperLU, one thread) and the rational preconditioner of eq. (RA)
+    (the oracle's own AAA table to 1e-12 on the exact spectrum) applied by banded solves.
+    Assembly and factorization are reported apart from the solve."""
+    import numpy as np
+
+    import workloads
+    from oracle import aaa, ra, spectral, system
+    t0 = time.perf_counter()
+    R = system.Riesz(2, n, K, mu)
+    lam = spectral.interface_eigs_1d(n)
+    c0, c, p = aaa.ra_table(spectral.f_precond(K, 1.0 / mu), lam[0], lam[-1], tol=1e-12, extra=lam)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    R.interior_lu()
+    t_fact = time.perf_counter() - t0
+    L, M = R.P.A_G, R.P.M_G
+    b = workloads.rhs(2, n, seed)
+    t0 = time.perf_counter()
+    x, its, _ = R.schur_pcg(b, precond=lambda r: ra.apply_tridiagonal(L, M, c0, c, p, r), rtol=rtol)
+    t_solve = time.perf_counter() - t0
+    err = float(np.linalg.norm(x - system.solve_dst_2d(n, K, mu, b)) / np.linalg.norm(x))
+    return {"n": n, "K": K, "mu": mu, "solves_per_s": 1.0 / t_solve, "solve_s": t_solve,
+            "factorization_s": t_fact, "assembly_gevp_and_table_s": t_setup, "outer_its": its,
+            "poles": len(p), "rel_err_vs_separable": err, "threads": 1}
+
+
+def cpu_baseline(args, dst_cases, pf_case):
+    """The oracle timed on this host on bounded samples of the headline workload.
+
+    value: the oracle's separable sine-transform solver (exact, O(n^2 log n)) at the headline n,
+    one core.  Beside it the paper-faithful solver (sparse-LU Schur PCG with the same RA poles)
+    on one case at n = args.cpu_pf_n (its element-by-element assembly and factorization at
+    n = 1024 take minutes, so the default run uses a smaller n; the n = 1024 figure is recorded
+    separately by --cpu-only --cpu-pf-n 1024).
+    """
+    rate, done, dt = cpu_dst_rate(args.n, dst_cases, args.cpu_seconds)
+    out = {"value": rate, "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": f"{done} solves of the 2D n={args.n} problem by the oracle's separable "
+                     f"sine-transform solver (FP64, numpy/scipy, one thread), cycling the timed "
+                     f"(K, mu, seed) cases, {dt:.1f} s",
+           "host": host_info()}
+    if args.cpu_pf_n:
+        K, mu, seed = pf_case
+        out["paper_faithful"] = cpu_paper_faithful(args.cpu_pf_n, K, mu, seed, args.rtol)
+    return out
+
+
+def cpu_instances(cases, seconds):
+    """Instance solves/s of the oracle's separable solver over a bounded sample of batch instances."""
+    import workloads
+    from oracle import system
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < seconds or done == 0:
+        c = cases[done % len(cases)]
+        system.solve_dst_2d(c["n"], c["K"], c["mu"], workloads.rhs(2, c["n"], c["seed"]))
+        done += 1
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "instance solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} instance solves by the oracle's separable sine-transform solver "
+                      f"(one thread), cycling the batch's instances, {dt:.1f} s"}
+
+
+def cpu_3d(n, K, mu, seed):
+    """One 3D solve by the oracle's sparse LU of the full system (SuperLU, one thread)."""
+    import workloads
+    from oracle import system
+    t0 = time.perf_counter()
+    R = system.Riesz(3, n, K, mu)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    R.solve_splu(workloads.rhs(3, n, seed))
+    dt = time.perf_counter() - t0
+    return {"n": n, "K": K, "mu": mu, "solves_per_s": 1.0 / dt, "kind": "oracle sparse LU of the full system",
+            "assembly_and_gevp_s": t_setup, "cores": 1}
 
 
 # Algorithmic bytes of the finest-level down kernel per interior dof (FP32): it reads r and z,
@@ -133,9 +236,14 @@ class OracleLeg:
 
     def __init__(self):
         self.items = []
+        self.jobs = []
 
     def check(self, slot, key, n, K, mu, b, x):
         self.items.append((slot, key, n, K, mu, b.detach().cpu().numpy(), x.detach().cpu().numpy()))
+
+    def defer(self, slot, key, fn):
+        """slot[key] = fn() when the leg runs (CPU timings of the oracle beside a GPU leg)."""
+        self.jobs.append((slot, key, fn))
 
     def run(self):
         import numpy as np
@@ -144,6 +252,9 @@ class OracleLeg:
             xr = system.solve_dst_2d(n, K, mu, b)
             slot[key] = float(np.linalg.norm(x - xr) / np.linalg.norm(xr))
         self.items = []
+        for slot, key, fn in self.jobs:
+            slot[key] = fn()
+        self.jobs = []
 
 
 def setup_instances(F, cases, tol_p, max_p, tol_h, threads=8):
@@ -211,7 +322,7 @@ def run_batched(F, args, label, cases, tol_p, max_p, leg):
         c = cases[i]
         leg.check(errs, i, c["n"], c["K"], c["mu"], bs[i], xs[i])
     outer = [s_["outer_its"] for s_ in st]
-    return {
+    res = {
         "label": label, "value": value, "unit": "instance solves/s", "instances": len(cases),
         "dofs": int(sum(c["n"] * (c["n"] - 1) for c in cases)), "ms_per_batch": 1e3 * el / args.batch_steps,
         "batches_timed": args.batch_steps, "setup_s": setup_s,
@@ -225,8 +336,12 @@ def run_batched(F, args, label, cases, tol_p, max_p, leg):
                      "kernel": f"kb_mg_down<{opts.mg_nu},true,32> (finest level of every instance, "
                                "PCG update fused)",
                      "launches": nl, "avg_launch_us": 1e3 * ms / max(nl, 1),
-                     "alg_bytes_per_batch_solve": alg},
+                     "alg_bytes_per_batch_solve": alg,
+                     "working_set_MB": sum(i[0].workspace_bytes() + 16 * i[0].N for i in inst) / 1e6},
+        "cpu_baseline": None,
     }
+    leg.defer(res, "cpu_baseline", lambda: cpu_instances(cases, args.cpu_seconds / 4))
+    return res
 
 
 CNN_FWD_FLOP_PER_PX = 2 * 9 * (5 * 32 + 4 * 32 * 32 + 32 * 1)  # the six convolutions
@@ -298,7 +413,8 @@ def run_learned(F, args, leg, sizes=(256, 512, 1024), mus=(1e-3, 1.0)):
             b = torch.as_tensor(workloads.rhs(2, n, 5000 + 10 * ci + n), dtype=torch.float64, device="cuda")
             row = {"n": n, "K": 1.0, "mu": mu}
             for label, ws in (("plain", None), ("learned", net.h.value)):
-                opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, mg_nu=args.nu)
+                opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, mg_nu=args.nu,
+                                      check_true_residual=1)
                 opts.warmstart = ws
                 x = torch.zeros_like(b)
                 for _ in range(2):
@@ -313,6 +429,10 @@ def run_learned(F, args, leg, sizes=(256, 512, 1024), mus=(1e-3, 1.0)):
                               "inner_its": st["inner_its_total"], "warm_accepted": st["warm_accepted"],
                               "warm_starts": st["warm_starts"], "rel_err_vs_oracle": None}
                 leg.check(row[label], "rel_err_vs_oracle", n, 1.0, mu, b, x)
+            row["cpu_oracle_solves_per_s"] = None
+            seed = 5000 + 10 * ci + n
+            leg.defer(row, "cpu_oracle_solves_per_s",
+                      lambda n=n, mu=mu, seed=seed: cpu_dst_rate(n, [(1.0, mu, seed)], 1.0)[0])
             res["cases"].append(row)
     return res
 
@@ -353,7 +473,7 @@ def run_sweep(F, args, leg, sizes=(128, 256, 512, 1024, 2048)):
     return out
 
 
-def run_3d(F, args, sizes=(32, 64, 128), mus=(1e-4, 1.0, 1e2), reps=2):
+def run_3d(F, args, leg, sizes=(32, 64, 128), mus=(1e-4, 1.0, 1e2), reps=2):
     """3D unit cube (Kuhn tetrahedra), Gamma = top face, K = 1: solves/s per (n, mu); FP64 outer
     PCG and face solves, FP32 multigrid-PCG inside FP64 refinement for the interior."""
     import torch
@@ -383,6 +503,11 @@ def run_3d(F, args, sizes=(32, 64, 128), mus=(1e-4, 1.0, 1e2), reps=2):
                         "outer_its": st["outer_its"], "inner_its": st["inner_its_total"],
                         "poles_P": TP.query()["m"], "poles_H": TH.query()["m"],
                         "true_rel_res": chk["true_rel_res"]})
+            if n == sizes[0] and ci == 0:
+                out[-1]["cpu_baseline"] = None
+                leg.defer(out[-1], "cpu_baseline", lambda n=n, mu=mu, seed=3000 + len(out) - 1: cpu_3d(n, 1.0, mu, seed))
+            else:
+                out[-1]["cpu_baseline"] = "not run: the oracle's sparse LU takes minutes beyond n = 32"
     return out
 
 
@@ -392,6 +517,12 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.cpu_only:
+        case_list = cases(args)
+        dst_cases = [(K, mu, timed_seed(ci, k)) for k in range(SEEDS_PER_CASE) for ci, (K, mu) in enumerate(case_list)]
+        print(json.dumps({"cpu_baseline": cpu_baseline(args, dst_cases, (case_list[0][0], case_list[0][1],
+                                                                         timed_seed(0, 0)))}))
+        return
     import numpy as np
     import torch
 
@@ -410,7 +541,11 @@ def main():
         print(json.dumps({"network": cnn_timing(F, torch.as_tensor(th, device="cuda"))}))
         return
     if args.only_3d:
-        print(json.dumps({"three_d": run_3d(F, args)}))
+        leg = OracleLeg()
+        res = run_3d(F, args, leg)
+        if not args.no_cpu_baseline:
+            leg.run()
+        print(json.dumps({"three_d": res}))
         return
     if args.sweep:
         leg = OracleLeg()
@@ -445,27 +580,47 @@ def main():
         torch.cuda.synchronize()
         case_list = case_list[:2]
         args.steps, args.warmup = 2, 1
+    # set-up (not timed as solves, reported as setup_s): mesh plans, rational tables, workspaces,
+    # and for every case two solves of a right-hand side that is never timed (the first measures
+    # the launch schedule, the second captures the outer-iteration graphs)
+    t_setup = time.perf_counter()
     probs = []
     for ci, (K, mu) in enumerate(case_list):
         P = F.setup_mesh(args.n, K, mu)
         P.bind_workspace()
         TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
         TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
-        b = torch.as_tensor(workloads.rhs(2, args.n, 1000 + ci), dtype=torch.float64, device=dev)
-        x = torch.zeros_like(b)
-        probs.append((P, TP, TH, b, x, K, mu))
+        b_cal = torch.as_tensor(workloads.rhs(2, args.n, calibration_seed(ci)), dtype=torch.float64, device=dev)
+        bs = [torch.as_tensor(workloads.rhs(2, args.n, timed_seed(ci, k)), dtype=torch.float64, device=dev)
+              for k in range(SEEDS_PER_CASE)]
+        x = torch.zeros_like(b_cal)
+        for _ in range(2):
+            P.solve(TP, TH, b_cal, x, opts)
+        probs.append((P, TP, TH, bs, x, K, mu))
     torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+
+    def step_case(s):
+        ci = s % len(probs)
+        k = (s // len(probs)) % SEEDS_PER_CASE
+        return ci, k
+
+    # one step = one complete solve: rhs reduction, outer PCG, back-substitution and the true
+    # residual ||b - A x|| / ||b|| (check_true_residual = 1)
+    opts.check_true_residual = 1
     stats = []
     for s in range(args.warmup):
-        P, TP, TH, b, x, K, mu = probs[s % len(probs)]
-        P.solve(TP, TH, b, x, opts)
+        ci, k = step_case(s)
+        P, TP, TH, bs, x, K, mu = probs[ci]
+        P.solve(TP, TH, bs[k], x, opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        P, TP, TH, b, x, K, mu = probs[s % len(probs)]
-        st = P.solve(TP, TH, b, x, opts)
-        stats.append(dict(K=K, mu=mu, outer=st["outer_its"], inner=st["inner_its_total"],
-                          refine=st["refine_steps"], ms=st["t_solve_ms"]))
+    for s in range(args.warmup, args.warmup + args.steps):
+        ci, k = step_case(s)
+        P, TP, TH, bs, x, K, mu = probs[ci]
+        st = P.solve(TP, TH, bs[k], x, opts)
+        stats.append(dict(K=K, mu=mu, seed=timed_seed(ci, k), outer=st["outer_its"], inner=st["inner_its_total"],
+                          refine=st["refine_steps"], res=st["true_rel_res"], ms=st["t_solve_ms"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = args.steps / elapsed
@@ -478,9 +633,10 @@ def main():
     for P, *_ in probs:
         P.set_kernel_timer(FF.FDD_KT_DOWN0)
     its = runs = 0
-    for s in range(args.steps):
-        P, TP, TH, b, x, K, mu = probs[s % len(probs)]
-        st = P.solve(TP, TH, b, x, opts)
+    for s in range(args.warmup, args.warmup + args.steps):
+        ci, k = step_case(s)
+        P, TP, TH, bs, x, K, mu = probs[ci]
+        st = P.solve(TP, TH, bs[k], x, opts)
         its += st["inner_its_total"]
         runs += st["refine_steps"] if prec == F.FDD_MIXED else st["inner_solves"]
     launches = tot_ms = long_n = long_ms = 0
@@ -500,20 +656,25 @@ def main():
     alg_bytes = ni * elem / 4 * (DOWN0_BYTES_K * its + DOWN0_BYTES_K0 * runs)
     achieved = alg_bytes / (long_ms * 1e-3) / 1e9 if long_ms > 0 else 0.0
     traffic = traffic_from_profile(ROOT, args.nu) if prec == F.FDD_MIXED and args.n == 1024 else None
+    ws_mb = (probs[0][0].workspace_bytes() + 2 * 8 * probs[0][0].N) / 1e6
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": f"k_mg_down<float,{args.nu},true,32,true> (finest level, PCG update fused)",
                 "launches": launches, "avg_launch_us": 1e3 * tot_ms / max(launches, 1),
                 "working_launches": its + runs, "timed_long_launches": long_n,
                 "avg_working_launch_us": 1e3 * long_ms / max(long_n, 1),
-                "alg_bytes_per_working_launch": alg_bytes / max(its + runs, 1)}
+                "alg_bytes_per_working_launch": alg_bytes / max(its + runs, 1),
+                "working_set_MB": ws_mb,
+                "cache_note": (f"one instance's working set ({ws_mb:.0f} MB) fits the 256 MB Infinity Cache, so "
+                               "part of this kernel's traffic may be served from it; the batched roofline "
+                               "(batched_1024, ~32x larger working set) is the one measured beyond it")}
     # parity spot-check of one solve of the first cases against the separable oracle
     leg = OracleLeg()
     errs = [None] * min(3, len(probs))
     for ci in range(len(errs)):
-        P, TP, TH, b, x, K, mu = probs[ci]
-        P.solve(TP, TH, b, x, opts)
-        leg.check(errs, ci, args.n, K, mu, b, x)
+        P, TP, TH, bs, x, K, mu = probs[ci]
+        P.solve(TP, TH, bs[0], x, opts)
+        leg.check(errs, ci, args.n, K, mu, bs[0], x)
     batched = {}
     if args.batched in ("all", "1024"):
         batched["batched_1024"] = run_batched(F, args, "32 instances, n=1024",
@@ -539,8 +700,10 @@ def main():
                                f"(K, mu) cycling {len(case_list)} cases of the sweep, b ~ N(0,1), "
                                f"outer rtol {args.rtol}, inner rtol {args.inner_rtol}",
                    "n": args.n, "cases": len(case_list), "precision": args.precision},
-        "outer_its": [s["outer"] for s in stats[: len(case_list)]],
-        "inner_its": [s["inner"] for s in stats[: len(case_list)]],
+        "setup_s": setup_s,
+        "timed_solves": [dict(K=s_["K"], mu=s_["mu"], seed=s_["seed"], outer_its=s_["outer"],
+                              inner_its=s_["inner"], true_rel_res=s_["res"]) for s_ in stats],
+        "true_rel_res_max": max(s_["res"] for s_ in stats),
         "rel_err_vs_oracle": errs,
         "roofline": roofline,
         "cpu_baseline": None,
@@ -549,11 +712,12 @@ def main():
     if args.learned == "auto":
         out["learned"] = run_learned(F, args, leg)
     if not args.no_3d:
-        out["three_d"] = run_3d(F, args)
+        out["three_d"] = run_3d(F, args, leg)
     # the oracle leg, after every GPU measurement: parity spot-checks and the CPU baseline
     leg.run()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args, case_list)
+        dst_cases = [(s_["K"], s_["mu"], s_["seed"]) for s_ in stats]
+        out["cpu_baseline"] = cpu_baseline(args, dst_cases, (case_list[0][0], case_list[0][1], timed_seed(0, 0)))
     print(json.dumps(out))
 
 

@@ -41,3 +41,24 @@ def dense_operator(L, M, c0, c, p):
 def dense_operator_H(L, M, d0, d, q):
     """M (d0 M^{-1} + sum_k d_k (L + q_k M)^{-1}) M: the RA realization of L^{-1/2}."""
     return M @ dense_operator(L, M, d0, d, q) @ M
+
+
+def apply_tridiagonal(L, M, c0, c, p, r):
+    """c0 M^{-1} r + sum_k c_k (L + p_k M)^{-1} r for tridiagonal L, M (the 2D interface, eq. (RA)).
+
+    Every shifted system is solved by a banded LU (scipy.linalg.solve_banded), the way a CPU
+    code applies the rational preconditioner on a 1D interface.
+    """
+    import scipy.linalg as sla
+
+    def banded(A):
+        ab = np.zeros((3, A.shape[0]))
+        ab[0, 1:] = np.diag(A, 1)
+        ab[1, :] = np.diag(A)
+        ab[2, :-1] = np.diag(A, -1)
+        return ab
+
+    out = c0 * sla.solve_banded((1, 1), banded(M), r)
+    for ck, pk in zip(c, p):
+        out = out + ck * sla.solve_banded((1, 1), banded(L + pk * M), r)
+    return out

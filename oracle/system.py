@@ -260,3 +260,73 @@ def harmonic_extension_sine_2d(n, q):
     # sinh(om j)/sinh(om n) written without overflow for large n
     ratio = np.exp(om * (j - n)) * (-np.expm1(-2.0 * om * j)) / (-np.expm1(-2.0 * om * n))
     return (np.sin(th * i)[None, :] * ratio[:, None]).ravel()
+
+
+def schur_pcg_dst_2d(n, K, mu, b, precond_symbol, rtol=1e-10, maxit=500):
+    """The Schur-complement PCG of ``Riesz.schur_pcg`` computed in the interface sine basis (2D).
+
+    Sec. 2, eq. (block_op) and the PCG of Sec. 3 (x_0 = 0, stop when (r^T z)^{1/2} has fallen by
+    rtol).  In 2D every operator on Gamma is diagonal on s_q = sin(theta_q i): S has the
+    closed-form eigenvalue of ``schur_eigs_2d``, and an interface preconditioner of the form
+    U phi(Lambda) U^T (eq. (RA) or the exact S_Gamma^{-1}) has phi(lambda_q) / mu_q, with mu_q the
+    mass symbol.  Writing every Gamma vector as v = sum_q v_q s_q turns the PCG into the same
+    recurrences on coefficient vectors with the inner product (n/2) sum_q v_q w_q.  The reduced
+    right-hand side and the back-substitution are the block elimination of eq. (block_op),
+    done per mode by tridiagonal solves along y (interior rows j = 1..n-1, zero at j = 0 and
+    j = n); A_{Gamma I} couples the interface node to the one below it with weight -1.
+
+    precond_symbol: callable lambda -> phi(lambda) (e.g. ``ra.eval_scalar`` of a table, or
+    ``spectral.f_precond``).  Returns (x, iterations, history of (r^T z)^{1/2}).
+    """
+    gamma = 1.0 / mu
+    h = 1.0 / n
+    B = np.asarray(b, dtype=np.float64).reshape(n, n - 1)
+    # coefficients on s_q: v = sum_q vhat_q s_q, vhat_q = (2/n) sum_i v_i sin(theta_q i)
+    Bh = sfft.dst(B, type=1, axis=1) / n
+    th = np.arange(1, n) * np.pi / n
+    sig = 2.0 - 2.0 * np.cos(th)
+    mu_q = (h / 6.0) * (4.0 + 2.0 * np.cos(th))
+    lam_q = spectral.interface_eigs_1d(n)
+
+    def interior_solve(F):
+        """A_II^{-1} per mode: F is (n-1 rows j, n-1 modes q) of sine coefficients."""
+        W = np.empty_like(F)
+        for q in range(n - 1):
+            ab = np.zeros((3, n - 1))
+            ab[0, 1:] = -1.0
+            ab[2, :-1] = -1.0
+            ab[1, :] = 2.0 + sig[q]
+            W[:, q] = sla.solve_banded((1, 1), ab, F[:, q])
+        return W
+
+    W = interior_solve(Bh[: n - 1])
+    g = Bh[n - 1] + W[n - 2]                          # g = b_G - A_GI A_II^{-1} b_I
+    s_diag = schur_eigs_2d(n, K, mu)
+    p_diag = np.asarray(precond_symbol(lam_q), dtype=np.float64) / mu_q
+    dot = lambda u, v: 0.5 * n * float(u @ v)
+    xg = np.zeros(n - 1)
+    r = g.copy()
+    z = p_diag * r
+    rz = rz0 = dot(r, z)
+    hist = [np.sqrt(rz)]
+    p = z.copy()
+    its = 0
+    while np.sqrt(rz) > rtol * np.sqrt(rz0) and its < maxit:
+        q = s_diag * p
+        alpha = rz / dot(p, q)
+        xg += alpha * p
+        r -= alpha * q
+        z = p_diag * r
+        rz_new = dot(r, z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        its += 1
+        hist.append(np.sqrt(abs(rz)))
+    # x_I = A_II^{-1} (b_I / K - A_IG x_G): -A_IG x_G adds x_G on the row below Gamma
+    F = Bh[: n - 1] / K
+    F[n - 2] += xg
+    XI = interior_solve(F)
+    Xh = np.vstack([XI, xg[None, :]])
+    # back to nodal values: v_i = sum_q vhat_q sin(theta_q i)
+    X = sfft.idst(Xh * n, type=1, axis=1)
+    return X.ravel(), its, hist

@@ -533,6 +533,10 @@ int fdd_bind_workspace(fdd_problem P, void* dev, size_t bytes, void* stream) {
   if (bytes < need) return fail(FDD_E_WORKSPACE, "workspace %zu bytes < %zu needed", bytes, need);
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
+  // captured graphs hold pointers into the old workspace
+  for (auto& kv : P->graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  P->graphs.clear();
   P->ws = (char*)dev;
   P->ws_bytes = bytes;
   plan_workspace(P, P->ws);
@@ -710,6 +714,21 @@ int fdd_apply_operator(fdd_problem P, fdd_ratpc H, const double* x, double* y, v
 
 namespace {
 
+// FNV-1a digest of a shift table as the kernels receive it (by value).
+uint64_t table_digest(const ShiftTable& T) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t nb) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < nb; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  mix(&T.m, sizeof(T.m));
+  mix(T.alpha, sizeof(double) * T.m);
+  mix(T.beta, sizeof(double) * T.m);
+  mix(T.coef, sizeof(double) * T.m);
+  mix(&T.d0, sizeof(T.d0));
+  return h;
+}
+
 // One outer PCG step after the interior solve for the lifted p (version v -> v+1):
 // the Schur product y = S p, alpha, x and r updates, then z = P r, rho, beta and p.
 void enqueue_outer_tail(fdd_problem_s* P, hipStream_t s, const ShiftTable& tabP, const double* u,
@@ -755,13 +774,19 @@ void enqueue_outer_iteration(fdd_problem_s* P, hipStream_t s, const ShiftTable& 
 // Replays (capturing first if needed) the graph of outer iteration v for the current schedule.
 int launch_outer_graph(fdd_problem_s* P, hipStream_t s, const ShiftTable& tabP,
                        const ShiftTable& tabH, const fdd_opts& o, int v, InnerTrack& t) {
-  // everything the captured launch sequence depends on
+  // everything the captured launch sequence depends on: the schedule, the options passed to the
+  // kernels by value (tolerances as bit patterns), and both rational tables by content (their
+  // shifts, weights and system counts are kernel arguments, so a table of another tol or
+  // max_poles, or one given by fdd_ratpc_from_table, needs a graph of its own)
   std::vector<int> key = {v & 1, (int)t.fp64, o.mg_nu, P->sc->steps, P->sc->its, P->sc->its64,
-                          (int)std::lround(std::log10(o.step_rtol) * 16.0), o.back_solve ? 1 : 0};
+                          o.back_solve ? 1 : 0};
   key.insert(key.end(), P->sc->step_its, P->sc->step_its + 8);
-  const uint64_t ws = (uint64_t)(uintptr_t)o.warmstart;
-  key.push_back((int)(ws & 0xffffffffu));
-  key.push_back((int)(ws >> 32));
+  push_bits(key, o.step_rtol);
+  push_bits(key, o.inner_rtol);
+  push_bits(key, table_digest(tabP));
+  push_bits(key, table_digest(tabH));
+  push_bits(key, (uint64_t)(uintptr_t)o.warmstart);
+  if (o.warmstart) push_bits(key, cnn_binding_id((const fdd_cnn_s*)o.warmstart));
   auto it = P->graphs.find(key);
   if (it == P->graphs.end()) {
     hipGraph_t g = nullptr;
@@ -779,7 +804,6 @@ int launch_outer_graph(fdd_problem_s* P, hipStream_t s, const ShiftTable& tabP,
     ge.k = t.k;
     it = P->graphs.emplace(key, ge).first;
   }
-  // the tables are baked into the graph: they depend only on the problem
   t.cur_r = it->second.cur_r;
   t.cur_p = it->second.cur_p;
   t.S = it->second.S;

@@ -731,6 +731,16 @@ int bind3(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s) {
   const size_t need = workspace3(P);
   if (bytes < need) return fail(FDD_E_WORKSPACE, "workspace %zu bytes < %zu needed", bytes, need);
   HIPCHK(hipSetDevice(P->device));
+  // captured graphs hold pointers into the old workspace: capture again on the next solve
+  for (hipGraphExec_t* g : {&Q->m64.g_init, &Q->m32.g_init}) {
+    if (*g) (void)hipGraphExecDestroy(*g);
+    *g = nullptr;
+  }
+  Q->m64.g_it.clear();
+  Q->m32.g_it.clear();
+  Q->m64.g_nu = Q->m32.g_nu = 0;
+  for (Chunks& c : Q->g_face) c.clear();
+  Q->g_face_m[0] = Q->g_face_m[1] = 0;
   P->ws = (char*)dev;
   P->ws_bytes = bytes;
   plan3(P, P->ws);

@@ -263,9 +263,14 @@ void enqueue_outer(const fdd_batch_s* B, const BatchCtx& c, BTrack& t, int v, co
 
 int replay_outer(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, int v,
                  const fdd_opts& o) {
-  std::vector<int> key = {v & 1, o.mg_nu, B->sc->steps, B->sc->its,
-                          (int)std::lround(std::log10(o.step_rtol) * 16.0), o.back_solve ? 1 : 0};
+  // everything the captured launches bake in: the schedule and the options passed by value
+  // (the inner and per-step tolerances of the residual kernels, the outer tolerance of the
+  // device-side stop test), tolerances as bit patterns
+  std::vector<int> key = {v & 1, o.mg_nu, B->sc->steps, B->sc->its, o.back_solve ? 1 : 0};
   key.insert(key.end(), B->sc->step_its, B->sc->step_its + 8);
+  push_bits(key, o.step_rtol);
+  push_bits(key, o.inner_rtol);
+  push_bits(key, o.outer_rtol);
   auto it = B->graphs.find(key);
   if (it == B->graphs.end()) {
     hipGraph_t g = nullptr;

@@ -123,6 +123,8 @@ int cnn_warm_guess(fdd_cnn_s* C, hipStream_t s, const double* trace, int n, cons
   return FDD_OK;
 }
 
+uint64_t cnn_binding_id(const fdd_cnn_s* C) { return (uint64_t)(uintptr_t)C->ws; }
+
 int cnn_check_for(const fdd_cnn_s* C, int n) {
   if (!C) return fail(FDD_E_ARG, "null network");
   if (n > C->n_max) return fail(FDD_E_ARG, "network sized for n <= %d, problem has n = %d", C->n_max, n);

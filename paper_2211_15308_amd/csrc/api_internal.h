@@ -3,6 +3,8 @@
 #pragma once
 #include "fdd.h"
 
+#include <cstdint>
+#include <cstring>
 #include <map>
 #include <string>
 #include <tuple>
@@ -22,6 +24,18 @@ int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
   } while (0)
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Appends the bit pattern of a value to a graph-cache key (exact: distinct tolerances never
+// share a captured graph).
+inline void push_bits(std::vector<int>& key, uint64_t v) {
+  key.push_back((int)(uint32_t)(v & 0xffffffffu));
+  key.push_back((int)(uint32_t)(v >> 32));
+}
+inline void push_bits(std::vector<int>& key, double v) {
+  uint64_t u;
+  std::memcpy(&u, &v, sizeof(u));
+  push_bits(key, u);
+}
 inline int round_up(int x, int a) { return (x + a - 1) / a * a; }
 
 // Launch schedule of the interior solves: refinement steps x FP32 PCG iterations per step
@@ -111,7 +125,8 @@ struct fdd_problem_s {
   // launch schedules by (mg_nu, step_rtol (0 in FP64), right-hand-side kind)
   std::map<std::tuple<int, double, int>, fdd::Schedule> scheds;
   fdd::Schedule* sc = nullptr;
-  // captured outer iterations, keyed by (parity, schedule, precision, smoother)
+  // captured outer iterations, keyed by everything their launches bake in (parity, schedule,
+  // precision, smoother, tolerances, table contents, warm-start binding)
   std::map<std::vector<int>, GraphEntry> graphs;
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -153,6 +168,8 @@ int solve3(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, const
            double* x, const fdd_opts& o, hipStream_t s, fdd_stats* stats);
 // warm-start network (api_cnn.cpp)
 int cnn_check_for(const fdd_cnn_s* C, int n);
+// identifies the network's current workspace binding (its buffers are kernel arguments)
+uint64_t cnn_binding_id(const fdd_cnn_s* C);
 int cnn_warm_guess(fdd_cnn_s* C, hipStream_t s, const double* trace, int n, const double* lk_lmu,
                    const float** guess, const double** scale);
 int check_problem(fdd_problem_s* P);

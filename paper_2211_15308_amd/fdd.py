@@ -171,6 +171,26 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+_DTYPES = {"f64": "float64", "f32": "float32"}
+
+
+def _vec(t, numel, device, name, dtype="f64", at_least=False):
+    """Pointer of a contiguous device tensor after checking what the kernels assume of it: its
+    dtype, that it lives on the problem's device, and its length (the kernels index it up to
+    numel without bounds, so a short or mistyped vector must never reach them)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if (t.numel() < numel) if at_least else (t.numel() != numel):
+        raise ValueError(f"{name} has {t.numel()} entries, expected {'>= ' if at_least else ''}{numel}")
+    want = getattr(torch, _DTYPES[dtype])
+    if t.dtype != want:
+        raise ValueError(f"{name} must be {want} (got {t.dtype})")
+    if t.device.type != "cuda" or t.device.index != device:
+        raise ValueError(f"{name} must be on cuda:{device} (got {t.device})")
+    return _ptr(t)
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -221,6 +241,9 @@ class Problem:
         self.N, self.NI, self.NG = N.value, NI.value, NG.value
         self.lam_lo, self.lam_hi = lo.value, hi.value
 
+    def _v(self, t, numel, name):
+        return _vec(t, numel, self.device, name)
+
     def workspace_bytes(self, opts=None):
         b = ctypes.c_size_t()
         _check(load().fdd_workspace_bytes(self.h, ctypes.byref(opts or opts_default()), ctypes.byref(b)))
@@ -254,24 +277,28 @@ class Problem:
 
     def interior_solve(self, f, u, opts=None, stream=None):
         its = ctypes.c_int()
-        rc = load().fdd_interior_solve(self.h, _ptr(f), _ptr(u), ctypes.byref(opts or opts_default()),
+        rc = load().fdd_interior_solve(self.h, self._v(f, self.NI, "f"), self._v(u, self.NI, "u"),
+                                       ctypes.byref(opts or opts_default()),
                                        _stream(stream), ctypes.byref(its))
         _check(rc)
         return its.value
 
     def schur_apply(self, H, x_G, y_G, opts=None, stream=None):
-        _check(load().fdd_schur_apply(self.h, H.h, _ptr(x_G), _ptr(y_G),
+        _check(load().fdd_schur_apply(self.h, H.h, self._v(x_G, self.NG, "x_G"), self._v(y_G, self.NG, "y_G"),
                                       ctypes.byref(opts or opts_default()), _stream(stream)))
 
     def precond_apply(self, P, r_G, z_G, stream=None):
-        _check(load().fdd_precond_apply(self.h, P.h, _ptr(r_G), _ptr(z_G), _stream(stream)))
+        _check(load().fdd_precond_apply(self.h, P.h, self._v(r_G, self.NG, "r_G"), self._v(z_G, self.NG, "z_G"),
+                                        _stream(stream)))
 
     def apply_operator(self, H, x, y, stream=None):
-        _check(load().fdd_apply_operator(self.h, H.h, _ptr(x), _ptr(y), _stream(stream)))
+        _check(load().fdd_apply_operator(self.h, H.h, self._v(x, self.N, "x"), self._v(y, self.N, "y"),
+                                         _stream(stream)))
 
     def solve(self, P, H, b, x, opts=None, stream=None, allow_not_converged=False):
         st = FddStats()
-        rc = load().fdd_solve(self.h, P.h, H.h, _ptr(b), _ptr(x), ctypes.byref(opts or opts_default()),
+        rc = load().fdd_solve(self.h, P.h, H.h, self._v(b, self.N, "b"), self._v(x, self.N, "x"),
+                              ctypes.byref(opts or opts_default()),
                               _stream(stream), ctypes.byref(st))
         _check(rc, (FDD_OK, FDD_NOT_CONVERGED) if allow_not_converged else (FDD_OK,))
         return st.as_dict()
@@ -326,11 +353,10 @@ class Batch:
         n = self.count
         if len(bs) != n or len(xs) != n:
             raise ValueError("one b and one x per instance")
-        for p, b, x in zip(self.problems, bs, xs):
-            if b.numel() != p.N or x.numel() != p.N:
-                raise ValueError("vector length does not match its problem")
-        ba = (ctypes.c_void_p * n)(*[_ptr(b).value for b in bs])
-        xa = (ctypes.c_void_p * n)(*[_ptr(x).value for x in xs])
+        ba = (ctypes.c_void_p * n)(*[_vec(b, p.N, p.device, f"b[{i}]").value
+                                     for i, (p, b) in enumerate(zip(self.problems, bs))])
+        xa = (ctypes.c_void_p * n)(*[_vec(x, p.N, p.device, f"x[{i}]").value
+                                     for i, (p, x) in enumerate(zip(self.problems, xs))])
         st = (FddStats * n)()
         rc = load().fdd_solve_batched(self.h, ba, xa, ctypes.byref(opts or opts_default()),
                                       _stream(stream), st)
@@ -368,6 +394,7 @@ class Cnn:
         _check(lib.fdd_cnn_create(batch_max, n_max, 1 if train else 0, device, ctypes.byref(h)))
         self.h = h
         self.batch_max, self.n_max, self.train = batch_max, n_max, train
+        self.device = device
         c = ctypes.c_int64()
         _check(lib.fdd_cnn_param_count(h, ctypes.byref(c)))
         self.param_count = c.value
@@ -379,26 +406,36 @@ class Cnn:
         _check(lib.fdd_cnn_bind_workspace(h, ctypes.c_void_p(ptr + off), ws.numel() - off, _stream(stream)))
         self.workspace = ws
 
+    def _p(self, t, name):
+        return _vec(t, self.param_count, self.device, name, "f32")
+
     def set_params(self, theta, stream=None):
-        if theta.numel() != self.param_count:
-            raise ValueError("parameter vector has the wrong length")
-        _check(load().fdd_cnn_set_params(self.h, _ptr(theta), _stream(stream)))
+        _check(load().fdd_cnn_set_params(self.h, self._p(theta, "theta"), _stream(stream)))
 
     def forward(self, traces, log10K, log10mu, out, n, rescale=True, stream=None):
+        if traces.dim() != 2 or traces.shape[1] < n - 1:
+            raise ValueError("traces must be (batch, >= n - 1)")
         B = traces.shape[0]
-        _check(load().fdd_cnn_forward(self.h, _ptr(traces), traces.stride(0), B, n, _ptr(log10K),
-                                      _ptr(log10mu), _ptr(out), 1 if rescale else 0, _stream(stream)))
+        d = self.device
+        tr = _vec(traces, B * traces.shape[1], d, "traces")
+        _check(load().fdd_cnn_forward(self.h, tr, traces.stride(0), B, n, _vec(log10K, B, d, "log10K"),
+                                      _vec(log10mu, B, d, "log10mu"),
+                                      _vec(out, B * (n - 1) ** 2, d, "out", "f32"), 1 if rescale else 0,
+                                      _stream(stream)))
 
     def loss(self, out, target, n, loss=None, stream=None):
         B = out.shape[0]
-        _check(load().fdd_cnn_loss(self.h, _ptr(out), _ptr(target), B, n, _ptr(loss), _stream(stream)))
+        d = self.device
+        _check(load().fdd_cnn_loss(self.h, _vec(out, B * (n - 1) ** 2, d, "out", "f32"),
+                                   _vec(target, B * (n - 1) ** 2, d, "target", "f32"), B, n,
+                                   None if loss is None else _vec(loss, 1, d, "loss"), _stream(stream)))
 
     def backward(self, batch, n, grad, stream=None):
-        _check(load().fdd_cnn_backward(self.h, batch, n, _ptr(grad), _stream(stream)))
+        _check(load().fdd_cnn_backward(self.h, batch, n, self._p(grad, "grad"), _stream(stream)))
 
     def adam_step(self, theta, grad, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=None):
-        _check(load().fdd_cnn_adam_step(self.h, _ptr(theta), _ptr(grad), _ptr(m), _ptr(v), lr, b1, b2,
-                                        eps, step, _stream(stream)))
+        _check(load().fdd_cnn_adam_step(self.h, self._p(theta, "theta"), self._p(grad, "grad"), self._p(m, "m"),
+                                        self._p(v, "v"), lr, b1, b2, eps, step, _stream(stream)))
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

@@ -116,6 +116,54 @@ def test_batch_of_the_batched_workload_at_bench_settings():
           f"{stats[0]['t_solve_ms']:.1f} ms", flush=True)
 
 
+def test_batch_of_32_instances_at_n1024_at_target_tolerance():
+    # the benchmark's 32 x 1024^2 batch (K, mu log-uniform as in the batched workload), every
+    # instance held to ||x - x_ref|| / ||x_ref|| <= 1e-8 at outer rtol 1e-10, inner rtol 1e-12,
+    # after a first call that measures the schedule (the second call replays graphs)
+    cases = workloads.batch_instances(count=32, seed=4, sizes=[1024])
+    print("[batch 32 x 1024^2]", flush=True)
+    B, probs, TP, TH, bs = make_batch(cases)
+    opts = F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12, mg_nu=2)
+    xs = [torch.zeros_like(b) for b in bs]
+    B.solve(bs, xs, opts)
+    xs = [torch.zeros_like(b) for b in bs]
+    stats = B.solve(bs, xs, opts)
+    worst = 0.0
+    for i, c in enumerate(cases):
+        x_ref = system.solve_dst_2d(c["n"], c["K"], c["mu"], host(bs[i]))
+        err = rel(host(xs[i]), x_ref)
+        worst = max(worst, err)
+        assert stats[i]["status"] == F.FDD_OK
+        assert err <= 1e-8, (i, c, err)
+    print(f"  worst rel err {worst:.2e}; outer its {[s['outer_its'] for s in stats]}; "
+          f"{stats[0]['t_solve_ms']:.1f} ms per batch", flush=True)
+
+
+def test_batch_graphs_follow_the_tolerances():
+    # a batch solved at outer rtol 1e-8 (graphs captured), then at 1e-10 with a tighter inner
+    # tolerance: the second solve must run to the new tolerances (they are kernel arguments
+    # baked into captured graphs), i.e. match a fresh batch and the oracle at 1e-8
+    cases = workloads.batch_instances(count=5, seed=17, sizes=[64, 128, 256])
+    print("[batch graph keys]", flush=True)
+    B, probs, TP, TH, bs = make_batch(cases)
+    lo = F.opts_default(outer_rtol=1e-8, inner_rtol=1e-10)
+    hi = F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12)
+    for _ in range(2):
+        xs = [torch.zeros_like(b) for b in bs]
+        st_lo = B.solve(bs, xs, lo)
+    xs = [torch.zeros_like(b) for b in bs]
+    st_hi = B.solve(bs, xs, hi)
+    B2, _, _, _, bs2 = make_batch(cases)
+    xs2 = [torch.zeros_like(b) for b in bs2]
+    st2 = B2.solve(bs2, xs2, hi)
+    for i, c in enumerate(cases):
+        x_ref = system.solve_dst_2d(c["n"], c["K"], c["mu"], host(bs[i]))
+        assert st_hi[i]["outer_its"] == st2[i]["outer_its"] > st_lo[i]["outer_its"], i
+        assert st_hi[i]["rel_precond_res"] <= 1e-10
+        assert rel(host(xs[i]), x_ref) <= 1e-8
+        assert rel(host(xs[i]), host(xs2[i])) <= 1e-9
+
+
 def test_batched_graph_replay_matches_eager_launches():
     cases = workloads.batch_instances(count=6, seed=11, sizes=[64, 96, 128, 160, 192, 256])
     print("[batch graph]", flush=True)

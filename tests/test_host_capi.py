@@ -145,3 +145,32 @@ def test_setup_3d_sizes_bounds_and_validation():
             F.setup_mesh(bad, 1.0, 1.0, dim=3)
     T = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-10)
     assert T.query()["max_rel_err"] <= 1e-9
+
+
+def test_binding_rejects_vectors_the_kernels_cannot_take():
+    # the marshaller checks length, dtype and device before any library call, so a short,
+    # mistyped or host-resident vector never reaches a kernel (no GPU is touched here)
+    torch = pytest.importorskip("torch")
+    n = 16
+    P = F.setup_mesh(n, 1.0, 1.0)
+    TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-10)
+    TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-10)
+    good = torch.zeros(P.N, dtype=torch.float64)
+    short = torch.zeros(P.N - 1, dtype=torch.float64)
+    f32 = torch.zeros(P.N, dtype=torch.float32)
+    with pytest.raises(ValueError, match="entries"):
+        P.solve(TP, TH, short, good)
+    with pytest.raises(ValueError, match="float64"):
+        P.solve(TP, TH, f32, good)
+    with pytest.raises(ValueError, match="cuda:0"):
+        P.solve(TP, TH, good, good)
+    with pytest.raises(ValueError, match="entries"):
+        P.interior_solve(torch.zeros(P.NI + 1, dtype=torch.float64), torch.zeros(P.NI, dtype=torch.float64))
+    with pytest.raises(ValueError, match="entries"):
+        P.schur_apply(TH, torch.zeros(P.NG - 1, dtype=torch.float64), torch.zeros(P.NG, dtype=torch.float64))
+    with pytest.raises(ValueError, match="float64"):
+        P.precond_apply(TP, torch.zeros(P.NG, dtype=torch.float32), torch.zeros(P.NG, dtype=torch.float64))
+    with pytest.raises(ValueError, match="entries"):
+        P.apply_operator(TH, torch.zeros(P.NG, dtype=torch.float64), good)
+    with pytest.raises(TypeError):
+        P.apply_operator(TH, good.numpy(), good)

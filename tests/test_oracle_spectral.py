@@ -91,3 +91,32 @@ def test_paper_pole_count_statement():
     assert abs(len(p) - m_paper) <= 6
     # the interface size statement: 6 n^2 + 2 nodes on the boundary of the cube at n = 32
     assert 6 * 32 * 32 + 2 < gold["interface_unknowns_3d_upper"]["value"]
+
+
+@pytest.mark.parametrize("dim,n", [(2, 16), (2, 48), (3, 6)])
+def test_operator_table_realizes_inverse_square_root(dim, n):
+    # eq. (RA) applied to g(lambda) = lambda^{-1/2}: M (d0 M^{-1} + sum_k d_k (L + q_k M)^{-1}) M
+    # must equal the exact L^{-1/2} = (M U) Lambda^{-1/2} (M U)^T of eq. (gevp) to the table's
+    # error on the spectrum (relative, since both are SPD and share the eigenvectors U)
+    P = fem.Problem(dim, n)
+    L, M = P.A_G, P.M_G
+    lam, _ = spectral.gevp(L, M)
+    d0, d, q = aaa.ra_table(spectral.g_operator, lam[0], lam[-1], tol=1e-12, extra=lam)
+    err = ra.max_rel_error(spectral.g_operator, d0, d, q, lam)
+    H_ra = ra.dense_operator_H(L, M, d0, d, q)
+    H = spectral.frac_power(L, M, -0.5)
+    assert np.linalg.norm(H_ra - H, 2) <= 2 * err * np.linalg.norm(H, 2)
+    # a dropped term is visible: without the d0 M part the operator is off by far more
+    H_bad = ra.dense_operator_H(L, M, 0.0, d, q)
+    assert np.linalg.norm(H_bad - H, 2) > 1e3 * err * np.linalg.norm(H, 2)
+
+
+def test_tridiagonal_ra_apply_equals_dense_operator():
+    P = fem.Problem(2, 40)
+    L, M = P.A_G, P.M_G
+    lam = spectral.interface_eigs_1d(40)
+    c0, c, p = aaa.ra_table(spectral.f_precond(1e-2, 1e3), lam[0], lam[-1], tol=1e-10, extra=lam)
+    r = np.random.default_rng(2).standard_normal(39)
+    z = ra.apply_tridiagonal(L, M, c0, c, p, r)
+    zd = ra.dense_operator(L, M, c0, c, p) @ r
+    assert np.linalg.norm(z - zd) <= 1e-12 * np.linalg.norm(zd)

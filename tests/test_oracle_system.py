@@ -117,3 +117,36 @@ def test_small_K_makes_preconditioner_exact():
     R = system.Riesz(2, 16, 1e-12, 1.0)
     _, its, _ = R.schur_pcg(workloads.rhs(2, 16, 1), rtol=1e-8)
     assert its <= 2
+
+
+@pytest.mark.parametrize("n,K,mu", [(16, 1.0, 1.0), (32, 1e-2, 1e-3), (24, 1e-4, 1e3), (32, 1.0, 1e-6)])
+def test_sine_basis_schur_pcg_equals_assembled_schur_pcg(n, K, mu):
+    # the same PCG, once on assembled matrices (LU of A_II, dense S_Gamma^{-1} or a dense RA
+    # operator) and once in the sine basis: same iteration count, same residual history, same x
+    from oracle import aaa, ra, spectral
+    R = system.Riesz(2, n, K, mu)
+    b = workloads.rhs(2, n, 11)
+    x1, its1, h1 = R.schur_pcg(b, rtol=1e-10)
+    x2, its2, h2 = system.schur_pcg_dst_2d(n, K, mu, b, spectral.f_precond(K, 1.0 / mu), rtol=1e-10)
+    assert its1 == its2
+    assert np.allclose(h1, h2, rtol=1e-8, atol=1e-12 * h1[0])
+    assert rel(x2, x1) < 1e-11
+    assert rel(x2, R.solve_dense(b)) < 1e-9
+    # with a coarse rational table as the preconditioner (many more iterations)
+    lam = spectral.interface_eigs_1d(n)
+    c0, c, p = aaa.ra_table(spectral.f_precond(K, 1.0 / mu), lam[0], lam[-1], tol=1e-3, extra=lam)
+    D = ra.dense_operator(R.P.A_G, R.P.M_G, c0, c, p)
+    x3, its3, h3 = R.schur_pcg(b, precond=lambda r: D @ r, rtol=1e-10)
+    x4, its4, h4 = system.schur_pcg_dst_2d(n, K, mu, b, lambda l: ra.eval_scalar(c0, c, p, l), rtol=1e-10)
+    assert its3 == its4
+    assert np.allclose(h3, h4, rtol=1e-7, atol=1e-12 * h3[0])
+    assert rel(x4, x3) < 1e-10
+
+
+def test_sine_basis_schur_pcg_large_n_solves_the_system():
+    n, K, mu = 512, 1e-2, 1e-3
+    from oracle import spectral
+    b = workloads.rhs(2, n, 12)
+    x, its, _ = system.schur_pcg_dst_2d(n, K, mu, b, spectral.f_precond(K, 1.0 / mu), rtol=1e-11)
+    assert rel(x, system.solve_dst_2d(n, K, mu, b)) < 1e-10
+    assert 2 <= its <= 20
