@@ -177,6 +177,19 @@ int fdd_schur_apply(fdd_problem prob, fdd_ratpc H, const double* x_G, double* y_
  * Asynchronous.                                                                              */
 int fdd_precond_apply(fdd_problem prob, fdd_ratpc P, const double* r_G, double* z_G, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same z_G as fdd_precond_apply (same kernels,
+ * same summation order, bit-identical), with the systems' solutions staged in a library-owned
+ * static device array of (64 + 1) x 2048 FP64 entries (1.02 MiB, held on each device the
+ * library runs on until the process ends) instead of the bound workspace.  No workspace needs
+ * to be bound (2D only); nothing is allocated.  Every call on one device shares that array, so
+ * calls that overlap on one device (different streams, or threads) race: serialize them.
+ * Errors: FDD_E_ARG for dim 3, or a table / interface size beyond the array (m + 1 > 65
+ * systems or N_G > 2048); FDD_E_HIP if the array's device address cannot be found.
+ * Asynchronous.                                                                              */
+int fdd_precond_apply_static(fdd_problem prob, fdd_ratpc P, const double* r_G, double* z_G,
+                             void* stream);
+
 /* y = A x = K A_Omega x + gamma T^T H_RA T x on all N free dofs.  Asynchronous.             */
 int fdd_apply_operator(fdd_problem prob, fdd_ratpc H, const double* x, double* y, void* stream);
 

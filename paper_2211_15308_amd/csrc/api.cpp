@@ -666,6 +666,26 @@ int fdd_precond_apply(fdd_problem P, fdd_ratpc T, const double* r, double* z, vo
   return FDD_OK;
 }
 
+int fdd_precond_apply_static(fdd_problem P, fdd_ratpc T, const double* r, double* z, void* stream) {
+  if (!P) return fail(FDD_E_ARG, "null problem");
+  int rc = check_table(P, T, FDD_RA_PRECOND);
+  if (rc) return rc;
+  if (!r || !z) return fail(FDD_E_ARG, "null vector");
+  if (P->dim != 2) return fail(FDD_E_ARG, "the static-scratch preconditioner apply is 2D only");
+  ShiftTable tab = make_table(T);
+  if (tab.m > kStaticPrecondSystems || P->NG > kStaticPrecondN)
+    return fail(FDD_E_ARG, "%d systems of %lld unknowns exceed the static scratch (%d x %d)", tab.m,
+                (long long)P->NG, kStaticPrecondSystems, kStaticPrecondN);
+  HIPCHK(hipSetDevice(P->device));
+  double* scratch = nullptr;
+  if (static_precond_scratch(P->device, &scratch))
+    return fail(FDD_E_HIP, "device %d: no address for the static scratch", P->device);
+  launch_iface_batch((hipStream_t)stream, (int)P->NG, P->h, tab, kIfacePrecond, r, z, scratch,
+                     nullptr, nullptr, nullptr, 0, 0);
+  HIPCHK(hipGetLastError());
+  return FDD_OK;
+}
+
 int fdd_schur_apply(fdd_problem P, fdd_ratpc H, const double* x, double* y, const fdd_opts* opts,
                     void* stream) {
   int rc = check_problem(P);

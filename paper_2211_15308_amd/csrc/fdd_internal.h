@@ -179,6 +179,14 @@ struct ShiftTable {
 
 enum IfaceMode { kIfacePrecond = 0, kIfaceOperator = 1, kIfacePrecondOuter = 2 };
 
+// Static scratch of the no-allocation preconditioner apply: kStaticPrecondSystems systems of up
+// to kStaticPrecondN unknowns.  static_precond_scratch looks its address up on `device`, which
+// must be current, once per device (0 on success).
+constexpr int kStaticPrecondSystems = kMaxPoles + 1;
+constexpr int kStaticPrecondN = 2048;
+constexpr int kMaxStaticDevices = 64;
+int static_precond_scratch(int device, double** out);
+
 void launch_iface_batch(hipStream_t s, int ng, double h, const ShiftTable& tab, int mode,
                         const double* in, double* out, double* scratch, DevState* st,
                         const double* p_prev, double* p_next, int ver, int first);

@@ -10,6 +10,8 @@
 // the epilogue (outer-PCG update, or the mass products of the operator H).
 #include "iface_device.h"
 
+#include <mutex>
+
 namespace fdd {
 
 __global__ __launch_bounds__(kIfaceThreads) void k_iface_solve(int n, double h, ShiftTable tab,
@@ -160,6 +162,27 @@ __global__ __launch_bounds__(256) void k_full_operator(int n, double K, double g
       res[1] = tb;
     }
   }
+}
+
+// ---- device-resident scratch for callers that cannot allocate --------------------------------
+// Room for kStaticPrecondSystems shifted systems of up to kStaticPrecondN unknowns (1.02 MiB).
+// Each device holds its own copy at its own address; host code uses the address returned by
+// hipGetSymbolAddress on that device, never the array's name.
+static_assert(kStaticPrecondN <= kIfaceMaxN, "static scratch rows exceed the interface kernels");
+static __device__ __align__(256) double precond_scratch[(size_t)kStaticPrecondSystems * kStaticPrecondN];
+
+int static_precond_scratch(int device, double** out) {
+  static std::mutex mu;
+  static double* addr[kMaxStaticDevices] = {};
+  if (device < 0 || device >= kMaxStaticDevices) return -1;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(precond_scratch)) != hipSuccess || !p) return -2;
+    addr[device] = (double*)p;
+  }
+  *out = addr[device];
+  return 0;
 }
 
 // ---- launchers ----------------------------------------------------------------------------

@@ -36,7 +36,8 @@ STATUS_NAMES = {
 EXPORTED = [
     "fdd_opts_default", "fdd_setup_mesh", "fdd_problem_info", "fdd_workspace_bytes",
     "fdd_bind_workspace", "fdd_build_rational_pc", "fdd_ratpc_from_table", "fdd_ratpc_query",
-    "fdd_interior_solve", "fdd_schur_apply", "fdd_precond_apply", "fdd_apply_operator",
+    "fdd_interior_solve", "fdd_schur_apply", "fdd_precond_apply", "fdd_precond_apply_static",
+    "fdd_apply_operator",
     "fdd_solve", "fdd_set_kernel_timer", "fdd_get_kernel_timer", "fdd_destroy_problem",
     "fdd_destroy_ratpc", "fdd_last_error", "fdd_version", "fdd_batch_create",
     "fdd_batch_workspace_bytes", "fdd_batch_bind_workspace", "fdd_solve_batched",
@@ -106,6 +107,7 @@ def load():
     lib.fdd_interior_solve.argtypes = [P, V, V, ctypes.POINTER(FddOpts), V, ctypes.POINTER(I)]
     lib.fdd_schur_apply.argtypes = [P, P, V, V, ctypes.POINTER(FddOpts), V]
     lib.fdd_precond_apply.argtypes = [P, P, V, V, V]
+    lib.fdd_precond_apply_static.argtypes = [P, P, V, V, V]
     lib.fdd_apply_operator.argtypes = [P, P, V, V, V]
     lib.fdd_solve.argtypes = [P, P, P, V, V, ctypes.POINTER(FddOpts), V, ctypes.POINTER(FddStats)]
     lib.fdd_set_kernel_timer.argtypes = [P, I, D]
@@ -290,6 +292,11 @@ class Problem:
     def precond_apply(self, P, r_G, z_G, stream=None):
         _check(load().fdd_precond_apply(self.h, P.h, self._v(r_G, self.NG, "r_G"), self._v(z_G, self.NG, "z_G"),
                                         _stream(stream)))
+
+    def precond_apply_static(self, P, r_G, z_G, stream=None):
+        """fdd_precond_apply_static: the same product with no workspace and no allocation."""
+        _check(load().fdd_precond_apply_static(self.h, P.h, self._v(r_G, self.NG, "r_G"),
+                                               self._v(z_G, self.NG, "z_G"), _stream(stream)))
 
     def apply_operator(self, H, x, y, stream=None):
         _check(load().fdd_apply_operator(self.h, H.h, self._v(x, self.N, "x"), self._v(y, self.N, "y"),
