@@ -21,6 +21,8 @@ Domain decomposition pieces (Sec. 2, eq. (block_op), eq. (dd_preconditioner)):
                        residual norm (r^T z)^{1/2} has fallen by the factor rtol (Sec. 3)
   * ``full_pcg``       PCG on the whole A with the symmetric block preconditioner B of
                        eq. (dd_preconditioner), exact leading block
+  * ``lazy_full_pcg``  the same PCG with the operator's H by RA and B's leading block by one
+                       multigrid V-cycle (remark on evaluating the operator, Sec. 3)
 
 Parity: pinned by agreement of the three solvers, by the closed-form Schur and
 harmonic-extension spectra in 2D, by the gamma = 0 reduction to the mixed
@@ -200,6 +202,80 @@ class Riesz:
             rz = rz_new
             its += 1
         return x, its
+
+
+# ----------------------------------------------------------------------------
+# Full-system PCG with the lazy block preconditioner (remark on evaluating the operator)
+# ----------------------------------------------------------------------------
+
+def operator_ra(R, tabH):
+    """x -> A_RA x = K A_Omega x + gamma T^T H_RA T x, with H_RA the rational realization of
+    L^{-1/2} by the table (d0, d_k, q_k): H_RA = M (d0 M^{-1} + sum_k d_k (L + q_k M)^{-1}) M
+    (eq. (RA) for g(lambda) = lambda^{-1/2}; the remark on evaluating the operator, Sec. 3)."""
+    from . import ra
+    P = R.P
+    d0, d, q = tabH
+    HR = ra.dense_operator_H(P.A_G, P.M_G, d0, d, q)
+
+    def apply(x):
+        y = R.K * (P.A @ x)
+        y[P.NI:] += R.gamma * (HR @ x[P.NI:])
+        return y
+    return apply, HR
+
+
+def lazy_precond(R, tabP, vcycle):
+    """r -> B r, the preconditioner of eq. (dd_preconditioner) with the leading block
+    (A^00)^{-1} = (K A_II)^{-1} replaced by V / K (V one multigrid V-cycle for A_II, a
+    ``multigrid.VCycle``) and S_Gamma^{-1} by the rational table (c0, c_k, p_k) of eq. (RA).
+
+    With A^{i0} = K A_GI and A^{0i} = K A_IG the three factors give
+      lower:     t_G = r_G - A^{i0} (V r_I / K) = r_G - A_GI V r_I
+      diagonal:  y_I = V r_I / K,  z_G = S_Gamma^{-1} t_G
+      upper:     z_I = y_I - (V / K) A^{0i} z_G = V (r_I - K A_IG z_G) / K.
+    Every factor is applied as written (two V-cycles per application)."""
+    from . import ra
+    P = R.P
+    NI = P.NI
+    _, A_IG, A_GI, _ = P.blocks()
+    c0, c, p = tabP
+
+    def apply(r):
+        rI, rG = r[:NI], r[NI:]
+        tG = rG - A_GI @ vcycle.apply(rI)
+        zG = ra.apply_tridiagonal(P.A_G, P.M_G, c0, c, p, tG)
+        zI = vcycle.apply(rI - R.K * (A_IG @ zG)) / R.K
+        return np.concatenate([zI, zG])
+    return apply
+
+
+def lazy_full_pcg(R, b, tabP, tabH, nu=2, exact_nf=0, rtol=1e-10, maxit=500):
+    """PCG on the whole system A_RA x = b (operator with H by RA) preconditioned by the lazy B
+    (one V-cycle for the leading block, RA for S_Gamma^{-1}); x_0 = 0, stop when (r^T z)^{1/2}
+    has fallen by rtol (Sec. 3).  Returns (x, iterations, history of (r^T z)^{1/2})."""
+    from .multigrid import VCycle
+    V = VCycle(R.n - 1, nu=nu, exact_nf=exact_nf)
+    A, _ = operator_ra(R, tabH)
+    B = lazy_precond(R, tabP, V)
+    x = np.zeros_like(b)
+    r = np.array(b, dtype=np.float64)
+    z = B(r)
+    rz = rz0 = r @ z
+    hist = [np.sqrt(rz)]
+    p = z.copy()
+    its = 0
+    while np.sqrt(rz) > rtol * np.sqrt(rz0) and its < maxit:
+        q = A(p)
+        alpha = rz / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        z = B(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        its += 1
+        hist.append(np.sqrt(abs(rz)))
+    return x, its, hist
 
 
 # ----------------------------------------------------------------------------
