@@ -201,6 +201,29 @@ int fdd_apply_operator(fdd_problem prob, fdd_ratpc H, const double* x, double* y
 int fdd_solve(fdd_problem prob, fdd_ratpc P, fdd_ratpc H, const double* b, double* x,
               const fdd_opts* opts, void* stream, fdd_stats* stats);
 
+/* ---- full-system PCG with the lazy block preconditioner -------------------------------------
+ * The preconditioner of eq. (dd_preconditioner) in the form of the paper's remark on evaluating
+ * the operator (Sec. 3, Fig. 4-left), 2D only: the leading block (A^00)^{-1} = (K A_II)^{-1} is
+ * replaced by one multigrid V-cycle V / K (the interior solver's symmetric V(nu, nu) cycle,
+ * nu = opts->mg_nu; FP64 arithmetic for opts->precision = FDD_FP64, FP32 for FDD_MIXED) and
+ * S_Gamma^{-1} by the table P (eq. (RA)):
+ *     t_G = r_G - A_GI V r_I,   z_G = S_Gamma^{-1} t_G,   z_I = V (r_I - K A_IG z_G) / K.
+ * fdd_dd_precond_apply: z = B r on all N free dofs (r, z: device, length N, caller layout).
+ * Asynchronous.  Errors: FDD_E_ARG (dim 3, null vector, invalid options), FDD_E_STATE (a
+ * table of another problem or kind), FDD_E_WORKSPACE (none bound).                          */
+int fdd_dd_precond_apply(fdd_problem prob, fdd_ratpc P, const double* r, double* z,
+                         const fdd_opts* opts, void* stream);
+/* fdd_solve_full: x = A^{-1} b by PCG on the whole system, A = K A_Omega + gamma T^T H_RA T with
+ * H by the table H (so every iteration costs two V-cycles, two batches of shifted interface
+ * solves and two stencil passes, and no interior solve), preconditioned by B above; x_0 = 0,
+ * stop when (r^T z)^{1/2} <= outer_rtol (r_0^T z_0)^{1/2} (Sec. 3).  inner_rtol, step_rtol and
+ * use_graph are not used (eager launches, one read-back per iteration).  stats: outer_its = PCG
+ * iterations, inner_solves = V-cycles, true_rel_res if check_true_residual.  Returns
+ * FDD_NOT_CONVERGED after outer_maxit iterations (x holds the last iterate), FDD_E_BREAKDOWN /
+ * FDD_E_NONFINITE on breakdown.  Synchronizes the stream once per iteration.                */
+int fdd_solve_full(fdd_problem prob, fdd_ratpc P, fdd_ratpc H, const double* b, double* x,
+                   const fdd_opts* opts, void* stream, fdd_stats* stats);
+
 /* ---- batched solves -------------------------------------------------------------------------
  * Many independent problems of possibly different n, K, mu (and tables) solved together: the
  * same method as fdd_solve, applied to every instance, with each kernel launch covering all

@@ -174,5 +174,8 @@ int cnn_warm_guess(fdd_cnn_s* C, hipStream_t s, const double* trace, int n, cons
                    const float** guess, const double** scale);
 int check_problem(fdd_problem_s* P);
 int check_table(const fdd_problem_s* P, const fdd_ratpc_s* t, int which);
+LaunchCtx make_ctx(const fdd_problem_s* P, hipStream_t s, int nu, bool fp64);
+// copies the device state to the pinned host copy (synchronizes the stream)
+int read_state(fdd_problem_s* P, hipStream_t s);
 
 }  // namespace fdd

@@ -155,6 +155,12 @@ template <typename T>
 void launch_pcg_iteration(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
                           T* r_new, T* z, T* p_old, T* p_new, bool update_only = false);
 
+// One V-cycle z = V f on its own (the preconditioner of the full-system PCG, not inside an
+// interior solve): the same kernels as the start of a PCG run, without its bookkeeping.  The
+// problem's flags must not mark a stopped solve (the kernels return at once then).
+template <typename T>
+void launch_vcycle(const LaunchCtx& c, const MGBuffers<T>& mg, const T* f, T* z);
+
 // FP64 refinement residual: uout = uin + e (uout = 0 on the first call; a plain copy once the
 // solve has converged), r = f - A uout.  The step's bookkeeping (convergence test, state of the
 // next PCG run) is done by the first kernel of the next PCG run; finalize = true adds a one-block
@@ -294,5 +300,35 @@ double ra_eval_rel_err(int which, double K, double gamma, const RaResult& r, con
 // dense linear algebra used by the builder (exposed for host tests)
 int eig_real_general(int n, const double* A, double* wr, double* wi);   // A row-major
 int svd_min_right(int rows, int cols, const double* A, double* v, double* smin, double* smax);
+
+// ---- full-system PCG with the lazy block preconditioner (kernels_full.hip) ----------------
+// Buffers of one problem as the full-system PCG uses them: interior parts on the padded level-0
+// grid (FP64), Gamma parts as n - 1 vectors.
+struct FullCtx {
+  hipStream_t stream;
+  int nf, pitch;
+  double K, gamma, h;
+  double *xI, *rI, *pI[2], *qI;
+  double *xG, *rG, *pG[2], *qG, *zG, *tG, *Hp;
+  double *scratchP, *scratchH, *partials;
+  DevState* st;
+};
+// r = b, x = 0; vr = vf = r_I in the V-cycle's precision
+template <typename VT>
+void launch_full_init(const FullCtx& c, const double* b, VT* vr, VT* vf);
+// t_G = r_G + W|top row, z_G = S_Gamma^{-1} t_G (table P), vf|top row = r_I + K z_G
+template <typename VT>
+void launch_full_precond_tail(const FullCtx& c, const ShiftTable& tabP, const VT* W, VT* vf);
+// rz = r . z (z_I = Z / K) into st->o_rho[cur], beta, and the stop test (first: rz_0)
+template <typename VT>
+void launch_full_rz(const FullCtx& c, const VT* Z, int cur, int first, double rtol2);
+// p = z + beta p' (version a -> a ^ 1), q = A p with H_RA by table H, alpha = rz / p.q,
+// x += alpha p, r -= alpha q, vr = vf = r_I
+template <typename VT>
+void launch_full_step(const FullCtx& c, const ShiftTable& tabH, const VT* Z, int a, int cur,
+                      int first, VT* vr, VT* vf);
+// out (caller layout) = (aI * sI, aG)
+template <typename VT>
+void launch_full_scatter(const FullCtx& c, const VT* aI, double sI, const double* aG, double* out);
 
 }  // namespace fdd

@@ -281,6 +281,31 @@ void launch_pcg_init(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* 
 }
 
 template <typename T, int NU>
+static void vcycle_nu(const LaunchCtx& c, const MGBuffers<T>& mg, const T* f, T* z) {
+  const Level& L = c.lev[0];
+  auto down0 = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, tiles(L.nf), tblock(), 0, c.stream, f, mg.u[0], mg.f[1], L.nf,
+                       L.pitch, c.lev[1].pitch, (const T*)nullptr, (const T*)nullptr, (T*)nullptr,
+                       (T*)nullptr, (T*)nullptr, c.st, c.red, 0, 0, 0, 0);
+  };
+  if constexpr (sizeof(T) == 4) {
+    if (c.red.nb0 <= kResidentTiles) down0(k_mg_down<T, NU, false, kTile, true>);
+    else down0(k_mg_down<T, NU, false, kTile, false>);
+  } else {
+    down0(k_mg_down<T, NU, false, kTile, false>);
+  }
+  vcycle_tail_nu<T, NU>(c, mg, 0);
+  hipLaunchKernelGGL((k_mg_up<T, NU, false>), tiles(L.nf), tblock(), 0, c.stream, f, mg.u[0],
+                     mg.e[1], z, L.nf, L.pitch, c.lev[1].pitch, c.st, c.red, 0, 0);
+}
+
+template <typename T>
+void launch_vcycle(const LaunchCtx& c, const MGBuffers<T>& mg, const T* f, T* z) {
+  if (c.nu == 2) vcycle_nu<T, 2>(c, mg, f, z);
+  else vcycle_nu<T, 1>(c, mg, f, z);
+}
+
+template <typename T, int NU>
 static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
                         T* r_new, T* z, T* p_old, T* p_new, bool update_only) {
   const Level& L = c.lev[0];
@@ -341,6 +366,10 @@ template void launch_pcg_init<float>(const LaunchCtx&, const MGBuffers<float>&, 
                                      float*);
 template void launch_pcg_init<double>(const LaunchCtx&, const MGBuffers<double>&, const double*,
                                       double*);
+template void launch_vcycle<float>(const LaunchCtx&, const MGBuffers<float>&, const float*,
+                                   float*);
+template void launch_vcycle<double>(const LaunchCtx&, const MGBuffers<double>&, const double*,
+                                    double*);
 template void launch_pcg_iteration<float>(const LaunchCtx&, const MGBuffers<float>&, int, float*,
                                           float*, float*, float*, float*, float*, bool);
 template void launch_pcg_iteration<double>(const LaunchCtx&, const MGBuffers<double>&, int,

@@ -37,7 +37,7 @@ EXPORTED = [
     "fdd_opts_default", "fdd_setup_mesh", "fdd_problem_info", "fdd_workspace_bytes",
     "fdd_bind_workspace", "fdd_build_rational_pc", "fdd_ratpc_from_table", "fdd_ratpc_query",
     "fdd_interior_solve", "fdd_schur_apply", "fdd_precond_apply", "fdd_precond_apply_static",
-    "fdd_apply_operator",
+    "fdd_apply_operator", "fdd_dd_precond_apply", "fdd_solve_full",
     "fdd_solve", "fdd_set_kernel_timer", "fdd_get_kernel_timer", "fdd_destroy_problem",
     "fdd_destroy_ratpc", "fdd_last_error", "fdd_version", "fdd_batch_create",
     "fdd_batch_workspace_bytes", "fdd_batch_bind_workspace", "fdd_solve_batched",
@@ -110,6 +110,8 @@ def load():
     lib.fdd_precond_apply_static.argtypes = [P, P, V, V, V]
     lib.fdd_apply_operator.argtypes = [P, P, V, V, V]
     lib.fdd_solve.argtypes = [P, P, P, V, V, ctypes.POINTER(FddOpts), V, ctypes.POINTER(FddStats)]
+    lib.fdd_dd_precond_apply.argtypes = [P, P, V, V, ctypes.POINTER(FddOpts), V]
+    lib.fdd_solve_full.argtypes = [P, P, P, V, V, ctypes.POINTER(FddOpts), V, ctypes.POINTER(FddStats)]
     lib.fdd_set_kernel_timer.argtypes = [P, I, D]
     lib.fdd_get_kernel_timer.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D),
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D),
@@ -307,6 +309,19 @@ class Problem:
         rc = load().fdd_solve(self.h, P.h, H.h, self._v(b, self.N, "b"), self._v(x, self.N, "x"),
                               ctypes.byref(opts or opts_default()),
                               _stream(stream), ctypes.byref(st))
+        _check(rc, (FDD_OK, FDD_NOT_CONVERGED) if allow_not_converged else (FDD_OK,))
+        return st.as_dict()
+
+    def dd_precond_apply(self, P, r, z, opts=None, stream=None):
+        """z = B r with the lazy block preconditioner (fdd_dd_precond_apply)."""
+        _check(load().fdd_dd_precond_apply(self.h, P.h, self._v(r, self.N, "r"), self._v(z, self.N, "z"),
+                                           ctypes.byref(opts or opts_default()), _stream(stream)))
+
+    def solve_full(self, P, H, b, x, opts=None, stream=None, allow_not_converged=False):
+        """Full-system PCG with the lazy block preconditioner (fdd_solve_full)."""
+        st = FddStats()
+        rc = load().fdd_solve_full(self.h, P.h, H.h, self._v(b, self.N, "b"), self._v(x, self.N, "x"),
+                                   ctypes.byref(opts or opts_default()), _stream(stream), ctypes.byref(st))
         _check(rc, (FDD_OK, FDD_NOT_CONVERGED) if allow_not_converged else (FDD_OK,))
         return st.as_dict()
 
