@@ -59,6 +59,8 @@ def parse():
                     help="run the learned-warm-start comparison (auto: if weights exist)")
     ap.add_argument("--learned-steps", type=int, default=6)
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D cases")
+    ap.add_argument("--full-lazy", choices=["auto", "none", "only"], default="auto",
+                    help="the full-system PCG with the lazy block preconditioner beside the headline")
     ap.add_argument("--cnn-only", action="store_true", help="only time the warm-start network kernels")
     ap.add_argument("--only-3d", action="store_true")
     ap.add_argument("--sweep", action="store_true",
@@ -437,6 +439,54 @@ def run_learned(F, args, leg, sizes=(256, 512, 1024), mus=(1e-3, 1.0)):
     return res
 
 
+def run_full_lazy(F, args, leg, n=1024, reps=2):
+    """Full-system PCG with the lazy block preconditioner (one V-cycle for the leading block, H and
+    S_Gamma^{-1} by RA) on the headline's 12 (K, mu) cases: solves/s, PCG counts and parity
+    against the separable oracle, FP32 and FP64 V-cycles, same outer rtol.  Each case is solved
+    once untimed, then `reps` times on timed right-hand sides."""
+    import torch
+
+    import workloads
+    res = {"n": n, "rtol": args.rtol, "mg_nu": args.nu, "variants": {}}
+    case_list = cases(args)
+    probs = []
+    for ci, (K, mu) in enumerate(case_list):
+        P = F.setup_mesh(n, K, mu)
+        P.bind_workspace()
+        TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+        TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+        bs = [torch.as_tensor(workloads.rhs(2, n, timed_seed(ci, k)), dtype=torch.float64, device="cuda")
+              for k in range(reps)]
+        b_cal = torch.as_tensor(workloads.rhs(2, n, calibration_seed(ci)), dtype=torch.float64, device="cuda")
+        probs.append((P, TP, TH, b_cal, bs, K, mu))
+    for label, prec in (("fp32_vcycles", F.FDD_MIXED), ("fp64_vcycles", F.FDD_FP64)):
+        opts = F.opts_default(outer_rtol=args.rtol, precision=prec, mg_nu=args.nu, outer_maxit=200,
+                              check_true_residual=1)
+        for P, TP, TH, b_cal, bs, K, mu in probs:
+            P.solve_full(TP, TH, b_cal, torch.zeros_like(b_cal), opts)
+        torch.cuda.synchronize()
+        rows = []
+        t0 = time.perf_counter()
+        for k in range(reps):
+            for P, TP, TH, b_cal, bs, K, mu in probs:
+                x = torch.zeros_like(bs[k])
+                st = P.solve_full(TP, TH, bs[k], x, opts)
+                rows.append({"K": K, "mu": mu, "its": st["outer_its"], "true_rel_res": st["true_rel_res"], "x": x,
+                             "b": bs[k]})
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        v = {"solves_per_s": len(rows) / el, "ms_per_solve": 1e3 * el / len(rows),
+             "its_min_mean_max": [min(r["its"] for r in rows), sum(r["its"] for r in rows) / len(rows),
+                                  max(r["its"] for r in rows)],
+             "true_rel_res_max": max(r["true_rel_res"] for r in rows),
+             "rel_err_vs_oracle_first3": [None] * 3}
+        for q in range(3):
+            r = rows[q]
+            leg.check(v["rel_err_vs_oracle_first3"], q, n, r["K"], r["mu"], r["b"], r["x"])
+        res["variants"][label] = v
+    return res
+
+
 def run_sweep(F, args, leg, sizes=(128, 256, 512, 1024, 2048)):
     """2D sweep n x K in {1, 1e-2, 1e-4} x mu in {1e-6, 1e-3, 1, 1e3} (seed 1000 + index): outer and
     inner iterations, solves/s (one warm-up and two timed solves) and the error of the solution."""
@@ -552,6 +602,12 @@ def main():
         res = run_sweep(F, args, leg)
         leg.run()
         print(json.dumps({"sweep": res}))
+        return
+    if args.full_lazy == "only":
+        leg = OracleLeg()
+        res = run_full_lazy(F, args, leg)
+        leg.run()
+        print(json.dumps({"full_lazy": res}))
         return
     if args.learned == "only":
         leg = OracleLeg()
@@ -709,6 +765,8 @@ def main():
         "cpu_baseline": None,
     }
     out.update(batched)
+    if args.full_lazy == "auto":
+        out["full_lazy"] = run_full_lazy(F, args, leg)
     if args.learned == "auto":
         out["learned"] = run_learned(F, args, leg)
     if not args.no_3d:

@@ -727,7 +727,7 @@ int fdd_apply_operator(fdd_problem P, fdd_ratpc H, const double* x, double* y, v
   launch_iface_batch(s, (int)P->NG, P->h, tab, kIfaceOperator, x + P->NI, P->Hp, P->scratchH,
                      P->st, nullptr, nullptr, 0, 0);
   launch_full_operator(s, P->n, P->K, P->gamma, x, P->Hp, y, nullptr, P->partials,
-                       &P->st->counters[9], P->st->t_res);
+                       P->st->t_res);
   HIPCHK(hipGetLastError());
   return FDD_OK;
 }
@@ -968,7 +968,7 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
     launch_iface_batch(s, ng, P->h, tabH, kIfaceOperator, x + P->NI, P->Hp, P->scratchH, P->st,
                        nullptr, nullptr, 0, 0);
     launch_full_operator(s, P->n, P->K, P->gamma, x, P->Hp, nullptr, b, P->partials,
-                         &P->st->counters[9], P->st->t_res);
+                         P->st->t_res);
   }
   HIPCHK(hipGetLastError());
   if ((rc = read_state(P, s))) return finish(rc);

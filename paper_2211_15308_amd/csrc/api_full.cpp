@@ -89,20 +89,26 @@ int solve_full_t(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT,
   // r = b, x = 0, z = B r, p = z
   launch_full_init<VT>(fc, b, v.vr, v.vf);
   enqueue_precond<VT>(c, fc, tP, v);
-  launch_full_rz<VT>(fc, v.Z, 0, 1, rtol2);
+  launch_full_rz<VT>(fc, v.Z, 0, 1, rtol2, 0);
   HIPCHK(hipGetLastError());
-  int rc = read_state(P, s);
-  if (rc) return rc;
-  int its = 0;
-  while (!P->host_st->outer_done && its < o.outer_maxit) {
-    const int a = its & 1;
-    launch_full_step<VT>(fc, tH, v.Z, a, a, its == 0 ? 1 : 0, v.vr, v.vf);
-    enqueue_precond<VT>(c, fc, tP, v);
-    launch_full_rz<VT>(fc, v.Z, a ^ 1, 0, rtol2);
+  // iterations are enqueued ahead of the read-back: as many as this problem's last solve took
+  // (kernels of iterations beyond the stop return at once), then one at a time
+  int its = 0, want = std::max(P->full_its_hint, 1), rc = FDD_OK;
+  for (;;) {
+    for (; its < want && its < o.outer_maxit; ++its) {
+      const int a = its & 1;
+      launch_full_step<VT>(fc, tH, v.Z, a, a, its == 0 ? 1 : 0, v.vr, v.vf, its);
+      enqueue_precond<VT>(c, fc, tP, v);
+      launch_full_rz<VT>(fc, v.Z, a ^ 1, 0, rtol2, its + 1);
+    }
     HIPCHK(hipGetLastError());
-    ++its;
     if ((rc = read_state(P, s))) return rc;
+    if (P->host_st->outer_done || its >= o.outer_maxit) break;
+    want = its + 1;
   }
+  launch_full_clear_stop(fc);
+  if (P->host_st->outer_done) its = P->host_st->o_its;
+  P->full_its_hint = its;
   const DevState& h = *P->host_st;
   st.outer_its = its;
   st.inner_solves = 2 * (its + 1);  // V-cycles
@@ -116,7 +122,7 @@ int solve_full_t(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT,
     launch_iface_batch(s, (int)P->NG, P->h, tH, kIfaceOperator, x + P->NI, P->Hp, P->scratchH,
                        P->st, nullptr, nullptr, 0, 0);
     launch_full_operator(s, P->n, P->K, P->gamma, x, P->Hp, nullptr, b, P->partials,
-                         &P->st->counters[9], P->st->t_res);
+                         P->st->t_res);
   }
   HIPCHK(hipGetLastError());
   if ((rc = read_state(P, s))) return rc;

@@ -125,6 +125,7 @@ struct fdd_problem_s {
   // launch schedules by (mg_nu, step_rtol (0 in FP64), right-hand-side kind)
   std::map<std::tuple<int, double, int>, fdd::Schedule> scheds;
   fdd::Schedule* sc = nullptr;
+  int full_its_hint = 0;        // iterations of the last full-system PCG (enqueued ahead)
   // captured outer iterations, keyed by everything their launches bake in (parity, schedule,
   // precision, smoother, tolerances, table contents, warm-start binding)
   std::map<std::vector<int>, GraphEntry> graphs;

@@ -212,7 +212,7 @@ void launch_interior_axpy(hipStream_t s, int nf, int pitch, const double* a, con
                           const double* coef, double scale, double* out);
 void launch_full_operator(hipStream_t s, int n, double K, double gamma, const double* x,
                           const double* Hx, double* y, const double* b, double* partials,
-                          unsigned* counter, double* res);
+                          double* res);
 
 // ---- batched solve (kernels_batch.hip) ------------------------------------------------------
 // One independent 2D instance of a batch, as seen by the batched kernels (device memory).  All
@@ -319,14 +319,17 @@ void launch_full_init(const FullCtx& c, const double* b, VT* vr, VT* vf);
 // t_G = r_G + W|top row, z_G = S_Gamma^{-1} t_G (table P), vf|top row = r_I + K z_G
 template <typename VT>
 void launch_full_precond_tail(const FullCtx& c, const ShiftTable& tabP, const VT* W, VT* vf);
-// rz = r . z (z_I = Z / K) into st->o_rho[cur], beta, and the stop test (first: rz_0)
+// rz = r . z (z_I = Z / K) into st->o_rho[cur], beta, and the stop test (first: rz_0); a
+// passed test records `it` (the iterations done) and stops every later kernel of the solve
 template <typename VT>
-void launch_full_rz(const FullCtx& c, const VT* Z, int cur, int first, double rtol2);
+void launch_full_rz(const FullCtx& c, const VT* Z, int cur, int first, double rtol2, int it);
 // p = z + beta p' (version a -> a ^ 1), q = A p with H_RA by table H, alpha = rz / p.q,
 // x += alpha p, r -= alpha q, vr = vf = r_I
 template <typename VT>
 void launch_full_step(const FullCtx& c, const ShiftTable& tabH, const VT* Z, int a, int cur,
-                      int first, VT* vr, VT* vf);
+                      int first, VT* vr, VT* vf, int it);
+// clears the stop mark the stop test leaves on the multigrid kernels
+void launch_full_clear_stop(const FullCtx& c);
 // out (caller layout) = (aI * sI, aG)
 template <typename VT>
 void launch_full_scatter(const FullCtx& c, const VT* aI, double sI, const double* aG, double* out);

@@ -25,6 +25,24 @@ __device__ __forceinline__ double bsum(double v) {
   return tot;  // broadcast to every thread
 }
 
+// Sum of count partials p[q * stride] (q = 0 .. count - 1) by every thread of the calling block
+// (blockDim.x a multiple of 64, at most 1024), read at agent scope (written by other blocks of the
+// same kernel), in a fixed order: thread t adds q = t, t + blockDim.x, ..., then a fixed tree over
+// the block.  Every thread receives the total.
+__device__ __forceinline__ double block_sum_partials(const double* p, int count, int stride) {
+  __shared__ double sw[16];
+  double v = 0.0;
+  for (int q = threadIdx.x; q < count; q += blockDim.x)
+    v += __hip_atomic_load(&p[(size_t)q * stride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sw[w];
+  return t;
+}
+
 __device__ __forceinline__ double mass_apply(const double* v, int n, double h, int i) {
   const double l = i > 0 ? v[i - 1] : 0.0;
   const double r = i < n - 1 ? v[i + 1] : 0.0;

@@ -11,8 +11,13 @@
 // takes two V-cycles and one batch of shifted interface solves; one PCG iteration adds one
 // operator application (one batch of shifted solves for H_RA p_G and a stencil pass).
 //
-// Scalars stay on the device: each reduction stores per-block partials and the last block to
-// finish (an atomic ticket) sums them in block order, so every result is deterministic.
+// Iterations can be enqueued ahead of the host's read-back: once the stop test has passed (or
+// a breakdown was flagged) every kernel of a later iteration returns at once, the V-cycles too
+// (the stop test marks the multigrid solve stopped; the solve's end clears the mark).
+//
+// Scalars stay on the device: each reduction stores per-block partials and a one-block kernel
+// sums them in a fixed order (no atomics: a ticket counter that every block of a 2048-block grid
+// increments costs more than the launch), so every result is deterministic.
 #include "iface_device.h"
 
 namespace fdd {
@@ -22,13 +27,9 @@ namespace {
 constexpr int kFullThreads = 256;
 constexpr int kFullMaxBlocks = 2048;
 
-// Sum over the grid of one value per thread: partials per block, the last block sums them in
-// block order and returns true in every one of its threads (with the total in *total).
-__device__ __forceinline__ bool grid_sum_last(double v, double* __restrict__ partials,
-                                              unsigned* counter, double* total) {
+// Block sum of one value per thread, stored by thread 0 as this block's partial.
+__device__ __forceinline__ void block_partial(double v, double* __restrict__ partials) {
   __shared__ double sw[kFullThreads / 64];
-  __shared__ int s_last;
-  __shared__ double s_tot;
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -36,22 +37,7 @@ __device__ __forceinline__ bool grid_sum_last(double v, double* __restrict__ par
     double a = 0.0;
     for (int w = 0; w < kFullThreads / 64; ++w) a += sw[w];
     partials[blockIdx.x] = a;
-    __threadfence();
-    const unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (t == gridDim.x - 1);
   }
-  __syncthreads();
-  if (!s_last) return false;
-  if (threadIdx.x == 0) {
-    __threadfence();
-    double a = 0.0;
-    for (unsigned q = 0; q < gridDim.x; ++q) a += __hip_atomic_load(&partials[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_tot = a;
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  *total = s_tot;
-  return true;
 }
 
 inline int grid_blocks(int64_t tot) {
@@ -98,7 +84,9 @@ __global__ __launch_bounds__(kFullThreads) void kf_init(int nf, int pitch, const
 template <typename VT>
 __global__ __launch_bounds__(kIfaceThreads) void kf_gamma_rhs(int nf, int pitch, const VT* __restrict__ W,
                                                               const double* __restrict__ rG,
-                                                              double* __restrict__ tG) {
+                                                              double* __restrict__ tG,
+                                                              const DevState* st) {
+  if (st->outer_done) return;
   const size_t row = (size_t)(nf - 1) * pitch;
   for (int i = threadIdx.x; i < nf; i += blockDim.x) tG[i] = rG[i] + (double)W[row + i];
 }
@@ -108,7 +96,8 @@ template <typename VT>
 __global__ __launch_bounds__(kIfaceThreads) void kf_lift(int nf, int pitch, double K,
                                                          const double* __restrict__ rI,
                                                          const double* __restrict__ zG,
-                                                         VT* __restrict__ vf) {
+                                                         VT* __restrict__ vf, const DevState* st) {
+  if (st->outer_done) return;
   const size_t row = (size_t)(nf - 1) * pitch;
   for (int i = threadIdx.x; i < nf; i += blockDim.x) vf[row + i] = (VT)(rI[row + i] + K * zG[i]);
 }
@@ -124,6 +113,7 @@ __global__ __launch_bounds__(kFullThreads) void kf_rz(int nf, int pitch, double 
                                                       const double* __restrict__ rG, DevState* st,
                                                       double* __restrict__ partials, int cur,
                                                       int first, double rtol2) {
+  if (st->outer_done) return;
   const int64_t NI = (int64_t)nf * nf;
   double acc = 0.0;
   for (int64_t k = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; k < NI + nf;
@@ -136,8 +126,15 @@ __global__ __launch_bounds__(kFullThreads) void kf_rz(int nf, int pitch, double 
       acc += rG[i] * zG[i];
     }
   }
-  double rz;
-  if (!grid_sum_last(acc, partials, &st->counters[10], &rz)) return;
+  block_partial(acc, partials);
+}
+
+// beta, rz and the stop test from kf_rz's partials (one block).
+__global__ __launch_bounds__(kFullThreads) void kf_rz_finish(DevState* st, const double* __restrict__ partials,
+                                                             int nb, int cur, int first, double rtol2,
+                                                             int it) {
+  if (st->outer_done) return;
+  const double rz = block_sum_partials(partials, nb, 1);
   if (threadIdx.x != 0) return;
   if (first) st->o_rho0 = rz;
   const double rho0 = first ? rz : st->o_rho0;
@@ -146,7 +143,11 @@ __global__ __launch_bounds__(kFullThreads) void kf_rz(int nf, int pitch, double 
   st->o_beta = first ? 0.0 : rz / prev;
   if (!isfinite(rz)) st->breakdown |= 4;
   else if (rz < 0.0) st->breakdown |= 2;
-  if (!(rz > rtol2 * rho0) || st->breakdown) st->outer_done = 1;
+  if (!(rz > rtol2 * rho0) || st->breakdown) {
+    st->outer_done = 1;
+    st->o_its = it;
+    st->inner_done = 1;  // the V-cycles of iterations enqueued beyond this one return at once
+  }
 }
 
 // p_G = z_G + beta p_G' (first: p_G = z_G).  One block.
@@ -154,6 +155,7 @@ __global__ __launch_bounds__(kIfaceThreads) void kf_gamma_p(int ng, const double
                                                             const double* __restrict__ pGo,
                                                             double* __restrict__ pGn,
                                                             const DevState* st, int first) {
+  if (st->outer_done) return;
   const double beta = first ? 0.0 : st->o_beta;
   for (int i = threadIdx.x; i < ng; i += blockDim.x) pGn[i] = first ? zG[i] : zG[i] + beta * pGo[i];
 }
@@ -172,6 +174,7 @@ __global__ __launch_bounds__(kFullThreads) void kf_apply(int nf, int pitch, doub
                                                          double* __restrict__ qG, DevState* st,
                                                          double* __restrict__ partials, int cur,
                                                          int first) {
+  if (st->outer_done) return;
   const double beta = first ? 0.0 : st->o_beta;
   auto pI = [&](int i, int j) -> double {  // p at interior node (i, j), 0-based, 0 outside
     if (i < 0 || i >= nf || j < 0) return 0.0;
@@ -201,8 +204,14 @@ __global__ __launch_bounds__(kFullThreads) void kf_apply(int nf, int pitch, doub
       acc += c * q;
     }
   }
-  double pq;
-  if (!grid_sum_last(acc, partials, &st->counters[11], &pq)) return;
+  block_partial(acc, partials);
+}
+
+// alpha = rz / p.q from kf_apply's partials (one block).
+__global__ __launch_bounds__(kFullThreads) void kf_pq_finish(DevState* st, const double* __restrict__ partials,
+                                                             int nb, int cur, int it) {
+  if (st->outer_done) return;
+  const double pq = block_sum_partials(partials, nb, 1);
   if (threadIdx.x != 0) return;
   const double rz = st->o_rho[cur];
   const bool ok = pq > 0.0 && isfinite(pq);
@@ -211,6 +220,8 @@ __global__ __launch_bounds__(kFullThreads) void kf_apply(int nf, int pitch, doub
   if (!ok) {
     st->breakdown |= isfinite(pq) ? 2 : 4;
     st->outer_done = 1;
+    st->o_its = it;
+    st->inner_done = 1;
   }
 }
 
@@ -226,6 +237,7 @@ __global__ __launch_bounds__(kFullThreads) void kf_update(int nf, int pitch, dou
                                                           const double* __restrict__ qG,
                                                           VT* __restrict__ vr, VT* __restrict__ vf,
                                                           DevState* st) {
+  if (st->outer_done) return;
   const double alpha = st->o_alpha;
   const int64_t NI = (int64_t)nf * nf;
   for (int64_t k = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; k < NI + nf;
@@ -259,6 +271,11 @@ __global__ __launch_bounds__(kFullThreads) void kf_scatter(int nf, int pitch, co
   }
 }
 
+// The solve's end: the multigrid solve is no longer marked stopped.
+__global__ void kf_clear_stop(DevState* st) {
+  if (threadIdx.x == 0) st->inner_done = 0;
+}
+
 // ---- launchers ----------------------------------------------------------------------------
 
 template <typename VT>
@@ -272,35 +289,45 @@ template <typename VT>
 void launch_full_precond_tail(const FullCtx& c, const ShiftTable& tabP, const VT* W, VT* vf) {
   // lower factor and the interface block, then the upper factor's right-hand side
   hipLaunchKernelGGL(kf_gamma_rhs<VT>, dim3(1), dim3(kIfaceThreads), 0, c.stream, c.nf, c.pitch,
-                     W, c.rG, c.tG);
+                     W, c.rG, c.tG, (const DevState*)c.st);
   launch_iface_batch(c.stream, c.nf, c.h, tabP, kIfacePrecond, c.tG, c.zG, c.scratchP, c.st,
                      nullptr, nullptr, 0, 0);
   hipLaunchKernelGGL(kf_lift<VT>, dim3(1), dim3(kIfaceThreads), 0, c.stream, c.nf, c.pitch, c.K,
-                     c.rI, c.zG, vf);
+                     c.rI, c.zG, vf, (const DevState*)c.st);
 }
 
 template <typename VT>
-void launch_full_rz(const FullCtx& c, const VT* Z, int cur, int first, double rtol2) {
+void launch_full_rz(const FullCtx& c, const VT* Z, int cur, int first, double rtol2, int it) {
   const int64_t tot = (int64_t)c.nf * c.nf + c.nf;
-  hipLaunchKernelGGL(kf_rz<VT>, dim3(grid_blocks(tot)), dim3(kFullThreads), 0, c.stream, c.nf,
-                     c.pitch, 1.0 / c.K, Z, c.rI, c.zG, c.rG, c.st, c.partials, cur, first, rtol2);
+  const int nb = grid_blocks(tot);
+  hipLaunchKernelGGL(kf_rz<VT>, dim3(nb), dim3(kFullThreads), 0, c.stream, c.nf, c.pitch,
+                     1.0 / c.K, Z, c.rI, c.zG, c.rG, c.st, c.partials, cur, first, rtol2);
+  hipLaunchKernelGGL(kf_rz_finish, dim3(1), dim3(kFullThreads), 0, c.stream, c.st,
+                     (const double*)c.partials, nb, cur, first, rtol2, it);
 }
 
 template <typename VT>
 void launch_full_step(const FullCtx& c, const ShiftTable& tabH, const VT* Z, int a, int cur,
-                      int first, VT* vr, VT* vf) {
+                      int first, VT* vr, VT* vf, int it) {
   const int64_t tot = (int64_t)c.nf * c.nf + c.nf;
   const int b = a ^ 1;  // p version written now
   hipLaunchKernelGGL(kf_gamma_p, dim3(1), dim3(kIfaceThreads), 0, c.stream, c.nf, c.zG, c.pG[a],
                      c.pG[b], (const DevState*)c.st, first);
   launch_iface_batch(c.stream, c.nf, c.h, tabH, kIfaceOperator, c.pG[b], c.Hp, c.scratchH, c.st,
                      nullptr, nullptr, 0, 0);
-  hipLaunchKernelGGL(kf_apply<VT>, dim3(grid_blocks(tot)), dim3(kFullThreads), 0, c.stream, c.nf,
-                     c.pitch, c.K, c.gamma, 1.0 / c.K, Z, c.pI[a], c.pI[b], c.pG[b], c.Hp, c.qI,
-                     c.qG, c.st, c.partials, cur, first);
+  const int nb = grid_blocks(tot);
+  hipLaunchKernelGGL(kf_apply<VT>, dim3(nb), dim3(kFullThreads), 0, c.stream, c.nf, c.pitch, c.K,
+                     c.gamma, 1.0 / c.K, Z, c.pI[a], c.pI[b], c.pG[b], c.Hp, c.qI, c.qG, c.st,
+                     c.partials, cur, first);
+  hipLaunchKernelGGL(kf_pq_finish, dim3(1), dim3(kFullThreads), 0, c.stream, c.st,
+                     (const double*)c.partials, nb, cur, it);
   hipLaunchKernelGGL(kf_update<VT>, dim3(grid_blocks(tot)), dim3(kFullThreads), 0, c.stream,
                      c.nf, c.pitch, c.xI, c.rI, c.pI[b], c.qI, c.xG, c.rG, c.pG[b], c.qG, vr, vf,
                      c.st);
+}
+
+void launch_full_clear_stop(const FullCtx& c) {
+  hipLaunchKernelGGL(kf_clear_stop, dim3(1), dim3(64), 0, c.stream, c.st);
 }
 
 template <typename VT>
@@ -313,9 +340,9 @@ void launch_full_scatter(const FullCtx& c, const VT* aI, double sI, const double
 #define FDD_FULL_INST(VT)                                                                          \
   template void launch_full_init<VT>(const FullCtx&, const double*, VT*, VT*);                    \
   template void launch_full_precond_tail<VT>(const FullCtx&, const ShiftTable&, const VT*, VT*);  \
-  template void launch_full_rz<VT>(const FullCtx&, const VT*, int, int, double);                  \
+  template void launch_full_rz<VT>(const FullCtx&, const VT*, int, int, double, int);             \
   template void launch_full_step<VT>(const FullCtx&, const ShiftTable&, const VT*, int, int, int, \
-                                     VT*, VT*);                                                   \
+                                     VT*, VT*, int);                                              \
   template void launch_full_scatter<VT>(const FullCtx&, const VT*, double, const double*, double*);
 FDD_FULL_INST(float)
 FDD_FULL_INST(double)

@@ -95,15 +95,14 @@ __global__ __launch_bounds__(256) void k_interior_axpy(int nf, int pitch, const 
 }
 
 // y = A x on all free dofs: K times the P1 stiffness (5-point inside, the natural-boundary row
-// (2, -1/2, -1/2, -1 below) on Gamma) plus gamma Hx on the Gamma row.  Optionally reduces
-// ||b - y||^2 and ||b||^2 into res[0], res[1] (via partials and the last block).
+// (2, -1/2, -1/2, -1 below) on Gamma) plus gamma Hx on the Gamma row.  Optionally the block
+// partials of ||b - y||^2 and ||b||^2 (summed by k_full_operator_sum).
 __global__ __launch_bounds__(256) void k_full_operator(int n, double K, double gamma,
                                                        const double* __restrict__ x,
                                                        const double* __restrict__ Hx,
                                                        double* __restrict__ y,
                                                        const double* __restrict__ b,
-                                                       double* __restrict__ partials,
-                                                       unsigned* counter, double* res) {
+                                                       double* __restrict__ partials) {
   const int m = n - 1;
   const int64_t N = (int64_t)n * m;
   double e2 = 0.0, b2 = 0.0;
@@ -138,7 +137,6 @@ __global__ __launch_bounds__(256) void k_full_operator(int n, double K, double g
     s2[1][threadIdx.x >> 6] = b2;
   }
   __syncthreads();
-  __shared__ int s_last;
   if (threadIdx.x == 0) {
     double a = 0.0, bb = 0.0;
     for (int w = 0; w < 4; ++w) {
@@ -147,20 +145,17 @@ __global__ __launch_bounds__(256) void k_full_operator(int n, double K, double g
     }
     partials[2 * blockIdx.x] = a;
     partials[2 * blockIdx.x + 1] = bb;
-    __threadfence();
-    unsigned t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (t == gridDim.x - 1);
-    if (s_last) {
-      __threadfence();
-      __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      double ta = 0.0, tb = 0.0;
-      for (unsigned q = 0; q < gridDim.x; ++q) {
-        ta += partials[2 * q];
-        tb += partials[2 * q + 1];
-      }
-      res[0] = ta;
-      res[1] = tb;
-    }
+  }
+}
+
+// res = the sums of k_full_operator's partials (one block, fixed order).
+__global__ __launch_bounds__(256) void k_full_operator_sum(const double* __restrict__ partials,
+                                                           int nb, double* res) {
+  const double ta = block_sum_partials(partials, nb, 2);
+  const double tb = block_sum_partials(partials + 1, nb, 2);
+  if (threadIdx.x == 0) {
+    res[0] = ta;
+    res[1] = tb;
   }
 }
 
@@ -233,11 +228,12 @@ void launch_interior_axpy(hipStream_t s, int nf, int pitch, const double* a, con
 
 void launch_full_operator(hipStream_t s, int n, double K, double gamma, const double* x,
                           const double* Hx, double* y, const double* b, double* partials,
-                          unsigned* counter, double* res) {
+                          double* res) {
   const int64_t N = (int64_t)n * (n - 1);
   int blocks = (int)std::min<int64_t>((N + 255) / 256, 2048);
   hipLaunchKernelGGL(k_full_operator, dim3(blocks), dim3(256), 0, s, n, K, gamma, x, Hx, y, b,
-                     partials, counter, res);
+                     partials);
+  if (b) hipLaunchKernelGGL(k_full_operator_sum, dim3(1), dim3(256), 0, s, partials, blocks, res);
 }
 
 }  // namespace fdd
