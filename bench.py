@@ -329,6 +329,7 @@ def run_batched(F, args, label, cases, tol_p, max_p, leg):
         "dofs": int(sum(c["n"] * (c["n"] - 1) for c in cases)), "ms_per_batch": 1e3 * el / args.batch_steps,
         "batches_timed": args.batch_steps, "setup_s": setup_s,
         "schedule": {"mg_nu": opts.mg_nu, "step_rtol": opts.step_rtol,
+                     "mid_tile": tune["mid_tile"] if tune else 0, "tile_edges": B.tile_edges(),
                      "autotune_ms_per_batch": tune["ms_per_batch"] if tune else None},
         "outer_its_min_mean_max": [min(outer), float(np.mean(outer)), max(outer)],
         "poles_P_min_max": [min(i[1].query()["m"] for i in inst), max(i[1].query()["m"] for i in inst)],

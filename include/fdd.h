@@ -245,6 +245,15 @@ int fdd_batch_workspace_bytes(fdd_batch batch, size_t* bytes);
 /* Binds caller-owned device memory (256-byte aligned) to the batch and initializes it on
  * `stream`; synchronizes the stream.  Errors: FDD_E_WORKSPACE.                              */
 int fdd_batch_bind_workspace(fdd_batch batch, void* dev_ptr, size_t bytes, void* stream);
+/* Tile edge of the intermediate multigrid levels (every level below the finest that runs tiled
+ * kernels; the finest level always runs 32 x 32 tiles): 16 or 32 for every such level, or 0 (the
+ * default) to choose per level by tile count (16 x 16 where the batch has fewer than four
+ * 32 x 32 tiles per compute unit on that level).  A change drops the batch's captured graphs and
+ * re-uploads its tile lists at the next solve; results are the same up to rounding order (the
+ * levels' arithmetic does not depend on the tiling).  Host only.  Errors: FDD_E_ARG.       */
+int fdd_batch_set_mid_tile(fdd_batch batch, int edge);
+/* *levels = number of tiled levels; edges (NULL or room for 16 entries) = tile edge per level. */
+int fdd_batch_tile_edges(fdd_batch batch, int* levels, int* edges);
 /* x[i] = A_i^{-1} b[i] for every instance.  b, x: host arrays of `count` device pointers (each
  * of length N of its problem).  stats: NULL or an array of `count` entries (per-instance
  * status, iteration counts and residuals; t_solve_ms is the batch's wall time).  Returns

@@ -1,12 +1,16 @@
-"""Autotuner of the launch schedule (batched and single-problem solves).
+"""Autotuner of the launch schedule and tiling (batched and single-problem solves).
 
-Two launch-schedule parameters trade work against launches and are chosen by timing the
-caller's own workload on the device:
+Launch parameters that trade work against launches are chosen by timing the caller's own
+workload on the device:
 
   * mg_nu      -- red-black sweep pairs per level in the multigrid V-cycle (1 or 2): more
                   smoothing per V-cycle, fewer PCG iterations;
   * step_rtol  -- residual reduction of each FP32 multigrid-PCG run inside the FP64 iterative
-                  refinement (1e-4, 1e-5, 1e-6): fewer, longer runs or more, shorter ones.
+                  refinement (1e-4, 1e-5, 1e-6): fewer, longer runs or more, shorter ones;
+  * mid_tile   -- (batches) tile edge of the intermediate multigrid levels: 16 x 16 tiles spread a
+                  latency-bound level over more workgroups, 32 x 32 tiles re-read less halo; 0
+                  chooses per level by tile count.  Searched after (mg_nu, step_rtol), at the best
+                  of those.
 
 Every candidate is run once untimed (it measures its launch schedule and captures its graphs),
 then timed; the fastest wins.  Choices are cached as JSON keyed by the workload signature (the
@@ -55,8 +59,9 @@ def _store(path, table):
 
 
 def tune_batch(batch, bs, xs, base_opts=None, reps=2, cache_path=None, candidates=CANDIDATES,
-               force=False):
-    """Returns (opts, record) with the fastest (mg_nu, step_rtol) for this batch.
+               force=False, mid_tiles=(16, 32)):
+    """Returns (opts, record) with the fastest (mg_nu, step_rtol) for this batch, and sets the
+    batch's fastest intermediate-level tile edge (recorded as mid_tile and tile_edges).
 
     base_opts supplies every other option (tolerances, graph use).  The record holds the key,
     the per-candidate timings (ms per batch solve) and whether it came from the cache.
@@ -66,25 +71,38 @@ def tune_batch(batch, bs, xs, base_opts=None, reps=2, cache_path=None, candidate
     from . import fdd as F
     opts = base_opts or F.opts_default()
     key = "|".join(["solve_batched", signature(batch.problems), "mixed", arch(),
-                    f"rtol={opts.outer_rtol:g}", f"inner={opts.inner_rtol:g}"])
+                    f"rtol={opts.outer_rtol:g}", f"inner={opts.inner_rtol:g}", "tiles"])
     path = cache_path or default_cache_path()
     table = _load(path)
     if key in table and not force:
         rec = dict(table[key], cached=True)
+        batch.set_mid_tile(rec["mid_tile"])
         return _with(F, opts, rec["mg_nu"], rec["step_rtol"]), rec
-    timings = {}
-    for nu, tau in candidates:
-        o = _with(F, opts, nu, tau)
+
+    def timed(o):
         batch.solve(bs, xs, o)  # measures the schedule, captures the graphs
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
             batch.solve(bs, xs, o)
         torch.cuda.synchronize()
-        timings[f"nu={nu},tau={tau:g}"] = 1e3 * (time.perf_counter() - t0) / reps
-    best = min(candidates, key=lambda c: timings[f"nu={c[0]},tau={c[1]:g}"])
-    rec = {"key": key, "mg_nu": best[0], "step_rtol": best[1], "ms_per_batch": timings,
-           "instances": batch.count}
+        return 1e3 * (time.perf_counter() - t0) / reps
+
+    timings = {}
+    batch.set_mid_tile(0)
+    for nu, tau in candidates:
+        timings[f"nu={nu},tau={tau:g},mid=0"] = timed(_with(F, opts, nu, tau))
+    best = min(candidates, key=lambda c: timings[f"nu={c[0]},tau={c[1]:g},mid=0"])
+    best_mid, best_ms = 0, timings[f"nu={best[0]},tau={best[1]:g},mid=0"]
+    for mid in mid_tiles:
+        batch.set_mid_tile(mid)
+        ms = timed(_with(F, opts, best[0], best[1]))
+        timings[f"nu={best[0]},tau={best[1]:g},mid={mid}"] = ms
+        if ms < best_ms:
+            best_mid, best_ms = mid, ms
+    batch.set_mid_tile(best_mid)
+    rec = {"key": key, "mg_nu": best[0], "step_rtol": best[1], "mid_tile": best_mid,
+           "tile_edges": batch.tile_edges(), "ms_per_batch": timings, "instances": batch.count}
     table[key] = rec
     _store(path, table)
     return _with(F, opts, best[0], best[1]), dict(rec, cached=False)

@@ -36,6 +36,8 @@ struct fdd_batch_s {
   int max_tiled = 1;
   int tiles_total[kMaxLevels] = {};
   int tile_edge[kMaxLevels] = {};  // kTile, or kMidTile on intermediate levels with few tiles
+  int mid_tile = 0;                // intermediate-level tile edge: 0 (by tile count), 16 or 32
+  bool tiles_dirty = false;        // tile lists changed since the workspace was written
   int sysP_total = 0, sysH_total = 0;
   std::vector<int> tiles_prefix[kMaxLevels];
   std::vector<int> sysP_prefix, sysH_prefix;
@@ -85,6 +87,46 @@ size_t plan_batch(fdd_batch_s* B, char* base) {
   B->d_tab = (ShiftTable*)take(sizeof(ShiftTable) * 2 * c);
   B->d_states = (DevState*)take(sizeof(DevState) * c);
   return align_up(off, 256);
+}
+
+// Tile edge of every tiled level and the concatenated tile lists.  Level 0 always runs 32 x 32
+// tiles.  An intermediate level takes B->mid_tile (16 or 32) when set; otherwise (0) 16 x 16 tiles
+// where the batch has fewer than four 32 x 32 tiles per compute unit on that level (latency-bound:
+// smaller tiles spread it further), else 32 x 32 (less halo re-read).
+void plan_tiles(fdd_batch_s* B) {
+  const int count = B->count;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    int t32 = 0;
+    for (int i = 0; i < count; ++i)
+      if (l < B->probs[i]->first_coarse32) {
+        const int tx = (B->probs[i]->lev[l].nf + kTile - 1) / kTile;
+        t32 += tx * tx;
+      }
+    if (l == 0) B->tile_edge[l] = kTile;
+    else if (B->mid_tile) B->tile_edge[l] = B->mid_tile;
+    else B->tile_edge[l] = t32 < 4 * 256 ? kMidTile : kTile;
+    auto& pre = B->tiles_prefix[l];
+    pre.assign(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+      const fdd_problem_s* Q = B->probs[i];
+      int t = 0;
+      if (l < Q->first_coarse32) {
+        const int tt = B->tile_edge[l];
+        const int tx = (Q->lev[l].nf + tt - 1) / tt;
+        t = tx * tx;
+      }
+      pre[i + 1] = pre[i] + t;
+    }
+    B->tiles_total[l] = pre[count];
+  }
+}
+
+// Copies the tile lists to the batch workspace (on stream s).
+int upload_tiles(fdd_batch_s* B, hipStream_t s) {
+  for (int l = 0; l < kMaxLevels; ++l)
+    HIPCHK(hipMemcpyAsync(B->d_tiles[l], B->tiles_prefix[l].data(), sizeof(int) * (B->count + 1),
+                          hipMemcpyHostToDevice, s));
+  return FDD_OK;
 }
 
 // Descriptor of instance i from its problem's bound workspace and the caller's vectors.
@@ -326,30 +368,7 @@ int fdd_batch_create(int count, const fdd_problem* probs, const fdd_ratpc* P, co
   B->tabH.assign(H, H + count);
   B->max_tiled = 1;
   for (int i = 0; i < count; ++i) B->max_tiled = std::max(B->max_tiled, probs[i]->first_coarse32);
-  for (int l = 0; l < kMaxLevels; ++l) {
-    // an intermediate level with fewer than four 32 x 32 tiles per compute unit over the batch is
-    // latency-bound: 16 x 16 tiles spread it further; otherwise the larger tiles re-read less halo
-    int t32 = 0;
-    for (int i = 0; i < count; ++i)
-      if (l < probs[i]->first_coarse32) {
-        const int tx = (probs[i]->lev[l].nf + kTile - 1) / kTile;
-        t32 += tx * tx;
-      }
-    B->tile_edge[l] = (l > 0 && t32 < 4 * 256) ? kMidTile : kTile;
-    auto& pre = B->tiles_prefix[l];
-    pre.assign(count + 1, 0);
-    for (int i = 0; i < count; ++i) {
-      const fdd_problem_s* Q = probs[i];
-      int t = 0;
-      if (l < Q->first_coarse32) {
-        const int tt = B->tile_edge[l];
-        const int tx = (Q->lev[l].nf + tt - 1) / tt;
-        t = tx * tx;
-      }
-      pre[i + 1] = pre[i] + t;
-    }
-    B->tiles_total[l] = pre[count];
-  }
+  plan_tiles(B);
   B->sysP_prefix.assign(count + 1, 0);
   B->sysH_prefix.assign(count + 1, 0);
   for (int i = 0; i < count; ++i) {
@@ -393,9 +412,9 @@ int fdd_batch_bind_workspace(fdd_batch B, void* dev, size_t bytes, void* stream)
     tabs[B->count + i] = make_table(B->tabH[i]);
   }
   HIPCHK(hipMemsetAsync(B->ws, 0, need, s));
-  for (int l = 0; l < kMaxLevels; ++l)
-    HIPCHK(hipMemcpyAsync(B->d_tiles[l], B->tiles_prefix[l].data(), sizeof(int) * (B->count + 1),
-                          hipMemcpyHostToDevice, s));
+  int rc = upload_tiles(B, s);
+  if (rc) return rc;
+  B->tiles_dirty = false;
   HIPCHK(hipMemcpyAsync(B->d_sysP, B->sysP_prefix.data(), sizeof(int) * (B->count + 1),
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(B->d_sysH, B->sysH_prefix.data(), sizeof(int) * (B->count + 1),
@@ -403,6 +422,30 @@ int fdd_batch_bind_workspace(fdd_batch B, void* dev, size_t bytes, void* stream)
   HIPCHK(hipMemcpyAsync(B->d_tab, tabs.data(), sizeof(ShiftTable) * tabs.size(),
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
+  return FDD_OK;
+}
+
+int fdd_batch_set_mid_tile(fdd_batch B, int edge) {
+  if (!B) return fail(FDD_E_ARG, "null batch");
+  if (edge != 0 && edge != kMidTile && edge != kTile)
+    return fail(FDD_E_ARG, "intermediate-level tile edge must be 0, %d or %d (got %d)", kMidTile,
+                kTile, edge);
+  if (edge == B->mid_tile) return FDD_OK;
+  B->mid_tile = edge;
+  plan_tiles(B);
+  // captured graphs bake in the grid sizes
+  for (auto& kv : B->graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  B->graphs.clear();
+  B->tiles_dirty = true;
+  return FDD_OK;
+}
+
+int fdd_batch_tile_edges(fdd_batch B, int* levels, int* edges) {
+  if (!B || !levels) return fail(FDD_E_ARG, "null argument");
+  *levels = B->max_tiled;
+  if (edges)
+    for (int l = 0; l < B->max_tiled; ++l) edges[l] = B->tile_edge[l];
   return FDD_OK;
 }
 
@@ -457,7 +500,12 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
     if (stats) std::memcpy(stats, st.data(), sizeof(fdd_stats) * n);
     return code;
   };
-  // descriptors (uploaded when a vector or a problem's workspace changed)
+  if (B->tiles_dirty) {
+    int rc0 = upload_tiles(B, s);
+    if (rc0) return finish(rc0);
+    B->tiles_dirty = false;
+  }
+  // descriptors (uploaded when a vector, a problem's workspace or the tile plan changed)
   std::vector<BInst> cur(n);
   for (int i = 0; i < n; ++i) cur[i] = make_inst(B, i, b[i], x[i]);
   if (B->uploaded.size() != (size_t)n ||

@@ -40,7 +40,7 @@ EXPORTED = [
     "fdd_apply_operator", "fdd_dd_precond_apply", "fdd_solve_full",
     "fdd_solve", "fdd_set_kernel_timer", "fdd_get_kernel_timer", "fdd_destroy_problem",
     "fdd_destroy_ratpc", "fdd_last_error", "fdd_version", "fdd_batch_create",
-    "fdd_batch_workspace_bytes", "fdd_batch_bind_workspace", "fdd_solve_batched",
+    "fdd_batch_set_mid_tile", "fdd_batch_tile_edges", "fdd_batch_workspace_bytes", "fdd_batch_bind_workspace", "fdd_solve_batched",
     "fdd_batch_destroy", "fdd_batch_set_kernel_timer", "fdd_batch_get_kernel_timer",
     "fdd_cnn_create", "fdd_cnn_param_count", "fdd_cnn_workspace_bytes", "fdd_cnn_bind_workspace",
     "fdd_cnn_set_params", "fdd_cnn_forward", "fdd_cnn_loss", "fdd_cnn_backward",
@@ -123,6 +123,8 @@ def load():
     lib.fdd_batch_create.argtypes = [I, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
                                      ctypes.POINTER(P)]
     lib.fdd_batch_workspace_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.fdd_batch_set_mid_tile.argtypes = [P, I]
+    lib.fdd_batch_tile_edges.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.fdd_batch_bind_workspace.argtypes = [P, V, ctypes.c_size_t, V]
     lib.fdd_solve_batched.argtypes = [P, ctypes.POINTER(V), ctypes.POINTER(V), ctypes.POINTER(FddOpts), V,
                                       ctypes.POINTER(FddStats)]
@@ -384,6 +386,16 @@ class Batch:
                                       _stream(stream), st)
         _check(rc, (FDD_OK, FDD_NOT_CONVERGED) if allow_not_converged else (FDD_OK,))
         return [s.as_dict() for s in st]
+
+    def set_mid_tile(self, edge):
+        """Tile edge of the intermediate levels: 16, 32, or 0 (by tile count)."""
+        _check(load().fdd_batch_set_mid_tile(self.h, edge))
+
+    def tile_edges(self):
+        levels = ctypes.c_int()
+        edges = (ctypes.c_int * 16)()
+        _check(load().fdd_batch_tile_edges(self.h, ctypes.byref(levels), edges))
+        return list(edges)[:levels.value]
 
     def set_kernel_timer(self, kind, split_us=8.0):
         _check(load().fdd_batch_set_kernel_timer(self.h, kind, split_us))

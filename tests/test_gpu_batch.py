@@ -223,11 +223,15 @@ def test_autotuner_times_candidates_then_reuses_its_cache(tmp_path):
     cache = str(tmp_path / "tune.json")
     cands = [(1, 1e-5), (2, 1e-5), (1, 1e-4)]
     opts, rec = autotune.tune_batch(B, bs, xs, reps=1, cache_path=cache, candidates=cands)
-    print(f"[autotune] {rec['ms_per_batch']} -> nu={rec['mg_nu']} tau={rec['step_rtol']}", flush=True)
-    assert not rec["cached"] and len(rec["ms_per_batch"]) == len(cands)
-    assert (opts.mg_nu, opts.step_rtol) in cands
+    print(f"[autotune] {rec['ms_per_batch']} -> nu={rec['mg_nu']} tau={rec['step_rtol']} "
+          f"mid={rec['mid_tile']} edges={rec['tile_edges']}", flush=True)
+    # (mg_nu, step_rtol) first, then the two forced intermediate tile edges at the best of them
+    assert not rec["cached"] and len(rec["ms_per_batch"]) == len(cands) + 2
+    assert (opts.mg_nu, opts.step_rtol) in cands and rec["mid_tile"] in (0, 16, 32)
+    assert B.tile_edges() == rec["tile_edges"] and rec["tile_edges"][0] == 32
     opts2, rec2 = autotune.tune_batch(B, bs, xs, reps=1, cache_path=cache, candidates=cands)
     assert rec2["cached"] and (opts2.mg_nu, opts2.step_rtol) == (opts.mg_nu, opts.step_rtol)
+    assert B.tile_edges() == rec["tile_edges"]
     # every candidate solves to the method's tolerance
     for nu, tau in cands:
         xs = [torch.zeros_like(b) for b in bs]
@@ -236,3 +240,31 @@ def test_autotuner_times_candidates_then_reuses_its_cache(tmp_path):
             x_ref = system.solve_dst_2d(c["n"], c["K"], c["mu"], host(bs[i]))
             assert rel(host(xs[i]), x_ref) <= 1e-6
             assert st[i]["status"] == F.FDD_OK
+
+
+@pytest.mark.parametrize("nu", [1, 2])
+def test_intermediate_tile_edge_changes_nothing_but_rounding(nu):
+    # the same batch on 16 x 16 and 32 x 32 intermediate tiles (and the per-level default):
+    # every instance meets the oracle, and the tilings agree to rounding (per-tile partial sums
+    # are added in another order)
+    cases = workloads.batch_instances(count=3, seed=17, sizes=[256, 512, 1024])
+    B, probs, TP, TH, bs = make_batch(cases, tol_p=1e-12, max_p=64)
+    opts = F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12, mg_nu=nu)
+    out = {}
+    for mid in (16, 32, 0):
+        B.set_mid_tile(mid)
+        edges = B.tile_edges()
+        assert edges[0] == 32 and all(e == (mid or e) for e in edges[1:])
+        xs = [torch.zeros_like(b) for b in bs]
+        B.solve(bs, xs, opts)   # the first solve after a change re-uploads the tile lists
+        B.solve(bs, xs, opts)   # graph replay on the new tiling
+        out[mid] = [host(x) for x in xs]
+        print(f"[tiles] nu={nu} mid={mid} edges={edges}", flush=True)
+    for i, c in enumerate(cases):
+        x_ref = system.solve_dst_2d(c["n"], c["K"], c["mu"], host(bs[i]))
+        for mid in (16, 32, 0):
+            assert rel(out[mid][i], x_ref) <= 1e-8
+        assert rel(out[16][i], out[32][i]) <= 1e-9
+    with pytest.raises(F.FddError) as e:
+        B.set_mid_tile(64)
+    assert e.value.status == F.FDD_E_ARG
