@@ -221,11 +221,25 @@ def traffic_from_profile(root, nu):
     return rec.get("traffic_bytes_per_launch")
 
 
-def kernel_source_sha(root):
-    """sha256 over the sources the multigrid kernels are compiled from."""
+def batched_traffic_from_profile(root, nu):
+    """HBM bytes per working launch of the batched finest down kernel (32 x 1024^2 batch) from the
+    committed PMC record, if it matches the current kernel sources."""
+    path = os.path.join(root, "profiles", "kb_down0_traffic.json")
+    try:
+        rec = json.load(open(path))
+        sha = kernel_source_sha(root, ("kernels_batch.hip", "mg_device.h", "fdd_internal.h"))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sources_sha256") != sha or rec.get("kernel") != f"void fdd::kb_mg_down<{nu}, true, 32>":
+        return None
+    return rec
+
+
+def kernel_source_sha(root, names=("kernels_mg.hip", "mg_device.h", "fdd_internal.h")):
+    """sha256 over the sources a kernel is compiled from."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels_mg.hip", "mg_device.h", "fdd_internal.h"):
+    for name in names:
         h.update(open(os.path.join(root, "paper_2211_15308_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
@@ -338,11 +352,16 @@ def run_batched(F, args, label, cases, tol_p, max_p, leg):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": f"kb_mg_down<{opts.mg_nu},true,32> (finest level of every instance, "
                                "PCG update fused)",
+                     "alg_bytes_per_working_launch": alg / max(nlong, 1),
                      "launches": nl, "avg_launch_us": 1e3 * ms / max(nl, 1),
                      "alg_bytes_per_batch_solve": alg,
                      "working_set_MB": sum(i[0].workspace_bytes() + 16 * i[0].N for i in inst) / 1e6},
         "cpu_baseline": None,
     }
+    tr = batched_traffic_from_profile(ROOT, opts.mg_nu) if label.startswith("32 instances") else None
+    if tr:
+        # measured HBM bytes of a working launch (FETCH_SIZE and WRITE_SIZE, scaled by a copy)
+        res["roofline"]["traffic"] = tr["traffic_bytes_per_launch"]
     leg.defer(res, "cpu_baseline", lambda: cpu_instances(cases, args.cpu_seconds / 4))
     return res
 
@@ -619,6 +638,12 @@ def main():
     if args.only_batched:
         res = {}
         leg = OracleLeg()
+        if args.pmc_mode:
+            # calibration copy of known size (256 MiB), then the 1024^2 batch once, untuned
+            src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+            args.batch_steps, args.no_autotune, args.batched = 1, True, "1024"
         if args.batched in ("all", "1024"):
             res["batched_1024"] = run_batched(F, args, "32 instances, n=1024",
                                               workloads.batch_instances(count=32, seed=4, sizes=[1024]), 1e-12, 64,

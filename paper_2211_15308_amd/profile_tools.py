@@ -10,6 +10,7 @@ under profiles/.  Command line:
   python -m paper_2211_15308_amd.profile_tools csvpmc <counter_collection.csv>
   python -m paper_2211_15308_amd.profile_tools csvtrace <kernel_trace.csv> <name> <split_us>
   python -m paper_2211_15308_amd.profile_tools traffic <fetch.csv> <write.csv> <kernel> <out.json>
+  python -m paper_2211_15308_amd.profile_tools traffic_batched <fetch.csv> <write.csv> <kernel> <out.json>
 
 `traffic` turns a FETCH_SIZE run and a WRITE_SIZE run of ``bench.py --pmc-mode`` (which also
 copies 256 MiB device-to-device once, as the calibration of known size) into HBM bytes per
@@ -147,20 +148,28 @@ def main(argv):
         durs, long = csv_trace_split(argv[1], argv[2], float(argv[3]))
         print(f"{argv[2]}: dispatches {len(durs)} avg_us {sum(durs) / max(len(durs), 1):.2f}; "
               f">= {argv[3]} us: {len(long)} avg_us {sum(long) / max(len(long), 1):.2f}")
-    elif argv[0] == "traffic":
+    elif argv[0] in ("traffic", "traffic_batched"):
         import json
         import os
         sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
         import bench
         rec = traffic_record(argv[1], argv[2], argv[3])
         root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-        rec["kernel_sources_sha256"] = bench.kernel_source_sha(root)
-        rec["workload"] = "2D n=1024 finest level (1023^2 interior points), FP32"
+        if argv[0] == "traffic":
+            rec["kernel_sources_sha256"] = bench.kernel_source_sha(root)
+            rec["workload"] = "2D n=1024 finest level (1023^2 interior points), FP32"
+            mode, out = "--pmc-mode", "profiles/down0_traffic.json"
+        else:
+            rec["kernel_sources_sha256"] = bench.kernel_source_sha(
+                root, ("kernels_batch.hip", "mg_device.h", "fdd_internal.h"))
+            rec["workload"] = ("32 instances at n=1024 (32 x 1023^2 interior points), FP32, every "
+                               "instance's finest level in one launch")
+            mode, out = "--only-batched --pmc-mode", "profiles/kb_down0_traffic.json"
         rec["commands"] = [
-            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d /tmp/pmc_fetch -o pmc -- python3 bench.py --pmc-mode",
-            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d /tmp/pmc_write -o pmc -- python3 bench.py --pmc-mode",
-            "python3 -m paper_2211_15308_amd.profile_tools traffic /tmp/pmc_fetch/pmc_counter_collection.csv "
-            f"/tmp/pmc_write/pmc_counter_collection.csv '{argv[3]}' profiles/down0_traffic.json"]
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d /tmp/pmc_fetch -o pmc -- python3 bench.py {mode}",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d /tmp/pmc_write -o pmc -- python3 bench.py {mode}",
+            f"python3 -m paper_2211_15308_amd.profile_tools {argv[0]} /tmp/pmc_fetch/pmc_counter_collection.csv "
+            f"/tmp/pmc_write/pmc_counter_collection.csv '{argv[3]}' {out}"]
         json.dump(rec, open(argv[4], "w"), indent=1)
         print(json.dumps(rec))
     elif argv[0] == "pmc":
