@@ -20,8 +20,11 @@
  *     free-dof order: 2D index (j-1)(n-1)+(i-1) over j = 1..n, i = 1..n-1; 3D index
  *     ((k-1)(n-1)+(j-1))(n-1)+(i-1) over i, j = 1..n-1, k = 1..n.  The N_G interface dofs are
  *     the last N_G entries.  Interface-only vectors (x_G, y_G, r_G, z_G) have length N_G.
- *   - The caller owns b, x and the workspace.  After fdd_bind_workspace the library allocates
- *     no device memory; all device scratch lives in the bound workspace.
+ *   - The caller owns b, x and the workspace.  All device vectors and scratch of the solver live
+ *     in the bound workspace.  Besides it the library creates, on first use: one non-blocking
+ *     stream and two events per problem or batch (graph replay), instantiated hipGraphs of outer
+ *     iterations, small pinned host blocks for the state read back after synchronizations, HIP
+ *     events for the kernel timer, and (fdd_precond_apply_static) a static 1 MiB device array.
  *   - All device work is enqueued on the caller's HIP stream (hipStream_t passed as void*;
  *     NULL means the default stream).  fdd_schur_apply, fdd_precond_apply, fdd_apply_operator
  *     and fdd_interior_solve synchronize only where documented.  fdd_solve returns after
@@ -123,8 +126,9 @@ void fdd_opts_default(fdd_opts* opts);
  * fdd_setup_mesh: validates the description and builds the host-side plan: level hierarchy of
  * the interior multigrid, the coarsest-grid inverse, the spectral interval of (A_G, M_G).
  * Host only; hip_device is recorded and made current by later device calls.
- * Errors: FDD_E_ARG for dim != 2, n odd, n < 4 or n > 2048 (one interface vector must fit in
- * a workgroup's LDS), n whose multigrid coarsest grid exceeds 16 x 16 interior points, K <= 0,
+ * Errors: FDD_E_ARG for dim other than 2 or 3; in 2D n odd, n < 4 or n > 2048 (one interface
+ * vector must fit in a workgroup's LDS) or n whose multigrid coarsest grid exceeds 16 x 16
+ * interior points; in 3D n odd, n < 4 or n > 256, or a coarsest grid beyond 4^3 points; K <= 0,
  * mu <= 0, or non-finite values.                                                             */
 int fdd_setup_mesh(const fdd_desc* desc, int hip_device, fdd_problem* out);
 
