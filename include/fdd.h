@@ -132,6 +132,25 @@ void fdd_opts_default(fdd_opts* opts);
  * mu <= 0, or non-finite values.                                                             */
 int fdd_setup_mesh(const fdd_desc* desc, int hip_device, fdd_problem* out);
 
+/* The paper's own model problem (Sec. 3, eq. (model_problem)) in 2D:
+ *     K (-Delta + I) x + gamma (-Delta_Gamma + I)^t x = b,   x in V = H^1(Omega), Omega = (0,1)^2,
+ * with Gamma the whole boundary, P1 on the diagonal-split mesh of n cells per side (every node is
+ * a dof).  In the form of eq. (generic): A = K (A_Omega + M_Omega) + gamma T^T L^t T, L = A_G + M_G
+ * the P1 matrix of -Delta_Gamma + I on the closed boundary curve (4n nodes) and L^t as in
+ * eq. (gevp).  Dof order: the (n-1)^2 interior nodes (index (j-1)(n-1) + (i-1), i fastest), then
+ * the N_G = 4n boundary nodes counter-clockwise from the corner (0, 0): (i, 0) -> i, (n, j) ->
+ * n + j, (i, n) -> 2n + (n - i), (0, j) -> 3n + (n - j).  The returned problem takes the same
+ * calls as fdd_setup_mesh's (workspace, tables, interior solve, Schur and operator products,
+ * preconditioner, fdd_solve); rational tables: FDD_RA_PRECOND approximates
+ * (K lam^{1/2} + gamma lam^t)^{-1} (S_Gamma = K L^{1/2} + gamma L^t, Sec. 3) and
+ * FDD_RA_OPERATOR lam^t for t < 0 or lam^(t-1) for t >= 0 (then L^t = L (table)(L)), on the
+ * spectrum [1, 1 + 12 n^2] of (L, M_G).  The interior block A_II = A_Omega + M_Omega is solved
+ * by PCG with the interior multigrid's V-cycles.  Not offered for it: warm starts, batches, the
+ * full-system and static-scratch calls.  Host only.  Errors: FDD_E_ARG for n odd, n < 4,
+ * n > 1024 (one loop vector per workgroup in LDS) or a coarsest grid beyond 16 x 16, K <= 0,
+ * gamma < 0, t outside (-1, 1), or non-finite values.                                        */
+int fdd_setup_model(int n, double K, double gamma, double t, int hip_device, fdd_problem* out);
+
 /* Sizes: N free dofs, N_I interior, N_G interface; [lam_lo, lam_hi] encloses the discrete
  * spectrum of L_h w.r.t. M_h (2D: the exact extreme eigenvalues).  Host only.               */
 int fdd_problem_info(fdd_problem prob, int64_t* N, int64_t* N_I, int64_t* N_G,

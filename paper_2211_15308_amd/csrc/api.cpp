@@ -167,7 +167,7 @@ ShiftTable make_table(const fdd_ratpc_s* t) {
     T.coef[0] = r.c0;
     for (int k = 0; k < r.m; ++k) {
       T.alpha[k + 1] = 1.0;
-      T.beta[k + 1] = r.p[k];
+      T.beta[k + 1] = t->shift0 + r.p[k];  // L + p_k M = A_G + (shift0 + p_k) M_G
       T.coef[k + 1] = r.c[k];
     }
     T.d0 = 0.0;
@@ -176,12 +176,20 @@ ShiftTable make_table(const fdd_ratpc_s* t) {
     T.alpha[0] = 0.0;
     T.beta[0] = 1.0;
     T.coef[0] = 0.0;
+    double csum = 0.0;
     for (int k = 0; k < r.m; ++k) {
       T.alpha[k] = 1.0;
-      T.beta[k] = r.p[k];
+      T.beta[k] = t->shift0 + r.p[k];
       T.coef[k] = r.c[k];
+      csum += r.c[k];
     }
     T.d0 = r.c0;
+    if (t->lam_factor) {
+      // the table approximates lam^(t-1); lam^t = c0 lam + sum_k c_k - sum_k c_k p_k / (lam + p_k)
+      T.dL = r.c0;
+      T.d0 = csum;
+      for (int k = 0; k < r.m; ++k) T.coef[k] = -r.c[k] * r.p[k];
+    }
   }
   return T;
 }
@@ -402,6 +410,8 @@ int check_table(const fdd_problem_s* P, const fdd_ratpc_s* t, int which) {
   if (t->which != which) return fail(FDD_E_STATE, "rational table of the wrong kind");
   if (t->n != P->n || (which == FDD_RA_PRECOND && (t->K != P->K || t->mu != P->mu)))
     return fail(FDD_E_STATE, "rational table built for another problem");
+  if (t->tpow != P->tpow || (t->shift0 != 0.0) != (P->kind == kProblemModel))
+    return fail(FDD_E_STATE, "rational table built for another problem");
   return FDD_OK;
 }
 
@@ -569,8 +579,11 @@ int fdd_build_rational_pc(fdd_problem P, int which, double tol, int max_poles, f
   if (!(tol > 0) || tol >= 1) return fail(FDD_E_ARG, "tol must be in (0, 1)");
   if (max_poles < 1 || max_poles > kMaxPoles)
     return fail(FDD_E_ARG, "max_poles must be in [1, %d]", kMaxPoles);
+  // the model problem with t >= 0: the operator table approximates lam^(t-1) (L^t = L (table)(L))
+  const bool lam_factor = P->kind == kProblemModel && which == FDD_RA_OPERATOR && P->tpow >= 0;
+  const double texp = lam_factor ? P->tpow - 1.0 : P->tpow;
   RaResult r = build_rational(which, P->K, P->gamma, P->lam_lo, P->lam_hi, P->eig.data(),
-                              (int)P->eig.size(), tol, max_poles);
+                              (int)P->eig.size(), tol, max_poles, texp);
   if (r.status != 0)
     return fail(FDD_E_RA, "no admissible rational approximation: best error %.3e > %.3e",
                 r.max_rel_err, 10 * tol);
@@ -581,6 +594,9 @@ int fdd_build_rational_pc(fdd_problem P, int which, double tol, int max_poles, f
   t->n = P->n;
   t->K = P->K;
   t->mu = P->mu;
+  t->tpow = P->tpow;
+  t->shift0 = P->kind == kProblemModel ? 1.0 : 0.0;
+  t->lam_factor = lam_factor ? 1 : 0;
   t->r = r;
   *out = t;
   return FDD_OK;
@@ -604,6 +620,10 @@ int fdd_ratpc_from_table(fdd_problem P, int which, int m, double c0, const doubl
   t->n = P->n;
   t->K = P->K;
   t->mu = P->mu;
+  const bool lam_factor = P->kind == kProblemModel && which == FDD_RA_OPERATOR && P->tpow >= 0;
+  t->tpow = P->tpow;
+  t->shift0 = P->kind == kProblemModel ? 1.0 : 0.0;
+  t->lam_factor = lam_factor ? 1 : 0;
   t->r.status = 0;
   t->r.c0 = c0;
   t->r.m = m;
@@ -611,7 +631,8 @@ int fdd_ratpc_from_table(fdd_problem P, int which, int m, double c0, const doubl
     t->r.c[k] = c[k];
     t->r.p[k] = p[k];
   }
-  t->r.max_rel_err = ra_eval_rel_err(which, P->K, P->gamma, t->r, P->eig.data(), (int)P->eig.size());
+  t->r.max_rel_err = ra_eval_rel_err(which, P->K, P->gamma, t->r, P->eig.data(), (int)P->eig.size(),
+                                     lam_factor ? P->tpow - 1.0 : P->tpow);
   *out = t;
   return FDD_OK;
 }
@@ -641,6 +662,7 @@ int fdd_interior_solve(fdd_problem P, const double* f, double* u, const fdd_opts
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
   if (P->dim == 3) return interior_solve3(P, f, u, o, s, its);
+  if (P->kind == kProblemModel) return model_interior_solve(P, f, u, o, s, its);
   InnerTrack t;
   InnerResult res;
   rc = interior_solve(P, s, RhsDesc{f, 1.0, nullptr, 0.0}, o, t, &res);
@@ -659,6 +681,7 @@ int fdd_precond_apply(fdd_problem P, fdd_ratpc T, const double* r, double* z, vo
   if (!r || !z) return fail(FDD_E_ARG, "null vector");
   HIPCHK(hipSetDevice(P->device));
   if (P->dim == 3) return precond_apply3(P, T, r, z, (hipStream_t)stream);
+  if (P->kind == kProblemModel) return model_precond_apply(P, T, r, z, (hipStream_t)stream);
   ShiftTable tab = make_table(T);
   launch_iface_batch((hipStream_t)stream, (int)P->NG, P->h, tab, kIfacePrecond, r, z, P->scratchP,
                      P->st, nullptr, nullptr, 0, 0);
@@ -671,7 +694,8 @@ int fdd_precond_apply_static(fdd_problem P, fdd_ratpc T, const double* r, double
   int rc = check_table(P, T, FDD_RA_PRECOND);
   if (rc) return rc;
   if (!r || !z) return fail(FDD_E_ARG, "null vector");
-  if (P->dim != 2) return fail(FDD_E_ARG, "the static-scratch preconditioner apply is 2D only");
+  if (P->dim != 2 || P->kind != kProblemFacet)
+    return fail(FDD_E_ARG, "the static-scratch preconditioner apply is for the 2D facet problem only");
   ShiftTable tab = make_table(T);
   if (tab.m > kStaticPrecondSystems || P->NG > kStaticPrecondN)
     return fail(FDD_E_ARG, "%d systems of %lld unknowns exceed the static scratch (%d x %d)", tab.m,
@@ -700,6 +724,7 @@ int fdd_schur_apply(fdd_problem P, fdd_ratpc H, const double* x, double* y, cons
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
   if (P->dim == 3) return schur_apply3(P, H, x, y, o, s);
+  if (P->kind == kProblemModel) return model_schur_apply(P, H, x, y, o, s);
   InnerTrack t;
   InnerResult res;
   rc = interior_solve(P, s, RhsDesc{nullptr, 0.0, x, 1.0}, o, t, &res);
@@ -723,6 +748,7 @@ int fdd_apply_operator(fdd_problem P, fdd_ratpc H, const double* x, double* y, v
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
   if (P->dim == 3) return apply_operator3(P, H, x, y, s);
+  if (P->kind == kProblemModel) return model_apply_operator(P, H, x, y, s);
   ShiftTable tab = make_table(H);
   launch_iface_batch(s, (int)P->NG, P->h, tab, kIfaceOperator, x + P->NI, P->Hp, P->scratchH,
                      P->st, nullptr, nullptr, 0, 0);
@@ -853,6 +879,11 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
     if (o.warmstart) return fail(FDD_E_ARG, "3D solves take no warm start");
     HIPCHK(hipSetDevice(P->device));
     return solve3(P, PT, HT, b, x, o, (hipStream_t)stream, stats);
+  }
+  if (P->kind == kProblemModel) {
+    if (o.warmstart) return fail(FDD_E_ARG, "the model problem takes no warm start");
+    HIPCHK(hipSetDevice(P->device));
+    return model_solve(P, PT, HT, b, x, o, (hipStream_t)stream, stats);
   }
   if (o.warmstart && (rc = cnn_check_for((const fdd_cnn_s*)o.warmstart, P->n))) return rc;
   use_schedule(P, o, kSchedGeneral);

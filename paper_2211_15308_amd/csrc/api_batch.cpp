@@ -353,7 +353,8 @@ int fdd_batch_create(int count, const fdd_problem* probs, const fdd_ratpc* P, co
       return fail(rc, "batch instance %d: %s", i, fdd_last_error());
     if (probs[i]->device != probs[0]->device)
       return fail(FDD_E_ARG, "batch instances on different devices");
-    if (probs[i]->dim != 2) return fail(FDD_E_ARG, "batch instance %d: batched solves are 2D", i);
+    if (probs[i]->dim != 2 || probs[i]->kind != kProblemFacet)
+      return fail(FDD_E_ARG, "batch instance %d: batched solves are for the 2D facet problem", i);
   }
   std::vector<fdd_problem_s*> sorted(probs, probs + count);
   std::sort(sorted.begin(), sorted.end());

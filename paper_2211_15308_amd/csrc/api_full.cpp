@@ -71,7 +71,8 @@ void enqueue_precond(const LaunchCtx& c, const FullCtx& fc, const ShiftTable& ta
 
 int check_full_args(fdd_problem_s* P, fdd_ratpc PT, const double* in, const double* out,
                     const fdd_opts& o) {
-  if (P->dim != 2) return fail(FDD_E_ARG, "the full-system PCG is built for the 2D problem");
+  if (P->dim != 2 || P->kind != kProblemFacet)
+    return fail(FDD_E_ARG, "the full-system PCG is built for the 2D facet problem");
   if (!in || !out) return fail(FDD_E_ARG, "null vector");
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
   if (o.warmstart) return fail(FDD_E_ARG, "the full-system PCG takes no warm start");

@@ -88,6 +88,9 @@ struct Problem3D;  // the 3D solver's state (api_3d.cpp)
 
 struct fdd_problem_s {
   int dim = 2, n = 0, device = 0;
+  int kind = 0;                 // fdd::kProblemFacet, or fdd::kProblemModel (Gamma = the boundary)
+  double tpow = -0.5;           // exponent t of the perturbation (the facet problems: -1/2)
+  int model_its_hint = 0;       // iterations of the model problem's last interior solve
   double K = 1, mu = 1, gamma = 1, h = 1;
   int64_t N = 0, NI = 0, NG = 0;
   double lam_lo = 0, lam_hi = 0;
@@ -143,13 +146,29 @@ struct fdd_ratpc_s {
   const fdd_problem_s* prob = nullptr;
   int n = 0;
   double K = 0, mu = 0;
+  double tpow = -0.5;           // the problem's exponent t
+  double shift0 = 0.0;          // L = A_G + shift0 M_G (the model problem's L = -Delta_Gamma + I)
+  int lam_factor = 0;           // operator table of lam^(t-1): L^t = L (table)(L) (t >= 0)
   RaResult r{};
 };
 
 
 namespace fdd {
 
+enum ProblemKind { kProblemFacet = 0, kProblemModel = 1 };
+
 ShiftTable make_table(const fdd_ratpc_s* t);
+// the paper's model problem in 2D (api_model.cpp)
+int model_interior_solve(fdd_problem_s* P, const double* f, double* u, const fdd_opts& o,
+                         hipStream_t s, int* its);
+int model_precond_apply(fdd_problem_s* P, const fdd_ratpc_s* T, const double* r, double* z,
+                        hipStream_t s);
+int model_apply_operator(fdd_problem_s* P, const fdd_ratpc_s* H, const double* x, double* y,
+                         hipStream_t s);
+int model_schur_apply(fdd_problem_s* P, const fdd_ratpc_s* H, const double* x, double* y,
+                      const fdd_opts& o, hipStream_t s);
+int model_solve(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, const double* b,
+                double* x, const fdd_opts& o, hipStream_t s, fdd_stats* stats);
 bool opts_ok(const fdd_opts* o);
 double step_tau(const fdd_opts& o);
 // the 3D path (api_3d.cpp)

@@ -180,7 +180,8 @@ struct ShiftTable {
   double alpha[kMaxPoles + 1]; // system k: (alpha_k A_G + beta_k M_G) y_k = rhs
   double beta[kMaxPoles + 1];
   double coef[kMaxPoles + 1];  // sum_k coef_k y_k
-  double d0;                   // operator mode: H p = d0 M p + M sum
+  double d0;                   // operator mode: H p = dL L p + d0 M p + M sum
+  double dL;                   // (nonzero only for L^t with t >= 0 of the model problem)
 };
 
 enum IfaceMode { kIfacePrecond = 0, kIfaceOperator = 1, kIfacePrecondOuter = 2 };
@@ -291,11 +292,13 @@ struct RaResult {
   int dropped;                 // poles discarded by the filter
 };
 
-// f(lam) = 1 / (K sqrt(lam) + gamma / sqrt(lam)) (which = 0) or lam^{-1/2} (which = 1).
+// f(lam) = 1 / (K lam^{1/2} + gamma lam^t) (which = 0) or lam^t (which = 1); t = -1/2 for the
+// Riesz map of the facet problems.
 RaResult build_rational(int which, double K, double gamma, double lam_lo, double lam_hi,
-                        const double* check_pts, int ncheck, double tol, int max_poles);
+                        const double* check_pts, int ncheck, double tol, int max_poles,
+                        double t = -0.5);
 double ra_eval_rel_err(int which, double K, double gamma, const RaResult& r, const double* pts,
-                       int npts);
+                       int npts, double t = -0.5);
 
 // dense linear algebra used by the builder (exposed for host tests)
 int eig_real_general(int n, const double* A, double* wr, double* wi);   // A row-major
@@ -333,5 +336,45 @@ void launch_full_clear_stop(const FullCtx& c);
 // out (caller layout) = (aI * sI, aG)
 template <typename VT>
 void launch_full_scatter(const FullCtx& c, const VT* aI, double sI, const double* aG, double* out);
+
+// ---- the paper's model problem in 2D (kernels_model.hip) -------------------------------------
+// Interior nodes on the padded level-0 grid, the 4n boundary nodes as a loop vector.
+// yI = scale (A_Omega + M_Omega)(xI, xG) on the interior rows (+ add_scale addc, addc compact
+// with pitch n - 1, may be null); xI or xG null means zero there.
+void launch_model_interior_rows(hipStream_t s, int n, int pitch, double scale, const double* xI,
+                                const double* xG, double* yI, const double* addc = nullptr,
+                                double add_scale = 0.0);
+// yG = add + scale (A_Omega + M_Omega)(xI, xG) + gamma Hp on the loop rows (add, Hp may be null)
+void launch_model_loop_rows(hipStream_t s, int n, int pitch, double scale, double gamma,
+                            const double* xI, const double* xG, const double* Hp,
+                            const double* add, double* yG);
+// y = K (A_Omega + M_Omega) x + gamma T^T Hx on all dofs (caller layout); with b: res[0] =
+// ||b - y||^2, res[1] = ||b||^2
+void launch_model_full_apply(hipStream_t s, int n, double K, double gamma, const double* x,
+                             const double* Hx, double* y, const double* b, double* partials,
+                             double* res);
+// all shifted loop systems of a table (cyclic, eq. (RA)) and their combination
+void launch_model_loop_batch(hipStream_t s, int n, const ShiftTable& tab, int mode,
+                             const double* in, double* out, double* scratch);
+// interior PCG on A_II = A_Omega + M_Omega (interior block) with V-cycles of the 5-point
+// Laplacian as the preconditioner (scalars and flags in st: rho, cg_alpha[0], cg_gam[1], rr, ff,
+// tol2, inner_done, inner_its)
+template <typename VT>
+void launch_model_ii_start(hipStream_t s, int nf, int pitch, const double* f, double* x,
+                           double* r, VT* vr, DevState* st, double* partials, double tol2);
+template <typename VT>
+void launch_model_ii_rz(hipStream_t s, int nf, int pitch, const double* r, const VT* Z, double zs,
+                        DevState* st, double* partials, int first);
+template <typename VT>
+void launch_model_ii_step(hipStream_t s, int n, int pitch, const VT* Z, double zs, double* p_old,
+                          double* p_new, double* q, double* x, double* r, VT* vr, DevState* st,
+                          double* partials, int first);
+// outer PCG on the loop vectors (one block each): alpha = rho / p.y, x += alpha p, r -= alpha y;
+// and rho' = r.z, beta, p' = z + beta p with the stop test (first: rho_0, p = z)
+void launch_model_outer_update(hipStream_t s, int m, const double* p, const double* y, double* x,
+                               double* r, DevState* st);
+void launch_model_outer_direction(hipStream_t s, int m, const double* r, const double* z,
+                                  const double* p_old, double* p_new, DevState* st, int first,
+                                  double rtol2);
 
 }  // namespace fdd

@@ -245,10 +245,17 @@ int eig_real_general(int n, const double* A, double* wr, double* wi) {
 }
 
 // ---- the approximated functions ---------------------------------------------------------------
-static inline double fval(int which, double K, double gamma, double lam) {
-  if (which == 1) return 1.0 / std::sqrt(lam);
-  const double s = std::sqrt(lam);
-  return 1.0 / (K * s + gamma / s);
+// which = 0: f(lam) = 1 / (K lam^{1/2} + gamma lam^t) (the preconditioner of eq. (schur_precond)
+// with s = 1/2); which = 1: lam^t (the operator's fractional power).  The Riesz map of the facet
+// problems has t = -1/2.
+static inline double fval(int which, double K, double gamma, double t, double lam) {
+  if (t == -0.5) {
+    if (which == 1) return 1.0 / std::sqrt(lam);
+    const double s = std::sqrt(lam);
+    return 1.0 / (K * s + gamma / s);
+  }
+  if (which == 1) return std::pow(lam, t);
+  return 1.0 / (K * std::sqrt(lam) + gamma * std::pow(lam, t));
 }
 
 static inline double ra_value(const RaResult& r, double lam) {
@@ -258,10 +265,10 @@ static inline double ra_value(const RaResult& r, double lam) {
 }
 
 double ra_eval_rel_err(int which, double K, double gamma, const RaResult& r, const double* pts,
-                       int npts) {
+                       int npts, double t) {
   double e = 0.0;
   for (int i = 0; i < npts; ++i) {
-    const double f = fval(which, K, gamma, pts[i]);
+    const double f = fval(which, K, gamma, t, pts[i]);
     e = std::max(e, std::fabs(f - ra_value(r, pts[i])) / std::fabs(f));
   }
   return e;
@@ -496,7 +503,8 @@ static void vf_refine(const std::vector<double>& Z, const std::vector<double>& F
 }
 
 static RaResult build_direct(int which, double K, double gamma, double lam_lo, double lam_hi,
-                             const double* check_pts, int ncheck, double tol, int max_poles) {
+                             const double* check_pts, int ncheck, double tol, int max_poles,
+                             double t) {
   RaResult best;
   std::memset(&best, 0, sizeof(best));
   best.status = -4;  // FDD_E_RA until something acceptable is found
@@ -514,7 +522,7 @@ static RaResult build_direct(int which, double K, double gamma, double lam_lo, d
     std::vector<double> Z(lam.size()), F(lam.size());
     for (size_t i = 0; i < lam.size(); ++i) {
       Z[i] = lam[i] / lam_hi;
-      F[i] = fval(which, K, gamma, lam[i]);
+      F[i] = fval(which, K, gamma, t, lam[i]);
     }
     const double aaa_tol = tol * (attempt == 0 ? 0.5 : 0.1);
     double aaa_err = 0.0;
@@ -543,9 +551,9 @@ static RaResult build_direct(int which, double K, double gamma, double lam_lo, d
     }
     r.aaa_support = (int)B.z.size();
     r.dropped = dropped;
-    double err = ra_eval_rel_err(which, K, gamma, r, lam.data(), (int)lam.size());
+    double err = ra_eval_rel_err(which, K, gamma, r, lam.data(), (int)lam.size(), t);
     if (check_pts && ncheck > 0)
-      err = std::max(err, ra_eval_rel_err(which, K, gamma, r, check_pts, ncheck));
+      err = std::max(err, ra_eval_rel_err(which, K, gamma, r, check_pts, ncheck, t));
     // positivity of the approximate inverse on the spectrum
     bool positive = true;
     for (double x : lam) positive = positive && (ra_value(r, x) > 0.0);
@@ -560,7 +568,7 @@ static RaResult build_direct(int which, double K, double gamma, double lam_lo, d
     if (check_pts && ncheck > 0) {
       extra.clear();
       for (int i = 0; i < ncheck; ++i) {
-        const double f = fval(which, K, gamma, check_pts[i]);
+        const double f = fval(which, K, gamma, t, check_pts[i]);
         if (std::fabs(f - ra_value(r, check_pts[i])) / std::fabs(f) > tol) extra.push_back(check_pts[i]);
         if (extra.size() > 400) break;
       }
@@ -601,9 +609,9 @@ static RaResult derive_precond(const RaResult& g, double K, double gamma) {
 }
 
 RaResult build_rational(int which, double K, double gamma, double lam_lo, double lam_hi,
-                        const double* check_pts, int ncheck, double tol, int max_poles) {
+                        const double* check_pts, int ncheck, double tol, int max_poles, double t) {
   if (which == 1)
-    return build_direct(1, K, gamma, lam_lo, lam_hi, check_pts, ncheck, tol, max_poles);
+    return build_direct(1, K, gamma, lam_lo, lam_hi, check_pts, ncheck, tol, max_poles, t);
   // preconditioner: the product form first, direct AAA as the alternative.  The preconditioner
   // only steers the iteration, so a table within 1e-9 is accepted even when 10 tol is below
   // the rounding floor of the partial-fraction form (large a = gamma / K nearly cancels c0).
@@ -612,9 +620,12 @@ RaResult build_rational(int which, double K, double gamma, double lam_lo, double
   std::memset(&best, 0, sizeof(best));
   best.status = -4;
   best.max_rel_err = INFINITY;
-  const RaResult g = build_direct(1, K, gamma, lam_lo, lam_hi, check_pts, ncheck, tol,
-                                  std::max(1, max_poles - 1));
-  if (g.status == 0) {
+  // (the product form needs t = -1/2 and gamma > 0: f = lam g / (K (lam + gamma / K)))
+  const RaResult g = (t == -0.5 && gamma > 0)
+                         ? build_direct(1, K, gamma, lam_lo, lam_hi, check_pts, ncheck, tol,
+                                        std::max(1, max_poles - 1), t)
+                         : RaResult{};
+  if (t == -0.5 && gamma > 0 && g.status == 0) {
     RaResult r = derive_precond(g, K, gamma);
     if (r.status == 0) {
       std::vector<double> pts;
@@ -622,7 +633,7 @@ RaResult build_rational(int which, double K, double gamma, double lam_lo, double
       for (int i = 0; i < ns; ++i)
         pts.push_back(std::exp(std::log(lam_lo) + (std::log(lam_hi) - std::log(lam_lo)) * i / (ns - 1)));
       for (int i = 0; i < ncheck && check_pts; ++i) pts.push_back(check_pts[i]);
-      r.max_rel_err = ra_eval_rel_err(0, K, gamma, r, pts.data(), (int)pts.size());
+      r.max_rel_err = ra_eval_rel_err(0, K, gamma, r, pts.data(), (int)pts.size(), t);
       bool positive = true;
       for (double x : pts) positive = positive && (ra_value(r, x) > 0.0);
       r.status = (positive && r.max_rel_err <= accept) ? 0 : -4;
@@ -630,7 +641,7 @@ RaResult build_rational(int which, double K, double gamma, double lam_lo, double
       if (r.status == 0 && r.max_rel_err <= tol) return r;
     }
   }
-  RaResult d = build_direct(0, K, gamma, lam_lo, lam_hi, check_pts, ncheck, tol, max_poles);
+  RaResult d = build_direct(0, K, gamma, lam_lo, lam_hi, check_pts, ncheck, tol, max_poles, t);
   if (d.status != 0 && d.max_rel_err <= accept && d.m > 0) d.status = 0;
   if (d.status == 0 && (best.status != 0 || d.max_rel_err < best.max_rel_err)) return d;
   if (best.status != 0 && d.max_rel_err < best.max_rel_err) return d;

@@ -34,7 +34,7 @@ STATUS_NAMES = {
 
 # every symbol declared in include/fdd.h
 EXPORTED = [
-    "fdd_opts_default", "fdd_setup_mesh", "fdd_problem_info", "fdd_workspace_bytes",
+    "fdd_opts_default", "fdd_setup_mesh", "fdd_setup_model", "fdd_problem_info", "fdd_workspace_bytes",
     "fdd_bind_workspace", "fdd_build_rational_pc", "fdd_ratpc_from_table", "fdd_ratpc_query",
     "fdd_interior_solve", "fdd_schur_apply", "fdd_precond_apply", "fdd_precond_apply_static",
     "fdd_apply_operator", "fdd_dd_precond_apply", "fdd_solve_full",
@@ -96,6 +96,7 @@ def load():
     lib.fdd_opts_default.argtypes = [ctypes.POINTER(FddOpts)]
     lib.fdd_opts_default.restype = None
     lib.fdd_setup_mesh.argtypes = [ctypes.POINTER(FddDesc), I, ctypes.POINTER(P)]
+    lib.fdd_setup_model.argtypes = [I, D, D, D, I, ctypes.POINTER(P)]
     lib.fdd_problem_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.fdd_workspace_bytes.argtypes = [P, ctypes.POINTER(FddOpts), ctypes.POINTER(ctypes.c_size_t)]
@@ -231,13 +232,20 @@ class RationalTable:
 class Problem:
     """A set-up problem (fdd_setup_mesh); host only until bind_workspace is called."""
 
-    def __init__(self, n, K, mu, dim=2, device=0):
+    def __init__(self, n, K, mu, dim=2, device=0, model_t=None):
+        """model_t is None: eq. (riesz) with Gamma a facet (fdd_setup_mesh); otherwise the paper's
+        model problem with Gamma the whole boundary, gamma = mu and exponent t = model_t
+        (fdd_setup_model)."""
         lib = load()
-        d = FddDesc(dim, n, K, mu)
         h = ctypes.c_void_p()
-        _check(lib.fdd_setup_mesh(ctypes.byref(d), device, ctypes.byref(h)))
+        if model_t is None:
+            d = FddDesc(dim, n, K, mu)
+            _check(lib.fdd_setup_mesh(ctypes.byref(d), device, ctypes.byref(h)))
+        else:
+            _check(lib.fdd_setup_model(n, K, mu, model_t, device, ctypes.byref(h)))
         self.h = h
         self.n, self.K, self.mu, self.dim = n, K, mu, dim
+        self.model_t = model_t
         self.device = device
         self.workspace = None
         N, NI, NG = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -500,6 +508,11 @@ def unpack_params(theta, widths=(5, 32, 32, 32, 32, 32, 1)):
 # names of the C ABI calls
 def setup_mesh(n, K, mu, dim=2, device=0):
     return Problem(n, K, mu, dim, device)
+
+
+def setup_model(n, K, gamma, t, device=0):
+    """The paper's model problem (Gamma = the whole boundary, exponent t): fdd_setup_model."""
+    return Problem(n, K, gamma, 2, device, model_t=t)
 
 
 def build_rational_pc(prob, which=FDD_RA_PRECOND, tol=1e-12, max_poles=64):

@@ -1,0 +1,195 @@
+"""GPU parity of the paper's own model problem (Sec. 3, eq. (model_problem), 2D: Gamma the whole
+boundary, K(-Delta + I) + gamma(-Delta_Gamma + I)^t) against the oracle (oracle/model.py).
+
+Both sides use the same rational tables, built by the oracle's AAA and handed to the library with
+fdd_ratpc_from_table; the operator's L^t is then the table's realization on both sides
+(model.ra_operator), so products are compared element by element.  Tolerances: products 1e-12
+relative; interior solves <= 100 x inner rtol; solves at outer rtol 1e-10 within 1e-8 of the
+oracle's solution of the same (table) system, outer counts within one of the oracle's Schur PCG.
+"""
+import numpy as np
+import pytest
+
+from oracle import aaa, model, ra
+
+torch = pytest.importorskip("torch")
+F = pytest.importorskip("paper_2211_15308_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def tables(n, K, gamma, t, tol=1e-12):
+    lam = model.loop_eigs(n)
+    lo, hi = lam[0], lam[-1]
+    f = lambda x: 1.0 / (K * np.sqrt(x) + gamma * x ** t)
+    g = (lambda x: x ** t) if t < 0 else (lambda x: x ** (t - 1))
+    return aaa.ra_table(f, lo, hi, tol, extra=lam), aaa.ra_table(g, lo, hi, tol, extra=lam)
+
+
+def setup(n, K, gamma, t):
+    P = F.setup_model(n, K, gamma, t)
+    P.bind_workspace()
+    tp, th = tables(n, K, gamma, t)
+    TP = P.ratpc_from_table(F.FDD_RA_PRECOND, tp[0], list(tp[1]), list(tp[2]))
+    TH = P.ratpc_from_table(F.FDD_RA_OPERATOR, th[0], list(th[1]), list(th[2]))
+    return P, TP, TH, tp, th
+
+
+def ra_system(M, th):
+    """The oracle's matrix with L^t by the operator table: K (A + M) + gamma T^T L^t_RA T."""
+    Lt = model.ra_operator(M.L, M.M_G, M.t, th)
+    A = (M.K * M.omega_block()).toarray()
+    A[M.NI:, M.NI:] += M.gamma * Lt
+    return A, Lt
+
+
+@pytest.mark.parametrize("n,K,gamma,t", [(8, 1.0, 1.0, -0.5), (16, 1e-2, 10.0, 0.5), (64, 1.0, 1e3, -0.9),
+                                         (64, 3.0, 0.0, 0.5)])
+def test_apply_operator_and_precond_match_oracle(n, K, gamma, t):
+    print(f"[model products] n={n} K={K} gamma={gamma} t={t}", flush=True)
+    P, TP, TH, tp, th = setup(n, K, gamma, t)
+    M = model.ModelProblem(n, K, gamma, t)
+    A, Lt = ra_system(M, th)
+    x = np.random.default_rng(n).standard_normal(M.N)
+    y = torch.zeros(M.N, dtype=torch.float64, device="cuda")
+    P.apply_operator(TH, dev(x), y)
+    e1 = rel(host(y), A @ x)
+    r = np.random.default_rng(n + 1).standard_normal(M.NG)
+    z = torch.zeros(M.NG, dtype=torch.float64, device="cuda")
+    P.precond_apply(TP, dev(r), z)
+    D = ra.dense_operator(M.L, M.M_G, *tp)
+    e2 = rel(host(z), D @ r)
+    print(f"[model products] operator {e1:.2e} precond {e2:.2e}", flush=True)
+    assert e1 <= 1e-12 and e2 <= 1e-12
+    # and the table operators stay within their errors of the exact ones (the preconditioner's
+    # table only steers the iteration; its scalar error bounds the matrix error)
+    assert rel(Lt, M.Lt) <= 1e-10
+    lam = model.loop_eigs(n)
+    err_p = ra.max_rel_error(M.f_precond(), *tp, lam)
+    assert rel(D, M.exact_precond()) <= 2 * err_p + 1e-12
+
+
+@pytest.mark.parametrize("n,precision", [(8, F.FDD_FP64), (64, F.FDD_FP64), (64, F.FDD_MIXED),
+                                         (256, F.FDD_MIXED), (512, F.FDD_FP64)])
+def test_interior_solve_matches_oracle(n, precision):
+    print(f"[model interior] n={n} precision={precision}", flush=True)
+    P = F.setup_model(n, 1.0, 1.0, -0.5)
+    P.bind_workspace()
+    nf = n - 1
+    f = np.random.default_rng(7 + n).standard_normal(nf * nf)
+    u = torch.zeros(nf * nf, dtype=torch.float64, device="cuda")
+    its = P.interior_solve(dev(f), u, F.opts_default(precision=precision, inner_rtol=1e-12))
+    import scipy.sparse.linalg as spla
+    M = model.ModelProblem(n, 1.0, 1.0, -0.5) if n <= 256 else None
+    if M is not None:
+        u_ref = spla.spsolve(M.blocks()[0], f)
+    else:
+        # n = 512: the interior block alone, assembled from the 7-point stencil the oracle pins
+        from oracle import multigrid
+        h2 = 1.0 / n ** 2
+        import scipy.sparse as sp
+        e = np.ones(nf)
+        I = sp.identity(nf)
+        A5 = multigrid.stiffness(nf)
+        Mb = (h2 / 2) * sp.identity(nf * nf) + (h2 / 12) * (
+            sp.kron(I, sp.diags([e[:-1], e[:-1]], [-1, 1])) + sp.kron(sp.diags([e[:-1], e[:-1]], [-1, 1]), I)
+            + sp.kron(sp.diags([e[:-1]], [1]), sp.diags([e[:-1]], [1]))
+            + sp.kron(sp.diags([e[:-1]], [-1]), sp.diags([e[:-1]], [-1])))
+        u_ref = spla.spsolve((A5 + Mb).tocsc(), f)
+    err = rel(host(u), u_ref)
+    print(f"[model interior] its {its} rel err {err:.2e}", flush=True)
+    assert err <= 1e-9
+    assert its <= 30
+
+
+@pytest.mark.parametrize("n,K,gamma,t", [(8, 1.0, 1.0, -0.5), (32, 1e-2, 10.0, 0.5)])
+def test_schur_apply_matches_oracle(n, K, gamma, t):
+    P, TP, TH, tp, th = setup(n, K, gamma, t)
+    M = model.ModelProblem(n, K, gamma, t)
+    _, Lt = ra_system(M, th)
+    B_II, B_IG, B_GI, B_GG = M.blocks()
+    S = K * (B_GG - B_GI @ M.interior_lu().solve(B_IG.toarray())) + gamma * Lt
+    p = np.random.default_rng(3).standard_normal(M.NG)
+    y = torch.zeros(M.NG, dtype=torch.float64, device="cuda")
+    P.schur_apply(TH, dev(p), y, F.opts_default(precision=F.FDD_FP64, inner_rtol=1e-13))
+    err = rel(host(y), S @ p)
+    print(f"[model schur] n={n} rel err {err:.2e}", flush=True)
+    assert err <= 1e-9
+
+
+@pytest.mark.parametrize("n,K,gamma,t,precision", [
+    (16, 1.0, 1.0, -0.5, F.FDD_FP64), (16, 1.0, 1.0, 0.5, F.FDD_MIXED), (64, 1e-2, 10.0, -0.5, F.FDD_MIXED),
+    (64, 1.0, 1e3, 0.5, F.FDD_FP64), (128, 1.0, 100.0, -0.9, F.FDD_MIXED), (128, 1e-2, 1.0, 0.9, F.FDD_MIXED)])
+def test_solve_matches_oracle(n, K, gamma, t, precision):
+    print(f"[model solve] n={n} K={K} gamma={gamma} t={t} precision={precision}", flush=True)
+    P, TP, TH, tp, th = setup(n, K, gamma, t)
+    M = model.ModelProblem(n, K, gamma, t)
+    A, Lt = ra_system(M, th)
+    b = np.random.default_rng(100 + n).standard_normal(M.N)
+    x = torch.zeros(M.N, dtype=torch.float64, device="cuda")
+    st = P.solve(TP, TH, dev(b), x, F.opts_default(precision=precision, outer_rtol=1e-10,
+                                                   inner_rtol=1e-12, check_true_residual=1))
+    x_ref = np.linalg.solve(A, b)
+    err = rel(host(x), x_ref)
+    # the oracle's Schur PCG with the same preconditioner table (exact L^t in the operator)
+    D = ra.dense_operator(M.L, M.M_G, *tp)
+    _, its_ref = M.schur_pcg(b, precond=lambda r: D @ r, rtol=1e-10)
+    print(f"[model solve] outer {st['outer_its']} (oracle {its_ref}) inner {st['inner_its_total']} "
+          f"err {err:.2e} res {st['true_rel_res']:.2e}", flush=True)
+    assert err <= 1e-8
+    assert abs(st["outer_its"] - its_ref) <= 1
+    assert st["true_rel_res"] <= 1e-8
+
+
+@pytest.mark.parametrize("n,t", [(512, -0.5), (1024, 0.5)])
+def test_solve_large_residual(n, t):
+    # beyond the oracle's dense sizes: the true residual of the returned x against the table
+    # system, computed on the device, and a second right-hand side on the same problem
+    P = F.setup_model(n, 1.0, 10.0, t)
+    P.bind_workspace()
+    TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+    TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+    for seed in (1, 2):
+        b = np.random.default_rng(seed).standard_normal(P.N)
+        x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+        st = P.solve(TP, TH, dev(b), x, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12,
+                                                       check_true_residual=1))
+        print(f"[model large] n={n} t={t} outer {st['outer_its']} inner {st['inner_its_total']} "
+              f"res {st['true_rel_res']:.2e}", flush=True)
+        assert st["true_rel_res"] <= 1e-8
+        assert st["outer_its"] <= 40
+
+
+def test_model_error_paths():
+    for args in ((1026, 1.0, 1.0, 0.5), (7, 1.0, 1.0, 0.5), (64, 1.0, 1.0, 1.0), (64, -1.0, 1.0, 0.0),
+                 (64, 1.0, -1.0, 0.0)):
+        with pytest.raises(F.FddError) as e:
+            F.setup_model(*args)
+        assert e.value.status == F.FDD_E_ARG
+    P, TP, TH, _, _ = setup(16, 1.0, 1.0, -0.5)
+    Q = F.setup_mesh(16, 1.0, 1.0)
+    Q.bind_workspace()
+    TQ = Q.build_rational_pc(F.FDD_RA_PRECOND, 1e-8)
+    r = torch.zeros(P.NG, dtype=torch.float64, device="cuda")
+    with pytest.raises(F.FddError) as e:
+        P.precond_apply(TQ, r, r)            # a facet problem's table
+    assert e.value.status == F.FDD_E_STATE
+    with pytest.raises(F.FddError) as e:
+        P.precond_apply_static(TP, r, r)
+    assert e.value.status == F.FDD_E_ARG
+    with pytest.raises(F.FddError) as e:
+        F.Batch([P], [TP], [TH])
+    assert e.value.status == F.FDD_E_ARG
