@@ -59,6 +59,8 @@ def parse():
                     help="run the learned-warm-start comparison (auto: if weights exist)")
     ap.add_argument("--learned-steps", type=int, default=6)
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D cases")
+    ap.add_argument("--model", choices=["auto", "none", "only"], default="auto",
+                    help="the paper's own model problem (Gamma = the whole boundary) beside the headline")
     ap.add_argument("--full-lazy", choices=["auto", "none", "only"], default="auto",
                     help="the full-system PCG with the lazy block preconditioner beside the headline")
     ap.add_argument("--cnn-only", action="store_true", help="only time the warm-start network kernels")
@@ -507,6 +509,72 @@ def run_full_lazy(F, args, leg, n=1024, reps=2):
     return res
 
 
+def run_model(F, args, leg, n=1024, reps=2, ts=(-0.5, 0.5), gammas=(1.0, 1e3)):
+    """The paper's own model problem (Gamma = the whole boundary, K(-Delta + I) + gamma
+    (-Delta_Gamma + I)^t), K = 1: solves/s, outer and inner counts and true residuals at n, rtol
+    1e-8 (FP32 V-cycles inside FP64 PCG); parity spot-checks at n = 128 against the oracle's
+    sparse solve, and the oracle's Schur PCG (sparse LU interior solves) timed at n = 128."""
+    import numpy as np
+    import torch
+
+    res = {"n": n, "K": 1.0, "rtol": args.rtol, "cases": []}
+    for t in ts:
+        for g in gammas:
+            P = F.setup_model(n, 1.0, g, t)
+            P.bind_workspace()
+            TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+            TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+            opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, mg_nu=args.nu,
+                                  check_true_residual=1)
+            bs = [torch.as_tensor(np.random.default_rng(7000 + k).standard_normal(P.N), dtype=torch.float64,
+                                  device="cuda") for k in range(reps + 1)]
+            x = torch.zeros_like(bs[0])
+            P.solve(TP, TH, bs[reps], x, opts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = [P.solve(TP, TH, bs[k], x, opts) for k in range(reps)]
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            row = {"t": t, "gamma": g, "solves_per_s": reps / el, "outer_its": sts[-1]["outer_its"],
+                   "inner_its": sts[-1]["inner_its_total"],
+                   "true_rel_res_max": max(s_["true_rel_res"] for s_ in sts)}
+            # parity spot-check at n = 128 (the oracle assembles and factors that size in seconds)
+            Q = F.setup_model(128, 1.0, g, t)
+            Q.bind_workspace()
+            QP = Q.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+            QH = Q.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+            bq = torch.as_tensor(np.random.default_rng(7100).standard_normal(Q.N), dtype=torch.float64, device="cuda")
+            xq = torch.zeros_like(bq)
+            stq = Q.solve(QP, QH, bq, xq, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12))
+            row["n128_outer_its"] = stq["outer_its"]
+            row["n128_rel_err_vs_oracle"] = None
+            bh, xh = bq.cpu().numpy(), xq.cpu().numpy()
+
+            def parity(t=t, g=g, bh=bh, xh=xh):
+                from oracle import model
+                M = model.ModelProblem(128, 1.0, g, t)
+                xr = M.solve_splu(bh)
+                return float(np.linalg.norm(xh - xr) / np.linalg.norm(xr))
+            leg.defer(row, "n128_rel_err_vs_oracle", parity)
+            res["cases"].append(row)
+
+    def cpu_rate():
+        from oracle import model
+        M = model.ModelProblem(128, 1.0, 1.0, -0.5)
+        b = np.random.default_rng(7200).standard_normal(M.N)
+        t0 = time.perf_counter()
+        M.interior_lu()
+        t_fact = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, its = M.schur_pcg(b, rtol=args.rtol)
+        return {"n": 128, "t": -0.5, "gamma": 1.0, "solves_per_s": 1.0 / (time.perf_counter() - t0),
+                "factorization_s": t_fact, "outer_its": its, "kind": "oracle Schur PCG, sparse LU interior, exact S_Gamma",
+                "cores": 1}
+    res["cpu_baseline"] = None
+    leg.defer(res, "cpu_baseline", cpu_rate)
+    return res
+
+
 def run_sweep(F, args, leg, sizes=(128, 256, 512, 1024, 2048)):
     """2D sweep n x K in {1, 1e-2, 1e-4} x mu in {1e-6, 1e-3, 1, 1e3} (seed 1000 + index): outer and
     inner iterations, solves/s (one warm-up and two timed solves) and the error of the solution."""
@@ -622,6 +690,12 @@ def main():
         res = run_sweep(F, args, leg)
         leg.run()
         print(json.dumps({"sweep": res}))
+        return
+    if args.model == "only":
+        leg = OracleLeg()
+        res = run_model(F, args, leg)
+        leg.run()
+        print(json.dumps({"model_problem": res}))
         return
     if args.full_lazy == "only":
         leg = OracleLeg()
@@ -793,6 +867,8 @@ def main():
     out.update(batched)
     if args.full_lazy == "auto":
         out["full_lazy"] = run_full_lazy(F, args, leg)
+    if args.model == "auto":
+        out["model_problem"] = run_model(F, args, leg)
     if args.learned == "auto":
         out["learned"] = run_learned(F, args, leg)
     if not args.no_3d:
