@@ -35,8 +35,10 @@ def parse():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--nu", type=int, default=2,
-                    help="red-black sweep pairs per level (2: the autotuner's choice on MI355X for "
-                         "this workload, see paper_2211_15308_amd.autotune.tune_solves)")
+                    help="red-black sweep pairs per level for the legs beside the headline")
+    ap.add_argument("--headline-nu", type=int, default=0,
+                    help="smoother depth of the headline; 0: chosen with the step tolerance by the "
+                         "autotuner (paper_2211_15308_amd.autotune.tune_solves) during set-up")
     ap.add_argument("--inner-rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -458,6 +460,44 @@ def run_learned(F, args, leg, sizes=(256, 512, 1024), mus=(1e-3, 1.0)):
             leg.defer(row, "cpu_oracle_solves_per_s",
                       lambda n=n, mu=mu, seed=seed: cpu_dst_rate(n, [(1.0, mu, seed)], 1.0)[0])
             res["cases"].append(row)
+    # batched form: 8 instances of one n (K = 1, mu alternating), plain vs one batched forward
+    # pass per outer iteration
+    res["batched"] = []
+    for n in sizes:
+        count = 8
+        net = F.Cnn(count, n)
+        net.set_params(theta)
+        probs, TPs, THs, bs = [], [], [], []
+        for i in range(count):
+            mu = mus[i % len(mus)]
+            P = F.setup_mesh(n, 1.0, mu)
+            P.bind_workspace()
+            probs.append(P)
+            TPs.append(P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12))
+            THs.append(P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12))
+            bs.append(torch.as_tensor(workloads.rhs(2, n, 5500 + 10 * i + n), dtype=torch.float64, device="cuda"))
+        B = F.Batch(probs, TPs, THs)
+        row = {"n": n, "instances": count, "K": 1.0, "mu": list(mus)}
+        for label, ws in (("plain", None), ("learned", net.h.value)):
+            opts = F.opts_default(outer_rtol=args.rtol, inner_rtol=args.inner_rtol, mg_nu=args.nu)
+            opts.warmstart = ws
+            xs = [torch.zeros_like(b) for b in bs]
+            for _ in range(2):
+                st = B.solve(bs, xs, opts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.batch_steps):
+                st = B.solve(bs, xs, opts)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            row[label] = {"instance_solves_per_s": count * args.batch_steps / el,
+                          "inner_its_mean": sum(s_["inner_its_total"] for s_ in st) / count,
+                          "outer_its_mean": sum(s_["outer_its"] for s_ in st) / count,
+                          "warm_accepted": sum(s_["warm_accepted"] for s_ in st),
+                          "warm_starts": sum(s_["warm_starts"] for s_ in st),
+                          "rel_err_vs_oracle_first": None}
+            leg.check(row[label], "rel_err_vs_oracle_first", n, 1.0, mus[0], bs[0], xs[0])
+        res["batched"].append(row)
     return res
 
 
@@ -649,6 +689,11 @@ def run_3d(F, args, leg, sizes=(32, 64, 128), mus=(1e-4, 1.0, 1e2), reps=2):
     return out
 
 
+def progress(msg):
+    """One line per finished step on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -750,11 +795,22 @@ def main():
         bs = [torch.as_tensor(workloads.rhs(2, args.n, timed_seed(ci, k)), dtype=torch.float64, device=dev)
               for k in range(SEEDS_PER_CASE)]
         x = torch.zeros_like(b_cal)
+        probs.append((P, TP, TH, bs, x, K, mu, b_cal))
+    tune = None
+    if args.headline_nu == 0 and not args.pmc_mode:
+        # the smoother depth and per-step reduction: timed on the calibration right-hand sides
+        from paper_2211_15308_amd import autotune
+        opts, tune = autotune.tune_solves([(P, TP, TH, b_cal, x) for P, TP, TH, bs, x, K, mu, b_cal in probs],
+                                          opts, reps=1)
+    elif args.headline_nu:
+        opts.mg_nu = args.headline_nu
+    for P, TP, TH, bs, x, K, mu, b_cal in probs:
         for _ in range(2):
             P.solve(TP, TH, b_cal, x, opts)
-        probs.append((P, TP, TH, bs, x, K, mu))
+    probs = [q[:7] for q in probs]
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
+    progress(f"headline set-up done ({setup_s:.1f} s, mg_nu {opts.mg_nu}, step_rtol {opts.step_rtol:g})")
 
     def step_case(s):
         ci = s % len(probs)
@@ -780,6 +836,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = args.steps / elapsed
+    progress(f"headline timed: {value:.1f} solves/s")
     if args.pmc_mode:
         print(json.dumps({"pmc_mode": True, "steps": args.steps}))
         return
@@ -811,11 +868,11 @@ def main():
     # time is the achieved rate
     alg_bytes = ni * elem / 4 * (DOWN0_BYTES_K * its + DOWN0_BYTES_K0 * runs)
     achieved = alg_bytes / (long_ms * 1e-3) / 1e9 if long_ms > 0 else 0.0
-    traffic = traffic_from_profile(ROOT, args.nu) if prec == F.FDD_MIXED and args.n == 1024 else None
+    traffic = traffic_from_profile(ROOT, opts.mg_nu) if prec == F.FDD_MIXED and args.n == 1024 else None
     ws_mb = (probs[0][0].workspace_bytes() + 2 * 8 * probs[0][0].N) / 1e6
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": f"k_mg_down<float,{args.nu},true,32,true> (finest level, PCG update fused)",
+                "kernel": f"k_mg_down<float,{opts.mg_nu},true,32,true> (finest level, PCG update fused)",
                 "launches": launches, "avg_launch_us": 1e3 * tot_ms / max(launches, 1),
                 "working_launches": its + runs, "timed_long_launches": long_n,
                 "avg_working_launch_us": 1e3 * long_ms / max(long_n, 1),
@@ -833,10 +890,12 @@ def main():
         leg.check(errs, ci, args.n, K, mu, bs[0], x)
     batched = {}
     if args.batched in ("all", "1024"):
+        progress("batched 32 x 1024^2")
         batched["batched_1024"] = run_batched(F, args, "32 instances, n=1024",
                                               workloads.batch_instances(count=32, seed=4, sizes=[1024]), 1e-12, 64,
                                               leg)
     if args.batched in ("all", "c4"):
+        progress("batched 256 instances n <= 512")
         batched["c4"] = run_batched(F, args, "256 instances, n in {64,...,512}",
                                     workloads.batch_instances(count=256, seed=4), 1e-8, 20, leg)
     out = {
@@ -857,6 +916,8 @@ def main():
                                f"outer rtol {args.rtol}, inner rtol {args.inner_rtol}",
                    "n": args.n, "cases": len(case_list), "precision": args.precision},
         "setup_s": setup_s,
+        "schedule": {"mg_nu": opts.mg_nu, "step_rtol": opts.step_rtol,
+                     "autotune_ms_per_solve": tune["ms_per_solve"] if tune else None},
         "timed_solves": [dict(K=s_["K"], mu=s_["mu"], seed=s_["seed"], outer_its=s_["outer"],
                               inner_its=s_["inner"], true_rel_res=s_["res"]) for s_ in stats],
         "true_rel_res_max": max(s_["res"] for s_ in stats),
@@ -866,18 +927,24 @@ def main():
     }
     out.update(batched)
     if args.full_lazy == "auto":
+        progress("full-system lazy PCG")
         out["full_lazy"] = run_full_lazy(F, args, leg)
     if args.model == "auto":
+        progress("model problem")
         out["model_problem"] = run_model(F, args, leg)
     if args.learned == "auto":
+        progress("learned warm start")
         out["learned"] = run_learned(F, args, leg)
     if not args.no_3d:
+        progress("3D")
         out["three_d"] = run_3d(F, args, leg)
+    progress("oracle leg (parity spot-checks, CPU baselines)")
     # the oracle leg, after every GPU measurement: parity spot-checks and the CPU baseline
     leg.run()
     if not args.no_cpu_baseline:
         dst_cases = [(s_["K"], s_["mu"], s_["seed"]) for s_ in stats]
         out["cpu_baseline"] = cpu_baseline(args, dst_cases, (case_list[0][0], case_list[0][1], timed_seed(0, 0)))
+    progress("done")
     print(json.dumps(out))
 
 

@@ -255,6 +255,10 @@ int fdd_solve_full(fdd_problem prob, fdd_ratpc P, fdd_ratpc H, const double* b, 
  * PCG with its own stop rule; an instance that has converged is skipped by the kernels of later
  * iterations.  All instances share one launch schedule, and each outer iteration of the batch
  * is replayed from a captured hipGraph (opts->use_graph).  Only FDD_MIXED precision.
+ * opts->warmstart may name a network (fdd_cnn) whose batch_max covers the whole batch and whose
+ * n_max covers every instance: each outer iteration then runs one forward pass per group of
+ * instances of equal n on their search directions and starts every lifted interior solve from
+ * its instance's guess, scaled by its Galerkin factor (as in fdd_solve).
  *
  * fdd_batch_create: count >= 1 distinct problems, each with its own workspace bound, and their
  * tables (P[i] of kind FDD_RA_PRECOND and H[i] of kind FDD_RA_OPERATOR built for probs[i]).

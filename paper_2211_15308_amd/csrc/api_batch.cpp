@@ -50,6 +50,17 @@ struct fdd_batch_s {
   int* d_sysH = nullptr;
   ShiftTable* d_tab = nullptr;  // P tables, then H tables
   DevState* d_states = nullptr;
+  // learned warm start: the network's input traces (one row of tmax per instance, in the order
+  // of `slot`), log10 K and log10 mu per row; instances grouped by n (one forward pass a group)
+  int tmax = 1;
+  double* d_traces = nullptr;
+  double* d_lk = nullptr;
+  double* d_lmu = nullptr;
+  std::vector<int> slot;              // row of instance i
+  struct Group { int n, off, count; int64_t img; };  // img: offset of its first output image
+  std::vector<Group> groups;
+  const fdd_cnn_s* warm_for = nullptr; // the network the rows/groups were last prepared for
+  const fdd_cnn_s* warm = nullptr;     // the network of the running solve (null: no warm start)
   // pinned host mirrors
   BInst* h_inst = nullptr;      // staging of the descriptors
   DevState* h_states = nullptr;
@@ -86,6 +97,9 @@ size_t plan_batch(fdd_batch_s* B, char* base) {
   B->d_sysH = (int*)take(sizeof(int) * (c + 1));
   B->d_tab = (ShiftTable*)take(sizeof(ShiftTable) * 2 * c);
   B->d_states = (DevState*)take(sizeof(DevState) * c);
+  B->d_traces = (double*)take(sizeof(double) * c * (size_t)B->tmax);
+  B->d_lk = (double*)take(sizeof(double) * c);
+  B->d_lmu = (double*)take(sizeof(double) * c);
   return align_up(off, 256);
 }
 
@@ -175,6 +189,16 @@ BInst make_inst(const fdd_batch_s* B, int i, const double* b, double* x) {
   I.scrH = P->scratchH;
   I.tabP = B->d_tab + i;
   I.tabH = B->d_tab + B->count + i;
+  I.warm = nullptr;
+  I.trace = nullptr;
+  if (B->warm) {
+    const int sl = B->slot[i];
+    for (const auto& g : B->groups)
+      if (sl >= g.off && sl < g.off + g.count)
+        I.warm = cnn_output(const_cast<fdd_cnn_s*>(B->warm), nullptr) + g.img +
+                 (int64_t)(sl - g.off) * (g.n - 1) * (g.n - 1);
+    I.trace = B->d_traces + (size_t)sl * B->tmax;
+  }
   return I;
 }
 
@@ -269,6 +293,10 @@ int finish_inner(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, in
     if (!live[i]) continue;
     const DevState& h = B->h_states[i];
     st[i].inner_solves += 1;
+    if (rhs == kRhsLiftP && B->warm) {
+      st[i].warm_starts += 1;
+      st[i].warm_accepted += h.warm_used;
+    }
     st[i].inner_its_total += h.inner_its;
     st[i].inner_its_max = std::max(st[i].inner_its_max, h.inner_its);
     st[i].refine_steps += h.refine_steps;
@@ -294,8 +322,21 @@ int batch_inner(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, int
   return rc;
 }
 
+// The network's guesses for every instance's p_G of version v (one forward pass per group of
+// instances of equal n, all images in the network's output buffer) and their Galerkin factors.
+void enqueue_warm(const fdd_batch_s* B, const BatchCtx& c, int v) {
+  launch_b_gather_traces(c, v);
+  fdd_cnn_s* C = const_cast<fdd_cnn_s*>(B->warm);
+  float* out = cnn_output(C, nullptr);
+  for (const auto& g : B->groups)
+    (void)cnn_warm_guess_batch(C, c.stream, B->d_traces + (size_t)g.off * B->tmax, B->tmax, g.count,
+                               g.n, B->d_lk + g.off, B->d_lmu + g.off, out + g.img);
+  launch_b_warm_alpha(c, v);
+}
+
 // Everything of outer iteration v up to the synchronization, for the instances still running.
 void enqueue_outer(const fdd_batch_s* B, const BatchCtx& c, BTrack& t, int v, const fdd_opts& o) {
+  if (B->warm) enqueue_warm(B, c, v);
   enqueue_start(c, t, kRhsLiftP, v, o);
   if (!B->sc->calibrated) enqueue_steps(B, c, t, kRhsLiftP, v, 1, 30);  // measures the schedule
   else enqueue_steps(B, c, t, kRhsLiftP, v, B->sc->steps, -1);
@@ -313,6 +354,9 @@ int replay_outer(fdd_batch_s* B, hipStream_t s, const BatchCtx& c, BTrack& t, in
   push_bits(key, o.step_rtol);
   push_bits(key, o.inner_rtol);
   push_bits(key, o.outer_rtol);
+  // the network's buffers and parameters are kernel arguments of a warm-started iteration
+  push_bits(key, (uint64_t)(uintptr_t)B->warm);
+  if (B->warm) push_bits(key, cnn_binding_id(B->warm));
   auto it = B->graphs.find(key);
   if (it == B->graphs.end()) {
     hipGraph_t g = nullptr;
@@ -378,6 +422,8 @@ int fdd_batch_create(int count, const fdd_problem* probs, const fdd_ratpc* P, co
   }
   B->sysP_total = B->sysP_prefix[count];
   B->sysH_total = B->sysH_prefix[count];
+  B->tmax = 1;
+  for (int i = 0; i < count; ++i) B->tmax = std::max(B->tmax, (int)probs[i]->NG);
   *out = B;
   return FDD_OK;
 }
@@ -386,6 +432,7 @@ int fdd_batch_workspace_bytes(fdd_batch B, size_t* bytes) {
   if (!B || !bytes) return fail(FDD_E_ARG, "null argument");
   fdd_batch_s tmp;
   tmp.count = B->count;
+  tmp.tmax = B->tmax;
   *bytes = plan_batch(&tmp, nullptr);
   return FDD_OK;
 }
@@ -395,6 +442,7 @@ int fdd_batch_bind_workspace(fdd_batch B, void* dev, size_t bytes, void* stream)
   if (((uintptr_t)dev) & 255) return fail(FDD_E_WORKSPACE, "workspace must be 256-byte aligned");
   fdd_batch_s tmp;
   tmp.count = B->count;
+  tmp.tmax = B->tmax;
   const size_t need = plan_batch(&tmp, nullptr);
   if (bytes < need) return fail(FDD_E_WORKSPACE, "workspace %zu bytes < %zu needed", bytes, need);
   HIPCHK(hipSetDevice(B->device));
@@ -407,6 +455,7 @@ int fdd_batch_bind_workspace(fdd_batch B, void* dev, size_t bytes, void* stream)
   if (!B->h_states)
     HIPCHK(hipHostMalloc((void**)&B->h_states, sizeof(DevState) * B->count, hipHostMallocDefault));
   B->uploaded.clear();
+  B->warm_for = nullptr;
   std::vector<ShiftTable> tabs(2 * (size_t)B->count);
   for (int i = 0; i < B->count; ++i) {
     tabs[i] = make_table(B->tabP[i]);
@@ -465,7 +514,53 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
   if (!opts_ok(&o)) return fail(FDD_E_ARG, "invalid options");
   if (o.precision != FDD_MIXED)
     return fail(FDD_E_ARG, "batched solves run FP32 multigrid-PCG inside FP64 refinement only");
-  if (o.warmstart) return fail(FDD_E_ARG, "the batched solve takes no warm start");
+  B->warm = nullptr;
+  if (o.warmstart) {
+    // the network must take every instance's n and the whole batch in its output buffer
+    const fdd_cnn_s* C = (const fdd_cnn_s*)o.warmstart;
+    for (int i = 0; i < B->count; ++i) {
+      int rc0 = cnn_check_for(C, B->probs[i]->n);
+      if (rc0) return fail(rc0, "batch instance %d: %s", i, fdd_last_error());
+    }
+    if (cnn_batch_max(C) < B->count)
+      return fail(FDD_E_ARG, "the network takes %d images per pass, the batch has %d instances",
+                  cnn_batch_max(C), B->count);
+    if (B->warm_for != C) {
+      // rows ordered by n: one forward pass per group of equal n
+      std::vector<int> order(B->count);
+      for (int i = 0; i < B->count; ++i) order[i] = i;
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int a, int b2) { return B->probs[a]->n < B->probs[b2]->n; });
+      B->slot.assign(B->count, 0);
+      B->groups.clear();
+      std::vector<double> lk(B->count), lmu(B->count);
+      int64_t img = 0;
+      for (int r = 0; r < B->count; ++r) {
+        const fdd_problem_s* Q = B->probs[order[r]];
+        B->slot[order[r]] = r;
+        lk[r] = std::log10(Q->K);
+        lmu[r] = std::log10(Q->mu);
+        if (B->groups.empty() || B->groups.back().n != Q->n) {
+          if (!B->groups.empty()) {
+            const auto& g = B->groups.back();
+            img += (int64_t)g.count * (g.n - 1) * (g.n - 1);
+          }
+          B->groups.push_back({Q->n, r, 0, img});
+        }
+        B->groups.back().count += 1;
+      }
+      const auto& last = B->groups.back();
+      int64_t cap = 0;
+      (void)cnn_output(const_cast<fdd_cnn_s*>(C), &cap);
+      if (img + (int64_t)last.count * (last.n - 1) * (last.n - 1) > cap)
+        return fail(FDD_E_ARG, "the batch's guesses exceed the network's output buffer");
+      HIPCHK(hipSetDevice(B->device));
+      HIPCHK(hipMemcpy(B->d_lk, lk.data(), sizeof(double) * B->count, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(B->d_lmu, lmu.data(), sizeof(double) * B->count, hipMemcpyHostToDevice));
+      B->warm_for = C;
+    }
+    B->warm = C;
+  }
   B->sc = &B->scheds[std::make_tuple(o.mg_nu, o.step_rtol, 0)];
   HIPCHK(hipSetDevice(B->device));
   hipStream_t us = (hipStream_t)stream;
@@ -527,7 +622,8 @@ int fdd_solve_batched(fdd_batch B, const double* const* b, double* const* x, con
   launch_b_precond_init(c0, o.outer_rtol);
   HIPCHK(hipGetLastError());
   if ((rc = read_states(B, s))) return finish(rc);
-  B->sc = &B->scheds[std::make_tuple(o.mg_nu, o.step_rtol, 1)];
+  // lifted-p solves have their own schedule, warm-started ones another
+  B->sc = &B->scheds[std::make_tuple(o.mg_nu, o.step_rtol, B->warm ? 2 : 1)];
   std::vector<char> live(n);
   int nlive = 0;
   for (int i = 0; i < n; ++i) {

@@ -123,6 +123,23 @@ int cnn_warm_guess(fdd_cnn_s* C, hipStream_t s, const double* trace, int n, cons
   return FDD_OK;
 }
 
+// Guesses for B traces of one size n (rows of `traces`, stride ld, device) into `out` (image b at
+// out + b (n-1)^2); out must lie in the network's output buffer (cnn_output).
+int cnn_warm_guess_batch(fdd_cnn_s* C, hipStream_t s, const double* traces, int ld, int B, int n,
+                         const double* lk, const double* lmu, float* out) {
+  int rc = check_shape(C, B, n);
+  if (rc) return rc;
+  enqueue_forward(C, s, traces, ld, B, n, lk, lmu, out, nullptr);
+  return FDD_OK;
+}
+
+float* cnn_output(fdd_cnn_s* C, int64_t* capacity) {
+  if (capacity) *capacity = (int64_t)(C->n_max - 1) * (C->n_max - 1) * C->batch_max;
+  return C->wout;
+}
+
+int cnn_batch_max(const fdd_cnn_s* C) { return C->batch_max; }
+
 uint64_t cnn_binding_id(const fdd_cnn_s* C) { return (uint64_t)(uintptr_t)C->ws; }
 
 int cnn_check_for(const fdd_cnn_s* C, int n) {

@@ -192,6 +192,11 @@ int cnn_check_for(const fdd_cnn_s* C, int n);
 uint64_t cnn_binding_id(const fdd_cnn_s* C);
 int cnn_warm_guess(fdd_cnn_s* C, hipStream_t s, const double* trace, int n, const double* lk_lmu,
                    const float** guess, const double** scale);
+// batched form: B traces of one size n in one forward pass (the batched solver's warm start)
+int cnn_warm_guess_batch(fdd_cnn_s* C, hipStream_t s, const double* traces, int ld, int B, int n,
+                         const double* lk, const double* lmu, float* out);
+float* cnn_output(fdd_cnn_s* C, int64_t* capacity);
+int cnn_batch_max(const fdd_cnn_s* C);
 int check_problem(fdd_problem_s* P);
 int check_table(const fdd_problem_s* P, const fdd_ratpc_s* t, int which);
 LaunchCtx make_ctx(const fdd_problem_s* P, hipStream_t s, int nu, bool fp64);

@@ -240,6 +240,9 @@ struct BInst {
   double *xG[2], *rG[2], *pG[2], *zG, *yG, *Hp, *scrP, *scrH;
   const ShiftTable* tabP;
   const ShiftTable* tabH;
+  // learned warm start of the lifted-p interior solves (null: zero initial guess)
+  const float* warm;                  // the network's image for this instance (pitch nf[0])
+  double* trace;                      // this instance's row of the network's input traces
 };
 
 // Work lists of a batch (device memory): prefix sums over instances.
@@ -267,6 +270,10 @@ struct BatchCtx {
 };
 
 void launch_b_inner_start(const BatchCtx& c, int rhs, int ver, double tol2, double tau2);
+// learned warm start: every instance's p_G (version ver) into its trace row; the Galerkin factor
+// alpha = f.g / g.A g of every instance's image g for its lifted right-hand side
+void launch_b_gather_traces(const BatchCtx& c, int ver);
+void launch_b_warm_alpha(const BatchCtx& c, int ver);
 void launch_b_inner_step(const BatchCtx& c, int rhs, int ver, int its, int S, int& cur_r,
                          int& cur_p);
 void launch_b_rhs_reduce(const BatchCtx& c, int S);

@@ -159,10 +159,42 @@ __global__ __launch_bounds__(kBlock) void kb_ir_residual(const BInst* __restrict
   const int t = b - first_tile(start, i);
   const int tx = P.tiles_x[0];
   RhsDesc f = b_rhs(P, rhs, ver);
+  // the first residual of a lifted-p solve starts from the learned guess, if any, scaled by its
+  // Galerkin factor (kb_warm_alpha)
+  const bool warm = first && rhs == kRhsLiftP && P.warm;
   d_ir_residual<float>(f, first ? nullptr : P.u64[S & 1], P.x,
                        first ? P.u64[0] : P.u64[(S + 1) & 1], P.r[cur_r], nullptr,
                        P.nf[0], P.pitch[0], first, tol2, tau2, 0, st, P.red, t % tx, t / tx,
-                       t, t == 0);
+                       t, t == 0, warm ? P.warm : nullptr, warm ? &st->warm_alpha : nullptr);
+}
+
+// Every instance's p_G of version ver into its row of the network's input (one block each).
+__global__ __launch_bounds__(256) void kb_gather_traces(const BInst* __restrict__ I, int ver,
+                                                        int skip_done) {
+  const BInst& P = I[blockIdx.x];
+  if (!P.trace || inst_idle(P.st, skip_done)) return;
+  const double* src = P.pG[ver & 1];
+  for (int i = threadIdx.x; i < P.ng; i += blockDim.x) P.trace[i] = src[i];
+}
+
+// Tile partials of f.g and g.A g for every instance's guess g (over the level-0 tile list).
+__global__ __launch_bounds__(kBlock) void kb_warm_dots(const BInst* __restrict__ I, BLists L,
+                                                       int ver, int skip_done) {
+  const int b = xcd_linear();
+  const int* start = L.tiles[0];
+  const int i = find_inst(start, L.ninst, b);
+  const BInst& P = I[i];
+  if (!P.warm || inst_idle(P.st, skip_done)) return;
+  const int t = b - first_tile(start, i);
+  const int tx = P.tiles_x[0];
+  d_warm_dots(b_rhs(P, kRhsLiftP, ver), P.warm, P.nf[0], P.red, t % tx, t / tx, t);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_warm_alpha(const BInst* __restrict__ I,
+                                                        int skip_done) {
+  const BInst& P = I[blockIdx.x];
+  if (!P.warm || inst_idle(P.st, skip_done)) return;
+  d_warm_alpha(P.st, P.red);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_ir_finalize(const BInst* __restrict__ I,
@@ -357,6 +389,18 @@ void launch_b_inner_step(const BatchCtx& c, int rhs, int ver, int its, int S, in
                          int& cur_p) {
   if (c.nu == 2) b_step<2>(c, rhs, ver, its, S, cur_r, cur_p);
   else b_step<1>(c, rhs, ver, its, S, cur_r, cur_p);
+}
+
+void launch_b_gather_traces(const BatchCtx& c, int ver) {
+  hipLaunchKernelGGL(kb_gather_traces, dim3(c.lists.ninst), dim3(256), 0, c.stream, c.inst, ver,
+                     c.skip_done);
+}
+
+void launch_b_warm_alpha(const BatchCtx& c, int ver) {
+  hipLaunchKernelGGL(kb_warm_dots, dim3(c.tiles_total[0]), tb(), 0, c.stream, c.inst, c.lists, ver,
+                     c.skip_done);
+  hipLaunchKernelGGL(kb_warm_alpha, dim3(c.lists.ninst), dim3(kBlock), 0, c.stream, c.inst,
+                     c.skip_done);
 }
 
 void launch_b_rhs_reduce(const BatchCtx& c, int S) {

@@ -84,3 +84,51 @@ def test_warm_start_in_the_solver(mu):
     assert res["learned"][3] <= 1e-6 and res["plain"][3] <= 1e-6
     assert res["learned"][0] <= res["plain"][0] + 1
     assert res["learned"][1] <= res["plain"][1] + 2
+
+
+def test_warm_start_in_the_batched_solver():
+    # one forward pass per group of equal n per outer iteration (n = 256 and 512 here), every
+    # instance's guess scaled by its own Galerkin factor; solutions stay exact to tolerance and
+    # the counts are printed beside the plain batch's
+    cases = [dict(n=n, K=1.0, mu=mu, seed=6000 + i)
+             for i, (n, mu) in enumerate([(256, 1e-3), (512, 1.0), (256, 1.0), (512, 1e-3)])]
+    theta, _ = train_warmstart.load_weights()
+    net = F.Cnn(len(cases), 512)
+    net.set_params(torch.as_tensor(theta, dtype=torch.float32, device="cuda"))
+    probs, TP, TH, bs = [], [], [], []
+    for c in cases:
+        P = F.setup_mesh(c["n"], c["K"], c["mu"])
+        P.bind_workspace()
+        probs.append(P)
+        TP.append(P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12))
+        TH.append(P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12))
+        bs.append(torch.as_tensor(workloads.rhs(2, c["n"], c["seed"]), device="cuda"))
+    B = F.Batch(probs, TP, TH)
+    res = {}
+    for label, ws in (("plain", None), ("learned", net.h.value)):
+        opts = F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12)
+        opts.warmstart = ws
+        xs = [torch.zeros_like(b) for b in bs]
+        B.solve(bs, xs, opts)            # measures the schedule
+        st = B.solve(bs, xs, opts)       # graph replay
+        errs = [float(np.linalg.norm(x.cpu().numpy() - system.solve_dst_2d(c["n"], c["K"], c["mu"],
+                                                                           b.cpu().numpy()))
+                      / np.linalg.norm(system.solve_dst_2d(c["n"], c["K"], c["mu"], b.cpu().numpy())))
+                for x, b, c in zip(xs, bs, cases)]
+        res[label] = (st, errs)
+    for i, c in enumerate(cases):
+        sp, sl = res["plain"][0][i], res["learned"][0][i]
+        print(f"[learned batch] n={c['n']} mu={c['mu']:g}: plain outer/inner {sp['outer_its']}/"
+              f"{sp['inner_its_total']}, learned {sl['outer_its']}/{sl['inner_its_total']} (guess kept "
+              f"in {sl['warm_accepted']} of {sl['warm_starts']})", flush=True)
+        assert res["plain"][1][i] <= 1e-8 and res["learned"][1][i] <= 1e-8
+        assert sl["warm_starts"] == sl["outer_its"] and sp["warm_starts"] == 0
+        assert sl["outer_its"] <= sp["outer_its"] + 1
+    # a network that cannot take the whole batch in one pass is refused
+    small = F.Cnn(2, 512)
+    small.set_params(torch.as_tensor(theta, dtype=torch.float32, device="cuda"))
+    opts = F.opts_default()
+    opts.warmstart = small.h.value
+    with pytest.raises(F.FddError) as e:
+        B.solve(bs, [torch.zeros_like(b) for b in bs], opts)
+    assert e.value.status == F.FDD_E_ARG
