@@ -89,6 +89,7 @@ struct Problem3D {
   FaceBufs fb[2];  // [0] preconditioner batch, [1] operator batch
   double *xG = nullptr, *rG = nullptr, *pG = nullptr, *zG = nullptr, *yG = nullptr, *Hp = nullptr;
   double* gpart = nullptr;
+  double* sc = nullptr;  // the outer PCG's scalars (kSc3*), summed and derived on the device
   // pinned host mirrors
   State3* hst = nullptr;
   int* hstop = nullptr;
@@ -171,6 +172,7 @@ size_t plan3(fdd_problem_s* P, char* base) {
   for (double** v : {&Q->xG, &Q->rG, &Q->pG, &Q->zG, &Q->yG, &Q->Hp})
     *v = (double*)take(8 * ng);
   Q->gpart = (double*)take(8 * 2 * kPart3);
+  Q->sc = (double*)take(8 * kSc3Count);
   return align_up(off, 256);
 }
 
@@ -578,17 +580,18 @@ int face_batch(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* T, const doub
   return rc ? rc : face_finish(P, s, run, in, out);
 }
 
-double face_dot(Problem3D* Q, hipStream_t s, const double* a, const double* b, int* rc) {
+// a.b into the device scalar `slot` (partials summed on the device), also returned to the host
+// (for the stop and breakdown tests)
+double face_dot(Problem3D* Q, hipStream_t s, const double* a, const double* b, int slot, int* rc) {
   const int64_t N = (int64_t)Q->nf * Q->nf;
   kf_launch_vdot(s, a, b, N, Q->gpart);
-  if (hipMemcpyAsync(Q->hpart, Q->gpart, 8 * kPart3, hipMemcpyDeviceToHost, s) != hipSuccess ||
+  k3_launch_sum_partials(s, Q->gpart, kPart3, 1, Q->sc, slot);
+  if (hipMemcpyAsync(Q->hpart, Q->sc, 8 * kSc3Count, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     *rc = fail(FDD_E_HIP, "device read-back failed");
     return 0.0;
   }
-  double t = 0.0;
-  for (int k = 0; k < kPart3; ++k) t += Q->hpart[k];
-  return t;
+  return Q->hpart[slot];
 }
 
 // y = S p (Schur complement with H_RA); u = L7^{-1} lift(p) is left in Q->x
@@ -617,11 +620,11 @@ int schur3(fdd_problem_s* P, hipStream_t s, const fdd_ratpc_s* HT, const double*
   kf_launch_schur(s, p, Q->x, Q->nf, 1.0 / Q->n, P->K, P->gamma, Q->Hp, y, Q->gpart);
   HIPCHK(hipGetLastError());
   if (pq) {
-    HIPCHK(hipMemcpyAsync(Q->hpart, Q->gpart, 8 * kPart3, hipMemcpyDeviceToHost, s));
+    // p.Sp summed on the device into the outer PCG's scalars; the host reads it for the test
+    k3_launch_sum_partials(s, Q->gpart, kPart3, 1, Q->sc, kSc3Pq);
+    HIPCHK(hipMemcpyAsync(Q->hpart, Q->sc, 8 * kSc3Count, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    double t = 0.0;
-    for (int k = 0; k < kPart3; ++k) t += Q->hpart[k];
-    *pq = t;
+    *pq = Q->hpart[kSc3Pq];
   }
   return FDD_OK;
 }
@@ -865,8 +868,9 @@ int solve3(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, const
   if (!o.back_solve) k3_launch_scale_add(s, Q->xI, Q->x, 1.0 / P->K, 0, (int64_t)vol(nf));
   // 2. outer PCG from x_G = 0
   if ((rc = face_batch(P, s, PT, Q->rG, Q->zG))) return finish(rc);
-  const double rho0 = face_dot(Q, s, Q->rG, Q->zG, &rc);
+  const double rho0 = face_dot(Q, s, Q->rG, Q->zG, kSc3Rz, &rc);
   if (rc) return finish(rc);
+  k3_launch_outer_scalars(s, Q->sc, 0);
   if (!(rho0 >= 0.0)) return finish(fail(FDD_E_BREAKDOWN, "preconditioner not positive"));
   HIPCHK(hipMemcpyAsync(Q->pG, Q->zG, 8 * NG, hipMemcpyDeviceToDevice, s));
   double rho = rho0;
@@ -882,19 +886,22 @@ int solve3(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, const
     if (!(pq > 0.0) || !std::isfinite(pq))
       return finish(fail(std::isfinite(pq) ? FDD_E_BREAKDOWN : FDD_E_NONFINITE,
                          "3D outer PCG breakdown (p.Sp = %g)", pq));
-    const double alpha = rho / pq;
-    kf_launch_outer_axpy(s, Q->xG, Q->rG, Q->pG, Q->yG, nullptr, NG, alpha);
+    // alpha = rho / p.Sp on the device, then x += alpha p, r -= alpha S p
+    k3_launch_outer_scalars(s, Q->sc, 1);
+    kf_launch_outer_axpy(s, Q->xG, Q->rG, Q->pG, Q->yG, nullptr, NG, Q->sc + kSc3Alpha);
     // x_I += alpha E p (Q->x holds E p = L7^{-1} lift(p) from the Schur product)
-    if (!o.back_solve) k3_launch_scale_add(s, Q->xI, Q->x, alpha, 1, (int64_t)vol(nf));
+    if (!o.back_solve)
+      k3_launch_scale_add(s, Q->xI, Q->x, 0.0, 1, (int64_t)vol(nf), Q->sc + kSc3Alpha);
     if ((rc = face_batch(P, s, PT, Q->rG, Q->zG))) return finish(rc);
-    const double rho_new = face_dot(Q, s, Q->rG, Q->zG, &rc);
+    const double rho_new = face_dot(Q, s, Q->rG, Q->zG, kSc3Rz, &rc);
     if (rc) return finish(rc);
     ++st.outer_its;
     if (!(rho_new >= 0.0)) return finish(fail(FDD_E_BREAKDOWN, "3D outer r.z < 0"));
     conv = std::sqrt(rho_new) <= o.outer_rtol * std::sqrt(rho0);
-    const double beta = rho_new / rho;
     rho = rho_new;
-    if (!conv) kf_launch_outer_axpy(s, nullptr, nullptr, Q->pG, nullptr, Q->zG, NG, beta);
+    // beta = rho_new / rho and p = z + beta p on the device
+    k3_launch_outer_scalars(s, Q->sc, 2);
+    if (!conv) kf_launch_outer_axpy(s, nullptr, nullptr, Q->pG, nullptr, Q->zG, NG, Q->sc + kSc3Beta);
   }
   st.rel_precond_res = rho0 > 0 ? std::sqrt(std::max(rho, 0.0) / rho0) : 0.0;
   // 3. x_I = A_II^{-1} (b_I / K - A_IG x_G) = L7^{-1} (b_I / (K h) + lift(x_G)): accumulated
@@ -908,18 +915,14 @@ int solve3(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, const
   if (o.check_true_residual) {
     if ((rc = face_batch(P, s, HT, x + P->NI, Q->Hp))) return finish(rc);
     k3_launch_full_operator(s, P->n, P->K, P->gamma, x, Q->Hp, nullptr, b, Q->gpart);
-    HIPCHK(hipMemcpyAsync(Q->hpart, Q->gpart, 8 * 2 * kPart3, hipMemcpyDeviceToHost, s));
+    k3_launch_sum_partials(s, Q->gpart, kPart3, 2, Q->sc, kSc3E2);
+    k3_launch_sum_partials(s, Q->gpart + 1, kPart3, 2, Q->sc, kSc3B2);
+    HIPCHK(hipMemcpyAsync(Q->hpart, Q->sc, 8 * kSc3Count, hipMemcpyDeviceToHost, s));
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
-  if (o.check_true_residual) {
-    double e2 = 0.0, b2 = 0.0;
-    for (int k = 0; k < kPart3; ++k) {
-      e2 += Q->hpart[2 * k];
-      b2 += Q->hpart[2 * k + 1];
-    }
-    if (b2 > 0) st.true_rel_res = std::sqrt(e2 / b2);
-  }
+  if (o.check_true_residual && Q->hpart[kSc3B2] > 0)
+    st.true_rel_res = std::sqrt(Q->hpart[kSc3E2] / Q->hpart[kSc3B2]);
   return finish(conv ? FDD_OK : FDD_NOT_CONVERGED);
 }
 

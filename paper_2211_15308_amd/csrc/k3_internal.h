@@ -110,11 +110,18 @@ void kf_launch_schur(hipStream_t s, const double* p, const double* u, int nf, do
                      double gamma, const double* Hp, double* y, double* part);
 void k3_launch_full_operator(hipStream_t s, int n, double K, double gamma, const double* x,
                              const double* Hx, double* y, const double* b, double* part);
+// outer PCG vector steps with the device scalar *coef: x += a p, r -= a y (x given), or
+// p = z + a p
 void kf_launch_outer_axpy(hipStream_t s, double* x, double* r, double* p, const double* y,
-                          const double* z, int64_t N, double a);
-// out = (accumulate ? out : 0) + c u over n elements
+                          const double* z, int64_t N, const double* coef);
+// out = (accumulate ? out : 0) + c u over n elements (c = *coef when coef is given)
 void k3_launch_scale_add(hipStream_t s, double* out, const double* u, double c, int accumulate,
-                         int64_t n);
+                         int64_t n, const double* coef = nullptr);
+// slots of the outer PCG's device scalars
+enum { kSc3Rho0 = 0, kSc3Rho, kSc3Rz, kSc3Pq, kSc3Alpha, kSc3Beta, kSc3E2, kSc3B2, kSc3Count };
+void k3_launch_sum_partials(hipStream_t s, const double* part, int count, int stride, double* sc,
+                            int slot);
+void k3_launch_outer_scalars(hipStream_t s, double* sc, int mode);
 void kf_launch_rhs_reduce(hipStream_t s, const double* bG, const double* w, int nf, double h,
                           double* g, double* xg);
 void kf_launch_vdot(hipStream_t s, const double* a, const double* b, int64_t N, double* part);

@@ -940,7 +940,8 @@ __global__ __launch_bounds__(kB3) void kf_outer_axpy(double* __restrict__ x, dou
                                                     double* __restrict__ p,
                                                     const double* __restrict__ y,
                                                     const double* __restrict__ z, int64_t N,
-                                                    double a) {
+                                                    const double* __restrict__ coef) {
+  const double a = *coef;  // alpha or beta of the outer PCG (k3_outer_scalars)
   for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3) {
     if (x) {
       x[q] += a * p[q];
@@ -953,7 +954,9 @@ __global__ __launch_bounds__(kB3) void kf_outer_axpy(double* __restrict__ x, dou
 
 __global__ __launch_bounds__(kB3) void k3_scale_add(double* __restrict__ out,
                                                    const double* __restrict__ u, double c,
+                                                   const double* __restrict__ coef,
                                                    int accumulate, int64_t N) {
+  if (coef) c = *coef;
   for (int64_t q = blockIdx.x * (int64_t)kB3 + threadIdx.x; q < N; q += (int64_t)gridDim.x * kB3)
     out[q] = (accumulate ? out[q] : 0.0) + c * u[q];
 }
@@ -973,6 +976,34 @@ __global__ __launch_bounds__(kB3) void kf_rhs_reduce(const double* __restrict__ 
 }
 
 // plain block partials of a . b over compact vectors of length N
+// sc[slot] = sum of count partials part[q * stride] (one block; thread t adds q = t, t + kB3, ...,
+// then a fixed tree), so the outer PCG's dots are summed on the device in a fixed order
+__global__ __launch_bounds__(kB3) void k3_sum_partials(const double* __restrict__ part, int count,
+                                                       int stride, double* __restrict__ sc,
+                                                       int slot) {
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < count; q += kB3) acc += part[(size_t)q * stride];
+  acc = block_sum3(acc);
+  if (threadIdx.x == 0) sc[slot] = acc;
+}
+
+// The outer PCG's step scalars from the summed dots (one thread):
+//   mode 0 (start):  rho0 = rho = rz
+//   mode 1 (after p.Sp): alpha = rho / pq
+//   mode 2 (after the new r.z): beta = rz / rho, rho = rz
+__global__ void k3_outer_scalars(double* __restrict__ sc, int mode) {
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    sc[kSc3Rho0] = sc[kSc3Rz];
+    sc[kSc3Rho] = sc[kSc3Rz];
+  } else if (mode == 1) {
+    sc[kSc3Alpha] = sc[kSc3Rho] / sc[kSc3Pq];
+  } else {
+    sc[kSc3Beta] = sc[kSc3Rz] / sc[kSc3Rho];
+    sc[kSc3Rho] = sc[kSc3Rz];
+  }
+}
+
 __global__ __launch_bounds__(kB3) void kf_vdot(const double* __restrict__ a,
                                               const double* __restrict__ b, int64_t N,
                                               double* __restrict__ part) {
@@ -1264,13 +1295,21 @@ void k3_launch_full_operator(hipStream_t s, int n, double K, double gamma, const
                      part);
 }
 void kf_launch_outer_axpy(hipStream_t s, double* x, double* r, double* p, const double* y,
-                          const double* z, int64_t N, double a) {
-  hipLaunchKernelGGL(kf_outer_axpy, dim3(grid_for(N, 1024)), dim3(kB3), 0, s, x, r, p, y, z, N, a);
+                          const double* z, int64_t N, const double* coef) {
+  hipLaunchKernelGGL(kf_outer_axpy, dim3(grid_for(N, 1024)), dim3(kB3), 0, s, x, r, p, y, z, N,
+                     coef);
 }
 void k3_launch_scale_add(hipStream_t s, double* out, const double* u, double c, int accumulate,
-                         int64_t n) {
-  hipLaunchKernelGGL(k3_scale_add, dim3(grid_for(n, 2048)), dim3(kB3), 0, s, out, u, c,
+                         int64_t n, const double* coef) {
+  hipLaunchKernelGGL(k3_scale_add, dim3(grid_for(n, 2048)), dim3(kB3), 0, s, out, u, c, coef,
                      accumulate, n);
+}
+void k3_launch_sum_partials(hipStream_t s, const double* part, int count, int stride, double* sc,
+                            int slot) {
+  hipLaunchKernelGGL(k3_sum_partials, dim3(1), dim3(kB3), 0, s, part, count, stride, sc, slot);
+}
+void k3_launch_outer_scalars(hipStream_t s, double* sc, int mode) {
+  hipLaunchKernelGGL(k3_outer_scalars, dim3(1), dim3(64), 0, s, sc, mode);
 }
 void kf_launch_rhs_reduce(hipStream_t s, const double* bG, const double* w, int nf, double h,
                           double* g, double* xg) {
