@@ -151,6 +151,35 @@ int fdd_setup_mesh(const fdd_desc* desc, int hip_device, fdd_problem* out);
  * gamma < 0, t outside (-1, 1), or non-finite values.                                        */
 int fdd_setup_model(int n, double K, double gamma, double t, int hip_device, fdd_problem* out);
 
+/* The H(div) problem of Sec. 3's remark on H(div)-elliptic problems (eq. (graddiv)): find u in
+ * V = H(div, Omega), Omega = (0,1)^2, with
+ *     K int (u.v + div u div v) + gamma int_{dOmega} (u.nu)(v.nu) = <b, v>   for all v,
+ * lowest-order Brezzi-Douglas-Marini elements (BDM1) on the diagonal-split mesh of n cells per
+ * side, Gamma the whole boundary, trace space Q_h = discontinuous P1 on the 4n boundary segments.
+ * Dofs: two per edge, the normal component u.n_e at the edge's first and at its second endpoint
+ * (edge e holds dofs 2e, 2e + 1).  Edge order: interior horizontal (i,j)->(i+1,j), j = 1..n-1,
+ * i = 0..n-1, n_e = (0,1), index (j-1)n + i; interior vertical (i,j)->(i,j+1), i = 1..n-1,
+ * j = 0..n-1, n_e = (1,0), index n(n-1) + j(n-1) + i-1; diagonal (i,j)->(i+1,j+1), n_e =
+ * (1,-1)/sqrt 2, index 2n(n-1) + jn + i; then the 4n boundary segments counter-clockwise from
+ * (0,0) (bottom, right, top, left; first endpoint = the one met first), n_e = the outward normal,
+ * index 3n^2 - 2n + k.  So N = 6n^2 + 4n, N_I = 6n^2 - 4n interior dofs and N_G = 8n trace dofs
+ * (the DG P1 values of u.nu, segment by segment along the loop) last.
+ * The preconditioner is S_Gamma = K L^{-1/2} + gamma I_Gamma with I_Gamma the DG P1 mass M_Q and
+ * L the symmetric interior-penalty matrix of -u'' + u on the loop (penalty 4/h), both block
+ * circulant; FDD_RA_PRECOND tables approximate f(lam)/lam = (K lam^{1/2} + gamma lam)^{-1} on the
+ * spectrum of (L, M_Q) (f = (K lam^{-1/2} + gamma)^{-1}; the preconditioner applies
+ * lam (table)(lam)).  The operator has no fractional term: the operator-table argument of
+ * fdd_schur_apply, fdd_apply_operator and fdd_solve must be NULL, and FDD_RA_OPERATOR tables are
+ * refused.  The interior block A^00 = K(I - grad div) on the zero-normal-trace subspace is
+ * solved by PCG with a V-cycle (additive Schwarz over vertex patches, damping 1/2, opts.mg_nu
+ * sweeps; nested BDM1 spaces, so the coarse matrices are the Galerkin ones); inner_rtol and
+ * inner_maxit apply, precision and step_rtol do not (FP64 throughout).  Not offered for it: warm
+ * starts, batches, the full-system and static-scratch calls.  Host only (assembly of every level
+ * on the host; the workspace holds the matrices, uploaded by fdd_bind_workspace).
+ * Errors: FDD_E_ARG for n not a power of two in [4, 1024] (one loop vector per workgroup in LDS),
+ * K <= 0, gamma < 0 or non-finite values.                                                     */
+int fdd_setup_hdiv(int n, double K, double gamma, int hip_device, fdd_problem* out);
+
 /* Sizes: N free dofs, N_I interior, N_G interface; [lam_lo, lam_hi] encloses the discrete
  * spectrum of L_h w.r.t. M_h (2D: the exact extreme eigenvalues).  Host only.               */
 int fdd_problem_info(fdd_problem prob, int64_t* N, int64_t* N_I, int64_t* N_G,

@@ -529,6 +529,10 @@ int fdd_workspace_bytes(fdd_problem P, const fdd_opts* o, size_t* bytes) {
     *bytes = workspace3(P);
     return FDD_OK;
   }
+  if (P->kind == kProblemHdiv) {
+    *bytes = hdiv_workspace_bytes(P);
+    return FDD_OK;
+  }
   fdd_problem_s tmp = *P;
   *bytes = plan_workspace(&tmp, nullptr);
   return FDD_OK;
@@ -538,6 +542,7 @@ int fdd_bind_workspace(fdd_problem P, void* dev, size_t bytes, void* stream) {
   if (!P || !dev) return fail(FDD_E_ARG, "null argument");
   if (((uintptr_t)dev) & 255) return fail(FDD_E_WORKSPACE, "workspace must be 256-byte aligned");
   if (P->dim == 3) return bind3(P, dev, bytes, (hipStream_t)stream);
+  if (P->kind == kProblemHdiv) return hdiv_bind(P, dev, bytes, (hipStream_t)stream);
   fdd_problem_s tmp = *P;
   const size_t need = plan_workspace(&tmp, nullptr);
   if (bytes < need) return fail(FDD_E_WORKSPACE, "workspace %zu bytes < %zu needed", bytes, need);
@@ -579,6 +584,8 @@ int fdd_build_rational_pc(fdd_problem P, int which, double tol, int max_poles, f
   if (!(tol > 0) || tol >= 1) return fail(FDD_E_ARG, "tol must be in (0, 1)");
   if (max_poles < 1 || max_poles > kMaxPoles)
     return fail(FDD_E_ARG, "max_poles must be in [1, %d]", kMaxPoles);
+  if (P->kind == kProblemHdiv && which == FDD_RA_OPERATOR)
+    return fail(FDD_E_ARG, "the H(div) problem's operator has no fractional term (no operator table)");
   // the model problem with t >= 0: the operator table approximates lam^(t-1) (L^t = L (table)(L))
   const bool lam_factor = P->kind == kProblemModel && which == FDD_RA_OPERATOR && P->tpow >= 0;
   const double texp = lam_factor ? P->tpow - 1.0 : P->tpow;
@@ -608,6 +615,8 @@ int fdd_ratpc_from_table(fdd_problem P, int which, int m, double c0, const doubl
   *out = nullptr;
   if (which != FDD_RA_PRECOND && which != FDD_RA_OPERATOR) return fail(FDD_E_ARG, "bad kind");
   if (m < 0 || m > kMaxPoles) return fail(FDD_E_ARG, "m must be in [0, %d]", kMaxPoles);
+  if (P->kind == kProblemHdiv && which == FDD_RA_OPERATOR)
+    return fail(FDD_E_ARG, "the H(div) problem's operator has no fractional term (no operator table)");
   if (!std::isfinite(c0)) return fail(FDD_E_RA, "non-finite c0");
   for (int k = 0; k < m; ++k) {
     if (!std::isfinite(c[k]) || !std::isfinite(p[k])) return fail(FDD_E_RA, "non-finite entry");
@@ -663,6 +672,7 @@ int fdd_interior_solve(fdd_problem P, const double* f, double* u, const fdd_opts
   hipStream_t s = (hipStream_t)stream;
   if (P->dim == 3) return interior_solve3(P, f, u, o, s, its);
   if (P->kind == kProblemModel) return model_interior_solve(P, f, u, o, s, its);
+  if (P->kind == kProblemHdiv) return hdiv_interior_solve(P, f, u, o, s, its);
   InnerTrack t;
   InnerResult res;
   rc = interior_solve(P, s, RhsDesc{f, 1.0, nullptr, 0.0}, o, t, &res);
@@ -682,6 +692,7 @@ int fdd_precond_apply(fdd_problem P, fdd_ratpc T, const double* r, double* z, vo
   HIPCHK(hipSetDevice(P->device));
   if (P->dim == 3) return precond_apply3(P, T, r, z, (hipStream_t)stream);
   if (P->kind == kProblemModel) return model_precond_apply(P, T, r, z, (hipStream_t)stream);
+  if (P->kind == kProblemHdiv) return hdiv_precond_apply(P, T, r, z, (hipStream_t)stream);
   ShiftTable tab = make_table(T);
   launch_iface_batch((hipStream_t)stream, (int)P->NG, P->h, tab, kIfacePrecond, r, z, P->scratchP,
                      P->st, nullptr, nullptr, 0, 0);
@@ -714,7 +725,9 @@ int fdd_schur_apply(fdd_problem P, fdd_ratpc H, const double* x, double* y, cons
                     void* stream) {
   int rc = check_problem(P);
   if (rc) return rc;
-  if ((rc = check_table(P, H, FDD_RA_OPERATOR))) return rc;
+  if (P->kind == kProblemHdiv && H)
+    return fail(FDD_E_ARG, "the H(div) problem takes no operator table (pass NULL)");
+  if (P->kind != kProblemHdiv && (rc = check_table(P, H, FDD_RA_OPERATOR))) return rc;
   if (!x || !y) return fail(FDD_E_ARG, "null vector");
   fdd_opts o;
   if (opts) o = *opts;
@@ -725,6 +738,7 @@ int fdd_schur_apply(fdd_problem P, fdd_ratpc H, const double* x, double* y, cons
   hipStream_t s = (hipStream_t)stream;
   if (P->dim == 3) return schur_apply3(P, H, x, y, o, s);
   if (P->kind == kProblemModel) return model_schur_apply(P, H, x, y, o, s);
+  if (P->kind == kProblemHdiv) return hdiv_schur_apply(P, x, y, o, s);
   InnerTrack t;
   InnerResult res;
   rc = interior_solve(P, s, RhsDesc{nullptr, 0.0, x, 1.0}, o, t, &res);
@@ -743,12 +757,15 @@ int fdd_schur_apply(fdd_problem P, fdd_ratpc H, const double* x, double* y, cons
 int fdd_apply_operator(fdd_problem P, fdd_ratpc H, const double* x, double* y, void* stream) {
   int rc = check_problem(P);
   if (rc) return rc;
-  if ((rc = check_table(P, H, FDD_RA_OPERATOR))) return rc;
+  if (P->kind == kProblemHdiv && H)
+    return fail(FDD_E_ARG, "the H(div) problem takes no operator table (pass NULL)");
+  if (P->kind != kProblemHdiv && (rc = check_table(P, H, FDD_RA_OPERATOR))) return rc;
   if (!x || !y) return fail(FDD_E_ARG, "null vector");
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
   if (P->dim == 3) return apply_operator3(P, H, x, y, s);
   if (P->kind == kProblemModel) return model_apply_operator(P, H, x, y, s);
+  if (P->kind == kProblemHdiv) return hdiv_apply_operator(P, x, y, s);
   ShiftTable tab = make_table(H);
   launch_iface_batch(s, (int)P->NG, P->h, tab, kIfaceOperator, x + P->NI, P->Hp, P->scratchH,
                      P->st, nullptr, nullptr, 0, 0);
@@ -869,7 +886,9 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   int rc = check_problem(P);
   if (rc) return rc;
   if ((rc = check_table(P, PT, FDD_RA_PRECOND))) return rc;
-  if ((rc = check_table(P, HT, FDD_RA_OPERATOR))) return rc;
+  if (P->kind == kProblemHdiv && HT)
+    return fail(FDD_E_ARG, "the H(div) problem takes no operator table (pass NULL)");
+  if (P->kind != kProblemHdiv && (rc = check_table(P, HT, FDD_RA_OPERATOR))) return rc;
   if (!b || !x) return fail(FDD_E_ARG, "null vector");
   fdd_opts o;
   if (opts) o = *opts;
@@ -884,6 +903,11 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
     if (o.warmstart) return fail(FDD_E_ARG, "the model problem takes no warm start");
     HIPCHK(hipSetDevice(P->device));
     return model_solve(P, PT, HT, b, x, o, (hipStream_t)stream, stats);
+  }
+  if (P->kind == kProblemHdiv) {
+    if (o.warmstart) return fail(FDD_E_ARG, "the H(div) problem takes no warm start");
+    HIPCHK(hipSetDevice(P->device));
+    return hdiv_solve(P, PT, b, x, o, (hipStream_t)stream, stats);
   }
   if (o.warmstart && (rc = cnn_check_for((const fdd_cnn_s*)o.warmstart, P->n))) return rc;
   use_schedule(P, o, kSchedGeneral);
@@ -1043,6 +1067,7 @@ int fdd_get_kernel_timer(fdd_problem P, int64_t* launches, double* total_ms, int
 void fdd_destroy_problem(fdd_problem P) {
   if (!P) return;
   destroy3(P);
+  hdiv_destroy(P);
   if (P->hook.ev) {
     for (int i = 0; i < 2 * P->hook.cap; ++i) (void)hipEventDestroy(P->hook.ev[i]);
     delete[] P->hook.ev;

@@ -85,10 +85,13 @@ using fdd::Reductions;
 using fdd::kMaxLevels;
 
 struct Problem3D;  // the 3D solver's state (api_3d.cpp)
+namespace fdd {
+struct ProblemHdiv;  // the H(div) problem's state (hdiv_setup.cpp, api_hdiv.cpp)
+}
 
 struct fdd_problem_s {
   int dim = 2, n = 0, device = 0;
-  int kind = 0;                 // fdd::kProblemFacet, or fdd::kProblemModel (Gamma = the boundary)
+  int kind = 0;                 // fdd::kProblemFacet, kProblemModel (Gamma = the boundary) or kProblemHdiv
   double tpow = -0.5;           // exponent t of the perturbation (the facet problems: -1/2)
   int model_its_hint = 0;       // iterations of the model problem's last interior solve
   double K = 1, mu = 1, gamma = 1, h = 1;
@@ -120,6 +123,7 @@ struct fdd_problem_s {
   double* Hp = nullptr;
   double* lk_lmu = nullptr;     // {log10 K, log10 mu} for the warm-start network
   Problem3D* p3 = nullptr;      // dim = 3: everything of the 3D path
+  fdd::ProblemHdiv* ph = nullptr;  // the H(div) problem: everything of its path
   double* scratchP = nullptr;
   double* scratchH = nullptr;
   DevState* host_st = nullptr;  // pinned copy
@@ -155,10 +159,23 @@ struct fdd_ratpc_s {
 
 namespace fdd {
 
-enum ProblemKind { kProblemFacet = 0, kProblemModel = 1 };
+enum ProblemKind { kProblemFacet = 0, kProblemModel = 1, kProblemHdiv = 2 };
 
 ShiftTable make_table(const fdd_ratpc_s* t);
 // the paper's model problem in 2D (api_model.cpp)
+// the H(div) problem (api_hdiv.cpp)
+size_t hdiv_workspace_bytes(fdd_problem_s* P);
+int hdiv_bind(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s);
+void hdiv_destroy(fdd_problem_s* P);
+int hdiv_interior_solve(fdd_problem_s* P, const double* f, double* u, const fdd_opts& o,
+                        hipStream_t s, int* its);
+int hdiv_precond_apply(fdd_problem_s* P, const fdd_ratpc_s* T, const double* r, double* z,
+                       hipStream_t s);
+int hdiv_schur_apply(fdd_problem_s* P, const double* x, double* y, const fdd_opts& o,
+                     hipStream_t s);
+int hdiv_apply_operator(fdd_problem_s* P, const double* x, double* y, hipStream_t s);
+int hdiv_solve(fdd_problem_s* P, const fdd_ratpc_s* PT, const double* b, double* x,
+               const fdd_opts& o, hipStream_t s, fdd_stats* stats);
 int model_interior_solve(fdd_problem_s* P, const double* f, double* u, const fdd_opts& o,
                          hipStream_t s, int* its);
 int model_precond_apply(fdd_problem_s* P, const fdd_ratpc_s* T, const double* r, double* z,

@@ -34,7 +34,7 @@ STATUS_NAMES = {
 
 # every symbol declared in include/fdd.h
 EXPORTED = [
-    "fdd_opts_default", "fdd_setup_mesh", "fdd_setup_model", "fdd_problem_info", "fdd_workspace_bytes",
+    "fdd_opts_default", "fdd_setup_mesh", "fdd_setup_model", "fdd_setup_hdiv", "fdd_problem_info", "fdd_workspace_bytes",
     "fdd_bind_workspace", "fdd_build_rational_pc", "fdd_ratpc_from_table", "fdd_ratpc_query",
     "fdd_interior_solve", "fdd_schur_apply", "fdd_precond_apply", "fdd_precond_apply_static",
     "fdd_apply_operator", "fdd_dd_precond_apply", "fdd_solve_full",
@@ -97,6 +97,7 @@ def load():
     lib.fdd_opts_default.restype = None
     lib.fdd_setup_mesh.argtypes = [ctypes.POINTER(FddDesc), I, ctypes.POINTER(P)]
     lib.fdd_setup_model.argtypes = [I, D, D, D, I, ctypes.POINTER(P)]
+    lib.fdd_setup_hdiv.argtypes = [I, D, D, I, ctypes.POINTER(P)]
     lib.fdd_problem_info.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.fdd_workspace_bytes.argtypes = [P, ctypes.POINTER(FddOpts), ctypes.POINTER(ctypes.c_size_t)]
@@ -229,16 +230,24 @@ class RationalTable:
             self.h = None
 
 
+def _th(T):
+    """The handle of a rational table, or NULL for None (the H(div) problem has no operator table)."""
+    return None if T is None else T.h
+
+
 class Problem:
     """A set-up problem (fdd_setup_mesh); host only until bind_workspace is called."""
 
-    def __init__(self, n, K, mu, dim=2, device=0, model_t=None):
+    def __init__(self, n, K, mu, dim=2, device=0, model_t=None, hdiv=False):
         """model_t is None: eq. (riesz) with Gamma a facet (fdd_setup_mesh); otherwise the paper's
         model problem with Gamma the whole boundary, gamma = mu and exponent t = model_t
-        (fdd_setup_model)."""
+        (fdd_setup_model).  hdiv: the H(div) problem of eq. (graddiv) with gamma = mu
+        (fdd_setup_hdiv)."""
         lib = load()
         h = ctypes.c_void_p()
-        if model_t is None:
+        if hdiv:
+            _check(lib.fdd_setup_hdiv(n, K, mu, device, ctypes.byref(h)))
+        elif model_t is None:
             d = FddDesc(dim, n, K, mu)
             _check(lib.fdd_setup_mesh(ctypes.byref(d), device, ctypes.byref(h)))
         else:
@@ -246,6 +255,7 @@ class Problem:
         self.h = h
         self.n, self.K, self.mu, self.dim = n, K, mu, dim
         self.model_t = model_t
+        self.hdiv = hdiv
         self.device = device
         self.workspace = None
         N, NI, NG = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -298,7 +308,7 @@ class Problem:
         return its.value
 
     def schur_apply(self, H, x_G, y_G, opts=None, stream=None):
-        _check(load().fdd_schur_apply(self.h, H.h, self._v(x_G, self.NG, "x_G"), self._v(y_G, self.NG, "y_G"),
+        _check(load().fdd_schur_apply(self.h, _th(H), self._v(x_G, self.NG, "x_G"), self._v(y_G, self.NG, "y_G"),
                                       ctypes.byref(opts or opts_default()), _stream(stream)))
 
     def precond_apply(self, P, r_G, z_G, stream=None):
@@ -311,12 +321,12 @@ class Problem:
                                                self._v(z_G, self.NG, "z_G"), _stream(stream)))
 
     def apply_operator(self, H, x, y, stream=None):
-        _check(load().fdd_apply_operator(self.h, H.h, self._v(x, self.N, "x"), self._v(y, self.N, "y"),
+        _check(load().fdd_apply_operator(self.h, _th(H), self._v(x, self.N, "x"), self._v(y, self.N, "y"),
                                          _stream(stream)))
 
     def solve(self, P, H, b, x, opts=None, stream=None, allow_not_converged=False):
         st = FddStats()
-        rc = load().fdd_solve(self.h, P.h, H.h, self._v(b, self.N, "b"), self._v(x, self.N, "x"),
+        rc = load().fdd_solve(self.h, P.h, _th(H), self._v(b, self.N, "b"), self._v(x, self.N, "x"),
                               ctypes.byref(opts or opts_default()),
                               _stream(stream), ctypes.byref(st))
         _check(rc, (FDD_OK, FDD_NOT_CONVERGED) if allow_not_converged else (FDD_OK,))
@@ -513,6 +523,11 @@ def setup_mesh(n, K, mu, dim=2, device=0):
 def setup_model(n, K, gamma, t, device=0):
     """The paper's model problem (Gamma = the whole boundary, exponent t): fdd_setup_model."""
     return Problem(n, K, gamma, 2, device, model_t=t)
+
+
+def setup_hdiv(n, K, gamma, device=0):
+    """The H(div) problem of eq. (graddiv) (BDM1, Gamma = the whole boundary): fdd_setup_hdiv."""
+    return Problem(n, K, gamma, 2, device, hdiv=True)
 
 
 def build_rational_pc(prob, which=FDD_RA_PRECOND, tol=1e-12, max_poles=64):
