@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D cases")
     ap.add_argument("--model", choices=["auto", "none", "only"], default="auto",
                     help="the paper's own model problem (Gamma = the whole boundary) beside the headline")
+    ap.add_argument("--hdiv", choices=["auto", "none", "only"], default="auto",
+                    help="the H(div) variant (eq. (graddiv), BDM1) beside the headline")
     ap.add_argument("--full-lazy", choices=["auto", "none", "only"], default="auto",
                     help="the full-system PCG with the lazy block preconditioner beside the headline")
     ap.add_argument("--cnn-only", action="store_true", help="only time the warm-start network kernels")
@@ -615,6 +617,80 @@ def run_model(F, args, leg, n=1024, reps=2, ts=(-0.5, 0.5), gammas=(1.0, 1e3)):
     return res
 
 
+def run_hdiv(F, args, leg, n=512, reps=2, gammas=(1e-3, 1.0, 1e3), robust_sizes=(64, 128, 256, 512)):
+    """The H(div) variant (Sec. 3 remark, eq. (graddiv); BDM1, Gamma = the whole boundary), K = 1,
+    outer rtol 1e-10, inner 1e-12:
+    solves/s at n (6n^2 + 4n dofs) per gamma with outer/inner counts and true residuals, the outer
+    counts over n (the robustness of Fig. 4, right), parity spot-checks at n = 64 against the
+    oracle's sparse LU, and the oracle's Schur PCG (sparse LU interior, exact S_Gamma) timed at
+    n = 32.  FP64 throughout."""
+    import numpy as np
+    import torch
+
+    # the paper's stop rule of Sec. 3: the preconditioned residual norm reduced by 1e10
+    rtol, inner_rtol = 1e-10, 1e-12
+    res = {"n": n, "K": 1.0, "rtol": rtol, "inner_rtol": inner_rtol, "cases": [], "outer_its_over_n": {}}
+    for g in gammas:
+        P = F.setup_hdiv(n, 1.0, g)
+        P.bind_workspace()
+        TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+        opts = F.opts_default(outer_rtol=rtol, inner_rtol=inner_rtol, check_true_residual=1)
+        bs = [torch.as_tensor(np.random.default_rng(8000 + k).standard_normal(P.N), dtype=torch.float64,
+                              device="cuda") for k in range(reps + 1)]
+        x = torch.zeros_like(bs[0])
+        P.solve(TP, None, bs[reps], x, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [P.solve(TP, None, bs[k], x, opts) for k in range(reps)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        row = {"gamma": g, "dofs": P.N, "solves_per_s": reps / el, "outer_its": sts[-1]["outer_its"],
+               "inner_its": sts[-1]["inner_its_total"], "poles_P": TP.query()["m"],
+               "true_rel_res_max": max(s_["true_rel_res"] for s_ in sts)}
+        # parity spot-check at n = 64
+        Q = F.setup_hdiv(64, 1.0, g)
+        Q.bind_workspace()
+        QP = Q.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+        bq = torch.as_tensor(np.random.default_rng(8100).standard_normal(Q.N), dtype=torch.float64, device="cuda")
+        xq = torch.zeros_like(bq)
+        Q.solve(QP, None, bq, xq, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12))
+        row["n64_rel_err_vs_oracle"] = None
+        bh, xh = bq.cpu().numpy(), xq.cpu().numpy()
+
+        def parity(g=g, bh=bh, xh=xh):
+            from oracle import hdiv
+            xr = hdiv.HdivProblem(64, 1.0, g).solve_splu(bh)
+            return float(np.linalg.norm(xh - xr) / np.linalg.norm(xr))
+        leg.defer(row, "n64_rel_err_vs_oracle", parity)
+        res["cases"].append(row)
+        progress(f"H(div) n={n} gamma={g:g}: {row['solves_per_s']:.1f} solves/s, outer {row['outer_its']}")
+        counts = []
+        for m in robust_sizes:
+            R = F.setup_hdiv(m, 1.0, g)
+            R.bind_workspace()
+            RP = R.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+            br = torch.as_tensor(np.random.default_rng(8200 + m).standard_normal(R.N), dtype=torch.float64,
+                                 device="cuda")
+            counts.append(R.solve(RP, None, br, torch.zeros_like(br), opts)["outer_its"])
+        res["outer_its_over_n"][f"gamma={g:g}"] = dict(zip([str(m) for m in robust_sizes], counts))
+
+    def cpu_rate():
+        from oracle import hdiv
+        M = hdiv.HdivProblem(32, 1.0, 1.0)
+        b = np.random.default_rng(8300).standard_normal(M.N)
+        t0 = time.perf_counter()
+        M.interior_lu()
+        t_fact = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, its = M.schur_pcg(b, rtol=rtol)
+        return {"n": 32, "gamma": 1.0, "solves_per_s": 1.0 / (time.perf_counter() - t0),
+                "factorization_s": t_fact, "outer_its": its,
+                "kind": "oracle Schur PCG, sparse LU interior, exact S_Gamma", "cores": 1}
+    res["cpu_baseline"] = None
+    leg.defer(res, "cpu_baseline", cpu_rate)
+    return res
+
+
 def run_sweep(F, args, leg, sizes=(128, 256, 512, 1024, 2048)):
     """2D sweep n x K in {1, 1e-2, 1e-4} x mu in {1e-6, 1e-3, 1, 1e3} (seed 1000 + index): outer and
     inner iterations, solves/s (one warm-up and two timed solves) and the error of the solution."""
@@ -741,6 +817,12 @@ def main():
         res = run_model(F, args, leg)
         leg.run()
         print(json.dumps({"model_problem": res}))
+        return
+    if args.hdiv == "only":
+        leg = OracleLeg()
+        res = run_hdiv(F, args, leg)
+        leg.run()
+        print(json.dumps({"hdiv": res}))
         return
     if args.full_lazy == "only":
         leg = OracleLeg()
@@ -932,6 +1014,9 @@ def main():
     if args.model == "auto":
         progress("model problem")
         out["model_problem"] = run_model(F, args, leg)
+    if args.hdiv == "auto":
+        progress("H(div) variant")
+        out["hdiv"] = run_hdiv(F, args, leg)
     if args.learned == "auto":
         progress("learned warm start")
         out["learned"] = run_learned(F, args, leg)

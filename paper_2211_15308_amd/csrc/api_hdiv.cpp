@@ -149,7 +149,8 @@ int hdiv_bind(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s) {
   };
   auto upm = [&](const HdMat& M) -> int {
     int rc = up(M.dcol, M.col.data(), M.col.size() * sizeof(int));
-    return rc ? rc : up(M.dval, M.val.data(), M.val.size() * sizeof(double));
+    if (!rc) rc = up(M.drtype, M.rtype.data(), M.rtype.size() * sizeof(int));
+    return rc ? rc : up(M.dtval, M.tval.data(), M.tval.size() * sizeof(double));
   };
   int rc = FDD_OK;
   for (int l = 0; l < Q->nlev && !rc; ++l) {

@@ -20,7 +20,7 @@ namespace fdd {
 constexpr int kHdPatch = 12;       // dofs of a vertex patch (six incident edges)
 constexpr int kHdMaxTypes = 16;    // distinct patch matrices per level
 constexpr int kHdMaxLevels = 12;
-constexpr int kHdCoarseN = 2;      // cells per side of the coarsest level (16 dofs)
+constexpr int kHdCoarseN = 8;      // the coarsest level: min(n, 8) cells per side, dense inverse
 constexpr int kHdMaxN = 1024;      // the loop solves hold 4n segments in one workgroup's LDS
 
 // Device state of one H(div) problem: scalars of the interior PCG (A^00 u = f) and of the outer
@@ -46,15 +46,18 @@ struct HdTable {
   double d[kMaxPoles], q[kMaxPoles];
 };
 
-// A sparse matrix in ELL form: every row holds `width` (column, value) slots, slot k of row i
-// at k * rows + i (consecutive rows are consecutive in memory, so a wave's loads coalesce);
-// unused slots have value 0 and column i.  Host copy built at setup, device copy in the workspace.
+// A sparse matrix in ELL form with typed rows: every row holds `width` column slots, slot k of
+// row i at k * rows + i (consecutive rows are consecutive in memory, so a wave's loads coalesce;
+// unused slots point at column min(i, cols - 1) with value 0), and its values come from a small
+// table: row i's slot k has value tval[rtype[i] * width + k].  On the uniform mesh rows repeat
+// (translation invariance), so a product reads 4 bytes per slot and per row instead of 12.
+// Host copies (val: the expanded values) built at setup, device copies in the workspace.
 struct HdMat {
-  int rows = 0, cols = 0, width = 0;
-  std::vector<int> col;
-  std::vector<double> val;
-  int* dcol = nullptr;
-  double* dval = nullptr;
+  int rows = 0, cols = 0, width = 0, ntypes = 0;
+  std::vector<int> col, rtype;
+  std::vector<double> val, tval;
+  int *dcol = nullptr, *drtype = nullptr;
+  double* dtval = nullptr;
 };
 
 struct HdLevel {
@@ -79,7 +82,7 @@ struct ProblemHdiv {
   double K = 1, gamma = 0, theta = 0.5;
   int N = 0, N0 = 0, NG = 0;
   HdLevel lev[kHdMaxLevels];
-  std::vector<double> cinv;  // dense inverse of the coarsest A^00 (n0 x n0)
+  std::vector<double> cinv;  // dense inverse of the coarsest A^00 (n0 x n0, row-major)
   HdMat A0G, AG0, AGG, Afull;
   HdLoopBlocks blk;          // the trace operator L and mass M_Q on the loop
   int its_hint = 0;          // iterations of the last interior solve (enqueued ahead)
@@ -95,7 +98,7 @@ struct ProblemHdiv {
   size_t ws_need = 0;
 };
 
-constexpr int kHdPartials = 1024;
+constexpr int kHdPartials = 8192;
 
 // ---- host setup (hdiv_setup.cpp) ------------------------------------------------------------
 // Builds every level's matrices, transfers and patch tables.  Returns 0 or a message.
@@ -108,10 +111,11 @@ std::vector<double> hdiv_loop_eigs(const ProblemHdiv* Q);
 // ---- kernels (kernels_hdiv.hip) --------------------------------------------------------------
 struct HdView {
   const int* col;
-  const double* val;
+  const int* rtype;
+  const double* tval;
   int rows, width;
 };
-inline HdView view(const HdMat& m) { return HdView{m.dcol, m.dval, m.rows, m.width}; }
+inline HdView view(const HdMat& m) { return HdView{m.dcol, m.drtype, m.dtval, m.rows, m.width}; }
 
 // Every launcher takes `stop`: kernels return at once when stop->done is set (null: never).
 // y = beta y + alpha A x  (beta = 0: y is only written)
@@ -125,7 +129,7 @@ void launch_hd_patch_solve(hipStream_t s, const HdLevel& L, const double* r, con
 // x = (add ? x : 0) + theta (sum of the patch solutions holding each dof)
 void launch_hd_patch_sum(hipStream_t s, const HdLevel& L, double theta, double* x, int add,
                          const HdState* stop);
-// x = C b on the coarsest level (dense, one workgroup)
+// x = C b on the coarsest level (dense, row-major C, one wave per row)
 void launch_hd_coarse(hipStream_t s, const double* C, int n0, const double* b, double* x,
                       const HdState* stop);
 // interior PCG on A^00 (scalars on the device, fixed-order reductions)

@@ -16,6 +16,8 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "hdiv_internal.h"
@@ -156,7 +158,7 @@ struct RowBuilder {
     ++cnt[i];
     return true;
   }
-  // ELL form, columns ascending within a row
+  // ELL form, columns ascending within a row, rows typed by their value sequence
   void to_ell(HdMat* M, int ncols) const {
     int w = 1;
     for (int i = 0; i < rows; ++i) w = std::max(w, cnt[i]);
@@ -165,7 +167,11 @@ struct RowBuilder {
     M->width = w;
     M->col.assign((size_t)rows * w, 0);
     M->val.assign((size_t)rows * w, 0.0);
+    M->rtype.assign(rows, 0);
+    M->tval.clear();
+    std::unordered_map<std::string, int> types;
     std::vector<std::pair<int, double>> tmp;
+    std::vector<double> vals(w);
     for (int i = 0; i < rows; ++i) {
       tmp.clear();
       for (int k = 0; k < cnt[i]; ++k) tmp.emplace_back(col[(size_t)i * cap + k], val[(size_t)i * cap + k]);
@@ -173,9 +179,22 @@ struct RowBuilder {
       for (int k = 0; k < w; ++k) {
         const bool used = k < (int)tmp.size();
         M->col[(size_t)k * rows + i] = used ? tmp[k].first : std::min(i, ncols - 1);
-        M->val[(size_t)k * rows + i] = used ? tmp[k].second : 0.0;
+        vals[k] = used ? tmp[k].second : 0.0;
+        M->val[(size_t)k * rows + i] = vals[k];
       }
+      const std::string key((const char*)vals.data(), vals.size() * sizeof(double));
+      auto it = types.find(key);
+      int t;
+      if (it == types.end()) {
+        t = (int)types.size();
+        types.emplace(key, t);
+        M->tval.insert(M->tval.end(), vals.begin(), vals.end());
+      } else {
+        t = it->second;
+      }
+      M->rtype[i] = t;
     }
+    M->ntypes = (int)types.size();
   }
 };
 
@@ -188,7 +207,7 @@ double ell_entry(const HdMat& M, int i, int j) {
   return 0.0;
 }
 
-// SPD inverse by Cholesky (m <= 16); false if not positive definite.
+// SPD inverse by Cholesky; false if not positive definite.
 bool spd_inverse(std::vector<double>& A, int m) {
   std::vector<double> L((size_t)m * m, 0.0);
   for (int j = 0; j < m; ++j) {
@@ -357,38 +376,6 @@ const char* build_patches(HdLevel* L) {
   return nullptr;
 }
 
-// Gauss-Jordan inverse with partial pivoting (the coarsest level's dense matrix).
-bool dense_inverse(std::vector<double>& A, int m) {
-  std::vector<double> I((size_t)m * m, 0.0);
-  for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = 1.0;
-  for (int c = 0; c < m; ++c) {
-    int piv = c;
-    for (int r = c + 1; r < m; ++r)
-      if (std::fabs(A[(size_t)r * m + c]) > std::fabs(A[(size_t)piv * m + c])) piv = r;
-    if (A[(size_t)piv * m + c] == 0.0) return false;
-    for (int k = 0; k < m; ++k) {
-      std::swap(A[(size_t)c * m + k], A[(size_t)piv * m + k]);
-      std::swap(I[(size_t)c * m + k], I[(size_t)piv * m + k]);
-    }
-    const double d = A[(size_t)c * m + c];
-    for (int k = 0; k < m; ++k) {
-      A[(size_t)c * m + k] /= d;
-      I[(size_t)c * m + k] /= d;
-    }
-    for (int r = 0; r < m; ++r) {
-      if (r == c) continue;
-      const double f = A[(size_t)r * m + c];
-      if (f == 0.0) continue;
-      for (int k = 0; k < m; ++k) {
-        A[(size_t)r * m + k] -= f * A[(size_t)c * m + k];
-        I[(size_t)r * m + k] -= f * I[(size_t)c * m + k];
-      }
-    }
-  }
-  A = I;
-  return true;
-}
-
 // Blocks of the trace operator on the loop (segment k holds u at its start and at its end):
 // L = sum_e int (u'v' + uv) - sum_vertices ({u'}[v] + {v'}[u]) + (sigma / h) sum [u][v],
 // [u] = u(end of the segment before the vertex) - u(start of the one after), {u'} the mean
@@ -428,7 +415,7 @@ const char* hdiv_build(ProblemHdiv* Q, int n, double K, double gamma) {
   Q->NG = 8 * n;
   Q->N = Q->N0 + Q->NG;
   int nl = 0;
-  for (int m = n; m >= kHdCoarseN; m /= 2) {
+  for (int m = n; m >= std::min(n, kHdCoarseN); m /= 2) {
     if (nl == kHdMaxLevels) return "too many levels";
     HdLevel& L = Q->lev[nl++];
     L.n = m;
@@ -447,7 +434,7 @@ const char* hdiv_build(ProblemHdiv* Q, int n, double K, double gamma) {
     std::vector<double> A((size_t)C.n0 * C.n0);
     for (int i = 0; i < C.n0; ++i)
       for (int j = 0; j < C.n0; ++j) A[(size_t)i * C.n0 + j] = ell_entry(C.A, i, j);
-    if (!dense_inverse(A, C.n0)) return "singular coarsest matrix";
+    if (!spd_inverse(A, C.n0)) return "the coarsest matrix is not positive definite";
     Q->cinv = A;
   }
   // the whole operator and its blocks
@@ -514,7 +501,8 @@ size_t hdiv_plan(ProblemHdiv* Q, char* base) {
   };
   auto mat = [&](HdMat& M) {
     M.dcol = (int*)take(M.col.size() * sizeof(int));
-    M.dval = (double*)take(M.val.size() * sizeof(double));
+    M.drtype = (int*)take(M.rtype.size() * sizeof(int));
+    M.dtval = (double*)take(M.tval.size() * sizeof(double));
   };
   for (int l = 0; l < Q->nlev; ++l) {
     HdLevel& L = Q->lev[l];

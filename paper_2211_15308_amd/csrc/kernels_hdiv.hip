@@ -1,7 +1,8 @@
 // Kernels of the H(div) problem (Sec. 3, remark on H(div)-elliptic problems, eq. (graddiv)).
 //
-// * Sparse products in ELL form (slot k of row i at k * rows + i: a wave reads consecutive rows,
-//   so its loads of values and columns coalesce; the gathered x entries come from L2).
+// * Sparse products in typed ELL form (slot k of row i at k * rows + i: a wave reads consecutive
+//   rows, so its column loads coalesce; values come from a small per-row-type table, the gathered
+//   x entries from L2).
 // * The multigrid smoother for A^00 = K(I - grad div) on V_0 is additive Schwarz over vertex
 //   patches (the dofs on the edges at a vertex; the patches hold the curls of the P2 vertex and
 //   edge functions, which span the kernel of div): one thread per vertex multiplies the patch's
@@ -53,45 +54,26 @@ __device__ double sum_partials(const double* p, int nb) {
   return block_sum(v);
 }
 
-__device__ __forceinline__ double ell_row(const int* __restrict__ col, const double* __restrict__ val,
-                                          int rows, int width, int i, const double* __restrict__ x) {
+__device__ __forceinline__ double ell_row(const HdView& A, int i, const double* __restrict__ x) {
+  const double* v = A.tval + (size_t)A.rtype[i] * A.width;
   double s = 0.0;
-  for (int k = 0; k < width; ++k) {
-    const size_t o = (size_t)k * rows + i;
-    s += val[o] * x[col[o]];
-  }
+  for (int k = 0; k < A.width; ++k) s += v[k] * x[A.col[(size_t)k * A.rows + i]];
   return s;
 }
 
 // ---- sparse products, smoother, coarse solve ------------------------------------------------
 
-__global__ __launch_bounds__(kT) void k_hd_spmv(HdView A, const double* __restrict__ x,
-                                                double* __restrict__ y, double alpha, double beta,
-                                                const HdState* stop) {
-  if (stopped(stop)) return;
-  const int i = blockIdx.x * kT + threadIdx.x;
-  if (i >= A.rows) return;
-  const double s = ell_row(A.col, A.val, A.rows, A.width, i, x);
+__device__ __forceinline__ void spmv_row(const HdView& A, int i, const double* __restrict__ x,
+                                         double* __restrict__ y, double alpha, double beta) {
+  const double s = ell_row(A, i, x);
   y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + alpha * s;
 }
 
-__global__ __launch_bounds__(kT) void k_hd_residual(HdView A, const double* __restrict__ b,
-                                                    const double* __restrict__ x,
-                                                    double* __restrict__ r, const HdState* stop) {
-  if (stopped(stop)) return;
-  const int i = blockIdx.x * kT + threadIdx.x;
-  if (i >= A.rows) return;
-  r[i] = b[i] - ell_row(A.col, A.val, A.rows, A.width, i, x);
-}
-
-__global__ __launch_bounds__(kT) void k_hd_patch_solve(const int* __restrict__ patch,
-                                                       const int* __restrict__ ptype,
-                                                       const double* __restrict__ pinv, int nvert,
-                                                       const double* __restrict__ r,
-                                                       double* __restrict__ Y, const HdState* stop) {
-  if (stopped(stop)) return;
-  const int v = blockIdx.x * kT + threadIdx.x;
-  if (v >= nvert) return;
+__device__ __forceinline__ void patch_solve_vertex(const int* __restrict__ patch,
+                                                   const int* __restrict__ ptype,
+                                                   const double* pinv, int v,
+                                                   const double* __restrict__ r,
+                                                   double* __restrict__ Y) {
   const int t = ptype[v];
   if (t < 0) return;
   double rl[kHdPatch];
@@ -110,13 +92,9 @@ __global__ __launch_bounds__(kT) void k_hd_patch_solve(const int* __restrict__ p
   }
 }
 
-__global__ __launch_bounds__(kT) void k_hd_patch_sum(const int* __restrict__ slot, int n0,
-                                                     const double* __restrict__ Y, double theta,
-                                                     double* __restrict__ x, int add,
-                                                     const HdState* stop) {
-  if (stopped(stop)) return;
-  const int i = blockIdx.x * kT + threadIdx.x;
-  if (i >= n0) return;
+__device__ __forceinline__ void patch_sum_dof(const int* __restrict__ slot, int i,
+                                              const double* __restrict__ Y, double theta,
+                                              double* __restrict__ x, int add) {
   const int s0 = slot[2 * (size_t)i], s1 = slot[2 * (size_t)i + 1];
   double v = 0.0;
   if (s0 >= 0) v += Y[s0];
@@ -124,15 +102,68 @@ __global__ __launch_bounds__(kT) void k_hd_patch_sum(const int* __restrict__ slo
   x[i] = (add ? x[i] : 0.0) + theta * v;
 }
 
+__global__ __launch_bounds__(kT) void k_hd_spmv(HdView A, const double* __restrict__ x,
+                                                double* __restrict__ y, double alpha, double beta,
+                                                const HdState* stop) {
+  if (stopped(stop)) return;
+  const int i = blockIdx.x * kT + threadIdx.x;
+  if (i >= A.rows) return;
+  spmv_row(A, i, x, y, alpha, beta);
+}
+
+__global__ __launch_bounds__(kT) void k_hd_residual(HdView A, const double* __restrict__ b,
+                                                    const double* __restrict__ x,
+                                                    double* __restrict__ r, const HdState* stop) {
+  if (stopped(stop)) return;
+  const int i = blockIdx.x * kT + threadIdx.x;
+  if (i >= A.rows) return;
+  r[i] = b[i] - ell_row(A, i, x);
+}
+
+// (the few inverse patch matrices are staged in LDS: every lane reads a row of its vertex's)
+__global__ __launch_bounds__(kT) void k_hd_patch_solve(const int* __restrict__ patch,
+                                                       const int* __restrict__ ptype,
+                                                       const double* __restrict__ pinv, int ntypes,
+                                                       int nvert, const double* __restrict__ r,
+                                                       double* __restrict__ Y, const HdState* stop) {
+  if (stopped(stop)) return;
+  __shared__ double sp[kHdMaxTypes * kHdPatch * kHdPatch];
+  for (int k = threadIdx.x; k < ntypes * kHdPatch * kHdPatch; k += kT) sp[k] = pinv[k];
+  __syncthreads();
+  const int v = blockIdx.x * kT + threadIdx.x;
+  if (v >= nvert) return;
+  patch_solve_vertex(patch, ptype, sp, v, r, Y);
+}
+
+__global__ __launch_bounds__(kT) void k_hd_patch_sum(const int* __restrict__ slot, int n0,
+                                                     const double* __restrict__ Y, double theta,
+                                                     double* __restrict__ x, int add,
+                                                     const HdState* stop) {
+  if (stopped(stop)) return;
+  const int i = blockIdx.x * kT + threadIdx.x;
+  if (i >= n0) return;
+  patch_sum_dof(slot, i, Y, theta, x, add);
+}
+
+__device__ __forceinline__ double dense_row(const double* __restrict__ C, int n0, int row, int lane,
+                                            const double* __restrict__ b) {
+  const double* c = C + (size_t)row * n0;
+  double s = 0.0;
+  for (int j = lane; j < n0; j += 64) s += c[j] * b[j];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  return s;
+}
+
+// x = C b, one wave per row (C row-major): the lanes read consecutive entries of the row and
+// the wave sums them in fixed order
 __global__ __launch_bounds__(kT) void k_hd_coarse(const double* __restrict__ C, int n0,
                                                   const double* __restrict__ b,
                                                   double* __restrict__ x, const HdState* stop) {
   if (stopped(stop)) return;
-  for (int i = threadIdx.x; i < n0; i += kT) {
-    double s = 0.0;
-    for (int j = 0; j < n0; ++j) s += C[(size_t)i * n0 + j] * b[j];
-    x[i] = s;
-  }
+  const int row = blockIdx.x * (kT / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= n0) return;
+  const double s = dense_row(C, n0, row, lane, b);
+  if (lane == 0) x[row] = s;
 }
 
 // ---- interior PCG ------------------------------------------------------------------------------
@@ -202,12 +233,12 @@ __global__ __launch_bounds__(kT) void k_hd_pq(HdView A, const double* __restrict
   double s = 0.0;
   for (int i = blockIdx.x * kT + threadIdx.x; i < A.rows; i += gridDim.x * kT) {
     // q = A (z + beta p_old), with the direction formed where the product reads it
+    const double* v = A.tval + (size_t)A.rtype[i] * A.width;
     double qi = 0.0;
     for (int k = 0; k < A.width; ++k) {
-      const size_t o = (size_t)k * A.rows + i;
-      const int c = A.col[o];
+      const int c = A.col[(size_t)k * A.rows + i];
       const double pc = first ? z[c] : z[c] + beta * p_old[c];
-      qi += A.val[o] * pc;
+      qi += v[k] * pc;
     }
     const double pi = first ? z[i] : z[i] + beta * p_old[i];
     p_new[i] = pi;
@@ -437,7 +468,7 @@ __global__ __launch_bounds__(kT) void k_hd_true_res(HdView A, const double* __re
                                                     double* __restrict__ partials) {
   double s = 0.0, t = 0.0;
   for (int i = blockIdx.x * kT + threadIdx.x; i < A.rows; i += gridDim.x * kT) {
-    const double e = b[i] - ell_row(A.col, A.val, A.rows, A.width, i, x);
+    const double e = b[i] - ell_row(A, i, x);
     s += e * e;
     t += b[i] * b[i];
   }
@@ -483,8 +514,8 @@ void launch_hd_residual(hipStream_t s, HdView A, const double* b, const double* 
 
 void launch_hd_patch_solve(hipStream_t s, const HdLevel& L, const double* r, const HdState* stop) {
   hipLaunchKernelGGL(k_hd_patch_solve, dim3(blocks_for(L.nvert)), dim3(kT), 0, s,
-                     (const int*)L.dpatch, (const int*)L.dptype, (const double*)L.dpinv, L.nvert,
-                     r, L.Y, stop);
+                     (const int*)L.dpatch, (const int*)L.dptype, (const double*)L.dpinv, L.ntypes,
+                     L.nvert, r, L.Y, stop);
 }
 
 void launch_hd_patch_sum(hipStream_t s, const HdLevel& L, double theta, double* x, int add,
@@ -495,7 +526,8 @@ void launch_hd_patch_sum(hipStream_t s, const HdLevel& L, double theta, double* 
 
 void launch_hd_coarse(hipStream_t s, const double* C, int n0, const double* b, double* x,
                       const HdState* stop) {
-  hipLaunchKernelGGL(k_hd_coarse, dim3(1), dim3(kT), 0, s, C, n0, b, x, stop);
+  hipLaunchKernelGGL(k_hd_coarse, dim3((n0 + kT / 64 - 1) / (kT / 64)), dim3(kT), 0, s, C, n0, b, x,
+                     stop);
 }
 
 void launch_hd_pcg_start(hipStream_t s, int n0, const double* f, double* u, double* r,

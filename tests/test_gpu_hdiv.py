@@ -82,7 +82,7 @@ def test_interior_solve_matches_oracle(n, nu):
 
 def test_interior_iterations_bounded_in_h():
     counts = []
-    for n in (16, 64, 256):
+    for n in (64, 256, 1024):
         P = F.setup_hdiv(n, 1.0, 1.0)
         P.bind_workspace()
         f = np.random.default_rng(n).standard_normal(P.NI)
