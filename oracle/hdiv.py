@@ -42,7 +42,8 @@ blocks, one per segment), so their generalized spectrum has a closed form per Fo
 
 Parity: pinned by the dual-basis property of the BDM1 fields (evaluated pointwise), exactness on
 linear vector fields (mass, divergence and boundary terms against closed-form integrals), the
-divergence theorem per triangle, second-order convergence to a manufactured solution, the closed
+divergence theorem per triangle, nestedness (the Galerkin product of the inclusion reproduces the
+coarse matrices, and linear fields are carried over exactly), second-order convergence to a manufactured solution, the closed
 form of the loop spectrum, consistency of L on smooth periodic functions, the Schur complement
 identity and bounded condition numbers of S_Gamma^{-1} S over h and gamma
 (tests/test_oracle_hdiv.py).
@@ -188,6 +189,30 @@ def assemble(n):
         Bd[a, b] += h / 6
         Bd[b, a] += h / 6
     return Mass, Div, Bd.tocsr()
+
+
+def prolongation(nc):
+    """The natural inclusion of BDM1 on n_c cells per side into BDM1 on 2 n_c (the meshes are
+    nested): each fine dof "u.n_e at an endpoint" of a coarse field is its value there, taken in
+    the coarse triangle that holds the fine edge, times the fine edge's normal.  All dofs."""
+    nf = 2 * nc
+    coarse = triangle_bases(nc)
+    rows, cols, vals = [], [], []
+    for e, (p, q, nrm) in enumerate(edges(nf)):
+        mid = (np.array(p) + np.array(q)) / 2.0 / nf
+        xc = mid * nc
+        ci = min(int(np.floor(xc[0])), nc - 1)
+        cj = min(int(np.floor(xc[1])), nc - 1)
+        t = 2 * (cj * nc + ci) + (0 if xc[0] - ci >= xc[1] - cj else 1)
+        T = coarse[t]
+        for k, pt in enumerate((p, q)):
+            v = T.eval(np.array(pt) / nf) @ np.array(nrm)
+            for d, val in zip(T.dofs, v):
+                if abs(val) > 1e-14:
+                    rows.append(2 * e + k)
+                    cols.append(d)
+                    vals.append(val)
+    return sp.coo_matrix((vals, (rows, cols)), shape=(sizes(nf)[0], sizes(nc)[0])).tocsr()
 
 
 # ----------------------------------------------------------------------------

@@ -114,6 +114,19 @@ def test_divergence_theorem_per_triangle():
             assert abs(d[a] * T.area - flux) < 1e-9
 
 
+@pytest.mark.parametrize("nc", [2, 4])
+def test_nested_spaces_galerkin(nc):
+    # BDM1 on the refined mesh contains the coarse space: P^T A_f P = A_c for mass and div-div,
+    # and the inclusion maps the interpolant of a linear field to the fine interpolant
+    P = hdiv.prolongation(nc)
+    Mf, Df, _ = hdiv.assemble(2 * nc)
+    Mc, Dc, _ = hdiv.assemble(nc)
+    assert abs(P.T @ Mf @ P - Mc).max() < 1e-14
+    assert abs(P.T @ Df @ P - Dc).max() < 1e-12
+    u = lambda x: np.array([0.2 - x[0] + 3 * x[1], 1.1 + 0.5 * x[0] - 2 * x[1]])
+    assert np.max(np.abs(P @ interpolate(nc, u) - interpolate(2 * nc, u))) < 1e-12
+
+
 def test_manufactured_solution_second_order():
     # K (u - grad div u) = f in Omega, K div u + gamma u.nu = g on the boundary (the natural
     # condition of eq. (graddiv)); u = (sin(pi x) cos(pi y / 2), x^2 e^y)
