@@ -104,6 +104,21 @@ __global__ __launch_bounds__(kPairThreads) void k_triple_up(
                   tile_y);
 }
 
+template <int NU>
+__global__ __launch_bounds__(kPairThreads) void k_quad_up(
+    const float* __restrict__ f0, const float* __restrict__ u0pre, const float* __restrict__ f1,
+    const float* __restrict__ u1pre, const float* __restrict__ f2, const float* __restrict__ u2pre,
+    const float* __restrict__ f3, const float* __restrict__ u3pre, const float* __restrict__ f4,
+    const float* __restrict__ S, const float* __restrict__ lam, float* __restrict__ z, int nf0,
+    int p0, int p1, int p2, int p3, int p4, DevState* st, Reductions red, int kn,
+    int count_iteration) {
+  if (stopped(st)) return;
+  int tile_x, tile_y;
+  (void)xcd_tile(&tile_x, &tile_y);
+  d_quad_up<NU>(f0, u0pre, f1, u1pre, f2, u2pre, f3, u3pre, f4, S, lam, z, nf0, p0, p1, p2, p3, p4,
+                st, red, kn, count_iteration, tile_x, tile_y, block0());
+}
+
 template <typename T, int NU>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_vcycle(
     const T* __restrict__ fin, int pin, T* __restrict__ eout, LaunchLevels lv,
@@ -165,8 +180,16 @@ static inline dim3 ptiles(int nf) {
   return dim3(t, t);
 }
 
+// FP32 V-cycles whose tiled levels below the finest are exactly 1, 2, 3 (the coarse solve on level
+// 4; n = 1024 and 768): the whole up side runs as one kernel (k_quad_up) in the CG iterations
+template <typename T>
+static bool quad_up(const LaunchCtx& c) {
+  return sizeof(T) == 4 && c.first_coarse == 4 && c.nlev >= 5;
+}
+
 template <typename T, int NU>
-static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check) {
+static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check,
+                           bool skip_up = false) {
   // levels 1 .. first_coarse-1 go down, the coarse kernel, then back up to level 1; in FP32 the
   // tiled levels run in pairs (1, 2), (3, 4), ... in one kernel each, an odd last one alone (the
   // FP64 windows of a pair exceed the LDS); the first of these kernels also runs the PCG
@@ -220,6 +243,7 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
                        mg.f[l], mg.u[l], mg.e[l + 1], mg.e[l], L.nf, L.pitch, c.lev[l + 1].pitch,
                        c.st, c.red, 0, 0);
   }
+  if (skip_up) return;  // the caller's k_quad_up does the up side
   if (kPairs && ntiled % 2 == 1) {
     if constexpr (kPairs) {
       if (ntiled >= 3) {
@@ -254,6 +278,18 @@ static void vcycle_tail_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int check
   }
 }
 
+template <int NU>
+static void launch_quad_up(const LaunchCtx& c, const MGBuffers<float>& mg, const float* r, float* z,
+                           int kn, int count_iteration) {
+  const dim3 pblock(32, kPairThreads / 32);
+  launch_timed(c.hook, kTimeUp0, k_quad_up<NU>, ptiles(c.lev[2].nf), pblock, c.stream, r,
+               (const float*)mg.u[0], (const float*)mg.f[1], (const float*)mg.u[1],
+               (const float*)mg.f[2], (const float*)mg.u[2], (const float*)mg.f[3],
+               (const float*)mg.u[3], (const float*)mg.f[4], c.dst_S, c.dst_lam, z, c.lev[0].nf,
+               c.lev[0].pitch, c.lev[1].pitch, c.lev[2].pitch, c.lev[3].pitch, c.lev[4].pitch,
+               c.st, c.red, kn, count_iteration);
+}
+
 template <typename T, int NU>
 static void pcg_init_nu(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, T* z) {
   const Level& L = c.lev[0];
@@ -269,7 +305,12 @@ static void pcg_init_nu(const LaunchCtx& c, const MGBuffers<T>& mg, const T* r, 
   } else {
     down0(k_mg_down<T, NU, false, kTile, false>);
   }
-  vcycle_tail_nu<T, NU>(c, mg, 0);
+  const bool quad = quad_up<T>(c);
+  vcycle_tail_nu<T, NU>(c, mg, 0, quad);
+  if (quad) {
+    if constexpr (sizeof(T) == 4) launch_quad_up<NU>(c, mg, r, z, 0, 0);
+    return;
+  }
   hipLaunchKernelGGL((k_mg_up<T, NU, true>), tiles(L.nf), tblock(), 0, c.stream, r, mg.u[0],
                      mg.e[1], z, L.nf, L.pitch, c.lev[1].pitch, c.st, c.red, 0, 0);
 }
@@ -327,7 +368,12 @@ static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x,
     down0(k_mg_down<T, NU, true, kTile, false>);
   }
   if (update_only) return;  // the refinement residual that follows takes the run's test
-  vcycle_tail_nu<T, NU>(c, mg, 1);
+  const bool quad = quad_up<T>(c);
+  vcycle_tail_nu<T, NU>(c, mg, 1, quad);
+  if (quad) {
+    if constexpr (sizeof(T) == 4) launch_quad_up<NU>(c, mg, r_new, z, k + 1, 1);
+    return;
+  }
   launch_timed(c.hook, kTimeUp0, k_mg_up<T, NU, true>, tiles(L.nf), tblock(), c.stream,
                (const T*)r_new, (const T*)mg.u[0], (const T*)mg.e[1], z, L.nf, L.pitch,
                c.lev[1].pitch, c.st, c.red, k + 1, 1);

@@ -1299,6 +1299,190 @@ __device__ __forceinline__ void d_triple_up(
   }
 }
 
+// The whole up side of an FP32 V-cycle whose tiled levels are 1 (the finest's first coarse
+// level), 2 and 3, with the coarse level 4 solved by sine transforms, in one launch: every
+// 1024-thread block solves level 4 (as d_triple_up), then corrects and smooths levels 3, 2 and 1
+// on windows whose valid parts cover the coarse patch each finer window interpolates from, and
+// finally does the finest level as the CG up kernel does (u_0 = u_0,pre + P e_1, 2 nu half-sweeps,
+// z stored, the dots r.z and z.A z) on a 64 x 64 tile.  It replaces d_triple_up and the finest
+// up kernel (one launch and one inter-kernel gap fewer per V-cycle).  Every value sees the same
+// operations as in the separate kernels; the dots are formed per 32 x 32 sub-tile and stored at
+// the index the finest up kernel's tile would use, so the down kernel reads the same number of
+// partials (their values sum the same products in another order).
+template <int NU>
+struct QuadUp {
+  static constexpr int H0 = 2 * NU + 1;            // finest halo (z valid one beyond the tile)
+  static constexpr int T0 = 4 * kPairTile;         // finest tile edge (64)
+  static constexpr int W0 = T0 + 2 * H0;           // finest window
+  static constexpr int CW0 = W0 / 2 + 2;           // its coarse patch (valid part of level 1)
+  static constexpr int H = 2 * NU;                 // halo of the coarser up windows
+  static constexpr int W1 = CW0 + 2 * H + ((CW0 + 2 * H) & 1);   // even: sweeps take pairs
+  static constexpr int CW1 = W1 / 2 + 2;
+  static constexpr int W2 = CW1 + 2 * H + ((CW1 + 2 * H) & 1);
+  static constexpr int CW2 = W2 / 2 + 2;
+  static constexpr int W3 = CW2 + 2 * H + ((CW2 + 2 * H) & 1);
+  static constexpr int N0 = (W0 * W0 + kPairThreads - 1) / kPairThreads;
+  static constexpr int N1 = (W1 * W1 + kPairThreads - 1) / kPairThreads;
+  static constexpr int N2 = (W2 * W2 + kPairThreads - 1) / kPairThreads;
+  static constexpr int N3 = (W3 * W3 + kPairThreads - 1) / kPairThreads;
+  static_assert(2 * W0 * (W0 + 1) <= 3 * kDstN * kDstP, "the finest windows fit the DST arrays");
+};
+
+// A window of an up kernel with kPairThreads threads: f and u_pre into registers (zero outside
+// the grid), all loads issued before any is used.
+template <int N, int W>
+__device__ __forceinline__ void up_window_load(float (&fr)[N], float (&ur)[N], int t, int ib,
+                                               int jb, int nf, int pitch,
+                                               const float* __restrict__ fin,
+                                               const float* __restrict__ upre) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const int c = t + kPairThreads * q;
+    const int i = ib + c % W, j = jb + c / W;
+    const bool in = c < W * W && i >= 1 && i <= nf && j >= 1 && j <= nf;
+    const unsigned o = (__umul24(j - 1, pitch) + (i - 1));
+    fr[q] = in ? ldg(fin, o) : 0.f;
+    ur[q] = in ? ldg(upre, o) : 0.f;
+  }
+}
+
+// u = u_pre + P e on a window (e from the coarser level's values coarse(J - cjb, I - cib), valid
+// there), f and u into LDS.
+template <int N, int W, typename C>
+__device__ __forceinline__ void up_window_init(float (*sf)[W + 1], float (*su)[W + 1],
+                                               const float (&fr)[N], const float (&ur)[N], int t,
+                                               int ib, int jb, int nf, const C& coarse, int cib,
+                                               int cjb) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const int c = t + kPairThreads * q;
+    if (c >= W * W) continue;
+    const int lj = c / W, li = c % W;
+    const int i = ib + li, j = jb + lj;
+    float u = 0.f;
+    if (i >= 1 && i <= nf && j >= 1 && j <= nf) {
+      const int ci = (i >> 1) - cib, cj = (j >> 1) - cjb;
+      const float e = 0.5f * (coarse(cj, ci) + coarse(cj + (j & 1), ci + (i & 1)));
+      u = ur[q] + e;
+    }
+    sf[lj][li] = fr[q];
+    su[lj][li] = u;
+  }
+  __syncthreads();
+}
+
+template <int NU>
+__device__ __forceinline__ void d_quad_up(
+    const float* __restrict__ f0, const float* __restrict__ u0pre, const float* __restrict__ f1,
+    const float* __restrict__ u1pre, const float* __restrict__ f2, const float* __restrict__ u2pre,
+    const float* __restrict__ f3, const float* __restrict__ u3pre, const float* __restrict__ f4,
+    const float* __restrict__ Sg, const float* __restrict__ lamg, float* __restrict__ z,
+    int nf0, int p0, int p1, int p2, int p3, int p4, DevState* st, const Reductions& red, int kn,
+    int count_iteration, int tile_x, int tile_y, bool lead) {
+  using T = float;
+  using G = QuadUp<NU>;
+  constexpr int H0 = G::H0, H = G::H, W0 = G::W0, W1 = G::W1, W2 = G::W2, W3 = G::W3;
+  constexpr int TT = G::T0;
+  static_assert(kPairThreads == 1024, "16 waves");
+  // the sine-transform arrays; after the coarse solve they hold the finest level's windows
+  __shared__ float sdst[3 * kDstN * kDstP];
+  __shared__ float sl[kDstN];
+  __shared__ float se[kDstN + 1][kDstN + 2];  // e_4 by coarse index, zero ring
+  __shared__ T sf1[W1][W1 + 1];
+  __shared__ T su1[W1][W1 + 1];
+  __shared__ T sf2[W2][W2 + 1];
+  __shared__ T su2[W2][W2 + 1];
+  __shared__ T sf3[W3][W3 + 1];
+  __shared__ T su3[W3][W3 + 1];
+  __shared__ double sdot[kPairThreads / 64][8];
+  float* sS = sdst;
+  float* sX = sdst + kDstN * kDstP;
+  float* sY = sdst + 2 * kDstN * kDstP;
+  auto sf0 = reinterpret_cast<T(*)[W0 + 1]>(sdst);
+  auto su0 = reinterpret_cast<T(*)[W0 + 1]>(sdst + W0 * (W0 + 1));
+  const int t = flat_tid();
+  __builtin_assume(t >= 0 && t < kPairThreads);
+  const int nf1 = (nf0 - 1) >> 1, nf2 = (nf1 - 1) >> 1, nf3 = (nf2 - 1) >> 1, m = (nf3 - 1) >> 1;
+  const int i0 = tile_x * TT, j0 = tile_y * TT;
+  const int ib0 = i0 + 1 - H0, jb0 = j0 + 1 - H0;           // finest window origin
+  const int ib1 = (ib0 >> 1) - H, jb1 = (jb0 >> 1) - H;     // level-1 window (floor shifts)
+  const int ib2 = (ib1 >> 1) - H, jb2 = (jb1 >> 1) - H;
+  const int ib3 = (ib2 >> 1) - H, jb3 = (jb2 >> 1) - H;
+  DstIn din;
+  dst_load(din, f4, p4, m, Sg, lamg, t);
+  T f3r[G::N3], u3r[G::N3], f2r[G::N2], u2r[G::N2], f1r[G::N1], u1r[G::N1], f0r[G::N0], u0r[G::N0];
+  up_window_load<G::N3, W3>(f3r, u3r, t, ib3, jb3, nf3, p3, f3, u3pre);
+  up_window_load<G::N2, W2>(f2r, u2r, t, ib2, jb2, nf2, p2, f2, u2pre);
+  up_window_load<G::N1, W1>(f1r, u1r, t, ib1, jb1, nf1, p1, f1, u1pre);
+  up_window_load<G::N0, W0>(f0r, u0r, t, ib0, jb0, nf0, p0, f0, u0pre);
+  // the coarse solve into se (zero ring)
+  for (int c = t; c < (kDstN + 1) * (kDstN + 2); c += kPairThreads) (&se[0][0])[c] = 0.f;
+  dst_solve<false>(din, sS, sX, sY, sl, m, t, &se[0][0], kDstN + 2, 1);
+  __syncthreads();
+  // each level: u = u_pre + P e from the coarser level's (valid) values, then 2 nu half-sweeps
+  up_window_init<G::N3, W3>(sf3, su3, f3r, u3r, t, ib3, jb3, nf3,
+                            [&](int a, int b) { return se[a][b]; }, 0, 0);
+  tile_sweeps<T, W3, 2 * NU, kPairThreads>(su3, sf3, ib3, jb3, nf3, false);  // black, red, ...
+  up_window_init<G::N2, W2>(sf2, su2, f2r, u2r, t, ib2, jb2, nf2,
+                            [&](int a, int b) { return su3[a][b]; }, ib3, jb3);
+  tile_sweeps<T, W2, 2 * NU, kPairThreads>(su2, sf2, ib2, jb2, nf2, false);
+  up_window_init<G::N1, W1>(sf1, su1, f1r, u1r, t, ib1, jb1, nf1,
+                            [&](int a, int b) { return su2[a][b]; }, ib2, jb2);
+  tile_sweeps<T, W1, 2 * NU, kPairThreads>(su1, sf1, ib1, jb1, nf1, false);
+  up_window_init<G::N0, W0>(sf0, su0, f0r, u0r, t, ib0, jb0, nf0,
+                            [&](int a, int b) { return su1[a][b]; }, ib1, jb1);
+  tile_sweeps<T, W0, 2 * NU, kPairThreads>(su0, sf0, ib0, jb0, nf0, false);
+  // z on the own cells; r.z and z.A z per 32 x 32 sub-tile (sub-tile column by lane half, row by
+  // slot half: thread t covers cells (t % 64, t / 64 + 16 q))
+  double dz[2][2] = {{0.0, 0.0}, {0.0, 0.0}};   // [sub-tile row][r.z, z.A z]
+#pragma unroll
+  for (int q = 0; q < TT * TT / kPairThreads; ++q) {
+    const int c = t + kPairThreads * q;
+    const int bi = c % TT, bj = c / TT;
+    const int i = i0 + 1 + bi, j = j0 + 1 + bj;
+    if (j > nf0 || i > nf0) continue;
+    const int lj = bj + H0, li = bi + H0;
+    const T zv = su0[lj][li];
+    stg(z, (__umul24(j - 1, p0) + (i - 1)), zv);
+    const T wv = T(4) * zv - su0[lj][li - 1] - su0[lj][li + 1] - su0[lj - 1][li] - su0[lj + 1][li];
+    const int sy = q >= (TT * TT / kPairThreads) / 2 ? 1 : 0;
+    dz[sy][0] += (double)sf0[lj][li] * (double)zv;
+    dz[sy][1] += (double)zv * (double)wv;
+  }
+  // each half-wave (32 lanes) holds one sub-tile column: reduce within halves, fixed order
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+      for (int o = 16; o > 0; o >>= 1) dz[a][b] += __shfl_down(dz[a][b], o, 32);
+  const int lane = t & 63, w = t >> 6;
+  if ((lane & 31) == 0) {
+    const int sx = lane >> 5;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) sdot[w][(a * 2 + sx) * 2 + b] = dz[a][b];
+  }
+  __syncthreads();
+  if (t < 8) {
+    double v = 0.0;
+    for (int q = 0; q < kPairThreads / 64; ++q) v += sdot[q][t];
+    const int sub = t >> 1, b = t & 1;           // sub = sy * 2 + sx
+    const int sx = sub & 1, sy = sub >> 1;
+    const int nbx = (nf0 + kTile - 1) / kTile;   // the finest up kernel's tiles per row
+    const int tx = 2 * tile_x + sx, ty = 2 * tile_y + sy;
+    if (tx < nbx && ty < nbx) {
+      double* dst = b == 0 ? ((kn & 1) ? red.rz[1] : red.rz[0]) : ((kn & 1) ? red.zw[1] : red.zw[0]);
+      stg(dst, (unsigned)(ty * nbx + tx), v);
+    }
+  }
+  if (count_iteration && lead && thread0()) {
+    st->inner_its += 1;
+    st->pcg_k += 1;
+    st->run_its_max = max(st->run_its_max, st->pcg_k);
+  }
+}
+
 // --------------------------------------------------------------------------------------------
 // FP64 residual of the interior solve (iterative refinement)
 // --------------------------------------------------------------------------------------------
