@@ -230,6 +230,33 @@ def test_solve_3d_n64_true_residual():
     assert st["true_rel_res"] <= 1e-7
 
 
+def test_solve_3d_n64_against_golden():
+    # n = 64 against the oracle's sparse-LU solution written by tests/golden/make_3d_n64.py
+    # (4096 seeded entries and the norm): the outer rtol 1e-10 bar of the smaller sizes
+    import json
+    import os
+    G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "solve_3d_n64.json")))
+    n, K, mu = G["n"], G["K"], G["mu"]
+    print(f"[3d solve] n={n} against the stored oracle solution", flush=True)
+    P = make3(n, K, mu)
+    TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+    TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+    b = workloads.rhs(3, n, 3064)
+    x = torch.zeros_like(dev(b))
+    st = P.solve(TP, TH, dev(b), x, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12,
+                                                   check_true_residual=1))
+    xh = host(x)
+    idx = np.array(G["indices"])
+    ref = np.array(G["values"])
+    err = float(np.linalg.norm(xh[idx] - ref) / np.linalg.norm(ref))
+    nerr = abs(np.linalg.norm(xh) - G["norm_x"]) / G["norm_x"]
+    print(f"  sampled rel err {err:.2e} norm rel err {nerr:.2e} outer {st['outer_its']} "
+          f"res {st['true_rel_res']:.2e}", flush=True)
+    assert len(xh) == G["N"]
+    assert err <= 1e-8 and nerr <= 1e-8
+    assert st["true_rel_res"] <= 1e-9
+
+
 @pytest.mark.parametrize("precision", [F.FDD_MIXED, F.FDD_FP64])
 def test_solve_3d_graph_replay_matches_eager_launches(precision):
     # the captured iteration chunks and the eager launches run the same kernels in the same
