@@ -312,6 +312,27 @@ void enqueue_inner_more(fdd_problem_s* P, const LaunchCtx& c, InnerTrack& t, int
 }
 
 int read_state(fdd_problem_s* P, hipStream_t s) {
+  if (P->host_seq && P->hook.kind == kTimeNone) {
+    // the state is published by a kernel behind the queued work; the host waits for its
+    // sequence word (no stream synchronization), checking the stream for errors now and then
+    // and falling back to a synchronization after a second
+    const unsigned seq = ++P->pub_seq;
+    launch_publish_state(s, P->st, P->host_st, P->host_seq, seq);
+    HIPCHK(hipGetLastError());
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned long spin = 0;; ++spin) {
+      if (__atomic_load_n(P->host_seq, __ATOMIC_ACQUIRE) == seq) return FDD_OK;
+      if ((spin & 4095) == 4095) {
+        const hipError_t q = hipStreamQuery(s);
+        if (q != hipSuccess && q != hipErrorNotReady)
+          return fail(FDD_E_HIP, "device state read-back: %s", hipGetErrorString(q));
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(1)) break;
+      }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (__atomic_load_n(P->host_seq, __ATOMIC_ACQUIRE) == seq) return FDD_OK;
+    return fail(FDD_E_HIP, "device state read-back: the published state did not arrive");
+  }
   HIPCHK(hipMemcpyAsync(P->host_st, P->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   // harvest the kernel timer: every recorded pair has completed
@@ -556,6 +577,11 @@ int fdd_bind_workspace(fdd_problem P, void* dev, size_t bytes, void* stream) {
   P->ws_bytes = bytes;
   plan_workspace(P, P->ws);
   if (!P->host_st) HIPCHK(hipHostMalloc((void**)&P->host_st, sizeof(DevState), hipHostMallocDefault));
+  if (!P->host_seq) {
+    HIPCHK(hipHostMalloc((void**)&P->host_seq, sizeof(unsigned), hipHostMallocDefault));
+    *P->host_seq = 0;
+    P->pub_seq = 0;
+  }
   HIPCHK(hipMemsetAsync(P->ws, 0, need, s));
   const size_t np = P->cinv.size();
   HIPCHK(hipMemcpyAsync(P->cinv64, P->cinv.data(), np * sizeof(double), hipMemcpyHostToDevice, s));
@@ -1078,6 +1104,7 @@ void fdd_destroy_problem(fdd_problem P) {
   if (P->ev_in) (void)hipEventDestroy(P->ev_in);
   if (P->ev_out) (void)hipEventDestroy(P->ev_out);
   if (P->host_st) (void)hipHostFree(P->host_st);
+  if (P->host_seq) (void)hipHostFree(P->host_seq);
   delete P;
 }
 

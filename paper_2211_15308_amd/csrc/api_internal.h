@@ -127,6 +127,8 @@ struct fdd_problem_s {
   double* scratchP = nullptr;
   double* scratchH = nullptr;
   DevState* host_st = nullptr;  // pinned copy
+  unsigned* host_seq = nullptr;  // pinned word: sequence number of the last published state
+  unsigned pub_seq = 0;
   // inner schedule (refinement steps x PCG iterations, or FP64 PCG iterations); only grows
   // one schedule per (smoother sweeps, per-step reduction); `sc` is the current one
   // launch schedules by (mg_nu, step_rtol (0 in FP64), right-hand-side kind)

@@ -193,6 +193,10 @@ constexpr int kStaticPrecondSystems = kMaxPoles + 1;
 constexpr int kStaticPrecondN = 2048;
 constexpr int kMaxStaticDevices = 64;
 int static_precond_scratch(int device, double** out);
+// Copies *st into pinned host memory `host` and then stores `seq` into the pinned word
+// `seq_word` (one small kernel; the host waits for the word instead of a stream synchronization).
+void launch_publish_state(hipStream_t s, const DevState* st, DevState* host, unsigned* seq_word,
+                          unsigned seq);
 
 void launch_iface_batch(hipStream_t s, int ng, double h, const ShiftTable& tab, int mode,
                         const double* in, double* out, double* scratch, DevState* st,

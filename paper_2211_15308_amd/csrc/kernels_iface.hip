@@ -182,6 +182,27 @@ int static_precond_scratch(int device, double** out) {
 
 // ---- launchers ----------------------------------------------------------------------------
 
+// Hands the device state to the host without a stream synchronization: copies it into pinned
+// host memory, makes the stores visible system-wide, then writes the sequence word the host is
+// waiting for (release order: the state before the word).
+__global__ __launch_bounds__(64) void k_publish_state(const DevState* __restrict__ st,
+                                                      DevState* __restrict__ host,
+                                                      unsigned* __restrict__ seq_word,
+                                                      unsigned seq) {
+  constexpr int kWords = (int)(sizeof(DevState) / sizeof(unsigned));
+  const unsigned* src = reinterpret_cast<const unsigned*>(st);
+  unsigned* dst = reinterpret_cast<unsigned*>(host);
+  for (int w = threadIdx.x; w < kWords; w += 64) dst[w] = src[w];
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __atomic_store_n(seq_word, seq, __ATOMIC_RELEASE);
+}
+
+void launch_publish_state(hipStream_t s, const DevState* st, DevState* host, unsigned* seq_word,
+                          unsigned seq) {
+  hipLaunchKernelGGL(k_publish_state, dim3(1), dim3(64), 0, s, st, host, seq_word, seq);
+}
+
 void launch_iface_batch(hipStream_t s, int ng, double h, const ShiftTable& tab, int mode,
                         const double* in, double* out, double* scratch, DevState* st,
                         const double* p_prev, double* p_next, int ver, int first) {
