@@ -45,7 +45,8 @@ linear vector fields (mass, divergence and boundary terms against closed-form in
 divergence theorem per triangle, nestedness (the Galerkin product of the inclusion reproduces the
 coarse matrices, and linear fields are carried over exactly), second-order convergence to a manufactured solution, the closed
 form of the loop spectrum, consistency of L on smooth periodic functions, the Schur complement
-identity and bounded condition numbers of S_Gamma^{-1} S over h and gamma
+identity, bounded condition numbers of S_Gamma^{-1} S over h and gamma, and the agreement of the
+dense and the Fourier-mode application of the preconditioner
 (tests/test_oracle_hdiv.py).
 """
 import numpy as np
@@ -390,3 +391,40 @@ def ra_precond(L, M, table):
     for dk, qk in zip(d, q):
         out = out - dk * qk * np.linalg.inv(L + qk * M)
     return out
+
+
+def loop_symbols(n, sigma=SIGMA):
+    """The 2 x 2 blocks of L on the loop (own segment, previous segment; the next one is the
+    transpose) and of M_Q, as the closed-form spectrum uses them."""
+    h = 1.0 / n
+    Ms = (h / 6) * np.array([[2.0, 1.0], [1.0, 2.0]])
+    own = Ms + (1.0 / h) * np.array([[1.0, -1.0], [-1.0, 1.0]])
+    ja, jb = np.array([0.0, 1.0]), np.array([-1.0, 0.0])
+    da = db = np.array([-0.5, 0.5]) / h
+
+    def vert(dr, jr, dc, jc):
+        return -(np.outer(dr, jc) + np.outer(jr, dc)) + (sigma / h) * np.outer(jr, jc)
+    own = own + vert(db, jb, db, jb) + vert(da, ja, da, ja)
+    prev = vert(db, jb, da, ja)
+    return own, prev, Ms
+
+
+def ra_precond_apply_fft(n, table, r, sigma=SIGMA):
+    """The preconditioner of ra_precond applied to r by the discrete Fourier transform over the 4n
+    loop segments (L and M_Q are block circulant): per mode theta the 2 x 2 symbol
+    S = own + prev e^{-i theta} + prev^T e^{i theta}, and
+    z_hat = (d0 Ms^-1 S Ms^-1 + (sum d) Ms^-1 - sum d_k q_k (S + q_k Ms)^-1) r_hat."""
+    d0, d, q = table
+    m = 4 * n
+    own, prev, Ms = loop_symbols(n, sigma)
+    th = 2.0 * np.pi * np.arange(m) / m
+    S = (own[None] + prev[None] * np.exp(-1j * th)[:, None, None]
+         + prev.T[None] * np.exp(1j * th)[:, None, None])
+    Msi = np.linalg.inv(Ms)
+    R = np.fft.fft(np.asarray(r, dtype=float).reshape(m, 2), axis=0)
+    op = d0 * (Msi[None] @ S @ Msi[None]) + float(np.sum(d)) * Msi[None]
+    for dk, qk in zip(d, q):
+        op = op - dk * qk * np.linalg.inv(S + qk * Ms[None])
+    Z = np.einsum("qab,qb->qa", op, R)
+    return np.fft.ifft(Z, axis=0).real.reshape(-1)
+

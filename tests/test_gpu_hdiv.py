@@ -65,6 +65,24 @@ def test_operator_and_preconditioner_match_oracle(n, K, gamma):
     assert rel(host(z2), M.exact_precond() @ r) <= 2 * err + 1e-11
 
 
+@pytest.mark.parametrize("n,K,gamma", [(256, 1.0, 1e-3), (1024, 1.0, 1.0), (1024, 1e-2, 1e3)])
+def test_preconditioner_large_matches_fourier_oracle(n, K, gamma):
+    # up to the largest loop (4n = 4096 segments: the cyclic reduction's LDS limit) against the
+    # oracle's Fourier-mode application of the same table (pinned to the dense one)
+    print(f"[hdiv precond large] n={n} K={K} gamma={gamma}", flush=True)
+    P = F.setup_hdiv(n, K, gamma)
+    P.bind_workspace()
+    T = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+    q = T.query()
+    tab = (q["c0"], np.array(q["c"]), np.array(q["p"]))
+    r = np.random.default_rng(n + 5).standard_normal(P.NG)
+    z = torch.zeros(P.NG, dtype=torch.float64, device="cuda")
+    P.precond_apply(T, dev(r), z)
+    err = rel(host(z), hdiv.ra_precond_apply_fft(n, tab, r))
+    print(f"[hdiv precond large] {q['m']} poles, rel err {err:.2e}", flush=True)
+    assert err <= 1e-11
+
+
 @pytest.mark.parametrize("n,nu", [(4, 1), (8, 1), (32, 1), (32, 2), (128, 1)])
 def test_interior_solve_matches_oracle(n, nu):
     print(f"[hdiv interior] n={n} nu={nu}", flush=True)

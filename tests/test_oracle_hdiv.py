@@ -277,3 +277,17 @@ def test_schur_pcg_matches_direct(K, gamma):
     assert rel(x, P.solve_splu(b)) < 1e-9
     assert rel(P.solve_dense(b), P.solve_splu(b)) < 1e-12
     assert its <= 30
+
+
+@pytest.mark.parametrize("n,K,gamma", [(4, 1.0, 1.0), (8, 1e-2, 1e3), (8, 1.0, 0.0)])
+def test_fft_preconditioner_matches_dense(n, K, gamma):
+    # the block-circulant (Fourier-mode) application used at sizes beyond the dense oracle
+    P = hdiv.HdivProblem(n, K, gamma)
+    lam = hdiv.loop_eigs(n)
+    tab = aaa.ra_table(P.g_table_function(), lam[0], lam[-1], 1e-12, extra=lam)
+    r = np.random.default_rng(n).standard_normal(P.NG)
+    z = hdiv.ra_precond_apply_fft(n, tab, r)
+    assert rel(z, hdiv.ra_precond(P.L, P.M_Q, tab) @ r) < 1e-12
+    own, prev, Ms = hdiv.loop_symbols(n)
+    assert np.max(np.abs(P.L[2:4, 2:4] - own)) < 1e-12 and np.max(np.abs(P.L[2:4, 0:2] - prev)) < 1e-12
+
