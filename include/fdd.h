@@ -276,6 +276,86 @@ int fdd_dd_precond_apply(fdd_problem prob, fdd_ratpc P, const double* r, double*
 int fdd_solve_full(fdd_problem prob, fdd_ratpc P, fdd_ratpc H, const double* b, double* x,
                    const fdd_opts* opts, void* stream, fdd_stats* stats);
 
+/* ---- the Darcy-Stokes outer solver (Sec. 4, eq. (darcy_stokes), eq. (darcy_stokes_precond)) --
+ * The coupled problem: Stokes velocity u and pressure p_S on Omega_S = (0,1) x (1,2), Darcy
+ * pressure p_D on Omega_D = (0,1)^2, interface Gamma = (0,1) x {1} with nu = (0,-1) (out of
+ * Omega_S); no slip on the Stokes sides x = 0, 1, zero traction on the Stokes top y = 2, p_D = 0
+ * on the rest of the Darcy boundary; on Gamma mass conservation u.nu + K grad p_D . nu = 0,
+ * normal stress balance -nu.sigma nu = p_D and the Beavers-Joseph-Saffman condition
+ * -P_nu(sigma nu) = alpha mu K^{-1/2} P_nu u, with sigma = mu grad u - p_S I.  Taylor-Hood P2-P1
+ * for Stokes and P1 for p_D on the diagonal-split meshes of n cells per side (matching on Gamma).
+ * Symmetric weak form (the Darcy equation multiplied by -1):
+ *     [A_u  B^T  C    ] [u  ]   A_u: mu int grad u : grad v + alpha mu K^{-1/2} int_Gamma u_x v_x
+ *     [B    0    0    ] [p_S]   B: -int q div v       C: int_Gamma q_D v.nu = -int_Gamma q_D v_y
+ *     [C^T  0    -K A_D] [p_D]   A_D: the facet problem's stiffness (fdd_setup_mesh, dim 2)
+ * Unknown order: u_x then u_y at the P2 nodes (A h/2, 1 + B h/2), A = 1..2n-1, B = 0..2n, index
+ * c (2n-1)(2n+1) + B (2n-1) + (A-1); p_S at the vertices (i h, 1 + j h), index Nu + j (n+1) + i;
+ * p_D in the facet problem's order (interior points row by row, Gamma last), index Nu + Np + k.
+ * Nu = 2 (2n-1)(2n+1), Np = (n+1)^2, ND = n (n-1).
+ *
+ * fdd_setup_darcy_stokes: host set-up of every matrix (and of the facet problem of the Darcy
+ * block, with the same n, K, mu); krylov = the FGMRES basis the workspace holds (iterations
+ * without restart).  fdd_problem_info gives N = Nu + Np + ND, N_I = Nu + Np, N_G = ND and the
+ * facet problem's spectral interval; fdd_build_rational_pc / fdd_ratpc_from_table on this problem
+ * build the facet problem's tables (the preconditioner's S_Gamma and the operator's H of the
+ * Darcy block); fdd_workspace_bytes / fdd_bind_workspace cover both parts; fdd_apply_operator
+ * (table NULL) applies the coupled operator above.  Host only.  Errors: FDD_E_ARG for n not a
+ * power of two in [8, 1024], K <= 0, mu <= 0, alpha < 0, non-finite values, or krylov outside
+ * [1, 400].                                                                                   */
+int fdd_setup_darcy_stokes(int n, double K, double mu, double alpha, int krylov, int hip_device,
+                           fdd_problem* out);
+int fdd_ds_sizes(fdd_problem prob, int64_t* Nu, int64_t* Np, int64_t* ND);
+
+/* Options of the outer solver and of the preconditioner's blocks (fdd_ds_opts_default fills
+ * the defaults given below). */
+typedef struct {
+  double rtol;            /* FGMRES: stop when ||b - A x_k||_2 <= rtol ||b||_2 (1e-10)         */
+  int maxit;              /* FGMRES iterations, capped by the problem's krylov (400)          */
+  double velocity_rtol;   /* A_u block: PCG with the P2 multigrid V-cycle to this relative
+                             residual (1e-12); 0: one V-cycle instead (the setting of Sec. 4) */
+  int velocity_maxit;     /* (100) */
+  int mg_nu;              /* smoothing steps of the velocity V-cycle, 1 or 2 (2)              */
+  double pressure_rtol;   /* mu^{-1} M_p block: Jacobi-PCG to this relative residual (1e-12)  */
+  int pressure_maxit;     /* (200) */
+  double darcy_rtol;      /* Darcy block: fdd_solve_full on the facet problem to this relative
+                             preconditioned residual (1e-5, the Appendix; Sec. 4: 1e-4)      */
+  int darcy_maxit;        /* (200) */
+  int darcy_precision;    /* FDD_FP64 (default) or FDD_MIXED: the Darcy PCG's V-cycles        */
+  int darcy_mg_nu;        /* (2) */
+  int check_true_residual; /* nonzero (default): ||b - A x|| / ||b|| of the returned x        */
+} fdd_ds_opts;
+
+typedef struct {
+  int status;
+  int its;                  /* FGMRES iterations                                             */
+  int velocity_its_total;   /* PCG iterations (or V-cycles) of the velocity block, summed     */
+  int velocity_its_max;
+  int pressure_its_total;
+  int darcy_its_total;      /* PCG iterations of the Darcy block, summed                      */
+  int darcy_its_max;
+  double rel_res;           /* FGMRES's least-squares residual / ||b||                        */
+  double true_rel_res;      /* ||b - A x||_2 / ||b||_2 if requested, else -1                  */
+  double t_solve_ms;        /* host wall time                                                 */
+} fdd_ds_stats;
+
+void fdd_ds_opts_default(fdd_ds_opts* opts);
+
+/* fdd_ds_precond_apply: z = B r, the block-diagonal preconditioner of eq. (darcy_stokes_precond)
+ *     B = diag(A_u, mu^{-1} M_p, K A_D + mu^{-1} T^T H T)^{-1},
+ * its blocks applied by the inner solves of the options (the Darcy block by the full-system PCG
+ * of fdd_solve_full with tables P and H).  r, z: device, length N.  Synchronizes the stream.
+ * fdd_ds_solve: x = A^{-1} b by flexible GMRES (right preconditioned by B, x_0 = 0, no restart,
+ * Arnoldi by classical Gram-Schmidt applied twice); stops when the least-squares residual
+ * ||b - A x_k||_2 <= rtol ||b||_2.  Returns FDD_NOT_CONVERGED after maxit iterations (x holds
+ * the last iterate), FDD_E_NONFINITE on non-finite values, and the errors of the inner solves.
+ * Synchronizes the stream at least once per iteration.
+ * Errors: FDD_E_ARG (not a Darcy-Stokes problem, null vector, invalid options), FDD_E_STATE
+ * (tables of another problem or kind), FDD_E_WORKSPACE (none bound).                          */
+int fdd_ds_precond_apply(fdd_problem prob, fdd_ratpc P, fdd_ratpc H, const double* r, double* z,
+                         const fdd_ds_opts* opts, void* stream, fdd_ds_stats* stats);
+int fdd_ds_solve(fdd_problem prob, fdd_ratpc P, fdd_ratpc H, const double* b, double* x,
+                 const fdd_ds_opts* opts, void* stream, fdd_ds_stats* stats);
+
 /* ---- batched solves -------------------------------------------------------------------------
  * Many independent problems of possibly different n, K, mu (and tables) solved together: the
  * same method as fdd_solve, applied to every instance, with each kernel launch covering all

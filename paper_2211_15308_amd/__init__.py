@@ -5,6 +5,7 @@ this package is its Python binding.
 """
 from .fdd import (FDD_E_ARG, FDD_E_BREAKDOWN, FDD_E_NONFINITE, FDD_E_RA, FDD_E_STATE,  # noqa: F401
                   FDD_E_WORKSPACE, FDD_FP64, FDD_MIXED, FDD_NOT_CONVERGED, FDD_OK, FDD_RA_OPERATOR,
-                  FDD_RA_PRECOND, Batch, Cnn, FddError, Problem, RationalTable, build_rational_pc,
-                  load, opts_default, pack_params, precond_apply, schur_apply, setup_hdiv, setup_mesh, setup_model, solve,
+                  FDD_RA_PRECOND, Batch, Cnn, DarcyStokes, FddError, Problem, RationalTable,
+                  build_rational_pc, ds_opts_default, load, opts_default, pack_params, precond_apply, schur_apply, setup_darcy_stokes, setup_hdiv, setup_mesh,
+                  setup_model, solve,
                   solve_batched, unpack_params)

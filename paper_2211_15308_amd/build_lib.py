@@ -10,7 +10,8 @@ OUT = os.path.join(HERE, "libfdd.so")
 
 SOURCES = ["kernels_mg.hip", "kernels_iface.hip", "kernels_batch.hip", "kernels_cnn.hip", "kernels_3d.hip",
            "kernels_full.hip", "kernels_model.hip", "ra_build.cpp", "api.cpp", "api_batch.cpp", "api_cnn.cpp", "api_3d.cpp",
-           "api_full.cpp", "api_model.cpp", "kernels_hdiv.hip", "hdiv_setup.cpp", "api_hdiv.cpp"]
+           "api_full.cpp", "api_model.cpp", "kernels_hdiv.hip", "hdiv_setup.cpp", "api_hdiv.cpp",
+           "ell_host.cpp", "ell_mg.cpp", "kernels_ds.hip", "ds_setup.cpp", "api_ds.cpp"]
 
 # Packed FP32 instructions are disabled in device code (see the project notes on gfx950).
 HIP_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -554,6 +554,10 @@ int fdd_workspace_bytes(fdd_problem P, const fdd_opts* o, size_t* bytes) {
     *bytes = hdiv_workspace_bytes(P);
     return FDD_OK;
   }
+  if (P->kind == kProblemDarcyStokes) {
+    *bytes = ds_workspace_bytes(P);
+    return *bytes ? FDD_OK : fail(FDD_E_ARG, "Darcy-Stokes workspace size unavailable");
+  }
   fdd_problem_s tmp = *P;
   *bytes = plan_workspace(&tmp, nullptr);
   return FDD_OK;
@@ -564,6 +568,7 @@ int fdd_bind_workspace(fdd_problem P, void* dev, size_t bytes, void* stream) {
   if (((uintptr_t)dev) & 255) return fail(FDD_E_WORKSPACE, "workspace must be 256-byte aligned");
   if (P->dim == 3) return bind3(P, dev, bytes, (hipStream_t)stream);
   if (P->kind == kProblemHdiv) return hdiv_bind(P, dev, bytes, (hipStream_t)stream);
+  if (P->kind == kProblemDarcyStokes) return ds_bind(P, dev, bytes, (hipStream_t)stream);
   fdd_problem_s tmp = *P;
   const size_t need = plan_workspace(&tmp, nullptr);
   if (bytes < need) return fail(FDD_E_WORKSPACE, "workspace %zu bytes < %zu needed", bytes, need);
@@ -688,6 +693,8 @@ int fdd_interior_solve(fdd_problem P, const double* f, double* u, const fdd_opts
                        void* stream, int* its) {
   int rc = check_problem(P);
   if (rc) return rc;
+  if (P->kind == kProblemDarcyStokes)
+    return fail(FDD_E_ARG, "the Darcy-Stokes problem is solved by fdd_ds_solve");
   if (!f || !u) return fail(FDD_E_ARG, "null vector");
   fdd_opts o;
   if (opts) o = *opts;
@@ -713,6 +720,8 @@ int fdd_interior_solve(fdd_problem P, const double* f, double* u, const fdd_opts
 int fdd_precond_apply(fdd_problem P, fdd_ratpc T, const double* r, double* z, void* stream) {
   int rc = check_problem(P);
   if (rc) return rc;
+  if (P->kind == kProblemDarcyStokes)
+    return fail(FDD_E_ARG, "the Darcy-Stokes problem is solved by fdd_ds_solve");
   if ((rc = check_table(P, T, FDD_RA_PRECOND))) return rc;
   if (!r || !z) return fail(FDD_E_ARG, "null vector");
   HIPCHK(hipSetDevice(P->device));
@@ -751,6 +760,8 @@ int fdd_schur_apply(fdd_problem P, fdd_ratpc H, const double* x, double* y, cons
                     void* stream) {
   int rc = check_problem(P);
   if (rc) return rc;
+  if (P->kind == kProblemDarcyStokes)
+    return fail(FDD_E_ARG, "the Darcy-Stokes problem is solved by fdd_ds_solve");
   if (P->kind == kProblemHdiv && H)
     return fail(FDD_E_ARG, "the H(div) problem takes no operator table (pass NULL)");
   if (P->kind != kProblemHdiv && (rc = check_table(P, H, FDD_RA_OPERATOR))) return rc;
@@ -783,15 +794,17 @@ int fdd_schur_apply(fdd_problem P, fdd_ratpc H, const double* x, double* y, cons
 int fdd_apply_operator(fdd_problem P, fdd_ratpc H, const double* x, double* y, void* stream) {
   int rc = check_problem(P);
   if (rc) return rc;
-  if (P->kind == kProblemHdiv && H)
-    return fail(FDD_E_ARG, "the H(div) problem takes no operator table (pass NULL)");
-  if (P->kind != kProblemHdiv && (rc = check_table(P, H, FDD_RA_OPERATOR))) return rc;
+  const bool no_table = P->kind == kProblemHdiv || P->kind == kProblemDarcyStokes;
+  if (no_table && H)
+    return fail(FDD_E_ARG, "this problem's operator has no fractional term (pass NULL)");
+  if (!no_table && (rc = check_table(P, H, FDD_RA_OPERATOR))) return rc;
   if (!x || !y) return fail(FDD_E_ARG, "null vector");
   HIPCHK(hipSetDevice(P->device));
   hipStream_t s = (hipStream_t)stream;
   if (P->dim == 3) return apply_operator3(P, H, x, y, s);
   if (P->kind == kProblemModel) return model_apply_operator(P, H, x, y, s);
   if (P->kind == kProblemHdiv) return hdiv_apply_operator(P, x, y, s);
+  if (P->kind == kProblemDarcyStokes) return ds_apply_operator(P, x, y, s);
   ShiftTable tab = make_table(H);
   launch_iface_batch(s, (int)P->NG, P->h, tab, kIfaceOperator, x + P->NI, P->Hp, P->scratchH,
                      P->st, nullptr, nullptr, 0, 0);
@@ -911,6 +924,8 @@ int fdd_solve(fdd_problem P, fdd_ratpc PT, fdd_ratpc HT, const double* b, double
   st.true_rel_res = -1.0;
   int rc = check_problem(P);
   if (rc) return rc;
+  if (P->kind == kProblemDarcyStokes)
+    return fail(FDD_E_ARG, "the Darcy-Stokes problem is solved by fdd_ds_solve");
   if ((rc = check_table(P, PT, FDD_RA_PRECOND))) return rc;
   if (P->kind == kProblemHdiv && HT)
     return fail(FDD_E_ARG, "the H(div) problem takes no operator table (pass NULL)");
@@ -1094,6 +1109,7 @@ void fdd_destroy_problem(fdd_problem P) {
   if (!P) return;
   destroy3(P);
   hdiv_destroy(P);
+  ds_destroy(P);
   if (P->hook.ev) {
     for (int i = 0; i < 2 * P->hook.cap; ++i) (void)hipEventDestroy(P->hook.ev[i]);
     delete[] P->hook.ev;

@@ -21,6 +21,7 @@
 #include <new>
 
 #include "api_internal.h"
+#include "ell_mg.h"
 #include "hdiv_internal.h"
 
 using namespace fdd;
@@ -29,71 +30,30 @@ namespace {
 
 constexpr double kTheta = 0.5;   // damping of the additive Schwarz smoother
 
-int read_hd(ProblemHdiv* Q, hipStream_t s) {
-  HIPCHK(hipMemcpyAsync(Q->hst, Q->st, sizeof(HdState), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  return FDD_OK;
+EllHier hier(const ProblemHdiv* Q) {
+  EllHier H;
+  H.lev = Q->lev;
+  H.nlev = Q->nlev;
+  H.cinv = Q->dcinv;
+  H.theta = Q->theta;
+  H.n0 = Q->N0;
+  H.r = Q->r;
+  H.z = Q->z;
+  H.p = Q->p;
+  H.q = Q->q;
+  H.partials = Q->partials;
+  H.st = Q->st;
+  H.hst = Q->hst;
+  return H;
 }
 
-// x = V b on level l (V(nu, nu) with x_0 = 0); kernels return at once once st->done is set
-void vcycle(const ProblemHdiv* Q, hipStream_t s, int nu, int l, const double* b, double* x,
-            const HdState* stop) {
-  const HdLevel& L = Q->lev[l];
-  if (l == Q->nlev - 1) {
-    launch_hd_coarse(s, Q->dcinv, L.n0, b, x, stop);
-    return;
-  }
-  const HdLevel& C = Q->lev[l + 1];
-  launch_hd_patch_solve(s, L, b, stop);
-  launch_hd_patch_sum(s, L, Q->theta, x, 0, stop);
-  for (int k = 1; k < nu; ++k) {
-    launch_hd_residual(s, view(L.A), b, x, L.r, stop);
-    launch_hd_patch_solve(s, L, L.r, stop);
-    launch_hd_patch_sum(s, L, Q->theta, x, 1, stop);
-  }
-  launch_hd_residual(s, view(L.A), b, x, L.r, stop);
-  launch_hd_spmv(s, view(L.R), L.r, C.b, 1.0, 0.0, stop);
-  vcycle(Q, s, nu, l + 1, C.b, C.x, stop);
-  launch_hd_spmv(s, view(L.P), C.x, x, 1.0, 1.0, stop);
-  for (int k = 0; k < nu; ++k) {
-    launch_hd_residual(s, view(L.A), b, x, L.r, stop);
-    launch_hd_patch_solve(s, L, L.r, stop);
-    launch_hd_patch_sum(s, L, Q->theta, x, 1, stop);
-  }
-}
+int read_hd(ProblemHdiv* Q, hipStream_t s) { return ell_read_state(hier(Q), s); }
 
 // A^00 u = f (f in Q->f, u into Q->u) to ||f - A^00 u|| <= inner_rtol ||f||.  As many iterations
 // as the last interior solve took are enqueued ahead of the read-back.
 int inner(ProblemHdiv* Q, hipStream_t s, const fdd_opts& o, int* its) {
-  const int n0 = Q->N0;
-  const HdLevel& L0 = Q->lev[0];
-  launch_hd_pcg_start(s, n0, Q->f, Q->u, Q->r, Q->partials, Q->st, o.inner_rtol * o.inner_rtol);
-  double* p[2] = {Q->p, Q->p + n0};
-  int k = 0, want = std::max(Q->its_hint, 2);
-  for (;;) {
-    for (; k < want && k < o.inner_maxit; ++k) {
-      vcycle(Q, s, o.mg_nu, 0, Q->r, Q->z, Q->st);
-      launch_hd_pcg_rz(s, n0, Q->r, Q->z, Q->partials, Q->st, k == 0);
-      launch_hd_pcg_pq(s, view(L0.A), Q->z, p[(k + 1) & 1], p[k & 1], Q->q, Q->partials, Q->st,
-                       k == 0);
-      launch_hd_pcg_update(s, n0, p[k & 1], Q->q, Q->u, Q->r, Q->partials, Q->st);
-    }
-    HIPCHK(hipGetLastError());
-    int rc = read_hd(Q, s);
-    if (rc) return rc;
-    const HdState& h = *Q->hst;
-    if (h.breakdown & 5)
-      return fail(h.breakdown & 4 ? FDD_E_NONFINITE : FDD_E_BREAKDOWN,
-                  "H(div) interior solve: breakdown (flags %d)", h.breakdown);
-    if (h.done) break;
-    if (k >= o.inner_maxit)
-      return fail(FDD_NOT_CONVERGED, "H(div) interior solve: %d iterations, residual %.3e of %.3e",
-                  k, std::sqrt(h.rr), std::sqrt(h.ff));
-    want = k + 2;
-  }
-  *its = Q->hst->its;
-  Q->its_hint = std::max(*its, 1);
-  return FDD_OK;
+  return ell_pcg(hier(Q), s, o.mg_nu, o.inner_rtol, o.inner_maxit, Q->f, Q->u, &Q->its_hint, its,
+                 "H(div) interior solve");
 }
 
 HdTable table_of(const fdd_ratpc_s* T) {

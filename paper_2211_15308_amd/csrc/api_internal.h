@@ -87,11 +87,13 @@ using fdd::kMaxLevels;
 struct Problem3D;  // the 3D solver's state (api_3d.cpp)
 namespace fdd {
 struct ProblemHdiv;  // the H(div) problem's state (hdiv_setup.cpp, api_hdiv.cpp)
+struct ProblemDS;    // the Darcy-Stokes problem's state (ds_setup.cpp, api_ds.cpp)
 }
 
 struct fdd_problem_s {
   int dim = 2, n = 0, device = 0;
-  int kind = 0;                 // fdd::kProblemFacet, kProblemModel (Gamma = the boundary) or kProblemHdiv
+  int kind = 0;                 // fdd::kProblemFacet, kProblemModel (Gamma = the boundary),
+                                // kProblemHdiv or kProblemDarcyStokes
   double tpow = -0.5;           // exponent t of the perturbation (the facet problems: -1/2)
   int model_its_hint = 0;       // iterations of the model problem's last interior solve
   double K = 1, mu = 1, gamma = 1, h = 1;
@@ -124,6 +126,7 @@ struct fdd_problem_s {
   double* lk_lmu = nullptr;     // {log10 K, log10 mu} for the warm-start network
   Problem3D* p3 = nullptr;      // dim = 3: everything of the 3D path
   fdd::ProblemHdiv* ph = nullptr;  // the H(div) problem: everything of its path
+  fdd::ProblemDS* pds = nullptr;   // the Darcy-Stokes problem: everything of its path
   double* scratchP = nullptr;
   double* scratchH = nullptr;
   DevState* host_st = nullptr;  // pinned copy
@@ -161,11 +164,15 @@ struct fdd_ratpc_s {
 
 namespace fdd {
 
-enum ProblemKind { kProblemFacet = 0, kProblemModel = 1, kProblemHdiv = 2 };
+enum ProblemKind { kProblemFacet = 0, kProblemModel = 1, kProblemHdiv = 2, kProblemDarcyStokes = 3 };
 
 ShiftTable make_table(const fdd_ratpc_s* t);
 // the paper's model problem in 2D (api_model.cpp)
 // the H(div) problem (api_hdiv.cpp)
+size_t ds_workspace_bytes(fdd_problem_s* P);
+int ds_bind(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s);
+void ds_destroy(fdd_problem_s* P);
+int ds_apply_operator(fdd_problem_s* P, const double* x, double* y, hipStream_t s);
 size_t hdiv_workspace_bytes(fdd_problem_s* P);
 int hdiv_bind(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s);
 void hdiv_destroy(fdd_problem_s* P);

@@ -15,11 +15,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <map>
-#include <string>
-#include <unordered_map>
 #include <vector>
 
+#include "ell_host.h"
 #include "hdiv_internal.h"
 
 namespace fdd {
@@ -134,111 +132,6 @@ Local local_fields(int n, int ci, int cj, int t) {
   return L;
 }
 
-// Rows of a matrix under assembly: at most `cap` (column, value) pairs per row.
-struct RowBuilder {
-  int rows, cap;
-  std::vector<int> cnt, col;
-  std::vector<double> val;
-  bool overflow = false;
-  RowBuilder(int r, int c) : rows(r), cap(c), cnt(r, 0), col((size_t)r * c), val((size_t)r * c) {}
-  bool add(int i, int j, double v) {
-    int* cs = &col[(size_t)i * cap];
-    double* vs = &val[(size_t)i * cap];
-    for (int k = 0; k < cnt[i]; ++k)
-      if (cs[k] == j) {
-        vs[k] += v;
-        return true;
-      }
-    if (cnt[i] == cap) {
-      overflow = true;
-      return false;
-    }
-    cs[cnt[i]] = j;
-    vs[cnt[i]] = v;
-    ++cnt[i];
-    return true;
-  }
-  // ELL form, columns ascending within a row, rows typed by their value sequence
-  void to_ell(HdMat* M, int ncols) const {
-    int w = 1;
-    for (int i = 0; i < rows; ++i) w = std::max(w, cnt[i]);
-    M->rows = rows;
-    M->cols = ncols;
-    M->width = w;
-    M->col.assign((size_t)rows * w, 0);
-    M->val.assign((size_t)rows * w, 0.0);
-    M->rtype.assign(rows, 0);
-    M->tval.clear();
-    std::unordered_map<std::string, int> types;
-    std::vector<std::pair<int, double>> tmp;
-    std::vector<double> vals(w);
-    for (int i = 0; i < rows; ++i) {
-      tmp.clear();
-      for (int k = 0; k < cnt[i]; ++k) tmp.emplace_back(col[(size_t)i * cap + k], val[(size_t)i * cap + k]);
-      std::sort(tmp.begin(), tmp.end());
-      for (int k = 0; k < w; ++k) {
-        const bool used = k < (int)tmp.size();
-        M->col[(size_t)k * rows + i] = used ? tmp[k].first : std::min(i, ncols - 1);
-        vals[k] = used ? tmp[k].second : 0.0;
-        M->val[(size_t)k * rows + i] = vals[k];
-      }
-      const std::string key((const char*)vals.data(), vals.size() * sizeof(double));
-      auto it = types.find(key);
-      int t;
-      if (it == types.end()) {
-        t = (int)types.size();
-        types.emplace(key, t);
-        M->tval.insert(M->tval.end(), vals.begin(), vals.end());
-      } else {
-        t = it->second;
-      }
-      M->rtype[i] = t;
-    }
-    M->ntypes = (int)types.size();
-  }
-};
-
-// Row i of an ELL matrix as (column, value) pairs (non-padding entries).
-double ell_entry(const HdMat& M, int i, int j) {
-  for (int k = 0; k < M.width; ++k) {
-    const size_t o = (size_t)k * M.rows + i;
-    if (M.col[o] == j && M.val[o] != 0.0) return M.val[o];
-  }
-  return 0.0;
-}
-
-// SPD inverse by Cholesky; false if not positive definite.
-bool spd_inverse(std::vector<double>& A, int m) {
-  std::vector<double> L((size_t)m * m, 0.0);
-  for (int j = 0; j < m; ++j) {
-    double d = A[(size_t)j * m + j];
-    for (int k = 0; k < j; ++k) d -= L[(size_t)j * m + k] * L[(size_t)j * m + k];
-    if (!(d > 0)) return false;
-    L[(size_t)j * m + j] = std::sqrt(d);
-    for (int i = j + 1; i < m; ++i) {
-      double v = A[(size_t)i * m + j];
-      for (int k = 0; k < j; ++k) v -= L[(size_t)i * m + k] * L[(size_t)j * m + k];
-      L[(size_t)i * m + j] = v / L[(size_t)j * m + j];
-    }
-  }
-  // inverse column by column: L L^T x = e_c
-  std::vector<double> inv((size_t)m * m), y(m);
-  for (int c = 0; c < m; ++c) {
-    for (int i = 0; i < m; ++i) {
-      double v = (i == c) ? 1.0 : 0.0;
-      for (int k = 0; k < i; ++k) v -= L[(size_t)i * m + k] * y[k];
-      y[i] = v / L[(size_t)i * m + i];
-    }
-    for (int i = m - 1; i >= 0; --i) {
-      double v = y[i];
-      for (int k = i + 1; k < m; ++k) v -= L[(size_t)k * m + i] * inv[(size_t)k * m + c];
-      inv[(size_t)i * m + c] = v / L[(size_t)i * m + i];
-    }
-  }
-  A = inv;
-  return true;
-}
-
 // Assembles K(mass + div-div) of level n: rows/cols below n0 only (interior == true: A^00), or
 // every dof plus gamma times the boundary mass of (u.nu)(v.nu) (the whole operator).
 void assemble(int n, double K, double gamma, bool interior, RowBuilder* rb) {
@@ -302,78 +195,27 @@ void build_prolongation(int n, HdLevel* fine) {
     }
   }
   rb.to_ell(&fine->P, n0c);
-  // R = P^T
-  std::vector<int> cnt(n0c, 0);
-  for (int k = 0; k < fine->P.width; ++k)
-    for (int i = 0; i < n0; ++i)
-      if (fine->P.val[(size_t)k * n0 + i] != 0.0) cnt[fine->P.col[(size_t)k * n0 + i]]++;
-  int w = 1;
-  for (int c : cnt) w = std::max(w, c);
-  RowBuilder rt(n0c, w);
-  for (int i = 0; i < n0; ++i)
-    for (int k = 0; k < fine->P.width; ++k) {
-      const double v = fine->P.val[(size_t)k * n0 + i];
-      if (v != 0.0) rt.add(fine->P.col[(size_t)k * n0 + i], i, v);
-    }
-  rt.to_ell(&fine->R, n0);
+  ell_transpose(fine->P, n0c, &fine->R);
 }
 
 // Vertex patches: the interior dofs on the edges incident to each vertex, ascending; patch
 // matrices deduplicated into types (congruent patches are bit-identical).
 const char* build_patches(HdLevel* L) {
   const int n = L->n, n0 = L->n0;
-  L->nvert = (n + 1) * (n + 1);
-  L->patch.assign((size_t)L->nvert * kHdPatch, -1);
-  L->ptype.assign(L->nvert, -1);
-  L->slot.assign((size_t)n0 * 2, -1);
-  std::vector<std::vector<double>> types;
-  std::vector<int> tsize;
   static const int nb[6][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {1, 1}};
-  for (int j = 0; j <= n; ++j)
-    for (int i = 0; i <= n; ++i) {
-      const int v = j * (n + 1) + i;
-      int dofs[kHdPatch], m = 0;
-      for (int k = 0; k < 6; ++k) {
-        const int bi = i + nb[k][0], bj = j + nb[k][1];
-        if (bi < 0 || bi > n || bj < 0 || bj > n) continue;
-        const int e = edge_between(n, i, j, bi, bj);
-        if (2 * e >= n0) continue;
-        dofs[m++] = 2 * e;
-        dofs[m++] = 2 * e + 1;
-      }
-      if (m == 0) continue;
-      std::sort(dofs, dofs + m);
-      std::vector<double> A((size_t)m * m);
-      for (int a = 0; a < m; ++a)
-        for (int b = 0; b < m; ++b) A[(size_t)a * m + b] = ell_entry(L->A, dofs[a], dofs[b]);
-      int t = -1;
-      for (size_t q = 0; q < types.size() && t < 0; ++q)
-        if (tsize[q] == m && std::memcmp(types[q].data(), A.data(), A.size() * sizeof(double)) == 0)
-          t = (int)q;
-      if (t < 0) {
-        if ((int)types.size() == kHdMaxTypes) return "too many distinct vertex patches";
-        types.push_back(A);
-        tsize.push_back(m);
-        t = (int)types.size() - 1;
-      }
-      L->ptype[v] = t;
-      for (int a = 0; a < m; ++a) {
-        L->patch[(size_t)v * kHdPatch + a] = dofs[a];
-        int* s = &L->slot[(size_t)dofs[a] * 2];
-        s[s[0] < 0 ? 0 : 1] = v * kHdPatch + a;
-      }
+  return build_patch_tables(L, (n + 1) * (n + 1), [&](int v, int* dofs) {
+    const int i = v % (n + 1), j = v / (n + 1);
+    int m = 0;
+    for (int k = 0; k < 6; ++k) {
+      const int bi = i + nb[k][0], bj = j + nb[k][1];
+      if (bi < 0 || bi > n || bj < 0 || bj > n) continue;
+      const int e = edge_between(n, i, j, bi, bj);
+      if (2 * e >= n0) continue;
+      dofs[m++] = 2 * e;
+      dofs[m++] = 2 * e + 1;
     }
-  L->ntypes = (int)types.size();
-  L->pinv.assign((size_t)L->ntypes * kHdPatch * kHdPatch, 0.0);
-  for (int t = 0; t < L->ntypes; ++t) {
-    std::vector<double> A = types[t];
-    const int m = tsize[t];
-    if (!spd_inverse(A, m)) return "a vertex patch matrix is not positive definite";
-    for (int a = 0; a < m; ++a)
-      for (int b = 0; b < m; ++b)
-        L->pinv[((size_t)t * kHdPatch + a) * kHdPatch + b] = A[(size_t)a * m + b];
-  }
-  return nullptr;
+    return m;
+  });
 }
 
 // Blocks of the trace operator on the loop (segment k holds u at its start and at its end):

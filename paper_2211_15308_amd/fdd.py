@@ -45,6 +45,8 @@ EXPORTED = [
     "fdd_cnn_create", "fdd_cnn_param_count", "fdd_cnn_workspace_bytes", "fdd_cnn_bind_workspace",
     "fdd_cnn_set_params", "fdd_cnn_forward", "fdd_cnn_loss", "fdd_cnn_backward",
     "fdd_cnn_adam_step", "fdd_cnn_destroy",
+    "fdd_setup_darcy_stokes", "fdd_ds_sizes", "fdd_ds_opts_default", "fdd_ds_precond_apply",
+    "fdd_ds_solve",
 ]
 FDD_KT_NONE, FDD_KT_DOWN0, FDD_KT_UP0, FDD_KT_COARSE = 0, 1, 2, 3
 
@@ -70,6 +72,26 @@ class FddStats(ctypes.Structure):
                 ("rel_precond_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
                 ("t_solve_ms", ctypes.c_double), ("warm_starts", ctypes.c_int),
                 ("warm_accepted", ctypes.c_int)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class FddDsOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("maxit", ctypes.c_int),
+                ("velocity_rtol", ctypes.c_double), ("velocity_maxit", ctypes.c_int),
+                ("mg_nu", ctypes.c_int), ("pressure_rtol", ctypes.c_double),
+                ("pressure_maxit", ctypes.c_int), ("darcy_rtol", ctypes.c_double),
+                ("darcy_maxit", ctypes.c_int), ("darcy_precision", ctypes.c_int),
+                ("darcy_mg_nu", ctypes.c_int), ("check_true_residual", ctypes.c_int)]
+
+
+class FddDsStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("its", ctypes.c_int),
+                ("velocity_its_total", ctypes.c_int), ("velocity_its_max", ctypes.c_int),
+                ("pressure_its_total", ctypes.c_int), ("darcy_its_total", ctypes.c_int),
+                ("darcy_its_max", ctypes.c_int), ("rel_res", ctypes.c_double),
+                ("true_rel_res", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -148,6 +170,14 @@ def load():
     lib.fdd_cnn_adam_step.argtypes = [P, V, V, V, V, F_, F_, F_, F_, I, V]
     lib.fdd_cnn_destroy.argtypes = [P]
     lib.fdd_cnn_destroy.restype = None
+    lib.fdd_setup_darcy_stokes.argtypes = [I, D, D, D, I, I, ctypes.POINTER(P)]
+    lib.fdd_ds_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(ctypes.c_int64)]
+    lib.fdd_ds_opts_default.argtypes = [ctypes.POINTER(FddDsOpts)]
+    lib.fdd_ds_opts_default.restype = None
+    lib.fdd_ds_precond_apply.argtypes = [P, P, P, V, V, ctypes.POINTER(FddDsOpts), V,
+                                         ctypes.POINTER(FddDsStats)]
+    lib.fdd_ds_solve.argtypes = [P, P, P, V, V, ctypes.POINTER(FddDsOpts), V, ctypes.POINTER(FddDsStats)]
     lib.fdd_last_error.restype = ctypes.c_char_p
     lib.fdd_version.restype = ctypes.c_char_p
     _lib = lib
@@ -362,6 +392,58 @@ class Problem:
             self.h = None
 
 
+def ds_opts_default(**kw):
+    o = FddDsOpts()
+    load().fdd_ds_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+class DarcyStokes(Problem):
+    """The coupled Darcy-Stokes problem of eq. (darcy_stokes) (fdd_setup_darcy_stokes): FGMRES
+    with the block-diagonal preconditioner of eq. (darcy_stokes_precond).  Rational tables are the
+    Darcy block's (the facet problem with the same n, K, mu)."""
+
+    def __init__(self, n, K, mu, alpha=0.0, krylov=200, device=0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.fdd_setup_darcy_stokes(n, K, mu, alpha, krylov, device, ctypes.byref(h)))
+        self.h = h
+        self.n, self.K, self.mu, self.dim = n, K, mu, 2
+        self.alpha, self.krylov = alpha, krylov
+        self.model_t, self.hdiv = None, False
+        self.device = device
+        self.workspace = None
+        N, NI, NG = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        _check(lib.fdd_problem_info(h, ctypes.byref(N), ctypes.byref(NI), ctypes.byref(NG),
+                                    ctypes.byref(lo), ctypes.byref(hi)))
+        self.N, self.NI, self.NG = N.value, NI.value, NG.value
+        self.lam_lo, self.lam_hi = lo.value, hi.value
+        nu, np_, nd = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.fdd_ds_sizes(h, ctypes.byref(nu), ctypes.byref(np_), ctypes.byref(nd)))
+        self.Nu, self.Np, self.ND = nu.value, np_.value, nd.value
+
+    def precond_apply(self, P, H, r, z, opts=None, stream=None):
+        """z = B r (fdd_ds_precond_apply); returns the inner counts."""
+        st = FddDsStats()
+        _check(load().fdd_ds_precond_apply(self.h, P.h, H.h, self._v(r, self.N, "r"), self._v(z, self.N, "z"),
+                                           ctypes.byref(opts or ds_opts_default()), _stream(stream),
+                                           ctypes.byref(st)))
+        return st.as_dict()
+
+    def solve(self, P, H, b, x, opts=None, stream=None, allow_not_converged=False):
+        """x = A^{-1} b by FGMRES (fdd_ds_solve)."""
+        st = FddDsStats()
+        rc = load().fdd_ds_solve(self.h, P.h, H.h, self._v(b, self.N, "b"), self._v(x, self.N, "x"),
+                                 ctypes.byref(opts or ds_opts_default()), _stream(stream), ctypes.byref(st))
+        _check(rc, (FDD_OK, FDD_NOT_CONVERGED) if allow_not_converged else (FDD_OK,))
+        return st.as_dict()
+
+
 class Batch:
     """A batch of set-up problems solved together (fdd_batch_create / fdd_solve_batched).
 
@@ -528,6 +610,11 @@ def setup_model(n, K, gamma, t, device=0):
 def setup_hdiv(n, K, gamma, device=0):
     """The H(div) problem of eq. (graddiv) (BDM1, Gamma = the whole boundary): fdd_setup_hdiv."""
     return Problem(n, K, gamma, 2, device, hdiv=True)
+
+
+def setup_darcy_stokes(n, K, mu, alpha=0.0, krylov=200, device=0):
+    """The coupled Darcy-Stokes problem of eq. (darcy_stokes): fdd_setup_darcy_stokes."""
+    return DarcyStokes(n, K, mu, alpha, krylov, device)
 
 
 def build_rational_pc(prob, which=FDD_RA_PRECOND, tol=1e-12, max_poles=64):

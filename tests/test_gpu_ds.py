@@ -1,0 +1,179 @@
+"""GPU parity of the Darcy-Stokes solver (Sec. 4 eq. (darcy_stokes), eq. (darcy_stokes_precond);
+Appendix) against the oracle (oracle/darcy_stokes.py).
+
+Both sides use the same rational tables for the Darcy block (the oracle's AAA, handed to the
+library with fdd_ratpc_from_table).  Tolerances:
+  * the coupled operator: 1e-13 relative (FP64 sums in another order);
+  * one preconditioner application: the velocity and pressure blocks at inner rtol 1e-13 within
+    1e-10 of the oracle's sparse LU; the Darcy block (PCG to 1e-5 with the lazy preconditioner,
+    FP64 V-cycles) within 1e-9 of the oracle's lazy PCG on the same tables, same iteration count;
+  * solves at rtol 1e-10: ||x - x_ref|| / ||x_ref|| <= 1e-8 against the oracle's sparse LU of the
+    whole system, FGMRES counts within two of the oracle's FGMRES with the same inexact blocks,
+    and the reported true residual equal to the oracle's residual of the returned x up to the
+    rounding of forming it.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import aaa, darcy_stokes as ds, spectral, system
+
+torch = pytest.importorskip("torch")
+F = pytest.importorskip("paper_2211_15308_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def tables(n, K, mu, tol=1e-12):
+    lo, hi = spectral.spectral_interval(2, n)
+    lam = spectral.interface_eigs_1d(n)
+    tp = aaa.ra_table(spectral.f_precond(K, 1.0 / mu), lo, hi, tol, extra=lam)
+    th = aaa.ra_table(spectral.g_operator, lo, hi, tol, extra=lam)
+    return tp, th
+
+
+def setup(n, K, mu, alpha, krylov=200, oracle=True):
+    P = F.setup_darcy_stokes(n, K, mu, alpha, krylov)
+    P.bind_workspace()
+    tp, th = tables(n, K, mu)
+    TP = P.ratpc_from_table(F.FDD_RA_PRECOND, tp[0], list(tp[1]), list(tp[2]))
+    TH = P.ratpc_from_table(F.FDD_RA_OPERATOR, th[0], list(th[1]), list(th[2]))
+    O = ds.DarcyStokes(n, K, mu, alpha) if oracle else None
+    return P, TP, TH, O, tp, th
+
+
+@pytest.mark.parametrize("n,K,mu,alpha", [(8, 1.0, 1.0, 3.0), (16, 1e-2, 1e-4, 3.0), (64, 1.0, 1e2, 0.0)])
+def test_operator_matches_oracle(n, K, mu, alpha):
+    print(f"[ds operator] n={n} K={K} mu={mu} alpha={alpha}", flush=True)
+    P, _, _, O, _, _ = setup(n, K, mu, alpha, krylov=4)
+    assert (P.N, P.Nu, P.Np, P.ND) == (O.N, O.Nu, O.Np, O.ND)
+    x = np.random.default_rng(n).standard_normal(O.N)
+    y = torch.zeros(O.N, dtype=torch.float64, device="cuda")
+    P.apply_operator(None, dev(x), y)
+    err = rel(host(y), O.A @ x)
+    print(f"[ds operator] rel err {err:.2e}", flush=True)
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("n,K,mu,alpha", [(8, 1.0, 1.0, 3.0), (32, 1e-2, 1e-4, 3.0), (64, 1.0, 1e-2, 0.0)])
+def test_precond_matches_oracle(n, K, mu, alpha):
+    print(f"[ds precond] n={n} K={K} mu={mu} alpha={alpha}", flush=True)
+    P, TP, TH, O, tp, th = setup(n, K, mu, alpha, krylov=4)
+    r = np.random.default_rng(10 + n).standard_normal(O.N)
+    z = torch.zeros(O.N, dtype=torch.float64, device="cuda")
+    st = P.precond_apply(TP, TH, dev(r), z, F.ds_opts_default(velocity_rtol=1e-13, pressure_rtol=1e-13,
+                                                              darcy_rtol=1e-5))
+    zh = host(z)
+    Nu, Np = O.Nu, O.Np
+    zu = spla.splu(O.A_u.tocsc()).solve(r[:Nu])
+    zp = O.mu * spla.splu(O.M_p.tocsc()).solve(r[Nu:Nu + Np])
+    zd, its_d, _ = system.lazy_full_pcg(O.riesz(), r[Nu + Np:], tp, th, nu=2, rtol=1e-5)
+    e = (rel(zh[:Nu], zu), rel(zh[Nu:Nu + Np], zp), rel(zh[Nu + Np:], zd))
+    print(f"[ds precond] velocity {e[0]:.2e} ({st['velocity_its_total']} its) pressure {e[1]:.2e} "
+          f"({st['pressure_its_total']} its) darcy {e[2]:.2e} ({st['darcy_its_total']} its, oracle {its_d})",
+          flush=True)
+    assert e[0] <= 1e-10 and e[1] <= 1e-10 and e[2] <= 1e-9
+    assert st["darcy_its_total"] == its_d
+
+
+@pytest.mark.parametrize("n,K,mu,alpha", [(8, 1.0, 1.0, 3.0), (16, 1e-2, 1e-4, 3.0), (32, 1.0, 1e-2, 0.0),
+                                          (64, 1e-2, 1.0, 3.0)])
+def test_solve_matches_oracle(n, K, mu, alpha):
+    print(f"[ds solve] n={n} K={K} mu={mu} alpha={alpha}", flush=True)
+    P, TP, TH, O, tp, th = setup(n, K, mu, alpha)
+    b = np.random.default_rng(100 + n).standard_normal(O.N)
+    x = torch.zeros(O.N, dtype=torch.float64, device="cuda")
+    st = P.solve(TP, TH, dev(b), x, F.ds_opts_default(rtol=1e-10))
+    xh = host(x)
+    err = rel(xh, O.solve_splu(b))
+    Bl, inner = O.precond_lazy(tp, th, darcy_rtol=1e-5)
+    _, its_ref, _ = ds.fgmres(lambda v: O.A @ v, b, Bl, rtol=1e-10, maxit=300)
+    res_ref = rel(O.A @ xh, b)
+    print(f"[ds solve] its {st['its']} (oracle {its_ref}) err {err:.2e} res {st['true_rel_res']:.2e} "
+          f"(oracle's residual of x {res_ref:.2e}) velocity {st['velocity_its_total']} "
+          f"darcy {st['darcy_its_total']} ms {st['t_solve_ms']:.1f}", flush=True)
+    assert err <= 1e-8
+    assert abs(st["its"] - its_ref) <= 2
+    assert st["rel_res"] <= 1e-10
+    rounding = 32 * np.finfo(float).eps * np.linalg.norm(abs(O.A) @ abs(xh)) / np.linalg.norm(b)
+    assert abs(st["true_rel_res"] - res_ref) <= 1e-3 * res_ref + rounding
+
+
+def test_solve_one_vcycle_velocity_block():
+    # Sec. 4's setting: one V-cycle for the velocity block; FGMRES absorbs the inexactness
+    n, K, mu, alpha = 32, 1e-2, 1e-4, 0.0
+    P, TP, TH, O, _, _ = setup(n, K, mu, alpha)
+    b = np.random.default_rng(3).standard_normal(O.N)
+    x = torch.zeros(O.N, dtype=torch.float64, device="cuda")
+    st = P.solve(TP, TH, dev(b), x, F.ds_opts_default(rtol=1e-10, velocity_rtol=0.0, darcy_rtol=1e-4))
+    err = rel(host(x), O.solve_splu(b))
+    print(f"[ds one V-cycle] its {st['its']} err {err:.2e} res {st['true_rel_res']:.2e}", flush=True)
+    assert err <= 1e-8 and st["true_rel_res"] <= 1e-9
+    assert st["velocity_its_total"] == st["its"]
+    assert st["its"] <= 150
+
+
+@pytest.mark.parametrize("K,mu", [(1e-2, 1e-4), (1.0, 1.0)])
+def test_counts_bounded_in_h(K, mu):
+    # Appendix (Fig. 6): FGMRES counts bounded in the mesh size
+    counts = []
+    for n in (32, 128, 256):
+        P, TP, TH, _, _, _ = setup(n, K, mu, 3.0, oracle=False)
+        b = np.random.default_rng(n).standard_normal(P.N)
+        x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+        st = P.solve(TP, TH, dev(b), x, F.ds_opts_default(rtol=1e-10))
+        print(f"[ds robust] n={n} K={K} mu={mu} its {st['its']} res {st['true_rel_res']:.2e} "
+              f"velocity max {st['velocity_its_max']} darcy max {st['darcy_its_max']} "
+              f"ms {st['t_solve_ms']:.0f}", flush=True)
+        assert st["true_rel_res"] <= 1e-9
+        counts.append(st["its"])
+    assert max(counts) <= 90 and max(counts) - min(counts) <= 6
+
+
+def test_ds_error_paths():
+    for args in ((6, 1.0, 1.0, 0.0, 10), (4, 1.0, 1.0, 0.0, 10), (8, 0.0, 1.0, 0.0, 10),
+                 (8, 1.0, -1.0, 0.0, 10), (8, 1.0, 1.0, -1.0, 10), (8, 1.0, 1.0, 0.0, 0),
+                 (8, 1.0, 1.0, 0.0, 401)):
+        with pytest.raises(F.FddError) as e:
+            F.setup_darcy_stokes(*args)
+        assert e.value.status == F.FDD_E_ARG
+    P, TP, TH, _, _, _ = setup(8, 1.0, 1.0, 0.0, krylov=8, oracle=False)
+    b = torch.ones(P.N, dtype=torch.float64, device="cuda")
+    x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+    with pytest.raises(F.FddError) as e:            # tables in the wrong slots
+        P.solve(TH, TP, b, x)
+    assert e.value.status == F.FDD_E_STATE
+    with pytest.raises(F.FddError) as e:            # invalid options
+        P.solve(TP, TH, b, x, F.ds_opts_default(rtol=0.0))
+    assert e.value.status == F.FDD_E_ARG
+    with pytest.raises(F.FddError) as e:            # the facet-problem calls are refused
+        F.Problem.solve(P, TP, TH, b, x)
+    assert e.value.status == F.FDD_E_ARG
+    Q = F.setup_mesh(8, 1.0, 1.0)
+    Q.bind_workspace()
+    TQ = Q.build_rational_pc(F.FDD_RA_PRECOND, 1e-10)
+    TQH = Q.build_rational_pc(F.FDD_RA_OPERATOR, 1e-10)
+    with pytest.raises(F.FddError) as e:            # not a Darcy-Stokes problem
+        F.DarcyStokes.solve(Q, TQ, TQH, torch.ones(Q.N, dtype=torch.float64, device="cuda"),
+                            torch.zeros(Q.N, dtype=torch.float64, device="cuda"))
+    assert e.value.status == F.FDD_E_ARG
+    # a zero right-hand side returns x = 0 at once; the Krylov capacity bounds the iterations
+    z = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+    x.fill_(1.0)
+    st = P.solve(TP, TH, z, x)
+    assert st["its"] == 0 and float(x.abs().max()) == 0.0
+    st = P.solve(TP, TH, b, x, allow_not_converged=True)
+    assert st["status"] == F.FDD_NOT_CONVERGED and st["its"] == 8
