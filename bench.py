@@ -65,6 +65,11 @@ def parse():
                     help="the paper's own model problem (Gamma = the whole boundary) beside the headline")
     ap.add_argument("--hdiv", choices=["auto", "none", "only"], default="auto",
                     help="the H(div) variant (eq. (graddiv), BDM1) beside the headline")
+    ap.add_argument("--ds", choices=["auto", "none", "only"], default="auto",
+                    help="the Darcy-Stokes outer solver (eq. (darcy_stokes), FGMRES) beside the headline")
+    ap.add_argument("--ds-n", type=int, default=0,
+                    help="Darcy-Stokes leg at this n only (the first (K, mu) case, no count sweep or "
+                         "oracle checks): for profiling")
     ap.add_argument("--full-lazy", choices=["auto", "none", "only"], default="auto",
                     help="the full-system PCG with the lazy block preconditioner beside the headline")
     ap.add_argument("--cnn-only", action="store_true", help="only time the warm-start network kernels")
@@ -691,6 +696,95 @@ def run_hdiv(F, args, leg, n=512, reps=2, gammas=(1e-3, 1.0, 1e3), robust_sizes=
     return res
 
 
+def run_darcy_stokes(F, args, leg, sizes=(256, 512), reps=2, params=((1e-2, 1e-4), (1.0, 1.0)),
+                     alpha=3.0, robust_sizes=(64, 128, 256)):
+    """The Darcy-Stokes outer solver (Sec. 4 eq. (darcy_stokes), eq. (darcy_stokes_precond);
+    Appendix): FGMRES to rtol 1e-10 with the block-diagonal preconditioner (velocity and pressure
+    blocks by PCG to 1e-12 (velocity V-cycle nu = 1), the Darcy block by the lazy PCG to 1e-5 as
+    in the Appendix; alpha = 3).  Solves/s per size and (K, mu) with FGMRES and inner counts and
+    true residuals, the setting of Sec. 4 (one velocity V-cycle with nu = 2, Darcy PCG to 1e-4), FGMRES counts over n (Fig. 6), a parity
+    spot-check at n = 32 against the oracle's sparse LU, and the oracle's FGMRES (sparse LU for the
+    Stokes blocks and the Riesz map) timed at n = 32.  FP64 throughout."""
+    import numpy as np
+    import torch
+
+    rtol = 1e-10
+    res = {"alpha": alpha, "rtol": rtol, "cases": [], "its_over_n": {}}
+    if args.ds_n:
+        sizes, params, robust_sizes = (args.ds_n,), params[:1], ()
+
+    def problem(n, K, mu):
+        P = F.setup_darcy_stokes(n, K, mu, alpha, krylov=200)
+        P.bind_workspace()
+        return P, P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12), P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+
+    settings = (("appendix", F.ds_opts_default(rtol=rtol)),
+                ("sec4", F.ds_opts_default(rtol=rtol, velocity_rtol=0.0, darcy_rtol=1e-4, mg_nu=2)))
+    for n in sizes:
+        for K, mu in (params if n == sizes[0] else params[:1]):
+            P, TP, TH = problem(n, K, mu)
+            bs = [torch.as_tensor(np.random.default_rng(9000 + k).standard_normal(P.N), dtype=torch.float64,
+                                  device="cuda") for k in range(reps + 1)]
+            x = torch.zeros_like(bs[0])
+            for name, o in settings:
+                P.solve(TP, TH, bs[reps], x, o)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sts = [P.solve(TP, TH, bs[k], x, o) for k in range(reps)]
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                row = {"n": n, "K": K, "mu": mu, "setting": name, "dofs": P.N, "solves_per_s": reps / el,
+                       "ms_per_solve": 1e3 * el / reps, "fgmres_its": sts[-1]["its"],
+                       "velocity_its_total": sts[-1]["velocity_its_total"],
+                       "pressure_its_total": sts[-1]["pressure_its_total"],
+                       "darcy_its_total": sts[-1]["darcy_its_total"],
+                       "true_rel_res_max": max(s_["true_rel_res"] for s_ in sts)}
+                res["cases"].append(row)
+                progress(f"Darcy-Stokes n={n} K={K:g} mu={mu:g} {name}: {row['solves_per_s']:.2f} solves/s, "
+                         f"FGMRES {row['fgmres_its']}")
+            del P
+    for K, mu in params:
+        counts = []
+        for m in robust_sizes:
+            P, TP, TH = problem(m, K, mu)
+            b = torch.as_tensor(np.random.default_rng(9100 + m).standard_normal(P.N), dtype=torch.float64,
+                                device="cuda")
+            counts.append(P.solve(TP, TH, b, torch.zeros_like(b), settings[0][1])["its"])
+        res["its_over_n"][f"K={K:g},mu={mu:g}"] = dict(zip([str(m) for m in robust_sizes], counts))
+    if args.ds_n:
+        return res
+    # parity spot-check at n = 32
+    K, mu = params[0]
+    Q, QP, QH = problem(32, K, mu)
+    bq = torch.as_tensor(np.random.default_rng(9200).standard_normal(Q.N), dtype=torch.float64, device="cuda")
+    xq = torch.zeros_like(bq)
+    Q.solve(QP, QH, bq, xq, settings[0][1])
+    res["n32_rel_err_vs_oracle"] = None
+    bh, xh = bq.cpu().numpy(), xq.cpu().numpy()
+
+    def parity(bh=bh, xh=xh):
+        from oracle import darcy_stokes
+        xr = darcy_stokes.DarcyStokes(32, K, mu, alpha).solve_splu(bh)
+        return float(np.linalg.norm(xh - xr) / np.linalg.norm(xr))
+    leg.defer(res, "n32_rel_err_vs_oracle", parity)
+
+    def cpu_rate():
+        from oracle import darcy_stokes
+        O = darcy_stokes.DarcyStokes(32, K, mu, alpha)
+        b = np.random.default_rng(9300).standard_normal(O.N)
+        t0 = time.perf_counter()
+        B = O.precond_exact()
+        t_fact = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, its, _ = darcy_stokes.fgmres(lambda v: O.A @ v, b, B, rtol=rtol, maxit=300)
+        return {"n": 32, "K": K, "mu": mu, "solves_per_s": 1.0 / (time.perf_counter() - t0),
+                "factorization_s": t_fact, "fgmres_its": its,
+                "kind": "oracle FGMRES, sparse LU Stokes blocks and Riesz map", "cores": 1}
+    res["cpu_baseline"] = None
+    leg.defer(res, "cpu_baseline", cpu_rate)
+    return res
+
+
 def run_sweep(F, args, leg, sizes=(128, 256, 512, 1024, 2048)):
     """2D sweep n x K in {1, 1e-2, 1e-4} x mu in {1e-6, 1e-3, 1, 1e3} (seed 1000 + index): outer and
     inner iterations, solves/s (one warm-up and two timed solves) and the error of the solution."""
@@ -823,6 +917,12 @@ def main():
         res = run_hdiv(F, args, leg)
         leg.run()
         print(json.dumps({"hdiv": res}))
+        return
+    if args.ds == "only":
+        leg = OracleLeg()
+        res = run_darcy_stokes(F, args, leg)
+        leg.run()
+        print(json.dumps({"darcy_stokes": res}))
         return
     if args.full_lazy == "only":
         leg = OracleLeg()
@@ -1017,6 +1117,9 @@ def main():
     if args.hdiv == "auto":
         progress("H(div) variant")
         out["hdiv"] = run_hdiv(F, args, leg)
+    if args.ds == "auto":
+        progress("Darcy-Stokes")
+        out["darcy_stokes"] = run_darcy_stokes(F, args, leg)
     if args.learned == "auto":
         progress("learned warm start")
         out["learned"] = run_learned(F, args, leg)

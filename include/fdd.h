@@ -314,7 +314,8 @@ typedef struct {
   double velocity_rtol;   /* A_u block: PCG with the P2 multigrid V-cycle to this relative
                              residual (1e-12); 0: one V-cycle instead (the setting of Sec. 4) */
   int velocity_maxit;     /* (100) */
-  int mg_nu;              /* smoothing steps of the velocity V-cycle, 1 or 2 (2)              */
+  int mg_nu;              /* smoothing steps of the velocity V-cycle, 1 (default: the PCG to
+                             velocity_rtol) or 2 (the better choice for one V-cycle)          */
   double pressure_rtol;   /* mu^{-1} M_p block: Jacobi-PCG to this relative residual (1e-12)  */
   int pressure_maxit;     /* (200) */
   double darcy_rtol;      /* Darcy block: fdd_solve_full on the facet problem to this relative

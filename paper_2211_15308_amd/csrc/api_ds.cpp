@@ -174,7 +174,8 @@ int ds_bind(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s) {
     return FDD_OK;
   };
   auto upm = [&](const HdMat& M) -> int {
-    int r = up(M.dcol, M.col.data(), M.col.size() * sizeof(int));
+    int r = M.toff.empty() ? up(M.dcol, M.col.data(), M.col.size() * sizeof(int))
+                           : up(M.dtoff, M.toff.data(), M.toff.size() * sizeof(int));
     if (!r) r = up(M.drtype, M.rtype.data(), M.rtype.size() * sizeof(int));
     return r ? r : up(M.dtval, M.tval.data(), M.tval.size() * sizeof(double));
   };
@@ -225,7 +226,7 @@ void fdd_ds_opts_default(fdd_ds_opts* o) {
   o->maxit = kDsMaxKrylov;
   o->velocity_rtol = 1e-12;
   o->velocity_maxit = 100;
-  o->mg_nu = 2;
+  o->mg_nu = 1;
   o->pressure_rtol = 1e-12;
   o->pressure_maxit = 200;
   o->darcy_rtol = 1e-5;

@@ -108,7 +108,8 @@ int hdiv_bind(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s) {
     return FDD_OK;
   };
   auto upm = [&](const HdMat& M) -> int {
-    int rc = up(M.dcol, M.col.data(), M.col.size() * sizeof(int));
+    int rc = M.toff.empty() ? up(M.dcol, M.col.data(), M.col.size() * sizeof(int))
+                            : up(M.dtoff, M.toff.data(), M.toff.size() * sizeof(int));
     if (!rc) rc = up(M.drtype, M.rtype.data(), M.rtype.size() * sizeof(int));
     return rc ? rc : up(M.dtval, M.tval.data(), M.tval.size() * sizeof(double));
   };

@@ -345,7 +345,9 @@ size_t ds_plan(ProblemDS* D, char* base) {
     return p;
   };
   auto mat = [&](HdMat& M) {
-    M.dcol = (int*)take(M.col.size() * sizeof(int));
+    // relative form: the per-type offsets replace the per-row columns on the device
+    M.dcol = M.toff.empty() ? (int*)take(M.col.size() * sizeof(int)) : nullptr;
+    M.dtoff = M.toff.empty() ? nullptr : (int*)take(M.toff.size() * sizeof(int));
     M.drtype = (int*)take(M.rtype.size() * sizeof(int));
     M.dtval = (double*)take(M.tval.size() * sizeof(double));
   };

@@ -63,6 +63,41 @@ void RowBuilder::to_ell(HdMat* M, int ncols) const {
     M->rtype[i] = t;
   }
   M->ntypes = (int)types.size();
+  M->toff.clear();
+  // relative form: a type is the value sequence together with the column offsets col - i; kept
+  // when at most kMaxRelTypes types arise and at least 64 rows share a type on average.  (Tables
+  // of thousands of types, read per row with little locality, were measured slower than the
+  // per-row columns: the H(div) levels keep the absolute form.)
+  constexpr size_t kMaxRelTypes = 256;
+  const size_t max_types = std::min<size_t>(kMaxRelTypes, (size_t)rows / 64);
+  std::unordered_map<std::string, int> rel;
+  std::vector<int> rtype(rows), toff;
+  std::vector<double> rtval;
+  std::vector<int> offs(w);
+  std::string key;
+  for (int i = 0; i < rows; ++i) {
+    for (int k = 0; k < w; ++k) {
+      vals[k] = M->val[(size_t)k * rows + i];
+      offs[k] = M->col[(size_t)k * rows + i] - i;
+    }
+    key.assign((const char*)vals.data(), vals.size() * sizeof(double));
+    key.append((const char*)offs.data(), offs.size() * sizeof(int));
+    auto it = rel.find(key);
+    if (it != rel.end()) {
+      rtype[i] = it->second;
+      continue;
+    }
+    if (rel.size() >= max_types) return;   // too many: keep the absolute columns
+    const int t = (int)rel.size();
+    rel.emplace(key, t);
+    rtval.insert(rtval.end(), vals.begin(), vals.end());
+    toff.insert(toff.end(), offs.begin(), offs.end());
+    rtype[i] = t;
+  }
+  M->rtype = rtype;
+  M->tval = rtval;
+  M->toff = toff;
+  M->ntypes = (int)rel.size();
 }
 
 double ell_entry(const HdMat& M, int i, int j) {

@@ -51,12 +51,18 @@ struct HdTable {
 // unused slots point at column min(i, cols - 1) with value 0), and its values come from a small
 // table: row i's slot k has value tval[rtype[i] * width + k].  On the uniform mesh rows repeat
 // (translation invariance), so a product reads 4 bytes per slot and per row instead of 12.
-// Host copies (val: the expanded values) built at setup, device copies in the workspace.
+// Where the column pattern repeats too (a row's neighbours at fixed index offsets, as on the
+// structured P2 grid), the type also fixes the columns: slot k of row i is column
+// i + toff[rtype[i] * width + k], and the per-row column array is not stored on the device (a
+// product then reads 4 bytes per row for the type plus the gathered x).  The relative form is
+// chosen when its type table stays small (to_ell); toff is empty otherwise.
+// Host copies (val: the expanded values, col: absolute columns) built at setup, device copies in
+// the workspace.
 struct HdMat {
   int rows = 0, cols = 0, width = 0, ntypes = 0;
-  std::vector<int> col, rtype;
+  std::vector<int> col, rtype, toff;
   std::vector<double> val, tval;
-  int *dcol = nullptr, *drtype = nullptr;
+  int *dcol = nullptr, *drtype = nullptr, *dtoff = nullptr;
   double* dtval = nullptr;
 };
 
@@ -110,12 +116,15 @@ std::vector<double> hdiv_loop_eigs(const ProblemHdiv* Q);
 
 // ---- kernels (kernels_hdiv.hip) --------------------------------------------------------------
 struct HdView {
-  const int* col;
+  const int* col;     // absolute columns (null when toff is set)
   const int* rtype;
   const double* tval;
+  const int* toff;    // per-type column offsets, or null
   int rows, width;
 };
-inline HdView view(const HdMat& m) { return HdView{m.dcol, m.drtype, m.dtval, m.rows, m.width}; }
+inline HdView view(const HdMat& m) {
+  return HdView{m.dcol, m.drtype, m.dtval, m.dtoff, m.rows, m.width};
+}
 
 // Every launcher takes `stop`: kernels return at once when stop->done is set (null: never).
 // y = beta y + alpha A x  (beta = 0: y is only written)

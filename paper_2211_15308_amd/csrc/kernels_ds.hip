@@ -198,9 +198,13 @@ __global__ __launch_bounds__(kT) void k_ds_scale(int n, double a, const double* 
 }
 
 __device__ __forceinline__ double ell_row(const HdView& A, int i, const double* __restrict__ x) {
-  const double* v = A.tval + (size_t)A.rtype[i] * A.width;
+  const int t = A.rtype[i];
+  const double* v = A.tval + (size_t)t * A.width;
   double s = 0.0;
-  for (int k = 0; k < A.width; ++k) s += v[k] * x[A.col[(size_t)k * A.rows + i]];
+  for (int k = 0; k < A.width; ++k) {
+    const int c = A.toff ? i + A.toff[t * A.width + k] : A.col[(size_t)k * A.rows + i];
+    s += v[k] * x[c];
+  }
   return s;
 }
 

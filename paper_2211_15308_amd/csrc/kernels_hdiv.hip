@@ -54,10 +54,17 @@ __device__ double sum_partials(const double* p, int nb) {
   return block_sum(v);
 }
 
+// row i of A times x; the two column forms in separate loops (the choice is uniform per launch)
 __device__ __forceinline__ double ell_row(const HdView& A, int i, const double* __restrict__ x) {
-  const double* v = A.tval + (size_t)A.rtype[i] * A.width;
+  const int t = A.rtype[i];
+  const double* v = A.tval + (size_t)t * A.width;
   double s = 0.0;
-  for (int k = 0; k < A.width; ++k) s += v[k] * x[A.col[(size_t)k * A.rows + i]];
+  if (A.toff) {
+    const int* o = A.toff + t * A.width;
+    for (int k = 0; k < A.width; ++k) s += v[k] * x[i + o[k]];
+  } else {
+    for (int k = 0; k < A.width; ++k) s += v[k] * x[A.col[(size_t)k * A.rows + i]];
+  }
   return s;
 }
 
@@ -83,6 +90,8 @@ __device__ __forceinline__ void patch_solve_vertex(const int* __restrict__ patch
     rl[k] = d >= 0 ? r[d] : 0.0;
   }
   const double* Pi = pinv + (size_t)t * kHdPatch * kHdPatch;
+  // every slot is written (a lane's 12 values are contiguous, so the stores combine; slots
+  // without a dof hold 0 and are never read back)
 #pragma unroll
   for (int a = 0; a < kHdPatch; ++a) {
     double y = 0.0;
@@ -233,12 +242,20 @@ __global__ __launch_bounds__(kT) void k_hd_pq(HdView A, const double* __restrict
   double s = 0.0;
   for (int i = blockIdx.x * kT + threadIdx.x; i < A.rows; i += gridDim.x * kT) {
     // q = A (z + beta p_old), with the direction formed where the product reads it
-    const double* v = A.tval + (size_t)A.rtype[i] * A.width;
+    const int t = A.rtype[i];
+    const double* v = A.tval + (size_t)t * A.width;
     double qi = 0.0;
-    for (int k = 0; k < A.width; ++k) {
-      const int c = A.col[(size_t)k * A.rows + i];
-      const double pc = first ? z[c] : z[c] + beta * p_old[c];
-      qi += v[k] * pc;
+    if (A.toff) {
+      const int* o = A.toff + t * A.width;
+      for (int k = 0; k < A.width; ++k) {
+        const int c = i + o[k];
+        qi += v[k] * (first ? z[c] : z[c] + beta * p_old[c]);
+      }
+    } else {
+      for (int k = 0; k < A.width; ++k) {
+        const int c = A.col[(size_t)k * A.rows + i];
+        qi += v[k] * (first ? z[c] : z[c] + beta * p_old[c]);
+      }
     }
     const double pi = first ? z[i] : z[i] + beta * p_old[i];
     p_new[i] = pi;

@@ -63,6 +63,12 @@ def pmc_per_dispatch(db, counter, name_filter):
     return list(out.values())
 
 
+def short_name(name):
+    """A kernel's name without its argument list ("(anonymous namespace)" is kept)."""
+    base = name.replace("(anonymous namespace)::", "")
+    return base.split("(")[0].strip()
+
+
 def csv_kernel_stats(path):
     """Rows of a rocprofv3 *_kernel_stats.csv, sorted by total time."""
     rows = list(csv.DictReader(open(path)))
@@ -91,7 +97,7 @@ def csv_trace_split(path, name, split_us):
     """Durations (us) of the dispatches of one kernel from a kernel_trace.csv, split at split_us."""
     durs = []
     for r in csv.DictReader(open(path)):
-        if r["Kernel_Name"].split("(")[0].strip() == name:
+        if short_name(r["Kernel_Name"]) == short_name(name):
             durs.append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     long = [d for d in durs if d >= split_us]
     return durs, long
@@ -138,12 +144,12 @@ def main(argv):
     elif argv[0] == "csvstats":
         print(f"{'total_us':>12} {'pct':>6} {'calls':>7} {'avg_us':>9}  kernel")
         for name, calls, tot, avg, pct in csv_kernel_stats(argv[1]):
-            print(f"{tot:12.1f} {pct:6.2f} {calls:7d} {avg:9.2f}  {name.split('(')[0]}")
+            print(f"{tot:12.1f} {pct:6.2f} {calls:7d} {avg:9.2f}  {short_name(name)}")
     elif argv[0] == "csvpmc":
         for k, (n, cn, vals) in sorted(csv_pmc(argv[1]).items(), key=lambda kv: -sum(kv[1][2])):
             big = [v for v in vals if v > 0.1 * max(vals)]
             print(f"{cn} dispatches {n:6d} working {len(big):6d} avg_working_KiB "
-                  f"{sum(big) / max(len(big), 1):14.1f} max_KiB {max(vals):14.1f}  {k.split('(')[0]}")
+                  f"{sum(big) / max(len(big), 1):14.1f} max_KiB {max(vals):14.1f}  {short_name(k)}")
     elif argv[0] == "csvtrace":
         durs, long = csv_trace_split(argv[1], argv[2], float(argv[3]))
         print(f"{argv[2]}: dispatches {len(durs)} avg_us {sum(durs) / max(len(durs), 1):.2f}; "

@@ -118,7 +118,8 @@ def test_solve_one_vcycle_velocity_block():
     P, TP, TH, O, _, _ = setup(n, K, mu, alpha)
     b = np.random.default_rng(3).standard_normal(O.N)
     x = torch.zeros(O.N, dtype=torch.float64, device="cuda")
-    st = P.solve(TP, TH, dev(b), x, F.ds_opts_default(rtol=1e-10, velocity_rtol=0.0, darcy_rtol=1e-4))
+    st = P.solve(TP, TH, dev(b), x, F.ds_opts_default(rtol=1e-10, velocity_rtol=0.0, darcy_rtol=1e-4,
+                                                      mg_nu=2))
     err = rel(host(x), O.solve_splu(b))
     print(f"[ds one V-cycle] its {st['its']} err {err:.2e} res {st['true_rel_res']:.2e}", flush=True)
     assert err <= 1e-8 and st["true_rel_res"] <= 1e-9
