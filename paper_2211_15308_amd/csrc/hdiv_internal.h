@@ -120,10 +120,10 @@ struct HdView {
   const int* rtype;
   const double* tval;
   const int* toff;    // per-type column offsets, or null
-  int rows, width;
+  int rows, width, ntypes;
 };
 inline HdView view(const HdMat& m) {
-  return HdView{m.dcol, m.drtype, m.dtval, m.dtoff, m.rows, m.width};
+  return HdView{m.dcol, m.drtype, m.dtval, m.dtoff, m.rows, m.width, m.ntypes};
 }
 
 // Every launcher takes `stop`: kernels return at once when stop->done is set (null: never).

@@ -68,13 +68,54 @@ __device__ __forceinline__ double ell_row(const HdView& A, int i, const double* 
   return s;
 }
 
-// ---- sparse products, smoother, coarse solve ------------------------------------------------
+// The type table of a product (values, and offsets in the relative form) staged in LDS when it
+// has at most kTabLds entries: every slot of every row reads it, and LDS serves a wave's reads of
+// one entry in one access where the cache would take a vector load per slot.
+constexpr int kTabLds = 1024;
+struct TabLds {
+  double v[kTabLds];
+  int o[kTabLds];
+};
 
-__device__ __forceinline__ void spmv_row(const HdView& A, int i, const double* __restrict__ x,
-                                         double* __restrict__ y, double alpha, double beta) {
-  const double s = ell_row(A, i, x);
-  y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + alpha * s;
+// every thread of the block calls it; true when the table is in LDS
+__device__ bool stage_table(const HdView& A, TabLds& T) {
+  const int nt = A.ntypes * A.width;
+  if (nt > kTabLds) return false;
+  for (int k = threadIdx.x; k < nt; k += blockDim.x) {
+    T.v[k] = A.tval[k];
+    if (A.toff) T.o[k] = A.toff[k];
+  }
+  __syncthreads();
+  return true;
 }
+
+// row i of A times x with the table in LDS (kLds) or in global memory
+template <bool kLds>
+__device__ __forceinline__ double ell_row_tab(const HdView& A, const TabLds& T, int i,
+                                              const double* __restrict__ x) {
+  const int base = A.rtype[i] * A.width;
+  double s = 0.0;
+  if (A.toff) {
+    for (int k = 0; k < A.width; ++k) {
+      const double v = kLds ? T.v[base + k] : A.tval[base + k];
+      const int o = kLds ? T.o[base + k] : A.toff[base + k];
+      s += v * x[i + o];
+    }
+  } else {
+    for (int k = 0; k < A.width; ++k) {
+      const double v = kLds ? T.v[base + k] : A.tval[base + k];
+      s += v * x[A.col[(size_t)k * A.rows + i]];
+    }
+  }
+  return s;
+}
+
+// grid of the row kernels: a grid-stride loop over at most kRowBlocks blocks, so that each block
+// stages the table once for several chunks of rows
+constexpr int kRowBlocks = 2048;
+inline int row_blocks(int64_t n) { return (int)std::min<int64_t>(blocks_for(n), kRowBlocks); }
+
+// ---- sparse products, smoother, coarse solve ------------------------------------------------
 
 __device__ __forceinline__ void patch_solve_vertex(const int* __restrict__ patch,
                                                    const int* __restrict__ ptype,
@@ -115,18 +156,22 @@ __global__ __launch_bounds__(kT) void k_hd_spmv(HdView A, const double* __restri
                                                 double* __restrict__ y, double alpha, double beta,
                                                 const HdState* stop) {
   if (stopped(stop)) return;
-  const int i = blockIdx.x * kT + threadIdx.x;
-  if (i >= A.rows) return;
-  spmv_row(A, i, x, y, alpha, beta);
+  __shared__ TabLds T;
+  const bool lds = stage_table(A, T);
+  for (int i = blockIdx.x * kT + threadIdx.x; i < A.rows; i += gridDim.x * kT) {
+    const double s = lds ? ell_row_tab<true>(A, T, i, x) : ell_row_tab<false>(A, T, i, x);
+    y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + alpha * s;
+  }
 }
 
 __global__ __launch_bounds__(kT) void k_hd_residual(HdView A, const double* __restrict__ b,
                                                     const double* __restrict__ x,
                                                     double* __restrict__ r, const HdState* stop) {
   if (stopped(stop)) return;
-  const int i = blockIdx.x * kT + threadIdx.x;
-  if (i >= A.rows) return;
-  r[i] = b[i] - ell_row(A, i, x);
+  __shared__ TabLds T;
+  const bool lds = stage_table(A, T);
+  for (int i = blockIdx.x * kT + threadIdx.x; i < A.rows; i += gridDim.x * kT)
+    r[i] = b[i] - (lds ? ell_row_tab<true>(A, T, i, x) : ell_row_tab<false>(A, T, i, x));
 }
 
 // (the few inverse patch matrices are staged in LDS: every lane reads a row of its vertex's)
@@ -232,31 +277,35 @@ __global__ __launch_bounds__(kOneBlock) void k_hd_rz_finish(const double* partia
   }
 }
 
+template <bool kLds>
+__device__ __forceinline__ double pq_row(const HdView& A, const TabLds& T, int i,
+                                         const double* __restrict__ z,
+                                         const double* __restrict__ p_old, double beta, int first) {
+  const int base = A.rtype[i] * A.width;
+  double qi = 0.0;
+  for (int k = 0; k < A.width; ++k) {
+    const double v = kLds ? T.v[base + k] : A.tval[base + k];
+    const int c = A.toff ? i + (kLds ? T.o[base + k] : A.toff[base + k])
+                         : A.col[(size_t)k * A.rows + i];
+    qi += v * (first ? z[c] : z[c] + beta * p_old[c]);
+  }
+  return qi;
+}
+
 __global__ __launch_bounds__(kT) void k_hd_pq(HdView A, const double* __restrict__ z,
                                               const double* __restrict__ p_old,
                                               double* __restrict__ p_new, double* __restrict__ q,
                                               double* __restrict__ partials, const HdState* st,
                                               int first) {
   if (st->done) return;
+  __shared__ TabLds T;
+  const bool lds = stage_table(A, T);
   const double beta = st->beta;
   double s = 0.0;
   for (int i = blockIdx.x * kT + threadIdx.x; i < A.rows; i += gridDim.x * kT) {
     // q = A (z + beta p_old), with the direction formed where the product reads it
-    const int t = A.rtype[i];
-    const double* v = A.tval + (size_t)t * A.width;
-    double qi = 0.0;
-    if (A.toff) {
-      const int* o = A.toff + t * A.width;
-      for (int k = 0; k < A.width; ++k) {
-        const int c = i + o[k];
-        qi += v[k] * (first ? z[c] : z[c] + beta * p_old[c]);
-      }
-    } else {
-      for (int k = 0; k < A.width; ++k) {
-        const int c = A.col[(size_t)k * A.rows + i];
-        qi += v[k] * (first ? z[c] : z[c] + beta * p_old[c]);
-      }
-    }
+    const double qi = lds ? pq_row<true>(A, T, i, z, p_old, beta, first)
+                          : pq_row<false>(A, T, i, z, p_old, beta, first);
     const double pi = first ? z[i] : z[i] + beta * p_old[i];
     p_new[i] = pi;
     q[i] = qi;
@@ -520,13 +569,13 @@ __global__ __launch_bounds__(kT) void k_hd_scale(const double* __restrict__ a, d
 void launch_hd_spmv(hipStream_t s, HdView A, const double* x, double* y, double alpha, double beta,
                     const HdState* stop) {
   if (A.rows == 0) return;
-  hipLaunchKernelGGL(k_hd_spmv, dim3(blocks_for(A.rows)), dim3(kT), 0, s, A, x, y, alpha, beta,
+  hipLaunchKernelGGL(k_hd_spmv, dim3(row_blocks(A.rows)), dim3(kT), 0, s, A, x, y, alpha, beta,
                      stop);
 }
 
 void launch_hd_residual(hipStream_t s, HdView A, const double* b, const double* x, double* r,
                         const HdState* stop) {
-  hipLaunchKernelGGL(k_hd_residual, dim3(blocks_for(A.rows)), dim3(kT), 0, s, A, b, x, r, stop);
+  hipLaunchKernelGGL(k_hd_residual, dim3(row_blocks(A.rows)), dim3(kT), 0, s, A, b, x, r, stop);
 }
 
 void launch_hd_patch_solve(hipStream_t s, const HdLevel& L, const double* r, const HdState* stop) {

@@ -112,6 +112,32 @@ def test_solve_matches_oracle(n, K, mu, alpha):
     assert abs(st["true_rel_res"] - res_ref) <= 1e-3 * res_ref + rounding
 
 
+def test_solve_n128_against_golden():
+    # n = 128 (163,967 unknowns) against the oracle's sparse-LU solution written by
+    # tests/golden/make_ds_n128.py (4096 seeded entries and the norm)
+    import json
+    import os
+
+    import workloads
+    G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "solve_ds_n128.json")))
+    n, K, mu, alpha = G["n"], G["K"], G["mu"], G["alpha"]
+    print(f"[ds n128] n={n} K={K} mu={mu} alpha={alpha} against the stored oracle solution", flush=True)
+    P, TP, TH, _, _, _ = setup(n, K, mu, alpha, oracle=False)
+    assert P.N == G["N"]
+    b = workloads.normal_vector(P.N, 128)
+    x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+    st = P.solve(TP, TH, dev(b), x, F.ds_opts_default(rtol=1e-10))
+    xh = host(x)
+    idx = np.array(G["indices"])
+    ref = np.array(G["values"])
+    err = float(np.linalg.norm(xh[idx] - ref) / np.linalg.norm(ref))
+    nerr = abs(np.linalg.norm(xh) - G["norm_x"]) / G["norm_x"]
+    print(f"[ds n128] its {st['its']} sampled rel err {err:.2e} norm rel err {nerr:.2e} "
+          f"res {st['true_rel_res']:.2e}", flush=True)
+    assert err <= 1e-8 and nerr <= 1e-8
+    assert st["true_rel_res"] <= 1e-9
+
+
 def test_solve_one_vcycle_velocity_block():
     # Sec. 4's setting: one V-cycle for the velocity block; FGMRES absorbs the inexactness
     n, K, mu, alpha = 32, 1e-2, 1e-4, 0.0

@@ -84,3 +84,9 @@ def cnn_init(widths=(5, 32, 32, 32, 32, 32, 1), seed=6):
         W = rng.standard_normal((3, 3, cin, cout)) * np.sqrt(2.0 / (9 * cin))
         params.append((W, np.zeros(cout)))
     return params
+
+
+def normal_vector(size, seed):
+    """b ~ N(0, 1) of the given length in FP64 (the right-hand sides of the coupled Darcy-Stokes
+    system, whose unknowns are not those of a facet problem)."""
+    return np.random.default_rng(seed).standard_normal(size)
