@@ -24,6 +24,7 @@ constexpr int kT = 256;
 inline int chunks_for(int64_t n) {
   return (int)std::min<int64_t>((n + kT - 1) / kT, kDsChunks);
 }
+inline int full_grid(int64_t n) { return (int)((n + kT - 1) / kT); }
 
 __device__ double block_sum(double v) {
   __shared__ double sh[kT / 64 + 1];
@@ -108,16 +109,27 @@ __global__ __launch_bounds__(kT) void k_ds_mdot_finish(const double* partials, i
   }
 }
 
-// w -= sum_{i <= k} hpass_i V_i
+// w -= sum_{i <= k} hpass_i V_i: one entry per thread (a full grid: the kernel streams k + 2
+// vectors), the coefficients staged in LDS, four independent partial sums
 __global__ __launch_bounds__(kT) void k_ds_subtract(int n, int k, const double* __restrict__ V,
                                                     const double* __restrict__ hpass,
                                                     double* __restrict__ w, const DsState* st) {
   if (st->done) return;
-  for (int j = blockIdx.x * kT + threadIdx.x; j < n; j += gridDim.x * kT) {
-    double s = w[j];
-    for (int i = 0; i <= k; ++i) s -= hpass[i] * V[(size_t)i * n + j];
-    w[j] = s;
+  __shared__ double h[kDsMaxKrylov + 1];
+  for (int i = threadIdx.x; i <= k; i += kT) h[i] = hpass[i];
+  __syncthreads();
+  const int j = blockIdx.x * kT + threadIdx.x;
+  if (j >= n) return;
+  double s0 = w[j], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = 0;
+  for (; i + 3 <= k; i += 4) {
+    s0 -= h[i] * V[(size_t)i * n + j];
+    s1 -= h[i + 1] * V[(size_t)(i + 1) * n + j];
+    s2 -= h[i + 2] * V[(size_t)(i + 2) * n + j];
+    s3 -= h[i + 3] * V[(size_t)(i + 3) * n + j];
   }
+  for (; i <= k; ++i) s0 -= h[i] * V[(size_t)i * n + j];
+  w[j] = (s0 + s1) + (s2 + s3);
 }
 
 __global__ __launch_bounds__(kT) void k_ds_norm(int n, const double* __restrict__ w,
@@ -181,15 +193,25 @@ __global__ __launch_bounds__(64) void k_ds_backsolve(int k, int ldh, const doubl
   }
 }
 
-// x = sum_{i < k} y_i Z_i
+// x = sum_{i < k} y_i Z_i (one entry per thread, y staged in LDS)
 __global__ __launch_bounds__(kT) void k_ds_combine(int n, int k, const double* __restrict__ y,
                                                    const double* __restrict__ Z,
                                                    double* __restrict__ x) {
-  for (int j = blockIdx.x * kT + threadIdx.x; j < n; j += gridDim.x * kT) {
-    double s = 0.0;
-    for (int i = 0; i < k; ++i) s += y[i] * Z[(size_t)i * n + j];
-    x[j] = s;
+  __shared__ double ys[kDsMaxKrylov];
+  for (int i = threadIdx.x; i < k; i += kT) ys[i] = y[i];
+  __syncthreads();
+  const int j = blockIdx.x * kT + threadIdx.x;
+  if (j >= n) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = 0;
+  for (; i + 4 <= k; i += 4) {
+    s0 += ys[i] * Z[(size_t)i * n + j];
+    s1 += ys[i + 1] * Z[(size_t)(i + 1) * n + j];
+    s2 += ys[i + 2] * Z[(size_t)(i + 2) * n + j];
+    s3 += ys[i + 3] * Z[(size_t)(i + 3) * n + j];
   }
+  for (; i < k; ++i) s0 += ys[i] * Z[(size_t)i * n + j];
+  x[j] = (s0 + s1) + (s2 + s3);
 }
 
 __global__ __launch_bounds__(kT) void k_ds_scale(int n, double a, const double* __restrict__ x,
@@ -259,7 +281,7 @@ void launch_ds_orthogonalize(hipStream_t s, int n, int k, const double* V, doubl
     hipLaunchKernelGGL(k_ds_mdot, dim3(nb, k + 1), dim3(kT), 0, s, n, V, w, partials, st);
     hipLaunchKernelGGL(k_ds_mdot_finish, dim3(k + 1), dim3(kT), 0, s, partials, nb, Hcol, hpass,
                        pass, st);
-    hipLaunchKernelGGL(k_ds_subtract, dim3(nb), dim3(kT), 0, s, n, k, V, hpass, w, st);
+    hipLaunchKernelGGL(k_ds_subtract, dim3(full_grid(n)), dim3(kT), 0, s, n, k, V, hpass, w, st);
   }
 }
 
@@ -270,14 +292,14 @@ void launch_ds_normalize_givens(hipStream_t s, int n, int k, int ldh, double* w,
   hipLaunchKernelGGL(k_ds_norm, dim3(nb), dim3(kT), 0, s, n, w, partials, st);
   hipLaunchKernelGGL(k_ds_givens, dim3(1), dim3(kT), 0, s, partials, nb, k, ldh, Hm, cs, sn, g, st,
                      rtol);
-  hipLaunchKernelGGL(k_ds_normalize, dim3(nb), dim3(kT), 0, s, n, w, st);
+  hipLaunchKernelGGL(k_ds_normalize, dim3(full_grid(n)), dim3(kT), 0, s, n, w, st);
 }
 
 void launch_ds_solution(hipStream_t s, int n, int k, int ldh, const double* Hm, const double* g,
                         double* y, const double* Z, double* x) {
   const int nb = chunks_for(n);
   if (k > 0) hipLaunchKernelGGL(k_ds_backsolve, dim3(1), dim3(64), 0, s, k, ldh, Hm, g, y);
-  hipLaunchKernelGGL(k_ds_combine, dim3(nb), dim3(kT), 0, s, n, k, y, Z, x);
+  hipLaunchKernelGGL(k_ds_combine, dim3(full_grid(n)), dim3(kT), 0, s, n, k, y, Z, x);
 }
 
 void launch_ds_scale(hipStream_t s, int n, double a, const double* x, double* y) {
