@@ -174,3 +174,26 @@ def test_binding_rejects_vectors_the_kernels_cannot_take():
         P.apply_operator(TH, torch.zeros(P.NG, dtype=torch.float64), good)
     with pytest.raises(TypeError):
         P.apply_operator(TH, good.numpy(), good)
+
+
+def test_darcy_stokes_setup_host_only():
+    # sizes of the coupled system, argument validation, and rational tables that are the facet
+    # problem's (the Darcy block of eq. (darcy_stokes_precond) is the Riesz map of eq. (riesz))
+    from oracle import darcy_stokes
+    for n in (8, 32):
+        P = F.setup_darcy_stokes(n, 1e-2, 1e-4, 3.0, krylov=16)
+        assert (P.Nu, P.Np, P.ND, P.N) == darcy_stokes.sizes(n)
+        assert (P.NI, P.NG) == (P.Nu + P.Np, P.ND)
+        Q = F.setup_mesh(n, 1e-2, 1e-4)
+        assert (P.lam_lo, P.lam_hi) == (Q.lam_lo, Q.lam_hi)
+        for which in (F.FDD_RA_PRECOND, F.FDD_RA_OPERATOR):
+            a, b = P.build_rational_pc(which, 1e-10).query(), Q.build_rational_pc(which, 1e-10).query()
+            assert a == b
+    for bad in ((6, 1.0, 1.0, 0.0, 8), (4, 1.0, 1.0, 0.0, 8), (2048, 1.0, 1.0, 0.0, 8),
+                (8, 0.0, 1.0, 0.0, 8), (8, 1.0, 0.0, 0.0, 8), (8, 1.0, 1.0, -1.0, 8),
+                (8, float("inf"), 1.0, 0.0, 8), (8, 1.0, 1.0, 0.0, 0), (8, 1.0, 1.0, 0.0, 401)):
+        with pytest.raises(F.FddError) as e:
+            F.setup_darcy_stokes(*bad)
+        assert e.value.status == F.FDD_E_ARG
+    o = F.ds_opts_default()
+    assert (o.rtol, o.velocity_rtol, o.darcy_rtol, o.mg_nu, o.check_true_residual) == (1e-10, 1e-12, 1e-5, 1, 1)
