@@ -112,6 +112,25 @@ def test_solve_matches_oracle(n, K, mu, alpha):
     assert abs(st["true_rel_res"] - res_ref) <= 1e-3 * res_ref + rounding
 
 
+@pytest.mark.parametrize("nu,darcy_precision", [(2, "fp64"), (1, "mixed")])
+def test_solve_options_match_oracle(nu, darcy_precision):
+    # the velocity V-cycle with two smoothing steps, and the Darcy block's PCG with FP32 V-cycles:
+    # the same solution at the same tolerance, FGMRES counts within two of the oracle's
+    n, K, mu, alpha = 32, 1e-2, 1e-4, 3.0
+    prec = F.FDD_FP64 if darcy_precision == "fp64" else F.FDD_MIXED
+    print(f"[ds options] nu={nu} darcy={darcy_precision}", flush=True)
+    P, TP, TH, O, tp, th = setup(n, K, mu, alpha)
+    b = np.random.default_rng(77).standard_normal(O.N)
+    x = torch.zeros(O.N, dtype=torch.float64, device="cuda")
+    st = P.solve(TP, TH, dev(b), x, F.ds_opts_default(rtol=1e-10, mg_nu=nu, darcy_precision=prec))
+    err = rel(host(x), O.solve_splu(b))
+    Bl, _ = O.precond_lazy(tp, th, darcy_rtol=1e-5)
+    _, its_ref, _ = ds.fgmres(lambda v: O.A @ v, b, Bl, rtol=1e-10, maxit=300)
+    print(f"[ds options] its {st['its']} (oracle {its_ref}) err {err:.2e} velocity {st['velocity_its_total']} "
+          f"darcy {st['darcy_its_total']}", flush=True)
+    assert err <= 1e-8 and abs(st["its"] - its_ref) <= 2
+
+
 def test_solve_n128_against_golden():
     # n = 128 (163,967 unknowns) against the oracle's sparse-LU solution written by
     # tests/golden/make_ds_n128.py (4096 seeded entries and the norm)
