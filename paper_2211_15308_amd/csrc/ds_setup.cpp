@@ -204,7 +204,7 @@ const char* velocity_patches(HdLevel* L) {
   const int m = L->n;
   static const int nb[7][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {1, 1}};
   const int nv = (m + 1) * (m + 1);
-  return build_patch_tables(L, 2 * nv, [&](int v, int* dofs) {
+  return build_patch_tables(L, 2 * nv, 8, [&](int v, int* dofs) {
     const int c = v / nv, i = (v % nv) % (m + 1), j = (v % nv) / (m + 1);
     int k = 0;
     for (int q = 0; q < 7; ++q) {
@@ -278,7 +278,7 @@ const char* ds_build(ProblemDS* D, int n, double K, double mu, double alpha, int
         }
     if (rb.overflow) return "pressure mass: more couplings per row than the mesh allows";
     rb.to_ell(&L.A, Np);
-    if (const char* err = build_patch_tables(&L, Np, [](int v, int* dofs) {
+    if (const char* err = build_patch_tables(&L, Np, 1, [](int v, int* dofs) {
           dofs[0] = v;
           return 1;
         }))
@@ -364,7 +364,7 @@ size_t ds_plan(ProblemDS* D, char* base) {
     L.x = (double*)take((size_t)L.n0 * 8);
     L.b = (double*)take((size_t)L.n0 * 8);
     L.r = (double*)take((size_t)L.n0 * 8);
-    L.Y = (double*)take((size_t)L.nvert * kHdPatch * 8);
+    L.Y = (double*)take((size_t)L.nvert * L.pw * 8);
   };
   for (int l = 0; l < D->nlev; ++l) level(D->lev[l], l + 1 < D->nlev);
   level(D->mass, false);

@@ -156,10 +156,13 @@ bool spd_inverse(std::vector<double>& A, int m) {
   return true;
 }
 
-const char* build_patch_tables(HdLevel* L, int nvert, const std::function<int(int, int*)>& list) {
+const char* build_patch_tables(HdLevel* L, int nvert, int pw,
+                               const std::function<int(int, int*)>& list) {
   const int n0 = L->n0;
+  if (pw != 1 && pw != 8 && pw != kHdPatch) return "patch stride must be 1, 8 or 12";
   L->nvert = nvert;
-  L->patch.assign((size_t)nvert * kHdPatch, -1);
+  L->pw = pw;
+  L->patch.assign((size_t)nvert * pw, -1);
   L->ptype.assign(nvert, -1);
   L->slot.assign((size_t)n0 * 2, -1);
   std::vector<std::vector<double>> types;
@@ -168,6 +171,7 @@ const char* build_patch_tables(HdLevel* L, int nvert, const std::function<int(in
     int dofs[kHdPatch];
     const int m = list(v, dofs);
     if (m == 0) continue;
+    if (m > pw) return "a vertex patch has more dofs than the patch stride";
     std::sort(dofs, dofs + m);
     std::vector<double> A((size_t)m * m);
     for (int a = 0; a < m; ++a)
@@ -184,21 +188,21 @@ const char* build_patch_tables(HdLevel* L, int nvert, const std::function<int(in
     }
     L->ptype[v] = t;
     for (int a = 0; a < m; ++a) {
-      L->patch[(size_t)v * kHdPatch + a] = dofs[a];
+      L->patch[(size_t)v * pw + a] = dofs[a];
       int* s = &L->slot[(size_t)dofs[a] * 2];
       if (s[0] >= 0 && s[1] >= 0) return "a dof lies in more than two vertex patches";
-      s[s[0] < 0 ? 0 : 1] = v * kHdPatch + a;
+      s[s[0] < 0 ? 0 : 1] = v * pw + a;
     }
   }
   L->ntypes = (int)types.size();
-  L->pinv.assign((size_t)L->ntypes * kHdPatch * kHdPatch, 0.0);
+  L->pinv.assign((size_t)L->ntypes * pw * pw, 0.0);
   for (int t = 0; t < L->ntypes; ++t) {
     std::vector<double> A = types[t];
     const int m = tsize[t];
     if (!spd_inverse(A, m)) return "a vertex patch matrix is not positive definite";
     for (int a = 0; a < m; ++a)
       for (int b = 0; b < m; ++b)
-        L->pinv[((size_t)t * kHdPatch + a) * kHdPatch + b] = A[(size_t)a * m + b];
+        L->pinv[((size_t)t * pw + a) * pw + b] = A[(size_t)a * m + b];
   }
   return nullptr;
 }

@@ -32,10 +32,11 @@ void ell_transpose(const HdMat& P, int cols, HdMat* R);
 // SPD inverse by Cholesky (row-major, in place); false if not positive definite.
 bool spd_inverse(std::vector<double>& A, int m);
 
-// Vertex-patch tables of level L (its matrix L->A set): `list(v, dofs)` writes the dofs of patch
-// v (at most kHdPatch) and returns their count (0: no patch).  Every dof may lie in at most two
-// patches.  Patch matrices are deduplicated into types (congruent patches are bit-identical) and
-// inverted.  Returns nullptr or a message.
-const char* build_patch_tables(HdLevel* L, int nvert, const std::function<int(int, int*)>& list);
+// Vertex-patch tables of level L (its matrix L->A set) with patch stride pw (1, 8 or kHdPatch):
+// `list(v, dofs)` writes the dofs of patch v (at most pw) and returns their count (0: no patch).
+// Every dof may lie in at most two patches.  Patch matrices are deduplicated into types
+// (congruent patches are bit-identical) and inverted.  Returns nullptr or a message.
+const char* build_patch_tables(HdLevel* L, int nvert, int pw,
+                               const std::function<int(int, int*)>& list);
 
 }  // namespace fdd

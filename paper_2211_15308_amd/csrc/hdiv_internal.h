@@ -73,10 +73,11 @@ struct HdLevel {
   int ntypes = 0;   // distinct patch matrices
   HdMat A;          // A^00 of this level (K(mass + div-div) on V_0)
   HdMat P, R;       // prolongation from the next coarser level (rows: this level) and R = P^T
-  std::vector<int> patch;   // nvert x kHdPatch interior dofs of the patch (-1: none)
+  int pw = kHdPatch;        // patch stride: 12 (H(div)), 8 (P2 velocity) or 1 (one-dof patches)
+  std::vector<int> patch;   // nvert x pw interior dofs of the patch (-1: none)
   std::vector<int> ptype;   // nvert: index of the patch matrix (-1: no interior edge)
-  std::vector<int> slot;    // n0 x 2: vertex * kHdPatch + position, for both endpoints (-1: none)
-  std::vector<double> pinv; // ntypes x kHdPatch x kHdPatch inverses (zero-padded)
+  std::vector<int> slot;    // n0 x 2: vertex * pw + position, for both patches holding the dof (-1: none)
+  std::vector<double> pinv; // ntypes x pw x pw inverses (zero-padded)
   // device views
   int *dpatch = nullptr, *dptype = nullptr, *dslot = nullptr;
   double* dpinv = nullptr;

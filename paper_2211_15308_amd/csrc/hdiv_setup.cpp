@@ -203,7 +203,7 @@ void build_prolongation(int n, HdLevel* fine) {
 const char* build_patches(HdLevel* L) {
   const int n = L->n, n0 = L->n0;
   static const int nb[6][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}, {-1, -1}, {1, 1}};
-  return build_patch_tables(L, (n + 1) * (n + 1), [&](int v, int* dofs) {
+  return build_patch_tables(L, (n + 1) * (n + 1), kHdPatch, [&](int v, int* dofs) {
     const int i = v % (n + 1), j = v / (n + 1);
     int m = 0;
     for (int k = 0; k < 6; ++k) {
@@ -362,7 +362,7 @@ size_t hdiv_plan(ProblemHdiv* Q, char* base) {
     L.x = (double*)take((size_t)L.n0 * 8);
     L.b = (double*)take((size_t)L.n0 * 8);
     L.r = (double*)take((size_t)L.n0 * 8);
-    L.Y = (double*)take((size_t)L.nvert * kHdPatch * 8);
+    L.Y = (double*)take((size_t)L.nvert * L.pw * 8);
   }
   Q->dcinv = (double*)take(Q->cinv.size() * 8);
   mat(Q->A0G);

@@ -117,6 +117,7 @@ inline int row_blocks(int64_t n) { return (int)std::min<int64_t>(blocks_for(n), 
 
 // ---- sparse products, smoother, coarse solve ------------------------------------------------
 
+template <int PW>
 __device__ __forceinline__ void patch_solve_vertex(const int* __restrict__ patch,
                                                    const int* __restrict__ ptype,
                                                    const double* pinv, int v,
@@ -124,21 +125,21 @@ __device__ __forceinline__ void patch_solve_vertex(const int* __restrict__ patch
                                                    double* __restrict__ Y) {
   const int t = ptype[v];
   if (t < 0) return;
-  double rl[kHdPatch];
+  double rl[PW];
 #pragma unroll
-  for (int k = 0; k < kHdPatch; ++k) {
-    const int d = patch[(size_t)v * kHdPatch + k];
+  for (int k = 0; k < PW; ++k) {
+    const int d = patch[(size_t)v * PW + k];
     rl[k] = d >= 0 ? r[d] : 0.0;
   }
-  const double* Pi = pinv + (size_t)t * kHdPatch * kHdPatch;
-  // every slot is written (a lane's 12 values are contiguous, so the stores combine; slots
+  const double* Pi = pinv + (size_t)t * PW * PW;
+  // every slot is written (a lane's PW values are contiguous, so the stores combine; slots
   // without a dof hold 0 and are never read back)
 #pragma unroll
-  for (int a = 0; a < kHdPatch; ++a) {
+  for (int a = 0; a < PW; ++a) {
     double y = 0.0;
 #pragma unroll
-    for (int b = 0; b < kHdPatch; ++b) y += Pi[a * kHdPatch + b] * rl[b];
-    Y[(size_t)v * kHdPatch + a] = y;
+    for (int b = 0; b < PW; ++b) y += Pi[a * PW + b] * rl[b];
+    Y[(size_t)v * PW + a] = y;
   }
 }
 
@@ -175,18 +176,19 @@ __global__ __launch_bounds__(kT) void k_hd_residual(HdView A, const double* __re
 }
 
 // (the few inverse patch matrices are staged in LDS: every lane reads a row of its vertex's)
+template <int PW>
 __global__ __launch_bounds__(kT) void k_hd_patch_solve(const int* __restrict__ patch,
                                                        const int* __restrict__ ptype,
                                                        const double* __restrict__ pinv, int ntypes,
                                                        int nvert, const double* __restrict__ r,
                                                        double* __restrict__ Y, const HdState* stop) {
   if (stopped(stop)) return;
-  __shared__ double sp[kHdMaxTypes * kHdPatch * kHdPatch];
-  for (int k = threadIdx.x; k < ntypes * kHdPatch * kHdPatch; k += kT) sp[k] = pinv[k];
+  __shared__ double sp[kHdMaxTypes * PW * PW];
+  for (int k = threadIdx.x; k < ntypes * PW * PW; k += kT) sp[k] = pinv[k];
   __syncthreads();
   const int v = blockIdx.x * kT + threadIdx.x;
   if (v >= nvert) return;
-  patch_solve_vertex(patch, ptype, sp, v, r, Y);
+  patch_solve_vertex<PW>(patch, ptype, sp, v, r, Y);
 }
 
 __global__ __launch_bounds__(kT) void k_hd_patch_sum(const int* __restrict__ slot, int n0,
@@ -579,9 +581,15 @@ void launch_hd_residual(hipStream_t s, HdView A, const double* b, const double* 
 }
 
 void launch_hd_patch_solve(hipStream_t s, const HdLevel& L, const double* r, const HdState* stop) {
-  hipLaunchKernelGGL(k_hd_patch_solve, dim3(blocks_for(L.nvert)), dim3(kT), 0, s,
-                     (const int*)L.dpatch, (const int*)L.dptype, (const double*)L.dpinv, L.ntypes,
-                     L.nvert, r, L.Y, stop);
+  // the patch stride is a template argument (12: H(div), 8: P2 velocity, 1: one-dof patches)
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, dim3(blocks_for(L.nvert)), dim3(kT), 0, s, (const int*)L.dpatch,
+                       (const int*)L.dptype, (const double*)L.dpinv, L.ntypes, L.nvert, r, L.Y,
+                       stop);
+  };
+  if (L.pw == 1) go(k_hd_patch_solve<1>);
+  else if (L.pw == 8) go(k_hd_patch_solve<8>);
+  else go(k_hd_patch_solve<kHdPatch>);
 }
 
 void launch_hd_patch_sum(hipStream_t s, const HdLevel& L, double theta, double* x, int add,
