@@ -316,8 +316,10 @@ typedef struct {
   int velocity_maxit;     /* (100) */
   int mg_nu;              /* smoothing steps of the velocity V-cycle, 1 (default: the PCG to
                              velocity_rtol) or 2 (the better choice for one V-cycle)          */
-  double pressure_rtol;   /* mu^{-1} M_p block: Jacobi-PCG to this relative residual (1e-12)  */
-  int pressure_maxit;     /* (200) */
+  double pressure_rtol;   /* mu^{-1} M_p block: Jacobi-preconditioned Chebyshev iteration on the
+                             spectrum [1/2, 2] of D^{-1} M_p with the step count that bounds the
+                             relative residual by this (1e-12: 27 steps)                      */
+  int pressure_maxit;     /* cap on those steps (200) */
   double darcy_rtol;      /* Darcy block: fdd_solve_full on the facet problem to this relative
                              preconditioned residual (1e-5, the Appendix; Sec. 4: 1e-4)      */
   int darcy_maxit;        /* (200) */
@@ -331,7 +333,7 @@ typedef struct {
   int its;                  /* FGMRES iterations                                             */
   int velocity_its_total;   /* PCG iterations (or V-cycles) of the velocity block, summed     */
   int velocity_its_max;
-  int pressure_its_total;
+  int pressure_its_total;   /* Chebyshev steps of the pressure block, summed                  */
   int darcy_its_total;      /* PCG iterations of the Darcy block, summed                      */
   int darcy_its_max;
   double rel_res;           /* FGMRES's least-squares residual / ||b||                        */

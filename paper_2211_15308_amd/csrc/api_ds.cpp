@@ -8,7 +8,8 @@
 //   * A_u (mu-Laplacian of the P2 velocity plus the Beavers-Joseph-Saffman term on Gamma): PCG
 //     with a multigrid V-cycle (nested P2 spaces, additive Schwarz over vertex patches) to a
 //     relative tolerance, or one V-cycle (the setting of Sec. 4);
-//   * mu^{-1} M_p (P1 Stokes pressure mass): PCG with Jacobi to a relative tolerance;
+//   * mu^{-1} M_p (P1 Stokes pressure mass): Jacobi-preconditioned Chebyshev iteration with the
+//     step count that guarantees a relative tolerance (the spectrum of D^{-1} M_p is known);
 //   * the Darcy block, the Riesz map of eq. (riesz) with gamma = 1/mu: PCG on the facet problem
 //     with the lazy preconditioner of eq. (dd_preconditioner) (one V-cycle for the leading block,
 //     the rational table for S_Gamma, H by its rational table in the operator) to a relative
@@ -31,7 +32,37 @@ using namespace fdd;
 namespace {
 
 constexpr double kThetaU = 0.5;   // damping of the velocity smoother (overlapping vertex patches)
-constexpr double kThetaP = 1.0;   // the pressure mass: plain Jacobi
+
+// The P1 pressure mass under Jacobi: on a triangle, D_T^{-1} M_T (D_T = diag(M_T) = |T|/6 I,
+// M_T = |T|/12 (I + 1 1^T)) has eigenvalues 1/2 (twice) and 2; since x^T M x = sum_T x_T^T M_T x_T
+// and D = sum_T D_T, the spectrum of D^{-1} M_p lies in [1/2, 2].  Chebyshev on that interval
+// reduces the residual in the D^{-1} norm by 2 rho^k after k steps, rho = (sqrt(4) - 1) /
+// (sqrt(4) + 1) = 1/3; the diagonal varies by at most a factor 6 (one to six triangles at a
+// vertex), so the Euclidean residual falls by 2 sqrt(6) rho^k.
+constexpr double kMassLo = 0.5, kMassHi = 2.0;
+
+int cheb_steps(double rtol, int maxit) {
+  const double rho = 1.0 / 3.0;
+  const int k = (int)std::ceil(std::log(rtol / (2.0 * std::sqrt(6.0))) / std::log(rho));
+  return std::max(1, std::min(k, maxit));
+}
+
+// x = M_p^{-1} b by `steps` Jacobi-Chebyshev steps (x_0 = 0); returns the buffer holding x
+const double* mass_solve(const ProblemDS* D, hipStream_t s, int steps, const double* b) {
+  const double theta = 0.5 * (kMassHi + kMassLo), delta = 0.5 * (kMassHi - kMassLo);
+  const double sigma = theta / delta;
+  double* cur = D->pz;
+  double* nxt = D->pq;
+  launch_hd_cheb_step(s, D->mass, b, nullptr, cur, D->pp, 0.0, 1.0 / theta, 1);
+  double rho_prev = 1.0 / sigma;
+  for (int k = 1; k < steps; ++k) {
+    const double rho = 1.0 / (2.0 * sigma - rho_prev);
+    launch_hd_cheb_step(s, D->mass, b, cur, nxt, D->pp, rho * rho_prev, 2.0 * rho / delta, 0);
+    std::swap(cur, nxt);
+    rho_prev = rho;
+  }
+  return cur;
+}
 
 EllHier hier_u(const ProblemDS* D) {
   EllHier H;
@@ -47,23 +78,6 @@ EllHier hier_u(const ProblemDS* D) {
   H.partials = D->partials;
   H.st = D->st_u;
   H.hst = D->hst_u;
-  return H;
-}
-
-EllHier hier_p(const ProblemDS* D) {
-  EllHier H;
-  H.lev = &D->mass;
-  H.nlev = 1;
-  H.cinv = nullptr;
-  H.theta = kThetaP;
-  H.n0 = D->Np;
-  H.r = D->pr;
-  H.z = D->pz;
-  H.p = D->pp;
-  H.q = D->pq;
-  H.partials = D->partials;
-  H.st = D->st_p;
-  H.hst = D->hst_p;
   return H;
 }
 
@@ -107,11 +121,9 @@ int precond(fdd_problem_s* P, const fdd_ratpc_s* PT, const fdd_ratpc_s* HT, cons
   st->velocity_its_total += its;
   st->velocity_its_max = std::max(st->velocity_its_max, its);
   // Stokes pressure: (mu^{-1} M_p)^{-1} r_p = mu M_p^{-1} r_p
-  rc = ell_pcg(hier_p(D), s, 1, o.pressure_rtol, o.pressure_maxit, r + Nu, D->tmp, &D->its_p, &its,
-               "Darcy-Stokes pressure block");
-  if (rc) return rc;
-  launch_ds_scale(s, Np, D->mu, D->tmp, z + Nu);
-  st->pressure_its_total += its;
+  const int steps = cheb_steps(o.pressure_rtol, o.pressure_maxit);
+  launch_ds_scale(s, Np, D->mu, mass_solve(D, s, steps, r + Nu), z + Nu);
+  st->pressure_its_total += steps;
   // Darcy: PCG on the Riesz map with the lazy preconditioner
   fdd_opts fo;
   fdd_opts_default(&fo);
@@ -167,7 +179,6 @@ int ds_bind(fdd_problem_s* P, void* dev, size_t bytes, hipStream_t s) {
   ds_plan(D, base);
   if (!D->hst) HIPCHK(hipHostMalloc((void**)&D->hst, sizeof(DsState), hipHostMallocDefault));
   if (!D->hst_u) HIPCHK(hipHostMalloc((void**)&D->hst_u, sizeof(HdState), hipHostMallocDefault));
-  if (!D->hst_p) HIPCHK(hipHostMalloc((void**)&D->hst_p, sizeof(HdState), hipHostMallocDefault));
   HIPCHK(hipMemsetAsync(base, 0, need - nd, s));
   auto up = [&](void* dst, const void* src, size_t nb) -> int {
     if (nb) HIPCHK(hipMemcpyAsync(dst, src, nb, hipMemcpyHostToDevice, s));
@@ -205,7 +216,6 @@ void ds_destroy(fdd_problem_s* P) {
   fdd_destroy_problem(D->darcy);
   if (D->hst) (void)hipHostFree(D->hst);
   if (D->hst_u) (void)hipHostFree(D->hst_u);
-  if (D->hst_p) (void)hipHostFree(D->hst_p);
   delete D;
   P->pds = nullptr;
 }

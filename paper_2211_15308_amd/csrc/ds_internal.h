@@ -38,24 +38,23 @@ struct ProblemDS {
   double K = 1, mu = 1, alpha = 0;
   int Nu = 0, Np = 0, ND = 0, N = 0;
   // the velocity block a(., .) on every level (finest first) and the pressure mass (one level,
-  // one-dof patches: Jacobi)
+  // one-dof patches: the Jacobi diagonal of its Chebyshev iteration)
   HdLevel lev[kHdMaxLevels];
   HdLevel mass;
   std::vector<double> cinv;   // dense inverse of the coarsest velocity matrix (row-major)
   // the coupled operator by row blocks, global columns: [A_u B^T C], [B], [C^T -K A_D]
   HdMat Au, Bp, Dd;
   fdd_problem_s* darcy = nullptr;  // the facet problem of the Darcy block (own workspace)
-  int its_u = 0, its_p = 0;        // iterations of the last velocity / pressure solves
+  int its_u = 0;                   // iterations of the last velocity solve
   // device
   double* dcinv = nullptr;
   double *ur = nullptr, *uz = nullptr, *up = nullptr, *uq = nullptr;   // velocity PCG
-  double *pr = nullptr, *pz = nullptr, *pp = nullptr, *pq = nullptr;   // pressure PCG
+  double *pz = nullptr, *pq = nullptr, *pp = nullptr;   // pressure Chebyshev: x (two), d
   double *V = nullptr, *Z = nullptr;       // (krylov + 1) x N and krylov x N
   double *Hm = nullptr;                    // (krylov + 1) x krylov, column-major
   double *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *hp = nullptr;
-  double *tmp = nullptr;                   // N
   double* partials = nullptr;              // (krylov + 1) x kDsChunks
-  HdState *st_u = nullptr, *st_p = nullptr, *hst_u = nullptr, *hst_p = nullptr;
+  HdState *st_u = nullptr, *hst_u = nullptr;
   DsState* st = nullptr;
   DsState* hst = nullptr;
   size_t ws_need = 0;

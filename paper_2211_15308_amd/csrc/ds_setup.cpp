@@ -377,10 +377,9 @@ size_t ds_plan(ProblemDS* D, char* base) {
   D->uz = (double*)take(nu);
   D->up = (double*)take(2 * nu);
   D->uq = (double*)take(nu);
-  D->pr = (double*)take(np);
   D->pz = (double*)take(np);
-  D->pp = (double*)take(2 * np);
   D->pq = (double*)take(np);
+  D->pp = (double*)take(np);
   const size_t m = (size_t)D->krylov;
   D->V = (double*)take((m + 1) * N);
   D->Z = (double*)take(m * N);
@@ -390,10 +389,8 @@ size_t ds_plan(ProblemDS* D, char* base) {
   D->g = (double*)take((m + 1) * 8);
   D->y = (double*)take(m * 8);
   D->hp = (double*)take((m + 1) * 8);
-  D->tmp = (double*)take(N);
   D->partials = (double*)take(std::max<size_t>((m + 1) * kDsChunks, 2 * kHdPartials) * 8);
   D->st_u = (HdState*)take(sizeof(HdState));
-  D->st_p = (HdState*)take(sizeof(HdState));
   D->st = (DsState*)take(sizeof(DsState));
   return (off + 255) / 256 * 256;
 }

@@ -139,6 +139,11 @@ void launch_hd_patch_solve(hipStream_t s, const HdLevel& L, const double* r, con
 // x = (add ? x : 0) + theta (sum of the patch solutions holding each dof)
 void launch_hd_patch_sum(hipStream_t s, const HdLevel& L, double theta, double* x, int add,
                          const HdState* stop);
+// One Jacobi-Chebyshev step for L.A x = b on a level with one-dof patches (the diagonal
+// inverse): first: d = c_res D^{-1} b, x_out = d; else d = c_prev d + c_res D^{-1} (b - A x_in),
+// x_out = x_in + d
+void launch_hd_cheb_step(hipStream_t s, const HdLevel& L, const double* b, const double* x_in,
+                         double* x_out, double* d, double c_prev, double c_res, int first);
 // x = C b on the coarsest level (dense, row-major C, one wave per row)
 void launch_hd_coarse(hipStream_t s, const double* C, int n0, const double* b, double* x,
                       const HdState* stop);

@@ -201,6 +201,36 @@ __global__ __launch_bounds__(kT) void k_hd_patch_sum(const int* __restrict__ slo
   patch_sum_dof(slot, i, Y, theta, x, add);
 }
 
+// One step of the Jacobi-preconditioned Chebyshev iteration for A x = b (x_0 = 0), the diagonal
+// inverse from one-dof patches (Dinv_i = pinv[ptype[i]]):
+//   first: d = c_res Dinv b, x_out = d;
+//   else:  r = b - A x_in (formed here), d = c_prev d + c_res Dinv r, x_out = x_in + d.
+// One launch per step, no inner products (the step count follows from the spectral bounds).
+__global__ __launch_bounds__(kT) void k_hd_cheb_step(HdView A, const int* __restrict__ ptype,
+                                                     const double* __restrict__ pinv,
+                                                     const double* __restrict__ b,
+                                                     const double* __restrict__ x_in,
+                                                     double* __restrict__ x_out,
+                                                     double* __restrict__ d, double c_prev,
+                                                     double c_res, int first) {
+  __shared__ TabLds T;
+  const bool lds = stage_table(A, T);
+  for (int i = blockIdx.x * kT + threadIdx.x; i < A.rows; i += gridDim.x * kT) {
+    const double dinv = pinv[ptype[i]];
+    if (first) {
+      const double di = c_res * dinv * b[i];
+      d[i] = di;
+      x_out[i] = di;
+    } else {
+      const double r = b[i] - (lds ? ell_row_tab<true>(A, T, i, x_in)
+                                   : ell_row_tab<false>(A, T, i, x_in));
+      const double di = c_prev * d[i] + c_res * dinv * r;
+      d[i] = di;
+      x_out[i] = x_in[i] + di;
+    }
+  }
+}
+
 __device__ __forceinline__ double dense_row(const double* __restrict__ C, int n0, int row, int lane,
                                             const double* __restrict__ b) {
   const double* c = C + (size_t)row * n0;
@@ -596,6 +626,13 @@ void launch_hd_patch_sum(hipStream_t s, const HdLevel& L, double theta, double* 
                          const HdState* stop) {
   hipLaunchKernelGGL(k_hd_patch_sum, dim3(blocks_for(L.n0)), dim3(kT), 0, s, (const int*)L.dslot,
                      L.n0, (const double*)L.Y, theta, x, add, stop);
+}
+
+void launch_hd_cheb_step(hipStream_t s, const HdLevel& L, const double* b, const double* x_in,
+                         double* x_out, double* d, double c_prev, double c_res, int first) {
+  hipLaunchKernelGGL(k_hd_cheb_step, dim3(row_blocks(L.A.rows)), dim3(kT), 0, s, view(L.A),
+                     (const int*)L.dptype, (const double*)L.dpinv, b, x_in, x_out, d, c_prev,
+                     c_res, first);
 }
 
 void launch_hd_coarse(hipStream_t s, const double* C, int n0, const double* b, double* x,
