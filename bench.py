@@ -699,13 +699,14 @@ def run_hdiv(F, args, leg, n=512, reps=2, gammas=(1e-3, 1.0, 1e3), robust_sizes=
 def run_darcy_stokes(F, args, leg, sizes=(256, 512), reps=2, params=((1e-2, 1e-4), (1.0, 1.0)),
                      alpha=3.0, robust_sizes=(64, 128, 256)):
     """The Darcy-Stokes outer solver (Sec. 4 eq. (darcy_stokes), eq. (darcy_stokes_precond);
-    Appendix): FGMRES to rtol 1e-10 with the block-diagonal preconditioner (velocity and pressure
-    blocks by PCG to 1e-12 (velocity V-cycle nu = 1), the Darcy block by the lazy PCG to 1e-5 as
-    in the Appendix; alpha = 3).  Solves/s per size and (K, mu) with FGMRES and inner counts and
-    true residuals, the setting of Sec. 4 (one V-cycle for the Stokes blocks: one nu = 2 velocity
-    V-cycle and the pressure-mass PCG to 1e-3, about seven Jacobi steps; Darcy PCG to 1e-4), FGMRES counts over n (Fig. 6), a parity
-    spot-check at n = 32 against the oracle's sparse LU, and the oracle's FGMRES (sparse LU for the
-    Stokes blocks and the Riesz map) timed at n = 32.  FP64 throughout."""
+    Appendix): FGMRES to rtol 1e-10 with the block-diagonal preconditioner.  Appendix setting:
+    velocity and pressure blocks to 1e-12 (velocity PCG with a nu = 1 V-cycle, pressure mass by
+    Chebyshev), the Darcy block by the lazy PCG to 1e-5; Sec. 4 setting: one V-cycle for the Stokes
+    blocks (one nu = 2 velocity V-cycle, the pressure mass to 1e-3, eight Chebyshev steps), Darcy
+    PCG to 1e-4; alpha = 3.  Solves/s per size and (K, mu) with FGMRES and inner counts and true
+    residuals, FGMRES counts over n (Fig. 6), a parity spot-check at n = 32 against the oracle's
+    sparse LU, and the oracle's FGMRES (sparse LU for the Stokes blocks and the Riesz map) timed at
+    n = 32.  FP64 throughout."""
     import numpy as np
     import torch
 
