@@ -703,7 +703,7 @@ def run_darcy_stokes(F, args, leg, sizes=(256, 512), reps=2, params=((1e-2, 1e-4
     velocity and pressure blocks to 1e-12 (velocity PCG with a nu = 1 V-cycle, pressure mass by
     Chebyshev), the Darcy block by the lazy PCG to 1e-5; Sec. 4 setting: one V-cycle for the Stokes
     blocks (one nu = 2 velocity V-cycle, the pressure mass to 1e-3, eight Chebyshev steps), Darcy
-    PCG to 1e-4; alpha = 3.  Solves/s per size and (K, mu) with FGMRES and inner counts and true
+    PCG to 1e-4 with FP32 V-cycles; alpha = 3.  Solves/s per size and (K, mu) with FGMRES and inner counts and true
     residuals, FGMRES counts over n (Fig. 6), a parity spot-check at n = 32 against the oracle's
     sparse LU, and the oracle's FGMRES (sparse LU for the Stokes blocks and the Riesz map) timed at
     n = 32.  FP64 throughout."""
@@ -722,7 +722,7 @@ def run_darcy_stokes(F, args, leg, sizes=(256, 512), reps=2, params=((1e-2, 1e-4
 
     settings = (("appendix", F.ds_opts_default(rtol=rtol)),
                 ("sec4", F.ds_opts_default(rtol=rtol, velocity_rtol=0.0, darcy_rtol=1e-4, mg_nu=2,
-                                           pressure_rtol=1e-3)))
+                                           pressure_rtol=1e-3, darcy_precision=F.FDD_MIXED)))
     for n in sizes:
         for K, mu in (params if n == sizes[0] else params[:1]):
             P, TP, TH = problem(n, K, mu)
