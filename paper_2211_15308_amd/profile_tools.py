@@ -9,6 +9,7 @@ under profiles/.  Command line:
   python -m paper_2211_15308_amd.profile_tools csvstats <kernel_stats.csv>
   python -m paper_2211_15308_amd.profile_tools csvpmc <counter_collection.csv>
   python -m paper_2211_15308_amd.profile_tools csvtrace <kernel_trace.csv> <name> <split_us>
+  python -m paper_2211_15308_amd.profile_tools csvgrid <kernel_trace.csv> [rows]
   python -m paper_2211_15308_amd.profile_tools traffic <fetch.csv> <write.csv> <kernel> <out.json>
   python -m paper_2211_15308_amd.profile_tools traffic_batched <fetch.csv> <write.csv> <kernel> <out.json>
 
@@ -103,6 +104,20 @@ def csv_trace_split(path, name, split_us):
     return durs, long
 
 
+def csv_grid_groups(path):
+    """Rows (kernel, threads of the grid, calls, average us, total us) of a kernel_trace.csv grouped
+    by kernel and grid size (for multigrid kernels: by level), sorted by total time."""
+    groups = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        threads = 1
+        for ax in ("X", "Y", "Z"):
+            threads *= int(r.get(f"Grid_Size_{ax}", "1") or 1)
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        groups[(short_name(r["Kernel_Name"]), threads)].append(dur)
+    out = [(k, t, len(v), sum(v) / len(v), sum(v)) for (k, t), v in groups.items()]
+    return sorted(out, key=lambda row: -row[4])
+
+
 def traffic_record(fetch_csv, write_csv, kernel, copy_bytes=256 << 20):
     """HBM bytes per working dispatch of `kernel`, each counter scaled by the copy's reading."""
     fet, wri = csv_pmc(fetch_csv), csv_pmc(write_csv)
@@ -145,6 +160,13 @@ def main(argv):
         print(f"{'total_us':>12} {'pct':>6} {'calls':>7} {'avg_us':>9}  kernel")
         for name, calls, tot, avg, pct in csv_kernel_stats(argv[1]):
             print(f"{tot:12.1f} {pct:6.2f} {calls:7d} {avg:9.2f}  {short_name(name)}")
+    elif argv[0] == "csvgrid":
+        rows = csv_grid_groups(argv[1])
+        total = sum(r[4] for r in rows)
+        print(f"total kernel time {total / 1e3:.1f} ms")
+        print(f"{'kernel':40s} {'threads':>9} {'calls':>7} {'avg_us':>8} {'pct':>6}")
+        for name, threads, calls, avg, tot in rows[:int(argv[2]) if len(argv) > 2 else 30]:
+            print(f"{name[:40]:40s} {threads:9d} {calls:7d} {avg:8.2f} {100 * tot / total:6.2f}")
     elif argv[0] == "csvpmc":
         for k, (n, cn, vals) in sorted(csv_pmc(argv[1]).items(), key=lambda kv: -sum(kv[1][2])):
             big = [v for v in vals if v > 0.1 * max(vals)]
