@@ -166,6 +166,34 @@ def test_outer_counts_bounded_in_h_and_gamma(gamma):
     assert max(counts) <= 30 and max(counts) - min(counts) <= 3
 
 
+def test_solve_n256_against_golden():
+    # n = 256 (394,240 dofs) against the oracle's sparse-LU solution (refined to the rounding floor
+    # of its residual) written by tests/golden/make_hdiv_n256.py (4096 seeded entries and the norm)
+    import json
+    import os
+
+    import workloads
+    G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "solve_hdiv_n256.json")))
+    n, K, gamma = G["n"], G["K"], G["gamma"]
+    print(f"[hdiv n256] n={n} K={K} gamma={gamma} against the stored oracle solution", flush=True)
+    P = F.setup_hdiv(n, K, gamma)
+    P.bind_workspace()
+    assert P.N == G["N"]
+    TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+    b = workloads.normal_vector(P.N, 2560)
+    x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+    st = P.solve(TP, None, dev(b), x, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12,
+                                                     check_true_residual=1))
+    xh = host(x)
+    idx = np.array(G["indices"])
+    ref = np.array(G["values"])
+    err = float(np.linalg.norm(xh[idx] - ref) / np.linalg.norm(ref))
+    nerr = abs(np.linalg.norm(xh) - G["norm_x"]) / G["norm_x"]
+    print(f"[hdiv n256] outer {st['outer_its']} sampled rel err {err:.2e} norm rel err {nerr:.2e} "
+          f"res {st['true_rel_res']:.2e}", flush=True)
+    assert err <= 1e-8 and nerr <= 1e-8
+
+
 def test_hdiv_error_paths():
     for args in ((6, 1.0, 1.0), (2, 1.0, 1.0), (2048, 1.0, 1.0), (8, 0.0, 1.0), (8, 1.0, -1.0)):
         with pytest.raises(F.FddError) as e:

@@ -173,6 +173,36 @@ def test_solve_large_residual(n, t):
         assert st["outer_its"] <= 40
 
 
+def test_solve_n512_against_golden():
+    # n = 512 (263,169 unknowns) against the oracle's sparse-LU solution of the exact-L^t system
+    # written by tests/golden/make_model_n512.py (4096 seeded entries and the norm); the library
+    # applies L^t by its 1e-12 table, whose effect on the solution is far below the 1e-8 bar
+    import json
+    import os
+
+    import workloads
+    G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "solve_model_n512.json")))
+    n, K, gamma, t = G["n"], G["K"], G["gamma"], G["t"]
+    print(f"[model n512] n={n} t={t} against the stored oracle solution", flush=True)
+    P = F.setup_model(n, K, gamma, t)
+    P.bind_workspace()
+    assert P.N == G["N"]
+    TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+    TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+    b = workloads.normal_vector(P.N, 5120)
+    x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+    st = P.solve(TP, TH, dev(b), x, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12,
+                                                   check_true_residual=1))
+    xh = host(x)
+    idx = np.array(G["indices"])
+    ref = np.array(G["values"])
+    err = float(np.linalg.norm(xh[idx] - ref) / np.linalg.norm(ref))
+    nerr = abs(np.linalg.norm(xh) - G["norm_x"]) / G["norm_x"]
+    print(f"[model n512] outer {st['outer_its']} sampled rel err {err:.2e} norm rel err {nerr:.2e} "
+          f"res {st['true_rel_res']:.2e}", flush=True)
+    assert err <= 1e-8 and nerr <= 1e-8
+
+
 def test_model_error_paths():
     for args in ((1026, 1.0, 1.0, 0.5), (7, 1.0, 1.0, 0.5), (64, 1.0, 1.0, 1.0), (64, -1.0, 1.0, 0.0),
                  (64, 1.0, -1.0, 0.0)):
