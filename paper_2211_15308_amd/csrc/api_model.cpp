@@ -67,14 +67,14 @@ int model_inner_t(fdd_problem_s* P, hipStream_t s, const fdd_opts& o, const VSet
   launch_model_ii_start<VT>(s, nf, pitch, b.f, b.x, b.r, v.vr, P->st, P->partials,
                             o.inner_rtol * o.inner_rtol);
   launch_vcycle<VT>(c, *v.mg, v.vr, v.Z);
-  launch_model_ii_rz<VT>(s, nf, pitch, b.r, v.Z, 1.0, P->st, P->partials, 1);
+  launch_model_ii_rz<VT>(s, nf, pitch, b.r, v.Z, 1.0, P->st, P->partials);
   int k = 0, want = std::max(P->model_its_hint, 2), rc;
   for (;;) {
     for (; k < want && k < o.inner_maxit; ++k) {
       launch_model_ii_step<VT>(s, n, pitch, v.Z, 1.0, b.p[k & 1], b.p[(k + 1) & 1], b.q, b.x, b.r,
                                v.vr, P->st, P->partials, k == 0 ? 1 : 0);
       launch_vcycle<VT>(c, *v.mg, v.vr, v.Z);
-      launch_model_ii_rz<VT>(s, nf, pitch, b.r, v.Z, 1.0, P->st, P->partials, 0);
+      launch_model_ii_rz<VT>(s, nf, pitch, b.r, v.Z, 1.0, P->st, P->partials);
     }
     HIPCHK(hipGetLastError());
     if ((rc = read_state(P, s))) return rc;

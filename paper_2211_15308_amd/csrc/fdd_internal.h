@@ -368,14 +368,16 @@ void launch_model_full_apply(hipStream_t s, int n, double K, double gamma, const
 void launch_model_loop_batch(hipStream_t s, int n, const ShiftTable& tab, int mode,
                              const double* in, double* out, double* scratch);
 // interior PCG on A_II = A_Omega + M_Omega (interior block) with V-cycles of the 5-point
-// Laplacian as the preconditioner (scalars and flags in st: rho, cg_alpha[0], cg_gam[1], rr, ff,
-// tol2, inner_done, inner_its)
+// Laplacian as the preconditioner (scalars and flags in st: rho, pq, cg_alpha[0], cg_gam, rr, ff,
+// tol2, inner_done, inner_its).  ii_rz leaves the partials of r.z; ii_step sums them (beta),
+// forms p and q = A_II p, sums p.q (alpha), updates x and r and tests ||r||.  partials holds
+// 8192 doubles.
 template <typename VT>
 void launch_model_ii_start(hipStream_t s, int nf, int pitch, const double* f, double* x,
                            double* r, VT* vr, DevState* st, double* partials, double tol2);
 template <typename VT>
 void launch_model_ii_rz(hipStream_t s, int nf, int pitch, const double* r, const VT* Z, double zs,
-                        DevState* st, double* partials, int first);
+                        DevState* st, double* partials);
 template <typename VT>
 void launch_model_ii_step(hipStream_t s, int n, int pitch, const VT* Z, double zs, double* p_old,
                           double* p_new, double* q, double* x, double* r, VT* vr, DevState* st,

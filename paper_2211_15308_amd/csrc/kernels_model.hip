@@ -322,17 +322,34 @@ __global__ __launch_bounds__(kIfaceThreads) void km_loop_combine(int m, double h
 
 // ---- interior PCG (A_II = A_Omega + M_Omega on the interior nodes, Dirichlet-zero boundary) ---
 
-// p = Z zs + beta p' (formed where read; first: p = Z zs), q = B_II p, partials of p.q.
+// rz = r . Z zs from the partials of km_ii_rz (every block sums them in the same order), beta =
+// rz / rho (first: 0); p = Z zs + beta p' (formed where read; first: p = Z zs), q = B_II p,
+// partials of p.q into pq_partials.  rho is read here by every block, so block 0 parks rz in
+// cg_gam[0] and km_ii_update moves it to rho.
 template <typename VT>
 __global__ __launch_bounds__(kModelThreads) void km_ii_apply(int n, int pitch, double h2,
                                                              const VT* __restrict__ Z, double zs,
                                                              const double* __restrict__ po,
                                                              double* __restrict__ pn,
-                                                             double* __restrict__ q,
-                                                             const DevState* st, int first,
-                                                             double* __restrict__ partials) {
+                                                             double* __restrict__ q, DevState* st,
+                                                             int first,
+                                                             const double* __restrict__ rz_partials,
+                                                             int nb_rz,
+                                                             double* __restrict__ pq_partials) {
   if (st->inner_done) return;
-  const double beta = first ? 0.0 : st->cg_gam[1];
+  const double rz = block_sum_partials(rz_partials, nb_rz, 1);
+  if (!(rz > 0.0) || !isfinite(rz)) {  // r = 0 ends the solve; otherwise M is not SPD
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (rz != 0.0) st->breakdown |= isfinite(rz) ? 1 : 4;
+      st->inner_done = 1;
+    }
+    return;
+  }
+  const double beta = first ? 0.0 : rz / st->rho;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->cg_gam[0] = rz;
+    st->cg_gam[1] = beta;
+  }
   const int nf = n - 1;
   auto P = [&](int i, int j) -> double {  // 0-based interior indices, zero outside
     if (i < 0 || i >= nf || j < 0 || j >= nf) return 0.0;
@@ -354,37 +371,37 @@ __global__ __launch_bounds__(kModelThreads) void km_ii_apply(int n, int pitch, d
     q[o] = v;
     acc += c * v;
   }
-  mblock_partial(acc, partials);
+  mblock_partial(acc, pq_partials);
 }
 
-// alpha = rz / p.q (one block)
-__global__ __launch_bounds__(kModelThreads) void km_ii_alpha(DevState* st,
-                                                             const double* __restrict__ partials,
-                                                             int nb) {
-  if (st->inner_done) return;
-  const double pq = block_sum_partials(partials, nb, 1);
-  if (threadIdx.x != 0) return;
-  const bool ok = pq > 0.0 && isfinite(pq);
-  st->pq = pq;
-  st->cg_alpha[0] = ok ? st->rho / pq : 0.0;
-  if (!ok) {
-    st->breakdown |= isfinite(pq) ? 1 : 4;
-    st->inner_done = 1;
-  }
-}
-
-// x += alpha p, r -= alpha q, vr = r (V-cycle input), partials of ||r||^2
+// p.q from the partials of km_ii_apply (every block, same order), alpha = rz / p.q;
+// x += alpha p, r -= alpha q, vr = r (V-cycle input), partials of ||r||^2.  Block 0 records
+// p.q, alpha and rho = rz.
 template <typename VT>
 __global__ __launch_bounds__(kModelThreads) void km_ii_update(int nf, int pitch,
                                                               double* __restrict__ x,
                                                               double* __restrict__ r,
                                                               const double* __restrict__ p,
                                                               const double* __restrict__ q,
-                                                              VT* __restrict__ vr,
-                                                              const DevState* st,
+                                                              VT* __restrict__ vr, DevState* st,
+                                                              const double* __restrict__ pq_partials,
+                                                              int nb_pq,
                                                               double* __restrict__ partials) {
   if (st->inner_done) return;
-  const double al = st->cg_alpha[0];
+  const double pq = block_sum_partials(pq_partials, nb_pq, 1);
+  const double rz = st->cg_gam[0];
+  const bool ok = pq > 0.0 && isfinite(pq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->pq = pq;
+    st->cg_alpha[0] = ok ? rz / pq : 0.0;
+    st->rho = rz;
+    if (!ok) {
+      st->breakdown |= isfinite(pq) ? 1 : 4;
+      st->inner_done = 1;
+    }
+  }
+  if (!ok) return;
+  const double al = rz / pq;
   double acc = 0.0;
   const int64_t tot = (int64_t)nf * nf;
   for (int64_t k = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; k < tot;
@@ -448,7 +465,7 @@ __global__ __launch_bounds__(kModelThreads) void km_ii_check(DevState* st,
   }
 }
 
-// rz = r . Z zs (partials), then (one block) beta = rz / rz_prev, rho = rz
+// partials of rz = r . Z zs (summed by the next km_ii_apply)
 template <typename VT>
 __global__ __launch_bounds__(kModelThreads) void km_ii_rz(int nf, int pitch,
                                                           const double* __restrict__ r,
@@ -464,20 +481,6 @@ __global__ __launch_bounds__(kModelThreads) void km_ii_rz(int nf, int pitch,
     acc += r[o] * ((double)Z[o] * zs);
   }
   mblock_partial(acc, partials);
-}
-
-__global__ __launch_bounds__(kModelThreads) void km_ii_beta(DevState* st,
-                                                            const double* __restrict__ partials,
-                                                            int nb, int first) {
-  if (st->inner_done) return;
-  const double rz = block_sum_partials(partials, nb, 1);
-  if (threadIdx.x != 0) return;
-  st->cg_gam[1] = first ? 0.0 : rz / st->rho;
-  st->rho = rz;
-  if (!(rz > 0.0) || !isfinite(rz)) {
-    if (rz != 0.0) st->breakdown |= isfinite(rz) ? 1 : 4;
-    st->inner_done = 1;
-  }
 }
 
 // ---- outer PCG on the loop (one block each) ---------------------------------------------------
@@ -614,14 +617,15 @@ void launch_model_ii_start(hipStream_t s, int nf, int pitch, const double* f, do
 
 template <typename VT>
 void launch_model_ii_rz(hipStream_t s, int nf, int pitch, const double* r, const VT* Z, double zs,
-                        DevState* st, double* partials, int first) {
+                        DevState* st, double* partials) {
   const int nb = mblocks((int64_t)nf * nf);
   hipLaunchKernelGGL(km_ii_rz<VT>, dim3(nb), dim3(kModelThreads), 0, s, nf, pitch, r, Z, zs,
                      (const DevState*)st, partials);
-  hipLaunchKernelGGL(km_ii_beta, dim3(1), dim3(kModelThreads), 0, s, st, (const double*)partials,
-                     nb, first);
 }
 
+// The r.z and ||r||^2 partials sit in partials[0, 2048), the p.q partials in [4096, 6144): the
+// kernel that sums one set writes the other, so no block overwrites a partial another block of
+// the same launch is still reading.
 template <typename VT>
 void launch_model_ii_step(hipStream_t s, int n, int pitch, const VT* Z, double zs, double* p_old,
                           double* p_new, double* q, double* x, double* r, VT* vr, DevState* st,
@@ -629,12 +633,13 @@ void launch_model_ii_step(hipStream_t s, int n, int pitch, const VT* Z, double z
   const int nf = n - 1;
   const int nb = mblocks((int64_t)nf * nf);
   const double h = 1.0 / n;
+  double* pq_partials = partials + 4096;
   hipLaunchKernelGGL(km_ii_apply<VT>, dim3(nb), dim3(kModelThreads), 0, s, n, pitch, h * h, Z, zs,
-                     (const double*)p_old, p_new, q, (const DevState*)st, first, partials);
-  hipLaunchKernelGGL(km_ii_alpha, dim3(1), dim3(kModelThreads), 0, s, st, (const double*)partials,
-                     nb);
+                     (const double*)p_old, p_new, q, st, first, (const double*)partials, nb,
+                     pq_partials);
   hipLaunchKernelGGL(km_ii_update<VT>, dim3(nb), dim3(kModelThreads), 0, s, nf, pitch, x, r,
-                     (const double*)p_new, (const double*)q, vr, (const DevState*)st, partials);
+                     (const double*)p_new, (const double*)q, vr, st, (const double*)pq_partials,
+                     nb, partials);
   hipLaunchKernelGGL(km_ii_check, dim3(1), dim3(kModelThreads), 0, s, st,
                      (const double*)partials, nb, 0);
 }
@@ -643,7 +648,7 @@ void launch_model_ii_step(hipStream_t s, int n, int pitch, const VT* Z, double z
   template void launch_model_ii_start<VT>(hipStream_t, int, int, const double*, double*, double*, \
                                           VT*, DevState*, double*, double);                       \
   template void launch_model_ii_rz<VT>(hipStream_t, int, int, const double*, const VT*, double,   \
-                                       DevState*, double*, int);                                  \
+                                       DevState*, double*);                                       \
   template void launch_model_ii_step<VT>(hipStream_t, int, int, const VT*, double, double*,       \
                                          double*, double*, double*, double*, VT*, DevState*,      \
                                          double*, int);
