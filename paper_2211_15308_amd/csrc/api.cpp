@@ -55,6 +55,7 @@ size_t plan_workspace(fdd_problem_s* P, char* base) {
   const size_t nb0 = (size_t)t0 * t0;
   P->partials = (double*)take(sizeof(double) * 4096 * 2);
   P->red.nb0 = (int)nb0;
+  P->red.nbd = (int)nb0;
   P->red.pq = (double*)take(sizeof(double) * nb0);
   P->red.rr = (double*)take(sizeof(double) * nb0);
   P->red.rz[0] = (double*)take(sizeof(double) * nb0);

@@ -101,6 +101,8 @@ struct Reductions {
   double* ir;      // ||f - A u||^2 of the refinement residual
   double* ff;      // ||f||^2
   int nb0;         // number of level-0 tiles
+  int nbd;         // r . z and z . A z partials per iteration (nb0; fewer when one up kernel
+                   // covers several level-0 tiles per block)
 };
 
 // Optional HIP-event timing of one kernel kind (pairs of events around each launch of it).

@@ -346,6 +346,19 @@ void launch_vcycle(const LaunchCtx& c, const MGBuffers<T>& mg, const T* f, T* z)
   else vcycle_nu<T, 1>(c, mg, f, z);
 }
 
+// The reductions as the level-0 down kernel of a PCG iteration reads them: the quad up kernel
+// stores one r.z and one z.A z partial per block (64 x 64 level-0 cells), the finest up kernel
+// one per 32 x 32 tile.
+template <typename T>
+static Reductions dot_red(const LaunchCtx& c) {
+  Reductions red = c.red;
+  if (quad_up<T>(c)) {
+    const dim3 g = ptiles(c.lev[2].nf);
+    red.nbd = (int)(g.x * g.y);
+  }
+  return red;
+}
+
 template <typename T, int NU>
 static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x, T* r_old,
                         T* r_new, T* z, T* p_old, T* p_new, bool update_only) {
@@ -353,13 +366,14 @@ static void pcg_iter_nu(const LaunchCtx& c, const MGBuffers<T>& mg, int k, T* x,
   // beyond kPresumTiles tiles the dot products are summed once, by one block, instead of by
   // every block of the down kernel (same order, same values)
   const int presum = c.red.nb0 > kPresumTiles ? 1 : 0;
-  if (presum) hipLaunchKernelGGL(k_sum_dots, dim3(1), dim3(kBlock), 0, c.stream, c.st, c.red, k);
+  const Reductions red = dot_red<T>(c);
+  if (presum) hipLaunchKernelGGL(k_sum_dots, dim3(1), dim3(kBlock), 0, c.stream, c.st, red, k);
   // FP32 grids of at most kResidentTiles tiles run the down kernel's RESIDENT form (every tile
   // in flight at once, four blocks per compute unit)
   auto down0 = [&](auto kernel) {
     launch_timed(c.hook, kTimeDown0, kernel, tiles(L.nf), tblock(), c.stream, (const T*)r_old,
                  mg.u[0], mg.f[1], L.nf, L.pitch, c.lev[1].pitch, (const T*)z, (const T*)p_old,
-                 p_new, x, r_new, c.st, c.red, k, 0, 0, presum);
+                 p_new, x, r_new, c.st, red, k, 0, 0, presum);
   };
   if constexpr (sizeof(T) == 4) {
     if (c.red.nb0 <= kResidentTiles) down0(k_mg_down<T, NU, true, kTile, true>);

@@ -207,7 +207,7 @@ __device__ __forceinline__ void d_sum_dots(const Reductions& red, int k, DevStat
   const double* rzp = (k & 1) ? red.rz[1] : red.rz[0];
   const double* zwp = (k & 1) ? red.zw[1] : red.zw[0];
   double gam = 0.0, del = 0.0;
-  for (int q = flat_tid(); q < red.nb0; q += kBlock) {
+  for (int q = flat_tid(); q < red.nbd; q += kBlock) {
     gam += ldg(rzp, (unsigned)q);
     del += ldg(zwp, (unsigned)q);
   }
@@ -309,7 +309,7 @@ __device__ __forceinline__ void d_mg_down_body(T* sf_, T* su_, T* s3_,
 #pragma unroll
   for (int a = 0; a < NP; ++a) {
     const int q = t + kBlock * a;
-    const bool ok = CG && !presum && q < red.nb0;
+    const bool ok = CG && !presum && q < red.nbd;
     rzr[a] = ok ? ldg(rzp, (unsigned)q) : 0.0;
     zwr[a] = ok ? ldg(zwp, (unsigned)q) : 0.0;
   }
@@ -348,7 +348,7 @@ __device__ __forceinline__ void d_mg_down_body(T* sf_, T* su_, T* s3_,
         gam += rzr[a];
         del += zwr[a];
       }
-      for (int q = t + kBlock * NP; q < red.nb0; q += kBlock) {
+      for (int q = t + kBlock * NP; q < red.nbd; q += kBlock) {
         gam += ldg(rzp, (unsigned)q);
         del += ldg(zwp, (unsigned)q);
       }
@@ -1306,9 +1306,9 @@ __device__ __forceinline__ void d_triple_up(
 // finally does the finest level as the CG up kernel does (u_0 = u_0,pre + P e_1, 2 nu half-sweeps,
 // z stored, the dots r.z and z.A z) on a 64 x 64 tile.  It replaces d_triple_up and the finest
 // up kernel (one launch and one inter-kernel gap fewer per V-cycle).  Every value sees the same
-// operations as in the separate kernels; the dots are formed per 32 x 32 sub-tile and stored at
-// the index the finest up kernel's tile would use, so the down kernel reads the same number of
-// partials (their values sum the same products in another order).
+// operations as in the separate kernels; the dots are summed per block (one r.z and one z.A z
+// partial per 64 x 64 tile, a quarter of the finest up kernel's count), so the same products are
+// summed in another order.
 template <int NU>
 struct QuadUp {
   static constexpr int H0 = 2 * NU + 1;            // finest halo (z valid one beyond the tile)
@@ -1432,8 +1432,8 @@ __device__ __forceinline__ void d_quad_up(
   up_window_init<G::N0, W0>(sf0, su0, f0r, u0r, t, ib0, jb0, nf0,
                             [&](int a, int b) { return su1[a][b]; }, ib1, jb1);
   tile_sweeps<T, W0, 2 * NU, kPairThreads>(su0, sf0, ib0, jb0, nf0, false);
-  // z on the own cells; r.z and z.A z per 32 x 32 sub-tile (sub-tile column by lane half, row by
-  // slot half: thread t covers cells (t % 64, t / 64 + 16 q))
+  // z on the own cells; r.z and z.A z per 32 x 32 sub-tile first (sub-tile column by lane half,
+  // row by slot half: thread t covers cells (t % 64, t / 64 + 16 q))
   double dz[2][2] = {{0.0, 0.0}, {0.0, 0.0}};   // [sub-tile row][r.z, z.A z]
 #pragma unroll
   for (int q = 0; q < TT * TT / kPairThreads; ++q) {
@@ -1464,16 +1464,16 @@ __device__ __forceinline__ void d_quad_up(
       for (int b = 0; b < 2; ++b) sdot[w][(a * 2 + sx) * 2 + b] = dz[a][b];
   }
   __syncthreads();
+  // one partial of each per block, stored at the block's tile index (the down kernels read
+  // gridDim.x * gridDim.y of them, red.nbd): lane 2 sub + b sums sub-tile sub's value b over
+  // the waves, then lanes 0 and 1 add the four sub-tiles in order
   if (t < 8) {
     double v = 0.0;
     for (int q = 0; q < kPairThreads / 64; ++q) v += sdot[q][t];
-    const int sub = t >> 1, b = t & 1;           // sub = sy * 2 + sx
-    const int sx = sub & 1, sy = sub >> 1;
-    const int nbx = (nf0 + kTile - 1) / kTile;   // the finest up kernel's tiles per row
-    const int tx = 2 * tile_x + sx, ty = 2 * tile_y + sy;
-    if (tx < nbx && ty < nbx) {
-      double* dst = b == 0 ? ((kn & 1) ? red.rz[1] : red.rz[0]) : ((kn & 1) ? red.zw[1] : red.zw[0]);
-      stg(dst, (unsigned)(ty * nbx + tx), v);
+    const double v2 = __shfl_down(v, 2, 8), v4 = __shfl_down(v, 4, 8), v6 = __shfl_down(v, 6, 8);
+    if (t < 2) {
+      double* dst = t == 0 ? ((kn & 1) ? red.rz[1] : red.rz[0]) : ((kn & 1) ? red.zw[1] : red.zw[0]);
+      stg(dst, (unsigned)(tile_y * gridDim.x + tile_x), ((v + v2) + v4) + v6);
     }
   }
   if (count_iteration && lead && thread0()) {
