@@ -230,6 +230,25 @@ def test_solve_3d_n64_true_residual():
     assert st["true_rel_res"] <= 1e-7
 
 
+def test_solve_3d_n128_true_residual():
+    # the largest 3D size of the benchmark (2.06 M dofs, K = 1, mu = 1e-4) at the stop rule of the
+    # parity tests: beyond the oracle's factorization sizes, held by the reported true residual,
+    # whose computation is checked against the oracle's residual at n = 8 and 12
+    n, K, mu = 128, 1.0, 1e-4
+    print(f"[3d solve] n={n} K={K} mu={mu}: true residual at outer rtol 1e-10", flush=True)
+    P = make3(n, K, mu)
+    TP = P.build_rational_pc(F.FDD_RA_PRECOND, 1e-12)
+    TH = P.build_rational_pc(F.FDD_RA_OPERATOR, 1e-12)
+    b = dev(workloads.rhs(3, n, 3128))
+    x = torch.zeros_like(b)
+    st = P.solve(TP, TH, b, x, F.opts_default(outer_rtol=1e-10, inner_rtol=1e-12,
+                                              check_true_residual=1))
+    print(f"  outer {st['outer_its']} inner {st['inner_its_total']} true res "
+          f"{st['true_rel_res']:.2e} {st['t_solve_ms']:.1f} ms", flush=True)
+    assert st["status"] == F.FDD_OK
+    assert st["true_rel_res"] <= 1e-9
+
+
 def test_solve_3d_n64_against_golden():
     # n = 64 against the oracle's sparse-LU solution written by tests/golden/make_3d_n64.py
     # (4096 seeded entries and the norm): the outer rtol 1e-10 bar of the smaller sizes
