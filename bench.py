@@ -870,7 +870,7 @@ def progress(msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+        print(json.dumps({"error": "the solver and this benchmark run on one GPU only; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.cpu_only:
