@@ -684,8 +684,9 @@ int setup3(const fdd_desc* d, int hip_device, fdd_problem_s* P) {
   Q->nlev = l + 1;
   Q->nc = Q->lnf[l];
   if (Q->nc > 4) {
+    const int nc = Q->nc;
     delete Q;
-    return fail(FDD_E_ARG, "3D: n = %d leaves a %d^3 coarsest grid (max 4^3)", n, Q->nc);
+    return fail(FDD_E_ARG, "3D: n = %d leaves a %d^3 coarsest grid (max 4^3)", n, nc);
   }
   // the coarse levels that fit one workgroup's LDS (level 0 always runs on the full grid)
   Q->lc = 1;
