@@ -77,37 +77,79 @@ struct TabLds {
   int o[kTabLds];
 };
 
-// every thread of the block calls it; true when the table is in LDS
+// every thread of the block (kT threads) calls it; true when the table is in LDS.  A thread
+// issues all its loads before its first LDS store, so the block waits for one load latency
+// (a loop that stores each entry as it arrives waits once per entry).
 __device__ bool stage_table(const HdView& A, TabLds& T) {
   const int nt = A.ntypes * A.width;
   if (nt > kTabLds) return false;
-  for (int k = threadIdx.x; k < nt; k += blockDim.x) {
-    T.v[k] = A.tval[k];
-    if (A.toff) T.o[k] = A.toff[k];
+  constexpr int R = kTabLds / kT;
+  static_assert(R * kT == kTabLds, "the table is a whole number of block-wide rows");
+  double v[R];
+  int o[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = threadIdx.x + q * kT;
+    v[q] = k < nt ? A.tval[k] : 0.0;
+    o[q] = (A.toff && k < nt) ? A.toff[k] : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = threadIdx.x + q * kT;
+    if (k < nt) {
+      T.v[k] = v[q];
+      T.o[k] = o[q];
+    }
   }
   __syncthreads();
   return true;
+}
+
+// Row i of A against a vector read through xat(column), with the table in LDS (kLds) or in
+// global memory.  The slots go in chunks of kSlotChunk: a chunk's columns and values first, then
+// all its gathers (in flight together), then its products added in slot order, so the sum is
+// the one-slot-at-a-time sum.  Slots past the row's width re-read the chunk's first slot (in
+// range) and are not added.
+constexpr int kSlotChunk = 8;
+template <bool kLds, bool kRel, typename XAt>
+__device__ __forceinline__ double ell_row_chunks(const HdView& A, const TabLds& T, int i,
+                                                 const XAt& xat) {
+  const int base = A.rtype[i] * A.width;
+  double s = 0.0;
+  for (int k0 = 0; k0 < A.width; k0 += kSlotChunk) {
+    double v[kSlotChunk], xv[kSlotChunk];
+    int c[kSlotChunk];
+#pragma unroll
+    for (int u = 0; u < kSlotChunk; ++u) {
+      const int k = k0 + u < A.width ? k0 + u : k0;
+      v[u] = kLds ? T.v[base + k] : A.tval[base + k];
+      c[u] = kRel ? i + (kLds ? T.o[base + k] : A.toff[base + k]) : A.col[(size_t)k * A.rows + i];
+    }
+    // (scheduling barriers keep the three phases apart: the compiler would otherwise move each
+    // gather next to its product and wait for every slot in turn)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kSlotChunk; ++u) xv[u] = xat(c[u]);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kSlotChunk; ++u)
+      if (k0 + u < A.width) s += v[u] * xv[u];
+  }
+  return s;
+}
+// (the column form is uniform per launch: one scalar branch per row, none per slot)
+template <bool kLds, typename XAt>
+__device__ __forceinline__ double ell_row_dot(const HdView& A, const TabLds& T, int i,
+                                              const XAt& xat) {
+  return A.toff ? ell_row_chunks<kLds, true>(A, T, i, xat)
+                : ell_row_chunks<kLds, false>(A, T, i, xat);
 }
 
 // row i of A times x with the table in LDS (kLds) or in global memory
 template <bool kLds>
 __device__ __forceinline__ double ell_row_tab(const HdView& A, const TabLds& T, int i,
                                               const double* __restrict__ x) {
-  const int base = A.rtype[i] * A.width;
-  double s = 0.0;
-  if (A.toff) {
-    for (int k = 0; k < A.width; ++k) {
-      const double v = kLds ? T.v[base + k] : A.tval[base + k];
-      const int o = kLds ? T.o[base + k] : A.toff[base + k];
-      s += v * x[i + o];
-    }
-  } else {
-    for (int k = 0; k < A.width; ++k) {
-      const double v = kLds ? T.v[base + k] : A.tval[base + k];
-      s += v * x[A.col[(size_t)k * A.rows + i]];
-    }
-  }
-  return s;
+  return ell_row_dot<kLds>(A, T, i, [&](int c) { return x[c]; });
 }
 
 // grid of the row kernels: a grid-stride loop over at most kRowBlocks blocks, so that each block
@@ -123,17 +165,22 @@ __device__ __forceinline__ void patch_solve_vertex(const int* __restrict__ patch
                                                    const double* pinv, int v,
                                                    const double* __restrict__ r,
                                                    double* __restrict__ Y) {
+  // no branches between the loads, so the vertex's type, dof indices and residual values are in
+  // flight together: indices of empty slots (-1) read r[0] and are zeroed, and a vertex without a
+  // patch (type -1, every slot empty) stores zeros into slots that are never read back
   const int t = ptype[v];
-  if (t < 0) return;
+  int d[PW];
+#pragma unroll
+  for (int k = 0; k < PW; ++k) d[k] = patch[(size_t)v * PW + k];
+  __builtin_amdgcn_sched_barrier(0);  // every index load issued before the gathers
   double rl[PW];
 #pragma unroll
-  for (int k = 0; k < PW; ++k) {
-    const int d = patch[(size_t)v * PW + k];
-    rl[k] = d >= 0 ? r[d] : 0.0;
-  }
-  const double* Pi = pinv + (size_t)t * PW * PW;
-  // every slot is written (a lane's PW values are contiguous, so the stores combine; slots
-  // without a dof hold 0 and are never read back)
+  for (int k = 0; k < PW; ++k) rl[k] = r[d[k] < 0 ? 0 : d[k]];
+  __builtin_amdgcn_sched_barrier(0);  // every gather issued before the first product
+#pragma unroll
+  for (int k = 0; k < PW; ++k) rl[k] = d[k] >= 0 ? rl[k] : 0.0;
+  const double* Pi = pinv + (size_t)(t < 0 ? 0 : t) * PW * PW;
+  // every slot is written (a lane's PW values are contiguous, so the stores combine)
 #pragma unroll
   for (int a = 0; a < PW; ++a) {
     double y = 0.0;
@@ -184,7 +231,22 @@ __global__ __launch_bounds__(kT) void k_hd_patch_solve(const int* __restrict__ p
                                                        double* __restrict__ Y, const HdState* stop) {
   if (stopped(stop)) return;
   __shared__ double sp[kHdMaxTypes * PW * PW];
-  for (int k = threadIdx.x; k < ntypes * PW * PW; k += kT) sp[k] = pinv[k];
+  {
+    // all of a thread's loads before its LDS stores (one load latency per block)
+    constexpr int R = (kHdMaxTypes * PW * PW + kT - 1) / kT;
+    const int nt = ntypes * PW * PW;
+    double w[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int k = threadIdx.x + q * kT;
+      w[q] = k < nt ? pinv[k] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int k = threadIdx.x + q * kT;
+      if (k < nt) sp[k] = w[q];
+    }
+  }
   __syncthreads();
   const int v = blockIdx.x * kT + threadIdx.x;
   if (v >= nvert) return;
@@ -313,15 +375,8 @@ template <bool kLds>
 __device__ __forceinline__ double pq_row(const HdView& A, const TabLds& T, int i,
                                          const double* __restrict__ z,
                                          const double* __restrict__ p_old, double beta, int first) {
-  const int base = A.rtype[i] * A.width;
-  double qi = 0.0;
-  for (int k = 0; k < A.width; ++k) {
-    const double v = kLds ? T.v[base + k] : A.tval[base + k];
-    const int c = A.toff ? i + (kLds ? T.o[base + k] : A.toff[base + k])
-                         : A.col[(size_t)k * A.rows + i];
-    qi += v * (first ? z[c] : z[c] + beta * p_old[c]);
-  }
-  return qi;
+  return ell_row_dot<kLds>(A, T, i,
+                           [&](int c) { return first ? z[c] : z[c] + beta * p_old[c]; });
 }
 
 __global__ __launch_bounds__(kT) void k_hd_pq(HdView A, const double* __restrict__ z,
