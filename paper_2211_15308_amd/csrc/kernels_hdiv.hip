@@ -105,51 +105,25 @@ __device__ bool stage_table(const HdView& A, TabLds& T) {
   return true;
 }
 
-// Row i of A against a vector read through xat(column), with the table in LDS (kLds) or in
-// global memory.  The slots go in chunks of kSlotChunk: a chunk's columns and values first, then
-// all its gathers (in flight together), then its products added in slot order, so the sum is
-// the one-slot-at-a-time sum.  Slots past the row's width re-read the chunk's first slot (in
-// range) and are not added.
-constexpr int kSlotChunk = 8;
-template <bool kLds, bool kRel, typename XAt>
-__device__ __forceinline__ double ell_row_chunks(const HdView& A, const TabLds& T, int i,
-                                                 const XAt& xat) {
-  const int base = A.rtype[i] * A.width;
-  double s = 0.0;
-  for (int k0 = 0; k0 < A.width; k0 += kSlotChunk) {
-    double v[kSlotChunk], xv[kSlotChunk];
-    int c[kSlotChunk];
-#pragma unroll
-    for (int u = 0; u < kSlotChunk; ++u) {
-      const int k = k0 + u < A.width ? k0 + u : k0;
-      v[u] = kLds ? T.v[base + k] : A.tval[base + k];
-      c[u] = kRel ? i + (kLds ? T.o[base + k] : A.toff[base + k]) : A.col[(size_t)k * A.rows + i];
-    }
-    // (scheduling barriers keep the three phases apart: the compiler would otherwise move each
-    // gather next to its product and wait for every slot in turn)
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int u = 0; u < kSlotChunk; ++u) xv[u] = xat(c[u]);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int u = 0; u < kSlotChunk; ++u)
-      if (k0 + u < A.width) s += v[u] * xv[u];
-  }
-  return s;
-}
-// (the column form is uniform per launch: one scalar branch per row, none per slot)
-template <bool kLds, typename XAt>
-__device__ __forceinline__ double ell_row_dot(const HdView& A, const TabLds& T, int i,
-                                              const XAt& xat) {
-  return A.toff ? ell_row_chunks<kLds, true>(A, T, i, xat)
-                : ell_row_chunks<kLds, false>(A, T, i, xat);
-}
-
 // row i of A times x with the table in LDS (kLds) or in global memory
 template <bool kLds>
 __device__ __forceinline__ double ell_row_tab(const HdView& A, const TabLds& T, int i,
                                               const double* __restrict__ x) {
-  return ell_row_dot<kLds>(A, T, i, [&](int c) { return x[c]; });
+  const int base = A.rtype[i] * A.width;
+  double s = 0.0;
+  if (A.toff) {
+    for (int k = 0; k < A.width; ++k) {
+      const double v = kLds ? T.v[base + k] : A.tval[base + k];
+      const int o = kLds ? T.o[base + k] : A.toff[base + k];
+      s += v * x[i + o];
+    }
+  } else {
+    for (int k = 0; k < A.width; ++k) {
+      const double v = kLds ? T.v[base + k] : A.tval[base + k];
+      s += v * x[A.col[(size_t)k * A.rows + i]];
+    }
+  }
+  return s;
 }
 
 // grid of the row kernels: a grid-stride loop over at most kRowBlocks blocks, so that each block
@@ -375,8 +349,15 @@ template <bool kLds>
 __device__ __forceinline__ double pq_row(const HdView& A, const TabLds& T, int i,
                                          const double* __restrict__ z,
                                          const double* __restrict__ p_old, double beta, int first) {
-  return ell_row_dot<kLds>(A, T, i,
-                           [&](int c) { return first ? z[c] : z[c] + beta * p_old[c]; });
+  const int base = A.rtype[i] * A.width;
+  double qi = 0.0;
+  for (int k = 0; k < A.width; ++k) {
+    const double v = kLds ? T.v[base + k] : A.tval[base + k];
+    const int c = A.toff ? i + (kLds ? T.o[base + k] : A.toff[base + k])
+                         : A.col[(size_t)k * A.rows + i];
+    qi += v * (first ? z[c] : z[c] + beta * p_old[c]);
+  }
+  return qi;
 }
 
 __global__ __launch_bounds__(kT) void k_hd_pq(HdView A, const double* __restrict__ z,
