@@ -164,16 +164,6 @@ __device__ __forceinline__ void patch_solve_vertex(const int* __restrict__ patch
   }
 }
 
-__device__ __forceinline__ void patch_sum_dof(const int* __restrict__ slot, int i,
-                                              const double* __restrict__ Y, double theta,
-                                              double* __restrict__ x, int add) {
-  const int s0 = slot[2 * (size_t)i], s1 = slot[2 * (size_t)i + 1];
-  double v = 0.0;
-  if (s0 >= 0) v += Y[s0];
-  if (s1 >= 0) v += Y[s1];
-  x[i] = (add ? x[i] : 0.0) + theta * v;
-}
-
 __global__ __launch_bounds__(kT) void k_hd_spmv(HdView A, const double* __restrict__ x,
                                                 double* __restrict__ y, double alpha, double beta,
                                                 const HdState* stop) {
@@ -234,7 +224,16 @@ __global__ __launch_bounds__(kT) void k_hd_patch_sum(const int* __restrict__ slo
   if (stopped(stop)) return;
   const int i = blockIdx.x * kT + threadIdx.x;
   if (i >= n0) return;
-  patch_sum_dof(slot, i, Y, theta, x, add);
+  // the slots and the old x first, then both patch values (clamped indices, no branch), so the
+  // dof waits for two load latencies rather than three
+  const int s0 = slot[2 * (size_t)i], s1 = slot[2 * (size_t)i + 1];
+  const double xo = add ? x[i] : 0.0;
+  __builtin_amdgcn_sched_barrier(0);
+  const double y0 = Y[s0 < 0 ? 0 : s0], y1 = Y[s1 < 0 ? 0 : s1];
+  double v = 0.0;
+  if (s0 >= 0) v += y0;
+  if (s1 >= 0) v += y1;
+  x[i] = xo + theta * v;
 }
 
 // One step of the Jacobi-preconditioned Chebyshev iteration for A x = b (x_0 = 0), the diagonal
