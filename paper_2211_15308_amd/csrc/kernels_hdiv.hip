@@ -105,11 +105,11 @@ __device__ bool stage_table(const HdView& A, TabLds& T) {
   return true;
 }
 
-// row i of A times x with the table in LDS (kLds) or in global memory
+// row i (of type t) of A times x with the table in LDS (kLds) or in global memory
 template <bool kLds>
-__device__ __forceinline__ double ell_row_tab(const HdView& A, const TabLds& T, int i,
+__device__ __forceinline__ double ell_row_tab(const HdView& A, const TabLds& T, int i, int t,
                                               const double* __restrict__ x) {
-  const int base = A.rtype[i] * A.width;
+  const int base = t * A.width;
   double s = 0.0;
   if (A.toff) {
     for (int k = 0; k < A.width; ++k) {
@@ -169,10 +169,17 @@ __global__ __launch_bounds__(kT) void k_hd_spmv(HdView A, const double* __restri
                                                 const HdState* stop) {
   if (stopped(stop)) return;
   __shared__ TabLds T;
+  // a row's type is loaded one step ahead: the first row's before the table is staged (the
+  // staging barrier waits for both), the next row's before the current row's gathers
+  const int stride = gridDim.x * kT;
+  int i = blockIdx.x * kT + threadIdx.x;
+  int t = i < A.rows ? A.rtype[i] : 0;
   const bool lds = stage_table(A, T);
-  for (int i = blockIdx.x * kT + threadIdx.x; i < A.rows; i += gridDim.x * kT) {
-    const double s = lds ? ell_row_tab<true>(A, T, i, x) : ell_row_tab<false>(A, T, i, x);
+  for (; i < A.rows; i += stride) {
+    const int tn = i + stride < A.rows ? A.rtype[i + stride] : 0;
+    const double s = lds ? ell_row_tab<true>(A, T, i, t, x) : ell_row_tab<false>(A, T, i, t, x);
     y[i] = (beta == 0.0 ? 0.0 : beta * y[i]) + alpha * s;
+    t = tn;
   }
 }
 
@@ -181,9 +188,20 @@ __global__ __launch_bounds__(kT) void k_hd_residual(HdView A, const double* __re
                                                     double* __restrict__ r, const HdState* stop) {
   if (stopped(stop)) return;
   __shared__ TabLds T;
+  // a row's type and b entry are loaded one step ahead, as in k_hd_spmv
+  const int stride = gridDim.x * kT;
+  int i = blockIdx.x * kT + threadIdx.x;
+  int t = i < A.rows ? A.rtype[i] : 0;
+  double bi = i < A.rows ? b[i] : 0.0;
   const bool lds = stage_table(A, T);
-  for (int i = blockIdx.x * kT + threadIdx.x; i < A.rows; i += gridDim.x * kT)
-    r[i] = b[i] - (lds ? ell_row_tab<true>(A, T, i, x) : ell_row_tab<false>(A, T, i, x));
+  for (; i < A.rows; i += stride) {
+    const bool more = i + stride < A.rows;
+    const int tn = more ? A.rtype[i + stride] : 0;
+    const double bn = more ? b[i + stride] : 0.0;
+    r[i] = bi - (lds ? ell_row_tab<true>(A, T, i, t, x) : ell_row_tab<false>(A, T, i, t, x));
+    t = tn;
+    bi = bn;
+  }
 }
 
 // (the few inverse patch matrices are staged in LDS: every lane reads a row of its vertex's)
@@ -249,16 +267,21 @@ __global__ __launch_bounds__(kT) void k_hd_cheb_step(HdView A, const int* __rest
                                                      double* __restrict__ d, double c_prev,
                                                      double c_res, int first) {
   __shared__ TabLds T;
+  // the first row's type and diagonal-patch type are loaded before the table is staged
+  int i = blockIdx.x * kT + threadIdx.x;
+  int t = i < A.rows ? A.rtype[i] : 0;
+  int pt = i < A.rows ? ptype[i] : 0;
   const bool lds = stage_table(A, T);
-  for (int i = blockIdx.x * kT + threadIdx.x; i < A.rows; i += gridDim.x * kT) {
-    const double dinv = pinv[ptype[i]];
+  for (; i < A.rows; i += gridDim.x * kT, t = i < A.rows ? A.rtype[i] : 0,
+                                         pt = i < A.rows ? ptype[i] : 0) {
+    const double dinv = pinv[pt];
     if (first) {
       const double di = c_res * dinv * b[i];
       d[i] = di;
       x_out[i] = di;
     } else {
-      const double r = b[i] - (lds ? ell_row_tab<true>(A, T, i, x_in)
-                                   : ell_row_tab<false>(A, T, i, x_in));
+      const double r = b[i] - (lds ? ell_row_tab<true>(A, T, i, t, x_in)
+                                   : ell_row_tab<false>(A, T, i, t, x_in));
       const double di = c_prev * d[i] + c_res * dinv * r;
       d[i] = di;
       x_out[i] = x_in[i] + di;
@@ -345,10 +368,10 @@ __global__ __launch_bounds__(kOneBlock) void k_hd_rz_finish(const double* partia
 }
 
 template <bool kLds>
-__device__ __forceinline__ double pq_row(const HdView& A, const TabLds& T, int i,
+__device__ __forceinline__ double pq_row(const HdView& A, const TabLds& T, int i, int t,
                                          const double* __restrict__ z,
                                          const double* __restrict__ p_old, double beta, int first) {
-  const int base = A.rtype[i] * A.width;
+  const int base = t * A.width;
   double qi = 0.0;
   for (int k = 0; k < A.width; ++k) {
     const double v = kLds ? T.v[base + k] : A.tval[base + k];
@@ -366,13 +389,19 @@ __global__ __launch_bounds__(kT) void k_hd_pq(HdView A, const double* __restrict
                                               int first) {
   if (st->done) return;
   __shared__ TabLds T;
+  // a row's type is loaded one step ahead, as in k_hd_spmv
+  const int stride = gridDim.x * kT;
+  int i = blockIdx.x * kT + threadIdx.x;
+  int t = i < A.rows ? A.rtype[i] : 0;
   const bool lds = stage_table(A, T);
   const double beta = st->beta;
   double s = 0.0;
-  for (int i = blockIdx.x * kT + threadIdx.x; i < A.rows; i += gridDim.x * kT) {
+  for (; i < A.rows; i += stride) {
+    const int tn = i + stride < A.rows ? A.rtype[i + stride] : 0;
     // q = A (z + beta p_old), with the direction formed where the product reads it
-    const double qi = lds ? pq_row<true>(A, T, i, z, p_old, beta, first)
-                          : pq_row<false>(A, T, i, z, p_old, beta, first);
+    const double qi = lds ? pq_row<true>(A, T, i, t, z, p_old, beta, first)
+                          : pq_row<false>(A, T, i, t, z, p_old, beta, first);
+    t = tn;
     const double pi = first ? z[i] : z[i] + beta * p_old[i];
     p_new[i] = pi;
     q[i] = qi;
