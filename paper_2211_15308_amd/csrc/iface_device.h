@@ -31,9 +31,24 @@ __device__ __forceinline__ double bsum(double v) {
 // the block.  Every thread receives the total.
 __device__ __forceinline__ double block_sum_partials(const double* p, int count, int stride) {
   __shared__ double sw[16];
+  // a thread's partials q = tid, tid + B, ... are added in that order, eight loads in flight at
+  // a time (a loop adding each value as it arrives waits once per partial)
+  constexpr int U = 8;
   double v = 0.0;
-  for (int q = threadIdx.x; q < count; q += blockDim.x)
-    v += __hip_atomic_load(&p[(size_t)q * stride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int q0 = threadIdx.x; q0 < count; q0 += U * (int)blockDim.x) {
+    double a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + u * (int)blockDim.x;
+      a[u] = q < count ? __hip_atomic_load(&p[(size_t)q * stride], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT)
+                       : 0.0;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (q0 + u * (int)blockDim.x < count) v += a[u];
+  }
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = v;

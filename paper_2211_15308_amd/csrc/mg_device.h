@@ -54,8 +54,23 @@ __device__ __forceinline__ double block_sum_all(double v) {
 
 // Fixed-order sum of nb partials, identical in every block of equal size.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int nb) {
+  // a thread's partials k = tid, tid + B, ... are added in that order, eight loads in flight at
+  // a time (a loop adding each value as it arrives waits once per partial)
+  constexpr int U = 8;
+  const int nt = nthreads();
   double v = 0.0;
-  for (int k = flat_tid(); k < nb; k += nthreads()) v += ldg(p, (unsigned)k);
+  for (int k0 = flat_tid(); k0 < nb; k0 += U * nt) {
+    double a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + u * nt;
+      a[u] = k < nb ? ldg(p, (unsigned)k) : 0.0;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + u * nt < nb) v += a[u];
+  }
   return block_sum_all(v);
 }
 
