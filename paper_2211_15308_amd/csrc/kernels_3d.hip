@@ -93,10 +93,30 @@ __device__ __forceinline__ double bsum3(double v) {
 }
 
 // Sum of np block partials (written by an earlier kernel), the same in every block.
-__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int np) {
+// (a thread's partials q = tid, tid + B, ... are added in that order, eight loads in flight at a
+// time: a loop adding each value as it arrives waits once per partial)
+template <int B>
+__device__ __forceinline__ double thread_partials(const double* __restrict__ part, int np, int t,
+                                                  int stride) {
+  constexpr int U = 8;
   double a = 0.0;
-  for (int q = tid3(); q < np; q += kX3 * kY3) a += part[q];
-  return bsum3(a);
+  for (int q0 = t; q0 < np; q0 += U * B) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + u * B;
+      v[u] = q < np ? part[(size_t)q * stride] : 0.0;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (q0 + u * B < np) a += v[u];
+  }
+  return a;
+}
+
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int np) {
+  return bsum3(thread_partials<kX3 * kY3>(part, np, tid3(), 1));
 }
 
 __device__ __forceinline__ void put_partial(double* part, double v) {
@@ -981,8 +1001,7 @@ __global__ __launch_bounds__(kB3) void kf_rhs_reduce(const double* __restrict__ 
 __global__ __launch_bounds__(kB3) void k3_sum_partials(const double* __restrict__ part, int count,
                                                        int stride, double* __restrict__ sc,
                                                        int slot) {
-  double acc = 0.0;
-  for (int q = threadIdx.x; q < count; q += kB3) acc += part[(size_t)q * stride];
+  double acc = thread_partials<kB3>(part, count, threadIdx.x, stride);
   acc = block_sum3(acc);
   if (threadIdx.x == 0) sc[slot] = acc;
 }
