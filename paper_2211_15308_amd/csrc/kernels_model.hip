@@ -351,22 +351,41 @@ __global__ __launch_bounds__(kModelThreads) void km_ii_apply(int n, int pitch, d
     st->cg_gam[1] = beta;
   }
   const int nf = n - 1;
-  auto P = [&](int i, int j) -> double {  // 0-based interior indices, zero outside
-    if (i < 0 || i >= nf || j < 0 || j >= nf) return 0.0;
-    const size_t o = (size_t)j * pitch + i;
-    const double z = (double)Z[o] * zs;
-    return first ? z : z + beta * po[o];
-  };
   const double c4 = 4.0 + h2 / 2.0, c1 = -1.0 + h2 / 12.0, cd = h2 / 12.0;
+  // the seven points c, w, e, s, n, ne, sw: offsets (di, dj) from the node
+  constexpr int kDi[7] = {0, -1, 1, 0, 0, 1, -1}, kDj[7] = {0, 0, 0, -1, 1, 1, -1};
   double acc = 0.0;
   const int64_t tot = (int64_t)nf * nf;
   for (int64_t k = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; k < tot;
        k += (int64_t)blockDim.x * gridDim.x) {
     const int i = (int)(k % nf), j = (int)(k / nf);
-    const double c = P(i, j);
-    const double v = c4 * c + c1 * (P(i - 1, j) + P(i + 1, j) + P(i, j - 1) + P(i, j + 1)) +
-                     cd * (P(i + 1, j + 1) + P(i - 1, j - 1));
     const size_t o = (size_t)j * pitch + i;
+    // p at the seven points (zero outside the interior), every load issued before the first use:
+    // a point outside reads the node's own entries and is zeroed
+    bool in[7];
+    size_t oo[7];
+    VT zr[7];
+    double pr[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      const int ii = i + kDi[a], jj = j + kDj[a];
+      in[a] = ii >= 0 && ii < nf && jj >= 0 && jj < nf;
+      oo[a] = in[a] ? (size_t)jj * pitch + ii : o;
+    }
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      zr[a] = Z[oo[a]];
+      pr[a] = first ? 0.0 : po[oo[a]];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double P[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+      const double z = (double)zr[a] * zs;
+      P[a] = in[a] ? (first ? z : z + beta * pr[a]) : 0.0;
+    }
+    const double c = P[0];
+    const double v = c4 * c + c1 * (P[1] + P[2] + P[3] + P[4]) + cd * (P[5] + P[6]);
     pn[o] = c;
     q[o] = v;
     acc += c * v;
