@@ -189,9 +189,38 @@ __global__ __launch_bounds__(kFullThreads) void kf_apply(int nf, int pitch, doub
        k += (int64_t)blockDim.x * gridDim.x) {
     if (k < NI) {
       const int i = (int)(k % nf), j = (int)(k / nf);
-      const double c = pI(i, j);
-      const double q = K * (4.0 * c - pI(i - 1, j) - pI(i + 1, j) - pI(i, j - 1) - pI(i, j + 1));
       const size_t o = (size_t)j * pitch + i;
+      // p at the node and its w, e, s, n neighbours as pI gives it, with every load issued before
+      // the first use: an interior point reads Z and p', the north point above the top row reads
+      // p_G, and a point outside reads the node's own entries and is zeroed
+      constexpr int kDi[5] = {0, -1, 1, 0, 0}, kDj[5] = {0, 0, 0, -1, 1};
+      bool in[5];
+      size_t oo[5];
+      VT zr[5];
+      double pr[5];
+#pragma unroll
+      for (int a = 0; a < 5; ++a) {
+        const int ii = i + kDi[a], jj = j + kDj[a];
+        in[a] = ii >= 0 && ii < nf && jj >= 0 && jj < nf;
+        oo[a] = in[a] ? (size_t)jj * pitch + ii : o;
+      }
+      const bool top = j == nf - 1;  // the north point is the interface node i
+#pragma unroll
+      for (int a = 0; a < 5; ++a) {
+        zr[a] = Z[oo[a]];
+        pr[a] = first ? 0.0 : pIo[oo[a]];
+      }
+      const double gn = pG[top ? i : 0];
+      __builtin_amdgcn_sched_barrier(0);
+      double P[5];
+#pragma unroll
+      for (int a = 0; a < 5; ++a) {
+        const double z = (double)zr[a] * invK;
+        P[a] = in[a] ? (first ? z : z + beta * pr[a]) : 0.0;
+      }
+      if (top) P[4] = gn;
+      const double c = P[0];
+      const double q = K * (4.0 * c - P[1] - P[2] - P[3] - P[4]);
       pIn[o] = c;
       qI[o] = q;
       acc += c * q;
