@@ -238,10 +238,27 @@ __global__ __launch_bounds__(kIfaceThreads) void km_loop_solve(int m, double h, 
   // g = -dia, so T' is tridiagonal with diagonal (dia - g, dia, ..., dia, dia - off^2 / g);
   // C x = r  =>  x = y - (v.y / (1 + v.z)) z,  T' y = r,  T' z = u.
   const double g = -dia;
-  // rows normalized by their diagonal: x_i + a_i x_{i-1} + a_i x_{i+1} = d_i (off-diagonals equal)
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+  // rows normalized by their diagonal: x_i + a_i x_{i-1} + a_i x_{i+1} = d_i (off-diagonals equal);
+  // a thread's right-hand-side loads (nodes tid + 1024 t and their loop neighbours) are all
+  // issued before the first is used
+  constexpr int R = kLoopMax / kIfaceThreads;
+  double vc[R], vl[R], vr[R];
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int i = threadIdx.x + t * kIfaceThreads;
+    const int ic = i < m ? i : 0;
+    vc[t] = in[ic];
+    vl[t] = in[(ic + m - 1) % m];
+    vr[t] = in[(ic + 1) % m];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int t = 0; t < R; ++t) {
+    const int i = threadIdx.x + t * kIfaceThreads;
+    if (i >= m) continue;
     const double di = (i == 0) ? dia - g : (i == m - 1 ? dia - off * off / g : dia);
-    const double rhs = (mode == kIfaceOperator) ? loop_mass(in, m, h, i) : in[i];
+    // (the operator-mode right-hand side is M_G in, as loop_mass forms it)
+    const double rhs = (mode == kIfaceOperator) ? (h / 6.0) * (4.0 * vc[t] + vl[t] + vr[t]) : vc[t];
     const double u = (i == 0) ? g : (i == m - 1 ? off : 0.0);
     sa[i] = off / di;
     sd[i] = rhs / di;
@@ -249,7 +266,6 @@ __global__ __launch_bounds__(kIfaceThreads) void km_loop_solve(int m, double h, 
   }
   __syncthreads();
   // parallel cyclic reduction with two right-hand sides (rows beyond the ends are zero)
-  constexpr int R = kLoopMax / kIfaceThreads;
   // lower and upper coefficients of a row evolve separately once rows are combined
   __shared__ double sc[kLoopMax];
   for (int i = threadIdx.x; i < m; i += blockDim.x) sc[i] = sa[i];
@@ -298,25 +314,45 @@ __global__ __launch_bounds__(kIfaceThreads) void km_loop_solve(int m, double h, 
 // Weighted sum of the systems (in system order) and the epilogue:
 //   precond mode:  out = sum
 //   operator mode: out = dL L in + d0 M in + M sum   (the RA realization of L^t)
-__global__ __launch_bounds__(kIfaceThreads) void km_loop_combine(int m, double h, int nsys,
-                                                                 double d0, double dL, int mode,
-                                                                 const double* __restrict__ in,
-                                                                 const double* __restrict__ scratch,
-                                                                 double* __restrict__ out) {
-  __shared__ double s[kLoopMax];
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+constexpr int kCombineThreads = 256;
+__global__ __launch_bounds__(kCombineThreads) void km_loop_combine(int m, double h, int nsys,
+                                                                   double d0, double dL, int mode,
+                                                                   const double* __restrict__ in,
+                                                                   const double* __restrict__ scratch,
+                                                                   double* __restrict__ out) {
+  // the block's nodes i0 .. i0 + 255 and one more on each side of the loop (cyclic): the
+  // operator epilogue applies M_G to the sum; each sum adds the systems in order, eight loads in
+  // flight at a time
+  __shared__ double s[kCombineThreads + 2];
+  const int i0 = blockIdx.x * kCombineThreads;
+  for (int c = threadIdx.x; c < kCombineThreads + 2; c += kCombineThreads) {
+    const int i = ((i0 - 1 + c) % m + m) % m;
+    constexpr int U = 8;
     double v = 0.0;
-    for (int k = 0; k < nsys; ++k) v += scratch[(size_t)k * m + i];
-    s[i] = v;
+    for (int k0 = 0; k0 < nsys; k0 += U) {
+      double a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = k0 + u < nsys ? k0 + u : k0;
+        a[u] = scratch[(size_t)k * m + i];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (k0 + u < nsys) v += a[u];
+    }
+    s[c] = v;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    if (mode == kIfaceOperator) {
-      const double Lin = loop_stiff(in, m, h, i) + loop_mass(in, m, h, i);
-      out[i] = dL * Lin + d0 * loop_mass(in, m, h, i) + loop_mass(s, m, h, i);
-    } else {
-      out[i] = s[i];
-    }
+  const int i = i0 + threadIdx.x;
+  if (i >= m) return;
+  if (mode == kIfaceOperator) {
+    const double Lin = loop_stiff(in, m, h, i) + loop_mass(in, m, h, i);
+    const int c = threadIdx.x + 1;  // node i in s (its neighbours at c - 1 and c + 1)
+    const double Ms = (h / 6.0) * (4.0 * s[c] + s[c - 1] + s[c + 1]);
+    out[i] = dL * Lin + d0 * loop_mass(in, m, h, i) + Ms;
+  } else {
+    out[i] = s[threadIdx.x + 1];
   }
 }
 
@@ -620,8 +656,9 @@ void launch_model_loop_batch(hipStream_t s, int n, const ShiftTable& tab, int mo
   const double h = 1.0 / n;
   hipLaunchKernelGGL(km_loop_solve, dim3(tab.m), dim3(kIfaceThreads), 0, s, m, h, tab, mode, in,
                      scratch);
-  hipLaunchKernelGGL(km_loop_combine, dim3(1), dim3(kIfaceThreads), 0, s, m, h, tab.m, tab.d0,
-                     tab.dL, mode, in, (const double*)scratch, out);
+  hipLaunchKernelGGL(km_loop_combine, dim3((m + kCombineThreads - 1) / kCombineThreads),
+                     dim3(kCombineThreads), 0, s, m, h, tab.m, tab.d0, tab.dL, mode, in,
+                     (const double*)scratch, out);
 }
 
 template <typename VT>
