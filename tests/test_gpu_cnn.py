@@ -57,11 +57,15 @@ def test_forward_matches_oracle(n, B):
     ref, _ = cnn.forward(params, X)
     ref = ref * s[:, None, None]
     err = rel(got, ref)
-    print(f"  rel err {err:.2e}", flush=True)
-    assert err <= 3e-2
+    emax = float(np.abs(got - ref).max() / np.abs(ref).max())
+    per = [rel(got[b], ref[b]) for b in range(B)]
+    print(f"  rel err {err:.2e}  element max {emax:.2e}  per image {max(per):.2e}", flush=True)
+    # about 3x the measured BF16 error through six layers (8.8e-3 relative, 1.0e-2 element-wise
+    # against the largest output): a wrong tap or channel block shows in the element-wise bound
+    assert err <= 2.5e-2 and emax <= 3e-2
     # per image, and the rescaling by the trace norm
     for b in range(B):
-        assert rel(got[b], ref[b]) <= 5e-2
+        assert per[b] <= 3e-2
 
 
 def test_backward_matches_oracle_and_is_deterministic():
@@ -92,8 +96,11 @@ def test_backward_matches_oracle_and_is_deterministic():
     got = F.unpack_params(grads[0])
     for k, ((gW, gb), (rW, rb)) in enumerate(zip(got, g_ref)):
         eW, eb = rel(gW, rW), rel(gb, rb)
-        print(f"  layer {k + 1}: dW rel err {eW:.2e}  db rel err {eb:.2e}", flush=True)
-        assert eW <= 6e-2 and eb <= 6e-2
+        mW = float(np.abs(gW - rW).max() / np.abs(rW).max())
+        print(f"  layer {k + 1}: dW rel err {eW:.2e} (element max {mW:.2e})  db rel err {eb:.2e}",
+              flush=True)
+        # about 3x the measured (at most 9.5e-4 relative, 1.3e-3 element-wise)
+        assert eW <= 3e-3 and mW <= 4e-3 and eb <= 3e-3
 
 
 def test_adam_matches_oracle_step():
